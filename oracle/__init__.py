@@ -1,0 +1,241 @@
+"""Plain FP64 CPU oracle for the DGSEM residual and tau-estimation (arXiv 2210.03523).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only users.  The GPU library never loads it and
+shares no code with it.
+
+The numerical work is done in ``dg_oracle.c`` (plain loops, natural element
+order); this module only marshals numpy arrays through ctypes.  Arrays are in
+the natural ragged layout: element ``e`` occupies ``5 * n_e`` values starting
+at ``5 * noff[e]``, ordered ``[var][node]`` with ``node = i + n1*(j + n2*k)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dg_oracle.c")
+_LIB = os.environ.get("DG_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
+
+NMAX = 12
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, OpenMP over elements)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-shared", "-fPIC",
+               "-std=c11", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("bc", ctypes.c_int * 6), ("flux", ctypes.c_int),
+                ("gamma", ctypes.c_double), ("qfar", ctypes.c_double * 5)]
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        for name, args in {
+            "orc_lgl": [ctypes.c_int, _D, _D],
+            "orc_dmat": [ctypes.c_int, _D],
+            "orc_interp": [ctypes.c_int, ctypes.c_int, _D],
+            "orc_proj": [ctypes.c_int, ctypes.c_int, _D],
+            "orc_node_coords": [ctypes.POINTER(_Mesh), _I, _D],
+            "orc_residual": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_int, ctypes.c_int],
+            "orc_restrict": [ctypes.c_int, _I, _I, _D, _D],
+            "orc_tau": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, _D, _D, _D, _D],
+            "orc_num_combos": [_I],
+            "orc_sweep": [ctypes.POINTER(_Mesh), _I, _D, _D, _I, ctypes.c_int, _D, _D],
+            "orc_rk3": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_double, ctypes.c_int],
+        }.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        for name in ("orc_flux_n",):
+            fn = getattr(lib, name)
+            fn.argtypes = [_D, _D, ctypes.c_double, _D]
+            fn.restype = None
+        lib.orc_numflux.argtypes = [_D, _D, _D, ctypes.c_double, ctypes.c_int, _D]
+        lib.orc_numflux.restype = None
+        lib.orc_roe_waves.argtypes = [_D, _D, _D, ctypes.c_double, _D, _D]
+        lib.orc_roe_waves.restype = None
+        _lib = lib
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_D)
+
+
+def _i(a):
+    return a.ctypes.data_as(_I)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _mesh(m: dict) -> _Mesh:
+    s = _Mesh()
+    s.nx, s.ny, s.nz = (int(v) for v in m["n"])
+    for d in range(3):
+        s.lo[d] = float(m["lo"][d])
+        s.hi[d] = float(m["hi"][d])
+    for f in range(6):
+        s.bc[f] = int(m["bc"][f])
+    s.flux = int(m["flux"])
+    s.gamma = float(m["gamma"])
+    for v in range(5):
+        s.qfar[v] = float(m["qfar"][v])
+    return s
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what}: invalid arguments")
+
+
+# --------------------------------------------------------------------------- tables
+def lgl(N: int):
+    x = np.zeros(N + 1)
+    w = np.zeros(N + 1)
+    _check(_load().orc_lgl(N, _d(x), _d(w)), "lgl")
+    return x, w
+
+
+def dmat(N: int):
+    D = np.zeros((N + 1, N + 1))
+    _check(_load().orc_dmat(N, _d(D)), "dmat")
+    return D
+
+
+def interp(M: int, N: int):
+    out = np.zeros((M + 1, N + 1))
+    _check(_load().orc_interp(M, N, _d(out)), "interp")
+    return out
+
+
+def proj(N: int, K: int):
+    out = np.zeros((N + 1, K + 1))
+    _check(_load().orc_proj(N, K, _d(out)), "proj")
+    return out
+
+
+# --------------------------------------------------------------------------- fluxes
+def flux_n(q, n, gamma=1.4):
+    q, n = _f64(q), _f64(n)
+    f = np.zeros(5)
+    _load().orc_flux_n(_d(q), _d(n), gamma, _d(f))
+    return f
+
+
+def numflux(qL, qR, n, gamma=1.4, kind=0):
+    qL, qR, n = _f64(qL), _f64(qR), _f64(n)
+    f = np.zeros(5)
+    _load().orc_numflux(_d(qL), _d(qR), _d(n), gamma, int(kind), _d(f))
+    return f
+
+
+def roe_waves(qL, qR, n, gamma=1.4):
+    qL, qR, n = _f64(qL), _f64(qR), _f64(n)
+    lam = np.zeros(4)
+    wave = np.zeros((4, 5))
+    _load().orc_roe_waves(_d(qL), _d(qR), _d(n), gamma, _d(lam), _d(wave))
+    return lam, wave
+
+
+# --------------------------------------------------------------------------- mesh-level
+def num_nodes(orders) -> int:
+    o = np.asarray(orders).reshape(-1, 3)
+    return int(np.prod(o + 1, axis=1).sum())
+
+
+def node_coords(mesh: dict, orders):
+    o = _i32(orders)
+    xyz = np.zeros(3 * num_nodes(o))
+    m = _mesh(mesh)
+    _check(_load().orc_node_coords(ctypes.byref(m), _i(o), _d(xyz)), "node_coords")
+    return xyz
+
+
+def residual(mesh: dict, orders, u, form: int = 0, isolated: bool = False):
+    """form 0: new form r = M^-1 F^N(u) (= -du/dt); form 1: traditional F^N(u)."""
+    o, u = _i32(orders), _f64(u)
+    r = np.zeros_like(u)
+    m = _mesh(mesh)
+    _check(_load().orc_residual(ctypes.byref(m), _i(o), _d(u), _d(r), int(form), int(bool(isolated))),
+           "residual")
+    return r
+
+
+def restrict(fine_orders, coarse_orders, u):
+    fo, co, u = _i32(fine_orders), _i32(coarse_orders), _f64(u)
+    E = fo.size // 3
+    uc = np.zeros(5 * num_nodes(co))
+    _check(_load().orc_restrict(E, _i(fo), _i(co), _d(u), _d(uc)), "restrict")
+    return uc
+
+
+def tau(mesh: dict, fine_orders, coarse_orders, u, dudt, isolated: bool = False):
+    """Returns (tau_new, tau_trad, norms[E,2], varnorms[E,2,5]) in the coarse layout."""
+    fo, co, u, dudt = _i32(fine_orders), _i32(coarse_orders), _f64(u), _f64(dudt)
+    E = fo.size // 3
+    nc = num_nodes(co)
+    tn = np.zeros(5 * nc)
+    tt = np.zeros(5 * nc)
+    norms = np.zeros((E, 2))
+    vn = np.zeros((E, 2, 5))
+    m = _mesh(mesh)
+    _check(_load().orc_tau(ctypes.byref(m), _i(fo), _i(co), _d(u), _d(dudt), int(bool(isolated)),
+                           _d(tn), _d(tt), _d(norms), _d(vn)), "tau")
+    return tn, tt, norms, vn
+
+
+def num_combos(order3) -> int:
+    o = _i32(order3)
+    return int(_load().orc_num_combos(_i(o)))
+
+
+def sweep(mesh: dict, orders, u, dudt, elems=None):
+    """Isolated sweep; returns (te_new, te_trad, combo_offsets) for the listed elements."""
+    o, u, dudt = _i32(orders), _f64(u), _f64(dudt)
+    E = o.size // 3
+    el = _i32(np.arange(E) if elems is None else elems)
+    o3 = o.reshape(-1, 3)
+    counts = [num_combos(o3[e]) for e in el]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    ten = np.zeros(int(offs[-1]))
+    tet = np.zeros(int(offs[-1]))
+    m = _mesh(mesh)
+    _check(_load().orc_sweep(ctypes.byref(m), _i(o), _d(u), _d(dudt), _i(el), len(el), _d(ten), _d(tet)),
+           "sweep")
+    return ten, tet, offs
+
+
+def rk3(mesh: dict, orders, u, dt: float, nsteps: int):
+    o = _i32(orders)
+    out = _f64(u).copy()
+    m = _mesh(mesh)
+    _check(_load().orc_rk3(ctypes.byref(m), _i(o), _d(out), float(dt), int(nsteps)), "rk3")
+    return out

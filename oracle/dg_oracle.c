@@ -1,0 +1,764 @@
+/*
+ * dg_oracle.c -- plain FP64 CPU oracle (test infrastructure only; see dg_oracle.h).
+ *
+ * What it follows in arXiv 2210.03523:
+ *   - DGSEM semi-discretisation, Section 2.1 (eqs. DGSEMsystem, DGMassMatrixLeft /
+ *     DGMassMatrixRight): tensor-product Lagrange basis on Gauss-Lobatto nodes,
+ *     collocated quadrature, diagonal mass matrix M = diag(J_j w_j).
+ *   - New and traditional truncation-error forms, Section 2.2 (eqs. TEtildedef,
+ *     TEdef): tau_new = M^-1 F^N(I q) - I F(q), tau_trad = M tau_new.
+ *   - Isolated truncation error, end of Section 2.2: surface numerical fluxes
+ *     replaced by the inner flux (all surface terms vanish on Gauss-Lobatto nodes).
+ *   - Tau-estimation, Section 2.3: fine solution injected into every coarser
+ *     anisotropic order; unsteady "variational DG" estimate of I F(q) by the
+ *     sampled fine time derivative I (M^P)^-1 F^P(q^P).
+ *   - Roe advective flux and Williamson low-storage RK3, Section 3 (set-up).
+ *
+ * The residual is written in the strong form, which on Gauss-Lobatto nodes is
+ * algebraically identical to the weak form of Section 2.1 (summation by parts):
+ *   J dQ/dt = -( sum_d D_d Ft^d + SAT ),   Ft^d = Ja^d . f(Q),
+ *   SAT at a face node of face (d, s) = (F*_out - s Ft^d) / w_end.
+ * Faces whose tangential orders differ are coupled on a mortar of order
+ * K = max per tangential direction: both traces are interpolated onto the
+ * mortar, the Riemann flux is evaluated once there (left = element on the
+ * minus side, normal +e_d), and each side takes the L2 projection back onto
+ * its own face nodes (the right side with a minus sign).
+ */
+#include "dg_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NV 5
+
+/* ------------------------------------------------------------------------ */
+/* 1D Legendre-Gauss-Lobatto tables (computed once in long double).          */
+
+static double g_x[ORC_NMAX + 1][ORC_NMAX + 1];
+static double g_w[ORC_NMAX + 1][ORC_NMAX + 1];
+static long double g_xl[ORC_NMAX + 1][ORC_NMAX + 1];
+static long double g_lam[ORC_NMAX + 1][ORC_NMAX + 1];
+static double g_D[ORC_NMAX + 1][(ORC_NMAX + 1) * (ORC_NMAX + 1)];
+static int g_ready = 0;
+
+/* Legendre polynomial L_N and its derivative at x (three-term recurrence). */
+static void legendre(int N, long double x, long double *L, long double *dL)
+{
+    long double p0 = 1.0L, p1 = x, d0 = 0.0L, d1 = 1.0L;
+    if (N == 0) { *L = 1.0L; *dL = 0.0L; return; }
+    for (int k = 2; k <= N; ++k) {
+        long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        long double d2 = d0 + (2 * k - 1) * p1;
+        p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+    *L = p1; *dL = d1;
+}
+
+static void build_tables(void)
+{
+    for (int N = 1; N <= ORC_NMAX; ++N) {
+        long double *x = g_xl[N];
+        x[0] = -1.0L; x[N] = 1.0L;
+        /* interior nodes: roots of L'_N, Newton from Chebyshev-Lobatto guesses */
+        for (int j = 1; j < N; ++j) {
+            long double t = -cosl(3.14159265358979323846264338327950288L * j / N);
+            for (int it = 0; it < 100; ++it) {
+                long double L, dL;
+                legendre(N, t, &L, &dL);
+                /* (1-t^2) L'' = 2 t L' - N(N+1) L */
+                long double d2 = (2.0L * t * dL - N * (N + 1.0L) * L) / (1.0L - t * t);
+                long double dt = dL / d2;
+                t -= dt;
+                if (fabsl(dt) < 1e-30L) break;
+            }
+            x[j] = t;
+        }
+        /* enforce exact symmetry, and 0 at the centre for even N */
+        for (int j = 0; j <= N / 2; ++j) {
+            long double s = 0.5L * (x[N - j] - x[j]);
+            x[j] = -s; x[N - j] = s;
+        }
+        if (N % 2 == 0) x[N / 2] = 0.0L;
+        for (int j = 0; j <= N; ++j) {
+            long double L, dL;
+            legendre(N, x[j], &L, &dL);
+            g_x[N][j] = (double)x[j];
+            g_w[N][j] = (double)(2.0L / (N * (N + 1.0L) * L * L));
+        }
+        /* barycentric weights */
+        for (int j = 0; j <= N; ++j) {
+            long double p = 1.0L;
+            for (int k = 0; k <= N; ++k)
+                if (k != j) p *= (x[j] - x[k]);
+            g_lam[N][j] = 1.0L / p;
+        }
+        /* derivative matrix D_jk = l_k'(x_j) */
+        for (int j = 0; j <= N; ++j) {
+            long double diag = 0.0L;
+            for (int k = 0; k <= N; ++k) {
+                if (k == j) continue;
+                long double djk = (g_lam[N][k] / g_lam[N][j]) / (x[j] - x[k]);
+                g_D[N][j * (N + 1) + k] = (double)djk;
+                diag -= djk;
+            }
+            g_D[N][j * (N + 1) + j] = (double)diag;
+        }
+    }
+    g_ready = 1;
+}
+
+static void ensure_tables(void)
+{
+    if (!g_ready) {
+#pragma omp critical(orc_tables)
+        if (!g_ready) build_tables();
+    }
+}
+
+int orc_lgl(int N, double *x, double *w)
+{
+    if (N < 1 || N > ORC_NMAX) return -1;
+    ensure_tables();
+    for (int j = 0; j <= N; ++j) { x[j] = g_x[N][j]; w[j] = g_w[N][j]; }
+    return 0;
+}
+
+int orc_dmat(int N, double *D)
+{
+    if (N < 1 || N > ORC_NMAX) return -1;
+    ensure_tables();
+    memcpy(D, g_D[N], sizeof(double) * (N + 1) * (N + 1));
+    return 0;
+}
+
+/* Lagrange basis of order N evaluated at the order-M nodes (barycentric form). */
+int orc_interp(int M, int N, double *I)
+{
+    if (M < 1 || M > ORC_NMAX || N < 1 || N > ORC_NMAX) return -1;
+    ensure_tables();
+    for (int a = 0; a <= M; ++a) {
+        long double xa = g_xl[M][a];
+        int hit = -1;
+        for (int k = 0; k <= N; ++k)
+            if (xa == g_xl[N][k]) hit = k;
+        if (hit >= 0) {
+            for (int k = 0; k <= N; ++k) I[a * (N + 1) + k] = (k == hit) ? 1.0 : 0.0;
+            continue;
+        }
+        long double den = 0.0L;
+        for (int k = 0; k <= N; ++k) den += g_lam[N][k] / (xa - g_xl[N][k]);
+        for (int k = 0; k <= N; ++k)
+            I[a * (N + 1) + k] = (double)((g_lam[N][k] / (xa - g_xl[N][k])) / den);
+    }
+    return 0;
+}
+
+/* L2 projection from order K onto order N <= K:  P = (S^T W_K S)^-1 S^T W_K,
+ * S = interpolation from order N to the order-K nodes (an exact embedding). */
+int orc_proj(int N, int K, double *P)
+{
+    if (N < 1 || K < N || K > ORC_NMAX) return -1;
+    ensure_tables();
+    int n = N + 1, k = K + 1;
+    if (N == K) {
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) P[a * n + b] = (a == b) ? 1.0 : 0.0;
+        return 0;
+    }
+    double S[(ORC_NMAX + 1) * (ORC_NMAX + 1)];
+    orc_interp(K, N, S); /* k x n */
+    long double A[ORC_NMAX + 1][ORC_NMAX + 1];       /* S^T W S  (n x n) */
+    long double B[ORC_NMAX + 1][ORC_NMAX + 1];       /* S^T W    (n x k) */
+    for (int a = 0; a < n; ++a) {
+        for (int b = 0; b < n; ++b) {
+            long double s = 0.0L;
+            for (int q = 0; q < k; ++q) s += (long double)S[q * n + a] * g_w[K][q] * S[q * n + b];
+            A[a][b] = s;
+        }
+        for (int q = 0; q < k; ++q) B[a][q] = (long double)S[q * n + a] * g_w[K][q];
+    }
+    /* Gauss-Jordan elimination with partial pivoting: A X = B */
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabsl(A[r][c]) > fabsl(A[piv][c])) piv = r;
+        if (piv != c) {
+            for (int j = 0; j < n; ++j) { long double t = A[c][j]; A[c][j] = A[piv][j]; A[piv][j] = t; }
+            for (int j = 0; j < k; ++j) { long double t = B[c][j]; B[c][j] = B[piv][j]; B[piv][j] = t; }
+        }
+        long double inv = 1.0L / A[c][c];
+        for (int j = 0; j < n; ++j) A[c][j] *= inv;
+        for (int j = 0; j < k; ++j) B[c][j] *= inv;
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            long double f = A[r][c];
+            if (f == 0.0L) continue;
+            for (int j = 0; j < n; ++j) A[r][j] -= f * A[c][j];
+            for (int j = 0; j < k; ++j) B[r][j] -= f * B[c][j];
+        }
+    }
+    for (int a = 0; a < n; ++a)
+        for (int q = 0; q < k; ++q) P[a * k + q] = (double)B[a][q];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Physics: compressible Euler.                                              */
+
+static double pressure(const double *q, double g)
+{
+    double ke = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+    return (g - 1.0) * (q[4] - ke);
+}
+
+void orc_flux_n(const double *q, const double *n, double g, double *f)
+{
+    double rho = q[0];
+    double u = q[1] / rho, v = q[2] / rho, w = q[3] / rho;
+    double p = pressure(q, g);
+    double un = u * n[0] + v * n[1] + w * n[2];
+    f[0] = rho * un;
+    f[1] = q[1] * un + p * n[0];
+    f[2] = q[2] * un + p * n[1];
+    f[3] = q[3] * un + p * n[2];
+    f[4] = (q[4] + p) * un;
+}
+
+/* Roe's approximate Riemann solver: eigenvalues and wave vectors alpha_k r_k of
+ * the Roe-averaged Jacobian, with both shear waves combined into one vector. */
+void orc_roe_waves(const double *qL, const double *qR, const double *n, double g,
+                   double *lam, double *wave)
+{
+    double rL = qL[0], rR = qR[0];
+    double uL[3] = {qL[1] / rL, qL[2] / rL, qL[3] / rL};
+    double uR[3] = {qR[1] / rR, qR[2] / rR, qR[3] / rR};
+    double pL = pressure(qL, g), pR = pressure(qR, g);
+    double HL = (qL[4] + pL) / rL, HR = (qR[4] + pR) / rR;
+    double sL = sqrt(rL), sR = sqrt(rR);
+    double ut[3];
+    for (int d = 0; d < 3; ++d) ut[d] = (sL * uL[d] + sR * uR[d]) / (sL + sR);
+    double Ht = (sL * HL + sR * HR) / (sL + sR);
+    double rt = sL * sR;
+    double q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+    double c2 = (g - 1.0) * (Ht - 0.5 * q2);
+    double c = sqrt(c2);
+    double un = ut[0] * n[0] + ut[1] * n[1] + ut[2] * n[2];
+    double du[3] = {uR[0] - uL[0], uR[1] - uL[1], uR[2] - uL[2]};
+    double dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+    double dut[3] = {du[0] - dun * n[0], du[1] - dun * n[1], du[2] - dun * n[2]};
+    double drho = rR - rL, dp = pR - pL;
+    double a1 = (dp - rt * c * dun) / (2.0 * c2);
+    double a2 = drho - dp / c2;
+    double a4 = (dp + rt * c * dun) / (2.0 * c2);
+    lam[0] = un - c; lam[1] = un; lam[2] = un; lam[3] = un + c;
+    /* k = 1: acoustic wave moving with u_n - c */
+    wave[0] = a1;
+    for (int d = 0; d < 3; ++d) wave[1 + d] = a1 * (ut[d] - c * n[d]);
+    wave[4] = a1 * (Ht - c * un);
+    /* k = 2: entropy wave */
+    wave[5] = a2;
+    for (int d = 0; d < 3; ++d) wave[6 + d] = a2 * ut[d];
+    wave[9] = a2 * 0.5 * q2;
+    /* k = 3: both shear waves, strength rho~ */
+    wave[10] = 0.0;
+    for (int d = 0; d < 3; ++d) wave[11 + d] = rt * dut[d];
+    wave[14] = rt * (ut[0] * dut[0] + ut[1] * dut[1] + ut[2] * dut[2]);
+    /* k = 4: acoustic wave moving with u_n + c */
+    wave[15] = a4;
+    for (int d = 0; d < 3; ++d) wave[16 + d] = a4 * (ut[d] + c * n[d]);
+    wave[19] = a4 * (Ht + c * un);
+}
+
+void orc_numflux(const double *qL, const double *qR, const double *n, double g, int kind,
+                 double *f)
+{
+    double fL[NV], fR[NV];
+    orc_flux_n(qL, n, g, fL);
+    orc_flux_n(qR, n, g, fR);
+    if (kind == 0) {
+        double lam[4], wave[20];
+        orc_roe_waves(qL, qR, n, g, lam, wave);
+        for (int v = 0; v < NV; ++v) {
+            double diss = 0.0;
+            for (int k = 0; k < 4; ++k) diss += fabs(lam[k]) * wave[k * NV + v];
+            f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * diss;
+        }
+    } else {
+        double rL = qL[0], rR = qR[0];
+        double unL = (qL[1] * n[0] + qL[2] * n[1] + qL[3] * n[2]) / rL;
+        double unR = (qR[1] * n[0] + qR[2] * n[1] + qR[3] * n[2]) / rR;
+        double cL = sqrt(g * pressure(qL, g) / rL), cR = sqrt(g * pressure(qR, g) / rR);
+        double s = fmax(fabs(unL) + cL, fabs(unR) + cR);
+        for (int v = 0; v < NV; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * s * (qR[v] - qL[v]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh helpers.                                                             */
+
+static int nnodes(const int *o) { return (o[0] + 1) * (o[1] + 1) * (o[2] + 1); }
+
+long orc_num_nodes(int E, const int *orders)
+{
+    long s = 0;
+    for (int e = 0; e < E; ++e) s += nnodes(orders + 3 * e);
+    return s;
+}
+
+static long *node_offsets(int E, const int *orders)
+{
+    long *off = (long *)malloc(sizeof(long) * (E + 1));
+    off[0] = 0;
+    for (int e = 0; e < E; ++e) off[e + 1] = off[e] + nnodes(orders + 3 * e);
+    return off;
+}
+
+static int check_orders(int E, const int *orders)
+{
+    for (int i = 0; i < 3 * E; ++i)
+        if (orders[i] < 1 || orders[i] > ORC_NMAX) return -1;
+    return 0;
+}
+
+static void elem_ijk(const orc_mesh *m, int e, int *c)
+{
+    c[0] = e % m->nx;
+    c[1] = (e / m->nx) % m->ny;
+    c[2] = e / (m->nx * m->ny);
+}
+
+static int elem_index(const orc_mesh *m, const int *c) { return c[0] + m->nx * (c[1] + m->ny * c[2]); }
+
+/* Affine geometry of a uniform box element: h_d, J = h1h2h3/8, |Ja^d| = J*2/h_d. */
+static void geometry(const orc_mesh *m, double *h, double *J, double *Ja)
+{
+    int nd[3] = {m->nx, m->ny, m->nz};
+    for (int d = 0; d < 3; ++d) h[d] = (m->hi[d] - m->lo[d]) / nd[d];
+    *J = h[0] * h[1] * h[2] / 8.0;
+    Ja[0] = h[1] * h[2] / 4.0;
+    Ja[1] = h[0] * h[2] / 4.0;
+    Ja[2] = h[0] * h[1] / 4.0;
+}
+
+int orc_node_coords(const orc_mesh *m, const int *orders, double *xyz)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (check_orders(E, orders)) return -1;
+    ensure_tables();
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+    long *off = node_offsets(E, orders);
+    for (int e = 0; e < E; ++e) {
+        const int *o = orders + 3 * e;
+        int n1 = o[0] + 1, n2 = o[1] + 1, n3 = o[2] + 1, ne = n1 * n2 * n3;
+        int c[3];
+        elem_ijk(m, e, c);
+        double *X = xyz + 3 * off[e];
+        for (int k = 0; k < n3; ++k)
+            for (int j = 0; j < n2; ++j)
+                for (int i = 0; i < n1; ++i) {
+                    int node = i + n1 * (j + n2 * k);
+                    int idx[3] = {i, j, k};
+                    for (int d = 0; d < 3; ++d)
+                        X[d * ne + node] = m->lo[d] + h[d] * (c[d] + 0.5 * (g_x[o[d]][idx[d]] + 1.0));
+                }
+    }
+    free(off);
+    return 0;
+}
+
+/* Volume node index of face node (a,b) on face (d, side). */
+static int face_node(const int *n, int d, int side, int a, int b)
+{
+    int idx[3];
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    idx[d] = side > 0 ? n[d] - 1 : 0;
+    idx[t1] = a;
+    idx[t2] = b;
+    return idx[0] + n[0] * (idx[1] + n[1] * idx[2]);
+}
+
+/* Outward numerical flux F*_out at the own face nodes of face (d, s) of element e:
+ * fout[v*(na*nb) + a + na*b]. */
+static void face_flux(const orc_mesh *m, const int *orders, const long *off, const double *u,
+                      int e, int d, int s, const double *Ja, double *fout)
+{
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
+    int na = n[t1], nb = n[t2];
+    int ne = n[0] * n[1] * n[2];
+    const double *Qe = u + NV * off[e];
+    double g = m->gamma;
+
+    int c[3], nd[3] = {m->nx, m->ny, m->nz};
+    elem_ijk(m, e, c);
+    c[d] += s;
+    int bc = 0;
+    if (c[d] < 0 || c[d] >= nd[d]) {
+        bc = m->bc[2 * d + (s > 0 ? 1 : 0)];
+        c[d] = (c[d] + nd[d]) % nd[d];
+    }
+
+    if (bc != 0) {
+        double nout[3] = {0, 0, 0};
+        nout[d] = (double)s;
+        for (int b = 0; b < nb; ++b)
+            for (int a = 0; a < na; ++a) {
+                int node = face_node(n, d, s, a, b);
+                double qin[NV], qg[NV], f[NV];
+                for (int v = 0; v < NV; ++v) qin[v] = Qe[v * ne + node];
+                if (bc == 1) {
+                    double mn = qin[1] * nout[0] + qin[2] * nout[1] + qin[3] * nout[2];
+                    qg[0] = qin[0];
+                    for (int k = 0; k < 3; ++k) qg[1 + k] = qin[1 + k] - 2.0 * mn * nout[k];
+                    qg[4] = qin[4];
+                } else {
+                    for (int v = 0; v < NV; ++v) qg[v] = m->qfar[v];
+                }
+                orc_numflux(qin, qg, nout, g, m->flux, f);
+                for (int v = 0; v < NV; ++v) fout[v * na * nb + a + na * b] = Ja[d] * f[v];
+            }
+        return;
+    }
+
+    int nbr = elem_index(m, c);
+    const int *on = orders + 3 * nbr;
+    int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1};
+    int nne = nn[0] * nn[1] * nn[2];
+    const double *Qn = u + NV * off[nbr];
+
+    /* left = element on the minus side of the face, right = plus side */
+    const int *nL = s > 0 ? n : nn;
+    const int *nR = s > 0 ? nn : n;
+    const double *QL = s > 0 ? Qe : Qn;
+    const double *QR = s > 0 ? Qn : Qe;
+    int neL = s > 0 ? ne : nne, neR = s > 0 ? nne : ne;
+    int aL = nL[t1], bL = nL[t2], aR = nR[t1], bR = nR[t2];
+    int K1 = aL > aR ? aL : aR, K2 = bL > bR ? bL : bR;
+
+    double *S1L = malloc(sizeof(double) * K1 * aL), *S2L = malloc(sizeof(double) * K2 * bL);
+    double *S1R = malloc(sizeof(double) * K1 * aR), *S2R = malloc(sizeof(double) * K2 * bR);
+    orc_interp(K1 - 1, aL - 1, S1L);
+    orc_interp(K2 - 1, bL - 1, S2L);
+    orc_interp(K1 - 1, aR - 1, S1R);
+    orc_interp(K2 - 1, bR - 1, S2R);
+    double *FK = malloc(sizeof(double) * NV * K1 * K2);
+    double nplus[3] = {0, 0, 0};
+    nplus[d] = 1.0;
+
+    for (int B = 0; B < K2; ++B)
+        for (int A = 0; A < K1; ++A) {
+            double qL[NV] = {0, 0, 0, 0, 0}, qR[NV] = {0, 0, 0, 0, 0}, f[NV];
+            for (int b = 0; b < bL; ++b)
+                for (int a = 0; a < aL; ++a) {
+                    double wgt = S1L[A * aL + a] * S2L[B * bL + b];
+                    int node = face_node(nL, d, +1, a, b);
+                    for (int v = 0; v < NV; ++v) qL[v] += wgt * QL[v * neL + node];
+                }
+            for (int b = 0; b < bR; ++b)
+                for (int a = 0; a < aR; ++a) {
+                    double wgt = S1R[A * aR + a] * S2R[B * bR + b];
+                    int node = face_node(nR, d, -1, a, b);
+                    for (int v = 0; v < NV; ++v) qR[v] += wgt * QR[v * neR + node];
+                }
+            orc_numflux(qL, qR, nplus, g, m->flux, f);
+            for (int v = 0; v < NV; ++v) FK[v * K1 * K2 + A + K1 * B] = Ja[d] * f[v];
+        }
+
+    /* project back onto the own face (L2 projection), outward sign */
+    double *P1 = malloc(sizeof(double) * na * K1), *P2 = malloc(sizeof(double) * nb * K2);
+    orc_proj(na - 1, K1 - 1, P1);
+    orc_proj(nb - 1, K2 - 1, P2);
+    for (int b = 0; b < nb; ++b)
+        for (int a = 0; a < na; ++a)
+            for (int v = 0; v < NV; ++v) {
+                double acc = 0.0;
+                for (int B = 0; B < K2; ++B)
+                    for (int A = 0; A < K1; ++A)
+                        acc += P1[a * K1 + A] * P2[b * K2 + B] * FK[v * K1 * K2 + A + K1 * B];
+                fout[v * na * nb + a + na * b] = (double)s * acc;
+            }
+    free(S1L); free(S2L); free(S1R); free(S2R); free(FK); free(P1); free(P2);
+}
+
+/* Residual of one element: r (= (V+SAT)/J for form 0, w_i w_j w_k (V+SAT) for form 1). */
+static void element_residual(const orc_mesh *m, const int *orders, const long *off,
+                             const double *u, int e, int form, int isolated, double *r)
+{
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
+    int ne = n[0] * n[1] * n[2];
+    const double *Q = u + NV * off[e];
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+
+    double *Ft = malloc(sizeof(double) * 3 * NV * ne);  /* [d][v][node] */
+    double *V = calloc((size_t)NV * ne, sizeof(double)); /* [v][node] */
+    for (int node = 0; node < ne; ++node) {
+        double q[NV], f[NV];
+        for (int v = 0; v < NV; ++v) q[v] = Q[v * ne + node];
+        for (int d = 0; d < 3; ++d) {
+            double nd[3] = {0, 0, 0};
+            nd[d] = 1.0;
+            orc_flux_n(q, nd, m->gamma, f);
+            for (int v = 0; v < NV; ++v) Ft[(d * NV + v) * ne + node] = Ja[d] * f[v];
+        }
+    }
+    /* volume term: sum_d D^{N_d} applied along direction d */
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int node = i + n[0] * (j + n[1] * k);
+                for (int v = 0; v < NV; ++v) {
+                    double acc = 0.0;
+                    for (int q = 0; q < n[0]; ++q)
+                        acc += g_D[o[0]][i * n[0] + q] * Ft[(0 * NV + v) * ne + q + n[0] * (j + n[1] * k)];
+                    for (int q = 0; q < n[1]; ++q)
+                        acc += g_D[o[1]][j * n[1] + q] * Ft[(1 * NV + v) * ne + i + n[0] * (q + n[1] * k)];
+                    for (int q = 0; q < n[2]; ++q)
+                        acc += g_D[o[2]][k * n[2] + q] * Ft[(2 * NV + v) * ne + i + n[0] * (j + n[1] * q)];
+                    V[v * ne + node] = acc;
+                }
+            }
+    /* surface terms */
+    if (!isolated) {
+        for (int d = 0; d < 3; ++d) {
+            int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            int na = n[t1], nb = n[t2];
+            double wend = g_w[o[d]][0];
+            double *fout = malloc(sizeof(double) * NV * na * nb);
+            for (int s = -1; s <= 1; s += 2) {
+                face_flux(m, orders, off, u, e, d, s, Ja, fout);
+                for (int b = 0; b < nb; ++b)
+                    for (int a = 0; a < na; ++a) {
+                        int node = face_node(n, d, s, a, b);
+                        for (int v = 0; v < NV; ++v)
+                            V[v * ne + node] += (fout[v * na * nb + a + na * b] -
+                                                 (double)s * Ft[(d * NV + v) * ne + node]) / wend;
+                    }
+            }
+            free(fout);
+        }
+    }
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int node = i + n[0] * (j + n[1] * k);
+                double www = g_w[o[0]][i] * g_w[o[1]][j] * g_w[o[2]][k];
+                for (int v = 0; v < NV; ++v)
+                    r[v * ne + node] = form == 0 ? V[v * ne + node] / J : www * V[v * ne + node];
+            }
+    free(Ft);
+    free(V);
+}
+
+int orc_residual(const orc_mesh *m, const int *orders, const double *u, double *r, int form,
+                 int isolated)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (E <= 0 || check_orders(E, orders) || (form != 0 && form != 1)) return -1;
+    ensure_tables();
+    long *off = node_offsets(E, orders);
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e)
+        element_residual(m, orders, off, u, e, form, isolated, r + NV * off[e]);
+    free(off);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tau-estimation.                                                           */
+
+/* Sample the order-(nf) element polynomial at the order-(nc) nodes:
+ * out[a,b,c] = sum_{i,j,k} I1[a,i] I2[b,j] I3[c,k] in[i,j,k], for each variable. */
+static void restrict_element(const int *of, const int *oc, const double *in, double *out)
+{
+    int nf[3] = {of[0] + 1, of[1] + 1, of[2] + 1};
+    int nc[3] = {oc[0] + 1, oc[1] + 1, oc[2] + 1};
+    int nef = nf[0] * nf[1] * nf[2], nec = nc[0] * nc[1] * nc[2];
+    double I1[(ORC_NMAX + 1) * (ORC_NMAX + 1)], I2[(ORC_NMAX + 1) * (ORC_NMAX + 1)],
+        I3[(ORC_NMAX + 1) * (ORC_NMAX + 1)];
+    orc_interp(oc[0], of[0], I1);
+    orc_interp(oc[1], of[1], I2);
+    orc_interp(oc[2], of[2], I3);
+    for (int v = 0; v < NV; ++v)
+        for (int c = 0; c < nc[2]; ++c)
+            for (int b = 0; b < nc[1]; ++b)
+                for (int a = 0; a < nc[0]; ++a) {
+                    double acc = 0.0;
+                    for (int k = 0; k < nf[2]; ++k)
+                        for (int j = 0; j < nf[1]; ++j)
+                            for (int i = 0; i < nf[0]; ++i)
+                                acc += I1[a * nf[0] + i] * I2[b * nf[1] + j] * I3[c * nf[2] + k] *
+                                       in[v * nef + i + nf[0] * (j + nf[1] * k)];
+                    out[v * nec + a + nc[0] * (b + nc[1] * c)] = acc;
+                }
+}
+
+int orc_restrict(int E, const int *fine_orders, const int *coarse_orders, const double *u,
+                 double *uc)
+{
+    if (E <= 0 || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
+    ensure_tables();
+    long *off = node_offsets(E, fine_orders), *offc = node_offsets(E, coarse_orders);
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e)
+        restrict_element(fine_orders + 3 * e, coarse_orders + 3 * e, u + NV * off[e], uc + NV * offc[e]);
+    free(off);
+    free(offc);
+    return 0;
+}
+
+int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders, const double *u,
+            const double *dudt, int isolated, double *tau_new, double *tau_trad, double *norms,
+            double *varnorms)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (E <= 0 || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
+    for (int i = 0; i < 3 * E; ++i)
+        if (coarse_orders[i] > fine_orders[i]) return -1;
+    ensure_tables();
+    long nc = orc_num_nodes(E, coarse_orders);
+    double *uc = malloc(sizeof(double) * NV * nc);
+    double *rdc = malloc(sizeof(double) * NV * nc);
+    /* I^N q^P and I^N (M^P)^-1 F^P(q^P) */
+    orc_restrict(E, fine_orders, coarse_orders, u, uc);
+    orc_restrict(E, fine_orders, coarse_orders, dudt, rdc);
+    /* (M^N)^-1 F^N (I^N q^P) on the coarse mesh */
+    orc_residual(m, coarse_orders, uc, tau_new, 0, isolated);
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+    long *offc = node_offsets(E, coarse_orders);
+    for (int e = 0; e < E; ++e) {
+        const int *o = coarse_orders + 3 * e;
+        int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+        double *tn = tau_new + NV * offc[e], *tt = tau_trad + NV * offc[e];
+        const double *rd = rdc + NV * offc[e];
+        double mx[2] = {0, 0}, vm[2][NV] = {{0}};
+        for (int v = 0; v < NV; ++v)
+            for (int k = 0; k < n[2]; ++k)
+                for (int j = 0; j < n[1]; ++j)
+                    for (int i = 0; i < n[0]; ++i) {
+                        int node = i + n[0] * (j + n[1] * k);
+                        int x = v * ne + node;
+                        tn[x] = tn[x] - rd[x];
+                        tt[x] = J * g_w[o[0]][i] * g_w[o[1]][j] * g_w[o[2]][k] * tn[x];
+                        double a0 = fabs(tn[x]), a1 = fabs(tt[x]);
+                        if (a0 > vm[0][v]) vm[0][v] = a0;
+                        if (a1 > vm[1][v]) vm[1][v] = a1;
+                    }
+        for (int v = 0; v < NV; ++v) {
+            if (vm[0][v] > mx[0]) mx[0] = vm[0][v];
+            if (vm[1][v] > mx[1]) mx[1] = vm[1][v];
+        }
+        norms[2 * e] = mx[0];
+        norms[2 * e + 1] = mx[1];
+        if (varnorms)
+            for (int f = 0; f < 2; ++f)
+                for (int v = 0; v < NV; ++v) varnorms[(2 * e + f) * NV + v] = vm[f][v];
+    }
+    free(offc);
+    free(uc);
+    free(rdc);
+    return 0;
+}
+
+int orc_num_combos(const int *o)
+{
+    int c = 1;
+    for (int d = 0; d < 3; ++d) c *= (o[d] > 1 ? o[d] - 1 : 1);
+    return c;
+}
+
+int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const double *dudt,
+              const int *elems, int nelems, double *te_new, double *te_trad)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (E <= 0 || check_orders(E, orders)) return -1;
+    for (int i = 0; i < nelems; ++i)
+        if (elems[i] < 0 || elems[i] >= E) return -1;
+    ensure_tables();
+    long *off = node_offsets(E, orders);
+    long *cofs = malloc(sizeof(long) * (nelems + 1));
+    cofs[0] = 0;
+    for (int i = 0; i < nelems; ++i) cofs[i + 1] = cofs[i] + orc_num_combos(orders + 3 * elems[i]);
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+
+#pragma omp parallel for schedule(guided)
+    for (int i = 0; i < nelems; ++i) {
+        int e = elems[i];
+        const int *of = orders + 3 * e;
+        int cmax[3];
+        for (int d = 0; d < 3; ++d) cmax[d] = of[d] > 1 ? of[d] - 1 : 1;
+        int nef = nnodes(of);
+        const double *Q = u + NV * off[e], *R = dudt + NV * off[e];
+        double *qc = malloc(sizeof(double) * NV * nef), *rc = malloc(sizeof(double) * NV * nef);
+        double *res = malloc(sizeof(double) * NV * nef);
+        long slot = cofs[i];
+        for (int c3 = 1; c3 <= cmax[2]; ++c3)
+            for (int c2 = 1; c2 <= cmax[1]; ++c2)
+                for (int c1 = 1; c1 <= cmax[0]; ++c1) {
+                    int oc[3] = {c1, c2, c3};
+                    int n[3] = {c1 + 1, c2 + 1, c3 + 1}, ne = n[0] * n[1] * n[2];
+                    restrict_element(of, oc, Q, qc);
+                    restrict_element(of, oc, R, rc);
+                    /* isolated coarse residual of the single element: a one-element
+                     * periodic mesh with the isolated flag evaluates only V/J */
+                    orc_mesh one = *m;
+                    one.nx = one.ny = one.nz = 1;
+                    for (int d = 0; d < 3; ++d) {
+                        one.lo[d] = 0.0;
+                        one.hi[d] = h[d];
+                    }
+                    long zero = 0;
+                    element_residual(&one, oc, &zero, qc, 0, 0, 1, res);
+                    double mx0 = 0.0, mx1 = 0.0;
+                    for (int v = 0; v < NV; ++v)
+                        for (int k = 0; k < n[2]; ++k)
+                            for (int j = 0; j < n[1]; ++j)
+                                for (int ii = 0; ii < n[0]; ++ii) {
+                                    int x = v * ne + ii + n[0] * (j + n[1] * k);
+                                    double tn = res[x] - rc[x];
+                                    double tt = J * g_w[c1][ii] * g_w[c2][j] * g_w[c3][k] * tn;
+                                    if (fabs(tn) > mx0) mx0 = fabs(tn);
+                                    if (fabs(tt) > mx1) mx1 = fabs(tt);
+                                }
+                    te_new[slot] = mx0;
+                    te_trad[slot] = mx1;
+                    ++slot;
+                }
+        free(qc);
+        free(rc);
+        free(res);
+    }
+    free(cofs);
+    free(off);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Williamson (1980) low-storage third-order Runge-Kutta.                    */
+
+int orc_rk3(const orc_mesh *m, const int *orders, double *u, double dt, int nsteps)
+{
+    static const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+    static const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    int E = m->nx * m->ny * m->nz;
+    if (E <= 0 || check_orders(E, orders) || nsteps < 0) return -1;
+    long n = NV * orc_num_nodes(E, orders);
+    double *r = malloc(sizeof(double) * n), *G = malloc(sizeof(double) * n);
+    for (int step = 0; step < nsteps; ++step)
+        for (int k = 0; k < 3; ++k) {
+            orc_residual(m, orders, u, r, 0, 0); /* r = -dQ/dt */
+            for (long x = 0; x < n; ++x) {
+                G[x] = (k == 0) ? -dt * r[x] : A[k] * G[x] - dt * r[x];
+                u[x] += B[k] * G[x];
+            }
+        }
+    free(r);
+    free(G);
+    return 0;
+}

@@ -1,0 +1,90 @@
+/*
+ * dg_oracle.h -- plain, slow FP64 CPU oracle for the DGSEM residual and the
+ * anisotropic truncation-error (tau) estimate of Rueda-Ramirez, Ferrer, Rubio
+ * et al., "Truncation error-based anisotropic p-adaptation for unsteady flows
+ * for high-order discontinuous Galerkin methods" (arXiv 2210.03523).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU library.
+ *
+ * Conventions (all arrays are host memory owned by the caller):
+ *   - Box mesh of nx*ny*nz equal hexahedra on [lo,hi]; element e = ix + nx*(iy + ny*iz).
+ *   - orders[e*3 + d] = polynomial order N_d (1..ORC_NMAX) of element e in direction d.
+ *   - Natural ragged layout: element e occupies 5*n_e doubles starting at
+ *     5*noff(e), noff = prefix sum of n_e = (N1+1)(N2+1)(N3+1); inside the
+ *     element [var][node], node = i + n1*(j + n2*k).
+ *   - Conserved variables (rho, rho u, rho v, rho w, rho E).
+ *   - Return value 0 on success, -1 on invalid arguments.
+ */
+#ifndef DG_ORACLE_H
+#define DG_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_NMAX 12
+
+typedef struct {
+    int nx, ny, nz;
+    double lo[3], hi[3];
+    int bc[6];       /* faces -x,+x,-y,+y,-z,+z: 0 periodic, 1 slip wall, 2 far field */
+    int flux;        /* 0 Roe, 1 Lax-Friedrichs (Rusanov) */
+    double gamma;
+    double qfar[5];  /* far-field state (conserved) */
+} orc_mesh;
+
+/* 1D tables on Legendre-Gauss-Lobatto nodes. x,w: N+1 entries; D: (N+1)^2 row-major. */
+int orc_lgl(int N, double *x, double *w);
+int orc_dmat(int N, double *D);
+/* I[a*(N+1)+k] = l^N_k(x^M_a): samples the order-N interpolant at the order-M nodes. */
+int orc_interp(int M, int N, double *I);
+/* L2 projection from order K to order N (N <= K), (N+1)x(K+1) row-major. */
+int orc_proj(int N, int K, double *P);
+
+/* Physical flux f.n and numerical flux (kind 0 Roe, 1 LF). */
+void orc_flux_n(const double *q, const double *n, double gamma, double *f);
+void orc_numflux(const double *qL, const double *qR, const double *n, double gamma,
+                 int kind, double *f);
+/* Roe wave decomposition: lam[4], wave[4*5] = alpha_k * r_k. */
+void orc_roe_waves(const double *qL, const double *qR, const double *n, double gamma,
+                   double *lam, double *wave);
+
+/* Node coordinates, natural ragged layout [e][3][node]. */
+int orc_node_coords(const orc_mesh *m, const int *orders, double *xyz);
+long orc_num_nodes(int E, const int *orders);
+
+/* Spatial residual. form 0: new form r = M^-1 F^N = -dQ/dt; form 1: traditional
+ * F^N = M r.  isolated != 0 drops every surface term. */
+int orc_residual(const orc_mesh *m, const int *orders, const double *u, double *r,
+                 int form, int isolated);
+
+/* Element-wise restriction (sampling of the fine polynomial at coarse nodes). */
+int orc_restrict(int E, const int *fine_orders, const int *coarse_orders,
+                 const double *u, double *uc);
+
+/* Coupled (isolated=0) or isolated tau-estimate on one coarse order map.
+ * dudt: fine r = -dQ/dt (new form, non-isolated residual of u on the fine map).
+ * Outputs in the coarse natural ragged layout; norms[e*2+{0,1}] = max |tau_new|,
+ * max |tau_trad| over nodes and variables; varnorms[(e*2+f)*5+v] (nullable). */
+int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
+            const double *u, const double *dudt, int isolated,
+            double *tau_new, double *tau_trad, double *norms, double *varnorms);
+
+/* Number of coarse combinations of an element: prod_d max(1, N_d - 1). */
+int orc_num_combos(const int *order3);
+/* Isolated sweep over every coarse combination (c1 fastest, then c2, then c3;
+ * c_d in 1..max(1,N_d-1)) for the listed elements (natural indices).
+ * te_new/te_trad: for list entry i, the combos of element elems[i] are stored
+ * contiguously, entries ordered as the list. */
+int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const double *dudt,
+              const int *elems, int nelems, double *te_new, double *te_trad);
+
+/* Williamson low-storage RK3, nsteps steps of size dt, in place on u. */
+int orc_rk3(const orc_mesh *m, const int *orders, double *u, double dt, int nsteps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
