@@ -1,0 +1,152 @@
+/*
+ * dgtau.h -- C ABI of the MI355X (gfx950) DGSEM residual and anisotropic
+ * truncation-error estimation library.
+ *
+ * Method: Rueda-Ramirez, Ferrer, Rubio et al., "Truncation error-based
+ * anisotropic p-adaptation for unsteady flows for high-order discontinuous
+ * Galerkin methods" (arXiv 2210.03523).
+ *
+ * General rules
+ *   - Every function returns a dg_status; DG_OK == 0.  On failure the text of
+ *     the error is available from dg_last_error() (thread-local).  Nothing
+ *     throws across this interface.
+ *   - Device pointers are HIP device memory owned by the caller; host pointers
+ *     are marked "host".  Compute calls are asynchronous on the given stream
+ *     (NULL = the legacy default stream) and allocate no memory.
+ *   - Plans own only their internal device buffers (tables, tiles, face lists,
+ *     face-flux and tau scratch).  A plan is immutable after creation; because
+ *     it holds scratch buffers, one plan must not be used by two streams at once.
+ *   - Device state arrays use the PLAN LAYOUT: elements stable-sorted by
+ *     (node-count class, N1, N2, N3, natural index); element p occupies
+ *     5 * n_p consecutive values starting at 5 * node_offset[p], ordered
+ *     [var][node] with node = i + n1*(j + n2*k), n_d = N_d + 1, variables
+ *     (rho, rho u, rho v, rho w, rho E).  dg_plan_layout() returns the
+ *     permutation and offsets.
+ */
+#ifndef DGTAU_H
+#define DGTAU_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dg_status;
+enum {
+    DG_OK = 0,
+    DG_EINVAL = -1,       /* invalid argument (null pointer, bad order, size mismatch) */
+    DG_ENOMEM = -2,       /* device or host allocation failed (plan creation only) */
+    DG_EHIP = -3,         /* a HIP runtime call failed; message in dg_last_error() */
+    DG_EUNSUPPORTED = -4  /* valid request this build does not implement */
+};
+
+enum { DG_BC_PERIODIC = 0, DG_BC_SLIP_WALL = 1, DG_BC_FARFIELD = 2 };
+enum { DG_FLUX_ROE = 0, DG_FLUX_LF = 1 };
+enum { DG_F64 = 0, DG_F32 = 1 };
+/* Residual forms (Section 2.2): NEW = M^-1 F^N(Q) = -dQ/dt, TRAD = F^N(Q) = M * NEW. */
+enum { DG_FORM_NEW = 0, DG_FORM_TRAD = 1 };
+
+#define DG_NMAX 9 /* polynomial orders 1..DG_NMAX in every direction */
+
+typedef struct dg_plan_s *dg_plan;
+
+/* Structured box mesh of nx*ny*nz equal axis-aligned hexahedra on [lo, hi];
+ * natural element index e = ix + nx*(iy + ny*iz).  bc[] per box face in the
+ * order -x,+x,-y,+y,-z,+z; a periodic pair must be periodic on both sides. */
+typedef struct {
+    int32_t nx, ny, nz;
+    double lo[3], hi[3];
+    int32_t bc[6];
+    int32_t flux;     /* DG_FLUX_ROE (the paper's advective flux) or DG_FLUX_LF */
+    double gamma;     /* ratio of specific heats */
+    double q_far[5];  /* conserved far-field state for DG_BC_FARFIELD faces */
+} dg_mesh_desc;
+
+/* Build a plan for the compressible Euler DGSEM (Section 2.1) on the mesh
+ * with per-element anisotropic orders.
+ *   orders_host: host int32 [E][3], natural element order, each in 1..DG_NMAX.
+ *   out: receives the plan (release with dg_plan_destroy).
+ * Errors: DG_EINVAL (bad mesh, orders or periodic pairing), DG_ENOMEM, DG_EHIP. */
+dg_status dg_plan_create(const dg_mesh_desc *mesh, const int32_t *orders_host, dg_plan *out);
+
+/* Build the coarse plan of a tau-estimate (Section 2.3): the same mesh with
+ * coarse orders 1 <= Nc <= Nf per element and direction.  The coarse plan keeps
+ * a reference to the fine one; destroy it before the fine plan. */
+dg_status dg_plan_create_coarse(dg_plan fine, const int32_t *coarse_orders_host, dg_plan *out);
+
+dg_status dg_plan_destroy(dg_plan plan);
+
+/* Layout queries (host outputs, any may be NULL):
+ *   n_elems, n_nodes: element and node counts;
+ *   perm[E]: natural index of plan element p;
+ *   node_offset[E+1]: first node of plan element p (prefix sums of n_p);
+ *   orders[E*3]: orders of plan element p. */
+dg_status dg_plan_layout(dg_plan plan, int64_t *n_elems, int64_t *n_nodes, int64_t *perm,
+                         int64_t *node_offset, int32_t *orders);
+
+/* Node coordinates in the plan layout, device double [E] blocks of [3][n_p]
+ * (x, y, z of every node, same node order as the state). */
+dg_status dg_node_coords(dg_plan plan, double *xyz, hipStream_t stream);
+
+/* Spatial residual of the DGSEM semi-discretisation (Section 2.1, eqs.
+ * DGSEMsystem, DGMassMatrixLeft/Right), strong form on Gauss-Lobatto nodes:
+ *   form DG_FORM_NEW:  r = M^-1 F^N(u)  (= -du/dt)
+ *   form DG_FORM_TRAD: r = F^N(u)        (= M * new form)
+ * isolated != 0 evaluates the isolated operator (end of Section 2.2): surface
+ * numerical fluxes replaced by the inner flux, i.e. no surface terms.
+ *   u, r: device arrays of 5*n_nodes values of type dtype (DG_F64: double,
+ *   DG_F32: float), plan layout; u and r must not overlap. */
+dg_status dg_residual(dg_plan plan, const void *u, void *r, int32_t dtype, int32_t form,
+                      int32_t isolated, hipStream_t stream);
+
+/* Tau-estimate on the coarse order map of `coarse` (Section 2.3, eqs. TEtildedef
+ * and TEdef with the variational DG estimate I F(q) ~ I (M^P)^-1 F^P(q^P)):
+ *   tau_new  = r^Nc(I u) - I dudt        (new form, "without the mass matrix")
+ *   tau_trad = J w_i w_j w_k * tau_new    (traditional form, coarse weights)
+ * I = sampling of the fine element polynomial at the coarse Gauss-Lobatto nodes.
+ *   u: device double, fine plan layout (5*n_fine values).
+ *   dudt: device double fine new-form residual -du/dt (non-isolated), or NULL to
+ *         have it computed here into the fine plan's scratch.
+ *   isolated: 0 coupled coarse residual (mortars between coarse orders), 1 isolated.
+ *   tau_new, tau_trad: device double, coarse plan layout (either may be NULL).
+ *   norms: device double [E_coarse][2], max |tau_new|, max |tau_trad| over nodes and
+ *          the 5 variables of each coarse plan element (may be NULL). */
+dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt,
+                          int32_t isolated, double *tau_new, double *tau_trad, double *norms,
+                          hipStream_t stream);
+
+/* Number of coarse combinations per fine plan element for the sweep:
+ * prod_d max(1, N_d - 1); combo_offset[E+1] (host) gets their prefix sums. */
+dg_status dg_sweep_layout(dg_plan fine, int64_t *combo_offset);
+
+/* Isolated anisotropic truncation-error map (Section 2.3 and Section 3,
+ * approach 2): for every fine plan element and every coarse combination
+ * (c1, c2, c3), c_d in 1..max(1, N_d - 1), enumerated c1 fastest, the maxima
+ * over nodes and variables of |tau_new| and |tau_trad| of the isolated estimate.
+ *   u, dudt: device double, fine plan layout (dudt as for dg_tau_estimate,
+ *            NULL computes it).
+ *   te_new, te_trad: device double [combo_offset[E]] (dg_sweep_layout). */
+dg_status dg_tau_sweep(dg_plan fine, const double *u, const double *dudt, double *te_new,
+                       double *te_trad, hipStream_t stream);
+
+/* nsteps steps of Williamson's low-storage RK3 (Section 4 set-up):
+ * for k = 0,1,2:  g = A_k g - dt * r(u);  u = u + B_k g,
+ * A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15), r = dg_residual new form.
+ *   u, g: device arrays (dtype) of 5*n_nodes values, updated in place; g is
+ *   scratch (its input value is ignored).  One step is captured once into a
+ *   HIP graph per (u, g, dt, dtype) and replayed. */
+dg_status dg_rk3_step(dg_plan plan, void *u, void *g, double dt, int32_t nsteps, int32_t dtype,
+                      hipStream_t stream);
+
+/* Synchronise the device and report a deferred HIP error, if any. */
+dg_status dg_check(void);
+
+/* Message of the last non-OK status on this thread ("" if none). */
+const char *dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

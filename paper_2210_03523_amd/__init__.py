@@ -1,0 +1,255 @@
+"""MI355X (gfx950) DGSEM residual and anisotropic truncation-error estimation.
+
+Thin ctypes binding of ``libdgtau.so`` (C ABI in ``include/dgtau.h``).  Every
+step of the computation runs in the library's HIP kernels; this module only
+marshals arguments: torch CUDA tensors provide device memory and the current
+stream, numpy arrays the host-side order maps.  There is no CPU fallback: if
+the library is not built, or no GPU is present, the calls raise.
+
+Layouts: device state arrays use the plan layout (elements grouped into order
+buckets, ``[elem][var][node]``); :meth:`Plan.to_plan` and
+:meth:`Plan.to_natural` convert from and to the natural ragged layout
+(natural element order ``e = ix + nx*(iy + ny*iz)``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libdgtau.so")
+
+DG_F64, DG_F32 = 0, 1
+FORM_NEW, FORM_TRAD = 0, 1
+NMAX = 9
+
+
+class DGError(RuntimeError):
+    pass
+
+
+class _MeshDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("bc", ctypes.c_int32 * 6), ("flux", ctypes.c_int32),
+                ("gamma", ctypes.c_double), ("q_far", ctypes.c_double * 5)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_I32P = ctypes.POINTER(ctypes.c_int32)
+
+# exported symbol -> argument types (restype is always dg_status = int32, except dg_last_error)
+SIGNATURES = {
+    "dg_plan_create": [ctypes.POINTER(_MeshDesc), _I32P, ctypes.POINTER(_P)],
+    "dg_plan_create_coarse": [_P, _I32P, ctypes.POINTER(_P)],
+    "dg_plan_destroy": [_P],
+    "dg_plan_layout": [_P, _I64P, _I64P, _I64P, _I64P, _I32P],
+    "dg_node_coords": [_P, _P, _P],
+    "dg_residual": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
+    "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P],
+    "dg_sweep_layout": [_P, _I64P],
+    "dg_tau_sweep": [_P, _P, _P, _P, _P, _P],
+    "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
+    "dg_check": [],
+}
+
+
+def lib():
+    """Load libdgtau.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DGError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int32
+        L.dg_last_error.argtypes = []
+        L.dg_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _call(name, *args):
+    st = getattr(lib(), name)(*args)
+    if st != 0:
+        raise DGError(f"{name} failed ({st}): {lib().dg_last_error().decode()}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise DGError("no GPU visible: the HIP library needs a gfx950 device")
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise DGError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return DG_F64
+    if t.dtype == torch.float32:
+        return DG_F32
+    raise DGError(f"unsupported dtype {t.dtype}")
+
+
+def mesh_desc(mesh: dict) -> _MeshDesc:
+    m = _MeshDesc()
+    m.nx, m.ny, m.nz = (int(v) for v in mesh["n"])
+    for d in range(3):
+        m.lo[d] = float(mesh["lo"][d])
+        m.hi[d] = float(mesh["hi"][d])
+    for f in range(6):
+        m.bc[f] = int(mesh["bc"][f])
+    m.flux = int(mesh["flux"])
+    m.gamma = float(mesh["gamma"])
+    for v in range(5):
+        m.q_far[v] = float(mesh["qfar"][v])
+    return m
+
+
+class Plan:
+    """Device plan of a box mesh with per-element orders (natural order [E][3])."""
+
+    def __init__(self, mesh: dict, orders, _parent: "Plan | None" = None):
+        self.mesh = dict(mesh)
+        o = np.ascontiguousarray(np.asarray(orders, dtype=np.int32).reshape(-1, 3))
+        self.orders_natural = o
+        h = ctypes.c_void_p()
+        if _parent is None:
+            md = mesh_desc(mesh)
+            _call("dg_plan_create", ctypes.byref(md), o.ctypes.data_as(_I32P), ctypes.byref(h))
+        else:
+            _call("dg_plan_create_coarse", _parent.handle, o.ctypes.data_as(_I32P), ctypes.byref(h))
+        self.handle = h
+        self.parent = _parent
+        ne = ctypes.c_int64()
+        nn = ctypes.c_int64()
+        _call("dg_plan_layout", h, ctypes.byref(ne), ctypes.byref(nn), None, None, None)
+        self.n_elems, self.n_nodes = int(ne.value), int(nn.value)
+        self.perm = np.zeros(self.n_elems, dtype=np.int64)
+        self.node_offset = np.zeros(self.n_elems + 1, dtype=np.int64)
+        self.orders = np.zeros((self.n_elems, 3), dtype=np.int32)
+        _call("dg_plan_layout", h, None, None, self.perm.ctypes.data_as(_I64P),
+              self.node_offset.ctypes.data_as(_I64P), self.orders.ctypes.data_as(_I32P))
+        counts = np.prod(o.astype(np.int64) + 1, axis=1)
+        self.natural_offset = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        self._idx = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.dg_plan_destroy(h)
+            self.handle = None
+
+    # ------------------------------------------------------------------ layout
+    def _index(self, nv: int) -> np.ndarray:
+        """Gather index: plan position -> natural position (nv values per node)."""
+        if nv not in self._idx:
+            cnt = np.diff(self.node_offset) * nv
+            src = nv * self.natural_offset[self.perm]
+            dst = nv * self.node_offset[:-1]
+            idx = np.repeat(src - dst, cnt) + np.arange(int(cnt.sum()), dtype=np.int64)
+            self._idx[nv] = idx
+        return self._idx[nv]
+
+    def to_plan(self, u_nat, dtype=None, nv: int = 5):
+        """Natural ragged numpy array -> device tensor in the plan layout."""
+        torch = _torch()
+        a = np.asarray(u_nat)[self._index(nv)]
+        t = torch.from_numpy(np.ascontiguousarray(a))
+        if dtype is not None:
+            t = t.to(dtype)
+        return t.cuda()
+
+    def to_natural(self, t, nv: int = 5) -> np.ndarray:
+        """Device tensor in the plan layout -> natural ragged numpy array."""
+        a = t.detach().cpu().numpy()
+        out = np.empty_like(a)
+        out[self._index(nv)] = a
+        return out
+
+    def elem_to_natural(self, a_plan: np.ndarray) -> np.ndarray:
+        """Per-plan-element rows -> natural element order."""
+        out = np.empty_like(a_plan)
+        out[self.perm] = a_plan
+        return out
+
+    def coarse(self, coarse_orders) -> "Plan":
+        return Plan(self.mesh, coarse_orders, _parent=self)
+
+    def node_coords(self):
+        torch = _torch()
+        xyz = torch.empty(3 * self.n_nodes, dtype=torch.float64, device="cuda")
+        _call("dg_node_coords", self.handle, _ptr(xyz), _stream())
+        return xyz
+
+    def combo_offsets(self) -> np.ndarray:
+        off = np.zeros(self.n_elems + 1, dtype=np.int64)
+        _call("dg_sweep_layout", self.handle, off.ctypes.data_as(_I64P))
+        return off
+
+
+# ---------------------------------------------------------------------- entry points
+def residual(plan: Plan, u, form: int = FORM_NEW, isolated: bool = False, out=None):
+    """r = M^-1 F^N(u) (form 0) or F^N(u) (form 1), plan layout, dtype of u."""
+    torch = _torch()
+    if u.numel() != 5 * plan.n_nodes:
+        raise DGError("state size does not match the plan")
+    r = torch.empty_like(u) if out is None else out
+    _call("dg_residual", plan.handle, _ptr(u), _ptr(r), _dtype_code(u), int(form), int(bool(isolated)),
+          _stream())
+    return r
+
+
+def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False):
+    """Returns (tau_new, tau_trad, norms[E,2]) in the coarse plan layout (float64)."""
+    torch = _torch()
+    if coarse.parent is not fine:
+        raise DGError("coarse plan was not built from this fine plan")
+    if u.dtype != torch.float64 or (dudt is not None and dudt.dtype != torch.float64):
+        raise DGError("the tau-estimate runs in float64")
+    tn = torch.empty(5 * coarse.n_nodes, dtype=torch.float64, device="cuda")
+    tt = torch.empty_like(tn)
+    norms = torch.empty((coarse.n_elems, 2), dtype=torch.float64, device="cuda")
+    _call("dg_tau_estimate", fine.handle, coarse.handle, _ptr(u), _ptr(dudt), int(bool(isolated)),
+          _ptr(tn), _ptr(tt), _ptr(norms), _stream())
+    return tn, tt, norms
+
+
+def tau_sweep(plan: Plan, u, dudt=None):
+    """Isolated TE map: (te_new, te_trad) per (plan element, combo), c1 fastest."""
+    torch = _torch()
+    off = plan.combo_offsets()
+    ten = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
+    tet = torch.empty_like(ten)
+    _call("dg_tau_sweep", plan.handle, _ptr(u), _ptr(dudt), _ptr(ten), _ptr(tet), _stream())
+    return ten, tet
+
+
+def rk3_step(plan: Plan, u, g, dt: float, nsteps: int = 1):
+    """Advance u in place by nsteps Williamson RK3 steps (g is scratch of the same shape)."""
+    if u.dtype != g.dtype or u.numel() != g.numel() or u.numel() != 5 * plan.n_nodes:
+        raise DGError("u and g must match the plan and each other")
+    _call("dg_rk3_step", plan.handle, _ptr(u), _ptr(g), float(dt), int(nsteps), _dtype_code(u), _stream())
+    return u
+
+
+def check():
+    _call("dg_check")

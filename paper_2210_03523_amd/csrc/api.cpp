@@ -1,0 +1,466 @@
+// C ABI of the library (declared in include/dgtau.h): plan construction (order
+// buckets, tiles, face lists, tables, scratch) and the host side of every entry
+// point.  All numerical work runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dgtau.h"
+#include "common.h"
+
+using namespace dgt;
+
+namespace {
+
+thread_local std::string g_err;
+
+dg_status fail(dg_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess)                                                               \
+            return fail(DG_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e));         \
+    } while (0)
+
+// Nodal tables, one copy per device, kept until the process ends.
+struct DevTables {
+    double *t64 = nullptr;
+    float *t32 = nullptr;
+};
+std::mutex g_tab_mu;
+std::map<int, DevTables> g_tabs;
+
+dg_status device_tables(DevTables *out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    auto it = g_tabs.find(dev);
+    if (it != g_tabs.end()) {
+        *out = it->second;
+        return DG_OK;
+    }
+    std::vector<double> h64(T_TOT);
+    std::vector<float> h32(T_TOT);
+    build_tables(h64.data(), h32.data());
+    DevTables t;
+    HIP_TRY(hipMalloc(&t.t64, sizeof(double) * T_TOT));
+    HIP_TRY(hipMalloc(&t.t32, sizeof(float) * T_TOT));
+    HIP_TRY(hipMemcpy(t.t64, h64.data(), sizeof(double) * T_TOT, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(t.t32, h32.data(), sizeof(float) * T_TOT, hipMemcpyHostToDevice));
+    g_tabs[dev] = t;
+    *out = t;
+    return DG_OK;
+}
+
+struct TileClass {
+    int npt, first, count;
+};
+
+struct GraphKey {
+    void *u, *g;
+    double dt;
+    int dtype;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(u, g, dt, dtype) < std::tie(o.u, o.g, o.dt, o.dtype);
+    }
+};
+
+}  // namespace
+
+struct dg_plan_s {
+    dg_mesh_desc mesh;
+    int device = 0;
+    int E = 0;
+    int64_t n_nodes = 0, ff_len = 0;
+    std::vector<int32_t> ord;   // plan order [E][3]
+    std::vector<int64_t> perm;  // plan -> natural
+    std::vector<int64_t> inv;   // natural -> plan
+    std::vector<int64_t> noff;  // [E+1]
+    std::vector<TileClass> classes;
+    Geom geom{};
+    PhysParams phys{};
+    DevTables tabs;
+    int nfaces = 0;
+    ElemInfo *d_el = nullptr;
+    Face *d_faces = nullptr;
+    Tile *d_tiles = nullptr;
+    void *d_ff = nullptr;        // face fluxes, sized for doubles
+    double *d_dudt = nullptr;    // fine time-derivative scratch (tau without dudt)
+    // coarse plans
+    dg_plan_s *parent = nullptr;
+    int32_t *d_fine_of = nullptr;
+    double *d_uc = nullptr, *d_rdc = nullptr;
+    // sweep
+    std::vector<int64_t> combo_off;
+    int64_t *d_combo_off = nullptr;
+    SweepTask *d_tasks = nullptr;
+    int ntasks = 0, x1cap = 0, x2cap = 0, max_order = 0;
+    // RK3 graphs
+    hipStream_t cap_stream = nullptr;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+template <typename T>
+dg_status upload(T **dst, const std::vector<T> &src) {
+    if (src.empty()) return DG_OK;
+    HIP_TRY(hipMalloc((void **)dst, sizeof(T) * src.size()));
+    HIP_TRY(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return DG_OK;
+}
+
+void destroy_plan(dg_plan p) {
+    if (!p) return;
+    for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    void *bufs[] = {p->d_el, p->d_faces, p->d_tiles, p->d_ff, p->d_dudt, p->d_fine_of,
+                    p->d_uc, p->d_rdc, p->d_combo_off, p->d_tasks};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+int npt_class(int npe) { return npe <= WG ? 1 : (npe <= 2 * WG ? 2 : 4); }
+
+dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *out) {
+    if (!mesh || !orders || !out) return fail(DG_EINVAL, "null argument");
+    if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(DG_EINVAL, "mesh needs at least one element per direction");
+    const int64_t E64 = (int64_t)mesh->nx * mesh->ny * mesh->nz;
+    if (E64 > (1 << 30)) return fail(DG_EINVAL, "too many elements");
+    for (int d = 0; d < 3; ++d) {
+        if (!(mesh->hi[d] > mesh->lo[d])) return fail(DG_EINVAL, "mesh extent must be positive");
+        int a = mesh->bc[2 * d], b = mesh->bc[2 * d + 1];
+        if (a < 0 || a > 2 || b < 0 || b > 2) return fail(DG_EINVAL, "unknown boundary condition");
+        if ((a == DG_BC_PERIODIC) != (b == DG_BC_PERIODIC)) return fail(DG_EINVAL, "periodic faces must come in pairs");
+    }
+    if (mesh->flux != DG_FLUX_ROE && mesh->flux != DG_FLUX_LF) return fail(DG_EINVAL, "unknown flux");
+    if (!(mesh->gamma > 1.0)) return fail(DG_EINVAL, "gamma must exceed 1");
+    const int E = (int)E64;
+    for (int i = 0; i < 3 * E; ++i)
+        if (orders[i] < 1 || orders[i] > DG_NMAX) return fail(DG_EINVAL, "orders must be in 1..9");
+
+    dg_plan p = new dg_plan_s();
+    p->mesh = *mesh;
+    p->E = E;
+    hipGetDevice(&p->device);
+    dg_status st = device_tables(&p->tabs);
+    if (st) { destroy_plan(p); return st; }
+
+    // stable sort by (tile class, N1, N2, N3), ties by natural index
+    std::vector<int64_t> perm(E);
+    std::iota(perm.begin(), perm.end(), 0);
+    auto key = [&](int64_t e) {
+        const int32_t *o = orders + 3 * e;
+        int npe = (o[0] + 1) * (o[1] + 1) * (o[2] + 1);
+        return std::make_tuple(npt_class(npe), o[0], o[1], o[2]);
+    };
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
+    p->perm = perm;
+    p->inv.assign(E, 0);
+    for (int i = 0; i < E; ++i) p->inv[perm[i]] = i;
+    p->ord.resize(3 * E);
+    p->noff.assign(E + 1, 0);
+    std::vector<ElemInfo> el(E);
+    int64_t foff = 0;
+    for (int i = 0; i < E; ++i) {
+        const int32_t *o = orders + 3 * perm[i];
+        ElemInfo &x = el[i];
+        for (int d = 0; d < 3; ++d) {
+            p->ord[3 * i + d] = o[d];
+            x.n[d] = o[d] + 1;
+            p->max_order = std::max(p->max_order, (int)o[d]);
+        }
+        x.nat = (int32_t)perm[i];
+        x.noff = p->noff[i];
+        x.foff = foff;
+        p->noff[i + 1] = p->noff[i] + (int64_t)x.n[0] * x.n[1] * x.n[2];
+        foff += fblock(x.n);
+    }
+    p->n_nodes = p->noff[E];
+    p->ff_len = foff;
+
+    // tiles: runs of equal orders, chunked to fill a workgroup
+    std::vector<Tile> tiles;
+    for (int i = 0; i < E;) {
+        int j = i;
+        while (j < E && p->ord[3 * j] == p->ord[3 * i] && p->ord[3 * j + 1] == p->ord[3 * i + 1] &&
+               p->ord[3 * j + 2] == p->ord[3 * i + 2])
+            ++j;
+        const int npe = el[i].n[0] * el[i].n[1] * el[i].n[2];
+        const int cls = npt_class(npe);
+        const int cap = npe <= WG ? WG / npe : 1;
+        if (p->classes.empty() || p->classes.back().npt != cls)
+            p->classes.push_back({cls, (int)tiles.size(), 0});
+        for (int k = i; k < j; k += cap) {
+            tiles.push_back({k, std::min(cap, j - k)});
+            p->classes.back().count++;
+        }
+        i = j;
+    }
+
+    // faces: the + face of every element in every direction, plus boundary faces at the minus ends
+    std::vector<Face> faces;
+    const int nd[3] = {mesh->nx, mesh->ny, mesh->nz};
+    for (int e = 0; e < E; ++e) {
+        int c[3] = {e % mesh->nx, (e / mesh->nx) % mesh->ny, e / (mesh->nx * mesh->ny)};
+        for (int d = 0; d < 3; ++d) {
+            int cn[3] = {c[0], c[1], c[2]};
+            if (c[d] == 0 && mesh->bc[2 * d] != DG_BC_PERIODIC)
+                faces.push_back({-1, (int32_t)p->inv[e], d, mesh->bc[2 * d]});
+            if (c[d] == nd[d] - 1) {
+                if (mesh->bc[2 * d + 1] != DG_BC_PERIODIC) {
+                    faces.push_back({(int32_t)p->inv[e], -1, d, mesh->bc[2 * d + 1]});
+                    continue;
+                }
+                cn[d] = 0;
+            } else {
+                cn[d] = c[d] + 1;
+            }
+            int en = cn[0] + mesh->nx * (cn[1] + mesh->ny * cn[2]);
+            faces.push_back({(int32_t)p->inv[e], (int32_t)p->inv[en], d, 0});
+        }
+    }
+    p->nfaces = (int)faces.size();
+
+    // geometry and physics
+    double h[3];
+    for (int d = 0; d < 3; ++d) h[d] = (mesh->hi[d] - mesh->lo[d]) / nd[d];
+    p->geom.J = h[0] * h[1] * h[2] / 8.0;
+    p->geom.Ja[0] = h[1] * h[2] / 4.0;
+    p->geom.Ja[1] = h[0] * h[2] / 4.0;
+    p->geom.Ja[2] = h[0] * h[1] / 4.0;
+    for (int d = 0; d < 3; ++d) {
+        p->geom.h[d] = h[d];
+        p->geom.lo[d] = mesh->lo[d];
+    }
+    p->phys.gamma = mesh->gamma;
+    p->phys.flux = mesh->flux;
+    for (int v = 0; v < NV; ++v) p->phys.qfar[v] = mesh->q_far[v];
+
+    // sweep layout: combos per element and the (p, c1, c2) work list
+    p->combo_off.assign(E + 1, 0);
+    std::vector<SweepTask> tasks;
+    for (int i = 0; i < E; ++i) {
+        int C[3];
+        for (int d = 0; d < 3; ++d) C[d] = std::max(1, p->ord[3 * i + d] - 1);
+        p->combo_off[i + 1] = p->combo_off[i] + (int64_t)C[0] * C[1] * C[2];
+        for (int c2 = 1; c2 <= C[1]; ++c2)
+            for (int c1 = 1; c1 <= C[0]; ++c1) tasks.push_back({i, c1, c2, 0});
+        int f2 = el[i].n[1], f3 = el[i].n[2];
+        int m1 = C[0] + 1, m2 = C[1] + 1;
+        p->x1cap = std::max(p->x1cap, NV * m1 * f2 * f3);
+        p->x2cap = std::max(p->x2cap, NV * m1 * m2 * f3);
+    }
+    p->ntasks = (int)tasks.size();
+
+    if ((st = upload(&p->d_el, el)) || (st = upload(&p->d_faces, faces)) || (st = upload(&p->d_tiles, tiles)) ||
+        (st = upload(&p->d_combo_off, p->combo_off)) || (st = upload(&p->d_tasks, tasks))) {
+        destroy_plan(p);
+        return st;
+    }
+    if (hipMalloc(&p->d_ff, sizeof(double) * std::max<int64_t>(1, p->ff_len)) != hipSuccess ||
+        hipMalloc((void **)&p->d_dudt, sizeof(double) * NV * p->n_nodes) != hipSuccess ||
+        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        destroy_plan(p);
+        return fail(DG_ENOMEM, "device allocation failed");
+    }
+    *out = p;
+    return DG_OK;
+}
+
+// face pass + element pass with the given epilogue
+template <typename T>
+dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s) {
+    const T *tab = std::is_same<T, double>::value ? (const T *)p->tabs.t64 : (const T *)p->tabs.t32;
+    if (!epi.isolated)
+        HIP_TRY(launch_face_flux<T>(p->d_faces, p->nfaces, p->d_el, u, (T *)p->d_ff, tab, p->geom, p->phys, s));
+    for (const TileClass &c : p->classes)
+        HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)p->d_ff, tab, p->geom,
+                                  p->phys, epi, s));
+    return DG_OK;
+}
+
+bool aligned(const void *x) { return ((uintptr_t)x & 15) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+dg_status dg_plan_create(const dg_mesh_desc *mesh, const int32_t *orders_host, dg_plan *out) {
+    return build_plan(mesh, orders_host, out);
+}
+
+dg_status dg_plan_create_coarse(dg_plan fine, const int32_t *coarse_orders_host, dg_plan *out) {
+    if (!fine || !coarse_orders_host || !out) return fail(DG_EINVAL, "null argument");
+    if (fine->parent) return fail(DG_EINVAL, "the fine plan of a coarse plan must not itself be coarse");
+    for (int e = 0; e < fine->E; ++e)
+        for (int d = 0; d < 3; ++d) {
+            int nc = coarse_orders_host[3 * e + d];
+            int nf = fine->ord[3 * fine->inv[e] + d];
+            if (nc < 1 || nc > nf) return fail(DG_EINVAL, "coarse orders must satisfy 1 <= Nc <= Nf");
+        }
+    dg_plan c = nullptr;
+    dg_status st = build_plan(&fine->mesh, coarse_orders_host, &c);
+    if (st) return st;
+    c->parent = fine;
+    std::vector<int32_t> fine_of(c->E);
+    for (int i = 0; i < c->E; ++i) fine_of[i] = (int32_t)fine->inv[c->perm[i]];
+    if ((st = upload(&c->d_fine_of, fine_of))) {
+        destroy_plan(c);
+        return st;
+    }
+    if (hipMalloc((void **)&c->d_uc, sizeof(double) * NV * c->n_nodes) != hipSuccess ||
+        hipMalloc((void **)&c->d_rdc, sizeof(double) * NV * c->n_nodes) != hipSuccess) {
+        destroy_plan(c);
+        return fail(DG_ENOMEM, "device allocation failed");
+    }
+    *out = c;
+    return DG_OK;
+}
+
+dg_status dg_plan_destroy(dg_plan plan) {
+    destroy_plan(plan);
+    return DG_OK;
+}
+
+dg_status dg_plan_layout(dg_plan p, int64_t *n_elems, int64_t *n_nodes, int64_t *perm, int64_t *node_offset,
+                         int32_t *orders) {
+    if (!p) return fail(DG_EINVAL, "null plan");
+    if (n_elems) *n_elems = p->E;
+    if (n_nodes) *n_nodes = p->n_nodes;
+    if (perm) std::copy(p->perm.begin(), p->perm.end(), perm);
+    if (node_offset) std::copy(p->noff.begin(), p->noff.end(), node_offset);
+    if (orders) std::copy(p->ord.begin(), p->ord.end(), orders);
+    return DG_OK;
+}
+
+dg_status dg_node_coords(dg_plan p, double *xyz, hipStream_t stream) {
+    if (!p || !xyz) return fail(DG_EINVAL, "null argument");
+    HIP_TRY(launch_coords(p->d_el, p->E, p->mesh.nx, p->mesh.ny, p->tabs.t64, p->geom, xyz, stream));
+    return DG_OK;
+}
+
+dg_status dg_residual(dg_plan p, const void *u, void *r, int32_t dtype, int32_t form, int32_t isolated,
+                      hipStream_t stream) {
+    if (!p || !u || !r) return fail(DG_EINVAL, "null argument");
+    if (!aligned(u) || !aligned(r)) return fail(DG_EINVAL, "arrays must be 16-byte aligned");
+    if (u == r) return fail(DG_EINVAL, "u and r must not overlap");
+    if (form != DG_FORM_NEW && form != DG_FORM_TRAD) return fail(DG_EINVAL, "unknown form");
+    EpiArgs epi{};
+    epi.mode = EPI_RESIDUAL;
+    epi.form = form;
+    epi.isolated = isolated ? 1 : 0;
+    epi.out = r;
+    if (dtype == DG_F64) return run_residual<double>(p, (const double *)u, epi, stream);
+    if (dtype == DG_F32) return run_residual<float>(p, (const float *)u, epi, stream);
+    return fail(DG_EINVAL, "unknown dtype");
+}
+
+dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt, int32_t isolated,
+                          double *tau_new, double *tau_trad, double *norms, hipStream_t stream) {
+    if (!fine || !coarse || !u) return fail(DG_EINVAL, "null argument");
+    if (coarse->parent != fine) return fail(DG_EINVAL, "coarse plan was not built from this fine plan");
+    if (!tau_new && !tau_trad && !norms) return DG_OK;
+    if (!dudt) {
+        EpiArgs epi{};
+        epi.mode = EPI_RESIDUAL;
+        epi.out = fine->d_dudt;
+        dg_status st = run_residual<double>(fine, u, epi, stream);
+        if (st) return st;
+        dudt = fine->d_dudt;
+    }
+    HIP_TRY(launch_restrict(coarse->d_fine_of, coarse->E, coarse->d_el, fine->d_el, u, dudt, coarse->d_uc,
+                            coarse->d_rdc, fine->tabs.t64, stream));
+    EpiArgs epi{};
+    epi.mode = EPI_TAU;
+    epi.isolated = isolated ? 1 : 0;
+    epi.out = tau_new;
+    epi.out2 = tau_trad;
+    epi.rdc = coarse->d_rdc;
+    epi.norms = norms;
+    return run_residual<double>(coarse, coarse->d_uc, epi, stream);
+}
+
+dg_status dg_sweep_layout(dg_plan p, int64_t *combo_offset) {
+    if (!p || !combo_offset) return fail(DG_EINVAL, "null argument");
+    std::copy(p->combo_off.begin(), p->combo_off.end(), combo_offset);
+    return DG_OK;
+}
+
+dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *te_new, double *te_trad,
+                       hipStream_t stream) {
+    if (!p || !u || !te_new || !te_trad) return fail(DG_EINVAL, "null argument");
+    if (p->max_order > 8) return fail(DG_EUNSUPPORTED, "the sweep supports fine orders up to 8");
+    if (!dudt) {
+        EpiArgs epi{};
+        epi.mode = EPI_RESIDUAL;
+        epi.out = p->d_dudt;
+        dg_status st = run_residual<double>(p, u, epi, stream);
+        if (st) return st;
+        dudt = p->d_dudt;
+    }
+    HIP_TRY(launch_sweep_tasks(p->d_tasks, p->ntasks, p->d_el, p->d_combo_off, u, dudt, p->tabs.t64, p->geom,
+                               p->mesh.gamma, p->x1cap, p->x2cap, te_new, te_trad, stream));
+    return DG_OK;
+}
+
+dg_status dg_rk3_step(dg_plan p, void *u, void *g, double dt, int32_t nsteps, int32_t dtype, hipStream_t stream) {
+    static const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+    static const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    if (!p || !u || !g) return fail(DG_EINVAL, "null argument");
+    if (u == g) return fail(DG_EINVAL, "u and g must not overlap");
+    if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_EINVAL, "unknown dtype");
+    if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return DG_OK;
+    GraphKey key{u, g, dt, dtype};
+    auto it = p->graphs.find(key);
+    if (it == p->graphs.end()) {
+        hipGraph_t graph;
+        HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        dg_status st = DG_OK;
+        for (int k = 0; k < 3 && !st; ++k) {
+            EpiArgs epi{};
+            epi.mode = EPI_RK;
+            epi.rkA = A[k];
+            epi.rkB = B[k];
+            epi.dt = dt;
+            epi.g = g;
+            st = dtype == DG_F64 ? run_residual<double>(p, (const double *)u, epi, p->cap_stream)
+                                 : run_residual<float>(p, (const float *)u, epi, p->cap_stream);
+        }
+        hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+        if (st) return st;
+        if (e != hipSuccess) return fail(DG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        hipGraphExec_t exec;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(DG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        it = p->graphs.emplace(key, exec).first;
+    }
+    for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(it->second, stream));
+    return DG_OK;
+}
+
+dg_status dg_check(void) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+}
+
+const char *dg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

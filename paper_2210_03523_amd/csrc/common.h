@@ -1,0 +1,124 @@
+// Internal definitions shared by the host plan code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dgt {
+
+constexpr int NV = 5;        // conserved variables
+constexpr int NMAX = 9;      // maximum polynomial order
+constexpr int NNMAX = NMAX + 1;
+constexpr int WG = 256;      // threads per workgroup of the element kernels
+
+// 1D tables, packed: orders 1..NMAX, n = N+1 values per order.
+// xoff(N) = sum_{k=1}^{N-1} (k+1)
+__host__ __device__ constexpr inline int xoff(int N) { return (N - 1) * (N + 4) / 2; }
+// doff(N) = sum_{k=1}^{N-1} (k+1)^2
+__host__ __device__ constexpr inline int doff(int N) { return N * (N + 1) * (2 * N + 1) / 6 - 1; }
+constexpr int XTOT = xoff(NMAX + 1);            // 54
+constexpr int DTOT = doff(NMAX + 1);            // 384
+// Matrices indexed by an order pair (A, B) with (A+1) rows and (B+1) columns.
+__host__ __device__ constexpr inline int moff(int A, int B) { return xoff(A) * XTOT + (A + 1) * xoff(B); }
+constexpr int MTOT = XTOT * XTOT;               // 2916
+
+// Table block layout (one block per precision): nodes, weights, D, I, P.
+constexpr int T_X = 0;
+constexpr int T_W = T_X + XTOT;
+constexpr int T_D = T_W + XTOT;
+constexpr int T_I = T_D + DTOT;                 // I^{A<-B}: samples order-B basis at order-A nodes
+constexpr int T_P = T_I + MTOT;                 // P^{A<-B}: L2 projection from order B onto order A (A <= B)
+constexpr int T_TOT = T_P + MTOT;
+
+// Per plan element record (device).
+struct ElemInfo {
+    int32_t n[3];     // nodes per direction (order + 1)
+    int32_t nat;      // natural element index
+    int64_t noff;     // first node of the element
+    int64_t foff;     // first value of the element's face-flux block
+};
+
+// Face between plan elements eL (minus side) and eR (plus side) along direction d.
+// Boundary faces have eL < 0 (box face at the minus end) or eR < 0 (plus end), and bc != 0.
+struct Face {
+    int32_t eL, eR;
+    int32_t d, bc;
+};
+
+// A tile: `count` consecutive plan elements with identical orders.
+struct Tile {
+    int32_t first, count;
+};
+
+// Offset of the face-flux slot (d, side) inside an element's face-flux block.
+__host__ __device__ inline int64_t fslot(const int32_t *n, int d, int side) {
+    int64_t off = 0;
+    for (int dd = 0; dd < d; ++dd) {
+        int a = n[dd == 0 ? 1 : 0], b = n[dd == 2 ? 1 : 2];
+        off += 2 * NV * a * b;
+    }
+    int a = n[d == 0 ? 1 : 0], b = n[d == 2 ? 1 : 2];
+    return off + (side > 0 ? NV * a * b : 0);
+}
+__host__ __device__ inline int64_t fblock(const int32_t *n) {
+    return 2 * NV * ((int64_t)n[1] * n[2] + (int64_t)n[0] * n[2] + (int64_t)n[0] * n[1]);
+}
+
+// Uniform affine geometry of the box elements.
+struct Geom {
+    double J;        // h1 h2 h3 / 8
+    double Ja[3];    // |Ja^d| = J * 2 / h_d
+    double h[3];
+    double lo[3];
+};
+
+struct PhysParams {
+    double gamma;
+    int32_t flux;
+    int32_t pad;
+    double qfar[NV];
+};
+
+// Host-side launch wrappers (defined in the .hip files).
+template <typename T>
+hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems, const T *u, T *fflux,
+                            const T *tab, Geom g, PhysParams ph, hipStream_t s);
+
+enum EpiMode { EPI_RESIDUAL = 0, EPI_RK = 1, EPI_TAU = 2 };
+
+struct EpiArgs {
+    int mode;
+    int form;           // residual: 0 new, 1 traditional
+    int isolated;
+    double rkA, rkB, dt;
+    void *out;          // residual output / tau_new
+    void *out2;         // tau_trad
+    void *g;            // RK register
+    const void *rdc;    // restricted fine time derivative (tau)
+    double *norms;      // [E][2] (tau)
+};
+
+template <typename T>
+hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, const ElemInfo *elems, const T *u,
+                          const T *fflux, const T *tab, Geom g, PhysParams ph, EpiArgs epi, hipStream_t s);
+
+hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
+                           const double *u, const double *dudt, double *uc, double *rdc, const double *tab,
+                           hipStream_t s);
+
+hipError_t launch_coords(const ElemInfo *elems, int E, int nx, int ny, const double *tab, Geom g, double *xyz,
+                         hipStream_t s);
+
+// One workgroup of the isolated sweep: fine plan element p and coarse orders (c1, c2).
+struct SweepTask {
+    int32_t p, c1, c2, pad;
+};
+
+hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *elems, const int64_t *combo_off,
+                              const double *u, const double *dudt, const double *tab, Geom g, double gamma,
+                              int x1cap, int x2cap, double *te_new, double *te_trad, hipStream_t s);
+
+// Host tables (tables.cpp): fills T_TOT values.
+void build_tables(double *tab64, float *tab32);
+
+}  // namespace dgt

@@ -1,0 +1,83 @@
+// Device physics of the compressible Euler equations: physical flux along a
+// coordinate axis and the numerical fluxes at an axis-aligned face.
+//
+// Roe's approximate Riemann solver (the advective flux of the paper's
+// numerical set-up, Section 4): F = (f_L + f_R)/2 - (1/2) sum_k |lam_k| alpha_k r_k
+// with Roe averages, acoustic waves u_n -/+ c, an entropy wave and both shear
+// waves combined; no entropy fix.  The Rusanov (local Lax-Friedrichs) flux is
+// the alternative: F = (f_L + f_R)/2 - (s/2)(Q_R - Q_L), s = max(|u_n| + c).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dgt {
+
+// Flux f_d(q) along the coordinate direction d (unit normal e_d).
+template <typename T>
+__device__ __forceinline__ void flux_axis(const T q[5], int d, T gm1, T f[5]) {
+    T ri = T(1) / q[0];
+    T ud = q[1 + d] * ri;
+    T p = gm1 * (q[4] - T(0.5) * ri * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]));
+    f[0] = q[1 + d];
+    f[1] = q[1] * ud;
+    f[2] = q[2] * ud;
+    f[3] = q[3] * ud;
+    f[1 + d] += p;
+    f[4] = (q[4] + p) * ud;
+}
+
+// Numerical flux through a face with normal s * e_d (s = +-1): returns F . n.
+template <typename T>
+__device__ __forceinline__ void numflux_axis(const T qL[5], const T qR[5], int d, T s, T gamma, int kind,
+                                             T F[5]) {
+    const T gm1 = gamma - T(1);
+    T fL[5], fR[5];
+    flux_axis(qL, d, gm1, fL);
+    flux_axis(qR, d, gm1, fR);
+    const T riL = T(1) / qL[0], riR = T(1) / qR[0];
+    T uL[3] = {qL[1] * riL, qL[2] * riL, qL[3] * riL};
+    T uR[3] = {qR[1] * riR, qR[2] * riR, qR[3] * riR};
+    T pL = gm1 * (qL[4] - T(0.5) * qL[0] * (uL[0] * uL[0] + uL[1] * uL[1] + uL[2] * uL[2]));
+    T pR = gm1 * (qR[4] - T(0.5) * qR[0] * (uR[0] * uR[0] + uR[1] * uR[1] + uR[2] * uR[2]));
+    if (kind == 1) {
+        T cL = sqrt(gamma * pL * riL), cR = sqrt(gamma * pR * riR);
+        T sp = fmax(fabs(uL[d]) + cL, fabs(uR[d]) + cR);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[v] = s * T(0.5) * (fL[v] + fR[v]) - T(0.5) * sp * (qR[v] - qL[v]);
+        return;
+    }
+    T sL = sqrt(qL[0]), sR = sqrt(qR[0]);
+    T ws = T(1) / (sL + sR);
+    T ut[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ut[k] = (sL * uL[k] + sR * uR[k]) * ws;
+    T HL = (qL[4] + pL) * riL, HR = (qR[4] + pR) * riR;
+    T Ht = (sL * HL + sR * HR) * ws;
+    T rt = sL * sR;
+    T q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+    T c2 = gm1 * (Ht - T(0.5) * q2);
+    T c = sqrt(c2);
+    T un = s * ut[d];
+    T du[3] = {uR[0] - uL[0], uR[1] - uL[1], uR[2] - uL[2]};
+    T dun = s * du[d];
+    du[d] = T(0);  // tangential part of the velocity jump
+    T drho = qR[0] - qL[0], dp = pR - pL;
+    T i2c2 = T(1) / (T(2) * c2);
+    T a1 = (dp - rt * c * dun) * i2c2;
+    T a2 = drho - dp / c2;
+    T a4 = (dp + rt * c * dun) * i2c2;
+    T l1 = fabs(un - c) * a1, l2 = fabs(un), l4 = fabs(un + c) * a4;
+    T w2 = l2 * a2, w3 = l2 * rt;
+    T cn = s * c;
+    T utdut = ut[0] * du[0] + ut[1] * du[1] + ut[2] * du[2];
+    T diss[5];
+    diss[0] = l1 + w2 + l4;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) diss[1 + k] = (l1 + w2 + l4) * ut[k] + w3 * du[k];
+    diss[1 + d] += (l4 - l1) * cn;
+    diss[4] = l1 * (Ht - c * un) + w2 * T(0.5) * q2 + w3 * utdut + l4 * (Ht + c * un);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[v] = s * T(0.5) * (fL[v] + fR[v]) - T(0.5) * diss[v];
+}
+
+}  // namespace dgt

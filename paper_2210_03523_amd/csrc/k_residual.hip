@@ -1,0 +1,406 @@
+// DGSEM residual kernels for gfx950 (Section 2.1, strong form on Gauss-Lobatto nodes):
+//
+//   J dQ/dt = -( sum_d D_d Ft^d + SAT ),  Ft^d = |Ja^d| f_d(Q),
+//   SAT(face node of face (d,s)) = (F*_out - s Ft^d) / w_end.
+//
+// Two passes:
+//   k_face  : one wavefront per face.  Gathers both traces, interpolates them onto
+//             the mortar (K = max order per tangential direction) when the orders
+//             differ, evaluates the Riemann flux once in the canonical orientation
+//             (left = minus side, normal +e_d), projects it back onto both faces
+//             (L2 projection; the plus side takes the minus sign) and stores the
+//             outward fluxes F*_out into per-element face slots.
+//   k_elem  : one workgroup per tile (consecutive plan elements with identical
+//             orders).  Loads Q once, stages the directional fluxes through LDS,
+//             applies the 1D derivative matrices (sum factorisation), adds the
+//             lifted surface terms and finishes with an epilogue: the residual in
+//             new or traditional form, a fused low-storage RK3 stage, or the
+//             tau difference of the estimate with per-element maxima.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "euler.h"
+
+namespace dgt {
+
+// Map workgroup ids so that each XCD (dispatch is round-robin over the 8 XCDs)
+// works on a contiguous range of tiles and keeps neighbours in its own L2.
+__device__ __forceinline__ int xcd_remap(int bid, int G) {
+    int q = G >> 3, r = G & 7;
+    int x = bid & 7, l = bid >> 3;
+    return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+__device__ __forceinline__ int face_node(const int32_t *n, int d, int side, int a, int b) {
+    int idx[3];
+    idx[d] = side > 0 ? n[d] - 1 : 0;
+    idx[d == 0 ? 1 : 0] = a;
+    idx[d == 2 ? 1 : 2] = b;
+    return idx[0] + n[0] * (idx[1] + n[1] * idx[2]);
+}
+
+// ---------------------------------------------------------------------------- faces
+template <typename T>
+__global__ __launch_bounds__(64) void k_face(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
+                                             const T *__restrict__ u, T *__restrict__ ff,
+                                             const T *__restrict__ tab, Geom g, PhysParams ph) {
+    __shared__ T sQL[NV][NNMAX * NNMAX];
+    __shared__ T sQR[NV][NNMAX * NNMAX];
+    __shared__ T sF[NV][NNMAX * NNMAX];
+    const Face f = faces[blockIdx.x];
+    const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const T Ja = (T)g.Ja[d];
+    const T gam = (T)ph.gamma;
+    const int lane = threadIdx.x;
+
+    if (f.bc != 0) {
+        const int e = f.eL >= 0 ? f.eL : f.eR;
+        const int s = f.eL >= 0 ? 1 : -1;
+        const ElemInfo E = el[e];
+        const int na = E.n[t1], nb = E.n[t2], ne = E.n[0] * E.n[1] * E.n[2];
+        const T *Q = u + NV * E.noff;
+        T *out = ff + E.foff + fslot(E.n, d, s);
+        for (int m = lane; m < na * nb; m += 64) {
+            int node = face_node(E.n, d, s, m % na, m / na);
+            T qin[NV], qg[NV], F[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qin[v] = Q[v * ne + node];
+            if (f.bc == 1) {  // slip wall: mirror the normal momentum
+#pragma unroll
+                for (int v = 0; v < NV; ++v) qg[v] = qin[v];
+                qg[1 + d] = -qin[1 + d];
+            } else {  // far field
+#pragma unroll
+                for (int v = 0; v < NV; ++v) qg[v] = (T)ph.qfar[v];
+            }
+            numflux_axis(qin, qg, d, (T)s, gam, ph.flux, F);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v * na * nb + m] = Ja * F[v];
+        }
+        return;
+    }
+
+    const ElemInfo L = el[f.eL], R = el[f.eR];
+    const int aL = L.n[t1], bL = L.n[t2], aR = R.n[t1], bR = R.n[t2];
+    const int K1 = aL > aR ? aL : aR, K2 = bL > bR ? bL : bR;
+    const int neL = L.n[0] * L.n[1] * L.n[2], neR = R.n[0] * R.n[1] * R.n[2];
+    for (int m = lane; m < aL * bL; m += 64) {
+        int node = face_node(L.n, d, 1, m % aL, m / aL);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sQL[v][m] = u[NV * L.noff + v * neL + node];
+    }
+    for (int m = lane; m < aR * bR; m += 64) {
+        int node = face_node(R.n, d, -1, m % aR, m / aR);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sQR[v][m] = u[NV * R.noff + v * neR + node];
+    }
+    __syncthreads();
+    const bool confL = (aL == K1 && bL == K2), confR = (aR == K1 && bR == K2);
+    for (int m = lane; m < K1 * K2; m += 64) {
+        const int A = m % K1, B = m / K1;
+        T qL[NV], qR[NV], F[NV];
+        if (confL) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qL[v] = sQL[v][m];
+        } else {
+            const T *S1 = tab + T_I + moff(K1 - 1, aL - 1) + A * aL;
+            const T *S2 = tab + T_I + moff(K2 - 1, bL - 1) + B * bL;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qL[v] = T(0);
+            for (int b = 0; b < bL; ++b) {
+                T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
+                for (int a = 0; a < aL; ++a) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc[v] += S1[a] * sQL[v][a + aL * b];
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) qL[v] += S2[b] * acc[v];
+            }
+        }
+        if (confR) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qR[v] = sQR[v][m];
+        } else {
+            const T *S1 = tab + T_I + moff(K1 - 1, aR - 1) + A * aR;
+            const T *S2 = tab + T_I + moff(K2 - 1, bR - 1) + B * bR;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qR[v] = T(0);
+            for (int b = 0; b < bR; ++b) {
+                T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
+                for (int a = 0; a < aR; ++a) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc[v] += S1[a] * sQR[v][a + aR * b];
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) qR[v] += S2[b] * acc[v];
+            }
+        }
+        numflux_axis(qL, qR, d, T(1), gam, ph.flux, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sF[v][m] = Ja * F[v];
+    }
+    __syncthreads();
+    // project onto each side's face nodes; outward sign (+ for L, - for R)
+    for (int side = 0; side < 2; ++side) {
+        const ElemInfo &E = side == 0 ? L : R;
+        const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
+        const bool conf = side == 0 ? confL : confR;
+        const T sg = side == 0 ? T(1) : T(-1);
+        T *out = ff + E.foff + fslot(E.n, d, side == 0 ? 1 : -1);
+        for (int m = lane; m < na * nb; m += 64) {
+            const int a = m % na, b = m / na;
+            if (conf) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) out[v * na * nb + m] = sg * sF[v][m];
+            } else {
+                const T *P1 = tab + T_P + moff(na - 1, K1 - 1) + a * K1;
+                const T *P2 = tab + T_P + moff(nb - 1, K2 - 1) + b * K2;
+                T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
+                for (int B = 0; B < K2; ++B) {
+                    T in[NV] = {T(0), T(0), T(0), T(0), T(0)};
+                    for (int A = 0; A < K1; ++A) {
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) in[v] += P1[A] * sF[v][A + K1 * B];
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) acc[v] += P2[B] * in[v];
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) out[v * na * nb + m] = sg * acc[v];
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems, const T *u, T *fflux,
+                            const T *tab, Geom g, PhysParams ph, hipStream_t s) {
+    if (nfaces == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_face<T>, dim3(nfaces), dim3(64), 0, s, faces, elems, u, fflux, tab, g, ph);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- elements
+template <typename T, int NPT>
+__global__ __launch_bounds__(WG) void k_elem(const Tile *__restrict__ tiles, int tile0, int ntiles,
+                                             const ElemInfo *__restrict__ el, const T *u,
+                                             const T *__restrict__ ff, const T *__restrict__ tab, Geom g,
+                                             PhysParams ph, EpiArgs epi) {
+    // u is not __restrict__: the RK epilogue writes the stage update in place
+    __shared__ T sF[NV][WG * NPT];
+    const int tid = threadIdx.x;
+    const Tile tl = tiles[tile0 + xcd_remap(blockIdx.x, ntiles)];
+    const ElemInfo E0 = el[tl.first];
+    const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
+    const int npe = n1 * n2 * n3;
+    const int total = tl.count * npe;
+    const T gm1 = (T)(ph.gamma - 1.0);
+    const int64_t fblk = fblock(E0.n);
+
+    T q[NPT][NV], V[NPT][NV];
+    int loc[NPT][3], le[NPT], nd[NPT];
+    bool ok[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int t = tid + k * WG;
+        ok[k] = t < total;
+        le[k] = ok[k] ? t / npe : 0;
+        nd[k] = ok[k] ? t - le[k] * npe : 0;
+        loc[k][0] = nd[k] % n1;
+        loc[k][1] = (nd[k] / n1) % n2;
+        loc[k][2] = nd[k] / (n1 * n2);
+        const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            q[k][v] = ok[k] ? u[base + v * npe + nd[k]] : T(1);
+            V[k][v] = T(0);
+        }
+    }
+    const int nn[3] = {n1, n2, n3};
+    const int stride[3] = {1, n1, n1 * n2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const T Ja = (T)g.Ja[d];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            T f[NV];
+            flux_axis(q[k], d, gm1, f);
+            const int t = tid + k * WG;
+            if (ok[k]) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sF[v][t] = Ja * f[v];
+            }
+        }
+        __syncthreads();
+        const int nd_ = nn[d];
+        const T *Dm = tab + T_D + doff(nd_ - 1);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            if (!ok[k]) continue;
+            const int t = tid + k * WG;
+            const int id = loc[k][d];
+            const T *Drow = Dm + id * nd_;
+            const int tb = t - id * stride[d];
+            for (int m = 0; m < nd_; ++m) {
+                const T dm = Drow[m];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) V[k][v] += dm * sF[v][tb + m * stride[d]];
+            }
+        }
+        __syncthreads();
+    }
+    // lifted surface terms from the face pass
+    if (!epi.isolated) {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            if (!ok[k]) continue;
+            const T *fb = ff + E0.foff + le[k] * fblk;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int id = loc[k][d];
+                const int nd_ = nn[d];
+                if (id != 0 && id != nd_ - 1) continue;
+                const int s = id == 0 ? -1 : 1;
+                const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+                const int na = nn[t1], nb = nn[t2];
+                const int fm = loc[k][t1] + na * loc[k][t2];
+                const T *fs = fb + fslot(E0.n, d, s);
+                const T iw = T(1) / tab[T_W + xoff(nd_ - 1)];
+                const T Ja = (T)g.Ja[d];
+                T f[NV];
+                flux_axis(q[k], d, gm1, f);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) V[k][v] += (fs[v * na * nb + fm] - T(s) * Ja * f[v]) * iw;
+            }
+        }
+    }
+    // epilogue
+    const T invJ = (T)(1.0 / g.J);
+    T mx[NPT][2];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        mx[k][0] = T(0);
+        mx[k][1] = T(0);
+        if (!ok[k]) continue;
+        const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
+        const T www = tab[T_W + xoff(n1 - 1) + loc[k][0]] * tab[T_W + xoff(n2 - 1) + loc[k][1]] *
+                      tab[T_W + xoff(n3 - 1) + loc[k][2]];
+        if (epi.mode == EPI_RESIDUAL) {
+            T *r = (T *)epi.out;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) r[base + v * npe + nd[k]] = epi.form == 0 ? V[k][v] * invJ : www * V[k][v];
+        } else if (epi.mode == EPI_RK) {
+            T *uu = (T *)u;
+            T *G = (T *)epi.g;
+            const T A = (T)epi.rkA, B = (T)epi.rkB, dt = (T)epi.dt;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const int64_t x = base + v * npe + nd[k];
+                const T r = V[k][v] * invJ;
+                const T gn = (epi.rkA == 0.0) ? -dt * r : A * G[x] - dt * r;
+                G[x] = gn;
+                uu[x] = q[k][v] + B * gn;
+            }
+        } else {  // EPI_TAU
+            // no contraction: the coarse residual is rounded exactly as the stored
+            // fine one, so tau vanishes bitwise when the coarse orders equal the fine
+#pragma clang fp contract(off)
+            const T *rd = (const T *)epi.rdc;
+            T *tn = (T *)epi.out;
+            T *tt = (T *)epi.out2;
+            const T Jw = (T)g.J * www;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const int64_t x = base + v * npe + nd[k];
+                const T a = V[k][v] * invJ - rd[x];
+                const T b = Jw * a;
+                if (tn) tn[x] = a;
+                if (tt) tt[x] = b;
+                mx[k][0] = fmax(mx[k][0], fabs(a));
+                mx[k][1] = fmax(mx[k][1], fabs(b));
+            }
+        }
+    }
+    if (epi.mode == EPI_TAU && epi.norms) {
+        // per-element maxima: stage in LDS, then reduce each element's segment
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int t = tid + k * WG;
+            sF[0][t] = mx[k][0];
+            sF[1][t] = mx[k][1];
+        }
+        __syncthreads();
+        if (tl.count == 1) {
+            for (int s = WG * NPT / 2; s > 0; s >>= 1) {
+#pragma unroll
+                for (int k = 0; k < NPT; ++k) {
+                    const int t = tid + k * WG;
+                    if (t < s) {
+                        sF[0][t] = fmax(sF[0][t], sF[0][t + s]);
+                        sF[1][t] = fmax(sF[1][t], sF[1][t + s]);
+                    }
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                epi.norms[2 * (int64_t)tl.first] = (double)sF[0][0];
+                epi.norms[2 * (int64_t)tl.first + 1] = (double)sF[1][0];
+            }
+        } else if (tid < tl.count) {
+            T m0 = T(0), m1 = T(0);
+            for (int i = 0; i < npe; ++i) {
+                m0 = fmax(m0, sF[0][tid * npe + i]);
+                m1 = fmax(m1, sF[1][tid * npe + i]);
+            }
+            epi.norms[2 * (int64_t)(tl.first + tid)] = (double)m0;
+            epi.norms[2 * (int64_t)(tl.first + tid) + 1] = (double)m1;
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, const ElemInfo *elems, const T *u,
+                          const T *fflux, const T *tab, Geom g, PhysParams ph, EpiArgs epi, hipStream_t s) {
+    if (ntiles == 0) return hipSuccess;
+    dim3 grid(ntiles), block(WG);
+    switch (npt) {
+        case 1: hipLaunchKernelGGL((k_elem<T, 1>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi); break;
+        case 2: hipLaunchKernelGGL((k_elem<T, 2>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi); break;
+        case 4: hipLaunchKernelGGL((k_elem<T, 4>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_face_flux<double>(const Face *, int, const ElemInfo *, const double *, double *,
+                                             const double *, Geom, PhysParams, hipStream_t);
+template hipError_t launch_face_flux<float>(const Face *, int, const ElemInfo *, const float *, float *,
+                                            const float *, Geom, PhysParams, hipStream_t);
+template hipError_t launch_element<double>(const Tile *, int, int, int, const ElemInfo *, const double *,
+                                           const double *, const double *, Geom, PhysParams, EpiArgs, hipStream_t);
+template hipError_t launch_element<float>(const Tile *, int, int, int, const ElemInfo *, const float *,
+                                          const float *, const float *, Geom, PhysParams, EpiArgs, hipStream_t);
+
+// ---------------------------------------------------------------------------- coordinates
+__global__ void k_coords(const ElemInfo *__restrict__ el, int nx, int ny, const double *__restrict__ tab, Geom g,
+                         double *__restrict__ xyz) {
+    const ElemInfo E = el[blockIdx.x];
+    const int npe = E.n[0] * E.n[1] * E.n[2];
+    const int c[3] = {E.nat % nx, (E.nat / nx) % ny, E.nat / (nx * ny)};
+    for (int t = threadIdx.x; t < npe; t += blockDim.x) {
+        const int id[3] = {t % E.n[0], (t / E.n[0]) % E.n[1], t / (E.n[0] * E.n[1])};
+        for (int d = 0; d < 3; ++d) {
+            const double xi = tab[T_X + xoff(E.n[d] - 1) + id[d]];
+            xyz[3 * E.noff + d * npe + t] = g.lo[d] + g.h[d] * (c[d] + 0.5 * (xi + 1.0));
+        }
+    }
+}
+
+hipError_t launch_coords(const ElemInfo *elems, int E, int nx, int ny, const double *tab, Geom g, double *xyz,
+                         hipStream_t s) {
+    if (E == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coords, dim3(E), dim3(128), 0, s, elems, nx, ny, tab, g, xyz);
+    return hipGetLastError();
+}
+
+}  // namespace dgt

@@ -1,0 +1,244 @@
+// Tau-estimation kernels for gfx950 (Section 2.3, variational DG estimate).
+//
+//   k_restrict : samples the fine element polynomial of Q and of the fine time
+//                derivative at the coarse Gauss-Lobatto nodes (sum-factorised
+//                I3 (x) I2 (x) I1, staged through LDS), writing the coarse plan
+//                layout.  The coarse residual and the tau difference then run in
+//                the element kernel's tau epilogue.
+//   k_sweep    : the isolated truncation-error map.  One workgroup per (fine
+//                element, c1, c2): the x-interpolation of Q and of the time
+//                derivative is shared by every (c2, c3), the y-interpolation by
+//                every c3; for each c3 the workgroup evaluates the isolated
+//                coarse volume residual V/J, the difference with the restricted
+//                time derivative, both forms and their maxima.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "euler.h"
+
+namespace dgt {
+
+__device__ __forceinline__ int xcd_remap_t(int bid, int G) {
+    int q = G >> 3, r = G & 7;
+    int x = bid & 7, l = bid >> 3;
+    return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
+// ---------------------------------------------------------------------------- restriction
+__global__ __launch_bounds__(256) void k_restrict(const int32_t *__restrict__ fine_of,
+                                                  const ElemInfo *__restrict__ cel,
+                                                  const ElemInfo *__restrict__ fel, const double *__restrict__ u,
+                                                  const double *__restrict__ dudt, double *__restrict__ uc,
+                                                  double *__restrict__ rdc, const double *__restrict__ tab) {
+    __shared__ double sA[NNMAX * NNMAX * NNMAX];
+    __shared__ double sB[NNMAX * NNMAX * NNMAX];
+    const int p = blockIdx.x;
+    const ElemInfo C = cel[p];
+    const ElemInfo F = fel[fine_of[p]];
+    const int f1 = F.n[0], f2 = F.n[1], f3 = F.n[2], nef = f1 * f2 * f3;
+    const int c1 = C.n[0], c2 = C.n[1], c3 = C.n[2], nec = c1 * c2 * c3;
+    const double *I1 = tab + T_I + moff(c1 - 1, f1 - 1);
+    const double *I2 = tab + T_I + moff(c2 - 1, f2 - 1);
+    const double *I3 = tab + T_I + moff(c3 - 1, f3 - 1);
+    for (int field = 0; field < 2; ++field) {
+        const double *src = (field == 0 ? u : dudt) + NV * F.noff;
+        double *dst = (field == 0 ? uc : rdc) + NV * C.noff;
+        for (int v = 0; v < NV; ++v) {
+            // x: sA[a + c1*(j + f2*k)] = sum_i I1[a,i] Q[i + f1*(j + f2*k)]
+            for (int t = threadIdx.x; t < c1 * f2 * f3; t += blockDim.x) {
+                const int a = t % c1, jk = t / c1;
+                const double *row = src + v * nef + f1 * jk;
+                double acc = 0.0;
+                for (int i = 0; i < f1; ++i) acc += I1[a * f1 + i] * row[i];
+                sA[t] = acc;
+            }
+            __syncthreads();
+            // y: sB[a + c1*(b + c2*k)] = sum_j I2[b,j] sA[a + c1*(j + f2*k)]
+            for (int t = threadIdx.x; t < c1 * c2 * f3; t += blockDim.x) {
+                const int a = t % c1, b = (t / c1) % c2, k = t / (c1 * c2);
+                double acc = 0.0;
+                for (int j = 0; j < f2; ++j) acc += I2[b * f2 + j] * sA[a + c1 * (j + f2 * k)];
+                sB[t] = acc;
+            }
+            __syncthreads();
+            // z
+            for (int t = threadIdx.x; t < nec; t += blockDim.x) {
+                const int ab = t % (c1 * c2), c = t / (c1 * c2);
+                double acc = 0.0;
+                for (int k = 0; k < f3; ++k) acc += I3[c * f3 + k] * sB[ab + c1 * c2 * k];
+                dst[v * nec + t] = acc;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
+                           const double *u, const double *dudt, double *uc, double *rdc, const double *tab,
+                           hipStream_t s) {
+    if (ncoarse == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict, dim3(ncoarse), dim3(256), 0, s, fine_of, celems, felems, u, dudt, uc, rdc, tab);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- sweep
+__device__ __forceinline__ double wave_max(double x) {
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+    return x;
+}
+
+constexpr int SW_WG = 256;
+
+// Dynamic LDS layout (doubles): X1 [5][m1][f2][f3] (aliased by the flux stage
+// [5][m1 m2 m3]), X2Q and X2R [5][m1][m2][f3], red [2][4].
+__global__ __launch_bounds__(SW_WG) void k_sweep(const SweepTask *__restrict__ tasks, int ntasks,
+                                                 const ElemInfo *__restrict__ el,
+                                                 const int64_t *__restrict__ combo_off,
+                                                 const double *__restrict__ u, const double *__restrict__ dudt,
+                                                 const double *__restrict__ tab, Geom g, double gamma,
+                                                 int x1cap, int x2cap, double *__restrict__ te_new,
+                                                 double *__restrict__ te_trad) {
+    extern __shared__ double lds[];
+    double *sX1 = lds;
+    double *sX2Q = sX1 + x1cap;
+    double *sX2R = sX2Q + x2cap;
+    double *sRed = sX2R + x2cap;
+    const SweepTask task = tasks[xcd_remap_t(blockIdx.x, ntasks)];
+    const ElemInfo E = el[task.p];
+    const int f1 = E.n[0], f2 = E.n[1], f3 = E.n[2], nef = f1 * f2 * f3;
+    const int m1 = task.c1 + 1, m2 = task.c2 + 1;
+    const int C1 = f1 > 2 ? f1 - 2 : 1, C2 = f2 > 2 ? f2 - 2 : 1, C3 = f3 > 2 ? f3 - 2 : 1;
+    const double *I1 = tab + T_I + moff(m1 - 1, f1 - 1);
+    const double *I2 = tab + T_I + moff(m2 - 1, f2 - 1);
+    const int tid = threadIdx.x;
+    const double gm1 = gamma - 1.0;
+
+    for (int field = 0; field < 2; ++field) {
+        const double *src = (field == 0 ? u : dudt) + NV * E.noff;
+        double *dst = field == 0 ? sX2Q : sX2R;
+        for (int t = tid; t < NV * m1 * f2 * f3; t += SW_WG) {
+            const int a = t % m1, r = t / m1;  // r = v*(f2*f3) + jk
+            const int v = r / (f2 * f3), jk = r - v * (f2 * f3);
+            const double *row = src + v * nef + f1 * jk;
+            double acc = 0.0;
+            for (int i = 0; i < f1; ++i) acc += I1[a * f1 + i] * row[i];
+            sX1[t] = acc;  // index a + m1*(jk + f2*f3*v)
+        }
+        __syncthreads();
+        for (int t = tid; t < NV * m1 * m2 * f3; t += SW_WG) {
+            const int a = t % m1, b = (t / m1) % m2, r = t / (m1 * m2);  // r = v*f3 + k
+            const int v = r / f3, k = r - v * f3;
+            double acc = 0.0;
+            for (int j = 0; j < f2; ++j) acc += I2[b * f2 + j] * sX1[a + m1 * (j + f2 * (k + f3 * v))];
+            dst[t] = acc;  // index a + m1*(b + m2*(k + f3*v))
+        }
+        __syncthreads();
+    }
+
+    const double invJ = 1.0 / g.J;
+    const double *w1 = tab + T_W + xoff(m1 - 1);
+    const double *w2 = tab + T_W + xoff(m2 - 1);
+    double *sF = sX1;  // X1 is dead now
+    for (int c3 = 1; c3 <= C3; ++c3) {
+        const int m3 = c3 + 1, M = m1 * m2 * m3;
+        const double *I3 = tab + T_I + moff(m3 - 1, f3 - 1);
+        const double *w3 = tab + T_W + xoff(m3 - 1);
+        double q[2][NV], V[2][NV];
+        int loc[2][3];
+        bool ok[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int t = tid + k * SW_WG;
+            ok[k] = t < M;
+            const int tt = ok[k] ? t : 0;
+            loc[k][0] = tt % m1;
+            loc[k][1] = (tt / m1) % m2;
+            loc[k][2] = tt / (m1 * m2);
+            const int ab = loc[k][0] + m1 * loc[k][1];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double acc = 0.0;
+                for (int kk = 0; kk < f3; ++kk) acc += I3[loc[k][2] * f3 + kk] * sX2Q[ab + m1 * m2 * (kk + f3 * v)];
+                q[k][v] = ok[k] ? acc : 1.0;
+                V[k][v] = 0.0;
+            }
+        }
+        const int mm[3] = {m1, m2, m3};
+        const int st[3] = {1, m1, m1 * m2};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double Ja = g.Ja[d];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (!ok[k]) continue;
+                double f[NV];
+                flux_axis(q[k], d, gm1, f);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sF[v * M + tid + k * SW_WG] = Ja * f[v];
+            }
+            __syncthreads();
+            const double *Dm = tab + T_D + doff(mm[d] - 1);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (!ok[k]) continue;
+                const int id = loc[k][d];
+                const int tb = tid + k * SW_WG - id * st[d];
+                for (int m = 0; m < mm[d]; ++m) {
+                    const double dm = Dm[id * mm[d] + m];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) V[k][v] += dm * sF[v * M + tb + m * st[d]];
+                }
+            }
+            __syncthreads();
+        }
+        double mx0 = 0.0, mx1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (!ok[k]) continue;
+            const int ab = loc[k][0] + m1 * loc[k][1];
+            const double Jw = g.J * w1[loc[k][0]] * w2[loc[k][1]] * w3[loc[k][2]];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double rc = 0.0;
+                for (int kk = 0; kk < f3; ++kk) rc += I3[loc[k][2] * f3 + kk] * sX2R[ab + m1 * m2 * (kk + f3 * v)];
+                const double a = V[k][v] * invJ - rc;
+                mx0 = fmax(mx0, fabs(a));
+                mx1 = fmax(mx1, fabs(Jw * a));
+            }
+        }
+        mx0 = wave_max(mx0);
+        mx1 = wave_max(mx1);
+        if ((tid & 63) == 0) {
+            sRed[tid >> 6] = mx0;
+            sRed[4 + (tid >> 6)] = mx1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const double r0 = fmax(fmax(sRed[0], sRed[1]), fmax(sRed[2], sRed[3]));
+            const double r1 = fmax(fmax(sRed[4], sRed[5]), fmax(sRed[6], sRed[7]));
+            const int64_t slot = combo_off[task.p] + (task.c1 - 1) + C1 * ((task.c2 - 1) + C2 * (c3 - 1));
+            te_new[slot] = r0;
+            te_trad[slot] = r1;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *elems, const int64_t *combo_off,
+                              const double *u, const double *dudt, const double *tab, Geom g, double gamma,
+                              int x1cap, int x2cap, double *te_new, double *te_trad, hipStream_t s) {
+    if (ntasks == 0) return hipSuccess;
+    size_t lds = sizeof(double) * (size_t)(x1cap + 2 * x2cap + 8);
+    static bool attr_set = false;
+    if (lds > 64 * 1024 && !attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_sweep, dim3(ntasks), dim3(SW_WG), lds, s, (const SweepTask *)tasks, ntasks, elems,
+                       combo_off, u, dudt, tab, g, gamma, x1cap, x2cap, te_new, te_trad);
+    return hipGetLastError();
+}
+
+}  // namespace dgt
