@@ -108,6 +108,8 @@ struct dg_plan_s {
     int64_t *d_combo_off = nullptr;
     SweepTask *d_tasks = nullptr;
     int ntasks = 0, x1cap = 0, x2cap = 0, max_order = 0;
+    int32_t *d_iso = nullptr;           // isotropic elements grouped by fine node count F
+    int iso_first[NNMAX + 1] = {0}, iso_count[NNMAX + 1] = {0};
     // RK3 graphs
     hipStream_t cap_stream = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -128,7 +130,7 @@ void destroy_plan(dg_plan p) {
     for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     void *bufs[] = {p->d_el, p->d_faces, p->d_tiles, p->d_ff, p->d_dudt, p->d_fine_of,
-                    p->d_uc, p->d_rdc, p->d_combo_off, p->d_tasks};
+                    p->d_uc, p->d_rdc, p->d_combo_off, p->d_tasks, p->d_iso};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -251,13 +253,20 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
     p->phys.flux = mesh->flux;
     for (int v = 0; v < NV; ++v) p->phys.qfar[v] = mesh->q_far[v];
 
-    // sweep layout: combos per element and the (p, c1, c2) work list
+    // sweep layout: combos per element; isotropic elements (F <= 8) go to the fast
+    // path grouped by F, the others to the generic (p, c1, c2) work list
     p->combo_off.assign(E + 1, 0);
     std::vector<SweepTask> tasks;
+    std::vector<std::vector<int32_t>> iso(NNMAX + 1);
     for (int i = 0; i < E; ++i) {
         int C[3];
         for (int d = 0; d < 3; ++d) C[d] = std::max(1, p->ord[3 * i + d] - 1);
         p->combo_off[i + 1] = p->combo_off[i] + (int64_t)C[0] * C[1] * C[2];
+        const int F = el[i].n[0];
+        if (F == el[i].n[1] && F == el[i].n[2] && F <= 8) {
+            iso[F].push_back(i);
+            continue;
+        }
         for (int c2 = 1; c2 <= C[1]; ++c2)
             for (int c1 = 1; c1 <= C[0]; ++c1) tasks.push_back({i, c1, c2, 0});
         int f2 = el[i].n[1], f3 = el[i].n[2];
@@ -266,9 +275,16 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
         p->x2cap = std::max(p->x2cap, NV * m1 * m2 * f3);
     }
     p->ntasks = (int)tasks.size();
+    std::vector<int32_t> iso_all;
+    for (int F = 0; F <= NNMAX; ++F) {
+        p->iso_first[F] = (int)iso_all.size();
+        p->iso_count[F] = (int)iso[F].size();
+        iso_all.insert(iso_all.end(), iso[F].begin(), iso[F].end());
+    }
 
     if ((st = upload(&p->d_el, el)) || (st = upload(&p->d_faces, faces)) || (st = upload(&p->d_tiles, tiles)) ||
-        (st = upload(&p->d_combo_off, p->combo_off)) || (st = upload(&p->d_tasks, tasks))) {
+        (st = upload(&p->d_combo_off, p->combo_off)) || (st = upload(&p->d_tasks, tasks)) ||
+        (st = upload(&p->d_iso, iso_all))) {
         destroy_plan(p);
         return st;
     }
@@ -413,6 +429,10 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *t
         if (st) return st;
         dudt = p->d_dudt;
     }
+    for (int F = 2; F <= 8; ++F)
+        if (p->iso_count[F])
+            HIP_TRY(launch_sweep_iso(F, p->d_iso + p->iso_first[F], p->iso_count[F], p->d_el, p->d_combo_off, u,
+                                     dudt, p->tabs.t64, p->geom, p->mesh.gamma, te_new, te_trad, stream));
     HIP_TRY(launch_sweep_tasks(p->d_tasks, p->ntasks, p->d_el, p->d_combo_off, u, dudt, p->tabs.t64, p->geom,
                                p->mesh.gamma, p->x1cap, p->x2cap, te_new, te_trad, stream));
     return DG_OK;

@@ -118,6 +118,11 @@ hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *ele
                               const double *u, const double *dudt, const double *tab, Geom g, double gamma,
                               int x1cap, int x2cap, double *te_new, double *te_trad, hipStream_t s);
 
+// Isotropic fast path of the sweep (fine nodes F per direction, 2 <= F <= 8).
+hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
+                            const double *u, const double *dudt, const double *tab, Geom g, double gamma,
+                            double *te_new, double *te_trad, hipStream_t s);
+
 // Host tables (tables.cpp): fills T_TOT values.
 void build_tables(double *tab64, float *tab32);
 

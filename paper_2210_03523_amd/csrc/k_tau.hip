@@ -242,3 +242,276 @@ hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *ele
 }
 
 }  // namespace dgt
+
+namespace dgt {
+
+// ---------------------------------------------------------------------------- isotropic sweep
+// Fast path of the isolated sweep for elements with the same fine order in every
+// direction (F = N+1 nodes, F <= 8).  With C = max(1, F-2) coarse orders per
+// direction and m = c+1 coarse nodes, the coarse x-rows of two orders c1 and
+// C+1-c1 are stacked (at most C+3 rows) and the coarse y-rows of every c2 are
+// stacked (sum_c m = C(C+3)/2 rows), so one workgroup of 256 lanes covers a
+// pair of c1 values and every c2 (243 lanes at F = 8), each lane owning one
+// z-line (a, b):
+//   - x-interpolation of Q and dQ/dt for the pair, cooperatively, into LDS;
+//   - each lane forms its y-interpolated z-line of both fields in registers;
+//   - for every c3 (compile-time): z-interpolation and the z part of the
+//     derivative in registers with wave-uniform coefficients; x- and y-fluxes
+//     are exchanged through LDS; the tau difference and its maxima per
+//     (c1, c2, c3) are folded with LDS atomics on the bit patterns.
+template <int F>
+__global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ elems, int njobs,
+                                                   const ElemInfo *__restrict__ el,
+                                                   const int64_t *__restrict__ combo_off,
+                                                   const double *__restrict__ u, const double *__restrict__ dudt,
+                                                   const double *__restrict__ tab, Geom g, double gamma,
+                                                   double *__restrict__ te_new, double *__restrict__ te_trad) {
+    constexpr int C = F > 2 ? F - 2 : 1;        // coarse orders per direction
+    constexpr int NPAIR = (C + 1) / 2;
+    constexpr int SUMM = C * (C + 3) / 2;       // stacked coarse rows over every order
+    constexpr int RMAX = C + 3;                 // rows of a pair of x-orders
+    constexpr int MM = C + 1;                   // largest coarse node count
+    constexpr int NL = 256;
+    constexpr int SLOTS = 2 * C * C * 2;        // [c3][c1 of the pair][c2][form]
+    extern __shared__ double lds[];
+    double *S = lds;                                                     // staging / X1
+    unsigned long long *slot = (unsigned long long *)(lds + 2 * NV * MM * NL);
+
+    const int job = xcd_remap_t(blockIdx.x, njobs);
+    const int pair = job % NPAIR;
+    const int p = elems[job / NPAIR];
+    const ElemInfo E = el[p];
+    const int cA = pair + 1, cBr = C - pair;
+    const int cB = cBr == cA ? 0 : cBr;
+    const int mA = cA + 1, mB = cB ? cB + 1 : 0;
+    const int rows = mA + mB;
+    const int lane = threadIdx.x;
+    const double gm1 = gamma - 1.0;
+
+    for (int i = lane; i < SLOTS; i += NL) slot[i] = 0ull;
+
+    // x-interpolation: X1[f][v][row][j][k], row over the pair's stacked coarse x-nodes
+    {
+        const double *IA = tab + T_I + moff(mA - 1, F - 1);
+        const double *IB = tab + T_I + moff((mB ? mB : 2) - 1, F - 1);
+        for (int r = lane; r < 2 * NV * F * F; r += NL) {
+            const int f = r / (NV * F * F), rem = r - f * NV * F * F;  // rem = v*F*F + jk
+            const double *src = (f == 0 ? u : dudt) + NV * E.noff + (int64_t)rem * F;
+            double row[F];
+#pragma unroll
+            for (int i = 0; i < F; ++i) row[i] = src[i];
+            const int v = rem / (F * F), jk = rem - v * F * F;
+            double *dst = S + ((f * NV + v) * RMAX) * (F * F) + jk;
+            for (int a = 0; a < mA; ++a) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < F; ++i) acc += IA[a * F + i] * row[i];
+                dst[a * F * F] = acc;
+            }
+            for (int a = 0; a < mB; ++a) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < F; ++i) acc += IB[a * F + i] * row[i];
+                dst[(mA + a) * F * F] = acc;
+            }
+        }
+    }
+    __syncthreads();
+
+    // lane -> z-line (a, B): a over the pair's rows, B over the stacked y-rows
+    const bool active = lane < rows * SUMM;
+    const int a = active ? lane % rows : 0;
+    const int B = active ? lane / rows : 0;
+    int c2 = 1, b = B;
+    while (c2 < C && b >= c2 + 1) {
+        b -= c2 + 1;
+        ++c2;
+    }
+    const int m2 = c2 + 1;
+    const int B0 = B - b;                       // first stacked row of this c2
+    const bool inA = a < mA;
+    const int c1 = inA ? cA : cB;
+    const int m1 = c1 + 1;
+    const int al = inA ? a : a - mA;            // local x-node
+    const int a0 = inA ? 0 : mA;                // first row of this c1
+
+    // per-lane rows of the 1D operators
+    double Dx[MM], Dy[MM], I2r[F];
+    {
+        const double *dx = tab + T_D + doff(m1 - 1) + al * m1;
+        const double *dy = tab + T_D + doff(m2 - 1) + b * m2;
+        const double *i2 = tab + T_I + moff(m2 - 1, F - 1) + b * F;
+#pragma unroll
+        for (int q = 0; q < MM; ++q) {
+            Dx[q] = q < m1 ? dx[q] : 0.0;
+            Dy[q] = q < m2 ? dy[q] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < F; ++j) I2r[j] = i2[j];
+    }
+    const double w12 = g.J * tab[T_W + xoff(m1 - 1) + al] * tab[T_W + xoff(m2 - 1) + b];
+
+    // y-interpolated z-lines of both fields
+    double XQ[NV][F], XR[NV][F];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double *x1 = S + ((f * NV + v) * RMAX + a) * (F * F);
+#pragma unroll
+            for (int k = 0; k < F; ++k) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < F; ++j) acc += I2r[j] * x1[j + F * k];
+                if (f == 0) XQ[v][k] = acc; else XR[v][k] = acc;
+            }
+        }
+    }
+    __syncthreads();  // X1 is dead; S becomes the flux staging area
+
+    const double invJ = 1.0 / g.J;
+    const double Jax = g.Ja[0], Jay = g.Ja[1], Jaz = g.Ja[2];
+    const int grp = (inA ? 0 : 1) * C + (c2 - 1);
+    double *Sx = S, *Sy = S + NV * MM * NL;
+
+#pragma unroll
+    for (int c3 = 1; c3 <= C; ++c3) {
+        const int m3 = c3 + 1;
+        const double *I3 = tab + T_I + moff(m3 - 1, F - 1);
+        const double *D3 = tab + T_D + doff(m3 - 1);
+        const double *w3 = tab + T_W + xoff(m3 - 1);
+        double Qc[NV][MM], V[NV][MM];
+#pragma unroll
+        for (int c = 0; c < MM; ++c) {
+            if (c >= m3) continue;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < F; ++k) acc += I3[c * F + k] * XQ[v][k];
+                Qc[v][c] = acc;
+                V[v][c] = 0.0;
+            }
+        }
+        // z: flux at each node, then D3 along the line (all in registers)
+#pragma unroll
+        for (int cp = 0; cp < MM; ++cp) {
+            if (cp >= m3) continue;
+            double q[NV], fz[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[v] = Qc[v][cp];
+            flux_axis(q, 2, gm1, fz);
+#pragma unroll
+            for (int c = 0; c < MM; ++c) {
+                if (c >= m3) continue;
+                const double dz = D3[c * m3 + cp];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) V[v][c] += dz * (Jaz * fz[v]);
+            }
+            double fx[NV], fy[NV];
+            flux_axis(q, 0, gm1, fx);
+            flux_axis(q, 1, gm1, fy);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Sx[(v * MM + cp) * NL + lane] = Jax * fx[v];
+                Sy[(v * MM + cp) * NL + lane] = Jay * fy[v];
+            }
+        }
+        __syncthreads();
+        if (active) {
+            // x: neighbours are the lanes of the same y-row and x-order
+#pragma unroll
+            for (int q = 0; q < MM; ++q) {
+                if (q >= m1) continue;
+                const int ln = (a0 + q) + rows * B;
+                const double d = Dx[q];
+#pragma unroll
+                for (int c = 0; c < MM; ++c) {
+                    if (c >= m3) continue;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) V[v][c] += d * Sx[(v * MM + c) * NL + ln];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < MM; ++q) {
+                if (q >= m2) continue;
+                const int ln = a + rows * (B0 + q);
+                const double d = Dy[q];
+#pragma unroll
+                for (int c = 0; c < MM; ++c) {
+                    if (c >= m3) continue;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) V[v][c] += d * Sy[(v * MM + c) * NL + ln];
+                }
+            }
+            double mx0 = 0.0, mx1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < MM; ++c) {
+                if (c >= m3) continue;
+                const double jw = w12 * w3[c];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double rc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < F; ++k) rc += I3[c * F + k] * XR[v][k];
+                    const double t = V[v][c] * invJ - rc;
+                    mx0 = fmax(mx0, fabs(t));
+                    mx1 = fmax(mx1, fabs(jw * t));
+                }
+            }
+            unsigned long long *sl = slot + ((c3 - 1) * 2 * C + grp) * 2;
+            atomicMax(sl, (unsigned long long)__double_as_longlong(mx0));
+            atomicMax(sl + 1, (unsigned long long)__double_as_longlong(mx1));
+        }
+        __syncthreads();
+    }
+    // write the maxima of every (c1, c2, c3) of this workgroup
+    for (int i = lane; i < 2 * C * C; i += NL) {
+        const int c3 = i / (2 * C) + 1, gi = i % (2 * C);
+        const int cc1 = gi < C ? cA : cB;
+        if (cc1 == 0) continue;
+        const int cc2 = gi % C + 1;
+        const int64_t s = combo_off[p] + (cc1 - 1) + C * ((cc2 - 1) + C * (c3 - 1));
+        te_new[s] = __longlong_as_double((long long)slot[2 * i]);
+        te_trad[s] = __longlong_as_double((long long)slot[2 * i + 1]);
+    }
+}
+
+template <int F>
+static hipError_t launch_iso(const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
+                             const double *u, const double *dudt, const double *tab, Geom g, double gamma,
+                             double *te_new, double *te_trad, hipStream_t s) {
+    constexpr int C = F > 2 ? F - 2 : 1;
+    constexpr int MM = C + 1;
+    constexpr int NPAIR = (C + 1) / 2;
+    const size_t lds = sizeof(double) * (size_t)(2 * NV * MM * 256) + sizeof(unsigned long long) * 2 * C * C * 2;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_sweep_iso<F>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int njobs = nelem * NPAIR;
+    hipLaunchKernelGGL(k_sweep_iso<F>, dim3(njobs), dim3(256), lds, s, elems, njobs, el, combo_off, u, dudt, tab,
+                       g, gamma, te_new, te_trad);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
+                            const double *u, const double *dudt, const double *tab, Geom g, double gamma,
+                            double *te_new, double *te_trad, hipStream_t s) {
+    if (nelem == 0) return hipSuccess;
+    switch (F) {
+        case 2: return launch_iso<2>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
+        case 3: return launch_iso<3>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
+        case 4: return launch_iso<4>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
+        case 5: return launch_iso<5>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
+        case 6: return launch_iso<6>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
+        case 7: return launch_iso<7>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
+        case 8: return launch_iso<8>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dgt

@@ -155,6 +155,25 @@ def test_sweep(shape, orng, seed):
     assert err(_sweep_natural(plan, ten2), ten_r, s) < TOL64
 
 
+def test_sweep_isotropic_fast_path():
+    """Elements with equal fine orders in every direction (N = 1..7) take the
+    isotropic sweep kernel; mixed with anisotropic elements in one call."""
+    rng = np.random.default_rng(24)
+    mesh = wl.box_mesh((3, 3, 2))
+    N = rng.integers(1, 8, 18)
+    fo = np.stack([N, N, N], axis=1).astype(np.int32)
+    fo[[2, 11]] = [[3, 5, 2], [7, 6, 7]]
+    u = wl.pulse_state(oracle.node_coords(mesh, fo), fo, sigma=0.2)
+    dudt = oracle.residual(mesh, fo, u)
+    ten_r, tet_r, offs = oracle.sweep(mesh, fo, u, dudt)
+    plan = dg.Plan(mesh, fo)
+    ten, tet = dg.tau_sweep(plan, plan.to_plan(u), plan.to_plan(dudt))
+    s = residual_scale(mesh, fo, u)
+    J = np.prod(1.0 / np.asarray(mesh["n"])) / 8
+    assert err(_sweep_natural(plan, ten), ten_r, s) < TOL64
+    assert err(_sweep_natural(plan, tet), tet_r, s * J) < TOL64
+
+
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
 def test_rk3_graph_replays(dtype, tol):
     mesh, orders = wl.c1()
