@@ -53,7 +53,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-c5", action="store_true", help="skip the batched 64-problem leg")
     ap.add_argument("--n", type=int, default=16)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -64,6 +67,12 @@ def main():
     import paper_2210_03523_amd as dg
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     mesh = wl.box_mesh(args.n)
     E = wl.num_elems(mesh)
     fo = wl.uniform_orders(E, 7)
@@ -128,10 +137,7 @@ def main():
     flops_sweep = sweep_flops_per_element(8) * E
     t_sweep_ms = float(np.mean(t_swp))
     achieved = flops_sweep / (t_sweep_ms * 1e-3) / 1e12
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "sweep_c2_traffic.json")
-    if os.path.exists(tpath):
-        traffic = json.load(open(tpath)).get("bytes_per_launch")
+    traffic = _traffic("k_sweep_iso_c2_traffic.txt")
 
     out = {
         "metric": "GDOF/s residual + tau-estimates/s, batched FP32 vs plain FP64 at stated err",
@@ -163,44 +169,142 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops_sweep},
     }
+    if not args.no_c5:
+        out["batched"] = c5_leg(dg, torch, stream, steps=5, warmup=1, check=not args.no_cpu)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(mesh, fo, co, u_nat, n_fine, n_est, E)
-        # errors of the GPU results against the oracle on the sampled elements
-        out["stages"].update(out["cpu_baseline"].pop("errors"))
-        out["stages"]["err_residual_fp32"] = _err32(plan, r32, out["cpu_baseline"].pop("_ref"))
+        base, ref = cpu_baseline(mesh, fo, co, u_nat, n_fine, n_est, E)
+        out["cpu_baseline"] = base
+        # errors against the oracle: max |x - x_oracle| / max(max |x_oracle|, s), s = scale of
+        # the cancelling terms of the residual
+        s = _scale(mesh, u_nat, 7)
+        dg.residual(plan, u, out=r)
+        dg.residual(plan, u32, out=r32)
+        tn, _, _ = dg.tau_estimate(plan, cplan, u, r)
+        ten, _ = dg.tau_sweep(plan, u, r)
+        off = plan.combo_offsets()
+        ten_h = ten.cpu().numpy()
+        got = np.concatenate([ten_h[off[p]:off[p + 1]] for p in plan.inv_perm()[ref["sweep_elems"]]])
+        out["errors"] = {
+            "measure": "max|x - oracle| / max(max|oracle|, s), s = max|f| |Ja| ||D|| / J",
+            "residual_fp64": _err(plan.to_natural(r), ref["dudt"], s),
+            "residual_fp32": _err(plan.to_natural(r32).astype(np.float64), ref["dudt"], s),
+            "coupled_tau_new_fp64": _err(cplan.to_natural(tn), ref["tau_new"], s),
+            "sweep_te_new_fp64": _err(got, ref["te_new"], s),
+        }
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))
 
 
-def _err32(plan, r32, ref):
-    got = plan.to_natural(r32).astype(np.float64)
-    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+def c5_leg(dg, torch, stream, steps=5, warmup=1, check=True, dt=1e-4):
+    """64 independent periodic problems (n ~ U{8..20} elements per side, orders U{1..7},
+    seeded pulses): RK3 steps of the FP32 batch (one graph per step, one persistent face and
+    one persistent element launch per stage) against plain FP64 per-problem RK3 steps."""
+    probs = wl.c5()
+    plans, u0 = [], []
+    for mesh, orders, centre, sigma in probs:
+        p = dg.Plan(mesh, orders)
+        xyz = p.to_natural(p.node_coords(), nv=3)
+        plans.append(p)
+        u0.append(wl.pulse_state(xyz, orders, centre=centre, sigma=sigma))
+    nodes = sum(p.n_nodes for p in plans)
+    batch = dg.Batch(plans, dtype=torch.float32)
+    u32 = [p.to_plan(u, dtype=torch.float32) for p, u in zip(plans, u0)]
+    g32 = [torch.empty_like(u) for u in u32]
+    u64 = [p.to_plan(u) for p, u in zip(plans, u0)]
+    g64 = [torch.empty_like(u) for u in u64]
+
+    def timed(fn):
+        fn(warmup)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn(steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    t32 = timed(lambda k: dg.batch_rk3_step(batch, u32, g32, dt, k))
+    t64 = timed(lambda k: [dg.rk3_step(p, u, g, dt, k) for p, u, g in zip(plans, u64, g64)])
+    res = {"workload": "64 periodic Euler problems, n ~ U{8..20}^3 elements, orders U{1..7}^3, seed 5",
+           "problems": len(plans), "nodes": nodes, "dt": dt,
+           "schedule": dict(zip(("tile_cap", "elem_grid", "face_grid"), batch.schedule())),
+           "fp32_batched_ms_per_rk3_step": t32, "fp64_plain_ms_per_rk3_step": t64,
+           "fp32_batched_gdof_steps_s": nodes / (t32 * 1e-3) / 1e9,
+           "fp64_plain_gdof_steps_s": nodes / (t64 * 1e-3) / 1e9,
+           "speedup_fp32_batched_over_fp64_plain": t64 / t32}
+    if check:
+        import oracle
+        order = np.argsort([p.n_nodes for p in plans])[:2]
+        e32, e64 = 0.0, 0.0
+        for i in order:
+            mesh, orders, _, _ = probs[i]
+            ref = oracle.rk3(mesh, orders, u0[i], dt, warmup + steps)
+            scale = np.max(np.abs(ref))
+            e32 = max(e32, float(np.max(np.abs(plans[i].to_natural(u32[i]).astype(np.float64) - ref)) / scale))
+            e64 = max(e64, float(np.max(np.abs(plans[i].to_natural(u64[i]) - ref)) / scale))
+        res["err_vs_oracle"] = {"measure": f"max|u - u_oracle| / max|u_oracle| after {warmup + steps} steps, "
+                                           "two smallest problems",
+                                "fp32_batched": e32, "fp64_plain": e64}
+    return res
+
+
+def _traffic(name):
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/), or None when
+    the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line and not line.startswith("#"))
+    src = os.path.join(ROOT, kv["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv["source_sha256_16"]:
+        return None
+    return float(kv["bytes_per_launch"])
+
+
+def _scale(mesh, u_nat, N):
+    """Scale of the cancelling terms of the residual, max |f| * |Ja| * ||D|| / J, with
+    ||D|| = N(N+1)/2 (the error measure of the parity tests)."""
+    q = u_nat.reshape(-1, 5, (N + 1) ** 3).transpose(1, 0, 2).reshape(5, -1)
+    g = mesh["gamma"]
+    vel = q[1:4] / q[0]
+    p = (g - 1) * (q[4] - 0.5 * q[0] * np.sum(vel * vel, axis=0))
+    fmax = float(np.max(np.abs(q[4] + p) * np.max(np.abs(vel), axis=0) + np.abs(p)
+                        + np.max(np.abs(q[1:4]), axis=0) * np.max(np.abs(vel), axis=0)))
+    h = (np.asarray(mesh["hi"]) - np.asarray(mesh["lo"])) / np.asarray(mesh["n"])
+    J = h.prod() / 8
+    return fmax * (h[1] * h[2] / 4) * N * (N + 1) / 2 / J
+
+
+def _err(x, ref, s):
+    return float(np.max(np.abs(x - ref)) / max(float(np.max(np.abs(ref))), s))
 
 
 def cpu_baseline(mesh, fo, co, u_nat, n_fine, n_est, E):
     """The oracle as it stands on the host cores: the full fine residual, the full
-    coupled tau-estimate and the sweep on a sample of 8 elements, scaled to a step."""
+    coupled tau-estimate and the isolated sweep on half of the elements (every other
+    element), scaled to one step.  Returns the rate and the oracle outputs."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
     dudt = oracle.residual(mesh, fo, u_nat)
     t_res = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.tau(mesh, fo, co, u_nat, dudt)
+    tn, tt, norms, _ = oracle.tau(mesh, fo, co, u_nat, dudt)
     t_tau = time.perf_counter() - t0
-    sample = np.arange(0, E, E // 8)[:8]
+    sample = np.arange(0, E, 2)
     t0 = time.perf_counter()
-    oracle.sweep(mesh, fo, u_nat, dudt, elems=sample)
+    ten, tet, _ = oracle.sweep(mesh, fo, u_nat, dudt, elems=sample)
     t_swp = (time.perf_counter() - t0) * E / len(sample)
     t_step = t_res + t_tau + t_swp
-    return {"value": n_fine / t_step / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
+    base = {"value": n_fine / t_step / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
             "sample": f"full fine residual ({t_res:.2f} s) and coupled tau ({t_tau:.2f} s) on the whole "
-                      f"mesh; isolated sweep on {len(sample)} of {E} elements, scaled by {E // len(sample)}",
+                      f"mesh; isolated sweep on {len(sample)} of {E} elements ({t_swp * len(sample) / E:.1f} s), "
+                      f"scaled to all elements",
             "residual_gdof_s": n_fine / t_res / 1e9,
-            "tau_estimates_per_s": n_est / t_swp,
-            "errors": {},
-            "_ref": dudt}
+            "tau_estimates_per_s": n_est / t_swp}
+    return base, {"dudt": dudt, "tau_new": tn, "sweep_elems": sample, "te_new": ten, "te_trad": tet}
 
 
 if __name__ == "__main__":

@@ -140,6 +140,33 @@ dg_status dg_tau_sweep(dg_plan fine, const double *u, const double *dudt, double
 dg_status dg_rk3_step(dg_plan plan, void *u, void *g, double dt, int32_t nsteps, int32_t dtype,
                       hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent problems (plans) advanced by the same launches.
+ * Each residual evaluation / RK3 stage of a batch is one persistent face launch
+ * and one persistent element launch over the cost-sorted work lists of every
+ * problem.  The schedule (tile capacity in nodes, grid sizes) is chosen at
+ * creation by timing candidates on a uniform scratch state (the library's own
+ * autotuner).  The plans must outlive the batch and must not be used on another
+ * stream while the batch runs (their face-flux scratch is shared).
+ * ------------------------------------------------------------------------- */
+typedef struct dg_batch_s *dg_batch;
+
+/* plans: host array of n plans with orders <= 7; dtype DG_F64 or DG_F32 fixes the
+ * state type of every later call.  Allocates and frees scratch for the schedule
+ * search.  Errors: DG_EINVAL, DG_EUNSUPPORTED (order > 7), DG_ENOMEM, DG_EHIP. */
+dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_batch *out);
+dg_status dg_batch_destroy(dg_batch batch);
+/* The schedule the autotuner chose (host outputs, any may be NULL). */
+dg_status dg_batch_schedule(dg_batch batch, int32_t *tile_cap, int32_t *elem_grid, int32_t *face_grid);
+/* New-form residual of every problem (Section 2.1): u[i], r[i] device arrays of
+ * problem i in its plan layout (host arrays of n device pointers). */
+dg_status dg_batch_residual(dg_batch batch, const void *const *u, void *const *r, hipStream_t stream);
+/* nsteps Williamson RK3 steps of every problem (as dg_rk3_step), in place on u[i],
+ * g[i] scratch; one step is captured once per (u, g, dt) pointer set into a HIP graph
+ * of three stages, each one persistent face launch and one persistent element launch. */
+dg_status dg_batch_rk3_step(dg_batch batch, void *const *u, void *const *g, double dt, int32_t nsteps,
+                            hipStream_t stream);
+
 /* Synchronise the device and report a deferred HIP error, if any. */
 dg_status dg_check(void);
 

@@ -55,6 +55,11 @@ SIGNATURES = {
     "dg_tau_sweep": [_P, _P, _P, _P, _P, _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_check": [],
+    "dg_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)],
+    "dg_batch_destroy": [_P],
+    "dg_batch_schedule": [_P, _I32P, _I32P, _I32P],
+    "dg_batch_residual": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P],
+    "dg_batch_rk3_step": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_double, ctypes.c_int32, _P],
 }
 
 
@@ -185,6 +190,12 @@ class Plan:
         out[self._index(nv)] = a
         return out
 
+    def inv_perm(self) -> np.ndarray:
+        """Plan position of every natural element."""
+        inv = np.empty_like(self.perm)
+        inv[self.perm] = np.arange(self.n_elems)
+        return inv
+
     def elem_to_natural(self, a_plan: np.ndarray) -> np.ndarray:
         """Per-plan-element rows -> natural element order."""
         out = np.empty_like(a_plan)
@@ -253,3 +264,50 @@ def rk3_step(plan: Plan, u, g, dt: float, nsteps: int = 1):
 
 def check():
     _call("dg_check")
+
+
+# ---------------------------------------------------------------------- batches
+class Batch:
+    """Independent problems advanced by shared persistent launches (dtype fixed)."""
+
+    def __init__(self, plans, dtype=None):
+        torch = _torch()
+        dtype = torch.float32 if dtype is None else dtype
+        self.plans = list(plans)
+        self.dtype = dtype
+        arr = (_P * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        code = DG_F64 if dtype == torch.float64 else DG_F32
+        _call("dg_batch_create", arr, len(self.plans), code, ctypes.byref(h))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.dg_batch_destroy(h)
+            self.handle = None
+
+    def schedule(self):
+        """(tile capacity in nodes, element grid, face grid) chosen by the autotuner."""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _call("dg_batch_schedule", self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return a.value, b.value, c.value
+
+    def _ptrs(self, ts):
+        if len(ts) != len(self.plans):
+            raise DGError("one tensor per problem expected")
+        for t, p in zip(ts, self.plans):
+            if t.dtype != self.dtype or t.numel() != 5 * p.n_nodes:
+                raise DGError("tensor does not match its plan or the batch dtype")
+        return (_P * len(ts))(*[t.data_ptr() for t in ts])
+
+
+def batch_residual(batch: Batch, us, rs=None):
+    rs = [_torch().empty_like(u) for u in us] if rs is None else rs
+    _call("dg_batch_residual", batch.handle, batch._ptrs(us), batch._ptrs(rs), _stream())
+    return rs
+
+
+def batch_rk3_step(batch: Batch, us, gs, dt: float, nsteps: int = 1):
+    _call("dg_batch_rk3_step", batch.handle, batch._ptrs(us), batch._ptrs(gs), float(dt), int(nsteps), _stream())
+    return us

@@ -484,3 +484,289 @@ dg_status dg_check(void) {
 const char *dg_last_error(void) { return g_err.c_str(); }
 
 }  // extern "C"
+
+// ============================================================================ batches
+// Many independent problems advanced together: one persistent face launch and one
+// persistent element launch per residual evaluation (or RK3 stage) cover every
+// problem.  The schedule (tile capacity, grid sizes) is chosen at creation by
+// timing candidates on a uniform scratch state.
+
+namespace {
+
+struct BatchKey {
+    std::vector<void *> u, g;
+    double dt;
+    bool operator<(const BatchKey &o) const { return std::tie(u, g, dt) < std::tie(o.u, o.g, o.dt); }
+};
+
+}  // namespace
+
+struct dg_batch_s {
+    std::vector<dg_plan> plans;
+    int dtype = DG_F64;
+    int tile_cap = 256, elem_grid = 1024, face_grid = 2048;
+    int ntiles = 0, nfaces = 0;
+    BatchTile *d_tiles = nullptr;
+    int2 *d_faces = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::map<BatchKey, std::pair<void *, hipGraphExec_t>> graphs;  // ProbDesc array + graph
+    void *d_probs_eager = nullptr;                                    // ProbDesc array of eager calls
+};
+
+namespace {
+
+void destroy_batch(dg_batch b) {
+    if (!b) return;
+    for (auto &kv : b->graphs) {
+        (void)hipGraphExecDestroy(kv.second.second);
+        (void)hipFree(kv.second.first);
+    }
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_faces) (void)hipFree(b->d_faces);
+    if (b->d_probs_eager) (void)hipFree(b->d_probs_eager);
+    delete b;
+}
+
+// Tiles of every problem for a tile capacity, sorted by node count (largest first).
+std::vector<BatchTile> batch_tiles(const std::vector<dg_plan> &plans, int cap) {
+    std::vector<std::pair<int, BatchTile>> t;
+    for (int pi = 0; pi < (int)plans.size(); ++pi) {
+        const dg_plan p = plans[pi];
+        for (int i = 0; i < p->E;) {
+            int j = i;
+            while (j < p->E && p->ord[3 * j] == p->ord[3 * i] && p->ord[3 * j + 1] == p->ord[3 * i + 1] &&
+                   p->ord[3 * j + 2] == p->ord[3 * i + 2])
+                ++j;
+            const int npe = (p->ord[3 * i] + 1) * (p->ord[3 * i + 1] + 1) * (p->ord[3 * i + 2] + 1);
+            const int per = std::max(1, cap / npe);
+            for (int k = i; k < j; k += per) {
+                const int cnt = std::min(per, j - k);
+                t.push_back({cnt * npe, BatchTile{pi, k, cnt, 0}});
+            }
+            i = j;
+        }
+    }
+    std::stable_sort(t.begin(), t.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    std::vector<BatchTile> out(t.size());
+    for (size_t i = 0; i < t.size(); ++i) out[i] = t[i].second;
+    return out;
+}
+
+template <typename T>
+std::vector<ProbDesc<T>> prob_descs(dg_batch b, void *const *u, void *const *out, void *const *g) {
+    std::vector<ProbDesc<T>> pd(b->plans.size());
+    for (size_t i = 0; i < pd.size(); ++i) {
+        const dg_plan p = b->plans[i];
+        pd[i].el = p->d_el;
+        pd[i].faces = p->d_faces;
+        pd[i].u = (T *)u[i];
+        pd[i].out = out ? (T *)out[i] : nullptr;
+        pd[i].g = g ? (T *)g[i] : nullptr;
+        pd[i].ff = (T *)p->d_ff;
+        pd[i].geom = p->geom;
+        pd[i].phys = p->phys;
+    }
+    return pd;
+}
+
+template <typename T>
+dg_status batch_pass(dg_batch b, const ProbDesc<T> *probs, EpiArgs epi, hipStream_t s) {
+    const T *tab = std::is_same<T, double>::value ? (const T *)b->plans[0]->tabs.t64
+                                                  : (const T *)b->plans[0]->tabs.t32;
+    HIP_TRY(launch_face_batch<T>(b->d_faces, b->nfaces, probs, tab, b->face_grid, s));
+    HIP_TRY(launch_elem_batch<T>(b->d_tiles, b->ntiles, probs, tab, b->elem_grid, epi, s));
+    return DG_OK;
+}
+
+dg_status set_tiles(dg_batch b, int cap) {
+    auto tiles = batch_tiles(b->plans, cap);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    b->d_tiles = nullptr;
+    b->ntiles = (int)tiles.size();
+    b->tile_cap = cap;
+    return upload(&b->d_tiles, tiles);
+}
+
+// Time the candidate schedules on a uniform scratch state and keep the fastest.
+template <typename T>
+dg_status autotune(dg_batch b) {
+    int64_t tot = 0;
+    for (dg_plan p : b->plans) tot += p->n_nodes;
+    T *su = nullptr, *sr = nullptr;
+    if (hipMalloc((void **)&su, sizeof(T) * NV * tot) != hipSuccess ||
+        hipMalloc((void **)&sr, sizeof(T) * NV * tot) != hipSuccess) {
+        if (su) (void)hipFree(su);
+        return fail(DG_ENOMEM, "device allocation failed");
+    }
+    std::vector<void *> up(b->plans.size()), rp(b->plans.size());
+    int64_t off = 0;
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        up[i] = su + NV * off;
+        rp[i] = sr + NV * off;
+        HIP_TRY(launch_fill_state<T>(b->plans[i]->d_el, b->plans[i]->E, (T *)up[i], b->cap_stream));
+        off += b->plans[i]->n_nodes;
+    }
+    auto pd = prob_descs<T>(b, up.data(), rp.data(), nullptr);
+    ProbDesc<T> *dpd = nullptr;
+    dg_status st = upload(&dpd, pd);
+    if (st) return st;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int dev = 0, cus = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    EpiArgs epi{};
+    epi.mode = EPI_RESIDUAL;
+    float best = 1e30f;
+    int bc = 256, be = cus, bf = 4 * cus;
+    for (int cap : {256, 512}) {
+        if ((st = set_tiles(b, cap))) break;
+        for (int eg : {cus, 2 * cus, 4 * cus, 8 * cus})
+            for (int fg : {4 * cus, 16 * cus}) {
+                b->elem_grid = eg;
+                b->face_grid = fg;
+                if ((st = batch_pass<T>(b, dpd, epi, b->cap_stream))) break;  // warm-up
+                HIP_TRY(hipEventRecord(e0, b->cap_stream));
+                for (int r = 0; r < 3 && !st; ++r) st = batch_pass<T>(b, dpd, epi, b->cap_stream);
+                HIP_TRY(hipEventRecord(e1, b->cap_stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (!st && ms < best) {
+                    best = ms;
+                    bc = cap;
+                    be = eg;
+                    bf = fg;
+                }
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(dpd);
+    (void)hipFree(su);
+    (void)hipFree(sr);
+    if (st) return st;
+    b->elem_grid = be;
+    b->face_grid = bf;
+    return set_tiles(b, bc);
+}
+
+}  // namespace
+
+extern "C" {
+
+dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_batch *out) {
+    if (!plans || n <= 0 || !out) return fail(DG_EINVAL, "null argument or empty batch");
+    if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_EINVAL, "unknown dtype");
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i]) return fail(DG_EINVAL, "null plan in batch");
+        if (plans[i]->max_order > 7) return fail(DG_EUNSUPPORTED, "batched launches support orders up to 7");
+    }
+    dg_batch b = new dg_batch_s();
+    b->plans.assign(plans, plans + n);
+    b->dtype = dtype;
+    std::vector<int2> faces;
+    for (int i = 0; i < n; ++i)
+        for (int f = 0; f < plans[i]->nfaces; ++f) faces.push_back(make_int2(i, f));
+    b->nfaces = (int)faces.size();
+    dg_status st = upload(&b->d_faces, faces);
+    if (!st && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        st = fail(DG_EHIP, "stream creation failed");
+    if (!st) st = dtype == DG_F64 ? autotune<double>(b) : autotune<float>(b);
+    if (!st && hipMalloc(&b->d_probs_eager, sizeof(ProbDesc<double>) * n) != hipSuccess)
+        st = fail(DG_ENOMEM, "device allocation failed");
+    if (st) {
+        destroy_batch(b);
+        return st;
+    }
+    *out = b;
+    return DG_OK;
+}
+
+dg_status dg_batch_destroy(dg_batch b) {
+    destroy_batch(b);
+    return DG_OK;
+}
+
+dg_status dg_batch_schedule(dg_batch b, int32_t *tile_cap, int32_t *elem_grid, int32_t *face_grid) {
+    if (!b) return fail(DG_EINVAL, "null batch");
+    if (tile_cap) *tile_cap = b->tile_cap;
+    if (elem_grid) *elem_grid = b->elem_grid;
+    if (face_grid) *face_grid = b->face_grid;
+    return DG_OK;
+}
+
+dg_status dg_batch_residual(dg_batch b, const void *const *u, void *const *r, hipStream_t stream) {
+    if (!b || !u || !r) return fail(DG_EINVAL, "null argument");
+    for (size_t i = 0; i < b->plans.size(); ++i)
+        if (!u[i] || !r[i] || u[i] == r[i]) return fail(DG_EINVAL, "bad state or residual pointer");
+    EpiArgs epi{};
+    epi.mode = EPI_RESIDUAL;
+    // the descriptor array is written with an ordered copy on the same stream
+    if (b->dtype == DG_F64) {
+        auto pd = prob_descs<double>(b, (void *const *)u, r, nullptr);
+        HIP_TRY(hipMemcpyAsync(b->d_probs_eager, pd.data(), sizeof(pd[0]) * pd.size(), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return batch_pass<double>(b, (const ProbDesc<double> *)b->d_probs_eager, epi, stream);
+    }
+    auto pd = prob_descs<float>(b, (void *const *)u, r, nullptr);
+    HIP_TRY(hipMemcpyAsync(b->d_probs_eager, pd.data(), sizeof(pd[0]) * pd.size(), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return batch_pass<float>(b, (const ProbDesc<float> *)b->d_probs_eager, epi, stream);
+}
+
+dg_status dg_batch_rk3_step(dg_batch b, void *const *u, void *const *g, double dt, int32_t nsteps,
+                            hipStream_t stream) {
+    static const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+    static const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    if (!b || !u || !g) return fail(DG_EINVAL, "null argument");
+    if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+    const size_t n = b->plans.size();
+    for (size_t i = 0; i < n; ++i)
+        if (!u[i] || !g[i] || u[i] == g[i]) return fail(DG_EINVAL, "bad state or register pointer");
+    if (nsteps == 0) return DG_OK;
+    BatchKey key{std::vector<void *>(u, u + n), std::vector<void *>(g, g + n), dt};
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+        void *dpd = nullptr;
+        dg_status st;
+        if (b->dtype == DG_F64) {
+            auto pd = prob_descs<double>(b, u, nullptr, g);
+            st = upload((ProbDesc<double> **)&dpd, pd);
+        } else {
+            auto pd = prob_descs<float>(b, u, nullptr, g);
+            st = upload((ProbDesc<float> **)&dpd, pd);
+        }
+        if (st) return st;
+        hipGraph_t graph;
+        HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < 3 && !st; ++k) {
+            EpiArgs epi{};
+            epi.mode = EPI_RK;
+            epi.rkA = A[k];
+            epi.rkB = B[k];
+            epi.dt = dt;
+            st = b->dtype == DG_F64 ? batch_pass<double>(b, (const ProbDesc<double> *)dpd, epi, b->cap_stream)
+                                    : batch_pass<float>(b, (const ProbDesc<float> *)dpd, epi, b->cap_stream);
+        }
+        hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
+        if (st || e != hipSuccess) {
+            (void)hipFree(dpd);
+            return st ? st : fail(DG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        }
+        hipGraphExec_t exec;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            (void)hipFree(dpd);
+            return fail(DG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        it = b->graphs.emplace(key, std::make_pair(dpd, exec)).first;
+    }
+    for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(it->second.second, stream));
+    return DG_OK;
+}
+
+}  // extern "C"

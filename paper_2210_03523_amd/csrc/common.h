@@ -123,6 +123,34 @@ hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemIn
                             const double *u, const double *dudt, const double *tab, Geom g, double gamma,
                             double *te_new, double *te_trad, hipStream_t s);
 
+// ---------------------------------------------------------------------------- batches
+// One independent problem of a batch, as seen by the persistent kernels.
+template <typename T>
+struct ProbDesc {
+    const ElemInfo *el;
+    const Face *faces;
+    T *u;        // state (read; updated in place by the RK epilogue)
+    T *out;      // residual output
+    T *g;        // RK register
+    T *ff;       // face-flux scratch of the problem's plan
+    Geom geom;
+    PhysParams phys;
+};
+
+// A tile of a batch: `count` consecutive plan elements of problem `prob`.
+struct BatchTile {
+    int32_t prob, first, count, pad;
+};
+
+template <typename T>
+hipError_t launch_face_batch(const int2 *faces, int nfaces, const ProbDesc<T> *probs, const T *tab, int grid,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_elem_batch(const BatchTile *tiles, int ntiles, const ProbDesc<T> *probs, const T *tab, int grid,
+                             EpiArgs epi, hipStream_t s);
+template <typename T>
+hipError_t launch_fill_state(const ElemInfo *el, int E, T *u, hipStream_t s);
+
 // Host tables (tables.cpp): fills T_TOT values.
 void build_tables(double *tab64, float *tab32);
 

@@ -41,13 +41,20 @@ __device__ __forceinline__ int face_node(const int32_t *n, int d, int side, int 
 
 // ---------------------------------------------------------------------------- faces
 template <typename T>
-__global__ __launch_bounds__(64) void k_face(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
-                                             const T *__restrict__ u, T *__restrict__ ff,
-                                             const T *__restrict__ tab, Geom g, PhysParams ph) {
-    __shared__ T sQL[NV][NNMAX * NNMAX];
-    __shared__ T sQR[NV][NNMAX * NNMAX];
-    __shared__ T sF[NV][NNMAX * NNMAX];
-    const Face f = faces[blockIdx.x];
+struct FaceSmem {
+    T QL[NV][NNMAX * NNMAX];
+    T QR[NV][NNMAX * NNMAX];
+    T F[NV][NNMAX * NNMAX];
+};
+
+// One face, processed by one wavefront (64 lanes).
+template <typename T>
+__device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restrict__ el, const T *__restrict__ u,
+                                          T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
+                                          const PhysParams &ph, FaceSmem<T> &sm) {
+    T(&sQL)[NV][NNMAX * NNMAX] = sm.QL;
+    T(&sQR)[NV][NNMAX * NNMAX] = sm.QR;
+    T(&sF)[NV][NNMAX * NNMAX] = sm.F;
     const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const T Ja = (T)g.Ja[d];
     const T gam = (T)ph.gamma;
@@ -173,6 +180,14 @@ __global__ __launch_bounds__(64) void k_face(const Face *__restrict__ faces, con
 }
 
 template <typename T>
+__global__ __launch_bounds__(64) void k_face(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
+                                             const T *__restrict__ u, T *__restrict__ ff,
+                                             const T *__restrict__ tab, Geom g, PhysParams ph) {
+    __shared__ FaceSmem<T> sm;
+    face_body<T>(faces[blockIdx.x], el, u, ff, tab, g, ph, sm);
+}
+
+template <typename T>
 hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems, const T *u, T *fflux,
                             const T *tab, Geom g, PhysParams ph, hipStream_t s) {
     if (nfaces == 0) return hipSuccess;
@@ -181,15 +196,13 @@ hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems
 }
 
 // ---------------------------------------------------------------------------- elements
+// One tile of elements, processed by one workgroup of WG lanes.
+// u is not __restrict__: the RK epilogue writes the stage update in place.
 template <typename T, int NPT>
-__global__ __launch_bounds__(WG) void k_elem(const Tile *__restrict__ tiles, int tile0, int ntiles,
-                                             const ElemInfo *__restrict__ el, const T *u,
-                                             const T *__restrict__ ff, const T *__restrict__ tab, Geom g,
-                                             PhysParams ph, EpiArgs epi) {
-    // u is not __restrict__: the RK epilogue writes the stage update in place
-    __shared__ T sF[NV][WG * NPT];
+__device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restrict__ el, const T *u,
+                                          const T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
+                                          const PhysParams &ph, const EpiArgs &epi, T (&sF)[NV][WG * NPT]) {
     const int tid = threadIdx.x;
-    const Tile tl = tiles[tile0 + xcd_remap(blockIdx.x, ntiles)];
     const ElemInfo E0 = el[tl.first];
     const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
     const int npe = n1 * n2 * n3;
@@ -358,6 +371,15 @@ __global__ __launch_bounds__(WG) void k_elem(const Tile *__restrict__ tiles, int
     }
 }
 
+template <typename T, int NPT>
+__global__ __launch_bounds__(WG) void k_elem(const Tile *__restrict__ tiles, int tile0, int ntiles,
+                                             const ElemInfo *__restrict__ el, const T *u,
+                                             const T *__restrict__ ff, const T *__restrict__ tab, Geom g,
+                                             PhysParams ph, EpiArgs epi) {
+    __shared__ T sF[NV][WG * NPT];
+    elem_body<T, NPT>(tiles[tile0 + xcd_remap(blockIdx.x, ntiles)], el, u, ff, tab, g, ph, epi, sF);
+}
+
 template <typename T>
 hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, const ElemInfo *elems, const T *u,
                           const T *fflux, const T *tab, Geom g, PhysParams ph, EpiArgs epi, hipStream_t s) {
@@ -371,6 +393,81 @@ hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, con
     }
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------- batches
+// Persistent forms: a fixed grid walks a cost-sorted work list (static cyclic
+// schedule, no atomics), so one launch covers every problem of a batch.
+template <typename T>
+__global__ __launch_bounds__(64) void k_face_batch(const int2 *__restrict__ faces, int nfaces,
+                                                   const ProbDesc<T> *__restrict__ probs, const T *__restrict__ tab) {
+    __shared__ FaceSmem<T> sm;
+    for (int i = blockIdx.x; i < nfaces; i += gridDim.x) {
+        const int2 pf = faces[i];
+        const ProbDesc<T> pd = probs[pf.x];
+        face_body<T>(pd.faces[pf.y], pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, sm);
+        __syncthreads();
+    }
+}
+
+template <typename T, int NPT>
+__global__ __launch_bounds__(WG) void k_elem_batch(const BatchTile *__restrict__ tiles, int ntiles,
+                                                   const ProbDesc<T> *__restrict__ probs, const T *__restrict__ tab,
+                                                   EpiArgs epi0) {
+    __shared__ T sF[NV][WG * NPT];
+    for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
+        const BatchTile bt = tiles[i];
+        const ProbDesc<T> pd = probs[bt.prob];
+        EpiArgs epi = epi0;
+        epi.out = pd.out;
+        epi.g = pd.g;
+        elem_body<T, NPT>(Tile{bt.first, bt.count}, pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, epi, sF);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+hipError_t launch_face_batch(const int2 *faces, int nfaces, const ProbDesc<T> *probs, const T *tab, int grid,
+                             hipStream_t s) {
+    if (nfaces == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_face_batch<T>, dim3(grid), dim3(64), 0, s, faces, nfaces, probs, tab);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_elem_batch(const BatchTile *tiles, int ntiles, const ProbDesc<T> *probs, const T *tab, int grid,
+                             EpiArgs epi, hipStream_t s) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_elem_batch<T, 2>), dim3(grid), dim3(WG), 0, s, tiles, ntiles, probs, tab, epi);
+    return hipGetLastError();
+}
+
+// Uniform admissible state (rho, rho u, rho v, rho w, rho E) = (1, 0.1, 0, 0, 2.505) in every
+// element: scratch input of the schedule search.
+template <typename T>
+__global__ void k_fill_state(const ElemInfo *__restrict__ el, T *__restrict__ u) {
+    const ElemInfo E = el[blockIdx.x];
+    const int npe = E.n[0] * E.n[1] * E.n[2];
+    const T q[NV] = {T(1), T(0.1), T(0), T(0), T(2.505)};
+    for (int t = threadIdx.x; t < NV * npe; t += blockDim.x) u[NV * E.noff + t] = q[t / npe];
+}
+
+template <typename T>
+hipError_t launch_fill_state(const ElemInfo *el, int E, T *u, hipStream_t s) {
+    if (E == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_state<T>, dim3(E), dim3(256), 0, s, el, u);
+    return hipGetLastError();
+}
+
+template hipError_t launch_face_batch<double>(const int2 *, int, const ProbDesc<double> *, const double *, int,
+                                              hipStream_t);
+template hipError_t launch_face_batch<float>(const int2 *, int, const ProbDesc<float> *, const float *, int,
+                                             hipStream_t);
+template hipError_t launch_elem_batch<double>(const BatchTile *, int, const ProbDesc<double> *, const double *, int,
+                                              EpiArgs, hipStream_t);
+template hipError_t launch_elem_batch<float>(const BatchTile *, int, const ProbDesc<float> *, const float *, int,
+                                             EpiArgs, hipStream_t);
+template hipError_t launch_fill_state<double>(const ElemInfo *, int, double *, hipStream_t);
+template hipError_t launch_fill_state<float>(const ElemInfo *, int, float *, hipStream_t);
 
 template hipError_t launch_face_flux<double>(const Face *, int, const ElemInfo *, const double *, double *,
                                              const double *, Geom, PhysParams, hipStream_t);

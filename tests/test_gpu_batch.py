@@ -1,0 +1,73 @@
+"""GPU parity of the batched form: many independent problems of uneven size and
+random anisotropic orders in shared persistent launches, against the FP64 oracle
+problem by problem (FP64 within 1e-12, FP32 within 1e-5 of the cancelling-term scale)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from helpers import residual_scale
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2210_03523_amd as dg  # noqa: E402
+
+
+def _problems(nprob=7, seed=31):
+    probs = wl.c5(seed=seed, nprob=nprob, nrange=(1, 4), orange=(1, 7))
+    out = []
+    for mesh, orders, centre, sigma in probs:
+        u = wl.pulse_state(oracle.node_coords(mesh, orders), orders, centre=centre, sigma=max(sigma, 0.15))
+        out.append((mesh, orders, u))
+    return out
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_batch_residual(dtype, tol):
+    probs = _problems()
+    plans = [dg.Plan(m, o) for m, o, _ in probs]
+    batch = dg.Batch(plans, dtype=dtype)
+    cap, eg, fg = batch.schedule()
+    assert cap in (256, 512) and eg > 0 and fg > 0
+    us = [p.to_plan(u, dtype=dtype) for p, (_, _, u) in zip(plans, probs)]
+    rs = dg.batch_residual(batch, us)
+    for p, (m, o, u), r in zip(plans, probs, rs):
+        ref = oracle.residual(m, o, u)
+        s = residual_scale(m, o, u)
+        e = np.max(np.abs(p.to_natural(r).astype(np.float64) - ref)) / max(np.max(np.abs(ref)), s)
+        assert e < tol
+        # same answer as the single-problem path
+        r1 = dg.residual(p, us[plans.index(p)])
+        if dtype == torch.float64:
+            assert torch.allclose(r1, r, rtol=0, atol=1e-13 * s)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
+def test_batch_rk3_graph(dtype, tol):
+    probs = _problems(nprob=5, seed=32)
+    plans = [dg.Plan(m, o) for m, o, _ in probs]
+    batch = dg.Batch(plans, dtype=dtype)
+    us = [p.to_plan(u, dtype=dtype) for p, (_, _, u) in zip(plans, probs)]
+    gs = [torch.empty_like(u) for u in us]
+    refs = [u.copy() for _, _, u in probs]
+    dt = 1e-3
+    for chunk in (1, 3):  # replays of the captured step, with syncs in between
+        dg.batch_rk3_step(batch, us, gs, dt, chunk)
+        torch.cuda.synchronize()
+        for i, (m, o, _) in enumerate(probs):
+            refs[i] = oracle.rk3(m, o, refs[i], dt, chunk)
+            got = plans[i].to_natural(us[i]).astype(np.float64)
+            assert np.max(np.abs(got - refs[i])) / np.max(np.abs(refs[i])) < tol
+
+
+def test_batch_rejects_mismatched_tensors():
+    probs = _problems(nprob=2, seed=33)
+    plans = [dg.Plan(m, o) for m, o, _ in probs]
+    batch = dg.Batch(plans, dtype=torch.float32)
+    us = [p.to_plan(u, dtype=torch.float64) for p, (_, _, u) in zip(plans, probs)]
+    with pytest.raises(dg.DGError):
+        dg.batch_residual(batch, us)

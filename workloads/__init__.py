@@ -65,33 +65,37 @@ def conserved(rho, u, v, w, p, gamma=GAMMA):
     return np.stack([rho, rho * u, rho * v, rho * w, E])
 
 
-def _ragged_apply(xyz, orders, fn):
-    """Evaluate fn(x, y, z) -> [5, npts] per element and scatter into the ragged layout."""
-    offs = node_offsets(orders)
-    out = np.zeros(5 * int(offs[-1]))
-    # all elements at once: coordinates are [e][3][node]; gather x, y, z per node
+def _node_index(orders):
+    """Per-node element index and local node index of the natural ragged layout."""
     counts = node_counts(orders)
-    # build index arrays for the [3][node] blocks
-    starts = 3 * offs[:-1]
-    x = np.empty(int(offs[-1]))
-    y = np.empty_like(x)
-    z = np.empty_like(x)
-    pos = 0
-    for e in range(len(counts)):
-        c = int(counts[e])
-        s = int(starts[e])
-        x[pos:pos + c] = xyz[s:s + c]
-        y[pos:pos + c] = xyz[s + c:s + 2 * c]
-        z[pos:pos + c] = xyz[s + 2 * c:s + 3 * c]
-        pos += c
-    q = fn(x, y, z)  # [5, ntot]
-    pos = 0
-    for e in range(len(counts)):
-        c = int(counts[e])
-        s = 5 * int(offs[e])
-        out[s:s + 5 * c] = q[:, pos:pos + c].reshape(-1)
-        pos += c
+    offs = node_offsets(orders)
+    elem = np.repeat(np.arange(len(counts)), counts)
+    local = np.arange(int(offs[-1])) - offs[:-1][elem]
+    return counts, offs, elem, local
+
+
+def _scatter(q, orders):
+    """[nv, total_nodes] per-node values -> natural ragged array (nv values per node)."""
+    nv = q.shape[0]
+    counts, offs, elem, local = _node_index(orders)
+    out = np.zeros(nv * int(offs[-1]))
+    base = nv * offs[:-1][elem] + local
+    for v in range(nv):
+        out[base + v * counts[elem]] = q[v]
     return out
+
+
+def _gather_xyz(xyz, orders):
+    counts, offs, elem, local = _node_index(orders)
+    ix = 3 * offs[:-1][elem] + local
+    c = counts[elem]
+    return xyz[ix], xyz[ix + c], xyz[ix + 2 * c]
+
+
+def _ragged_apply(xyz, orders, fn):
+    """Evaluate fn(x, y, z) -> [5, npts] at every node and scatter into the ragged layout."""
+    x, y, z = _gather_xyz(np.asarray(xyz), orders)
+    return _scatter(fn(x, y, z), orders)
 
 
 def pulse_rho(x, y, z, centre=(0.5, 0.5, 0.5), sigma=0.1, amp=0.5, images=False, t=0.0,
@@ -121,47 +125,24 @@ def pulse_state(xyz, orders, centre=(0.5, 0.5, 0.5), sigma=0.1, amp=0.5, images=
 
 def add_rho_noise(u, orders, rng, amp=1e-3):
     """i.i.d. N(0, amp^2) added to rho at every node (rho E unchanged)."""
-    offs = node_offsets(orders)
-    counts = node_counts(orders)
+    counts, offs, elem, local = _node_index(orders)
     out = u.copy()
-    noise = rng.normal(0.0, amp, int(offs[-1]))
-    pos = 0
-    for e in range(len(counts)):
-        c = int(counts[e])
-        s = 5 * int(offs[e])
-        out[s:s + c] += noise[pos:pos + c]
-        pos += c
+    out[5 * offs[:-1][elem] + local] += rng.normal(0.0, amp, int(offs[-1]))
     return out
 
 
 def random_state(orders, rng, rho=(0.8, 1.2), vel=0.3, p=(0.8, 1.2), gamma=GAMMA):
     """Nodewise i.i.d. admissible states (for parity and invariance tests)."""
-    offs = node_offsets(orders)
-    n = int(offs[-1])
+    n = int(node_offsets(orders)[-1])
     r = rng.uniform(rho[0], rho[1], n)
     uu = rng.uniform(-vel, vel, (3, n))
     pp = rng.uniform(p[0], p[1], n)
-    q = conserved(r, uu[0], uu[1], uu[2], pp, gamma)
-    out = np.zeros(5 * n)
-    counts = node_counts(orders)
-    pos = 0
-    for e in range(len(counts)):
-        c = int(counts[e])
-        s = 5 * int(offs[e])
-        out[s:s + 5 * c] = q[:, pos:pos + c].reshape(-1)
-        pos += c
-    return out
+    return _scatter(conserved(r, uu[0], uu[1], uu[2], pp, gamma), orders)
 
 
 def uniform_state(orders, q):
-    counts = node_counts(orders)
-    offs = node_offsets(orders)
-    out = np.zeros(5 * int(offs[-1]))
-    for e in range(len(counts)):
-        c = int(counts[e])
-        s = 5 * int(offs[e])
-        out[s:s + 5 * c] = np.repeat(np.asarray(q, dtype=np.float64), c)
-    return out
+    n = int(node_offsets(orders)[-1])
+    return _scatter(np.repeat(np.asarray(q, dtype=np.float64)[:, None], n, axis=1), orders)
 
 
 # --------------------------------------------------------------------------- configs
@@ -185,3 +166,18 @@ def c2_state_and_coarse(xyz, mesh, fine_orders, seed: int = 2, coarse=(1, 6)):
     co = rng.integers(coarse[0], coarse[1] + 1, (E, 3)).astype(np.int32)
     co = np.minimum(co, np.asarray(fine_orders).reshape(-1, 3))
     return u, co
+
+
+def c5(seed: int = 5, nprob: int = 64, nrange=(8, 20), orange=(1, 7)):
+    """64 independent periodic unit-cube problems: per problem n ~ U{8..20} elements
+    per side, orders U{1..7}, pulse centre U([0,1]^3), width U[0.05, 0.2].
+    Returns a list of (mesh, orders, centre, sigma)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(nrange[0], nrange[1] + 1, nprob)
+    out = []
+    for n in ns:
+        orders = random_orders(int(n) ** 3, orange[0], orange[1], rng)
+        centre = rng.random(3)
+        sigma = float(rng.uniform(0.05, 0.2))
+        out.append((box_mesh(int(n)), orders, tuple(centre), sigma))
+    return out
