@@ -64,6 +64,8 @@ def _load():
             "orc_num_combos": [_I],
             "orc_sweep": [ctypes.POINTER(_Mesh), _I, _D, _D, _I, ctypes.c_int, _D, _D],
             "orc_rk3": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_double, ctypes.c_int],
+            "orc_tau_eta": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, _D, _D],
+            "orc_functional": [ctypes.POINTER(_Mesh), _I, _D, _D, _D],
         }.items():
             fn = getattr(lib, name)
             fn.argtypes = args
@@ -239,3 +241,25 @@ def rk3(mesh: dict, orders, u, dt: float, nsteps: int):
     m = _mesh(mesh)
     _check(_load().orc_rk3(ctypes.byref(m), _i(o), _d(out), float(dt), int(nsteps)), "rk3")
     return out
+
+
+def tau_eta(mesh: dict, fine_orders, coarse_orders, u, dudt, psi, isolated: bool = False):
+    """eta[e] = sum over the coarse nodes and variables of (I psi) * tau_trad."""
+    fo, co = _i32(fine_orders), _i32(coarse_orders)
+    u, dudt, psi = _f64(u), _f64(dudt), _f64(psi)
+    E = fo.size // 3
+    eta = np.zeros(E)
+    m = _mesh(mesh)
+    _check(_load().orc_tau_eta(ctypes.byref(m), _i(fo), _i(co), _d(u), _d(dudt), int(bool(isolated)),
+                               _d(psi), _d(eta)), "tau_eta")
+    return eta
+
+
+def functional(mesh: dict, orders, u, grad: bool = True):
+    """Pressure force along x on the slip walls and (optionally) its gradient dJ/du."""
+    o, u = _i32(orders), _f64(u)
+    J = np.zeros(1)
+    g = np.zeros_like(u) if grad else None
+    m = _mesh(mesh)
+    _check(_load().orc_functional(ctypes.byref(m), _i(o), _d(u), _d(J), _d(g) if grad else None), "functional")
+    return (float(J[0]), g) if grad else float(J[0])

@@ -739,6 +739,74 @@ int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const doubl
     return 0;
 }
 
+int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_orders, const double *u,
+                const double *dudt, int isolated, const double *psi, double *eta)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (E <= 0 || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
+    long nc = orc_num_nodes(E, coarse_orders);
+    double *tn = malloc(sizeof(double) * NV * nc), *tt = malloc(sizeof(double) * NV * nc);
+    double *norms = malloc(sizeof(double) * 2 * E), *psic = malloc(sizeof(double) * NV * nc);
+    int rc = orc_tau(m, fine_orders, coarse_orders, u, dudt, isolated, tn, tt, norms, NULL);
+    if (rc == 0) {
+        orc_restrict(E, fine_orders, coarse_orders, psi, psic);
+        long *offc = node_offsets(E, coarse_orders);
+        for (int e = 0; e < E; ++e) {
+            long a = NV * offc[e], b = NV * offc[e + 1];
+            double acc = 0.0;
+            for (long x = a; x < b; ++x) acc += psic[x] * tt[x];
+            eta[e] = acc;
+        }
+        free(offc);
+    }
+    free(tn); free(tt); free(norms); free(psic);
+    return rc;
+}
+
+int orc_functional(const orc_mesh *m, const int *orders, const double *u, double *J, double *dJdu)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (E <= 0 || check_orders(E, orders)) return -1;
+    ensure_tables();
+    double h[3], Jm, Ja[3];
+    geometry(m, h, &Jm, Ja);
+    long *off = node_offsets(E, orders);
+    if (dJdu) memset(dJdu, 0, sizeof(double) * NV * off[E]);
+    double g = m->gamma, total = 0.0;
+    for (int e = 0; e < E; ++e) {
+        int c[3];
+        elem_ijk(m, e, c);
+        const int *o = orders + 3 * e;
+        int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+        for (int s = -1; s <= 1; s += 2) {
+            int at_wall = (s < 0 && c[0] == 0 && m->bc[0] == 1) || (s > 0 && c[0] == m->nx - 1 && m->bc[1] == 1);
+            if (!at_wall) continue;
+            /* face normal to x: tangential directions y (a) and z (b) */
+            for (int b = 0; b < n[2]; ++b)
+                for (int a = 0; a < n[1]; ++a) {
+                    int node = face_node(n, 0, s, a, b);
+                    const double *Q = u + NV * off[e];
+                    double q[NV];
+                    for (int v = 0; v < NV; ++v) q[v] = Q[v * ne + node];
+                    double wgt = g_w[o[1]][a] * g_w[o[2]][b] * Ja[0] * (double)s;
+                    total += wgt * pressure(q, g);
+                    if (dJdu) {
+                        double *D = dJdu + NV * off[e];
+                        double ux = q[1] / q[0], uy = q[2] / q[0], uz = q[3] / q[0];
+                        D[0 * ne + node] = wgt * (g - 1.0) * 0.5 * (ux * ux + uy * uy + uz * uz);
+                        D[1 * ne + node] = -wgt * (g - 1.0) * ux;
+                        D[2 * ne + node] = -wgt * (g - 1.0) * uy;
+                        D[3 * ne + node] = -wgt * (g - 1.0) * uz;
+                        D[4 * ne + node] = wgt * (g - 1.0);
+                    }
+                }
+        }
+    }
+    *J = total;
+    free(off);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Williamson (1980) low-storage third-order Runge-Kutta.                    */
 

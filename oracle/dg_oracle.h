@@ -81,6 +81,16 @@ int orc_num_combos(const int *order3);
 int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const double *dudt,
               const int *elems, int nelems, double *te_new, double *te_trad);
 
+/* Adjoint-weighted truncation error (used with an adjoint state psi on the fine
+ * layout): eta[e] = sum over coarse nodes and variables of (I psi) * tau_trad. */
+int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
+                const double *u, const double *dudt, int isolated, const double *psi, double *eta);
+
+/* Pressure force along x on the slip walls: J = sum over slip-wall faces with
+ * normal +-e_x of sum_{a,b} w_a w_b |Ja^1| p(Q) n_x; dJdu (nullable, natural
+ * layout) receives dJ/dQ (zero away from those faces). */
+int orc_functional(const orc_mesh *m, const int *orders, const double *u, double *J, double *dJdu);
+
 /* Williamson low-storage RK3, nsteps steps of size dt, in place on u. */
 int orc_rk3(const orc_mesh *m, const int *orders, double *u, double dt, int nsteps);
 
