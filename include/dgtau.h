@@ -112,10 +112,14 @@ dg_status dg_residual(dg_plan plan, const void *u, void *r, int32_t dtype, int32
  *   isolated: 0 coupled coarse residual (mortars between coarse orders), 1 isolated.
  *   tau_new, tau_trad: device double, coarse plan layout (either may be NULL).
  *   norms: device double [E_coarse][2], max |tau_new|, max |tau_trad| over nodes and
- *          the 5 variables of each coarse plan element (may be NULL). */
+ *          the 5 variables of each coarse plan element (may be NULL).
+ *   psi, eta: optional adjoint weighting (both NULL or both set): psi is a fine-layout
+ *          device double field (e.g. the adjoint of a force functional), eta[E_coarse]
+ *          receives sum over coarse nodes and variables of (I psi) * tau_trad; the
+ *          functional error estimate is -sum(eta). */
 dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt,
                           int32_t isolated, double *tau_new, double *tau_trad, double *norms,
-                          hipStream_t stream);
+                          const double *psi, double *eta, hipStream_t stream);
 
 /* Number of coarse combinations per fine plan element for the sweep:
  * prod_d max(1, N_d - 1); combo_offset[E+1] (host) gets their prefix sums. */
@@ -130,6 +134,22 @@ dg_status dg_sweep_layout(dg_plan fine, int64_t *combo_offset);
  *   te_new, te_trad: device double [combo_offset[E]] (dg_sweep_layout). */
 dg_status dg_tau_sweep(dg_plan fine, const double *u, const double *dudt, double *te_new,
                        double *te_trad, hipStream_t stream);
+
+/* Vector-Jacobian product of the residual: out = (d r / d u)^T v, r the form and
+ * operator of dg_residual (FP64 only).  Written by hand: transposed derivative
+ * matrices, transposed lifting, transposed mortar interpolation and projection, and
+ * the per-node Jacobians of the physical and Riemann fluxes (forward-mode duals).
+ * Deterministic: the face pass stores per-element shares that the element pass
+ * gathers.  u, v, out: device double, plan layout; out must not overlap u or v. */
+dg_status dg_residual_vjp(dg_plan plan, const double *u, const double *v, double *out, int32_t form,
+                          int32_t isolated, hipStream_t stream);
+
+/* Pressure force along x on the slip walls (faces normal to x):
+ *   J = sum over those faces of sum_{a,b} w_a w_b |Ja^1| p(Q_ab) n_x,
+ * the quadrature of the face integral of p n_x with the face's own nodes.
+ *   J: device double[1]; dJdu: device double, plan layout (nullable), receives
+ *   dJ/du (zero away from the wall nodes).  Deterministic reduction. */
+dg_status dg_functional(dg_plan plan, const double *u, double *J, double *dJdu, hipStream_t stream);
 
 /* nsteps steps of Williamson's low-storage RK3 (Section 4 set-up):
  * for k = 0,1,2:  g = A_k g - dt * r(u);  u = u + B_k g,

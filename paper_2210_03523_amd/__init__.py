@@ -50,7 +50,9 @@ SIGNATURES = {
     "dg_plan_layout": [_P, _I64P, _I64P, _I64P, _I64P, _I32P],
     "dg_node_coords": [_P, _P, _P],
     "dg_residual": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
-    "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P],
+    "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P, _P, _P],
+    "dg_residual_vjp": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P],
+    "dg_functional": [_P, _P, _P, _P, _P],
     "dg_sweep_layout": [_P, _I64P],
     "dg_tau_sweep": [_P, _P, _P, _P, _P, _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
@@ -229,19 +231,74 @@ def residual(plan: Plan, u, form: int = FORM_NEW, isolated: bool = False, out=No
     return r
 
 
-def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False):
-    """Returns (tau_new, tau_trad, norms[E,2]) in the coarse plan layout (float64)."""
+def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False, psi=None):
+    """Returns (tau_new, tau_trad, norms[E,2]) in the coarse plan layout (float64), plus
+    eta[E] (sum of (I psi) * tau_trad per coarse element) when an adjoint weight psi is given."""
     torch = _torch()
     if coarse.parent is not fine:
         raise DGError("coarse plan was not built from this fine plan")
-    if u.dtype != torch.float64 or (dudt is not None and dudt.dtype != torch.float64):
-        raise DGError("the tau-estimate runs in float64")
+    for t in (u, dudt, psi):
+        if t is not None and t.dtype != torch.float64:
+            raise DGError("the tau-estimate runs in float64")
     tn = torch.empty(5 * coarse.n_nodes, dtype=torch.float64, device="cuda")
     tt = torch.empty_like(tn)
     norms = torch.empty((coarse.n_elems, 2), dtype=torch.float64, device="cuda")
+    eta = torch.empty(coarse.n_elems, dtype=torch.float64, device="cuda") if psi is not None else None
     _call("dg_tau_estimate", fine.handle, coarse.handle, _ptr(u), _ptr(dudt), int(bool(isolated)),
-          _ptr(tn), _ptr(tt), _ptr(norms), _stream())
-    return tn, tt, norms
+          _ptr(tn), _ptr(tt), _ptr(norms), _ptr(psi), _ptr(eta), _stream())
+    return (tn, tt, norms) if psi is None else (tn, tt, norms, eta)
+
+
+def residual_vjp(plan: Plan, u, v, form: int = FORM_NEW, isolated: bool = False):
+    """(d r / d u)^T v for the residual of `residual` (float64)."""
+    torch = _torch()
+    if u.dtype != torch.float64 or v.dtype != torch.float64:
+        raise DGError("the adjoint runs in float64")
+    out = torch.empty_like(u)
+    _call("dg_residual_vjp", plan.handle, _ptr(u), _ptr(v), _ptr(out), int(form), int(bool(isolated)), _stream())
+    return out
+
+
+def functional(plan: Plan, u, grad: bool = True):
+    """x-pressure force on the slip walls, J (device scalar) and dJ/du (plan layout)."""
+    torch = _torch()
+    J = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(u) if grad else None
+    _call("dg_functional", plan.handle, _ptr(u), _ptr(J), _ptr(g), _stream())
+    return (J, g) if grad else J
+
+
+class ResidualFn:
+    """torch.autograd.Function: forward = dg_residual, backward = dg_residual_vjp."""
+
+    @staticmethod
+    def apply(plan: Plan, u, form: int = FORM_NEW, isolated: bool = False):
+        return _residual_fn().apply(plan, u, form, isolated)
+
+
+_RES_FN = None
+
+
+def _residual_fn():
+    global _RES_FN
+    if _RES_FN is None:
+        torch = _torch()
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, plan, u, form, isolated):
+                ctx.plan, ctx.form, ctx.isolated = plan, form, isolated
+                ctx.save_for_backward(u)
+                return residual(plan, u.detach().contiguous(), form=form, isolated=isolated)
+
+            @staticmethod
+            def backward(ctx, grad):
+                (u,) = ctx.saved_tensors
+                gu = residual_vjp(ctx.plan, u.detach().contiguous(), grad.contiguous(), ctx.form, ctx.isolated)
+                return None, gu, None, None
+
+        _RES_FN = _Fn
+    return _RES_FN
 
 
 def tau_sweep(plan: Plan, u, dudt=None):

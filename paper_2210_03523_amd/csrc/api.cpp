@@ -102,7 +102,11 @@ struct dg_plan_s {
     // coarse plans
     dg_plan_s *parent = nullptr;
     int32_t *d_fine_of = nullptr;
-    double *d_uc = nullptr, *d_rdc = nullptr;
+    double *d_uc = nullptr, *d_rdc = nullptr, *d_psic = nullptr;
+    // x-force functional: boundary faces on slip walls normal to x, and their partial sums
+    int32_t *d_wallx = nullptr;
+    int nwallx = 0;
+    double *d_part = nullptr;
     // sweep
     std::vector<int64_t> combo_off;
     int64_t *d_combo_off = nullptr;
@@ -129,8 +133,8 @@ void destroy_plan(dg_plan p) {
     if (!p) return;
     for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    void *bufs[] = {p->d_el, p->d_faces, p->d_tiles, p->d_ff, p->d_dudt, p->d_fine_of,
-                    p->d_uc, p->d_rdc, p->d_combo_off, p->d_tasks, p->d_iso};
+    void *bufs[] = {p->d_el, p->d_faces, p->d_tiles, p->d_ff, p->d_dudt, p->d_fine_of, p->d_uc, p->d_rdc,
+                    p->d_psic, p->d_combo_off, p->d_tasks, p->d_iso, p->d_wallx, p->d_part};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -237,6 +241,10 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
         }
     }
     p->nfaces = (int)faces.size();
+    std::vector<int32_t> wallx;
+    for (int f = 0; f < p->nfaces; ++f)
+        if (faces[f].bc == DG_BC_SLIP_WALL && faces[f].d == 0) wallx.push_back(f);
+    p->nwallx = (int)wallx.size();
 
     // geometry and physics
     double h[3];
@@ -284,11 +292,12 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
 
     if ((st = upload(&p->d_el, el)) || (st = upload(&p->d_faces, faces)) || (st = upload(&p->d_tiles, tiles)) ||
         (st = upload(&p->d_combo_off, p->combo_off)) || (st = upload(&p->d_tasks, tasks)) ||
-        (st = upload(&p->d_iso, iso_all))) {
+        (st = upload(&p->d_iso, iso_all)) || (st = upload(&p->d_wallx, wallx))) {
         destroy_plan(p);
         return st;
     }
     if (hipMalloc(&p->d_ff, sizeof(double) * std::max<int64_t>(1, p->ff_len)) != hipSuccess ||
+        hipMalloc((void **)&p->d_part, sizeof(double) * std::max(1, p->nwallx)) != hipSuccess ||
         hipMalloc((void **)&p->d_dudt, sizeof(double) * NV * p->n_nodes) != hipSuccess ||
         hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         destroy_plan(p);
@@ -340,7 +349,8 @@ dg_status dg_plan_create_coarse(dg_plan fine, const int32_t *coarse_orders_host,
         return st;
     }
     if (hipMalloc((void **)&c->d_uc, sizeof(double) * NV * c->n_nodes) != hipSuccess ||
-        hipMalloc((void **)&c->d_rdc, sizeof(double) * NV * c->n_nodes) != hipSuccess) {
+        hipMalloc((void **)&c->d_rdc, sizeof(double) * NV * c->n_nodes) != hipSuccess ||
+        hipMalloc((void **)&c->d_psic, sizeof(double) * NV * c->n_nodes) != hipSuccess) {
         destroy_plan(c);
         return fail(DG_ENOMEM, "device allocation failed");
     }
@@ -387,10 +397,12 @@ dg_status dg_residual(dg_plan p, const void *u, void *r, int32_t dtype, int32_t 
 }
 
 dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt, int32_t isolated,
-                          double *tau_new, double *tau_trad, double *norms, hipStream_t stream) {
+                          double *tau_new, double *tau_trad, double *norms, const double *psi, double *eta,
+                          hipStream_t stream) {
     if (!fine || !coarse || !u) return fail(DG_EINVAL, "null argument");
     if (coarse->parent != fine) return fail(DG_EINVAL, "coarse plan was not built from this fine plan");
-    if (!tau_new && !tau_trad && !norms) return DG_OK;
+    if ((psi == nullptr) != (eta == nullptr)) return fail(DG_EINVAL, "psi and eta go together");
+    if (!tau_new && !tau_trad && !norms && !eta) return DG_OK;
     if (!dudt) {
         EpiArgs epi{};
         epi.mode = EPI_RESIDUAL;
@@ -399,8 +411,8 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
         if (st) return st;
         dudt = fine->d_dudt;
     }
-    HIP_TRY(launch_restrict(coarse->d_fine_of, coarse->E, coarse->d_el, fine->d_el, u, dudt, coarse->d_uc,
-                            coarse->d_rdc, fine->tabs.t64, stream));
+    HIP_TRY(launch_restrict(coarse->d_fine_of, coarse->E, coarse->d_el, fine->d_el, u, dudt, psi, coarse->d_uc,
+                            coarse->d_rdc, coarse->d_psic, fine->tabs.t64, stream));
     EpiArgs epi{};
     epi.mode = EPI_TAU;
     epi.isolated = isolated ? 1 : 0;
@@ -408,6 +420,8 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
     epi.out2 = tau_trad;
     epi.rdc = coarse->d_rdc;
     epi.norms = norms;
+    epi.psic = psi ? coarse->d_psic : nullptr;
+    epi.eta = eta;
     return run_residual<double>(coarse, coarse->d_uc, epi, stream);
 }
 
@@ -472,6 +486,27 @@ dg_status dg_rk3_step(dg_plan p, void *u, void *g, double dt, int32_t nsteps, in
         it = p->graphs.emplace(key, exec).first;
     }
     for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(it->second, stream));
+    return DG_OK;
+}
+
+dg_status dg_residual_vjp(dg_plan p, const double *u, const double *v, double *out, int32_t form,
+                          int32_t isolated, hipStream_t stream) {
+    if (!p || !u || !v || !out) return fail(DG_EINVAL, "null argument");
+    if (out == u || out == v) return fail(DG_EINVAL, "out must not overlap u or v");
+    if (form != DG_FORM_NEW && form != DG_FORM_TRAD) return fail(DG_EINVAL, "unknown form");
+    for (size_t i = 0; i < p->classes.size(); ++i) {
+        const TileClass &c = p->classes[i];
+        HIP_TRY(launch_vjp(p->d_faces, p->nfaces, p->d_tiles, c.first, c.count, c.npt, p->d_el, u, v,
+                           (double *)p->d_ff, out, p->tabs.t64, p->geom, p->phys, form, isolated ? 1 : 0,
+                           i == 0 && !isolated, stream));
+    }
+    return DG_OK;
+}
+
+dg_status dg_functional(dg_plan p, const double *u, double *J, double *dJdu, hipStream_t stream) {
+    if (!p || !u || !J) return fail(DG_EINVAL, "null argument");
+    HIP_TRY(launch_functional(p->d_faces, p->d_wallx, p->nwallx, p->d_el, u, p->tabs.t64, p->geom, p->mesh.gamma,
+                              p->d_part, J, dJdu, (int64_t)NV * p->n_nodes, stream));
     return DG_OK;
 }
 
@@ -623,8 +658,9 @@ dg_status autotune(dg_batch b) {
     int bc = 256, be = cus, bf = 4 * cus;
     for (int cap : {256, 512}) {
         if ((st = set_tiles(b, cap))) break;
-        for (int eg : {cus, 2 * cus, 4 * cus, 8 * cus})
-            for (int fg : {4 * cus, 16 * cus}) {
+        // persistent grids of a few waves per CU, or one workgroup per work item
+        for (int eg : {2 * cus, 8 * cus, std::max(1, b->ntiles)})
+            for (int fg : {16 * cus, std::max(1, b->nfaces)}) {
                 b->elem_grid = eg;
                 b->face_grid = fg;
                 if ((st = batch_pass<T>(b, dpd, epi, b->cap_stream))) break;  // warm-up

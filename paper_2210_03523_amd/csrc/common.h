@@ -96,6 +96,8 @@ struct EpiArgs {
     void *g;            // RK register
     const void *rdc;    // restricted fine time derivative (tau)
     double *norms;      // [E][2] (tau)
+    const void *psic;   // restricted adjoint weight (tau, optional)
+    double *eta;        // [E] sum of psic * tau_trad (tau, optional)
 };
 
 template <typename T>
@@ -103,8 +105,16 @@ hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, con
                           const T *fflux, const T *tab, Geom g, PhysParams ph, EpiArgs epi, hipStream_t s);
 
 hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
-                           const double *u, const double *dudt, double *uc, double *rdc, const double *tab,
-                           hipStream_t s);
+                           const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
+                           double *psic, const double *tab, hipStream_t s);
+
+hipError_t launch_vjp(const Face *faces, int nfaces, const Tile *tiles, int tile0, int ntiles, int npt,
+                      const ElemInfo *el, const double *u, const double *v, double *fa, double *out,
+                      const double *tab, Geom g, PhysParams ph, int form, int isolated, bool do_faces,
+                      hipStream_t s);
+hipError_t launch_functional(const Face *faces, const int32_t *wall, int nwall, const ElemInfo *el,
+                             const double *u, const double *tab, Geom g, double gamma, double *part, double *J,
+                             double *dJdu, int64_t n_vals, hipStream_t s);
 
 hipError_t launch_coords(const ElemInfo *elems, int E, int nx, int ny, const double *tab, Geom g, double *xyz,
                          hipStream_t s);

@@ -42,19 +42,20 @@ __device__ __forceinline__ int face_node(const int32_t *n, int d, int side, int 
 // ---------------------------------------------------------------------------- faces
 template <typename T>
 struct FaceSmem {
-    T QL[NV][NNMAX * NNMAX];
-    T QR[NV][NNMAX * NNMAX];
-    T F[NV][NNMAX * NNMAX];
+    T QL[NV][NNMAX * NNMAX];   // left trace, later the left projection intermediate
+    T QR[NV][NNMAX * NNMAX];   // right trace, later the right projection intermediate
+    T TL[NV][NNMAX * NNMAX];   // left trace interpolated along the first tangential direction
+    T TR[NV][NNMAX * NNMAX];
+    T F[NV][NNMAX * NNMAX];    // Riemann flux on the mortar
 };
 
-// One face, processed by one wavefront (64 lanes).
+// One face, processed by one wavefront (64 lanes).  Mortar interpolation S2 (x) S1 and
+// projection P2 (x) P1 are applied one tangential direction at a time, and only in a
+// direction where the two sides' orders differ.
 template <typename T>
 __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restrict__ el, const T *__restrict__ u,
                                           T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
                                           const PhysParams &ph, FaceSmem<T> &sm) {
-    T(&sQL)[NV][NNMAX * NNMAX] = sm.QL;
-    T(&sQR)[NV][NNMAX * NNMAX] = sm.QR;
-    T(&sF)[NV][NNMAX * NNMAX] = sm.F;
     const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const T Ja = (T)g.Ja[d];
     const T gam = (T)ph.gamma;
@@ -91,90 +92,133 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
     const int aL = L.n[t1], bL = L.n[t2], aR = R.n[t1], bR = R.n[t2];
     const int K1 = aL > aR ? aL : aR, K2 = bL > bR ? bL : bR;
     const int neL = L.n[0] * L.n[1] * L.n[2], neR = R.n[0] * R.n[1] * R.n[2];
+    T *oL = ff + L.foff + fslot(L.n, d, 1);
+    T *oR = ff + R.foff + fslot(R.n, d, -1);
+
+    if (aL == aR && bL == bR) {
+        // conforming face: one node pair per lane, no staging
+        for (int m = lane; m < aL * bL; m += 64) {
+            const int nl = face_node(L.n, d, 1, m % aL, m / aL);
+            const int nr = face_node(R.n, d, -1, m % aL, m / aL);
+            T qL[NV], qR[NV], F[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                qL[v] = u[NV * L.noff + v * neL + nl];
+                qR[v] = u[NV * R.noff + v * neR + nr];
+            }
+            numflux_axis(qL, qR, d, T(1), gam, ph.flux, F);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                oL[v * aL * bL + m] = Ja * F[v];
+                oR[v * aL * bL + m] = -Ja * F[v];
+            }
+        }
+        return;
+    }
+
     for (int m = lane; m < aL * bL; m += 64) {
         int node = face_node(L.n, d, 1, m % aL, m / aL);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sQL[v][m] = u[NV * L.noff + v * neL + node];
+        for (int v = 0; v < NV; ++v) sm.QL[v][m] = u[NV * L.noff + v * neL + node];
     }
     for (int m = lane; m < aR * bR; m += 64) {
         int node = face_node(R.n, d, -1, m % aR, m / aR);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sQR[v][m] = u[NV * R.noff + v * neR + node];
+        for (int v = 0; v < NV; ++v) sm.QR[v][m] = u[NV * R.noff + v * neR + node];
     }
     __syncthreads();
-    const bool confL = (aL == K1 && bL == K2), confR = (aR == K1 && bR == K2);
+    // first tangential direction: T[A + K1 b] = sum_a S1[A][a] Q[a + na b]
+    for (int side = 0; side < 2; ++side) {
+        const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
+        if (na == K1) continue;
+        T(*Q)[NNMAX * NNMAX] = side == 0 ? sm.QL : sm.QR;
+        T(*Tt)[NNMAX * NNMAX] = side == 0 ? sm.TL : sm.TR;
+        const T *S1 = tab + T_I + moff(K1 - 1, na - 1);
+        for (int m = lane; m < K1 * nb; m += 64) {
+            const int A = m % K1, b = m / K1;
+            T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
+            for (int a = 0; a < na; ++a) {
+                const T s1 = S1[A * na + a];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] += s1 * Q[v][a + na * b];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Tt[v][m] = acc[v];
+        }
+    }
+    __syncthreads();
+    // second tangential direction, then the Riemann flux on the mortar
     for (int m = lane; m < K1 * K2; m += 64) {
         const int A = m % K1, B = m / K1;
-        T qL[NV], qR[NV], F[NV];
-        if (confL) {
+        T q[2][NV], F[NV];
+        for (int side = 0; side < 2; ++side) {
+            const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
+            T(*src)[NNMAX * NNMAX] = na == K1 ? (side == 0 ? sm.QL : sm.QR) : (side == 0 ? sm.TL : sm.TR);
+            if (nb == K2) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) qL[v] = sQL[v][m];
-        } else {
-            const T *S1 = tab + T_I + moff(K1 - 1, aL - 1) + A * aL;
-            const T *S2 = tab + T_I + moff(K2 - 1, bL - 1) + B * bL;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) qL[v] = T(0);
-            for (int b = 0; b < bL; ++b) {
+                for (int v = 0; v < NV; ++v) q[side][v] = src[v][A + K1 * B];
+            } else {
+                const T *S2 = tab + T_I + moff(K2 - 1, nb - 1) + B * nb;
                 T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
-                for (int a = 0; a < aL; ++a) {
+                for (int b = 0; b < nb; ++b) {
+                    const T s2 = S2[b];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[v] += S1[a] * sQL[v][a + aL * b];
+                    for (int v = 0; v < NV; ++v) acc[v] += s2 * src[v][A + K1 * b];
                 }
 #pragma unroll
-                for (int v = 0; v < NV; ++v) qL[v] += S2[b] * acc[v];
+                for (int v = 0; v < NV; ++v) q[side][v] = acc[v];
             }
         }
-        if (confR) {
+        numflux_axis(q[0], q[1], d, T(1), gam, ph.flux, F);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) qR[v] = sQR[v][m];
-        } else {
-            const T *S1 = tab + T_I + moff(K1 - 1, aR - 1) + A * aR;
-            const T *S2 = tab + T_I + moff(K2 - 1, bR - 1) + B * bR;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) qR[v] = T(0);
-            for (int b = 0; b < bR; ++b) {
-                T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
-                for (int a = 0; a < aR; ++a) {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[v] += S1[a] * sQR[v][a + aR * b];
-                }
-#pragma unroll
-                for (int v = 0; v < NV; ++v) qR[v] += S2[b] * acc[v];
-            }
-        }
-        numflux_axis(qL, qR, d, T(1), gam, ph.flux, F);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sF[v][m] = Ja * F[v];
+        for (int v = 0; v < NV; ++v) sm.F[v][m] = Ja * F[v];
     }
     __syncthreads();
-    // project onto each side's face nodes; outward sign (+ for L, - for R)
+    // projection, first tangential direction: U[a + na B] = sum_A P1[a][A] F[A + K1 B]
     for (int side = 0; side < 2; ++side) {
-        const ElemInfo &E = side == 0 ? L : R;
+        const int na = side == 0 ? aL : aR;
+        if (na == K1) continue;
+        T(*U)[NNMAX * NNMAX] = side == 0 ? sm.QL : sm.QR;
+        const T *P1 = tab + T_P + moff(na - 1, K1 - 1);
+        for (int m = lane; m < na * K2; m += 64) {
+            const int a = m % na, B = m / na;
+            T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
+            for (int A = 0; A < K1; ++A) {
+                const T p1 = P1[a * K1 + A];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] += p1 * sm.F[v][A + K1 * B];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) U[v][m] = acc[v];
+        }
+    }
+    __syncthreads();
+    // second tangential direction, outward sign (+ for L, - for R)
+    for (int side = 0; side < 2; ++side) {
         const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
-        const bool conf = side == 0 ? confL : confR;
+        T *out = side == 0 ? oL : oR;
         const T sg = side == 0 ? T(1) : T(-1);
-        T *out = ff + E.foff + fslot(E.n, d, side == 0 ? 1 : -1);
+        const bool x1 = na != K1;  // the first pass ran: intermediate in QL/QR as [a + na B]
+        T(*U)[NNMAX * NNMAX] = x1 ? (side == 0 ? sm.QL : sm.QR) : sm.F;
+        const int ld = x1 ? na : K1;
+        const T *P2 = tab + T_P + moff(nb - 1, K2 - 1);
         for (int m = lane; m < na * nb; m += 64) {
             const int a = m % na, b = m / na;
-            if (conf) {
+            T acc[NV];
+            if (nb == K2) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) out[v * na * nb + m] = sg * sF[v][m];
+                for (int v = 0; v < NV; ++v) acc[v] = U[v][a + ld * b];
             } else {
-                const T *P1 = tab + T_P + moff(na - 1, K1 - 1) + a * K1;
-                const T *P2 = tab + T_P + moff(nb - 1, K2 - 1) + b * K2;
-                T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] = T(0);
                 for (int B = 0; B < K2; ++B) {
-                    T in[NV] = {T(0), T(0), T(0), T(0), T(0)};
-                    for (int A = 0; A < K1; ++A) {
+                    const T p2 = P2[b * K2 + B];
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) in[v] += P1[A] * sF[v][A + K1 * B];
-                    }
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) acc[v] += P2[B] * in[v];
+                    for (int v = 0; v < NV; ++v) acc[v] += p2 * U[v][a + ld * B];
                 }
-#pragma unroll
-                for (int v = 0; v < NV; ++v) out[v * na * nb + m] = sg * acc[v];
             }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v * na * nb + m] = sg * acc[v];
         }
     }
 }
@@ -289,11 +333,12 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
     }
     // epilogue
     const T invJ = (T)(1.0 / g.J);
-    T mx[NPT][2];
+    T mx[NPT][3];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         mx[k][0] = T(0);
         mx[k][1] = T(0);
+        mx[k][2] = T(0);
         if (!ok[k]) continue;
         const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
         const T www = tab[T_W + xoff(n1 - 1) + loc[k][0]] * tab[T_W + xoff(n2 - 1) + loc[k][1]] *
@@ -331,16 +376,20 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
                 if (tt) tt[x] = b;
                 mx[k][0] = fmax(mx[k][0], fabs(a));
                 mx[k][1] = fmax(mx[k][1], fabs(b));
+                if (epi.psic) mx[k][2] += ((const T *)epi.psic)[x] * b;
             }
         }
     }
-    if (epi.mode == EPI_TAU && epi.norms) {
-        // per-element maxima: stage in LDS, then reduce each element's segment
+    if (epi.mode == EPI_TAU && (epi.norms || epi.eta)) {
+        // per-element maxima (and the eta sum): stage in LDS, then reduce each
+        // element's segment in a fixed order
+        __syncthreads();
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int t = tid + k * WG;
             sF[0][t] = mx[k][0];
             sF[1][t] = mx[k][1];
+            sF[2][t] = mx[k][2];
         }
         __syncthreads();
         if (tl.count == 1) {
@@ -351,22 +400,30 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
                     if (t < s) {
                         sF[0][t] = fmax(sF[0][t], sF[0][t + s]);
                         sF[1][t] = fmax(sF[1][t], sF[1][t + s]);
+                        sF[2][t] = sF[2][t] + sF[2][t + s];
                     }
                 }
                 __syncthreads();
             }
             if (tid == 0) {
-                epi.norms[2 * (int64_t)tl.first] = (double)sF[0][0];
-                epi.norms[2 * (int64_t)tl.first + 1] = (double)sF[1][0];
+                if (epi.norms) {
+                    epi.norms[2 * (int64_t)tl.first] = (double)sF[0][0];
+                    epi.norms[2 * (int64_t)tl.first + 1] = (double)sF[1][0];
+                }
+                if (epi.eta) epi.eta[tl.first] = (double)sF[2][0];
             }
         } else if (tid < tl.count) {
-            T m0 = T(0), m1 = T(0);
+            T m0 = T(0), m1 = T(0), e2 = T(0);
             for (int i = 0; i < npe; ++i) {
                 m0 = fmax(m0, sF[0][tid * npe + i]);
                 m1 = fmax(m1, sF[1][tid * npe + i]);
+                e2 += sF[2][tid * npe + i];
             }
-            epi.norms[2 * (int64_t)(tl.first + tid)] = (double)m0;
-            epi.norms[2 * (int64_t)(tl.first + tid) + 1] = (double)m1;
+            if (epi.norms) {
+                epi.norms[2 * (int64_t)(tl.first + tid)] = (double)m0;
+                epi.norms[2 * (int64_t)(tl.first + tid) + 1] = (double)m1;
+            }
+            if (epi.eta) epi.eta[tl.first + tid] = (double)e2;
         }
     }
 }

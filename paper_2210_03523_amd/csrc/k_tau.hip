@@ -28,8 +28,9 @@ __device__ __forceinline__ int xcd_remap_t(int bid, int G) {
 __global__ __launch_bounds__(256) void k_restrict(const int32_t *__restrict__ fine_of,
                                                   const ElemInfo *__restrict__ cel,
                                                   const ElemInfo *__restrict__ fel, const double *__restrict__ u,
-                                                  const double *__restrict__ dudt, double *__restrict__ uc,
-                                                  double *__restrict__ rdc, const double *__restrict__ tab) {
+                                                  const double *__restrict__ dudt, const double *__restrict__ psi,
+                                                  double *__restrict__ uc, double *__restrict__ rdc,
+                                                  double *__restrict__ psic, const double *__restrict__ tab) {
     __shared__ double sA[NNMAX * NNMAX * NNMAX];
     __shared__ double sB[NNMAX * NNMAX * NNMAX];
     const int p = blockIdx.x;
@@ -40,9 +41,10 @@ __global__ __launch_bounds__(256) void k_restrict(const int32_t *__restrict__ fi
     const double *I1 = tab + T_I + moff(c1 - 1, f1 - 1);
     const double *I2 = tab + T_I + moff(c2 - 1, f2 - 1);
     const double *I3 = tab + T_I + moff(c3 - 1, f3 - 1);
-    for (int field = 0; field < 2; ++field) {
-        const double *src = (field == 0 ? u : dudt) + NV * F.noff;
-        double *dst = (field == 0 ? uc : rdc) + NV * C.noff;
+    const int nfield = psi ? 3 : 2;
+    for (int field = 0; field < nfield; ++field) {
+        const double *src = (field == 0 ? u : field == 1 ? dudt : psi) + NV * F.noff;
+        double *dst = (field == 0 ? uc : field == 1 ? rdc : psic) + NV * C.noff;
         for (int v = 0; v < NV; ++v) {
             // x: sA[a + c1*(j + f2*k)] = sum_i I1[a,i] Q[i + f1*(j + f2*k)]
             for (int t = threadIdx.x; t < c1 * f2 * f3; t += blockDim.x) {
@@ -74,10 +76,11 @@ __global__ __launch_bounds__(256) void k_restrict(const int32_t *__restrict__ fi
 }
 
 hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
-                           const double *u, const double *dudt, double *uc, double *rdc, const double *tab,
-                           hipStream_t s) {
+                           const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
+                           double *psic, const double *tab, hipStream_t s) {
     if (ncoarse == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_restrict, dim3(ncoarse), dim3(256), 0, s, fine_of, celems, felems, u, dudt, uc, rdc, tab);
+    hipLaunchKernelGGL(k_restrict, dim3(ncoarse), dim3(256), 0, s, fine_of, celems, felems, u, dudt, psi, uc, rdc,
+                       psic, tab);
     return hipGetLastError();
 }
 

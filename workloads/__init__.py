@@ -181,3 +181,29 @@ def c5(seed: int = 5, nprob: int = 64, nrange=(8, 20), orange=(1, 7)):
         sigma = float(rng.uniform(0.05, 0.2))
         out.append((box_mesh(int(n)), orders, tuple(centre), sigma))
     return out
+
+
+def c4(n: int = 24, N: int = 5):
+    """Slip wall on x = 0, far field (free stream) on x = 1, periodic in y and z."""
+    q_inf = conserved(np.array(1.0), np.array(0.3), np.array(0.4), np.array(0.5), np.array(1.0))
+    mesh = box_mesh(n, bc=(WALL, FARFIELD, PERIODIC, PERIODIC, PERIODIC, PERIODIC), qfar=tuple(q_inf))
+    return mesh, uniform_orders(n ** 3, N)
+
+
+def c4_state(xyz, orders, seed: int = 4, nmodes: int = 8):
+    """rho = 1 + 0.1 * pulse (width 0.1), u = (0.3, 0.4, 0.5) + 1e-2 * (nmodes seeded smooth
+    Fourier modes per component), p = 1."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, 4, (nmodes, 3))
+    ph = rng.random((nmodes, 3)) * 2 * np.pi
+    amp = rng.normal(size=(nmodes, 3))
+
+    def fn(x, y, z):
+        rho = pulse_rho(x, y, z, amp=0.1, sigma=0.1)
+        vel = [np.full_like(x, c) for c in (0.3, 0.4, 0.5)]
+        for m in range(nmodes):
+            arg = 2 * np.pi * (k[m, 0] * x + k[m, 1] * y + k[m, 2] * z)
+            for c in range(3):
+                vel[c] = vel[c] + 1e-2 * amp[m, c] * np.sin(arg + ph[m, c])
+        return conserved(rho, vel[0], vel[1], vel[2], np.ones_like(x))
+    return _ragged_apply(xyz, orders, fn)
