@@ -66,6 +66,9 @@ def _load():
             "orc_rk3": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_double, ctypes.c_int],
             "orc_tau_eta": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, _D, _D],
             "orc_functional": [ctypes.POINTER(_Mesh), _I, _D, _D, _D],
+            "orc_gradient": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_int, _D],
+            "orc_residual_ns": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_double, ctypes.c_double, _D,
+                                ctypes.c_int, ctypes.c_int],
         }.items():
             fn = getattr(lib, name)
             fn.argtypes = args
@@ -78,6 +81,8 @@ def _load():
         lib.orc_numflux.restype = None
         lib.orc_roe_waves.argtypes = [_D, _D, _D, ctypes.c_double, _D, _D]
         lib.orc_roe_waves.restype = None
+        lib.orc_viscous_flux.argtypes = [_D, _D, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
+        lib.orc_viscous_flux.restype = None
         _lib = lib
     return _lib
 
@@ -263,3 +268,29 @@ def functional(mesh: dict, orders, u, grad: bool = True):
     m = _mesh(mesh)
     _check(_load().orc_functional(ctypes.byref(m), _i(o), _d(u), _d(J), _d(g) if grad else None), "functional")
     return (float(J[0]), g) if grad else float(J[0])
+
+
+def gradient(mesh: dict, orders, u, isolated: bool = False):
+    """BR1 gradients of the conserved variables, natural layout [e][3][5][node]."""
+    o, u = _i32(orders), _f64(u)
+    g = np.zeros(3 * u.size)
+    m = _mesh(mesh)
+    _check(_load().orc_gradient(ctypes.byref(m), _i(o), _d(u), int(bool(isolated)), _d(g)), "gradient")
+    return g
+
+
+def residual_ns(mesh: dict, orders, u, mu: float, Pr: float = 0.72, form: int = 0, isolated: bool = False):
+    """Navier-Stokes (BR1) residual, new (0) or traditional (1) form."""
+    o, u = _i32(orders), _f64(u)
+    r = np.zeros_like(u)
+    m = _mesh(mesh)
+    _check(_load().orc_residual_ns(ctypes.byref(m), _i(o), _d(u), float(mu), float(Pr), _d(r), int(form),
+                                   int(bool(isolated))), "residual_ns")
+    return r
+
+
+def viscous_flux(q, G, d: int, gamma=1.4, mu=0.01, Pr=0.72):
+    q, G = _f64(q), _f64(G)
+    f = np.zeros(5)
+    _load().orc_viscous_flux(_d(q), _d(G), int(d), gamma, mu, Pr, _d(f))
+    return f

@@ -569,6 +569,348 @@ int orc_residual(const orc_mesh *m, const int *orders, const double *u, double *
 }
 
 /* ------------------------------------------------------------------------ */
+/* Navier-Stokes: BR1 gradients and viscous fluxes.                           */
+
+void orc_viscous_flux(const double *q, const double *G, int d, double g, double mu, double Pr, double *f)
+{
+    double rho = q[0], u[3] = {q[1] / q[0], q[2] / q[0], q[3] / q[0]};
+    double p = pressure(q, g), T = p / rho;
+    double du[3][3]; /* du[k][l] = d u_k / d x_l */
+    double dT[3];
+    for (int l = 0; l < 3; ++l) {
+        const double *Gl = G + 5 * l;
+        for (int k = 0; k < 3; ++k) du[k][l] = (Gl[1 + k] - u[k] * Gl[0]) / rho;
+        double dp = (g - 1.0) * (Gl[4] - (u[0] * Gl[1] + u[1] * Gl[2] + u[2] * Gl[3]) +
+                                 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * Gl[0]);
+        dT[l] = (dp - T * Gl[0]) / rho;
+    }
+    double div = du[0][0] + du[1][1] + du[2][2];
+    double tau[3]; /* tau[k] = tau_{k d} */
+    for (int k = 0; k < 3; ++k) tau[k] = mu * (du[k][d] + du[d][k]) - (k == d ? 2.0 / 3.0 * mu * div : 0.0);
+    double kappa = mu * g / ((g - 1.0) * Pr);
+    f[0] = 0.0;
+    for (int k = 0; k < 3; ++k) f[1 + k] = tau[k];
+    f[4] = u[0] * tau[0] + u[1] * tau[1] + u[2] * tau[2] + kappa * dT[d];
+}
+
+/* Neighbour of element e across face (d, s): returns its index, or -1 with *bc set. */
+static int neighbour(const orc_mesh *m, int e, int d, int s, int *bc)
+{
+    int c[3], nd[3] = {m->nx, m->ny, m->nz};
+    elem_ijk(m, e, c);
+    c[d] += s;
+    *bc = 0;
+    if (c[d] < 0 || c[d] >= nd[d]) {
+        *bc = m->bc[2 * d + (s > 0 ? 1 : 0)];
+        if (*bc != 0) return -1;
+        c[d] = (c[d] + nd[d]) % nd[d];
+    }
+    return elem_index(m, c);
+}
+
+static void ghost_state(const orc_mesh *m, int bc, int d, int s, const double *qin, double *qg)
+{
+    if (bc == 1) {
+        for (int v = 0; v < NV; ++v) qg[v] = qin[v];
+        qg[1 + d] = -qin[1 + d] * 1.0;
+        (void)s;
+    } else {
+        for (int v = 0; v < NV; ++v) qg[v] = m->qfar[v];
+    }
+}
+
+/* Interpolate a face trace (nv fields of na*nb nodes, field stride na*nb) onto
+ * the K1 x K2 mortar: out[v*K1*K2 + A + K1*B]. */
+static void to_mortar(int nv, int na, int nb, int K1, int K2, const double *in, double *out)
+{
+    double *S1 = malloc(sizeof(double) * K1 * na), *S2 = malloc(sizeof(double) * K2 * nb);
+    orc_interp(K1 - 1, na - 1, S1);
+    orc_interp(K2 - 1, nb - 1, S2);
+    for (int v = 0; v < nv; ++v)
+        for (int B = 0; B < K2; ++B)
+            for (int A = 0; A < K1; ++A) {
+                double acc = 0.0;
+                for (int b = 0; b < nb; ++b)
+                    for (int a = 0; a < na; ++a) acc += S1[A * na + a] * S2[B * nb + b] * in[v * na * nb + a + na * b];
+                out[v * K1 * K2 + A + K1 * B] = acc;
+            }
+    free(S1);
+    free(S2);
+}
+
+/* L2 projection of nv mortar fields back onto an na x nb face. */
+static void from_mortar(int nv, int na, int nb, int K1, int K2, const double *in, double *out)
+{
+    double *P1 = malloc(sizeof(double) * na * K1), *P2 = malloc(sizeof(double) * nb * K2);
+    orc_proj(na - 1, K1 - 1, P1);
+    orc_proj(nb - 1, K2 - 1, P2);
+    for (int v = 0; v < nv; ++v)
+        for (int b = 0; b < nb; ++b)
+            for (int a = 0; a < na; ++a) {
+                double acc = 0.0;
+                for (int B = 0; B < K2; ++B)
+                    for (int A = 0; A < K1; ++A) acc += P1[a * K1 + A] * P2[b * K2 + B] * in[v * K1 * K2 + A + K1 * B];
+                out[v * na * nb + a + na * b] = acc;
+            }
+    free(P1);
+    free(P2);
+}
+
+/* Gather the face trace of nv fields (field stride ne) of element data X on face (d, s). */
+static void face_trace(const int *n, int d, int s, int nv, const double *X, double *out)
+{
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    int na = n[t1], nb = n[t2], ne = n[0] * n[1] * n[2];
+    for (int v = 0; v < nv; ++v)
+        for (int b = 0; b < nb; ++b)
+            for (int a = 0; a < na; ++a) out[v * na * nb + a + na * b] = X[v * ne + face_node(n, d, s, a, b)];
+}
+
+/* BR1 trace of the solution on face (d, s) of element e, projected on its own face:
+ * qhat = (1/2)(Q_in + Q_out) on the mortar (or with the ghost state at boundaries). */
+static void br1_qhat(const orc_mesh *m, const int *orders, const long *off, const double *u, int e, int d, int s,
+                     double *qhat)
+{
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
+    int na = n[t1], nb = n[t2];
+    double *own = malloc(sizeof(double) * NV * na * nb);
+    face_trace(n, d, s, NV, u + NV * off[e], own);
+    int bc;
+    int nbr = neighbour(m, e, d, s, &bc);
+    if (nbr < 0) {
+        for (int x = 0; x < na * nb; ++x) {
+            double qin[NV], qg[NV];
+            for (int v = 0; v < NV; ++v) qin[v] = own[v * na * nb + x];
+            ghost_state(m, bc, d, s, qin, qg);
+            for (int v = 0; v < NV; ++v) qhat[v * na * nb + x] = 0.5 * (qin[v] + qg[v]);
+        }
+        free(own);
+        return;
+    }
+    const int *on = orders + 3 * nbr;
+    int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1};
+    int ma = nn[t1], mb = nn[t2];
+    int K1 = na > ma ? na : ma, K2 = nb > mb ? nb : mb;
+    double *oth = malloc(sizeof(double) * NV * ma * mb);
+    face_trace(nn, d, -s, NV, u + NV * off[nbr], oth);
+    double *A = malloc(sizeof(double) * NV * K1 * K2), *B = malloc(sizeof(double) * NV * K1 * K2);
+    to_mortar(NV, na, nb, K1, K2, own, A);
+    to_mortar(NV, ma, mb, K1, K2, oth, B);
+    for (int x = 0; x < NV * K1 * K2; ++x) A[x] = 0.5 * (A[x] + B[x]);
+    from_mortar(NV, na, nb, K1, K2, A, qhat);
+    free(own); free(oth); free(A); free(B);
+}
+
+/* J dQ/dx_l = Ja_l [ D_l Q + sum_s (qhat - Q) s / w_end on the l-faces ] (affine). */
+static void element_gradient(const orc_mesh *m, const int *orders, const long *off, const double *u, int e,
+                             int isolated, double *grad)
+{
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+    const double *Q = u + NV * off[e];
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+    for (int l = 0; l < 3; ++l) {
+        double *Gl = grad + (size_t)l * NV * ne;
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i) {
+                    int idx[3] = {i, j, k};
+                    int node = i + n[0] * (j + n[1] * k);
+                    for (int v = 0; v < NV; ++v) {
+                        double acc = 0.0;
+                        for (int q = 0; q < n[l]; ++q) {
+                            int id2[3] = {i, j, k};
+                            id2[l] = q;
+                            acc += g_D[o[l]][idx[l] * n[l] + q] * Q[v * ne + id2[0] + n[0] * (id2[1] + n[1] * id2[2])];
+                        }
+                        Gl[v * ne + node] = acc;
+                    }
+                }
+        if (!isolated) {
+            int t1 = (l == 0) ? 1 : 0, t2 = (l == 2) ? 1 : 2;
+            int na = n[t1], nb = n[t2];
+            double *qh = malloc(sizeof(double) * NV * na * nb);
+            for (int s = -1; s <= 1; s += 2) {
+                br1_qhat(m, orders, off, u, e, l, s, qh);
+                for (int b = 0; b < nb; ++b)
+                    for (int a = 0; a < na; ++a) {
+                        int node = face_node(n, l, s, a, b);
+                        for (int v = 0; v < NV; ++v)
+                            Gl[v * ne + node] += (double)s * (qh[v * na * nb + a + na * b] - Q[v * ne + node]) /
+                                                 g_w[o[l]][0];
+                    }
+            }
+            free(qh);
+        }
+        for (int x = 0; x < NV * ne; ++x) Gl[x] *= Ja[l] / J;
+    }
+}
+
+int orc_gradient(const orc_mesh *m, const int *orders, const double *u, int isolated, double *grad)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (E <= 0 || check_orders(E, orders)) return -1;
+    ensure_tables();
+    long *off = node_offsets(E, orders);
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e) element_gradient(m, orders, off, u, e, isolated, grad + 3 * NV * off[e]);
+    free(off);
+    return 0;
+}
+
+/* Outward NS flux on face (d, s) of element e at its own face nodes:
+ * s * P_own [ |Ja| ( f*_Roe(QL^K, QR^K, e_d) - (1/2)(f^v_d(QL^K, GL^K) + f^v_d(QR^K, GR^K)) ) ],
+ * left = minus side; at boundaries the ghost state carries the inner gradient. */
+static void face_flux_ns(const orc_mesh *m, const int *orders, const long *off, const double *u,
+                         const double *grad, double mu, double Pr, int e, int d, int s, const double *Ja,
+                         double *fout)
+{
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
+    int na = n[t1], nb = n[t2];
+    const int nf = 4 * NV; /* Q and the three gradient components */
+    double *own = malloc(sizeof(double) * nf * na * nb);
+    face_trace(n, d, s, NV, u + NV * off[e], own);
+    face_trace(n, d, s, 3 * NV, grad + 3 * NV * off[e], own + NV * na * nb);
+    double g = m->gamma;
+    int bc;
+    int nbr = neighbour(m, e, d, s, &bc);
+    if (nbr < 0) {
+        double nout[3] = {0, 0, 0};
+        nout[d] = (double)s;
+        for (int x = 0; x < na * nb; ++x) {
+            double qin[NV], qg[NV], G[3 * NV], fa[NV], fv1[NV], fv2[NV];
+            for (int v = 0; v < NV; ++v) qin[v] = own[v * na * nb + x];
+            for (int c = 0; c < 3 * NV; ++c) G[c] = own[(NV + c) * na * nb + x];
+            ghost_state(m, bc, d, s, qin, qg);
+            orc_numflux(qin, qg, nout, g, m->flux, fa);
+            orc_viscous_flux(qin, G, d, g, mu, Pr, fv1);
+            orc_viscous_flux(qg, G, d, g, mu, Pr, fv2);
+            for (int v = 0; v < NV; ++v)
+                fout[v * na * nb + x] = Ja[d] * (fa[v] - (double)s * 0.5 * (fv1[v] + fv2[v]));
+        }
+        free(own);
+        return;
+    }
+    const int *on = orders + 3 * nbr;
+    int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1};
+    int ma = nn[t1], mb = nn[t2];
+    double *oth = malloc(sizeof(double) * nf * ma * mb);
+    face_trace(nn, d, -s, NV, u + NV * off[nbr], oth);
+    face_trace(nn, d, -s, 3 * NV, grad + 3 * NV * off[nbr], oth + NV * ma * mb);
+    int K1 = na > ma ? na : ma, K2 = nb > mb ? nb : mb;
+    double *A = malloc(sizeof(double) * nf * K1 * K2), *B = malloc(sizeof(double) * nf * K1 * K2);
+    to_mortar(nf, na, nb, K1, K2, own, A);
+    to_mortar(nf, ma, mb, K1, K2, oth, B);
+    double *L = s > 0 ? A : B, *R = s > 0 ? B : A;
+    double *FK = malloc(sizeof(double) * NV * K1 * K2);
+    double nplus[3] = {0, 0, 0};
+    nplus[d] = 1.0;
+    int KK = K1 * K2;
+    for (int x = 0; x < KK; ++x) {
+        double qL[NV], qR[NV], GL[3 * NV], GR[3 * NV], fa[NV], fvL[NV], fvR[NV];
+        for (int v = 0; v < NV; ++v) { qL[v] = L[v * KK + x]; qR[v] = R[v * KK + x]; }
+        for (int c = 0; c < 3 * NV; ++c) { GL[c] = L[(NV + c) * KK + x]; GR[c] = R[(NV + c) * KK + x]; }
+        orc_numflux(qL, qR, nplus, g, m->flux, fa);
+        orc_viscous_flux(qL, GL, d, g, mu, Pr, fvL);
+        orc_viscous_flux(qR, GR, d, g, mu, Pr, fvR);
+        for (int v = 0; v < NV; ++v) FK[v * KK + x] = Ja[d] * (fa[v] - 0.5 * (fvL[v] + fvR[v]));
+    }
+    from_mortar(NV, na, nb, K1, K2, FK, fout);
+    for (int x = 0; x < NV * na * nb; ++x) fout[x] *= (double)s;
+    free(own); free(oth); free(A); free(B); free(FK);
+}
+
+static void element_residual_ns(const orc_mesh *m, const int *orders, const long *off, const double *u,
+                                const double *grad, double mu, double Pr, int e, int form, int isolated, double *r)
+{
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+    const double *Q = u + NV * off[e];
+    const double *G = grad + 3 * NV * off[e];
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+    double *Ft = malloc(sizeof(double) * 3 * NV * ne), *V = calloc((size_t)NV * ne, sizeof(double));
+    for (int node = 0; node < ne; ++node) {
+        double q[NV], Gn[3 * NV], fa[NV], fv[NV];
+        for (int v = 0; v < NV; ++v) q[v] = Q[v * ne + node];
+        for (int l = 0; l < 3; ++l)
+            for (int v = 0; v < NV; ++v) Gn[5 * l + v] = G[(l * NV + v) * ne + node];
+        for (int d = 0; d < 3; ++d) {
+            double nd[3] = {0, 0, 0};
+            nd[d] = 1.0;
+            orc_flux_n(q, nd, m->gamma, fa);
+            orc_viscous_flux(q, Gn, d, m->gamma, mu, Pr, fv);
+            for (int v = 0; v < NV; ++v) Ft[(d * NV + v) * ne + node] = Ja[d] * (fa[v] - fv[v]);
+        }
+    }
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int node = i + n[0] * (j + n[1] * k);
+                for (int v = 0; v < NV; ++v) {
+                    double acc = 0.0;
+                    for (int q = 0; q < n[0]; ++q)
+                        acc += g_D[o[0]][i * n[0] + q] * Ft[(0 * NV + v) * ne + q + n[0] * (j + n[1] * k)];
+                    for (int q = 0; q < n[1]; ++q)
+                        acc += g_D[o[1]][j * n[1] + q] * Ft[(1 * NV + v) * ne + i + n[0] * (q + n[1] * k)];
+                    for (int q = 0; q < n[2]; ++q)
+                        acc += g_D[o[2]][k * n[2] + q] * Ft[(2 * NV + v) * ne + i + n[0] * (j + n[1] * q)];
+                    V[v * ne + node] = acc;
+                }
+            }
+    if (!isolated) {
+        for (int d = 0; d < 3; ++d) {
+            int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            int na = n[t1], nb = n[t2];
+            double *fout = malloc(sizeof(double) * NV * na * nb);
+            for (int s = -1; s <= 1; s += 2) {
+                face_flux_ns(m, orders, off, u, grad, mu, Pr, e, d, s, Ja, fout);
+                for (int b = 0; b < nb; ++b)
+                    for (int a = 0; a < na; ++a) {
+                        int node = face_node(n, d, s, a, b);
+                        for (int v = 0; v < NV; ++v)
+                            V[v * ne + node] += (fout[v * na * nb + a + na * b] -
+                                                 (double)s * Ft[(d * NV + v) * ne + node]) / g_w[o[d]][0];
+                    }
+            }
+            free(fout);
+        }
+    }
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int node = i + n[0] * (j + n[1] * k);
+                double www = g_w[o[0]][i] * g_w[o[1]][j] * g_w[o[2]][k];
+                for (int v = 0; v < NV; ++v)
+                    r[v * ne + node] = form == 0 ? V[v * ne + node] / J : www * V[v * ne + node];
+            }
+    free(Ft);
+    free(V);
+}
+
+int orc_residual_ns(const orc_mesh *m, const int *orders, const double *u, double mu, double Pr, double *r,
+                    int form, int isolated)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (E <= 0 || check_orders(E, orders) || (form != 0 && form != 1)) return -1;
+    ensure_tables();
+    long *off = node_offsets(E, orders);
+    double *grad = malloc(sizeof(double) * 3 * NV * off[E]);
+    orc_gradient(m, orders, u, isolated, grad);
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e)
+        element_residual_ns(m, orders, off, u, grad, mu, Pr, e, form, isolated, r + NV * off[e]);
+    free(grad);
+    free(off);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Tau-estimation.                                                           */
 
 /* Sample the order-(nf) element polynomial at the order-(nc) nodes:

@@ -91,6 +91,17 @@ int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_ord
  * layout) receives dJ/dQ (zero away from those faces). */
 int orc_functional(const orc_mesh *m, const int *orders, const double *u, double *J, double *dJdu);
 
+/* Navier-Stokes with the BR1 viscous discretisation (first-order system of
+ * Section 2.1, eqs. SystemAdvDiff and DGSEMsystem:2).  Gradients of the conserved
+ * variables: grad natural layout [e][3][5][node] (d(var)/dx_l at each node).
+ * Constant viscosity mu, Stokes hypothesis, heat conductivity mu gamma/((gamma-1) Pr)
+ * acting on T = p/rho.  isolated drops every surface term of both passes. */
+int orc_gradient(const orc_mesh *m, const int *orders, const double *u, int isolated, double *grad);
+int orc_residual_ns(const orc_mesh *m, const int *orders, const double *u, double mu, double Pr,
+                    double *r, int form, int isolated);
+/* Viscous flux f^v_d(Q, G) along direction d, G[l*5 + v] = d(var v)/dx_l. */
+void orc_viscous_flux(const double *q, const double *G, int d, double gamma, double mu, double Pr, double *f);
+
 /* Williamson low-storage RK3, nsteps steps of size dt, in place on u. */
 int orc_rk3(const orc_mesh *m, const int *orders, double *u, double dt, int nsteps);
 

@@ -312,7 +312,8 @@ template <typename T>
 dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s) {
     const T *tab = std::is_same<T, double>::value ? (const T *)p->tabs.t64 : (const T *)p->tabs.t32;
     if (!epi.isolated)
-        HIP_TRY(launch_face_flux<T>(p->d_faces, p->nfaces, p->d_el, u, (T *)p->d_ff, tab, p->geom, p->phys, s));
+        HIP_TRY(launch_face_flux<T>(p->d_faces, p->nfaces, p->d_el, u, (T *)p->d_ff, tab, p->geom, p->phys,
+                                    p->max_order, s));
     for (const TileClass &c : p->classes)
         HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)p->d_ff, tab, p->geom,
                                   p->phys, epi, s));

@@ -82,7 +82,7 @@ struct PhysParams {
 // Host-side launch wrappers (defined in the .hip files).
 template <typename T>
 hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems, const T *u, T *fflux,
-                            const T *tab, Geom g, PhysParams ph, hipStream_t s);
+                            const T *tab, Geom g, PhysParams ph, int max_order, hipStream_t s);
 
 enum EpiMode { EPI_RESIDUAL = 0, EPI_RK = 1, EPI_TAU = 2 };
 

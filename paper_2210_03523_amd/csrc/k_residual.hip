@@ -40,22 +40,25 @@ __device__ __forceinline__ int face_node(const int32_t *n, int d, int side, int 
 }
 
 // ---------------------------------------------------------------------------- faces
-template <typename T>
+// FN = largest number of nodes of a face (and of a mortar) the launch may meet:
+// 64 for orders up to 7, 100 up to 9.  It sizes the LDS staging and so the number
+// of faces resident per CU.
+template <typename T, int FN>
 struct FaceSmem {
-    T QL[NV][NNMAX * NNMAX];   // left trace, later the left projection intermediate
-    T QR[NV][NNMAX * NNMAX];   // right trace, later the right projection intermediate
-    T TL[NV][NNMAX * NNMAX];   // left trace interpolated along the first tangential direction
-    T TR[NV][NNMAX * NNMAX];
-    T F[NV][NNMAX * NNMAX];    // Riemann flux on the mortar
+    T QL[NV][FN];   // left trace, later the left projection intermediate
+    T QR[NV][FN];   // right trace, later the right projection intermediate
+    T TL[NV][FN];   // left trace interpolated along the first tangential direction
+    T TR[NV][FN];
+    T F[NV][FN];    // Riemann flux on the mortar
 };
 
 // One face, processed by one wavefront (64 lanes).  Mortar interpolation S2 (x) S1 and
 // projection P2 (x) P1 are applied one tangential direction at a time, and only in a
 // direction where the two sides' orders differ.
-template <typename T>
+template <typename T, int FN>
 __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restrict__ el, const T *__restrict__ u,
                                           T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
-                                          const PhysParams &ph, FaceSmem<T> &sm) {
+                                          const PhysParams &ph, FaceSmem<T, FN> &sm) {
     const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const T Ja = (T)g.Ja[d];
     const T gam = (T)ph.gamma;
@@ -131,8 +134,8 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
     for (int side = 0; side < 2; ++side) {
         const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
         if (na == K1) continue;
-        T(*Q)[NNMAX * NNMAX] = side == 0 ? sm.QL : sm.QR;
-        T(*Tt)[NNMAX * NNMAX] = side == 0 ? sm.TL : sm.TR;
+        T(*Q)[FN] = side == 0 ? sm.QL : sm.QR;
+        T(*Tt)[FN] = side == 0 ? sm.TL : sm.TR;
         const T *S1 = tab + T_I + moff(K1 - 1, na - 1);
         for (int m = lane; m < K1 * nb; m += 64) {
             const int A = m % K1, b = m / K1;
@@ -153,7 +156,7 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
         T q[2][NV], F[NV];
         for (int side = 0; side < 2; ++side) {
             const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
-            T(*src)[NNMAX * NNMAX] = na == K1 ? (side == 0 ? sm.QL : sm.QR) : (side == 0 ? sm.TL : sm.TR);
+            T(*src)[FN] = na == K1 ? (side == 0 ? sm.QL : sm.QR) : (side == 0 ? sm.TL : sm.TR);
             if (nb == K2) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) q[side][v] = src[v][A + K1 * B];
@@ -178,7 +181,7 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
     for (int side = 0; side < 2; ++side) {
         const int na = side == 0 ? aL : aR;
         if (na == K1) continue;
-        T(*U)[NNMAX * NNMAX] = side == 0 ? sm.QL : sm.QR;
+        T(*U)[FN] = side == 0 ? sm.QL : sm.QR;
         const T *P1 = tab + T_P + moff(na - 1, K1 - 1);
         for (int m = lane; m < na * K2; m += 64) {
             const int a = m % na, B = m / na;
@@ -199,7 +202,7 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
         T *out = side == 0 ? oL : oR;
         const T sg = side == 0 ? T(1) : T(-1);
         const bool x1 = na != K1;  // the first pass ran: intermediate in QL/QR as [a + na B]
-        T(*U)[NNMAX * NNMAX] = x1 ? (side == 0 ? sm.QL : sm.QR) : sm.F;
+        T(*U)[FN] = x1 ? (side == 0 ? sm.QL : sm.QR) : sm.F;
         const int ld = x1 ? na : K1;
         const T *P2 = tab + T_P + moff(nb - 1, K2 - 1);
         for (int m = lane; m < na * nb; m += 64) {
@@ -223,19 +226,22 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
     }
 }
 
-template <typename T>
+template <typename T, int FN>
 __global__ __launch_bounds__(64) void k_face(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
                                              const T *__restrict__ u, T *__restrict__ ff,
                                              const T *__restrict__ tab, Geom g, PhysParams ph) {
-    __shared__ FaceSmem<T> sm;
-    face_body<T>(faces[blockIdx.x], el, u, ff, tab, g, ph, sm);
+    __shared__ FaceSmem<T, FN> sm;
+    face_body<T, FN>(faces[blockIdx.x], el, u, ff, tab, g, ph, sm);
 }
 
 template <typename T>
 hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems, const T *u, T *fflux,
-                            const T *tab, Geom g, PhysParams ph, hipStream_t s) {
+                            const T *tab, Geom g, PhysParams ph, int max_order, hipStream_t s) {
     if (nfaces == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_face<T>, dim3(nfaces), dim3(64), 0, s, faces, elems, u, fflux, tab, g, ph);
+    if (max_order <= 7)
+        hipLaunchKernelGGL((k_face<T, 64>), dim3(nfaces), dim3(64), 0, s, faces, elems, u, fflux, tab, g, ph);
+    else
+        hipLaunchKernelGGL((k_face<T, 100>), dim3(nfaces), dim3(64), 0, s, faces, elems, u, fflux, tab, g, ph);
     return hipGetLastError();
 }
 
@@ -457,11 +463,11 @@ hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, con
 template <typename T>
 __global__ __launch_bounds__(64) void k_face_batch(const int2 *__restrict__ faces, int nfaces,
                                                    const ProbDesc<T> *__restrict__ probs, const T *__restrict__ tab) {
-    __shared__ FaceSmem<T> sm;
+    __shared__ FaceSmem<T, 64> sm;  // batches hold orders up to 7
     for (int i = blockIdx.x; i < nfaces; i += gridDim.x) {
         const int2 pf = faces[i];
         const ProbDesc<T> pd = probs[pf.x];
-        face_body<T>(pd.faces[pf.y], pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, sm);
+        face_body<T, 64>(pd.faces[pf.y], pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, sm);
         __syncthreads();
     }
 }
@@ -527,9 +533,9 @@ template hipError_t launch_fill_state<double>(const ElemInfo *, int, double *, h
 template hipError_t launch_fill_state<float>(const ElemInfo *, int, float *, hipStream_t);
 
 template hipError_t launch_face_flux<double>(const Face *, int, const ElemInfo *, const double *, double *,
-                                             const double *, Geom, PhysParams, hipStream_t);
+                                             const double *, Geom, PhysParams, int, hipStream_t);
 template hipError_t launch_face_flux<float>(const Face *, int, const ElemInfo *, const float *, float *,
-                                            const float *, Geom, PhysParams, hipStream_t);
+                                            const float *, Geom, PhysParams, int, hipStream_t);
 template hipError_t launch_element<double>(const Tile *, int, int, int, const ElemInfo *, const double *,
                                            const double *, const double *, Geom, PhysParams, EpiArgs, hipStream_t);
 template hipError_t launch_element<float>(const Tile *, int, int, int, const ElemInfo *, const float *,
