@@ -43,6 +43,7 @@ enum {
 };
 
 enum { DG_BC_PERIODIC = 0, DG_BC_SLIP_WALL = 1, DG_BC_FARFIELD = 2 };
+enum { DG_EULER = 0, DG_NAVIER_STOKES = 1 };
 enum { DG_FLUX_ROE = 0, DG_FLUX_LF = 1 };
 enum { DG_F64 = 0, DG_F32 = 1 };
 /* Residual forms (Section 2.2): NEW = M^-1 F^N(Q) = -dQ/dt, TRAD = F^N(Q) = M * NEW. */
@@ -62,10 +63,18 @@ typedef struct {
     int32_t flux;     /* DG_FLUX_ROE (the paper's advective flux) or DG_FLUX_LF */
     double gamma;     /* ratio of specific heats */
     double q_far[5];  /* conserved far-field state for DG_BC_FARFIELD faces */
+    int32_t equation; /* DG_EULER or DG_NAVIER_STOKES (BR1, Section 2.1 eqs. SystemAdvDiff) */
+    double mu;        /* Navier-Stokes: constant dynamic viscosity (nondimensional, 1/Re) */
+    double Pr;        /* Navier-Stokes: Prandtl number; heat conductivity mu gamma/((gamma-1) Pr) on T = p/rho */
 } dg_mesh_desc;
 
-/* Build a plan for the compressible Euler DGSEM (Section 2.1) on the mesh
- * with per-element anisotropic orders.
+/* Build a plan for the compressible Euler or Navier-Stokes DGSEM (Section 2.1) on
+ * the mesh with per-element anisotropic orders.  Navier-Stokes uses the BR1 scheme
+ * of the paper's set-up: gradients of the conserved variables from the averaged
+ * solution trace, viscous face flux = average of both sides' viscous fluxes; at
+ * boundaries the ghost state carries the inner gradient.  Navier-Stokes plans
+ * support orders up to 7 and neither the sweep, the VJP nor batches
+ * (DG_EUNSUPPORTED).
  *   orders_host: host int32 [E][3], natural element order, each in 1..DG_NMAX.
  *   out: receives the plan (release with dg_plan_destroy).
  * Errors: DG_EINVAL (bad mesh, orders or periodic pairing), DG_ENOMEM, DG_EHIP. */

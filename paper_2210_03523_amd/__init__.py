@@ -34,7 +34,8 @@ class _MeshDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("bc", ctypes.c_int32 * 6), ("flux", ctypes.c_int32),
-                ("gamma", ctypes.c_double), ("q_far", ctypes.c_double * 5)]
+                ("gamma", ctypes.c_double), ("q_far", ctypes.c_double * 5),
+                ("equation", ctypes.c_int32), ("mu", ctypes.c_double), ("Pr", ctypes.c_double)]
 
 
 _lib = None
@@ -128,6 +129,9 @@ def mesh_desc(mesh: dict) -> _MeshDesc:
     m.gamma = float(mesh["gamma"])
     for v in range(5):
         m.q_far[v] = float(mesh["qfar"][v])
+    m.equation = 1 if mesh.get("mu") is not None else 0
+    m.mu = float(mesh.get("mu") or 0.0)
+    m.Pr = float(mesh.get("Pr", 0.72))
     return m
 
 

@@ -103,6 +103,8 @@ struct dg_plan_s {
     dg_plan_s *parent = nullptr;
     int32_t *d_fine_of = nullptr;
     double *d_uc = nullptr, *d_rdc = nullptr, *d_psic = nullptr;
+    bool ns = false;              // Navier-Stokes plan
+    void *d_grad = nullptr;       // BR1 gradients [elem][3][5][node], sized for doubles
     // x-force functional: boundary faces on slip walls normal to x, and their partial sums
     int32_t *d_wallx = nullptr;
     int nwallx = 0;
@@ -134,7 +136,7 @@ void destroy_plan(dg_plan p) {
     for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     void *bufs[] = {p->d_el, p->d_faces, p->d_tiles, p->d_ff, p->d_dudt, p->d_fine_of, p->d_uc, p->d_rdc,
-                    p->d_psic, p->d_combo_off, p->d_tasks, p->d_iso, p->d_wallx, p->d_part};
+                    p->d_psic, p->d_combo_off, p->d_tasks, p->d_iso, p->d_wallx, p->d_part, p->d_grad};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -155,6 +157,9 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
     }
     if (mesh->flux != DG_FLUX_ROE && mesh->flux != DG_FLUX_LF) return fail(DG_EINVAL, "unknown flux");
     if (!(mesh->gamma > 1.0)) return fail(DG_EINVAL, "gamma must exceed 1");
+    if (mesh->equation != DG_EULER && mesh->equation != DG_NAVIER_STOKES) return fail(DG_EINVAL, "unknown equation");
+    if (mesh->equation == DG_NAVIER_STOKES && !(mesh->mu >= 0.0 && mesh->Pr > 0.0))
+        return fail(DG_EINVAL, "Navier-Stokes needs mu >= 0 and Pr > 0");
     const int E = (int)E64;
     for (int i = 0; i < 3 * E; ++i)
         if (orders[i] < 1 || orders[i] > DG_NMAX) return fail(DG_EINVAL, "orders must be in 1..9");
@@ -259,6 +264,15 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
     }
     p->phys.gamma = mesh->gamma;
     p->phys.flux = mesh->flux;
+    p->ns = mesh->equation == DG_NAVIER_STOKES;
+    if (p->ns) {
+        p->phys.mu = mesh->mu;
+        p->phys.kappa = mesh->mu * mesh->gamma / ((mesh->gamma - 1.0) * mesh->Pr);
+    }
+    if (p->ns && p->max_order > 7) {
+        destroy_plan(p);
+        return fail(DG_EUNSUPPORTED, "Navier-Stokes plans support orders up to 7");
+    }
     for (int v = 0; v < NV; ++v) p->phys.qfar[v] = mesh->q_far[v];
 
     // sweep layout: combos per element; isotropic elements (F <= 8) go to the fast
@@ -299,7 +313,8 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
     if (hipMalloc(&p->d_ff, sizeof(double) * std::max<int64_t>(1, p->ff_len)) != hipSuccess ||
         hipMalloc((void **)&p->d_part, sizeof(double) * std::max(1, p->nwallx)) != hipSuccess ||
         hipMalloc((void **)&p->d_dudt, sizeof(double) * NV * p->n_nodes) != hipSuccess ||
-        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        (p->ns && hipMalloc(&p->d_grad, sizeof(double) * 3 * NV * p->n_nodes) != hipSuccess)) {
         destroy_plan(p);
         return fail(DG_ENOMEM, "device allocation failed");
     }
@@ -311,6 +326,25 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
 template <typename T>
 dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s) {
     const T *tab = std::is_same<T, double>::value ? (const T *)p->tabs.t64 : (const T *)p->tabs.t32;
+    if (p->ns) {
+        // BR1: solution trace, gradients, viscous face fluxes, then the element pass
+        for (size_t i = 0; i < p->classes.size(); ++i) {
+            const TileClass &c = p->classes[i];
+            HIP_TRY(launch_ns_gradient<T>(p->d_faces, p->nfaces, p->d_tiles, c.first, c.count, c.npt, i == 0, p->d_el,
+                                          u, (T *)p->d_ff, (T *)p->d_grad, tab, p->geom, p->phys, p->max_order,
+                                          epi.isolated, s));
+        }
+        if (!epi.isolated)
+            HIP_TRY(launch_ns_faces<T>(p->d_faces, p->nfaces, p->d_el, u, (const T *)p->d_grad, (T *)p->d_ff, tab,
+                                       p->geom, p->phys, s));
+        epi.grad = p->d_grad;
+        epi.mu = p->phys.mu;
+        epi.kappa = p->phys.kappa;
+        for (const TileClass &c : p->classes)
+            HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)p->d_ff, tab,
+                                      p->geom, p->phys, epi, s));
+        return DG_OK;
+    }
     if (!epi.isolated)
         HIP_TRY(launch_face_flux<T>(p->d_faces, p->nfaces, p->d_el, u, (T *)p->d_ff, tab, p->geom, p->phys,
                                     p->max_order, s));
@@ -436,6 +470,7 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *t
                        hipStream_t stream) {
     if (!p || !u || !te_new || !te_trad) return fail(DG_EINVAL, "null argument");
     if (p->max_order > 8) return fail(DG_EUNSUPPORTED, "the sweep supports fine orders up to 8");
+    if (p->ns) return fail(DG_EUNSUPPORTED, "the sweep is implemented for the Euler equations");
     if (!dudt) {
         EpiArgs epi{};
         epi.mode = EPI_RESIDUAL;
@@ -495,6 +530,7 @@ dg_status dg_residual_vjp(dg_plan p, const double *u, const double *v, double *o
     if (!p || !u || !v || !out) return fail(DG_EINVAL, "null argument");
     if (out == u || out == v) return fail(DG_EINVAL, "out must not overlap u or v");
     if (form != DG_FORM_NEW && form != DG_FORM_TRAD) return fail(DG_EINVAL, "unknown form");
+    if (p->ns) return fail(DG_EUNSUPPORTED, "the VJP is implemented for the Euler equations");
     for (size_t i = 0; i < p->classes.size(); ++i) {
         const TileClass &c = p->classes[i];
         HIP_TRY(launch_vjp(p->d_faces, p->nfaces, p->d_tiles, c.first, c.count, c.npt, p->d_el, u, v,
@@ -700,6 +736,7 @@ dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_bat
     for (int i = 0; i < n; ++i) {
         if (!plans[i]) return fail(DG_EINVAL, "null plan in batch");
         if (plans[i]->max_order > 7) return fail(DG_EUNSUPPORTED, "batched launches support orders up to 7");
+        if (plans[i]->ns) return fail(DG_EUNSUPPORTED, "batched launches run the Euler equations");
     }
     dg_batch b = new dg_batch_s();
     b->plans.assign(plans, plans + n);

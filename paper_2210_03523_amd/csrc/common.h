@@ -77,6 +77,7 @@ struct PhysParams {
     int32_t flux;
     int32_t pad;
     double qfar[NV];
+    double mu, kappa;   // Navier-Stokes (mu = 0: Euler)
 };
 
 // Host-side launch wrappers (defined in the .hip files).
@@ -98,6 +99,8 @@ struct EpiArgs {
     double *norms;      // [E][2] (tau)
     const void *psic;   // restricted adjoint weight (tau, optional)
     double *eta;        // [E] sum of psic * tau_trad (tau, optional)
+    const void *grad;   // Navier-Stokes: BR1 gradients [elem][3][5][node] (null for Euler)
+    double mu, kappa;   // viscosity and heat conductivity
 };
 
 template <typename T>
@@ -160,6 +163,15 @@ hipError_t launch_elem_batch(const BatchTile *tiles, int ntiles, const ProbDesc<
                              EpiArgs epi, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_state(const ElemInfo *el, int E, T *u, hipStream_t s);
+
+// Navier-Stokes (BR1) passes: BR1 solution trace on the faces, gradients, viscous face fluxes.
+template <typename T>
+hipError_t launch_ns_gradient(const Face *faces, int nfaces, const Tile *tiles, int tile0, int ntiles, int npt,
+                              bool do_faces, const ElemInfo *el, const T *u, T *fq, T *grad, const T *tab, Geom g,
+                              PhysParams ph, int max_order, int isolated, hipStream_t s);
+template <typename T>
+hipError_t launch_ns_faces(const Face *faces, int nfaces, const ElemInfo *el, const T *u, const T *grad, T *ff,
+                           const T *tab, Geom g, PhysParams ph, hipStream_t s);
 
 // Host tables (tables.cpp): fills T_TOT values.
 void build_tables(double *tab64, float *tab32);

@@ -80,4 +80,36 @@ __device__ __forceinline__ void numflux_axis(const T qL[5], const T qR[5], int d
     for (int v = 0; v < 5; ++v) F[v] = s * T(0.5) * (fL[v] + fR[v]) - T(0.5) * diss[v];
 }
 
+// Viscous flux f^v_d(Q, G) of the Navier-Stokes equations along direction d
+// (BR1: G[l*5 + v] = d(conserved v)/dx_l): Stokes stress with constant mu and Fourier
+// heat flux kappa grad T on T = p/rho, kappa = mu gamma / ((gamma-1) Pr).
+template <typename T>
+__device__ __forceinline__ void viscous_axis(const T q[5], const T G[15], int d, T gamma, T mu, T kappa,
+                                             T f[5]) {
+    const T ri = T(1) / q[0];
+    const T u[3] = {q[1] * ri, q[2] * ri, q[3] * ri};
+    const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T p = (gamma - T(1)) * (q[4] - T(0.5) * q[0] * uu);
+    const T Tt = p * ri;
+    T du[3][3], dT[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const T *Gl = G + 5 * l;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) du[k][l] = (Gl[1 + k] - u[k] * Gl[0]) * ri;
+        const T dp = (gamma - T(1)) * (Gl[4] - (u[0] * Gl[1] + u[1] * Gl[2] + u[2] * Gl[3]) + T(0.5) * uu * Gl[0]);
+        dT[l] = (dp - Tt * Gl[0]) * ri;
+    }
+    const T div = du[0][0] + du[1][1] + du[2][2];
+    T tau[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) tau[k] = mu * (du[k][d] + du[d][k]);
+    tau[d] -= T(2.0 / 3.0) * mu * div;
+    f[0] = T(0);
+    f[1] = tau[0];
+    f[2] = tau[1];
+    f[3] = tau[2];
+    f[4] = u[0] * tau[0] + u[1] * tau[1] + u[2] * tau[2] + kappa * dT[d];
+}
+
 }  // namespace dgt

@@ -55,7 +55,10 @@ struct FaceSmem {
 // One face, processed by one wavefront (64 lanes).  Mortar interpolation S2 (x) S1 and
 // projection P2 (x) P1 are applied one tangential direction at a time, and only in a
 // direction where the two sides' orders differ.
-template <typename T, int FN>
+// MODE 0: outward Riemann flux F*_out (plus side negated).  MODE 1: the BR1 trace of the
+// solution, (Q_L + Q_R)/2 on the mortar projected back onto both sides (no sign, no
+// metric), the face input of the gradient pass.
+template <typename T, int FN, int MODE = 0>
 __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restrict__ el, const T *__restrict__ u,
                                           T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
                                           const PhysParams &ph, FaceSmem<T, FN> &sm) {
@@ -84,9 +87,14 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
 #pragma unroll
                 for (int v = 0; v < NV; ++v) qg[v] = (T)ph.qfar[v];
             }
-            numflux_axis(qin, qg, d, (T)s, gam, ph.flux, F);
+            if (MODE == 0) {
+                numflux_axis(qin, qg, d, (T)s, gam, ph.flux, F);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) out[v * na * nb + m] = Ja * F[v];
+                for (int v = 0; v < NV; ++v) out[v * na * nb + m] = Ja * F[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) out[v * na * nb + m] = T(0.5) * (qin[v] + qg[v]);
+            }
         }
         return;
     }
@@ -109,11 +117,20 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
                 qL[v] = u[NV * L.noff + v * neL + nl];
                 qR[v] = u[NV * R.noff + v * neR + nr];
             }
-            numflux_axis(qL, qR, d, T(1), gam, ph.flux, F);
+            if (MODE == 0) {
+                numflux_axis(qL, qR, d, T(1), gam, ph.flux, F);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                oL[v * aL * bL + m] = Ja * F[v];
-                oR[v * aL * bL + m] = -Ja * F[v];
+                for (int v = 0; v < NV; ++v) {
+                    oL[v * aL * bL + m] = Ja * F[v];
+                    oR[v * aL * bL + m] = -Ja * F[v];
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const T h = T(0.5) * (qL[v] + qR[v]);
+                    oL[v * aL * bL + m] = h;
+                    oR[v * aL * bL + m] = h;
+                }
             }
         }
         return;
@@ -172,9 +189,14 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
                 for (int v = 0; v < NV; ++v) q[side][v] = acc[v];
             }
         }
-        numflux_axis(q[0], q[1], d, T(1), gam, ph.flux, F);
+        if (MODE == 0) {
+            numflux_axis(q[0], q[1], d, T(1), gam, ph.flux, F);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sm.F[v][m] = Ja * F[v];
+            for (int v = 0; v < NV; ++v) sm.F[v][m] = Ja * F[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sm.F[v][m] = T(0.5) * (q[0][v] + q[1][v]);
+        }
     }
     __syncthreads();
     // projection, first tangential direction: U[a + na B] = sum_A P1[a][A] F[A + K1 B]
@@ -200,7 +222,7 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
     for (int side = 0; side < 2; ++side) {
         const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
         T *out = side == 0 ? oL : oR;
-        const T sg = side == 0 ? T(1) : T(-1);
+        const T sg = (side == 0 || MODE == 1) ? T(1) : T(-1);
         const bool x1 = na != K1;  // the first pass ran: intermediate in QL/QR as [a + na B]
         T(*U)[FN] = x1 ? (side == 0 ? sm.QL : sm.QR) : sm.F;
         const int ld = x1 ? na : K1;
@@ -263,6 +285,8 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
     T q[NPT][NV], V[NPT][NV];
     int loc[NPT][3], le[NPT], nd[NPT];
     bool ok[NPT];
+    const bool visc = epi.grad != nullptr;
+    const T mu = (T)epi.mu, kappa = (T)epi.kappa, gam = (T)ph.gamma;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int t = tid + k * WG;
@@ -279,6 +303,19 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
             V[k][v] = T(0);
         }
     }
+    // total flux along d at this thread's k-th node: |Ja^d| (f^a_d - f^v_d)
+    auto total_flux = [&](int k, int d, T f[NV]) {
+        flux_axis(q[k], d, gm1, f);
+        if (visc && ok[k]) {
+            const T *Gp = (const T *)epi.grad + (int64_t)3 * NV * (E0.noff + (int64_t)le[k] * npe) + nd[k];
+            T G[15], fv[NV];
+#pragma unroll
+            for (int c = 0; c < 15; ++c) G[c] = Gp[(int64_t)c * npe];
+            viscous_axis(q[k], G, d, gam, mu, kappa, fv);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) f[v] -= fv[v];
+        }
+    };
     const int nn[3] = {n1, n2, n3};
     const int stride[3] = {1, n1, n1 * n2};
 #pragma unroll
@@ -287,7 +324,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             T f[NV];
-            flux_axis(q[k], d, gm1, f);
+            total_flux(k, d, f);
             const int t = tid + k * WG;
             if (ok[k]) {
 #pragma unroll
@@ -331,7 +368,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
                 const T iw = T(1) / tab[T_W + xoff(nd_ - 1)];
                 const T Ja = (T)g.Ja[d];
                 T f[NV];
-                flux_axis(q[k], d, gm1, f);
+                total_flux(k, d, f);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) V[k][v] += (fs[v * na * nb + fm] - T(s) * Ja * f[v]) * iw;
             }
@@ -456,6 +493,243 @@ hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, con
     }
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------- Navier-Stokes (BR1)
+// Pass 1 (faces): BR1 solution trace qhat = (Q_L + Q_R)/2 on the mortar, projected back.
+// Pass 2 (elements): J dQ/dx_l = |Ja^l| [ D_l Q + sum_s s (qhat - Q) / w_end on the l-faces ]
+//   (affine elements: only the l-derivative and the l-faces contribute).
+// Pass 3 (faces): F*_out = |Ja^d| [ Roe(Q_L, Q_R) - (f^v(Q_L, G_L) + f^v(Q_R, G_R))/2 ] . e_d on the
+//   mortar (traces of Q and of the 15 gradient components interpolated), projected back.
+// Pass 4: the element pass with total flux f^a - f^v.
+template <typename T, int FN>
+__global__ __launch_bounds__(64) void k_face_avg(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
+                                                 const T *__restrict__ u, T *__restrict__ fq,
+                                                 const T *__restrict__ tab, Geom g, PhysParams ph) {
+    __shared__ FaceSmem<T, FN> sm;
+    face_body<T, FN, 1>(faces[blockIdx.x], el, u, fq, tab, g, ph, sm);
+}
+
+template <typename T, int NPT>
+__global__ __launch_bounds__(WG) void k_elem_grad(const Tile *__restrict__ tiles, int tile0, int ntiles,
+                                                  const ElemInfo *__restrict__ el, const T *__restrict__ u,
+                                                  const T *__restrict__ fq, T *__restrict__ grad,
+                                                  const T *__restrict__ tab, Geom g, int isolated) {
+    __shared__ T sQ[NV][WG * NPT];
+    const int tid = threadIdx.x;
+    const Tile tl = tiles[tile0 + xcd_remap(blockIdx.x, ntiles)];
+    const ElemInfo E0 = el[tl.first];
+    const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
+    const int npe = n1 * n2 * n3, total = tl.count * npe;
+    const int64_t fblk = fblock(E0.n);
+    const int nn[3] = {n1, n2, n3};
+    const int stride[3] = {1, n1, n1 * n2};
+    T q[NPT][NV];
+    int loc[NPT][3], le[NPT], nd[NPT];
+    bool ok[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int t = tid + k * WG;
+        ok[k] = t < total;
+        le[k] = ok[k] ? t / npe : 0;
+        nd[k] = ok[k] ? t - le[k] * npe : 0;
+        loc[k][0] = nd[k] % n1;
+        loc[k][1] = (nd[k] / n1) % n2;
+        loc[k][2] = nd[k] / (n1 * n2);
+        const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            q[k][v] = ok[k] ? u[base + v * npe + nd[k]] : T(0);
+            if (ok[k]) sQ[v][t] = q[k][v];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        if (!ok[k]) continue;
+        const int t = tid + k * WG;
+        T *Gp = grad + (int64_t)3 * NV * (E0.noff + (int64_t)le[k] * npe) + nd[k];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const int id = loc[k][l], nl = nn[l];
+            const T *Drow = tab + T_D + doff(nl - 1) + id * nl;
+            const int tb = t - id * stride[l];
+            T G[NV] = {T(0), T(0), T(0), T(0), T(0)};
+            for (int m = 0; m < nl; ++m) {
+                const T dm = Drow[m];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) G[v] += dm * sQ[v][tb + m * stride[l]];
+            }
+            if (!isolated && (id == 0 || id == nl - 1)) {
+                const int s = id == 0 ? -1 : 1;
+                const int t1 = l == 0 ? 1 : 0, t2 = l == 2 ? 1 : 2;
+                const int na = nn[t1], nb = nn[t2];
+                const T *fs = fq + E0.foff + le[k] * fblk + fslot(E0.n, l, s);
+                const int fm = loc[k][t1] + na * loc[k][t2];
+                const T iw = T(1) / tab[T_W + xoff(nl - 1)];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) G[v] += T(s) * (fs[v * na * nb + fm] - q[k][v]) * iw;
+            }
+            const T sc = (T)(g.Ja[l] / g.J);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Gp[(int64_t)(l * NV + v) * npe] = sc * G[v];
+        }
+    }
+}
+
+template <typename T, int FN>
+__global__ __launch_bounds__(64) void k_face_ns(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
+                                                const T *__restrict__ u, const T *__restrict__ grad,
+                                                T *__restrict__ ff, const T *__restrict__ tab, Geom g,
+                                                PhysParams ph) {
+    constexpr int NF = 4 * NV;  // Q and its three gradient components
+    __shared__ T sL[NF][FN], sR[NF][FN], sF[NV][FN];
+    const Face f = faces[blockIdx.x];
+    const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const T Ja = (T)g.Ja[d], gam = (T)ph.gamma, mu = (T)ph.mu, kappa = (T)ph.kappa;
+    const int lane = threadIdx.x;
+    auto load = [&](const ElemInfo &E, int node, T *x) {
+        const int ne = E.n[0] * E.n[1] * E.n[2];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[v] = u[NV * E.noff + v * ne + node];
+#pragma unroll
+        for (int c = 0; c < 3 * NV; ++c) x[NV + c] = grad[3 * NV * E.noff + (int64_t)c * ne + node];
+    };
+    if (f.bc != 0) {
+        const int e = f.eL >= 0 ? f.eL : f.eR;
+        const int s = f.eL >= 0 ? 1 : -1;
+        const ElemInfo E = el[e];
+        const int na = E.n[t1], nb = E.n[t2];
+        T *out = ff + E.foff + fslot(E.n, d, s);
+        for (int m = lane; m < na * nb; m += 64) {
+            T x[NF], qg[NV], F[NV], fv1[NV], fv2[NV];
+            load(E, face_node(E.n, d, s, m % na, m / na), x);
+            if (f.bc == 1) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) qg[v] = x[v];
+                qg[1 + d] = -x[1 + d];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) qg[v] = (T)ph.qfar[v];
+            }
+            numflux_axis(x, qg, d, (T)s, gam, ph.flux, F);
+            viscous_axis(x, x + NV, d, gam, mu, kappa, fv1);
+            viscous_axis(qg, x + NV, d, gam, mu, kappa, fv2);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v * na * nb + m] = Ja * (F[v] - T(s) * T(0.5) * (fv1[v] + fv2[v]));
+        }
+        return;
+    }
+    const ElemInfo L = el[f.eL], R = el[f.eR];
+    const int aL = L.n[t1], bL = L.n[t2], aR = R.n[t1], bR = R.n[t2];
+    const int K1 = aL > aR ? aL : aR, K2 = bL > bR ? bL : bR;
+    for (int m = lane; m < aL * bL; m += 64) {
+        T x[NF];
+        load(L, face_node(L.n, d, 1, m % aL, m / aL), x);
+#pragma unroll
+        for (int c = 0; c < NF; ++c) sL[c][m] = x[c];
+    }
+    for (int m = lane; m < aR * bR; m += 64) {
+        T x[NF];
+        load(R, face_node(R.n, d, -1, m % aR, m / aR), x);
+#pragma unroll
+        for (int c = 0; c < NF; ++c) sR[c][m] = x[c];
+    }
+    __syncthreads();
+    for (int m = lane; m < K1 * K2; m += 64) {
+        const int A = m % K1, B = m / K1;
+        T x[2][NF], F[NV], fvL[NV], fvR[NV];
+        for (int side = 0; side < 2; ++side) {
+            const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
+            T(*S)[FN] = side == 0 ? sL : sR;
+            if (na == K1 && nb == K2) {
+#pragma unroll
+                for (int c = 0; c < NF; ++c) x[side][c] = S[c][m];
+                continue;
+            }
+            const T *S1 = tab + T_I + moff(K1 - 1, na - 1) + A * na;
+            const T *S2 = tab + T_I + moff(K2 - 1, nb - 1) + B * nb;
+#pragma unroll
+            for (int c = 0; c < NF; ++c) x[side][c] = T(0);
+            for (int b = 0; b < nb; ++b)
+                for (int a = 0; a < na; ++a) {
+                    const T w = S1[a] * S2[b];
+#pragma unroll
+                    for (int c = 0; c < NF; ++c) x[side][c] += w * S[c][a + na * b];
+                }
+        }
+        numflux_axis(x[0], x[1], d, T(1), gam, ph.flux, F);
+        viscous_axis(x[0], x[0] + NV, d, gam, mu, kappa, fvL);
+        viscous_axis(x[1], x[1] + NV, d, gam, mu, kappa, fvR);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sF[v][m] = Ja * (F[v] - T(0.5) * (fvL[v] + fvR[v]));
+    }
+    __syncthreads();
+    for (int side = 0; side < 2; ++side) {
+        const ElemInfo &E = side == 0 ? L : R;
+        const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
+        const T sg = side == 0 ? T(1) : T(-1);
+        T *out = ff + E.foff + fslot(E.n, d, side == 0 ? 1 : -1);
+        const bool conf = na == K1 && nb == K2;
+        const T *P1 = tab + T_P + moff(na - 1, K1 - 1);
+        const T *P2 = tab + T_P + moff(nb - 1, K2 - 1);
+        for (int m = lane; m < na * nb; m += 64) {
+            const int a = m % na, b = m / na;
+            T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
+            if (conf) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) acc[v] = sF[v][m];
+            } else {
+                for (int B = 0; B < K2; ++B)
+                    for (int A = 0; A < K1; ++A) {
+                        const T w = P1[a * K1 + A] * P2[b * K2 + B];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) acc[v] += w * sF[v][A + K1 * B];
+                    }
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v * na * nb + m] = sg * acc[v];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_ns_gradient(const Face *faces, int nfaces, const Tile *tiles, int tile0, int ntiles, int npt,
+                              bool do_faces, const ElemInfo *el, const T *u, T *fq, T *grad, const T *tab, Geom g,
+                              PhysParams ph, int max_order, int isolated, hipStream_t s) {
+    if (do_faces && !isolated && nfaces > 0) {
+        if (max_order <= 7)
+            hipLaunchKernelGGL((k_face_avg<T, 64>), dim3(nfaces), dim3(64), 0, s, faces, el, u, fq, tab, g, ph);
+        else
+            hipLaunchKernelGGL((k_face_avg<T, 100>), dim3(nfaces), dim3(64), 0, s, faces, el, u, fq, tab, g, ph);
+    }
+    if (ntiles == 0) return hipGetLastError();
+    switch (npt) {
+        case 1: hipLaunchKernelGGL((k_elem_grad<T, 1>), dim3(ntiles), dim3(WG), 0, s, tiles, tile0, ntiles, el, u, fq, grad, tab, g, isolated); break;
+        case 2: hipLaunchKernelGGL((k_elem_grad<T, 2>), dim3(ntiles), dim3(WG), 0, s, tiles, tile0, ntiles, el, u, fq, grad, tab, g, isolated); break;
+        case 4: hipLaunchKernelGGL((k_elem_grad<T, 4>), dim3(ntiles), dim3(WG), 0, s, tiles, tile0, ntiles, el, u, fq, grad, tab, g, isolated); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ns_faces(const Face *faces, int nfaces, const ElemInfo *el, const T *u, const T *grad, T *ff,
+                           const T *tab, Geom g, PhysParams ph, hipStream_t s) {
+    if (nfaces == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_face_ns<T, 64>), dim3(nfaces), dim3(64), 0, s, faces, el, u, grad, ff, tab, g, ph);
+    return hipGetLastError();
+}
+
+template hipError_t launch_ns_gradient<double>(const Face *, int, const Tile *, int, int, int, bool, const ElemInfo *,
+                                               const double *, double *, double *, const double *, Geom, PhysParams,
+                                               int, int, hipStream_t);
+template hipError_t launch_ns_gradient<float>(const Face *, int, const Tile *, int, int, int, bool, const ElemInfo *,
+                                              const float *, float *, float *, const float *, Geom, PhysParams, int,
+                                              int, hipStream_t);
+template hipError_t launch_ns_faces<double>(const Face *, int, const ElemInfo *, const double *, const double *,
+                                            double *, const double *, Geom, PhysParams, hipStream_t);
+template hipError_t launch_ns_faces<float>(const Face *, int, const ElemInfo *, const float *, const float *, float *,
+                                           const float *, Geom, PhysParams, hipStream_t);
 
 // ---------------------------------------------------------------------------- batches
 // Persistent forms: a fixed grid walks a cost-sorted work list (static cyclic

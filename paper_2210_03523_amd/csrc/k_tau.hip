@@ -383,26 +383,27 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
         const double *I3 = tab + T_I + moff(m3 - 1, F - 1);
         const double *D3 = tab + T_D + doff(m3 - 1);
         const double *w3 = tab + T_W + xoff(m3 - 1);
-        double Qc[NV][MM], V[NV][MM];
+        double V[NV][MM];
 #pragma unroll
-        for (int c = 0; c < MM; ++c) {
-            if (c >= m3) continue;
+        for (int c = 0; c < MM; ++c)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) V[v][c] = 0.0;
+        // coarse state at node c of the line (z-interpolation with wave-uniform weights)
+        auto node_state = [&](int c, double q[NV]) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 double acc = 0.0;
 #pragma unroll
                 for (int k = 0; k < F; ++k) acc += I3[c * F + k] * XQ[v][k];
-                Qc[v][c] = acc;
-                V[v][c] = 0.0;
+                q[v] = acc;
             }
-        }
+        };
         // z: flux at each node, then D3 along the line (all in registers)
 #pragma unroll
         for (int cp = 0; cp < MM; ++cp) {
             if (cp >= m3) continue;
             double q[NV], fz[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) q[v] = Qc[v][cp];
+            node_state(cp, q);
             flux_axis(q, 2, gm1, fz);
 #pragma unroll
             for (int c = 0; c < MM; ++c) {

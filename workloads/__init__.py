@@ -207,3 +207,45 @@ def c4_state(xyz, orders, seed: int = 4, nmodes: int = 8):
                 vel[c] = vel[c] + 1e-2 * amp[m, c] * np.sin(arg + ph[m, c])
         return conserved(rho, vel[0], vel[1], vel[2], np.ones_like(x))
     return _ragged_apply(xyz, orders, fn)
+
+
+def ns_mesh(mesh, mu: float, Pr: float = 0.72):
+    """A copy of a box mesh description carrying Navier-Stokes parameters."""
+    out = dict(mesh)
+    out["mu"] = float(mu)
+    out["Pr"] = float(Pr)
+    return out
+
+
+def c3(seed: int = 3, n=(32, 32, 2), Re: float = 100.0, Ma: float = 0.2, Pr: float = 0.72):
+    """Navier-Stokes, Re = 100, Ma = 0.2, Pr = 0.72 on [0,1]^2 x [0, 1/16] (32 x 32 x 2 cubes),
+    periodic; per-element orders (Nx, Ny) drawn U{2..6}, Nz = 1.  Nondimensional with
+    rho = 1, |u| = 1, L = 1: mu = 1/Re, p = 1/(gamma Ma^2).  Returns (mesh, orders, rng)."""
+    rng = np.random.default_rng(seed)
+    mesh = ns_mesh(box_mesh(n, hi=(1.0, 1.0, n[2] / n[0])), mu=1.0 / Re, Pr=Pr)
+    E = n[0] * n[1] * n[2]
+    orders = np.ones((E, 3), dtype=np.int32)
+    orders[:, :2] = rng.integers(2, 7, (E, 2))
+    mesh["p_inf"] = 1.0 / (GAMMA * Ma * Ma)
+    return mesh, orders, rng
+
+
+def c3_state(xyz, orders, mesh, rng, nvort: int = 16, r0: float = 0.05, amp: float = 0.1):
+    """Free stream rho = 1, u = (1, 0, 0), p = p_inf plus nvort Gaussian vortices in x-y
+    (centres U([0,1]^2), swirl amp * (r/r0) exp((1 - r^2/r0^2)/2), minimum-image distance)."""
+    centres = rng.random((nvort, 2))
+    p_inf = mesh["p_inf"]
+
+    def fn(x, y, z):
+        u = np.ones_like(x)
+        v = np.zeros_like(x)
+        for cx, cy in centres:
+            dx = (x - cx + 0.5) % 1.0 - 0.5
+            dy = (y - cy + 0.5) % 1.0 - 0.5
+            r2 = dx * dx + dy * dy
+            s = amp / r0 * np.exp(0.5 * (1.0 - r2 / (r0 * r0)))
+            u = u - s * dy
+            v = v + s * dx
+        one = np.ones_like(x)
+        return conserved(one, u, v, 0.0 * x, p_inf * one)
+    return _ragged_apply(xyz, orders, fn)
