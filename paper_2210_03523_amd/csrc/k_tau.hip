@@ -276,6 +276,10 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
     constexpr int MM = C + 1;                   // largest coarse node count
     constexpr int NL = 256;
     constexpr int SLOTS = 2 * C * C * 2;        // [c3][c1 of the pair][c2][form]
+    // row stride of X1: odd in doubles, so the lanes of different x-rows that read
+    // the same (j, k) fall in different LDS banks
+    constexpr int X1S = F * F + 1;
+    static_assert(2 * NV * RMAX * X1S <= 2 * NV * MM * 256, "X1 fits in the staging area");
     extern __shared__ double lds[];
     double *S = lds;                                                     // staging / X1
     unsigned long long *slot = (unsigned long long *)(lds + 2 * NV * MM * NL);
@@ -304,18 +308,18 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
 #pragma unroll
             for (int i = 0; i < F; ++i) row[i] = src[i];
             const int v = rem / (F * F), jk = rem - v * F * F;
-            double *dst = S + ((f * NV + v) * RMAX) * (F * F) + jk;
+            double *dst = S + ((f * NV + v) * RMAX) * X1S + jk;
             for (int a = 0; a < mA; ++a) {
                 double acc = 0.0;
 #pragma unroll
                 for (int i = 0; i < F; ++i) acc += IA[a * F + i] * row[i];
-                dst[a * F * F] = acc;
+                dst[a * X1S] = acc;
             }
             for (int a = 0; a < mB; ++a) {
                 double acc = 0.0;
 #pragma unroll
                 for (int i = 0; i < F; ++i) acc += IB[a * F + i] * row[i];
-                dst[(mA + a) * F * F] = acc;
+                dst[(mA + a) * X1S] = acc;
             }
         }
     }
@@ -360,7 +364,7 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
     for (int f = 0; f < 2; ++f) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double *x1 = S + ((f * NV + v) * RMAX + a) * (F * F);
+            const double *x1 = S + ((f * NV + v) * RMAX + a) * X1S;
 #pragma unroll
             for (int k = 0; k < F; ++k) {
                 double acc = 0.0;
