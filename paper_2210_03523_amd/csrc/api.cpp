@@ -104,8 +104,6 @@ struct dg_plan_s {
     int32_t *d_fine_of = nullptr;
     double *d_uc = nullptr, *d_rdc = nullptr, *d_psic = nullptr;
     bool ns = false;              // Navier-Stokes plan
-    bool conforming = false;      // every interior face has equal tangential orders on both sides
-    int32_t *d_nbr = nullptr;     // [E][6] neighbour plan index per face (d, side), -1 wall, -2 far field
     void *d_grad = nullptr;       // BR1 gradients [elem][3][5][node], sized for doubles
     // x-force functional: boundary faces on slip walls normal to x, and their partial sums
     int32_t *d_wallx = nullptr;
@@ -138,8 +136,7 @@ void destroy_plan(dg_plan p) {
     for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     void *bufs[] = {p->d_el, p->d_faces, p->d_tiles, p->d_ff, p->d_dudt, p->d_fine_of, p->d_uc, p->d_rdc,
-                    p->d_psic, p->d_combo_off, p->d_tasks, p->d_iso, p->d_wallx, p->d_part, p->d_grad,
-                    p->d_nbr};
+                    p->d_psic, p->d_combo_off, p->d_tasks, p->d_iso, p->d_wallx, p->d_part, p->d_grad};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -253,17 +250,6 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
     for (int f = 0; f < p->nfaces; ++f)
         if (faces[f].bc == DG_BC_SLIP_WALL && faces[f].d == 0) wallx.push_back(f);
     p->nwallx = (int)wallx.size();
-    // neighbour table and the conforming test (tangential orders equal across every face)
-    std::vector<int32_t> nbr(6 * (size_t)E, 0);
-    p->conforming = true;
-    for (const Face &f : faces) {
-        const int t1 = f.d == 0 ? 1 : 0, t2 = f.d == 2 ? 1 : 2;
-        if (f.eL >= 0) nbr[6 * f.eL + 2 * f.d + 1] = f.eR >= 0 ? f.eR : -f.bc;
-        if (f.eR >= 0) nbr[6 * f.eR + 2 * f.d] = f.eL >= 0 ? f.eL : -f.bc;
-        if (f.eL >= 0 && f.eR >= 0 &&
-            (el[f.eL].n[t1] != el[f.eR].n[t1] || el[f.eL].n[t2] != el[f.eR].n[t2]))
-            p->conforming = false;
-    }
 
     // geometry and physics
     double h[3];
@@ -320,7 +306,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
 
     if ((st = upload(&p->d_el, el)) || (st = upload(&p->d_faces, faces)) || (st = upload(&p->d_tiles, tiles)) ||
         (st = upload(&p->d_combo_off, p->combo_off)) || (st = upload(&p->d_tasks, tasks)) ||
-        (st = upload(&p->d_iso, iso_all)) || (st = upload(&p->d_wallx, wallx)) || (st = upload(&p->d_nbr, nbr))) {
+        (st = upload(&p->d_iso, iso_all)) || (st = upload(&p->d_wallx, wallx))) {
         destroy_plan(p);
         return st;
     }
@@ -359,14 +345,9 @@ dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s) {
                                       p->geom, p->phys, epi, s));
         return DG_OK;
     }
-    if (p->conforming && !epi.isolated && epi.mode != EPI_RK) {
-        // faces formed inside the element pass; not for RK stages, which update the
-        // state in place while neighbouring workgroups would still read its traces
-        epi.nbr = p->d_nbr;
-    } else if (!epi.isolated) {
+    if (!epi.isolated)
         HIP_TRY(launch_face_flux<T>(p->d_faces, p->nfaces, p->d_el, u, (T *)p->d_ff, tab, p->geom, p->phys,
                                     p->max_order, s));
-    }
     for (const TileClass &c : p->classes)
         HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)p->d_ff, tab, p->geom,
                                   p->phys, epi, s));

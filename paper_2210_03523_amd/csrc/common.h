@@ -101,7 +101,6 @@ struct EpiArgs {
     double *eta;        // [E] sum of psic * tau_trad (tau, optional)
     const void *grad;   // Navier-Stokes: BR1 gradients [elem][3][5][node] (null for Euler)
     double mu, kappa;   // viscosity and heat conductivity
-    const int32_t *nbr; // fused conforming faces: [elem][6] neighbour plan index, -1 wall, -2 far field
 };
 
 template <typename T>

@@ -270,11 +270,7 @@ hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems
 // ---------------------------------------------------------------------------- elements
 // One tile of elements, processed by one workgroup of WG lanes.
 // u is not __restrict__: the RK epilogue writes the stage update in place.
-// FUSED: every face of the mesh is conforming (equal tangential orders on both sides);
-// the outward flux is then formed here, at the face node, from the own state and the
-// neighbour's matching node (epi.nbr), with the same flux call and argument order as the
-// face pass -- no face pass and no face-flux buffer.
-template <typename T, int NPT, bool FUSED = false>
+template <typename T, int NPT>
 __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restrict__ el, const T *u,
                                           const T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
                                           const PhysParams &ph, const EpiArgs &epi, T (&sF)[NV][WG * NPT]) {
@@ -353,7 +349,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
         }
         __syncthreads();
     }
-    // lifted surface terms
+    // lifted surface terms from the face pass
     if (!epi.isolated) {
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
@@ -367,50 +363,14 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
                 const int s = id == 0 ? -1 : 1;
                 const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
                 const int na = nn[t1], nb = nn[t2];
+                const int fm = loc[k][t1] + na * loc[k][t2];
+                const T *fs = fb + fslot(E0.n, d, s);
                 const T iw = T(1) / tab[T_W + xoff(nd_ - 1)];
                 const T Ja = (T)g.Ja[d];
-                T fo[NV];
-                if (FUSED) {
-                    const int nbi = epi.nbr[6 * (tl.first + le[k]) + 2 * d + (s > 0 ? 1 : 0)];
-                    T F[NV];
-                    if (nbi >= 0) {
-                        const ElemInfo En = el[nbi];
-                        int idx[3] = {loc[k][0], loc[k][1], loc[k][2]};
-                        idx[d] = s > 0 ? 0 : En.n[d] - 1;
-                        const int nnode = idx[0] + En.n[0] * (idx[1] + En.n[1] * idx[2]);
-                        const int nne = En.n[0] * En.n[1] * En.n[2];
-                        T qn[NV];
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) qn[v] = u[NV * En.noff + v * nne + nnode];
-                        if (s > 0) numflux_axis(q[k], qn, d, T(1), gam, ph.flux, F);
-                        else numflux_axis(qn, q[k], d, T(1), gam, ph.flux, F);
-                        const T sJa = s > 0 ? Ja : -Ja;
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) fo[v] = sJa * F[v];
-                    } else {
-                        T qg[NV];
-                        if (nbi == -1) {  // slip wall
-#pragma unroll
-                            for (int v = 0; v < NV; ++v) qg[v] = q[k][v];
-                            qg[1 + d] = -q[k][1 + d];
-                        } else {  // far field
-#pragma unroll
-                            for (int v = 0; v < NV; ++v) qg[v] = (T)ph.qfar[v];
-                        }
-                        numflux_axis(q[k], qg, d, (T)s, gam, ph.flux, F);
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) fo[v] = Ja * F[v];
-                    }
-                } else {
-                    const int fm = loc[k][t1] + na * loc[k][t2];
-                    const T *fs = fb + fslot(E0.n, d, s);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) fo[v] = fs[v * na * nb + fm];
-                }
                 T f[NV];
                 total_flux(k, d, f);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) V[k][v] += (fo[v] - T(s) * Ja * f[v]) * iw;
+                for (int v = 0; v < NV; ++v) V[k][v] += (fs[v * na * nb + fm] - T(s) * Ja * f[v]) * iw;
             }
         }
     }
@@ -511,13 +471,13 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
     }
 }
 
-template <typename T, int NPT, bool FUSED>
+template <typename T, int NPT>
 __global__ __launch_bounds__(WG) void k_elem(const Tile *__restrict__ tiles, int tile0, int ntiles,
                                              const ElemInfo *__restrict__ el, const T *u,
                                              const T *__restrict__ ff, const T *__restrict__ tab, Geom g,
                                              PhysParams ph, EpiArgs epi) {
     __shared__ T sF[NV][WG * NPT];
-    elem_body<T, NPT, FUSED>(tiles[tile0 + xcd_remap(blockIdx.x, ntiles)], el, u, ff, tab, g, ph, epi, sF);
+    elem_body<T, NPT>(tiles[tile0 + xcd_remap(blockIdx.x, ntiles)], el, u, ff, tab, g, ph, epi, sF);
 }
 
 template <typename T>
@@ -525,19 +485,12 @@ hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, con
                           const T *fflux, const T *tab, Geom g, PhysParams ph, EpiArgs epi, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
     dim3 grid(ntiles), block(WG);
-    const bool fused = epi.nbr != nullptr;
-#define DGT_ELEM(NP, FU) \
-    hipLaunchKernelGGL((k_elem<T, NP, FU>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi)
-    switch (npt * 2 + (fused ? 1 : 0)) {
-        case 2: DGT_ELEM(1, false); break;
-        case 3: DGT_ELEM(1, true); break;
-        case 4: DGT_ELEM(2, false); break;
-        case 5: DGT_ELEM(2, true); break;
-        case 8: DGT_ELEM(4, false); break;
-        case 9: DGT_ELEM(4, true); break;
+    switch (npt) {
+        case 1: hipLaunchKernelGGL((k_elem<T, 1>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi); break;
+        case 2: hipLaunchKernelGGL((k_elem<T, 2>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi); break;
+        case 4: hipLaunchKernelGGL((k_elem<T, 4>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi); break;
         default: return hipErrorInvalidValue;
     }
-#undef DGT_ELEM
     return hipGetLastError();
 }
 

@@ -90,23 +90,6 @@ def test_residual_fp32(shape, orng, seed, bc, flux, box):
     assert err(got.astype(np.float64), ref, residual_scale(mesh, orders, u)) < TOL32
 
 
-def test_fused_conforming_path_matches_face_pass():
-    """A mesh whose faces are all conforming (orders differ only in the normal
-    direction across each face) takes the fused element pass; its residual equals the
-    face-pass result of the RK3 stage path bitwise (same flux calls, same order)."""
-    rng = np.random.default_rng(12)
-    mesh = wl.box_mesh((3, 2, 2), bc=(1, 2, 0, 0, 0, 0), qfar=(1.1, 0.3, -0.1, 0.2, 2.4))
-    # x-order varies along x only, y-order along y only, z-order along z only
-    N = [rng.integers(1, 8, n) for n in (3, 2, 2)]
-    orders = np.array([[N[0][e % 3], N[1][(e // 3) % 2], N[2][e // 6]] for e in range(12)], dtype=np.int32)
-    u = wl.random_state(orders, rng)
-    plan = dg.Plan(mesh, orders)
-    ref = oracle.residual(mesh, orders, u)
-    got = plan.to_natural(dg.residual(plan, plan.to_plan(u)))
-    s = residual_scale(mesh, orders, u)
-    assert err(got, ref, s) < TOL64
-
-
 def test_residual_deterministic():
     mesh, orders, u, _ = _case((3, 3, 3), 1, 7, 11)
     plan = dg.Plan(mesh, orders)
