@@ -38,7 +38,9 @@ class _Mesh(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("bc", ctypes.c_int * 6), ("flux", ctypes.c_int),
-                ("gamma", ctypes.c_double), ("qfar", ctypes.c_double * 5)]
+                ("gamma", ctypes.c_double), ("qfar", ctypes.c_double * 5),
+                ("map_kind", ctypes.c_int), ("map_amp", ctypes.c_double),
+                ("geo_order", ctypes.c_int * 3)]
 
 
 _lib = None
@@ -58,6 +60,9 @@ def _load():
             "orc_interp": [ctypes.c_int, ctypes.c_int, _D],
             "orc_proj": [ctypes.c_int, ctypes.c_int, _D],
             "orc_node_coords": [ctypes.POINTER(_Mesh), _I, _D],
+            "orc_metrics": [ctypes.POINTER(_Mesh), _I, _D],
+            "orc_sweep_ns": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_double, ctypes.c_double, _I,
+                             ctypes.c_int, _D, _D],
             "orc_residual": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_int, ctypes.c_int],
             "orc_restrict": [ctypes.c_int, _I, _I, _D, _D],
             "orc_tau": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, _D, _D, _D, _D],
@@ -115,6 +120,10 @@ def _mesh(m: dict) -> _Mesh:
     s.gamma = float(m["gamma"])
     for v in range(5):
         s.qfar[v] = float(m["qfar"][v])
+    kind, amp, geo = m.get("map", (0, 0.0, (1, 1, 1)))
+    s.map_kind, s.map_amp = int(kind), float(amp)
+    for d in range(3):
+        s.geo_order[d] = int(geo[d])
     return s
 
 
@@ -186,6 +195,16 @@ def node_coords(mesh: dict, orders):
     return xyz
 
 
+def metrics(mesh: dict, orders):
+    """Metric terms per node, natural ragged layout [e][10][node]: Ja^1, Ja^2, Ja^3
+    (x, y, z components each), then J."""
+    o = _i32(orders)
+    met = np.zeros(10 * num_nodes(o))
+    m = _mesh(mesh)
+    _check(_load().orc_metrics(ctypes.byref(m), _i(o), _d(met)), "metrics")
+    return met
+
+
 def residual(mesh: dict, orders, u, form: int = 0, isolated: bool = False):
     """form 0: new form r = M^-1 F^N(u) (= -du/dt); form 1: traditional F^N(u)."""
     o, u = _i32(orders), _f64(u)
@@ -237,6 +256,22 @@ def sweep(mesh: dict, orders, u, dudt, elems=None):
     m = _mesh(mesh)
     _check(_load().orc_sweep(ctypes.byref(m), _i(o), _d(u), _d(dudt), _i(el), len(el), _d(ten), _d(tet)),
            "sweep")
+    return ten, tet, offs
+
+
+def sweep_ns(mesh: dict, orders, u, dudt, mu: float, Pr: float = 0.72, elems=None):
+    """Isolated sweep of the Navier-Stokes residual; same outputs as sweep()."""
+    o, u, dudt = _i32(orders), _f64(u), _f64(dudt)
+    E = o.size // 3
+    el = _i32(np.arange(E) if elems is None else elems)
+    o3 = o.reshape(-1, 3)
+    counts = [num_combos(o3[e]) for e in el]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    ten = np.zeros(int(offs[-1]))
+    tet = np.zeros(int(offs[-1]))
+    m = _mesh(mesh)
+    _check(_load().orc_sweep_ns(ctypes.byref(m), _i(o), _d(u), _d(dudt), float(mu), float(Pr), _i(el), len(el),
+                                _d(ten), _d(tet)), "sweep_ns")
     return ten, tet, offs
 
 

@@ -21,8 +21,10 @@
  * Faces whose tangential orders differ are coupled on a mortar of order
  * K = max per tangential direction: both traces are interpolated onto the
  * mortar, the Riemann flux is evaluated once there (left = element on the
- * minus side, normal +e_d), and each side takes the L2 projection back onto
- * its own face nodes (the right side with a minus sign).
+ * minus side; scaled normal = its Ja^d interpolated onto the mortar, e_d |Ja^d|
+ * on box elements), and each side takes the L2 projection back onto its own
+ * face nodes (the right side with a minus sign).  Curved elements carry their
+ * metric terms per node (see elem_metrics).
  */
 #include "dg_oracle.h"
 
@@ -321,6 +323,16 @@ static int check_orders(int E, const int *orders)
     return 0;
 }
 
+static int check_mesh(const orc_mesh *m)
+{
+    if (m->nx < 1 || m->ny < 1 || m->nz < 1) return -1;
+    if (m->map_kind == 0) return 0;
+    if (m->map_kind != 1) return -1;
+    for (int d = 0; d < 3; ++d)
+        if (m->geo_order[d] < 1 || m->geo_order[d] > ORC_NMAX) return -1;
+    return 0;
+}
+
 static void elem_ijk(const orc_mesh *m, int e, int *c)
 {
     c[0] = e % m->nx;
@@ -341,28 +353,149 @@ static void geometry(const orc_mesh *m, double *h, double *J, double *Ja)
     Ja[2] = h[0] * h[1] / 4.0;
 }
 
-int orc_node_coords(const orc_mesh *m, const int *orders, double *xyz)
+/* The curvilinear map (map_kind 1): (x, y, z) -> (x + f, y + f, z). */
+static void map_point(const orc_mesh *m, const double *xb, double *X)
 {
-    int E = m->nx * m->ny * m->nz;
-    if (check_orders(E, orders)) return -1;
-    ensure_tables();
+    const double twopi = 6.28318530717958647692528676655900577;
+    double f = m->map_amp * sin(twopi * (xb[0] - m->lo[0]) / (m->hi[0] - m->lo[0])) *
+               sin(twopi * (xb[1] - m->lo[1]) / (m->hi[1] - m->lo[1]));
+    X[0] = xb[0] + f;
+    X[1] = xb[1] + f;
+    X[2] = xb[2];
+}
+
+/* Node coordinates of element e at orders o: X[d*ne + node].  Box elements: the
+ * affine map of the reference cube.  Curved elements: the map sampled at the
+ * Gauss-Lobatto nodes of the geometry order, interpolated to the element's nodes. */
+static void elem_coords(const orc_mesh *m, const int *o, int e, double *X)
+{
     double h[3], J, Ja[3];
     geometry(m, h, &J, Ja);
-    long *off = node_offsets(E, orders);
-    for (int e = 0; e < E; ++e) {
-        const int *o = orders + 3 * e;
-        int n1 = o[0] + 1, n2 = o[1] + 1, n3 = o[2] + 1, ne = n1 * n2 * n3;
-        int c[3];
-        elem_ijk(m, e, c);
-        double *X = xyz + 3 * off[e];
-        for (int k = 0; k < n3; ++k)
-            for (int j = 0; j < n2; ++j)
-                for (int i = 0; i < n1; ++i) {
-                    int node = i + n1 * (j + n2 * k);
+    int c[3];
+    elem_ijk(m, e, c);
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+    if (m->map_kind == 0) {
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i) {
+                    int node = i + n[0] * (j + n[1] * k);
                     int idx[3] = {i, j, k};
                     for (int d = 0; d < 3; ++d)
                         X[d * ne + node] = m->lo[d] + h[d] * (c[d] + 0.5 * (g_x[o[d]][idx[d]] + 1.0));
                 }
+        return;
+    }
+    const int *G = m->geo_order;
+    int g[3] = {G[0] + 1, G[1] + 1, G[2] + 1}, ng = g[0] * g[1] * g[2];
+    double *P = malloc(sizeof(double) * 3 * ng);
+    for (int kc = 0; kc < g[2]; ++kc)
+        for (int kb = 0; kb < g[1]; ++kb)
+            for (int ka = 0; ka < g[0]; ++ka) {
+                int gi[3] = {ka, kb, kc};
+                double xb[3], Xm[3];
+                for (int d = 0; d < 3; ++d) xb[d] = m->lo[d] + h[d] * (c[d] + 0.5 * (g_x[G[d]][gi[d]] + 1.0));
+                map_point(m, xb, Xm);
+                for (int d = 0; d < 3; ++d) P[d * ng + ka + g[0] * (kb + g[1] * kc)] = Xm[d];
+            }
+    double I1[(ORC_NMAX + 1) * (ORC_NMAX + 1)], I2[(ORC_NMAX + 1) * (ORC_NMAX + 1)],
+        I3[(ORC_NMAX + 1) * (ORC_NMAX + 1)];
+    orc_interp(o[0], G[0], I1);
+    orc_interp(o[1], G[1], I2);
+    orc_interp(o[2], G[2], I3);
+    for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i) {
+                    double acc = 0.0;
+                    for (int kc = 0; kc < g[2]; ++kc)
+                        for (int kb = 0; kb < g[1]; ++kb)
+                            for (int ka = 0; ka < g[0]; ++ka)
+                                acc += I1[i * g[0] + ka] * I2[j * g[1] + kb] * I3[k * g[2] + kc] *
+                                       P[d * ng + ka + g[0] * (kb + g[1] * kc)];
+                    X[d * ne + i + n[0] * (j + n[1] * k)] = acc;
+                }
+    free(P);
+}
+
+/* Metric terms from node coordinates: covariant vectors a_i = D_i X (collocation
+ * derivative along reference direction i), contravariant Ja^1 = a_2 x a_3,
+ * Ja^2 = a_3 x a_1, Ja^3 = a_1 x a_2, Jacobian J = a_1 . (a_2 x a_3).
+ * Ja[(d*3 + l)*ne + node] = (Ja^d)_l.  For maps whose third coordinate is an affine
+ * function of the third reference coordinate alone (the box and the sine map), this
+ * cross-product form satisfies the discrete metric identities sum_d D_d (Ja^d)_l = 0
+ * up to rounding, which free-stream preservation needs. */
+static void metrics_from_coords(const int *o, const double *X, double *Ja, double *J)
+{
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int idx[3] = {i, j, k};
+                int node = i + n[0] * (j + n[1] * k);
+                double a[3][3];
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) {
+                        double acc = 0.0;
+                        for (int q = 0; q < n[r]; ++q) {
+                            int id2[3] = {i, j, k};
+                            id2[r] = q;
+                            acc += g_D[o[r]][idx[r] * n[r] + q] * X[c * ne + id2[0] + n[0] * (id2[1] + n[1] * id2[2])];
+                        }
+                        a[r][c] = acc;
+                    }
+                for (int d = 0; d < 3; ++d) {
+                    const double *p = a[(d + 1) % 3], *q = a[(d + 2) % 3];
+                    Ja[(d * 3 + 0) * ne + node] = p[1] * q[2] - p[2] * q[1];
+                    Ja[(d * 3 + 1) * ne + node] = p[2] * q[0] - p[0] * q[2];
+                    Ja[(d * 3 + 2) * ne + node] = p[0] * q[1] - p[1] * q[0];
+                }
+                J[node] = a[0][0] * Ja[0 * ne + node] + a[0][1] * Ja[1 * ne + node] + a[0][2] * Ja[2 * ne + node];
+            }
+}
+
+/* Metric terms of element e at orders o (box elements: the closed forms). */
+static void elem_metrics(const orc_mesh *m, const int *o, int e, double *Ja, double *J)
+{
+    int ne = nnodes(o);
+    if (m->map_kind == 0) {
+        double h[3], Jm, Jd[3];
+        geometry(m, h, &Jm, Jd);
+        for (int x = 0; x < ne; ++x) {
+            J[x] = Jm;
+            for (int d = 0; d < 3; ++d)
+                for (int l = 0; l < 3; ++l) Ja[(d * 3 + l) * ne + x] = (l == d) ? Jd[d] : 0.0;
+        }
+        return;
+    }
+    double *X = malloc(sizeof(double) * 3 * ne);
+    elem_coords(m, o, e, X);
+    metrics_from_coords(o, X, Ja, J);
+    free(X);
+}
+
+int orc_node_coords(const orc_mesh *m, const int *orders, double *xyz)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (check_mesh(m) || check_orders(E, orders)) return -1;
+    ensure_tables();
+    long *off = node_offsets(E, orders);
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e) elem_coords(m, orders + 3 * e, e, xyz + 3 * off[e]);
+    free(off);
+    return 0;
+}
+
+int orc_metrics(const orc_mesh *m, const int *orders, double *met)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (check_mesh(m) || check_orders(E, orders)) return -1;
+    ensure_tables();
+    long *off = node_offsets(E, orders);
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e) {
+        int ne = nnodes(orders + 3 * e);
+        double *M = met + 10 * off[e];
+        elem_metrics(m, orders + 3 * e, e, M, M + 9 * ne);
     }
     free(off);
     return 0;
@@ -377,220 +510,6 @@ static int face_node(const int *n, int d, int side, int a, int b)
     idx[t1] = a;
     idx[t2] = b;
     return idx[0] + n[0] * (idx[1] + n[1] * idx[2]);
-}
-
-/* Outward numerical flux F*_out at the own face nodes of face (d, s) of element e:
- * fout[v*(na*nb) + a + na*b]. */
-static void face_flux(const orc_mesh *m, const int *orders, const long *off, const double *u,
-                      int e, int d, int s, const double *Ja, double *fout)
-{
-    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-    const int *o = orders + 3 * e;
-    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
-    int na = n[t1], nb = n[t2];
-    int ne = n[0] * n[1] * n[2];
-    const double *Qe = u + NV * off[e];
-    double g = m->gamma;
-
-    int c[3], nd[3] = {m->nx, m->ny, m->nz};
-    elem_ijk(m, e, c);
-    c[d] += s;
-    int bc = 0;
-    if (c[d] < 0 || c[d] >= nd[d]) {
-        bc = m->bc[2 * d + (s > 0 ? 1 : 0)];
-        c[d] = (c[d] + nd[d]) % nd[d];
-    }
-
-    if (bc != 0) {
-        double nout[3] = {0, 0, 0};
-        nout[d] = (double)s;
-        for (int b = 0; b < nb; ++b)
-            for (int a = 0; a < na; ++a) {
-                int node = face_node(n, d, s, a, b);
-                double qin[NV], qg[NV], f[NV];
-                for (int v = 0; v < NV; ++v) qin[v] = Qe[v * ne + node];
-                if (bc == 1) {
-                    double mn = qin[1] * nout[0] + qin[2] * nout[1] + qin[3] * nout[2];
-                    qg[0] = qin[0];
-                    for (int k = 0; k < 3; ++k) qg[1 + k] = qin[1 + k] - 2.0 * mn * nout[k];
-                    qg[4] = qin[4];
-                } else {
-                    for (int v = 0; v < NV; ++v) qg[v] = m->qfar[v];
-                }
-                orc_numflux(qin, qg, nout, g, m->flux, f);
-                for (int v = 0; v < NV; ++v) fout[v * na * nb + a + na * b] = Ja[d] * f[v];
-            }
-        return;
-    }
-
-    int nbr = elem_index(m, c);
-    const int *on = orders + 3 * nbr;
-    int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1};
-    int nne = nn[0] * nn[1] * nn[2];
-    const double *Qn = u + NV * off[nbr];
-
-    /* left = element on the minus side of the face, right = plus side */
-    const int *nL = s > 0 ? n : nn;
-    const int *nR = s > 0 ? nn : n;
-    const double *QL = s > 0 ? Qe : Qn;
-    const double *QR = s > 0 ? Qn : Qe;
-    int neL = s > 0 ? ne : nne, neR = s > 0 ? nne : ne;
-    int aL = nL[t1], bL = nL[t2], aR = nR[t1], bR = nR[t2];
-    int K1 = aL > aR ? aL : aR, K2 = bL > bR ? bL : bR;
-
-    double *S1L = malloc(sizeof(double) * K1 * aL), *S2L = malloc(sizeof(double) * K2 * bL);
-    double *S1R = malloc(sizeof(double) * K1 * aR), *S2R = malloc(sizeof(double) * K2 * bR);
-    orc_interp(K1 - 1, aL - 1, S1L);
-    orc_interp(K2 - 1, bL - 1, S2L);
-    orc_interp(K1 - 1, aR - 1, S1R);
-    orc_interp(K2 - 1, bR - 1, S2R);
-    double *FK = malloc(sizeof(double) * NV * K1 * K2);
-    double nplus[3] = {0, 0, 0};
-    nplus[d] = 1.0;
-
-    for (int B = 0; B < K2; ++B)
-        for (int A = 0; A < K1; ++A) {
-            double qL[NV] = {0, 0, 0, 0, 0}, qR[NV] = {0, 0, 0, 0, 0}, f[NV];
-            for (int b = 0; b < bL; ++b)
-                for (int a = 0; a < aL; ++a) {
-                    double wgt = S1L[A * aL + a] * S2L[B * bL + b];
-                    int node = face_node(nL, d, +1, a, b);
-                    for (int v = 0; v < NV; ++v) qL[v] += wgt * QL[v * neL + node];
-                }
-            for (int b = 0; b < bR; ++b)
-                for (int a = 0; a < aR; ++a) {
-                    double wgt = S1R[A * aR + a] * S2R[B * bR + b];
-                    int node = face_node(nR, d, -1, a, b);
-                    for (int v = 0; v < NV; ++v) qR[v] += wgt * QR[v * neR + node];
-                }
-            orc_numflux(qL, qR, nplus, g, m->flux, f);
-            for (int v = 0; v < NV; ++v) FK[v * K1 * K2 + A + K1 * B] = Ja[d] * f[v];
-        }
-
-    /* project back onto the own face (L2 projection), outward sign */
-    double *P1 = malloc(sizeof(double) * na * K1), *P2 = malloc(sizeof(double) * nb * K2);
-    orc_proj(na - 1, K1 - 1, P1);
-    orc_proj(nb - 1, K2 - 1, P2);
-    for (int b = 0; b < nb; ++b)
-        for (int a = 0; a < na; ++a)
-            for (int v = 0; v < NV; ++v) {
-                double acc = 0.0;
-                for (int B = 0; B < K2; ++B)
-                    for (int A = 0; A < K1; ++A)
-                        acc += P1[a * K1 + A] * P2[b * K2 + B] * FK[v * K1 * K2 + A + K1 * B];
-                fout[v * na * nb + a + na * b] = (double)s * acc;
-            }
-    free(S1L); free(S2L); free(S1R); free(S2R); free(FK); free(P1); free(P2);
-}
-
-/* Residual of one element: r (= (V+SAT)/J for form 0, w_i w_j w_k (V+SAT) for form 1). */
-static void element_residual(const orc_mesh *m, const int *orders, const long *off,
-                             const double *u, int e, int form, int isolated, double *r)
-{
-    const int *o = orders + 3 * e;
-    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
-    int ne = n[0] * n[1] * n[2];
-    const double *Q = u + NV * off[e];
-    double h[3], J, Ja[3];
-    geometry(m, h, &J, Ja);
-
-    double *Ft = malloc(sizeof(double) * 3 * NV * ne);  /* [d][v][node] */
-    double *V = calloc((size_t)NV * ne, sizeof(double)); /* [v][node] */
-    for (int node = 0; node < ne; ++node) {
-        double q[NV], f[NV];
-        for (int v = 0; v < NV; ++v) q[v] = Q[v * ne + node];
-        for (int d = 0; d < 3; ++d) {
-            double nd[3] = {0, 0, 0};
-            nd[d] = 1.0;
-            orc_flux_n(q, nd, m->gamma, f);
-            for (int v = 0; v < NV; ++v) Ft[(d * NV + v) * ne + node] = Ja[d] * f[v];
-        }
-    }
-    /* volume term: sum_d D^{N_d} applied along direction d */
-    for (int k = 0; k < n[2]; ++k)
-        for (int j = 0; j < n[1]; ++j)
-            for (int i = 0; i < n[0]; ++i) {
-                int node = i + n[0] * (j + n[1] * k);
-                for (int v = 0; v < NV; ++v) {
-                    double acc = 0.0;
-                    for (int q = 0; q < n[0]; ++q)
-                        acc += g_D[o[0]][i * n[0] + q] * Ft[(0 * NV + v) * ne + q + n[0] * (j + n[1] * k)];
-                    for (int q = 0; q < n[1]; ++q)
-                        acc += g_D[o[1]][j * n[1] + q] * Ft[(1 * NV + v) * ne + i + n[0] * (q + n[1] * k)];
-                    for (int q = 0; q < n[2]; ++q)
-                        acc += g_D[o[2]][k * n[2] + q] * Ft[(2 * NV + v) * ne + i + n[0] * (j + n[1] * q)];
-                    V[v * ne + node] = acc;
-                }
-            }
-    /* surface terms */
-    if (!isolated) {
-        for (int d = 0; d < 3; ++d) {
-            int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-            int na = n[t1], nb = n[t2];
-            double wend = g_w[o[d]][0];
-            double *fout = malloc(sizeof(double) * NV * na * nb);
-            for (int s = -1; s <= 1; s += 2) {
-                face_flux(m, orders, off, u, e, d, s, Ja, fout);
-                for (int b = 0; b < nb; ++b)
-                    for (int a = 0; a < na; ++a) {
-                        int node = face_node(n, d, s, a, b);
-                        for (int v = 0; v < NV; ++v)
-                            V[v * ne + node] += (fout[v * na * nb + a + na * b] -
-                                                 (double)s * Ft[(d * NV + v) * ne + node]) / wend;
-                    }
-            }
-            free(fout);
-        }
-    }
-    for (int k = 0; k < n[2]; ++k)
-        for (int j = 0; j < n[1]; ++j)
-            for (int i = 0; i < n[0]; ++i) {
-                int node = i + n[0] * (j + n[1] * k);
-                double www = g_w[o[0]][i] * g_w[o[1]][j] * g_w[o[2]][k];
-                for (int v = 0; v < NV; ++v)
-                    r[v * ne + node] = form == 0 ? V[v * ne + node] / J : www * V[v * ne + node];
-            }
-    free(Ft);
-    free(V);
-}
-
-int orc_residual(const orc_mesh *m, const int *orders, const double *u, double *r, int form,
-                 int isolated)
-{
-    int E = m->nx * m->ny * m->nz;
-    if (E <= 0 || check_orders(E, orders) || (form != 0 && form != 1)) return -1;
-    ensure_tables();
-    long *off = node_offsets(E, orders);
-#pragma omp parallel for schedule(guided)
-    for (int e = 0; e < E; ++e)
-        element_residual(m, orders, off, u, e, form, isolated, r + NV * off[e]);
-    free(off);
-    return 0;
-}
-
-/* ------------------------------------------------------------------------ */
-/* Navier-Stokes: BR1 gradients and viscous fluxes.                           */
-
-void orc_viscous_flux(const double *q, const double *G, int d, double g, double mu, double Pr, double *f)
-{
-    double rho = q[0], u[3] = {q[1] / q[0], q[2] / q[0], q[3] / q[0]};
-    double p = pressure(q, g), T = p / rho;
-    double du[3][3]; /* du[k][l] = d u_k / d x_l */
-    double dT[3];
-    for (int l = 0; l < 3; ++l) {
-        const double *Gl = G + 5 * l;
-        for (int k = 0; k < 3; ++k) du[k][l] = (Gl[1 + k] - u[k] * Gl[0]) / rho;
-        double dp = (g - 1.0) * (Gl[4] - (u[0] * Gl[1] + u[1] * Gl[2] + u[2] * Gl[3]) +
-                                 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * Gl[0]);
-        dT[l] = (dp - T * Gl[0]) / rho;
-    }
-    double div = du[0][0] + du[1][1] + du[2][2];
-    double tau[3]; /* tau[k] = tau_{k d} */
-    for (int k = 0; k < 3; ++k) tau[k] = mu * (du[k][d] + du[d][k]) - (k == d ? 2.0 / 3.0 * mu * div : 0.0);
-    double kappa = mu * g / ((g - 1.0) * Pr);
-    f[0] = 0.0;
-    for (int k = 0; k < 3; ++k) f[1 + k] = tau[k];
-    f[4] = u[0] * tau[0] + u[1] * tau[1] + u[2] * tau[2] + kappa * dT[d];
 }
 
 /* Neighbour of element e across face (d, s): returns its index, or -1 with *bc set. */
@@ -608,12 +527,15 @@ static int neighbour(const orc_mesh *m, int e, int d, int s, int *bc)
     return elem_index(m, c);
 }
 
-static void ghost_state(const orc_mesh *m, int bc, int d, int s, const double *qin, double *qg)
+/* Ghost state of a boundary face with unit outward normal nout: slip wall (the
+ * normal momentum mirrored) or far field (the free stream). */
+static void ghost_state(const orc_mesh *m, int bc, const double *nout, const double *qin, double *qg)
 {
     if (bc == 1) {
-        for (int v = 0; v < NV; ++v) qg[v] = qin[v];
-        qg[1 + d] = -qin[1 + d] * 1.0;
-        (void)s;
+        double mn = qin[1] * nout[0] + qin[2] * nout[1] + qin[3] * nout[2];
+        qg[0] = qin[0];
+        for (int k = 0; k < 3; ++k) qg[1 + k] = qin[1 + k] - 2.0 * mn * nout[k];
+        qg[4] = qin[4];
     } else {
         for (int v = 0; v < NV; ++v) qg[v] = m->qfar[v];
     }
@@ -666,188 +588,75 @@ static void face_trace(const int *n, int d, int s, int nv, const double *X, doub
             for (int a = 0; a < na; ++a) out[v * na * nb + a + na * b] = X[v * ne + face_node(n, d, s, a, b)];
 }
 
-/* BR1 trace of the solution on face (d, s) of element e, projected on its own face:
- * qhat = (1/2)(Q_in + Q_out) on the mortar (or with the ghost state at boundaries). */
-static void br1_qhat(const orc_mesh *m, const int *orders, const long *off, const double *u, int e, int d, int s,
-                     double *qhat)
+/* Scaled normal of a face on its mortar, mK[c*K1*K2 + x] (c = x, y, z): the minus-side
+ * element's Ja^d (outward from it) interpolated onto the mortar nodes.  Box elements:
+ * the constant |Ja^d| e_d. */
+static void mortar_metric(const orc_mesh *m, const int *oL, int eL, int d, int K1, int K2, double *mK)
 {
-    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-    const int *o = orders + 3 * e;
-    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
-    int na = n[t1], nb = n[t2];
-    double *own = malloc(sizeof(double) * NV * na * nb);
-    face_trace(n, d, s, NV, u + NV * off[e], own);
-    int bc;
-    int nbr = neighbour(m, e, d, s, &bc);
-    if (nbr < 0) {
-        for (int x = 0; x < na * nb; ++x) {
-            double qin[NV], qg[NV];
-            for (int v = 0; v < NV; ++v) qin[v] = own[v * na * nb + x];
-            ghost_state(m, bc, d, s, qin, qg);
-            for (int v = 0; v < NV; ++v) qhat[v * na * nb + x] = 0.5 * (qin[v] + qg[v]);
-        }
-        free(own);
-        return;
-    }
-    const int *on = orders + 3 * nbr;
-    int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1};
-    int ma = nn[t1], mb = nn[t2];
-    int K1 = na > ma ? na : ma, K2 = nb > mb ? nb : mb;
-    double *oth = malloc(sizeof(double) * NV * ma * mb);
-    face_trace(nn, d, -s, NV, u + NV * off[nbr], oth);
-    double *A = malloc(sizeof(double) * NV * K1 * K2), *B = malloc(sizeof(double) * NV * K1 * K2);
-    to_mortar(NV, na, nb, K1, K2, own, A);
-    to_mortar(NV, ma, mb, K1, K2, oth, B);
-    for (int x = 0; x < NV * K1 * K2; ++x) A[x] = 0.5 * (A[x] + B[x]);
-    from_mortar(NV, na, nb, K1, K2, A, qhat);
-    free(own); free(oth); free(A); free(B);
-}
-
-/* J dQ/dx_l = Ja_l [ D_l Q + sum_s (qhat - Q) s / w_end on the l-faces ] (affine). */
-static void element_gradient(const orc_mesh *m, const int *orders, const long *off, const double *u, int e,
-                             int isolated, double *grad)
-{
-    const int *o = orders + 3 * e;
-    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
-    const double *Q = u + NV * off[e];
-    double h[3], J, Ja[3];
-    geometry(m, h, &J, Ja);
-    for (int l = 0; l < 3; ++l) {
-        double *Gl = grad + (size_t)l * NV * ne;
-        for (int k = 0; k < n[2]; ++k)
-            for (int j = 0; j < n[1]; ++j)
-                for (int i = 0; i < n[0]; ++i) {
-                    int idx[3] = {i, j, k};
-                    int node = i + n[0] * (j + n[1] * k);
-                    for (int v = 0; v < NV; ++v) {
-                        double acc = 0.0;
-                        for (int q = 0; q < n[l]; ++q) {
-                            int id2[3] = {i, j, k};
-                            id2[l] = q;
-                            acc += g_D[o[l]][idx[l] * n[l] + q] * Q[v * ne + id2[0] + n[0] * (id2[1] + n[1] * id2[2])];
-                        }
-                        Gl[v * ne + node] = acc;
-                    }
-                }
-        if (!isolated) {
-            int t1 = (l == 0) ? 1 : 0, t2 = (l == 2) ? 1 : 2;
-            int na = n[t1], nb = n[t2];
-            double *qh = malloc(sizeof(double) * NV * na * nb);
-            for (int s = -1; s <= 1; s += 2) {
-                br1_qhat(m, orders, off, u, e, l, s, qh);
-                for (int b = 0; b < nb; ++b)
-                    for (int a = 0; a < na; ++a) {
-                        int node = face_node(n, l, s, a, b);
-                        for (int v = 0; v < NV; ++v)
-                            Gl[v * ne + node] += (double)s * (qh[v * na * nb + a + na * b] - Q[v * ne + node]) /
-                                                 g_w[o[l]][0];
-                    }
-            }
-            free(qh);
-        }
-        for (int x = 0; x < NV * ne; ++x) Gl[x] *= Ja[l] / J;
-    }
-}
-
-int orc_gradient(const orc_mesh *m, const int *orders, const double *u, int isolated, double *grad)
-{
-    int E = m->nx * m->ny * m->nz;
-    if (E <= 0 || check_orders(E, orders)) return -1;
-    ensure_tables();
-    long *off = node_offsets(E, orders);
-#pragma omp parallel for schedule(guided)
-    for (int e = 0; e < E; ++e) element_gradient(m, orders, off, u, e, isolated, grad + 3 * NV * off[e]);
-    free(off);
-    return 0;
-}
-
-/* Outward NS flux on face (d, s) of element e at its own face nodes:
- * s * P_own [ |Ja| ( f*_Roe(QL^K, QR^K, e_d) - (1/2)(f^v_d(QL^K, GL^K) + f^v_d(QR^K, GR^K)) ) ],
- * left = minus side; at boundaries the ghost state carries the inner gradient. */
-static void face_flux_ns(const orc_mesh *m, const int *orders, const long *off, const double *u,
-                         const double *grad, double mu, double Pr, int e, int d, int s, const double *Ja,
-                         double *fout)
-{
-    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
-    const int *o = orders + 3 * e;
-    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
-    int na = n[t1], nb = n[t2];
-    const int nf = 4 * NV; /* Q and the three gradient components */
-    double *own = malloc(sizeof(double) * nf * na * nb);
-    face_trace(n, d, s, NV, u + NV * off[e], own);
-    face_trace(n, d, s, 3 * NV, grad + 3 * NV * off[e], own + NV * na * nb);
-    double g = m->gamma;
-    int bc;
-    int nbr = neighbour(m, e, d, s, &bc);
-    if (nbr < 0) {
-        double nout[3] = {0, 0, 0};
-        nout[d] = (double)s;
-        for (int x = 0; x < na * nb; ++x) {
-            double qin[NV], qg[NV], G[3 * NV], fa[NV], fv1[NV], fv2[NV];
-            for (int v = 0; v < NV; ++v) qin[v] = own[v * na * nb + x];
-            for (int c = 0; c < 3 * NV; ++c) G[c] = own[(NV + c) * na * nb + x];
-            ghost_state(m, bc, d, s, qin, qg);
-            orc_numflux(qin, qg, nout, g, m->flux, fa);
-            orc_viscous_flux(qin, G, d, g, mu, Pr, fv1);
-            orc_viscous_flux(qg, G, d, g, mu, Pr, fv2);
-            for (int v = 0; v < NV; ++v)
-                fout[v * na * nb + x] = Ja[d] * (fa[v] - (double)s * 0.5 * (fv1[v] + fv2[v]));
-        }
-        free(own);
-        return;
-    }
-    const int *on = orders + 3 * nbr;
-    int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1};
-    int ma = nn[t1], mb = nn[t2];
-    double *oth = malloc(sizeof(double) * nf * ma * mb);
-    face_trace(nn, d, -s, NV, u + NV * off[nbr], oth);
-    face_trace(nn, d, -s, 3 * NV, grad + 3 * NV * off[nbr], oth + NV * ma * mb);
-    int K1 = na > ma ? na : ma, K2 = nb > mb ? nb : mb;
-    double *A = malloc(sizeof(double) * nf * K1 * K2), *B = malloc(sizeof(double) * nf * K1 * K2);
-    to_mortar(nf, na, nb, K1, K2, own, A);
-    to_mortar(nf, ma, mb, K1, K2, oth, B);
-    double *L = s > 0 ? A : B, *R = s > 0 ? B : A;
-    double *FK = malloc(sizeof(double) * NV * K1 * K2);
-    double nplus[3] = {0, 0, 0};
-    nplus[d] = 1.0;
     int KK = K1 * K2;
-    for (int x = 0; x < KK; ++x) {
-        double qL[NV], qR[NV], GL[3 * NV], GR[3 * NV], fa[NV], fvL[NV], fvR[NV];
-        for (int v = 0; v < NV; ++v) { qL[v] = L[v * KK + x]; qR[v] = R[v * KK + x]; }
-        for (int c = 0; c < 3 * NV; ++c) { GL[c] = L[(NV + c) * KK + x]; GR[c] = R[(NV + c) * KK + x]; }
-        orc_numflux(qL, qR, nplus, g, m->flux, fa);
-        orc_viscous_flux(qL, GL, d, g, mu, Pr, fvL);
-        orc_viscous_flux(qR, GR, d, g, mu, Pr, fvR);
-        for (int v = 0; v < NV; ++v) FK[v * KK + x] = Ja[d] * (fa[v] - 0.5 * (fvL[v] + fvR[v]));
+    if (m->map_kind == 0) {
+        double h[3], J, Ja[3];
+        geometry(m, h, &J, Ja);
+        for (int c = 0; c < 3; ++c)
+            for (int x = 0; x < KK; ++x) mK[c * KK + x] = (c == d) ? Ja[d] : 0.0;
+        return;
     }
-    from_mortar(NV, na, nb, K1, K2, FK, fout);
-    for (int x = 0; x < NV * na * nb; ++x) fout[x] *= (double)s;
-    free(own); free(oth); free(A); free(B); free(FK);
+    int n[3] = {oL[0] + 1, oL[1] + 1, oL[2] + 1}, ne = n[0] * n[1] * n[2];
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    double *Ja = malloc(sizeof(double) * 9 * ne), *J = malloc(sizeof(double) * ne);
+    double *tr = malloc(sizeof(double) * 3 * n[t1] * n[t2]);
+    elem_metrics(m, oL, eL, Ja, J);
+    face_trace(n, d, +1, 3, Ja + 3 * d * ne, tr);
+    to_mortar(3, n[t1], n[t2], K1, K2, tr, mK);
+    free(Ja); free(J); free(tr);
 }
 
-static void element_residual_ns(const orc_mesh *m, const int *orders, const long *off, const double *u,
-                                const double *grad, double mu, double Pr, int e, int form, int isolated, double *r)
+/* Split a scaled normal into its length and the unit normal. */
+static double unit_normal(const double *mv, double *nh)
 {
-    const int *o = orders + 3 * e;
-    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
-    const double *Q = u + NV * off[e];
-    const double *G = grad + 3 * NV * off[e];
-    double h[3], J, Ja[3];
-    geometry(m, h, &J, Ja);
-    double *Ft = malloc(sizeof(double) * 3 * NV * ne), *V = calloc((size_t)NV * ne, sizeof(double));
+    double len = sqrt(mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2]);
+    for (int c = 0; c < 3; ++c) nh[c] = mv[c] / len;
+    return len;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Residual: contravariant fluxes, volume term, surface terms.               */
+
+/* Contravariant flux Ft^d = sum_l (Ja^d)_l (f^a_l - f^v_l) at every node,
+ * Ft[(d*NV + v)*ne + node].  G (nullable: Euler) holds the gradients [3][5][node]. */
+static void contravariant_flux(const orc_mesh *m, const int *o, const double *Q, const double *G, double mu,
+                               double Pr, const double *Ja, double *Ft)
+{
+    int ne = nnodes(o);
     for (int node = 0; node < ne; ++node) {
-        double q[NV], Gn[3 * NV], fa[NV], fv[NV];
+        double q[NV], f[3][NV], Gn[3 * NV];
         for (int v = 0; v < NV; ++v) q[v] = Q[v * ne + node];
-        for (int l = 0; l < 3; ++l)
-            for (int v = 0; v < NV; ++v) Gn[5 * l + v] = G[(l * NV + v) * ne + node];
-        for (int d = 0; d < 3; ++d) {
-            double nd[3] = {0, 0, 0};
-            nd[d] = 1.0;
-            orc_flux_n(q, nd, m->gamma, fa);
-            orc_viscous_flux(q, Gn, d, m->gamma, mu, Pr, fv);
-            for (int v = 0; v < NV; ++v) Ft[(d * NV + v) * ne + node] = Ja[d] * (fa[v] - fv[v]);
+        if (G)
+            for (int l = 0; l < 3; ++l)
+                for (int v = 0; v < NV; ++v) Gn[5 * l + v] = G[(l * NV + v) * ne + node];
+        for (int l = 0; l < 3; ++l) {
+            double el[3] = {0, 0, 0};
+            el[l] = 1.0;
+            orc_flux_n(q, el, m->gamma, f[l]);
+            if (G) {
+                double fv[NV];
+                orc_viscous_flux(q, Gn, l, m->gamma, mu, Pr, fv);
+                for (int v = 0; v < NV; ++v) f[l][v] = f[l][v] - fv[v];
+            }
         }
+        for (int d = 0; d < 3; ++d)
+            for (int v = 0; v < NV; ++v) {
+                double acc = 0.0;
+                for (int l = 0; l < 3; ++l) acc += Ja[(d * 3 + l) * ne + node] * f[l][v];
+                Ft[(d * NV + v) * ne + node] = acc;
+            }
     }
+}
+
+/* Volume term V = sum_d D^{N_d} Ft^d along direction d, V[v*ne + node]. */
+static void volume_term(const int *o, const double *Ft, double *V)
+{
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
     for (int k = 0; k < n[2]; ++k)
         for (int j = 0; j < n[1]; ++j)
             for (int i = 0; i < n[0]; ++i) {
@@ -863,19 +672,136 @@ static void element_residual_ns(const orc_mesh *m, const int *orders, const long
                     V[v * ne + node] = acc;
                 }
             }
+}
+
+/* Outward numerical flux F*_out at the own face nodes of face (d, s) of element e:
+ * fout[v*(na*nb) + a + na*b].  JaOwn: the element's metric terms.  With G (the
+ * gradients, Navier-Stokes) the BR1 viscous trace is subtracted:
+ *   F* = |m| [ f*(Q_L, Q_R, n) - (1/2) sum_l n_l (f^v_l(Q_L, G_L) + f^v_l(Q_R, G_R)) ],
+ * with m the scaled normal (Ja^d of the minus side on the mortar), n = m/|m|; at
+ * boundaries the ghost state carries the inner gradient. */
+static void face_flux(const orc_mesh *m, const int *orders, const long *off, const double *u,
+                      const double *grad, double mu, double Pr, int e, int d, int s, const double *JaOwn,
+                      double *fout)
+{
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
+    int na = n[t1], nb = n[t2], ne = n[0] * n[1] * n[2];
+    const int nf = grad ? 4 * NV : NV; /* Q (and the three gradient components) */
+    double g = m->gamma;
+    double *own = malloc(sizeof(double) * nf * na * nb);
+    face_trace(n, d, s, NV, u + NV * off[e], own);
+    if (grad) face_trace(n, d, s, 3 * NV, grad + 3 * NV * off[e], own + NV * na * nb);
+
+    int bc;
+    int nbr = neighbour(m, e, d, s, &bc);
+    if (nbr < 0) {
+        double *mo = malloc(sizeof(double) * 3 * na * nb);
+        face_trace(n, d, s, 3, JaOwn + 3 * d * ne, mo);
+        for (int x = 0; x < na * nb; ++x) {
+            double mv[3], nh[3], qin[NV], qg[NV], fa[NV], Gin[3 * NV];
+            for (int c = 0; c < 3; ++c) mv[c] = (double)s * mo[c * na * nb + x];
+            double len = unit_normal(mv, nh);
+            for (int v = 0; v < NV; ++v) qin[v] = own[v * na * nb + x];
+            ghost_state(m, bc, nh, qin, qg);
+            orc_numflux(qin, qg, nh, g, m->flux, fa);
+            if (grad) {
+                double vs[NV] = {0, 0, 0, 0, 0};
+                for (int c = 0; c < 3 * NV; ++c) Gin[c] = own[(NV + c) * na * nb + x];
+                for (int l = 0; l < 3; ++l) {
+                    double fv1[NV], fv2[NV];
+                    orc_viscous_flux(qin, Gin, l, g, mu, Pr, fv1);
+                    orc_viscous_flux(qg, Gin, l, g, mu, Pr, fv2);
+                    for (int v = 0; v < NV; ++v) vs[v] += nh[l] * (fv1[v] + fv2[v]);
+                }
+                for (int v = 0; v < NV; ++v) fout[v * na * nb + x] = len * (fa[v] - 0.5 * vs[v]);
+            } else {
+                for (int v = 0; v < NV; ++v) fout[v * na * nb + x] = len * fa[v];
+            }
+        }
+        free(mo);
+        free(own);
+        return;
+    }
+
+    const int *on = orders + 3 * nbr;
+    int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1};
+    int ma = nn[t1], mb = nn[t2];
+    double *oth = malloc(sizeof(double) * nf * ma * mb);
+    face_trace(nn, d, -s, NV, u + NV * off[nbr], oth);
+    if (grad) face_trace(nn, d, -s, 3 * NV, grad + 3 * NV * off[nbr], oth + NV * ma * mb);
+    int K1 = na > ma ? na : ma, K2 = nb > mb ? nb : mb, KK = K1 * K2;
+    double *A = malloc(sizeof(double) * nf * KK), *B = malloc(sizeof(double) * nf * KK);
+    to_mortar(nf, na, nb, K1, K2, own, A);
+    to_mortar(nf, ma, mb, K1, K2, oth, B);
+    /* left = element on the minus side of the face, right = plus side */
+    double *L = s > 0 ? A : B, *R = s > 0 ? B : A;
+    double *mK = malloc(sizeof(double) * 3 * KK);
+    if (s > 0) mortar_metric(m, o, e, d, K1, K2, mK);
+    else mortar_metric(m, on, nbr, d, K1, K2, mK);
+    double *FK = malloc(sizeof(double) * NV * KK);
+    for (int x = 0; x < KK; ++x) {
+        double mv[3] = {mK[x], mK[KK + x], mK[2 * KK + x]}, nh[3];
+        double len = unit_normal(mv, nh);
+        double qL[NV], qR[NV], fa[NV];
+        for (int v = 0; v < NV; ++v) {
+            qL[v] = L[v * KK + x];
+            qR[v] = R[v * KK + x];
+        }
+        orc_numflux(qL, qR, nh, g, m->flux, fa);
+        if (grad) {
+            double GL[3 * NV], GR[3 * NV], vs[NV] = {0, 0, 0, 0, 0};
+            for (int c = 0; c < 3 * NV; ++c) {
+                GL[c] = L[(NV + c) * KK + x];
+                GR[c] = R[(NV + c) * KK + x];
+            }
+            for (int l = 0; l < 3; ++l) {
+                double fvL[NV], fvR[NV];
+                orc_viscous_flux(qL, GL, l, g, mu, Pr, fvL);
+                orc_viscous_flux(qR, GR, l, g, mu, Pr, fvR);
+                for (int v = 0; v < NV; ++v) vs[v] += nh[l] * (fvL[v] + fvR[v]);
+            }
+            for (int v = 0; v < NV; ++v) FK[v * KK + x] = len * (fa[v] - 0.5 * vs[v]);
+        } else {
+            for (int v = 0; v < NV; ++v) FK[v * KK + x] = len * fa[v];
+        }
+    }
+    /* project back onto the own face (L2 projection), outward sign */
+    from_mortar(NV, na, nb, K1, K2, FK, fout);
+    for (int x = 0; x < NV * na * nb; ++x) fout[x] *= (double)s;
+    free(own); free(oth); free(A); free(B); free(mK); free(FK);
+}
+
+/* Residual of one element of orders o with data Q (natural layout of element e):
+ * r = (V + SAT)/J (form 0) or w_i w_j w_k (V + SAT) (form 1).  G: gradients (NS) or
+ * NULL (Euler).  Surface terms need the whole mesh (orders, off, u, grad); isolated
+ * evaluations pass isolated = 1 and may leave those NULL. */
+static void residual_core(const orc_mesh *m, const int *orders, const long *off, const double *u,
+                          const double *grad, double mu, double Pr, const int *o, int e, const double *Q,
+                          const double *G, int form, int isolated, double *r)
+{
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+    double *Ja = malloc(sizeof(double) * 9 * ne), *Jn = malloc(sizeof(double) * ne);
+    elem_metrics(m, o, e, Ja, Jn);
+    double *Ft = malloc(sizeof(double) * 3 * NV * ne);  /* [d][v][node] */
+    double *V = malloc(sizeof(double) * NV * ne);       /* [v][node] */
+    contravariant_flux(m, o, Q, G, mu, Pr, Ja, Ft);
+    volume_term(o, Ft, V);
     if (!isolated) {
         for (int d = 0; d < 3; ++d) {
             int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
             int na = n[t1], nb = n[t2];
+            double wend = g_w[o[d]][0];
             double *fout = malloc(sizeof(double) * NV * na * nb);
             for (int s = -1; s <= 1; s += 2) {
-                face_flux_ns(m, orders, off, u, grad, mu, Pr, e, d, s, Ja, fout);
+                face_flux(m, orders, off, u, grad, mu, Pr, e, d, s, Ja, fout);
                 for (int b = 0; b < nb; ++b)
                     for (int a = 0; a < na; ++a) {
                         int node = face_node(n, d, s, a, b);
                         for (int v = 0; v < NV; ++v)
                             V[v * ne + node] += (fout[v * na * nb + a + na * b] -
-                                                 (double)s * Ft[(d * NV + v) * ne + node]) / g_w[o[d]][0];
+                                                 (double)s * Ft[(d * NV + v) * ne + node]) / wend;
                     }
             }
             free(fout);
@@ -887,24 +813,250 @@ static void element_residual_ns(const orc_mesh *m, const int *orders, const long
                 int node = i + n[0] * (j + n[1] * k);
                 double www = g_w[o[0]][i] * g_w[o[1]][j] * g_w[o[2]][k];
                 for (int v = 0; v < NV; ++v)
-                    r[v * ne + node] = form == 0 ? V[v * ne + node] / J : www * V[v * ne + node];
+                    r[v * ne + node] = form == 0 ? V[v * ne + node] / Jn[node] : www * V[v * ne + node];
             }
-    free(Ft);
-    free(V);
+    free(Ja); free(Jn); free(Ft); free(V);
+}
+
+int orc_residual(const orc_mesh *m, const int *orders, const double *u, double *r, int form,
+                 int isolated)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (check_mesh(m) || check_orders(E, orders) || (form != 0 && form != 1)) return -1;
+    ensure_tables();
+    long *off = node_offsets(E, orders);
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e)
+        residual_core(m, orders, off, u, NULL, 0.0, 0.0, orders + 3 * e, e, u + NV * off[e], NULL, form, isolated,
+                      r + NV * off[e]);
+    free(off);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Navier-Stokes: BR1 gradients and viscous fluxes.                           */
+
+void orc_viscous_flux(const double *q, const double *G, int d, double g, double mu, double Pr, double *f)
+{
+    double rho = q[0], u[3] = {q[1] / q[0], q[2] / q[0], q[3] / q[0]};
+    double p = pressure(q, g), T = p / rho;
+    double du[3][3]; /* du[k][l] = d u_k / d x_l */
+    double dT[3];
+    for (int l = 0; l < 3; ++l) {
+        const double *Gl = G + 5 * l;
+        for (int k = 0; k < 3; ++k) du[k][l] = (Gl[1 + k] - u[k] * Gl[0]) / rho;
+        double dp = (g - 1.0) * (Gl[4] - (u[0] * Gl[1] + u[1] * Gl[2] + u[2] * Gl[3]) +
+                                 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * Gl[0]);
+        dT[l] = (dp - T * Gl[0]) / rho;
+    }
+    double div = du[0][0] + du[1][1] + du[2][2];
+    double tau[3]; /* tau[k] = tau_{k d} */
+    for (int k = 0; k < 3; ++k) tau[k] = mu * (du[k][d] + du[d][k]) - (k == d ? 2.0 / 3.0 * mu * div : 0.0);
+    double kappa = mu * g / ((g - 1.0) * Pr);
+    f[0] = 0.0;
+    for (int k = 0; k < 3; ++k) f[1 + k] = tau[k];
+    f[4] = u[0] * tau[0] + u[1] * tau[1] + u[2] * tau[2] + kappa * dT[d];
+}
+
+/* BR1 surface data of face (d, s) of element e on its own face nodes, for the
+ * gradient pass.  qhat = (1/2)(Q_in + Q_out) on the mortar (the ghost state at
+ * boundaries).  Box elements: out[v][node] = qhat projected back (the metric is the
+ * constant |Ja^d| e_d and is applied by the caller).  Curved elements:
+ * out[(l*NV + v)][node] = s P[qhat m_l], the outward scaled normal m (Ja^d of the
+ * minus side on the mortar) multiplied in before the projection, l = x, y, z. */
+static void br1_face(const orc_mesh *m, const int *orders, const long *off, const double *u, int e, int d, int s,
+                     const double *JaOwn, double *out)
+{
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
+    int na = n[t1], nb = n[t2], ne = n[0] * n[1] * n[2], F = na * nb;
+    const int curved = m->map_kind != 0;
+    double *own = malloc(sizeof(double) * NV * F);
+    face_trace(n, d, s, NV, u + NV * off[e], own);
+    int bc;
+    int nbr = neighbour(m, e, d, s, &bc);
+    if (nbr < 0) {
+        double *mo = malloc(sizeof(double) * 3 * F);
+        face_trace(n, d, s, 3, JaOwn + 3 * d * ne, mo);
+        for (int x = 0; x < F; ++x) {
+            double qin[NV], qg[NV], mv[3], nh[3];
+            for (int c = 0; c < 3; ++c) mv[c] = (double)s * mo[c * F + x];
+            unit_normal(mv, nh);
+            for (int v = 0; v < NV; ++v) qin[v] = own[v * F + x];
+            ghost_state(m, bc, nh, qin, qg);
+            for (int v = 0; v < NV; ++v) {
+                double qh = 0.5 * (qin[v] + qg[v]);
+                if (!curved) out[v * F + x] = qh;
+                else
+                    for (int l = 0; l < 3; ++l) out[(l * NV + v) * F + x] = qh * mv[l];
+            }
+        }
+        free(mo);
+        free(own);
+        return;
+    }
+    const int *on = orders + 3 * nbr;
+    int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1};
+    int ma = nn[t1], mb = nn[t2];
+    int K1 = na > ma ? na : ma, K2 = nb > mb ? nb : mb, KK = K1 * K2;
+    double *oth = malloc(sizeof(double) * NV * ma * mb);
+    face_trace(nn, d, -s, NV, u + NV * off[nbr], oth);
+    double *A = malloc(sizeof(double) * NV * KK), *B = malloc(sizeof(double) * NV * KK);
+    to_mortar(NV, na, nb, K1, K2, own, A);
+    to_mortar(NV, ma, mb, K1, K2, oth, B);
+    for (int x = 0; x < NV * KK; ++x) A[x] = 0.5 * (A[x] + B[x]);
+    if (!curved) {
+        from_mortar(NV, na, nb, K1, K2, A, out);
+    } else {
+        double *mK = malloc(sizeof(double) * 3 * KK), *prod = malloc(sizeof(double) * 3 * NV * KK);
+        if (s > 0) mortar_metric(m, o, e, d, K1, K2, mK);
+        else mortar_metric(m, on, nbr, d, K1, K2, mK);
+        for (int l = 0; l < 3; ++l)
+            for (int v = 0; v < NV; ++v)
+                for (int x = 0; x < KK; ++x) prod[(l * NV + v) * KK + x] = (double)s * A[v * KK + x] * mK[l * KK + x];
+        from_mortar(3 * NV, na, nb, K1, K2, prod, out);
+        free(mK);
+        free(prod);
+    }
+    free(own); free(oth); free(A); free(B);
+}
+
+/* BR1 gradient of element e (orders o, data Q), grad[(l*NV + v)*ne + node] = d(var v)/dx_l.
+ *   Box elements:    J dQ/dx_l = |Ja^l| [ D_l Q + sum_s s (qhat - Q) / w_end on the l-faces ].
+ *   Curved elements: J dQ/dx_l = sum_d D_d[(Ja^d)_l Q]
+ *                                + sum over faces (d, s) of (s P[qhat m_l] - Q s (Ja^d)_l) / w_end.
+ * isolated drops the surface terms (then orders, off and u may be NULL). */
+static void gradient_core(const orc_mesh *m, const int *orders, const long *off, const double *u, const int *o,
+                          int e, const double *Q, int isolated, double *grad)
+{
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+    if (m->map_kind == 0) {
+        double h[3], J, Ja[3];
+        geometry(m, h, &J, Ja);
+        double *Jfull = NULL;
+        if (!isolated) {
+            Jfull = malloc(sizeof(double) * 10 * ne);
+            elem_metrics(m, o, e, Jfull, Jfull + 9 * ne);
+        }
+        for (int l = 0; l < 3; ++l) {
+            double *Gl = grad + (size_t)l * NV * ne;
+            for (int k = 0; k < n[2]; ++k)
+                for (int j = 0; j < n[1]; ++j)
+                    for (int i = 0; i < n[0]; ++i) {
+                        int idx[3] = {i, j, k};
+                        int node = i + n[0] * (j + n[1] * k);
+                        for (int v = 0; v < NV; ++v) {
+                            double acc = 0.0;
+                            for (int q = 0; q < n[l]; ++q) {
+                                int id2[3] = {i, j, k};
+                                id2[l] = q;
+                                acc += g_D[o[l]][idx[l] * n[l] + q] * Q[v * ne + id2[0] + n[0] * (id2[1] + n[1] * id2[2])];
+                            }
+                            Gl[v * ne + node] = acc;
+                        }
+                    }
+            if (!isolated) {
+                int t1 = (l == 0) ? 1 : 0, t2 = (l == 2) ? 1 : 2;
+                int na = n[t1], nb = n[t2];
+                double *qh = malloc(sizeof(double) * NV * na * nb);
+                for (int s = -1; s <= 1; s += 2) {
+                    br1_face(m, orders, off, u, e, l, s, Jfull, qh);
+                    for (int b = 0; b < nb; ++b)
+                        for (int a = 0; a < na; ++a) {
+                            int node = face_node(n, l, s, a, b);
+                            for (int v = 0; v < NV; ++v)
+                                Gl[v * ne + node] += (double)s * (qh[v * na * nb + a + na * b] - Q[v * ne + node]) /
+                                                     g_w[o[l]][0];
+                        }
+                }
+                free(qh);
+            }
+            for (int x = 0; x < NV * ne; ++x) Gl[x] *= Ja[l] / J;
+        }
+        free(Jfull);
+        return;
+    }
+    double *Ja = malloc(sizeof(double) * 9 * ne), *Jn = malloc(sizeof(double) * ne);
+    double *P = malloc(sizeof(double) * NV * ne);
+    elem_metrics(m, o, e, Ja, Jn);
+    for (int l = 0; l < 3; ++l) {
+        double *Gl = grad + (size_t)l * NV * ne;
+        for (int x = 0; x < NV * ne; ++x) Gl[x] = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            /* P = (Ja^d)_l Q, differentiated along d */
+            for (int v = 0; v < NV; ++v)
+                for (int x = 0; x < ne; ++x) P[v * ne + x] = Ja[(d * 3 + l) * ne + x] * Q[v * ne + x];
+            for (int k = 0; k < n[2]; ++k)
+                for (int j = 0; j < n[1]; ++j)
+                    for (int i = 0; i < n[0]; ++i) {
+                        int idx[3] = {i, j, k};
+                        int node = i + n[0] * (j + n[1] * k);
+                        for (int v = 0; v < NV; ++v) {
+                            double acc = 0.0;
+                            for (int q = 0; q < n[d]; ++q) {
+                                int id2[3] = {i, j, k};
+                                id2[d] = q;
+                                acc += g_D[o[d]][idx[d] * n[d] + q] * P[v * ne + id2[0] + n[0] * (id2[1] + n[1] * id2[2])];
+                            }
+                            Gl[v * ne + node] += acc;
+                        }
+                    }
+        }
+    }
+    if (!isolated) {
+        for (int d = 0; d < 3; ++d) {
+            int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            int na = n[t1], nb = n[t2], F = na * nb;
+            double *bf = malloc(sizeof(double) * 3 * NV * F);
+            for (int s = -1; s <= 1; s += 2) {
+                br1_face(m, orders, off, u, e, d, s, Ja, bf);
+                for (int b = 0; b < nb; ++b)
+                    for (int a = 0; a < na; ++a) {
+                        int node = face_node(n, d, s, a, b);
+                        for (int l = 0; l < 3; ++l) {
+                            double ml = (double)s * Ja[(d * 3 + l) * ne + node];
+                            for (int v = 0; v < NV; ++v)
+                                grad[(l * NV + v) * ne + node] +=
+                                    (bf[(l * NV + v) * F + a + na * b] - Q[v * ne + node] * ml) / g_w[o[d]][0];
+                        }
+                    }
+            }
+            free(bf);
+        }
+    }
+    for (int l = 0; l < 3; ++l)
+        for (int v = 0; v < NV; ++v)
+            for (int x = 0; x < ne; ++x) grad[(l * NV + v) * ne + x] /= Jn[x];
+    free(Ja); free(Jn); free(P);
+}
+
+int orc_gradient(const orc_mesh *m, const int *orders, const double *u, int isolated, double *grad)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (check_mesh(m) || check_orders(E, orders)) return -1;
+    ensure_tables();
+    long *off = node_offsets(E, orders);
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e)
+        gradient_core(m, orders, off, u, orders + 3 * e, e, u + NV * off[e], isolated, grad + 3 * NV * off[e]);
+    free(off);
+    return 0;
 }
 
 int orc_residual_ns(const orc_mesh *m, const int *orders, const double *u, double mu, double Pr, double *r,
                     int form, int isolated)
 {
     int E = m->nx * m->ny * m->nz;
-    if (E <= 0 || check_orders(E, orders) || (form != 0 && form != 1)) return -1;
+    if (check_mesh(m) || check_orders(E, orders) || (form != 0 && form != 1)) return -1;
     ensure_tables();
     long *off = node_offsets(E, orders);
     double *grad = malloc(sizeof(double) * 3 * NV * off[E]);
     orc_gradient(m, orders, u, isolated, grad);
 #pragma omp parallel for schedule(guided)
     for (int e = 0; e < E; ++e)
-        element_residual_ns(m, orders, off, u, grad, mu, Pr, e, form, isolated, r + NV * off[e]);
+        residual_core(m, orders, off, u, grad, mu, Pr, orders + 3 * e, e, u + NV * off[e], grad + 3 * NV * off[e],
+                      form, isolated, r + NV * off[e]);
     free(grad);
     free(off);
     return 0;
@@ -958,7 +1110,7 @@ int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
             double *varnorms)
 {
     int E = m->nx * m->ny * m->nz;
-    if (E <= 0 || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
+    if (check_mesh(m) || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
     for (int i = 0; i < 3 * E; ++i)
         if (coarse_orders[i] > fine_orders[i]) return -1;
     ensure_tables();
@@ -970,12 +1122,12 @@ int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
     orc_restrict(E, fine_orders, coarse_orders, dudt, rdc);
     /* (M^N)^-1 F^N (I^N q^P) on the coarse mesh */
     orc_residual(m, coarse_orders, uc, tau_new, 0, isolated);
-    double h[3], J, Ja[3];
-    geometry(m, h, &J, Ja);
     long *offc = node_offsets(E, coarse_orders);
     for (int e = 0; e < E; ++e) {
         const int *o = coarse_orders + 3 * e;
         int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+        double *Ja = malloc(sizeof(double) * 9 * ne), *Jn = malloc(sizeof(double) * ne);
+        elem_metrics(m, o, e, Ja, Jn);
         double *tn = tau_new + NV * offc[e], *tt = tau_trad + NV * offc[e];
         const double *rd = rdc + NV * offc[e];
         double mx[2] = {0, 0}, vm[2][NV] = {{0}};
@@ -986,7 +1138,7 @@ int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
                         int node = i + n[0] * (j + n[1] * k);
                         int x = v * ne + node;
                         tn[x] = tn[x] - rd[x];
-                        tt[x] = J * g_w[o[0]][i] * g_w[o[1]][j] * g_w[o[2]][k] * tn[x];
+                        tt[x] = Jn[node] * g_w[o[0]][i] * g_w[o[1]][j] * g_w[o[2]][k] * tn[x];
                         double a0 = fabs(tn[x]), a1 = fabs(tt[x]);
                         if (a0 > vm[0][v]) vm[0][v] = a0;
                         if (a1 > vm[1][v]) vm[1][v] = a1;
@@ -1000,6 +1152,8 @@ int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
         if (varnorms)
             for (int f = 0; f < 2; ++f)
                 for (int v = 0; v < NV; ++v) varnorms[(2 * e + f) * NV + v] = vm[f][v];
+        free(Ja);
+        free(Jn);
     }
     free(offc);
     free(uc);
@@ -1010,15 +1164,18 @@ int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
 int orc_num_combos(const int *o)
 {
     int c = 1;
-    for (int d = 0; d < 3; ++d) c *= (o[d] > 1 ? o[d] - 1 : 1);
+    for (int d = 0; d < 3; ++d) c *= o[d] > 1 ? o[d] - 1 : 1;
     return c;
 }
 
-int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const double *dudt,
-              const int *elems, int nelems, double *te_new, double *te_trad)
+/* Isolated sweep, Euler (viscous = 0) or Navier-Stokes: for every combination the
+ * element's isolated coarse residual (its geometry sampled at the coarse nodes)
+ * minus the restricted fine time derivative, both forms, maxima. */
+static int sweep_impl(const orc_mesh *m, const int *orders, const double *u, const double *dudt, int viscous,
+                      double mu, double Pr, const int *elems, int nelems, double *te_new, double *te_trad)
 {
     int E = m->nx * m->ny * m->nz;
-    if (E <= 0 || check_orders(E, orders)) return -1;
+    if (check_mesh(m) || check_orders(E, orders)) return -1;
     for (int i = 0; i < nelems; ++i)
         if (elems[i] < 0 || elems[i] >= E) return -1;
     ensure_tables();
@@ -1026,8 +1183,6 @@ int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const doubl
     long *cofs = malloc(sizeof(long) * (nelems + 1));
     cofs[0] = 0;
     for (int i = 0; i < nelems; ++i) cofs[i + 1] = cofs[i] + orc_num_combos(orders + 3 * elems[i]);
-    double h[3], J, Ja[3];
-    geometry(m, h, &J, Ja);
 
 #pragma omp parallel for schedule(guided)
     for (int i = 0; i < nelems; ++i) {
@@ -1038,7 +1193,8 @@ int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const doubl
         int nef = nnodes(of);
         const double *Q = u + NV * off[e], *R = dudt + NV * off[e];
         double *qc = malloc(sizeof(double) * NV * nef), *rc = malloc(sizeof(double) * NV * nef);
-        double *res = malloc(sizeof(double) * NV * nef);
+        double *res = malloc(sizeof(double) * NV * nef), *G = malloc(sizeof(double) * 3 * NV * nef);
+        double *Ja = malloc(sizeof(double) * 9 * nef), *Jn = malloc(sizeof(double) * nef);
         long slot = cofs[i];
         for (int c3 = 1; c3 <= cmax[2]; ++c3)
             for (int c2 = 1; c2 <= cmax[1]; ++c2)
@@ -1047,24 +1203,18 @@ int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const doubl
                     int n[3] = {c1 + 1, c2 + 1, c3 + 1}, ne = n[0] * n[1] * n[2];
                     restrict_element(of, oc, Q, qc);
                     restrict_element(of, oc, R, rc);
-                    /* isolated coarse residual of the single element: a one-element
-                     * periodic mesh with the isolated flag evaluates only V/J */
-                    orc_mesh one = *m;
-                    one.nx = one.ny = one.nz = 1;
-                    for (int d = 0; d < 3; ++d) {
-                        one.lo[d] = 0.0;
-                        one.hi[d] = h[d];
-                    }
-                    long zero = 0;
-                    element_residual(&one, oc, &zero, qc, 0, 0, 1, res);
+                    if (viscous) gradient_core(m, NULL, NULL, NULL, oc, e, qc, 1, G);
+                    residual_core(m, NULL, NULL, NULL, NULL, mu, Pr, oc, e, qc, viscous ? G : NULL, 0, 1, res);
+                    elem_metrics(m, oc, e, Ja, Jn);
                     double mx0 = 0.0, mx1 = 0.0;
                     for (int v = 0; v < NV; ++v)
                         for (int k = 0; k < n[2]; ++k)
                             for (int j = 0; j < n[1]; ++j)
                                 for (int ii = 0; ii < n[0]; ++ii) {
-                                    int x = v * ne + ii + n[0] * (j + n[1] * k);
+                                    int node = ii + n[0] * (j + n[1] * k);
+                                    int x = v * ne + node;
                                     double tn = res[x] - rc[x];
-                                    double tt = J * g_w[c1][ii] * g_w[c2][j] * g_w[c3][k] * tn;
+                                    double tt = Jn[node] * g_w[c1][ii] * g_w[c2][j] * g_w[c3][k] * tn;
                                     if (fabs(tn) > mx0) mx0 = fabs(tn);
                                     if (fabs(tt) > mx1) mx1 = fabs(tt);
                                 }
@@ -1072,20 +1222,30 @@ int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const doubl
                     te_trad[slot] = mx1;
                     ++slot;
                 }
-        free(qc);
-        free(rc);
-        free(res);
+        free(qc); free(rc); free(res); free(G); free(Ja); free(Jn);
     }
     free(cofs);
     free(off);
     return 0;
 }
 
+int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const double *dudt,
+              const int *elems, int nelems, double *te_new, double *te_trad)
+{
+    return sweep_impl(m, orders, u, dudt, 0, 0.0, 0.0, elems, nelems, te_new, te_trad);
+}
+
+int orc_sweep_ns(const orc_mesh *m, const int *orders, const double *u, const double *dudt, double mu,
+                 double Pr, const int *elems, int nelems, double *te_new, double *te_trad)
+{
+    return sweep_impl(m, orders, u, dudt, 1, mu, Pr, elems, nelems, te_new, te_trad);
+}
+
 int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_orders, const double *u,
                 const double *dudt, int isolated, const double *psi, double *eta)
 {
     int E = m->nx * m->ny * m->nz;
-    if (E <= 0 || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
+    if (check_mesh(m) || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
     long nc = orc_num_nodes(E, coarse_orders);
     double *tn = malloc(sizeof(double) * NV * nc), *tt = malloc(sizeof(double) * NV * nc);
     double *norms = malloc(sizeof(double) * 2 * E), *psic = malloc(sizeof(double) * NV * nc);
@@ -1108,7 +1268,7 @@ int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_ord
 int orc_functional(const orc_mesh *m, const int *orders, const double *u, double *J, double *dJdu)
 {
     int E = m->nx * m->ny * m->nz;
-    if (E <= 0 || check_orders(E, orders)) return -1;
+    if (check_mesh(m) || m->map_kind != 0 || check_orders(E, orders)) return -1;
     ensure_tables();
     double h[3], Jm, Ja[3];
     geometry(m, h, &Jm, Ja);
@@ -1157,7 +1317,7 @@ int orc_rk3(const orc_mesh *m, const int *orders, double *u, double dt, int nste
     static const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
     static const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
     int E = m->nx * m->ny * m->nz;
-    if (E <= 0 || check_orders(E, orders) || nsteps < 0) return -1;
+    if (check_mesh(m) || check_orders(E, orders) || nsteps < 0) return -1;
     long n = NV * orc_num_nodes(E, orders);
     double *r = malloc(sizeof(double) * n), *G = malloc(sizeof(double) * n);
     for (int step = 0; step < nsteps; ++step)

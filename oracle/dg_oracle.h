@@ -33,6 +33,19 @@ typedef struct {
     int flux;        /* 0 Roe, 1 Lax-Friedrichs (Rusanov) */
     double gamma;
     double qfar[5];  /* far-field state (conserved) */
+    /* Geometry.  map_kind 0: the box elements themselves (affine).  map_kind 1: the
+     * box point (x, y, z) is moved to (x + f, y + f, z) with
+     *   f = map_amp sin(2 pi (x - lo_x)/(hi_x - lo_x)) sin(2 pi (y - lo_y)/(hi_y - lo_y)),
+     * each element's geometry being the tensor-product Gauss-Lobatto interpolant of
+     * that map of order geo_order[d] (sampled at the element's own nodes), and the
+     * metric terms Ja^d and J the cross products of the collocation derivatives of the
+     * node coordinates (Section 2.1: the mapping of each element onto the reference
+     * cube).  Curved elements need orders >= geo_order in every direction for the
+     * fine solution; coarse maps of the tau-estimate may go lower (their geometry is
+     * the same interpolant sampled at the coarse nodes). */
+    int map_kind;
+    double map_amp;
+    int geo_order[3];
 } orc_mesh;
 
 /* 1D tables on Legendre-Gauss-Lobatto nodes. x,w: N+1 entries; D: (N+1)^2 row-major. */
@@ -53,6 +66,8 @@ void orc_roe_waves(const double *qL, const double *qR, const double *n, double g
 
 /* Node coordinates, natural ragged layout [e][3][node]. */
 int orc_node_coords(const orc_mesh *m, const int *orders, double *xyz);
+/* Metric terms, natural ragged layout [e][10][node]: Ja^1 (x,y,z), Ja^2, Ja^3, J. */
+int orc_metrics(const orc_mesh *m, const int *orders, double *met);
 long orc_num_nodes(int E, const int *orders);
 
 /* Spatial residual. form 0: new form r = M^-1 F^N = -dQ/dt; form 1: traditional
@@ -80,6 +95,11 @@ int orc_num_combos(const int *order3);
  * contiguously, entries ordered as the list. */
 int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const double *dudt,
               const int *elems, int nelems, double *te_new, double *te_trad);
+
+/* The isolated sweep for the Navier-Stokes equations (BR1 gradients with the
+ * isolated flag, viscous flux of constant mu and Prandtl number Pr). */
+int orc_sweep_ns(const orc_mesh *m, const int *orders, const double *u, const double *dudt, double mu,
+                 double Pr, const int *elems, int nelems, double *te_new, double *te_trad);
 
 /* Adjoint-weighted truncation error (used with an adjoint state psi on the fine
  * layout): eta[e] = sum over coarse nodes and variables of (I psi) * tau_trad. */

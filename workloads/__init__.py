@@ -35,6 +35,28 @@ def box_mesh(n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=(0,) * 6, flux=ROE,
             "flux": int(flux), "gamma": float(gamma), "qfar": tuple(float(v) for v in qfar)}
 
 
+SINE_MAP = 1
+
+
+def sine_mapped(mesh, amp: float = 0.05, geo_order=(2, 2, 1)):
+    """The box mesh with its points moved by (x, y, z) -> (x + f, y + f, z),
+    f = amp sin(2 pi x') sin(2 pi y') (x', y' the box coordinates scaled to [0, 1]),
+    each element's geometry the Gauss-Lobatto interpolant of order geo_order."""
+    m = dict(mesh)
+    m["map"] = (SINE_MAP, float(amp), tuple(int(g) for g in geo_order))
+    return m
+
+
+def column_orders(mesh, lo: int, hi: int, rng, nz_order: int = 1) -> np.ndarray:
+    """Orders (Nx, Ny) drawn i.i.d. uniform in {lo..hi} per element column (ix, iy)
+    and shared by every layer of the column; Nz = nz_order."""
+    nx, ny, nz = mesh["n"]
+    col = rng.integers(lo, hi + 1, (nx * ny, 2))
+    orders = np.full((nx * ny * nz, 3), nz_order, dtype=np.int32)
+    orders[:, :2] = np.tile(col, (nz, 1))
+    return orders
+
+
 def num_elems(mesh) -> int:
     n = mesh["n"]
     return int(n[0] * n[1] * n[2])
@@ -217,15 +239,18 @@ def ns_mesh(mesh, mu: float, Pr: float = 0.72):
     return out
 
 
-def c3(seed: int = 3, n=(32, 32, 2), Re: float = 100.0, Ma: float = 0.2, Pr: float = 0.72):
-    """Navier-Stokes, Re = 100, Ma = 0.2, Pr = 0.72 on [0,1]^2 x [0, 1/16] (32 x 32 x 2 cubes),
-    periodic; per-element orders (Nx, Ny) drawn U{2..6}, Nz = 1.  Nondimensional with
-    rho = 1, |u| = 1, L = 1: mu = 1/Re, p = 1/(gamma Ma^2).  Returns (mesh, orders, rng)."""
+def c3(seed: int = 3, n=(32, 32, 2), Re: float = 100.0, Ma: float = 0.2, Pr: float = 0.72,
+       curved: bool = True):
+    """Navier-Stokes, Re = 100, Ma = 0.2, Pr = 0.72 on [0,1]^2 x [0, 1/16] (32 x 32 x 2 cubes)
+    under the sine map of amplitude 0.05 (geometry order (2, 2, 1)), periodic; orders
+    (Nx, Ny) drawn U{2..6} per element column (both layers of a column share them, so
+    the faces between layers are conforming), Nz = 1.  Nondimensional with rho = 1,
+    |u| = 1, L = 1: mu = 1/Re, p = 1/(gamma Ma^2).  Returns (mesh, orders, rng)."""
     rng = np.random.default_rng(seed)
     mesh = ns_mesh(box_mesh(n, hi=(1.0, 1.0, n[2] / n[0])), mu=1.0 / Re, Pr=Pr)
-    E = n[0] * n[1] * n[2]
-    orders = np.ones((E, 3), dtype=np.int32)
-    orders[:, :2] = rng.integers(2, 7, (E, 2))
+    if curved:
+        mesh = sine_mapped(mesh)
+    orders = column_orders(mesh, 2, 6, rng)
     mesh["p_inf"] = 1.0 / (GAMMA * Ma * Ma)
     return mesh, orders, rng
 
