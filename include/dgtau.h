@@ -45,6 +45,7 @@ enum {
 enum { DG_BC_PERIODIC = 0, DG_BC_SLIP_WALL = 1, DG_BC_FARFIELD = 2 };
 enum { DG_EULER = 0, DG_NAVIER_STOKES = 1 };
 enum { DG_FLUX_ROE = 0, DG_FLUX_LF = 1 };
+enum { DG_MAP_BOX = 0, DG_MAP_SINE = 1 };
 enum { DG_F64 = 0, DG_F32 = 1 };
 /* Residual forms (Section 2.2): NEW = M^-1 F^N(Q) = -dQ/dt, TRAD = F^N(Q) = M * NEW. */
 enum { DG_FORM_NEW = 0, DG_FORM_TRAD = 1 };
@@ -53,9 +54,21 @@ enum { DG_FORM_NEW = 0, DG_FORM_TRAD = 1 };
 
 typedef struct dg_plan_s *dg_plan;
 
-/* Structured box mesh of nx*ny*nz equal axis-aligned hexahedra on [lo, hi];
- * natural element index e = ix + nx*(iy + ny*iz).  bc[] per box face in the
- * order -x,+x,-y,+y,-z,+z; a periodic pair must be periodic on both sides. */
+/* Structured box mesh of nx*ny*nz equal hexahedra on [lo, hi]; natural element
+ * index e = ix + nx*(iy + ny*iz).  bc[] per box face in the order -x,+x,-y,+y,-z,+z;
+ * a periodic pair must be periodic on both sides.
+ * Geometry (Section 2.1: each element is mapped onto the reference cube, fluxes are
+ * contravariant, Ft^d = Ja^d . f, and J is the Jacobian of the map):
+ *   map_kind DG_MAP_BOX: the axis-aligned box elements (constant metric terms).
+ *   map_kind DG_MAP_SINE: the box point (x, y, z) moves to (x + f, y + f, z),
+ *     f = map_amp sin(2 pi (x - lo_x)/(hi_x - lo_x)) sin(2 pi (y - lo_y)/(hi_y - lo_y));
+ *     each element's geometry is the tensor-product Gauss-Lobatto interpolant of the
+ *     map of order geo_order (sampled at the element's nodes); the metric terms are
+ *     the cross products of the collocation derivatives of the node coordinates
+ *     (exact discrete metric identities for this quasi-2D map).  Fine orders must be
+ *     >= geo_order per direction; coarse plans sample the same geometry at their
+ *     nodes.  On faces the minus side's Ja^d, interpolated onto the mortar, is the
+ *     scaled normal of the Riemann problem. */
 typedef struct {
     int32_t nx, ny, nz;
     double lo[3], hi[3];
@@ -66,6 +79,9 @@ typedef struct {
     int32_t equation; /* DG_EULER or DG_NAVIER_STOKES (BR1, Section 2.1 eqs. SystemAdvDiff) */
     double mu;        /* Navier-Stokes: constant dynamic viscosity (nondimensional, 1/Re) */
     double Pr;        /* Navier-Stokes: Prandtl number; heat conductivity mu gamma/((gamma-1) Pr) on T = p/rho */
+    int32_t map_kind; /* DG_MAP_BOX or DG_MAP_SINE */
+    double map_amp;   /* DG_MAP_SINE: amplitude of f */
+    int32_t geo_order[3]; /* DG_MAP_SINE: geometry order per direction, 1..DG_NMAX */
 } dg_mesh_desc;
 
 /* Build a plan for the compressible Euler or Navier-Stokes DGSEM (Section 2.1) on
@@ -73,8 +89,10 @@ typedef struct {
  * of the paper's set-up: gradients of the conserved variables from the averaged
  * solution trace, viscous face flux = average of both sides' viscous fluxes; at
  * boundaries the ghost state carries the inner gradient.  Navier-Stokes plans
- * support orders up to 7 and neither the sweep, the VJP nor batches
- * (DG_EUNSUPPORTED).
+ * support orders up to 7, and neither the VJP nor batches (DG_EUNSUPPORTED).
+ * Curved (DG_MAP_SINE) plans support the residual, RK3, the isolated
+ * tau-estimate and the sweep (fine orders up to 7); the coupled tau-estimate, the
+ * VJP, the functional and batches return DG_EUNSUPPORTED.
  *   orders_host: host int32 [E][3], natural element order, each in 1..DG_NMAX.
  *   out: receives the plan (release with dg_plan_destroy).
  * Errors: DG_EINVAL (bad mesh, orders or periodic pairing), DG_ENOMEM, DG_EHIP. */
@@ -98,6 +116,10 @@ dg_status dg_plan_layout(dg_plan plan, int64_t *n_elems, int64_t *n_nodes, int64
 /* Node coordinates in the plan layout, device double [E] blocks of [3][n_p]
  * (x, y, z of every node, same node order as the state). */
 dg_status dg_node_coords(dg_plan plan, double *xyz, hipStream_t stream);
+
+/* Metric terms in the plan layout, device double [E] blocks of [10][n_p]:
+ * Ja^1 (x, y, z), Ja^2 (x, y, z), Ja^3 (x, y, z), J at every node (Section 2.1). */
+dg_status dg_plan_metrics(dg_plan plan, double *met, hipStream_t stream);
 
 /* Spatial residual of the DGSEM semi-discretisation (Section 2.1, eqs.
  * DGSEMsystem, DGMassMatrixLeft/Right), strong form on Gauss-Lobatto nodes:
@@ -137,7 +159,9 @@ dg_status dg_sweep_layout(dg_plan fine, int64_t *combo_offset);
 /* Isolated anisotropic truncation-error map (Section 2.3 and Section 3,
  * approach 2): for every fine plan element and every coarse combination
  * (c1, c2, c3), c_d in 1..max(1, N_d - 1), enumerated c1 fastest, the maxima
- * over nodes and variables of |tau_new| and |tau_trad| of the isolated estimate.
+ * over nodes and variables of |tau_new| and |tau_trad| of the isolated estimate
+ * (Euler or Navier-Stokes; on curved plans the element's geometry sampled at the
+ * coarse nodes).  Fine orders up to 8 (7 for Navier-Stokes and curved plans).
  *   u, dudt: device double, fine plan layout (dudt as for dg_tau_estimate,
  *            NULL computes it).
  *   te_new, te_trad: device double [combo_offset[E]] (dg_sweep_layout). */

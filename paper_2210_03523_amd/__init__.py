@@ -35,7 +35,8 @@ class _MeshDesc(ctypes.Structure):
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("bc", ctypes.c_int32 * 6), ("flux", ctypes.c_int32),
                 ("gamma", ctypes.c_double), ("q_far", ctypes.c_double * 5),
-                ("equation", ctypes.c_int32), ("mu", ctypes.c_double), ("Pr", ctypes.c_double)]
+                ("equation", ctypes.c_int32), ("mu", ctypes.c_double), ("Pr", ctypes.c_double),
+                ("map_kind", ctypes.c_int32), ("map_amp", ctypes.c_double), ("geo_order", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -50,6 +51,7 @@ SIGNATURES = {
     "dg_plan_destroy": [_P],
     "dg_plan_layout": [_P, _I64P, _I64P, _I64P, _I64P, _I32P],
     "dg_node_coords": [_P, _P, _P],
+    "dg_plan_metrics": [_P, _P, _P],
     "dg_residual": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P, _P, _P],
     "dg_residual_vjp": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P],
@@ -132,6 +134,10 @@ def mesh_desc(mesh: dict) -> _MeshDesc:
     m.equation = 1 if mesh.get("mu") is not None else 0
     m.mu = float(mesh.get("mu") or 0.0)
     m.Pr = float(mesh.get("Pr", 0.72))
+    kind, amp, geo = mesh.get("map", (0, 0.0, (1, 1, 1)))
+    m.map_kind, m.map_amp = int(kind), float(amp)
+    for d in range(3):
+        m.geo_order[d] = int(geo[d])
     return m
 
 
@@ -216,6 +222,13 @@ class Plan:
         xyz = torch.empty(3 * self.n_nodes, dtype=torch.float64, device="cuda")
         _call("dg_node_coords", self.handle, _ptr(xyz), _stream())
         return xyz
+
+    def metrics(self):
+        """Per-node metric terms, plan layout [E][10][n_p] (Ja^1, Ja^2, Ja^3, J)."""
+        torch = _torch()
+        met = torch.empty(10 * self.n_nodes, dtype=torch.float64, device="cuda")
+        _call("dg_plan_metrics", self.handle, _ptr(met), _stream())
+        return met
 
     def combo_offsets(self) -> np.ndarray:
         off = np.zeros(self.n_elems + 1, dtype=np.int64)

@@ -105,6 +105,18 @@ struct dg_plan_s {
     double *d_uc = nullptr, *d_rdc = nullptr, *d_psic = nullptr;
     bool ns = false;              // Navier-Stokes plan
     void *d_grad = nullptr;       // BR1 gradients [elem][3][5][node], sized for doubles
+    // curved elements: per-node metric terms [elem][10][node] (double and float copies),
+    // scaled face normals (3 values per mortar / boundary-face node from node offset
+    // fmo[face]); node coordinates [elem][3][node] of curved and Navier-Stokes plans
+    bool curved = false;
+    std::vector<double> xyz_h;
+    double *d_xyz = nullptr;
+    double *d_met64 = nullptr, *d_fmet64 = nullptr;
+    float *d_met32 = nullptr, *d_fmet32 = nullptr;
+    int64_t *d_fmo = nullptr;
+    // sweep of curved and Navier-Stokes plans: one task per (element, c1, c2, c3)
+    int4 *d_ctasks = nullptr;
+    int nctasks = 0, capA = 0, capB = 0, capS = 0;
     // x-force functional: boundary faces on slip walls normal to x, and their partial sums
     int32_t *d_wallx = nullptr;
     int nwallx = 0;
@@ -135,8 +147,10 @@ void destroy_plan(dg_plan p) {
     if (!p) return;
     for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    void *bufs[] = {p->d_el, p->d_faces, p->d_tiles, p->d_ff, p->d_dudt, p->d_fine_of, p->d_uc, p->d_rdc,
-                    p->d_psic, p->d_combo_off, p->d_tasks, p->d_iso, p->d_wallx, p->d_part, p->d_grad};
+    void *bufs[] = {p->d_el,    p->d_faces,  p->d_tiles,  p->d_ff,     p->d_dudt,   p->d_fine_of, p->d_uc,
+                    p->d_rdc,   p->d_psic,   p->d_combo_off, p->d_tasks, p->d_iso,  p->d_wallx,   p->d_part,
+                    p->d_grad,  p->d_xyz,    p->d_met64,  p->d_fmet64, p->d_met32,  p->d_fmet32,  p->d_fmo,
+                    p->d_ctasks};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -144,7 +158,97 @@ void destroy_plan(dg_plan p) {
 
 int npt_class(int npe) { return npe <= WG ? 1 : (npe <= 2 * WG ? 2 : 4); }
 
-dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *out) {
+// ---------------------------------------------------------------------------- host geometry
+// Node coordinates X[3][ne] of the element at box position c with nodes n[3]: box
+// elements are the affine image of the reference cube; DG_MAP_SINE moves the box point
+// (x, y, z) to (x + f, y + f, z) and takes the Gauss-Lobatto interpolant of order
+// geo_order of that map, sampled at the element's nodes.
+void element_coords(const dg_mesh_desc &m, const double *tab, const int c[3], const int32_t n[3], double *X) {
+    const int nd[3] = {m.nx, m.ny, m.nz};
+    double h[3];
+    for (int d = 0; d < 3; ++d) h[d] = (m.hi[d] - m.lo[d]) / nd[d];
+    const int ne = n[0] * n[1] * n[2];
+    if (m.map_kind == DG_MAP_BOX) {
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i) {
+                    const int idx[3] = {i, j, k};
+                    for (int d = 0; d < 3; ++d)
+                        X[d * ne + i + n[0] * (j + n[1] * k)] =
+                            m.lo[d] + h[d] * (c[d] + 0.5 * (tab[T_X + xoff(n[d] - 1) + idx[d]] + 1.0));
+                }
+        return;
+    }
+    const double two_pi = 6.283185307179586476925286766559;
+    const int G[3] = {m.geo_order[0], m.geo_order[1], m.geo_order[2]};
+    const int g[3] = {G[0] + 1, G[1] + 1, G[2] + 1}, ng = g[0] * g[1] * g[2];
+    std::vector<double> P(3 * (size_t)ng);
+    for (int kc = 0; kc < g[2]; ++kc)
+        for (int kb = 0; kb < g[1]; ++kb)
+            for (int ka = 0; ka < g[0]; ++ka) {
+                const int gi[3] = {ka, kb, kc};
+                double xb[3];
+                for (int d = 0; d < 3; ++d) xb[d] = m.lo[d] + h[d] * (c[d] + 0.5 * (tab[T_X + xoff(G[d]) + gi[d]] + 1.0));
+                const double f = m.map_amp * std::sin(two_pi * (xb[0] - m.lo[0]) / (m.hi[0] - m.lo[0])) *
+                                 std::sin(two_pi * (xb[1] - m.lo[1]) / (m.hi[1] - m.lo[1]));
+                const int gn = ka + g[0] * (kb + g[1] * kc);
+                P[gn] = xb[0] + f;
+                P[ng + gn] = xb[1] + f;
+                P[2 * ng + gn] = xb[2];
+            }
+    const double *I1 = tab + T_I + moff(n[0] - 1, G[0]);
+    const double *I2 = tab + T_I + moff(n[1] - 1, G[1]);
+    const double *I3 = tab + T_I + moff(n[2] - 1, G[2]);
+    for (int d = 0; d < 3; ++d)
+        for (int k = 0; k < n[2]; ++k)
+            for (int j = 0; j < n[1]; ++j)
+                for (int i = 0; i < n[0]; ++i) {
+                    double acc = 0.0;
+                    for (int kc = 0; kc < g[2]; ++kc)
+                        for (int kb = 0; kb < g[1]; ++kb)
+                            for (int ka = 0; ka < g[0]; ++ka)
+                                acc += I1[i * g[0] + ka] * I2[j * g[1] + kb] * I3[k * g[2] + kc] *
+                                       P[d * ng + ka + g[0] * (kb + g[1] * kc)];
+                    X[d * ne + i + n[0] * (j + n[1] * k)] = acc;
+                }
+}
+
+// Metric terms Mt[10][ne] from node coordinates: a_r = D_r X along reference direction r,
+// Ja^1 = a_2 x a_3, Ja^2 = a_3 x a_1, Ja^3 = a_1 x a_2, J = a_1 . Ja^1.
+void element_metrics(const double *tab, const int32_t n[3], const double *X, double *Mt) {
+    const int ne = n[0] * n[1] * n[2];
+    const int stride[3] = {1, n[0], n[0] * n[1]};
+    for (int t = 0; t < ne; ++t) {
+        const int idx[3] = {t % n[0], (t / n[0]) % n[1], t / (n[0] * n[1])};
+        double a[3][3];
+        for (int r = 0; r < 3; ++r) {
+            const double *Drow = tab + T_D + doff(n[r] - 1) + idx[r] * n[r];
+            const int tb = t - idx[r] * stride[r];
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int q = 0; q < n[r]; ++q) acc += Drow[q] * X[c * ne + tb + q * stride[r]];
+                a[r][c] = acc;
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            const double *p = a[(d + 1) % 3], *q = a[(d + 2) % 3];
+            Mt[(3 * d + 0) * ne + t] = p[1] * q[2] - p[2] * q[1];
+            Mt[(3 * d + 1) * ne + t] = p[2] * q[0] - p[0] * q[2];
+            Mt[(3 * d + 2) * ne + t] = p[0] * q[1] - p[1] * q[0];
+        }
+        Mt[9 * ne + t] = a[0][0] * Mt[0 * ne + t] + a[0][1] * Mt[1 * ne + t] + a[0][2] * Mt[2 * ne + t];
+    }
+}
+
+int face_node_h(const int32_t *n, int d, int side, int a, int b) {
+    int idx[3];
+    idx[d] = side > 0 ? n[d] - 1 : 0;
+    idx[d == 0 ? 1 : 0] = a;
+    idx[d == 2 ? 1 : 2] = b;
+    return idx[0] + n[0] * (idx[1] + n[1] * idx[2]);
+}
+
+dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan parent, dg_plan *out) {
     if (!mesh || !orders || !out) return fail(DG_EINVAL, "null argument");
     if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return fail(DG_EINVAL, "mesh needs at least one element per direction");
     const int64_t E64 = (int64_t)mesh->nx * mesh->ny * mesh->nz;
@@ -160,9 +264,20 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
     if (mesh->equation != DG_EULER && mesh->equation != DG_NAVIER_STOKES) return fail(DG_EINVAL, "unknown equation");
     if (mesh->equation == DG_NAVIER_STOKES && !(mesh->mu >= 0.0 && mesh->Pr > 0.0))
         return fail(DG_EINVAL, "Navier-Stokes needs mu >= 0 and Pr > 0");
+    if (mesh->map_kind != DG_MAP_BOX && mesh->map_kind != DG_MAP_SINE) return fail(DG_EINVAL, "unknown map");
+    if (mesh->map_kind == DG_MAP_SINE) {
+        for (int d = 0; d < 3; ++d)
+            if (mesh->geo_order[d] < 1 || mesh->geo_order[d] > DG_NMAX)
+                return fail(DG_EINVAL, "geometry orders must be in 1..9");
+        if (!(std::fabs(mesh->map_amp) < 1e3)) return fail(DG_EINVAL, "map amplitude out of range");
+    }
     const int E = (int)E64;
     for (int i = 0; i < 3 * E; ++i)
         if (orders[i] < 1 || orders[i] > DG_NMAX) return fail(DG_EINVAL, "orders must be in 1..9");
+    if (mesh->map_kind == DG_MAP_SINE && !parent)
+        for (int i = 0; i < 3 * E; ++i)
+            if (orders[i] < mesh->geo_order[i % 3])
+                return fail(DG_EINVAL, "curved elements need orders >= the geometry order");
 
     dg_plan p = new dg_plan_s();
     p->mesh = *mesh;
@@ -275,15 +390,118 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
     }
     for (int v = 0; v < NV; ++v) p->phys.qfar[v] = mesh->q_far[v];
 
-    // sweep layout: combos per element; isotropic elements (F <= 8) go to the fast
-    // path grouped by F, the others to the generic (p, c1, c2) work list
+    // geometry of curved plans (and node coordinates of Navier-Stokes plans, for the sweep)
+    p->curved = mesh->map_kind == DG_MAP_SINE;
+    std::vector<double> met_h, fmet_h;
+    std::vector<int64_t> fmo;
+    if (p->curved || p->ns) {
+        std::vector<double> tab(T_TOT);
+        std::vector<float> tab32(T_TOT);
+        build_tables(tab.data(), tab32.data());
+        p->xyz_h.assign(3 * (size_t)p->n_nodes, 0.0);
+        for (int i = 0; i < E; ++i) {
+            const int nat = (int)perm[i];
+            const int c[3] = {nat % mesh->nx, (nat / mesh->nx) % mesh->ny, nat / (mesh->nx * mesh->ny)};
+            double *X = p->xyz_h.data() + 3 * p->noff[i];
+            if (!parent) {
+                element_coords(*mesh, tab.data(), c, el[i].n, X);
+                continue;
+            }
+            // coarse plan: the fine element's coordinates sampled at the coarse nodes
+            const int fi = (int)parent->inv[nat];
+            const int32_t nf[3] = {parent->ord[3 * fi] + 1, parent->ord[3 * fi + 1] + 1, parent->ord[3 * fi + 2] + 1};
+            const double *Xf = parent->xyz_h.data() + 3 * parent->noff[fi];
+            const int32_t *nc = el[i].n;
+            const int nef = nf[0] * nf[1] * nf[2], nec = nc[0] * nc[1] * nc[2];
+            const double *I1 = tab.data() + T_I + moff(nc[0] - 1, nf[0] - 1);
+            const double *I2 = tab.data() + T_I + moff(nc[1] - 1, nf[1] - 1);
+            const double *I3 = tab.data() + T_I + moff(nc[2] - 1, nf[2] - 1);
+            for (int d = 0; d < 3; ++d)
+                for (int k = 0; k < nc[2]; ++k)
+                    for (int j = 0; j < nc[1]; ++j)
+                        for (int a = 0; a < nc[0]; ++a) {
+                            double acc = 0.0;
+                            for (int kk = 0; kk < nf[2]; ++kk)
+                                for (int jj = 0; jj < nf[1]; ++jj)
+                                    for (int ii = 0; ii < nf[0]; ++ii)
+                                        acc += I1[a * nf[0] + ii] * I2[j * nf[1] + jj] * I3[k * nf[2] + kk] *
+                                               Xf[d * nef + ii + nf[0] * (jj + nf[1] * kk)];
+                            X[d * nec + a + nc[0] * (j + nc[1] * k)] = acc;
+                        }
+        }
+        if (p->curved) {
+            met_h.assign(10 * (size_t)p->n_nodes, 0.0);
+            for (int i = 0; i < E; ++i) {
+                double *Mt = met_h.data() + 10 * p->noff[i];
+                element_metrics(tab.data(), el[i].n, p->xyz_h.data() + 3 * p->noff[i], Mt);
+                const int ne = el[i].n[0] * el[i].n[1] * el[i].n[2];
+                for (int t = 0; t < ne; ++t)
+                    if (!(Mt[9 * ne + t] > 0.0)) {
+                        destroy_plan(p);
+                        return fail(DG_EINVAL, "the map folds an element (non-positive Jacobian)");
+                    }
+            }
+            // scaled normals: minus side's Ja^d on the mortar, own outward s Ja^d on boundaries
+            fmo.assign(p->nfaces + 1, 0);
+            for (int fi = 0; fi < p->nfaces; ++fi) {
+                const Face &f = faces[fi];
+                const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+                if (f.bc != 0) {
+                    const int e = f.eL >= 0 ? f.eL : f.eR, s = f.eL >= 0 ? 1 : -1;
+                    const int32_t *n = el[e].n;
+                    const int ne = n[0] * n[1] * n[2], na = n[t1], nb = n[t2];
+                    const double *Mt = met_h.data() + 10 * p->noff[e];
+                    for (int m = 0; m < na * nb; ++m) {
+                        const int node = face_node_h(n, d, s, m % na, m / na);
+                        for (int c = 0; c < 3; ++c) fmet_h.push_back(s * Mt[(3 * d + c) * ne + node]);
+                    }
+                    fmo[fi + 1] = fmo[fi] + na * nb;
+                    continue;
+                }
+                const int32_t *nL = el[f.eL].n, *nR = el[f.eR].n;
+                const int aL = nL[t1], bL = nL[t2];
+                const int K1 = std::max(aL, (int)nR[t1]), K2 = std::max(bL, (int)nR[t2]);
+                const int neL = nL[0] * nL[1] * nL[2];
+                const double *Mt = met_h.data() + 10 * p->noff[f.eL];
+                const double *S1 = tab.data() + T_I + moff(K1 - 1, aL - 1);
+                const double *S2 = tab.data() + T_I + moff(K2 - 1, bL - 1);
+                for (int B = 0; B < K2; ++B)
+                    for (int A = 0; A < K1; ++A)
+                        for (int c = 0; c < 3; ++c) {
+                            double acc = 0.0;
+                            for (int b = 0; b < bL; ++b)
+                                for (int a = 0; a < aL; ++a)
+                                    acc += S1[A * aL + a] * S2[B * bL + b] *
+                                           Mt[(3 * d + c) * neL + face_node_h(nL, d, 1, a, b)];
+                            fmet_h.push_back(acc);
+                        }
+                fmo[fi + 1] = fmo[fi] + K1 * K2;
+            }
+        }
+    }
+
+    // sweep layout: combos per element; on box Euler plans isotropic elements (F <= 8)
+    // go to the fast path grouped by F and the others to the generic (p, c1, c2) work
+    // list; curved and Navier-Stokes plans take one task per (element, c1, c2, c3)
     p->combo_off.assign(E + 1, 0);
     std::vector<SweepTask> tasks;
+    std::vector<int4> ctasks;
     std::vector<std::vector<int32_t>> iso(NNMAX + 1);
     for (int i = 0; i < E; ++i) {
         int C[3];
         for (int d = 0; d < 3; ++d) C[d] = std::max(1, p->ord[3 * i + d] - 1);
         p->combo_off[i + 1] = p->combo_off[i] + (int64_t)C[0] * C[1] * C[2];
+        if (p->curved || p->ns) {
+            for (int c3 = 1; c3 <= C[2]; ++c3)
+                for (int c2 = 1; c2 <= C[1]; ++c2)
+                    for (int c1 = 1; c1 <= C[0]; ++c1) ctasks.push_back(make_int4(i, c1, c2, c3));
+            const int m1 = C[0] + 1, m2 = C[1] + 1, m3 = C[2] + 1, nc = m1 * m2 * m3;
+            const int f2 = el[i].n[1], f3 = el[i].n[2];
+            p->capA = std::max(p->capA, NFLD_SWEEP * std::max(m1 * f2 * f3, nc));
+            p->capB = std::max(p->capB, std::max(NFLD_SWEEP * m1 * m2 * f3, 10 * nc));
+            p->capS = std::max(p->capS, std::max(3 * NV * nc, 2 * WG));
+            continue;
+        }
         const int F = el[i].n[0];
         if (F == el[i].n[1] && F == el[i].n[2] && F <= 8) {
             iso[F].push_back(i);
@@ -304,13 +522,20 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
         iso_all.insert(iso_all.end(), iso[F].begin(), iso[F].end());
     }
 
+    p->nctasks = (int)ctasks.size();
+    std::vector<float> met32(met_h.begin(), met_h.end()), fmet32(fmet_h.begin(), fmet_h.end());
     if ((st = upload(&p->d_el, el)) || (st = upload(&p->d_faces, faces)) || (st = upload(&p->d_tiles, tiles)) ||
         (st = upload(&p->d_combo_off, p->combo_off)) || (st = upload(&p->d_tasks, tasks)) ||
-        (st = upload(&p->d_iso, iso_all)) || (st = upload(&p->d_wallx, wallx))) {
+        (st = upload(&p->d_iso, iso_all)) || (st = upload(&p->d_wallx, wallx)) ||
+        (st = upload(&p->d_ctasks, ctasks)) || (st = upload(&p->d_xyz, p->xyz_h)) ||
+        (st = upload(&p->d_met64, met_h)) || (st = upload(&p->d_met32, met32)) ||
+        (st = upload(&p->d_fmet64, fmet_h)) || (st = upload(&p->d_fmet32, fmet32)) || (st = upload(&p->d_fmo, fmo))) {
         destroy_plan(p);
         return st;
     }
-    if (hipMalloc(&p->d_ff, sizeof(double) * std::max<int64_t>(1, p->ff_len)) != hipSuccess ||
+    // the face buffer also carries the 15-value BR1 face data of curved Navier-Stokes plans
+    const int64_t ff_alloc = std::max<int64_t>(1, (p->curved && p->ns ? 3 : 1) * p->ff_len);
+    if (hipMalloc(&p->d_ff, sizeof(double) * ff_alloc) != hipSuccess ||
         hipMalloc((void **)&p->d_part, sizeof(double) * std::max(1, p->nwallx)) != hipSuccess ||
         hipMalloc((void **)&p->d_dudt, sizeof(double) * NV * p->n_nodes) != hipSuccess ||
         hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
@@ -325,7 +550,34 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan *o
 // face pass + element pass with the given epilogue
 template <typename T>
 dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s) {
-    const T *tab = std::is_same<T, double>::value ? (const T *)p->tabs.t64 : (const T *)p->tabs.t32;
+    const bool f64 = std::is_same<T, double>::value;
+    const T *tab = f64 ? (const T *)p->tabs.t64 : (const T *)p->tabs.t32;
+    if (p->curved) {
+        // curved elements: per-node metric terms, scaled face normals on the mortars
+        const T *met = f64 ? (const T *)p->d_met64 : (const T *)p->d_met32;
+        const T *fmet = f64 ? (const T *)p->d_fmet64 : (const T *)p->d_fmet32;
+        epi.met = met;
+        const T *grad = nullptr;
+        if (p->ns) {
+            for (size_t i = 0; i < p->classes.size(); ++i) {
+                const TileClass &c = p->classes[i];
+                HIP_TRY(launch_grad_curved<T>(p->d_faces, p->d_fmo, fmet, p->nfaces, p->d_tiles, c.first, c.count,
+                                              c.npt, i == 0, p->d_el, u, met, (T *)p->d_ff, (T *)p->d_grad, tab,
+                                              p->phys, epi.isolated, s));
+            }
+            grad = (const T *)p->d_grad;
+            epi.grad = p->d_grad;
+            epi.mu = p->phys.mu;
+            epi.kappa = p->phys.kappa;
+        }
+        if (!epi.isolated)
+            HIP_TRY(launch_face_curved<T>(p->d_faces, p->d_fmo, fmet, p->nfaces, p->d_el, u, grad, (T *)p->d_ff, tab,
+                                          p->phys, p->max_order, s));
+        for (const TileClass &c : p->classes)
+            HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)p->d_ff, tab,
+                                      p->geom, p->phys, epi, s));
+        return DG_OK;
+    }
     if (p->ns) {
         // BR1: solution trace, gradients, viscous face fluxes, then the element pass
         for (size_t i = 0; i < p->classes.size(); ++i) {
@@ -361,7 +613,7 @@ bool aligned(const void *x) { return ((uintptr_t)x & 15) == 0; }
 extern "C" {
 
 dg_status dg_plan_create(const dg_mesh_desc *mesh, const int32_t *orders_host, dg_plan *out) {
-    return build_plan(mesh, orders_host, out);
+    return build_plan(mesh, orders_host, nullptr, out);
 }
 
 dg_status dg_plan_create_coarse(dg_plan fine, const int32_t *coarse_orders_host, dg_plan *out) {
@@ -374,7 +626,7 @@ dg_status dg_plan_create_coarse(dg_plan fine, const int32_t *coarse_orders_host,
             if (nc < 1 || nc > nf) return fail(DG_EINVAL, "coarse orders must satisfy 1 <= Nc <= Nf");
         }
     dg_plan c = nullptr;
-    dg_status st = build_plan(&fine->mesh, coarse_orders_host, &c);
+    dg_status st = build_plan(&fine->mesh, coarse_orders_host, fine, &c);
     if (st) return st;
     c->parent = fine;
     std::vector<int32_t> fine_of(c->E);
@@ -411,7 +663,32 @@ dg_status dg_plan_layout(dg_plan p, int64_t *n_elems, int64_t *n_nodes, int64_t 
 
 dg_status dg_node_coords(dg_plan p, double *xyz, hipStream_t stream) {
     if (!p || !xyz) return fail(DG_EINVAL, "null argument");
+    if (p->d_xyz) {
+        HIP_TRY(hipMemcpyAsync(xyz, p->d_xyz, sizeof(double) * 3 * p->n_nodes, hipMemcpyDeviceToDevice, stream));
+        return DG_OK;
+    }
     HIP_TRY(launch_coords(p->d_el, p->E, p->mesh.nx, p->mesh.ny, p->tabs.t64, p->geom, xyz, stream));
+    return DG_OK;
+}
+
+dg_status dg_plan_metrics(dg_plan p, double *met, hipStream_t stream) {
+    if (!p || !met) return fail(DG_EINVAL, "null argument");
+    if (p->curved) {
+        HIP_TRY(hipMemcpyAsync(met, p->d_met64, sizeof(double) * 10 * p->n_nodes, hipMemcpyDeviceToDevice, stream));
+        return DG_OK;
+    }
+    // box elements: the constant metric terms, staged on the host
+    std::vector<double> h(10 * (size_t)p->n_nodes, 0.0);
+    for (int i = 0; i < p->E; ++i) {
+        const int64_t ne = p->noff[i + 1] - p->noff[i];
+        double *Mt = h.data() + 10 * p->noff[i];
+        for (int64_t t = 0; t < ne; ++t) {
+            for (int d = 0; d < 3; ++d) Mt[(3 * d + d) * ne + t] = p->geom.Ja[d];
+            Mt[9 * ne + t] = p->geom.J;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(met, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
     return DG_OK;
 }
 
@@ -436,6 +713,8 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
                           hipStream_t stream) {
     if (!fine || !coarse || !u) return fail(DG_EINVAL, "null argument");
     if (coarse->parent != fine) return fail(DG_EINVAL, "coarse plan was not built from this fine plan");
+    if (fine->curved && !isolated)
+        return fail(DG_EUNSUPPORTED, "on curved meshes the tau-estimate is the isolated one");
     if ((psi == nullptr) != (eta == nullptr)) return fail(DG_EINVAL, "psi and eta go together");
     if (!tau_new && !tau_trad && !norms && !eta) return DG_OK;
     if (!dudt) {
@@ -470,7 +749,8 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *t
                        hipStream_t stream) {
     if (!p || !u || !te_new || !te_trad) return fail(DG_EINVAL, "null argument");
     if (p->max_order > 8) return fail(DG_EUNSUPPORTED, "the sweep supports fine orders up to 8");
-    if (p->ns) return fail(DG_EUNSUPPORTED, "the sweep is implemented for the Euler equations");
+    if ((p->curved || p->ns) && p->max_order > 7)
+        return fail(DG_EUNSUPPORTED, "the sweep of curved and Navier-Stokes plans supports fine orders up to 7");
     if (!dudt) {
         EpiArgs epi{};
         epi.mode = EPI_RESIDUAL;
@@ -478,6 +758,11 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *t
         dg_status st = run_residual<double>(p, u, epi, stream);
         if (st) return st;
         dudt = p->d_dudt;
+    }
+    if (p->curved || p->ns) {
+        HIP_TRY(launch_sweep_curved(p->d_ctasks, p->nctasks, p->d_el, p->d_combo_off, u, dudt, p->d_xyz, p->tabs.t64,
+                                    p->phys, p->capA, p->capB, p->capS, p->ns ? 1 : 0, te_new, te_trad, stream));
+        return DG_OK;
     }
     for (int F = 2; F <= 8; ++F)
         if (p->iso_count[F])
@@ -531,6 +816,7 @@ dg_status dg_residual_vjp(dg_plan p, const double *u, const double *v, double *o
     if (out == u || out == v) return fail(DG_EINVAL, "out must not overlap u or v");
     if (form != DG_FORM_NEW && form != DG_FORM_TRAD) return fail(DG_EINVAL, "unknown form");
     if (p->ns) return fail(DG_EUNSUPPORTED, "the VJP is implemented for the Euler equations");
+    if (p->curved) return fail(DG_EUNSUPPORTED, "the VJP is implemented for box elements");
     for (size_t i = 0; i < p->classes.size(); ++i) {
         const TileClass &c = p->classes[i];
         HIP_TRY(launch_vjp(p->d_faces, p->nfaces, p->d_tiles, c.first, c.count, c.npt, p->d_el, u, v,
@@ -542,6 +828,7 @@ dg_status dg_residual_vjp(dg_plan p, const double *u, const double *v, double *o
 
 dg_status dg_functional(dg_plan p, const double *u, double *J, double *dJdu, hipStream_t stream) {
     if (!p || !u || !J) return fail(DG_EINVAL, "null argument");
+    if (p->curved) return fail(DG_EUNSUPPORTED, "the functional is implemented for box elements");
     HIP_TRY(launch_functional(p->d_faces, p->d_wallx, p->nwallx, p->d_el, u, p->tabs.t64, p->geom, p->mesh.gamma,
                               p->d_part, J, dJdu, (int64_t)NV * p->n_nodes, stream));
     return DG_OK;
@@ -737,6 +1024,7 @@ dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_bat
         if (!plans[i]) return fail(DG_EINVAL, "null plan in batch");
         if (plans[i]->max_order > 7) return fail(DG_EUNSUPPORTED, "batched launches support orders up to 7");
         if (plans[i]->ns) return fail(DG_EUNSUPPORTED, "batched launches run the Euler equations");
+        if (plans[i]->curved) return fail(DG_EUNSUPPORTED, "batched launches run box elements");
     }
     dg_batch b = new dg_batch_s();
     b->plans.assign(plans, plans + n);

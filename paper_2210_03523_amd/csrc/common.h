@@ -101,6 +101,7 @@ struct EpiArgs {
     double *eta;        // [E] sum of psic * tau_trad (tau, optional)
     const void *grad;   // Navier-Stokes: BR1 gradients [elem][3][5][node] (null for Euler)
     double mu, kappa;   // viscosity and heat conductivity
+    const void *met;    // curved elements: metric terms [elem][10][node] (Ja^1, Ja^2, Ja^3, J)
 };
 
 template <typename T>
@@ -172,6 +173,26 @@ hipError_t launch_ns_gradient(const Face *faces, int nfaces, const Tile *tiles, 
 template <typename T>
 hipError_t launch_ns_faces(const Face *faces, int nfaces, const ElemInfo *el, const T *u, const T *grad, T *ff,
                            const T *tab, Geom g, PhysParams ph, hipStream_t s);
+
+// Fields restricted per combination by the curved sweep: Q, dQ/dt, node coordinates.
+constexpr int NFLD_SWEEP = 2 * NV + 3;
+
+// Curved elements (k_curved.hip): face fluxes with per-face scaled normals (fmet, 3 values
+// per mortar / boundary-face node starting at node offset fmo[face]), the BR1 face data and
+// gradient pass, and the isolated sweep with per-combination coarse geometry.
+template <typename T>
+hipError_t launch_face_curved(const Face *faces, const int64_t *fmo, const T *fmet, int nfaces, const ElemInfo *el,
+                              const T *u, const T *grad, T *ff, const T *tab, PhysParams ph, int max_order,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_grad_curved(const Face *faces, const int64_t *fmo, const T *fmet, int nfaces, const Tile *tiles,
+                              int tile0, int ntiles, int npt, bool do_faces, const ElemInfo *el, const T *u,
+                              const T *met, T *fq, T *grad, const T *tab, PhysParams ph, int isolated,
+                              hipStream_t s);
+hipError_t launch_sweep_curved(const int4 *tasks, int ntasks, const ElemInfo *el, const int64_t *combo_off,
+                               const double *u, const double *dudt, const double *xyz, const double *tab,
+                               PhysParams ph, int capA, int capB, int capS, int viscous, double *te_new,
+                               double *te_trad, hipStream_t s);
 
 // Host tables (tables.cpp): fills T_TOT values.
 void build_tables(double *tab64, float *tab32);

@@ -270,7 +270,8 @@ hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems
 // ---------------------------------------------------------------------------- elements
 // One tile of elements, processed by one workgroup of WG lanes.
 // u is not __restrict__: the RK epilogue writes the stage update in place.
-template <typename T, int NPT>
+// CURVED: per-node metric terms (epi.met), contravariant fluxes Ja^d . f and per-node J.
+template <typename T, int NPT, bool CURVED = false>
 __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restrict__ el, const T *u,
                                           const T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
                                           const PhysParams &ph, const EpiArgs &epi, T (&sF)[NV][WG * NPT]) {
@@ -283,6 +284,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
     const int64_t fblk = fblock(E0.n);
 
     T q[NPT][NV], V[NPT][NV];
+    T M[CURVED ? NPT : 1][10];  // curved: Ja^1, Ja^2, Ja^3, J at the node
     int loc[NPT][3], le[NPT], nd[NPT];
     bool ok[NPT];
     const bool visc = epi.grad != nullptr;
@@ -302,25 +304,48 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
             q[k][v] = ok[k] ? u[base + v * npe + nd[k]] : T(1);
             V[k][v] = T(0);
         }
+        if (CURVED) {
+            const T *mp = (const T *)epi.met + (int64_t)10 * (E0.noff + (int64_t)le[k] * npe) + nd[k];
+#pragma unroll
+            for (int c = 0; c < 10; ++c) M[CURVED ? k : 0][c] = ok[k] ? mp[(int64_t)c * npe] : T(c == 9 ? 1 : 0);
+        }
     }
-    // total flux along d at this thread's k-th node: |Ja^d| (f^a_d - f^v_d)
+    // contravariant total flux along d at this thread's k-th node, Ja^d . (f^a - f^v):
+    // |Ja^d| (f^a_d - f^v_d) on box elements
     auto total_flux = [&](int k, int d, T f[NV]) {
-        flux_axis(q[k], d, gm1, f);
+        T G[15];
         if (visc && ok[k]) {
             const T *Gp = (const T *)epi.grad + (int64_t)3 * NV * (E0.noff + (int64_t)le[k] * npe) + nd[k];
-            T G[15], fv[NV];
 #pragma unroll
             for (int c = 0; c < 15; ++c) G[c] = Gp[(int64_t)c * npe];
+        }
+        if (CURVED) {
+            const T *m = M[CURVED ? k : 0];
+            const T n[3] = {m[3 * d], m[3 * d + 1], m[3 * d + 2]};
+            flux_n(q[k], n, gm1, f);
+            if (visc && ok[k]) {
+                T fv[NV];
+                viscous_n(q[k], G, n, gam, mu, kappa, fv);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) f[v] -= fv[v];
+            }
+            return;
+        }
+        flux_axis(q[k], d, gm1, f);
+        if (visc && ok[k]) {
+            T fv[NV];
             viscous_axis(q[k], G, d, gam, mu, kappa, fv);
 #pragma unroll
             for (int v = 0; v < NV; ++v) f[v] -= fv[v];
         }
+        const T Ja = (T)g.Ja[d];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) f[v] = Ja * f[v];
     };
     const int nn[3] = {n1, n2, n3};
     const int stride[3] = {1, n1, n1 * n2};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const T Ja = (T)g.Ja[d];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             T f[NV];
@@ -328,7 +353,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
             const int t = tid + k * WG;
             if (ok[k]) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) sF[v][t] = Ja * f[v];
+                for (int v = 0; v < NV; ++v) sF[v][t] = f[v];
             }
         }
         __syncthreads();
@@ -366,16 +391,15 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
                 const int fm = loc[k][t1] + na * loc[k][t2];
                 const T *fs = fb + fslot(E0.n, d, s);
                 const T iw = T(1) / tab[T_W + xoff(nd_ - 1)];
-                const T Ja = (T)g.Ja[d];
                 T f[NV];
                 total_flux(k, d, f);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) V[k][v] += (fs[v * na * nb + fm] - T(s) * Ja * f[v]) * iw;
+                for (int v = 0; v < NV; ++v) V[k][v] += (fs[v * na * nb + fm] - T(s) * f[v]) * iw;
             }
         }
     }
     // epilogue
-    const T invJ = (T)(1.0 / g.J);
+    const T invJbox = (T)(1.0 / g.J);
     T mx[NPT][3];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -383,6 +407,8 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
         mx[k][1] = T(0);
         mx[k][2] = T(0);
         if (!ok[k]) continue;
+        const T Jn = CURVED ? M[CURVED ? k : 0][9] : (T)g.J;
+        const T invJ = CURVED ? T(1) / Jn : invJbox;
         const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
         const T www = tab[T_W + xoff(n1 - 1) + loc[k][0]] * tab[T_W + xoff(n2 - 1) + loc[k][1]] *
                       tab[T_W + xoff(n3 - 1) + loc[k][2]];
@@ -409,7 +435,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
             const T *rd = (const T *)epi.rdc;
             T *tn = (T *)epi.out;
             T *tt = (T *)epi.out2;
-            const T Jw = (T)g.J * www;
+            const T Jw = Jn * www;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const int64_t x = base + v * npe + nd[k];
@@ -471,13 +497,13 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
     }
 }
 
-template <typename T, int NPT>
+template <typename T, int NPT, bool CURVED>
 __global__ __launch_bounds__(WG) void k_elem(const Tile *__restrict__ tiles, int tile0, int ntiles,
                                              const ElemInfo *__restrict__ el, const T *u,
                                              const T *__restrict__ ff, const T *__restrict__ tab, Geom g,
                                              PhysParams ph, EpiArgs epi) {
     __shared__ T sF[NV][WG * NPT];
-    elem_body<T, NPT>(tiles[tile0 + xcd_remap(blockIdx.x, ntiles)], el, u, ff, tab, g, ph, epi, sF);
+    elem_body<T, NPT, CURVED>(tiles[tile0 + xcd_remap(blockIdx.x, ntiles)], el, u, ff, tab, g, ph, epi, sF);
 }
 
 template <typename T>
@@ -485,12 +511,19 @@ hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, con
                           const T *fflux, const T *tab, Geom g, PhysParams ph, EpiArgs epi, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
     dim3 grid(ntiles), block(WG);
-    switch (npt) {
-        case 1: hipLaunchKernelGGL((k_elem<T, 1>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi); break;
-        case 2: hipLaunchKernelGGL((k_elem<T, 2>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi); break;
-        case 4: hipLaunchKernelGGL((k_elem<T, 4>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi); break;
+    const bool curved = epi.met != nullptr;
+#define DGT_ELEM(NP, CU) \
+    hipLaunchKernelGGL((k_elem<T, NP, CU>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi)
+    switch (npt * 2 + (curved ? 1 : 0)) {
+        case 2: DGT_ELEM(1, false); break;
+        case 3: DGT_ELEM(1, true); break;
+        case 4: DGT_ELEM(2, false); break;
+        case 5: DGT_ELEM(2, true); break;
+        case 8: DGT_ELEM(4, false); break;
+        case 9: DGT_ELEM(4, true); break;
         default: return hipErrorInvalidValue;
     }
+#undef DGT_ELEM
     return hipGetLastError();
 }
 
