@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 64-problem leg")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the curved Navier-Stokes (32x32x2) and adjoint (24^3) legs")
     ap.add_argument("--n", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 256 MiB device copy first (calibrates HBM byte counters)")
@@ -168,9 +170,20 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "flops_per_launch": flops_sweep},
+        # HBM fractions of the bandwidth-bound stages: algorithmic bytes (state in, result
+        # out; 80 B per fine node FP64, 40 B FP32; coupled tau adds 80 B per coarse node)
+        "roofline_stages": {
+            "unit": "fraction of 8 TB/s",
+            "residual_fp64": 80.0 * n_fine / (t_res64 * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "residual_fp32": 40.0 * n_fine / (t_res32 * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "coupled_tau": (80.0 * n_fine + 80.0 * cplan.n_nodes) / (np.mean(t_tau) * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        },
     }
     if not args.no_c5:
         out["batched"] = c5_leg(dg, torch, stream, steps=5, warmup=1, check=not args.no_cpu)
+    if not args.no_extra:
+        out["navier_stokes_curved"] = c3_leg(dg, torch, stream, check=not args.no_cpu)
+        out["adjoint"] = c4_leg(dg, torch, stream, check=not args.no_cpu)
     if not args.no_cpu:
         base, ref = cpu_baseline(mesh, fo, co, u_nat, n_fine, n_est, E)
         out["cpu_baseline"] = base
@@ -194,6 +207,111 @@ def main():
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out))
+
+
+def _timed(torch, stream, fn, reps, warmup=2):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def c3_leg(dg, torch, stream, check=True, dt=1e-5, nsteps=10):
+    """Navier-Stokes (BR1) on the sine-mapped 32 x 32 x 2 mesh, orders (Nx, Ny) U{2..6},
+    Nz = 1, 16 vortices: FP32 RK3 steps (graph replays), FP64 and FP32 residual rates, the
+    isolated FP64 sweep; errors of the FP32 steps and of the sweep against the oracle."""
+    mesh, orders, rng = wl.c3()
+    plan = dg.Plan(mesh, orders)
+    xyz = plan.to_natural(plan.node_coords(), nv=3)
+    u_nat = wl.c3_state(xyz, orders, mesh, rng)
+    n = plan.n_nodes
+    u64 = plan.to_plan(u_nat)
+    u32 = plan.to_plan(u_nat, dtype=torch.float32)
+    r64, r32 = torch.empty_like(u64), torch.empty_like(u32)
+    t64 = _timed(torch, stream, lambda: dg.residual(plan, u64, out=r64), 20)
+    t32 = _timed(torch, stream, lambda: dg.residual(plan, u32, out=r32), 20)
+    dudt = dg.residual(plan, u64)
+    n_est = int(plan.combo_offsets()[-1])
+    tsw = _timed(torch, stream, lambda: dg.tau_sweep(plan, u64, dudt), 10)
+    us = u32.clone()
+    g = torch.empty_like(us)
+    dg.rk3_step(plan, us, g, dt, 1)          # capture
+    us.copy_(u32)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    dg.rk3_step(plan, us, g, dt, nsteps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    trk = a.elapsed_time(b) / nsteps
+    res = {"workload": "NS Re=100 Ma=0.2 Pr=0.72, 32x32x2 sine-mapped hexes (geometry order 2,2,1), "
+                       "(Nx,Ny) U{2..6} per column, Nz=1, 16 vortices, seed 3",
+           "nodes": n, "sweep_combos": n_est,
+           "residual_fp64_ms": t64, "residual_fp64_gdof_s": n / (t64 * 1e-3) / 1e9,
+           "residual_fp32_ms": t32, "residual_fp32_gdof_s": n / (t32 * 1e-3) / 1e9,
+           "rk3_fp32_ms_per_step": trk, "rk3_fp32_gdof_steps_s": n / (trk * 1e-3) / 1e9,
+           "sweep_fp64_ms": tsw, "tau_estimates_per_s": n_est / (tsw * 1e-3)}
+    if check:
+        import oracle
+        A, B = (0.0, -5.0 / 9.0, -153.0 / 128.0), (1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0)
+        ref = u_nat.copy()
+        for _ in range(nsteps):
+            G = np.zeros_like(ref)
+            for k in range(3):
+                r = oracle.residual_ns(mesh, orders, ref, mesh["mu"], mesh["Pr"])
+                G = -dt * r if k == 0 else A[k] * G - dt * r
+                ref = ref + B[k] * G
+        d_ref = oracle.residual_ns(mesh, orders, u_nat, mesh["mu"], mesh["Pr"])
+        ten_r, _, _ = oracle.sweep_ns(mesh, orders, u_nat, d_ref, mesh["mu"], mesh["Pr"])
+        ten, _ = dg.tau_sweep(plan, u64, plan.to_plan(d_ref))
+        off = plan.combo_offsets()
+        got = np.concatenate([ten.cpu().numpy()[off[p]:off[p + 1]] for p in plan.inv_perm()])
+        s = _scale(mesh, u_nat, int(np.max(orders)), orders)
+        res["err_vs_oracle"] = {
+            "rk3_fp32": float(np.max(np.abs(plan.to_natural(us).astype(np.float64) - ref)) / np.max(np.abs(ref))),
+            "residual_fp64": _err(plan.to_natural(dudt), d_ref, s),
+            "sweep_te_new_fp64": _err(got, ten_r, s),
+            "measure": "rk3: max|u - u_oracle| / max|u_oracle| after 10 steps; others as in errors"}
+    return res
+
+
+def c4_leg(dg, torch, stream, check=True):
+    """Adjoint workload (24^3, N = 5, slip wall at x = 0, far field at x = 1): the residual
+    VJP and the wall functional; the VJP is checked by a central-difference dot test on
+    the oracle residual."""
+    mesh, orders = wl.c4()
+    plan = dg.Plan(mesh, orders)
+    xyz = plan.to_natural(plan.node_coords(), nv=3)
+    u_nat = wl.c4_state(xyz, orders)
+    n = plan.n_nodes
+    u = plan.to_plan(u_nat)
+    rng = np.random.default_rng(44)
+    v_nat = rng.normal(size=u_nat.shape)
+    v = plan.to_plan(v_nat)
+    out = torch.empty_like(u)
+    tv = _timed(torch, stream, lambda: dg.residual_vjp(plan, u, v), 10)
+    tf = _timed(torch, stream, lambda: dg.functional(plan, u), 10)
+    res = {"workload": "Euler 24^3 N=5, slip wall x=0, far field x=1, seed 4", "nodes": n,
+           "vjp_ms": tv, "vjp_gdof_s": n / (tv * 1e-3) / 1e9,
+           "vjp_hbm_frac": 120.0 * n / (tv * 1e-3) / 1e9 / PEAK_HBM_GBS,
+           "functional_ms": tf}
+    if check:
+        import oracle
+        w = rng.normal(size=u_nat.shape)
+        w *= 1.0 / np.max(np.abs(w))
+        eps = 1e-6
+        fd = (oracle.residual(mesh, orders, u_nat + eps * w) - oracle.residual(mesh, orders, u_nat - eps * w)) / (2 * eps)
+        jtv = plan.to_natural(dg.residual_vjp(plan, u, v))
+        lhs, rhs = float(v_nat @ fd), float(jtv @ w)
+        res["err_vs_oracle"] = {"dot_test_rel": abs(lhs - rhs) / abs(lhs),
+                                "measure": "|<v, (r(u+eps w) - r(u-eps w))/2eps> - <J^T v, w>| / |<v, ...>|, eps=1e-6"}
+    return res
 
 
 def c5_leg(dg, torch, stream, steps=5, warmup=1, check=True, dt=1e-4):
@@ -263,10 +381,15 @@ def _traffic(name):
     return float(kv["bytes_per_launch"])
 
 
-def _scale(mesh, u_nat, N):
+def _scale(mesh, u_nat, N, orders=None):
     """Scale of the cancelling terms of the residual, max |f| * |Ja| * ||D|| / J, with
-    ||D|| = N(N+1)/2 (the error measure of the parity tests)."""
-    q = u_nat.reshape(-1, 5, (N + 1) ** 3).transpose(1, 0, 2).reshape(5, -1)
+    ||D|| = N(N+1)/2 (the error measure of the parity tests); N the largest order,
+    orders (natural [E][3]) for a mixed-order state."""
+    if orders is None:
+        q = u_nat.reshape(-1, 5, (N + 1) ** 3).transpose(1, 0, 2).reshape(5, -1)
+    else:
+        offs = wl.node_offsets(orders)
+        q = np.concatenate([u_nat[5 * offs[e]:5 * offs[e + 1]].reshape(5, -1) for e in range(len(orders))], axis=1)
     g = mesh["gamma"]
     vel = q[1:4] / q[0]
     p = (g - 1) * (q[4] - 0.5 * q[0] * np.sum(vel * vel, axis=0))

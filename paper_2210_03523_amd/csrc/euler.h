@@ -12,9 +12,14 @@
 
 namespace dgt {
 
+// The direction index d selects register array elements: every function below is
+// written for a compile-time direction D, and the runtime-d entry points dispatch to
+// the three instances (a wave-uniform branch), so no private array is ever indexed by
+// a runtime value (which would place it in scratch memory).
+
 // Flux f_d(q) along the coordinate direction d (unit normal e_d).
-template <typename T>
-__device__ __forceinline__ void flux_axis(const T q[5], int d, T gm1, T f[5]) {
+template <int d, typename T>
+__device__ __forceinline__ void flux_axis_d(const T q[5], T gm1, T f[5]) {
     T ri = T(1) / q[0];
     T ud = q[1 + d] * ri;
     T p = gm1 * (q[4] - T(0.5) * ri * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]));
@@ -26,14 +31,20 @@ __device__ __forceinline__ void flux_axis(const T q[5], int d, T gm1, T f[5]) {
     f[4] = (q[4] + p) * ud;
 }
 
-// Numerical flux through a face with normal s * e_d (s = +-1): returns F . n.
 template <typename T>
-__device__ __forceinline__ void numflux_axis(const T qL[5], const T qR[5], int d, T s, T gamma, int kind,
-                                             T F[5]) {
+__device__ __forceinline__ void flux_axis(const T q[5], int d, T gm1, T f[5]) {
+    if (d == 0) flux_axis_d<0>(q, gm1, f);
+    else if (d == 1) flux_axis_d<1>(q, gm1, f);
+    else flux_axis_d<2>(q, gm1, f);
+}
+
+// Numerical flux through a face with normal s * e_d (s = +-1): returns F . n.
+template <int d, typename T>
+__device__ __forceinline__ void numflux_axis_d(const T qL[5], const T qR[5], T s, T gamma, int kind, T F[5]) {
     const T gm1 = gamma - T(1);
     T fL[5], fR[5];
-    flux_axis(qL, d, gm1, fL);
-    flux_axis(qR, d, gm1, fR);
+    flux_axis_d<d>(qL, gm1, fL);
+    flux_axis_d<d>(qR, gm1, fR);
     const T riL = T(1) / qL[0], riR = T(1) / qR[0];
     T uL[3] = {qL[1] * riL, qL[2] * riL, qL[3] * riL};
     T uR[3] = {qR[1] * riR, qR[2] * riR, qR[3] * riR};
@@ -78,6 +89,14 @@ __device__ __forceinline__ void numflux_axis(const T qL[5], const T qR[5], int d
     diss[4] = l1 * (Ht - c * un) + w2 * T(0.5) * q2 + w3 * utdut + l4 * (Ht + c * un);
 #pragma unroll
     for (int v = 0; v < 5; ++v) F[v] = s * T(0.5) * (fL[v] + fR[v]) - T(0.5) * diss[v];
+}
+
+template <typename T>
+__device__ __forceinline__ void numflux_axis(const T qL[5], const T qR[5], int d, T s, T gamma, int kind,
+                                             T F[5]) {
+    if (d == 0) numflux_axis_d<0>(qL, qR, s, gamma, kind, F);
+    else if (d == 1) numflux_axis_d<1>(qL, qR, s, gamma, kind, F);
+    else numflux_axis_d<2>(qL, qR, s, gamma, kind, F);
 }
 
 // Flux along an arbitrary vector n (not normalised): f(q) . n = sum_l n_l f_l(q), the
@@ -152,9 +171,8 @@ __device__ __forceinline__ void numflux_n(const T qL[5], const T qR[5], const T 
 // Viscous flux f^v_d(Q, G) of the Navier-Stokes equations along direction d
 // (BR1: G[l*5 + v] = d(conserved v)/dx_l): Stokes stress with constant mu and Fourier
 // heat flux kappa grad T on T = p/rho, kappa = mu gamma / ((gamma-1) Pr).
-template <typename T>
-__device__ __forceinline__ void viscous_axis(const T q[5], const T G[15], int d, T gamma, T mu, T kappa,
-                                             T f[5]) {
+template <int d, typename T>
+__device__ __forceinline__ void viscous_axis_d(const T q[5], const T G[15], T gamma, T mu, T kappa, T f[5]) {
     const T ri = T(1) / q[0];
     const T u[3] = {q[1] * ri, q[2] * ri, q[3] * ri};
     const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -179,6 +197,14 @@ __device__ __forceinline__ void viscous_axis(const T q[5], const T G[15], int d,
     f[2] = tau[1];
     f[3] = tau[2];
     f[4] = u[0] * tau[0] + u[1] * tau[1] + u[2] * tau[2] + kappa * dT[d];
+}
+
+template <typename T>
+__device__ __forceinline__ void viscous_axis(const T q[5], const T G[15], int d, T gamma, T mu, T kappa,
+                                             T f[5]) {
+    if (d == 0) viscous_axis_d<0>(q, G, gamma, mu, kappa, f);
+    else if (d == 1) viscous_axis_d<1>(q, G, gamma, mu, kappa, f);
+    else viscous_axis_d<2>(q, G, gamma, mu, kappa, f);
 }
 
 // Viscous flux along an arbitrary vector n: sum_l n_l f^v_l(Q, G) (same model).

@@ -98,17 +98,15 @@ __device__ __forceinline__ void from_mortar_node(const T (*F)[FN], int na, int n
 }  // namespace
 
 // ---------------------------------------------------------------------------- face flux
-template <typename T, int FN, bool VISC>
-__global__ __launch_bounds__(64) void k_face_curved(const Face *__restrict__ faces, const int64_t *__restrict__ fmo,
-                                                    const T *__restrict__ fmet, const ElemInfo *__restrict__ el,
-                                                    const T *__restrict__ u, const T *__restrict__ grad,
-                                                    T *__restrict__ ff, const T *__restrict__ tab, PhysParams ph) {
+// D: the face direction as a compile-time constant (a wave-uniform branch in the kernel),
+// so no register array is indexed at run time.
+template <typename T, int FN, bool VISC, int D>
+__device__ __forceinline__ void face_curved_d(const Face f, const T *__restrict__ mt, const ElemInfo *__restrict__ el,
+                                              const T *__restrict__ u, const T *__restrict__ grad,
+                                              T *__restrict__ ff, const T *__restrict__ tab, const PhysParams &ph,
+                                              T (*sL)[FN], T (*sR)[FN], T (*sF)[FN]) {
     constexpr int NF = VISC ? 4 * NV : NV;  // Q and, for Navier-Stokes, its three gradient components
-    __shared__ T sL[NF][FN], sR[NF][FN], sF[NV][FN];
-    const int fi = blockIdx.x;
-    const Face f = faces[fi];
-    const T *mt = fmet + 3 * fmo[fi];
-    const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    constexpr int d = D, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const T gam = (T)ph.gamma, mu = (T)ph.mu, kappa = (T)ph.kappa;
     const int lane = threadIdx.x;
     auto load = [&](const ElemInfo &E, int node, T *x) {
@@ -196,19 +194,30 @@ __global__ __launch_bounds__(64) void k_face_curved(const Face *__restrict__ fac
     }
 }
 
-// ---------------------------------------------------------------------------- BR1 face data
-// Output per own face node: 15 values (l*NV + v) at 3*E.foff + 3*fslot(E.n, d, s).
-template <typename T, int FN>
-__global__ __launch_bounds__(64) void k_face_avg_curved(const Face *__restrict__ faces,
-                                                        const int64_t *__restrict__ fmo, const T *__restrict__ fmet,
-                                                        const ElemInfo *__restrict__ el, const T *__restrict__ u,
-                                                        T *__restrict__ fq, const T *__restrict__ tab, PhysParams ph) {
-    constexpr int NP = 3 * NV;
-    __shared__ T sL[NV][FN], sR[NV][FN], sP[NP][FN];
+template <typename T, int FN, bool VISC>
+__global__ __launch_bounds__(64) void k_face_curved(const Face *__restrict__ faces, const int64_t *__restrict__ fmo,
+                                                    const T *__restrict__ fmet, const ElemInfo *__restrict__ el,
+                                                    const T *__restrict__ u, const T *__restrict__ grad,
+                                                    T *__restrict__ ff, const T *__restrict__ tab, PhysParams ph) {
+    constexpr int NF = VISC ? 4 * NV : NV;
+    __shared__ T sL[NF][FN], sR[NF][FN], sF[NV][FN];
     const int fi = blockIdx.x;
     const Face f = faces[fi];
     const T *mt = fmet + 3 * fmo[fi];
-    const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    if (f.d == 0) face_curved_d<T, FN, VISC, 0>(f, mt, el, u, grad, ff, tab, ph, sL, sR, sF);
+    else if (f.d == 1) face_curved_d<T, FN, VISC, 1>(f, mt, el, u, grad, ff, tab, ph, sL, sR, sF);
+    else face_curved_d<T, FN, VISC, 2>(f, mt, el, u, grad, ff, tab, ph, sL, sR, sF);
+}
+
+// ---------------------------------------------------------------------------- BR1 face data
+// Output per own face node: 15 values (l*NV + v) at 3*E.foff + 3*fslot(E.n, d, s).
+template <typename T, int FN, int D>
+__device__ __forceinline__ void face_avg_curved_d(const Face f, const T *__restrict__ mt,
+                                                  const ElemInfo *__restrict__ el, const T *__restrict__ u,
+                                                  T *__restrict__ fq, const T *__restrict__ tab, const PhysParams &ph,
+                                                  T (*sL)[FN], T (*sR)[FN], T (*sP)[FN]) {
+    constexpr int NP = 3 * NV;
+    constexpr int d = D, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const int lane = threadIdx.x;
     if (f.bc != 0) {
         const int e = f.eL >= 0 ? f.eL : f.eR;
@@ -274,6 +283,20 @@ __global__ __launch_bounds__(64) void k_face_avg_curved(const Face *__restrict__
             for (int c = 0; c < NP; ++c) out[c * na * nb + m] = sg * acc[c];
         }
     }
+}
+
+template <typename T, int FN>
+__global__ __launch_bounds__(64) void k_face_avg_curved(const Face *__restrict__ faces,
+                                                        const int64_t *__restrict__ fmo, const T *__restrict__ fmet,
+                                                        const ElemInfo *__restrict__ el, const T *__restrict__ u,
+                                                        T *__restrict__ fq, const T *__restrict__ tab, PhysParams ph) {
+    __shared__ T sL[NV][FN], sR[NV][FN], sP[3 * NV][FN];
+    const int fi = blockIdx.x;
+    const Face f = faces[fi];
+    const T *mt = fmet + 3 * fmo[fi];
+    if (f.d == 0) face_avg_curved_d<T, FN, 0>(f, mt, el, u, fq, tab, ph, sL, sR, sP);
+    else if (f.d == 1) face_avg_curved_d<T, FN, 1>(f, mt, el, u, fq, tab, ph, sL, sR, sP);
+    else face_avg_curved_d<T, FN, 2>(f, mt, el, u, fq, tab, ph, sL, sR, sP);
 }
 
 // ---------------------------------------------------------------------------- gradient pass

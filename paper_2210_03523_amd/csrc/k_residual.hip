@@ -58,11 +58,12 @@ struct FaceSmem {
 // MODE 0: outward Riemann flux F*_out (plus side negated).  MODE 1: the BR1 trace of the
 // solution, (Q_L + Q_R)/2 on the mortar projected back onto both sides (no sign, no
 // metric), the face input of the gradient pass.
-template <typename T, int FN, int MODE = 0>
-__device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restrict__ el, const T *__restrict__ u,
-                                          T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
-                                          const PhysParams &ph, FaceSmem<T, FN> &sm) {
-    const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+// D: the face direction as a compile-time constant (see face_body below).
+template <typename T, int FN, int MODE, int D>
+__device__ __forceinline__ void face_body_d(const Face f, const ElemInfo *__restrict__ el, const T *__restrict__ u,
+                                            T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
+                                            const PhysParams &ph, FaceSmem<T, FN> &sm) {
+    constexpr int d = D, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const T Ja = (T)g.Ja[d];
     const T gam = (T)ph.gamma;
     const int lane = threadIdx.x;
@@ -246,6 +247,18 @@ __device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restri
             for (int v = 0; v < NV; ++v) out[v * na * nb + m] = sg * acc[v];
         }
     }
+}
+
+// The face direction selects register-array elements all through the face body; it is
+// made a compile-time constant by a wave-uniform branch, so nothing is indexed at run
+// time (which would put the arrays in scratch memory).
+template <typename T, int FN, int MODE = 0>
+__device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restrict__ el, const T *__restrict__ u,
+                                          T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
+                                          const PhysParams &ph, FaceSmem<T, FN> &sm) {
+    if (f.d == 0) face_body_d<T, FN, MODE, 0>(f, el, u, ff, tab, g, ph, sm);
+    else if (f.d == 1) face_body_d<T, FN, MODE, 1>(f, el, u, ff, tab, g, ph, sm);
+    else face_body_d<T, FN, MODE, 2>(f, el, u, ff, tab, g, ph, sm);
 }
 
 template <typename T, int FN>
@@ -609,15 +622,13 @@ __global__ __launch_bounds__(WG) void k_elem_grad(const Tile *__restrict__ tiles
     }
 }
 
-template <typename T, int FN>
-__global__ __launch_bounds__(64) void k_face_ns(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
-                                                const T *__restrict__ u, const T *__restrict__ grad,
-                                                T *__restrict__ ff, const T *__restrict__ tab, Geom g,
-                                                PhysParams ph) {
+template <typename T, int FN, int D>
+__device__ __forceinline__ void face_ns_d(const Face f, const ElemInfo *__restrict__ el, const T *__restrict__ u,
+                                          const T *__restrict__ grad, T *__restrict__ ff,
+                                          const T *__restrict__ tab, const Geom &g, const PhysParams &ph,
+                                          T (*sL)[FN], T (*sR)[FN], T (*sF)[FN]) {
     constexpr int NF = 4 * NV;  // Q and its three gradient components
-    __shared__ T sL[NF][FN], sR[NF][FN], sF[NV][FN];
-    const Face f = faces[blockIdx.x];
-    const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    constexpr int d = D, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const T Ja = (T)g.Ja[d], gam = (T)ph.gamma, mu = (T)ph.mu, kappa = (T)ph.kappa;
     const int lane = threadIdx.x;
     auto load = [&](const ElemInfo &E, int node, T *x) {
@@ -723,6 +734,18 @@ __global__ __launch_bounds__(64) void k_face_ns(const Face *__restrict__ faces, 
             for (int v = 0; v < NV; ++v) out[v * na * nb + m] = sg * acc[v];
         }
     }
+}
+
+template <typename T, int FN>
+__global__ __launch_bounds__(64) void k_face_ns(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
+                                                const T *__restrict__ u, const T *__restrict__ grad,
+                                                T *__restrict__ ff, const T *__restrict__ tab, Geom g,
+                                                PhysParams ph) {
+    __shared__ T sL[4 * NV][FN], sR[4 * NV][FN], sF[NV][FN];
+    const Face f = faces[blockIdx.x];
+    if (f.d == 0) face_ns_d<T, FN, 0>(f, el, u, grad, ff, tab, g, ph, sL, sR, sF);
+    else if (f.d == 1) face_ns_d<T, FN, 1>(f, el, u, grad, ff, tab, g, ph, sL, sR, sF);
+    else face_ns_d<T, FN, 2>(f, el, u, grad, ff, tab, g, ph, sL, sR, sF);
 }
 
 template <typename T>

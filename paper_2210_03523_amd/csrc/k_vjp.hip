@@ -42,15 +42,16 @@ __device__ __forceinline__ double form_weight(const ElemInfo &E, int node, const
 }
 
 // ---------------------------------------------------------------------------- faces
-__global__ __launch_bounds__(64) void k_face_vjp(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
-                                                 const double *__restrict__ u, const double *__restrict__ v,
-                                                 double *__restrict__ fa, const double *__restrict__ tab, Geom g,
-                                                 PhysParams ph, int form) {
-    __shared__ double sQL[NV][NNMAX * NNMAX], sQR[NV][NNMAX * NNMAX];
-    __shared__ double sLL[NV][NNMAX * NNMAX], sLR[NV][NNMAX * NNMAX];
-    __shared__ double sAL[NV][NNMAX * NNMAX], sAR[NV][NNMAX * NNMAX];
-    const Face f = faces[blockIdx.x];
-    const int d = f.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+// D: the face direction as a compile-time constant (a wave-uniform branch in the kernel),
+// so no register array is indexed at run time.
+constexpr int FNV = NNMAX * NNMAX;
+template <int D>
+__device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restrict__ el, const double *__restrict__ u,
+                                           const double *__restrict__ v, double *__restrict__ fa,
+                                           const double *__restrict__ tab, const Geom &g, const PhysParams &ph,
+                                           int form, double (*sQL)[FNV], double (*sQR)[FNV], double (*sLL)[FNV],
+                                           double (*sLR)[FNV], double (*sAL)[FNV], double (*sAR)[FNV]) {
+    constexpr int d = D, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const double Ja = g.Ja[d], invJ = 1.0 / g.J;
     const int lane = threadIdx.x;
 
@@ -64,24 +65,31 @@ __global__ __launch_bounds__(64) void k_face_vjp(const Face *__restrict__ faces,
         for (int m = lane; m < na * nb; m += 64) {
             const int node = vjp_face_node(E.n, d, s, m % na, m / na);
             const double c = form_weight(E, node, tab, form, invJ) * iw;
-            Dual<5> qd[NV], qg[NV], F[NV];
-            double lam[NV];
+            double q0[NV], lam[NV];
 #pragma unroll
             for (int k = 0; k < NV; ++k) {
-                qd[k] = Dual<5>(u[NV * E.noff + k * ne + node]);
-                qd[k].d[k] = 1.0;
+                q0[k] = u[NV * E.noff + k * ne + node];
                 lam[k] = c * v[NV * E.noff + k * ne + node];
             }
+            // lam^T dF/dq of the boundary flux (the ghost depends on q for walls), one
+            // direction per forward-mode pass
+#pragma unroll 1
+            for (int j = 0; j < NV; ++j) {
+                const int i0 = j;
+                Dual<1> qd[NV], qg[NV], F[NV];
 #pragma unroll
-            for (int k = 0; k < NV; ++k) qg[k] = f.bc == 1 ? qd[k] : Dual<5>(ph.qfar[k]);
-            if (f.bc == 1) qg[1 + d] = -qd[1 + d];
-            numflux_axis(qd, qg, d, Dual<5>((double)s), Dual<5>(ph.gamma), ph.flux, F);
+                for (int k = 0; k < NV; ++k) {
+                    qd[k] = Dual<1>(q0[k]);
+                    qd[k].d[0] = k == i0 ? 1.0 : 0.0;
+                }
 #pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                double acc = 0.0;
+                for (int k = 0; k < NV; ++k) qg[k] = f.bc == 1 ? qd[k] : Dual<1>(ph.qfar[k]);
+                if (f.bc == 1) qg[1 + d] = -qd[1 + d];
+                numflux_axis(qd, qg, d, Dual<1>((double)s), Dual<1>(ph.gamma), ph.flux, F);
+                double a0 = 0.0;
 #pragma unroll
-                for (int w = 0; w < NV; ++w) acc += lam[w] * F[w].d[k];
-                out[k * na * nb + m] = Ja * acc;
+                for (int w = 0; w < NV; ++w) a0 += lam[w] * F[w].d[0];
+                out[i0 * na * nb + m] = Ja * a0;
             }
         }
         return;
@@ -116,12 +124,13 @@ __global__ __launch_bounds__(64) void k_face_vjp(const Face *__restrict__ faces,
         const int A = m % K1, B = m / K1;
         double qL[NV], qR[NV], gK[NV];
         // mortar traces (forward interpolation) and the mortar adjoint weight
-        // gK = P_L^T lambda_L - P_R^T lambda_R
+        // gK = P_L^T lambda_L - P_R^T lambda_R (unrolled: q and gK stay in registers)
+#pragma unroll
         for (int side = 0; side < 2; ++side) {
             const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
             const bool conf = side == 0 ? confL : confR;
-            double(*sQ)[NNMAX * NNMAX] = side == 0 ? sQL : sQR;
-            double(*sL)[NNMAX * NNMAX] = side == 0 ? sLL : sLR;
+            double(*sQ)[FNV] = side == 0 ? sQL : sQR;
+            double(*sL)[FNV] = side == 0 ? sLL : sLR;
             double *q = side == 0 ? qL : qR;
             const double sg = side == 0 ? 1.0 : -1.0;
             if (conf) {
@@ -160,25 +169,26 @@ __global__ __launch_bounds__(64) void k_face_vjp(const Face *__restrict__ faces,
                 gK[k] = (side == 0 ? 0.0 : gK[k]) + sg * ga[k];
             }
         }
-        Dual<10> dl[NV], dr[NV], F[NV];
+        // gK^T dF/dq for the 10 inputs (q_L then q_R), one direction per forward-mode
+        // pass: single-direction duals keep the Roe flux in registers
+#pragma unroll 1
+        for (int j = 0; j < 2 * NV; ++j) {
+            const int i0 = j;
+            Dual<1> dl[NV], dr[NV], F[NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            dl[k] = Dual<10>(qL[k]);
-            dl[k].d[k] = 1.0;
-            dr[k] = Dual<10>(qR[k]);
-            dr[k].d[5 + k] = 1.0;
-        }
-        numflux_axis(dl, dr, d, Dual<10>(1.0), Dual<10>(ph.gamma), ph.flux, F);
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double al = 0.0, ar = 0.0;
-#pragma unroll
-            for (int w = 0; w < NV; ++w) {
-                al += gK[w] * F[w].d[k];
-                ar += gK[w] * F[w].d[5 + k];
+            for (int k = 0; k < NV; ++k) {
+                dl[k] = Dual<1>(qL[k]);
+                dr[k] = Dual<1>(qR[k]);
+                dl[k].d[0] = k == i0 ? 1.0 : 0.0;
+                dr[k].d[0] = NV + k == i0 ? 1.0 : 0.0;
             }
-            sAL[k][m] = Ja * al;
-            sAR[k][m] = Ja * ar;
+            numflux_axis(dl, dr, d, Dual<1>(1.0), Dual<1>(ph.gamma), ph.flux, F);
+            double a0 = 0.0;
+#pragma unroll
+            for (int w = 0; w < NV; ++w) a0 += gK[w] * F[w].d[0];
+            // the direction index is a loop variable: write to LDS, not a register array
+            if (i0 < NV) sAL[i0][m] = Ja * a0;
+            else sAR[i0 - NV][m] = Ja * a0;
         }
     }
     __syncthreads();
@@ -187,7 +197,7 @@ __global__ __launch_bounds__(64) void k_face_vjp(const Face *__restrict__ faces,
         const ElemInfo &E = side == 0 ? L : R;
         const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
         const bool conf = side == 0 ? confL : confR;
-        double(*sA)[NNMAX * NNMAX] = side == 0 ? sAL : sAR;
+        double(*sA)[FNV] = side == 0 ? sAL : sAR;
         double *out = fa + E.foff + fslot(E.n, d, side == 0 ? 1 : -1);
         const double *S1 = tab + T_I + moff(K1 - 1, na - 1);
         const double *S2 = tab + T_I + moff(K2 - 1, nb - 1);
@@ -214,6 +224,17 @@ __global__ __launch_bounds__(64) void k_face_vjp(const Face *__restrict__ faces,
             for (int k = 0; k < NV; ++k) out[k * na * nb + m] = acc[k];
         }
     }
+}
+
+__global__ __launch_bounds__(64) void k_face_vjp(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
+                                                 const double *__restrict__ u, const double *__restrict__ v,
+                                                 double *__restrict__ fa, const double *__restrict__ tab, Geom g,
+                                                 PhysParams ph, int form) {
+    __shared__ double sQL[NV][FNV], sQR[NV][FNV], sLL[NV][FNV], sLR[NV][FNV], sAL[NV][FNV], sAR[NV][FNV];
+    const Face f = faces[blockIdx.x];
+    if (f.d == 0) face_vjp_d<0>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR);
+    else if (f.d == 1) face_vjp_d<1>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR);
+    else face_vjp_d<2>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR);
 }
 
 // ---------------------------------------------------------------------------- elements
