@@ -117,6 +117,8 @@ struct dg_plan_s {
     // sweep of curved and Navier-Stokes plans: one task per (element, c1, c2, c3)
     int4 *d_ctasks = nullptr;
     int nctasks = 0, capA = 0, capB = 0, capS = 0;
+    // restriction from the fine plan (coarse plans): LDS staging capacities
+    int rcapA = 0, rcapB = 0;
     // x-force functional: boundary faces on slip walls normal to x, and their partial sums
     int32_t *d_wallx = nullptr;
     int nwallx = 0;
@@ -630,7 +632,13 @@ dg_status dg_plan_create_coarse(dg_plan fine, const int32_t *coarse_orders_host,
     if (st) return st;
     c->parent = fine;
     std::vector<int32_t> fine_of(c->E);
-    for (int i = 0; i < c->E; ++i) fine_of[i] = (int32_t)fine->inv[c->perm[i]];
+    for (int i = 0; i < c->E; ++i) {
+        fine_of[i] = (int32_t)fine->inv[c->perm[i]];
+        const int32_t *of = fine->ord.data() + 3 * fine_of[i], *oc = c->ord.data() + 3 * i;
+        c->rcapA = std::max(c->rcapA, NV * (oc[0] + 1) * (of[1] + 1) * (of[2] + 1));
+        c->rcapB = std::max(c->rcapB, NV * std::max((oc[0] + 1) * (oc[1] + 1) * (of[2] + 1),
+                                                    (of[0] + 1) * (of[1] + 1) * (of[2] + 1)));
+    }
     if ((st = upload(&c->d_fine_of, fine_of))) {
         destroy_plan(c);
         return st;
@@ -726,7 +734,8 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
         dudt = fine->d_dudt;
     }
     HIP_TRY(launch_restrict(coarse->d_fine_of, coarse->E, coarse->d_el, fine->d_el, u, dudt, psi, coarse->d_uc,
-                            coarse->d_rdc, coarse->d_psic, fine->tabs.t64, stream));
+                            coarse->d_rdc, coarse->d_psic, fine->tabs.t64, coarse->rcapA, coarse->rcapB,
+                            stream));
     EpiArgs epi{};
     epi.mode = EPI_TAU;
     epi.isolated = isolated ? 1 : 0;

@@ -108,9 +108,11 @@ template <typename T>
 hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, const ElemInfo *elems, const T *u,
                           const T *fflux, const T *tab, Geom g, PhysParams ph, EpiArgs epi, hipStream_t s);
 
+// capA, capB: LDS capacities (doubles) of the two staging buffers, 5 c1 f2 f3 and
+// 5 max(c1 c2 f3, f1 f2 f3) maximised over the coarse plan's elements.
 hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
                            const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
-                           double *psic, const double *tab, hipStream_t s);
+                           double *psic, const double *tab, int capA, int capB, hipStream_t s);
 
 hipError_t launch_vjp(const Face *faces, int nfaces, const Tile *tiles, int tile0, int ntiles, int npt,
                       const ElemInfo *el, const double *u, const double *v, double *fa, double *out,

@@ -307,10 +307,17 @@ __global__ __launch_bounds__(WG) void k_elem_grad_curved(const Tile *__restrict_
                                                          T *__restrict__ grad, const T *__restrict__ tab,
                                                          int isolated) {
     __shared__ T sQ[NV][WG * NPT];
+    __shared__ T sD[3 * NNMAX * NNMAX];  // the tile's derivative matrices (per-lane rows)
     const int tid = threadIdx.x;
     const Tile tl = tiles[tile0 + blockIdx.x];
     const ElemInfo E0 = el[tl.first];
     const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
+    {
+        const int ns[3] = {n1, n2, n3};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            for (int t = tid; t < ns[d] * ns[d]; t += WG) sD[d * NNMAX * NNMAX + t] = tab[T_D + doff(ns[d] - 1) + t];
+    }
     const int npe = n1 * n2 * n3, total = tl.count * npe;
     const int64_t fblk = fblock(E0.n);
     const int nn[3] = {n1, n2, n3};
@@ -355,7 +362,7 @@ __global__ __launch_bounds__(WG) void k_elem_grad_curved(const Tile *__restrict_
                 if (!ok[k]) continue;
                 const int t = tid + k * WG;
                 const int id = loc[k][d], nl = nn[d];
-                const T *Drow = tab + T_D + doff(nl - 1) + id * nl;
+                const T *Drow = sD + d * NNMAX * NNMAX + id * nl;
                 const int tb = t - id * stride[d];
                 for (int m = 0; m < nl; ++m) {
                     const T dm = Drow[m];

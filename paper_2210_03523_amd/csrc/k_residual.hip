@@ -284,13 +284,22 @@ hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems
 // One tile of elements, processed by one workgroup of WG lanes.
 // u is not __restrict__: the RK epilogue writes the stage update in place.
 // CURVED: per-node metric terms (epi.met), contravariant fluxes Ja^d . f and per-node J.
+// sD (LDS, 3 NNMAX^2): the tile's derivative matrices, staged so that the per-lane rows are
+// read from LDS rather than through vector memory loads.
 template <typename T, int NPT, bool CURVED = false>
 __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restrict__ el, const T *u,
                                           const T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
-                                          const PhysParams &ph, const EpiArgs &epi, T (&sF)[NV][WG * NPT]) {
+                                          const PhysParams &ph, const EpiArgs &epi, T (&sF)[NV][WG * NPT],
+                                          T *sD) {
     const int tid = threadIdx.x;
     const ElemInfo E0 = el[tl.first];
     const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
+    {
+        const int ns[3] = {n1, n2, n3};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            for (int t = tid; t < ns[d] * ns[d]; t += WG) sD[d * NNMAX * NNMAX + t] = tab[T_D + doff(ns[d] - 1) + t];
+    }  // ordered before the first read by the barrier after the first flux staging
     const int npe = n1 * n2 * n3;
     const int total = tl.count * npe;
     const T gm1 = (T)(ph.gamma - 1.0);
@@ -371,7 +380,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
         }
         __syncthreads();
         const int nd_ = nn[d];
-        const T *Dm = tab + T_D + doff(nd_ - 1);
+        const T *Dm = sD + d * NNMAX * NNMAX;
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             if (!ok[k]) continue;
@@ -516,7 +525,8 @@ __global__ __launch_bounds__(WG) void k_elem(const Tile *__restrict__ tiles, int
                                              const T *__restrict__ ff, const T *__restrict__ tab, Geom g,
                                              PhysParams ph, EpiArgs epi) {
     __shared__ T sF[NV][WG * NPT];
-    elem_body<T, NPT, CURVED>(tiles[tile0 + xcd_remap(blockIdx.x, ntiles)], el, u, ff, tab, g, ph, epi, sF);
+    __shared__ T sD[3 * NNMAX * NNMAX];
+    elem_body<T, NPT, CURVED>(tiles[tile0 + xcd_remap(blockIdx.x, ntiles)], el, u, ff, tab, g, ph, epi, sF, sD);
 }
 
 template <typename T>
@@ -561,10 +571,17 @@ __global__ __launch_bounds__(WG) void k_elem_grad(const Tile *__restrict__ tiles
                                                   const T *__restrict__ fq, T *__restrict__ grad,
                                                   const T *__restrict__ tab, Geom g, int isolated) {
     __shared__ T sQ[NV][WG * NPT];
+    __shared__ T sD[3 * NNMAX * NNMAX];  // the tile's derivative matrices (per-lane rows)
     const int tid = threadIdx.x;
     const Tile tl = tiles[tile0 + xcd_remap(blockIdx.x, ntiles)];
     const ElemInfo E0 = el[tl.first];
     const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
+    {
+        const int ns[3] = {n1, n2, n3};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            for (int t = tid; t < ns[d] * ns[d]; t += WG) sD[d * NNMAX * NNMAX + t] = tab[T_D + doff(ns[d] - 1) + t];
+    }
     const int npe = n1 * n2 * n3, total = tl.count * npe;
     const int64_t fblk = fblock(E0.n);
     const int nn[3] = {n1, n2, n3};
@@ -597,7 +614,7 @@ __global__ __launch_bounds__(WG) void k_elem_grad(const Tile *__restrict__ tiles
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             const int id = loc[k][l], nl = nn[l];
-            const T *Drow = tab + T_D + doff(nl - 1) + id * nl;
+            const T *Drow = sD + l * NNMAX * NNMAX + id * nl;
             const int tb = t - id * stride[l];
             T G[NV] = {T(0), T(0), T(0), T(0), T(0)};
             for (int m = 0; m < nl; ++m) {
@@ -807,13 +824,14 @@ __global__ __launch_bounds__(WG) void k_elem_batch(const BatchTile *__restrict__
                                                    const ProbDesc<T> *__restrict__ probs, const T *__restrict__ tab,
                                                    EpiArgs epi0) {
     __shared__ T sF[NV][WG * NPT];
+    __shared__ T sD[3 * NNMAX * NNMAX];
     for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const BatchTile bt = tiles[i];
         const ProbDesc<T> pd = probs[bt.prob];
         EpiArgs epi = epi0;
         epi.out = pd.out;
         epi.g = pd.g;
-        elem_body<T, NPT>(Tile{bt.first, bt.count}, pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, epi, sF);
+        elem_body<T, NPT>(Tile{bt.first, bt.count}, pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, epi, sF, sD);
         __syncthreads();
     }
 }

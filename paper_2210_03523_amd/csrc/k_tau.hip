@@ -25,62 +25,91 @@ __device__ __forceinline__ int xcd_remap_t(int bid, int G) {
 }
 
 // ---------------------------------------------------------------------------- restriction
-__global__ __launch_bounds__(256) void k_restrict(const int32_t *__restrict__ fine_of,
-                                                  const ElemInfo *__restrict__ cel,
-                                                  const ElemInfo *__restrict__ fel, const double *__restrict__ u,
-                                                  const double *__restrict__ dudt, const double *__restrict__ psi,
-                                                  double *__restrict__ uc, double *__restrict__ rdc,
-                                                  double *__restrict__ psic, const double *__restrict__ tab) {
-    __shared__ double sA[NNMAX * NNMAX * NNMAX];
-    __shared__ double sB[NNMAX * NNMAX * NNMAX];
-    const int p = blockIdx.x;
+// One workgroup per coarse element.  The three interpolation matrices are staged into
+// LDS first (their rows vary across lanes, so read from global memory every FMA would
+// wait on a vector load); per field (Q, dQ/dt, optionally psi) the fine element block
+// is staged with coalesced loads, then the three sum-factorisation passes run over all
+// five variables at once.  Dynamic LDS: sI [I1 | I2 | I3], sA [5][c1][f2 f3],
+// sB [5][f1 f2 f3] (the staged block) and later [5][c1 c2][f3].
+constexpr int RS_WG = 256;
+constexpr int RS_TAB = 3 * NNMAX * NNMAX;
+
+__global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ fine_of,
+                                                    const ElemInfo *__restrict__ cel,
+                                                    const ElemInfo *__restrict__ fel, const double *__restrict__ u,
+                                                    const double *__restrict__ dudt, const double *__restrict__ psi,
+                                                    double *__restrict__ uc, double *__restrict__ rdc,
+                                                    double *__restrict__ psic, const double *__restrict__ tab,
+                                                    int capA) {
+    extern __shared__ double lds[];
+    double *sI = lds, *sA = lds + RS_TAB, *sB = lds + RS_TAB + capA;
+    const int p = xcd_remap_t(blockIdx.x, gridDim.x);
     const ElemInfo C = cel[p];
     const ElemInfo F = fel[fine_of[p]];
     const int f1 = F.n[0], f2 = F.n[1], f3 = F.n[2], nef = f1 * f2 * f3;
     const int c1 = C.n[0], c2 = C.n[1], c3 = C.n[2], nec = c1 * c2 * c3;
-    const double *I1 = tab + T_I + moff(c1 - 1, f1 - 1);
-    const double *I2 = tab + T_I + moff(c2 - 1, f2 - 1);
-    const double *I3 = tab + T_I + moff(c3 - 1, f3 - 1);
+    const int tid = threadIdx.x;
+    double *I1 = sI, *I2 = sI + c1 * f1, *I3 = I2 + c2 * f2;
+    {
+        const double *g1 = tab + T_I + moff(c1 - 1, f1 - 1), *g2 = tab + T_I + moff(c2 - 1, f2 - 1);
+        const double *g3 = tab + T_I + moff(c3 - 1, f3 - 1);
+        for (int t = tid; t < c1 * f1; t += RS_WG) I1[t] = g1[t];
+        for (int t = tid; t < c2 * f2; t += RS_WG) I2[t] = g2[t];
+        for (int t = tid; t < c3 * f3; t += RS_WG) I3[t] = g3[t];
+    }
+    const int nA = c1 * f2 * f3, nB = c1 * c2 * f3;
     const int nfield = psi ? 3 : 2;
     for (int field = 0; field < nfield; ++field) {
         const double *src = (field == 0 ? u : field == 1 ? dudt : psi) + NV * F.noff;
         double *dst = (field == 0 ? uc : field == 1 ? rdc : psic) + NV * C.noff;
-        for (int v = 0; v < NV; ++v) {
-            // x: sA[a + c1*(j + f2*k)] = sum_i I1[a,i] Q[i + f1*(j + f2*k)]
-            for (int t = threadIdx.x; t < c1 * f2 * f3; t += blockDim.x) {
-                const int a = t % c1, jk = t / c1;
-                const double *row = src + v * nef + f1 * jk;
-                double acc = 0.0;
-                for (int i = 0; i < f1; ++i) acc += I1[a * f1 + i] * row[i];
-                sA[t] = acc;
-            }
-            __syncthreads();
-            // y: sB[a + c1*(b + c2*k)] = sum_j I2[b,j] sA[a + c1*(j + f2*k)]
-            for (int t = threadIdx.x; t < c1 * c2 * f3; t += blockDim.x) {
-                const int a = t % c1, b = (t / c1) % c2, k = t / (c1 * c2);
-                double acc = 0.0;
-                for (int j = 0; j < f2; ++j) acc += I2[b * f2 + j] * sA[a + c1 * (j + f2 * k)];
-                sB[t] = acc;
-            }
-            __syncthreads();
-            // z
-            for (int t = threadIdx.x; t < nec; t += blockDim.x) {
-                const int ab = t % (c1 * c2), c = t / (c1 * c2);
-                double acc = 0.0;
-                for (int k = 0; k < f3; ++k) acc += I3[c * f3 + k] * sB[ab + c1 * c2 * k];
-                dst[v * nec + t] = acc;
-            }
-            __syncthreads();
+        // stage the fine block (the previous field's z-pass has finished reading sB)
+        if (field > 0) __syncthreads();
+        for (int t = tid; t < NV * nef; t += RS_WG) sB[t] = src[t];
+        __syncthreads();
+        // x: sA[v][a + c1 jk] = sum_i I1[a,i] Q_v[i + f1 jk]
+        for (int t = tid; t < NV * nA; t += RS_WG) {
+            const int v = t / nA, r = t - v * nA, a = r % c1, jk = r / c1;
+            const double *row = sB + v * nef + f1 * jk;
+            const double *w = I1 + a * f1;
+            double acc = 0.0;
+            for (int i = 0; i < f1; ++i) acc += w[i] * row[i];
+            sA[t] = acc;
+        }
+        __syncthreads();
+        // y: sB[v][a + c1 (b + c2 k)] = sum_j I2[b,j] sA[v][a + c1 (j + f2 k)]
+        for (int t = tid; t < NV * nB; t += RS_WG) {
+            const int v = t / nB, r = t - v * nB, a = r % c1, b = (r / c1) % c2, k = r / (c1 * c2);
+            const double *x = sA + v * nA + a + c1 * f2 * k;
+            const double *w = I2 + b * f2;
+            double acc = 0.0;
+            for (int j = 0; j < f2; ++j) acc += w[j] * x[c1 * j];
+            sB[t] = acc;
+        }
+        __syncthreads();
+        // z: straight to the coarse plan layout
+        for (int t = tid; t < NV * nec; t += RS_WG) {
+            const int v = t / nec, r = t - v * nec, ab = r % (c1 * c2), c = r / (c1 * c2);
+            const double *x = sB + v * nB + ab;
+            const double *w = I3 + c * f3;
+            double acc = 0.0;
+            for (int k = 0; k < f3; ++k) acc += w[k] * x[c1 * c2 * k];
+            dst[t] = acc;
         }
     }
 }
 
 hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
                            const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
-                           double *psic, const double *tab, hipStream_t s) {
+                           double *psic, const double *tab, int capA, int capB, hipStream_t s) {
     if (ncoarse == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_restrict, dim3(ncoarse), dim3(256), 0, s, fine_of, celems, felems, u, dudt, psi, uc, rdc,
-                       psic, tab);
+    const size_t lds = sizeof(double) * (size_t)(RS_TAB + capA + capB);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_restrict, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_restrict, dim3(ncoarse), dim3(RS_WG), lds, s, fine_of, celems, felems, u, dudt, psi, uc,
+                       rdc, psic, tab, capA);
     return hipGetLastError();
 }
 

@@ -245,10 +245,17 @@ __global__ __launch_bounds__(WG) void k_elem_vjp(const Tile *__restrict__ tiles,
                                                  double *__restrict__ out, const double *__restrict__ tab, Geom g,
                                                  PhysParams ph, int form, int isolated) {
     __shared__ double sV[NV][WG * NPT];
+    __shared__ double sD[3 * NNMAX * NNMAX];  // the tile's derivative matrices (per-lane columns)
     const int tid = threadIdx.x;
     const Tile tl = tiles[tile0 + remap8(blockIdx.x, ntiles)];
     const ElemInfo E0 = el[tl.first];
     const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
+    {
+        const int ns[3] = {n1, n2, n3};
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            for (int t = tid; t < ns[d] * ns[d]; t += WG) sD[d * NNMAX * NNMAX + t] = tab[T_D + doff(ns[d] - 1) + t];
+    }
     const int npe = n1 * n2 * n3, total = tl.count * npe;
     const int64_t fblk = fblock(E0.n);
     const double invJ = 1.0 / g.J, gm1 = ph.gamma - 1.0;
@@ -286,7 +293,7 @@ __global__ __launch_bounds__(WG) void k_elem_vjp(const Tile *__restrict__ tiles,
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const int id = loc[k][d], nd_ = nn[d];
-            const double *Dm = tab + T_D + doff(nd_ - 1);
+            const double *Dm = sD + d * NNMAX * NNMAX;
             const int tb = t - id * stride[d];
             double y[NV] = {0, 0, 0, 0, 0};
             for (int m = 0; m < nd_; ++m) {
