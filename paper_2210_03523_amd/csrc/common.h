@@ -30,6 +30,15 @@ constexpr int T_I = T_D + DTOT;                 // I^{A<-B}: samples order-B bas
 constexpr int T_P = T_I + MTOT;                 // P^{A<-B}: L2 projection from order B onto order A (A <= B)
 constexpr int T_TOT = T_P + MTOT;
 
+// Workgroup id -> work item such that each XCD (dispatch is round-robin over the 8
+// XCDs) takes a contiguous range of the G items and keeps neighbours in its own L2.
+// A bijection of [0, G).
+__device__ __forceinline__ int xcd_remap(int bid, int G) {
+    int q = G >> 3, r = G & 7;
+    int x = bid & 7, l = bid >> 3;
+    return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
 // Per plan element record (device).
 struct ElemInfo {
     int32_t n[3];     // nodes per direction (order + 1)

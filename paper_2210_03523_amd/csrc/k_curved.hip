@@ -22,6 +22,7 @@ namespace dgt {
 
 namespace {
 
+
 __device__ __forceinline__ int face_node_c(const int32_t *n, int d, int side, int a, int b) {
     int idx[3];
     idx[d] = side > 0 ? n[d] - 1 : 0;
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(64) void k_face_curved(const Face *__restrict__ fac
                                                     T *__restrict__ ff, const T *__restrict__ tab, PhysParams ph) {
     constexpr int NF = VISC ? 4 * NV : NV;
     __shared__ T sL[NF][FN], sR[NF][FN], sF[NV][FN];
-    const int fi = blockIdx.x;
+    const int fi = xcd_remap(blockIdx.x, gridDim.x);  // XCD-contiguous face ranges
     const Face f = faces[fi];
     const T *mt = fmet + 3 * fmo[fi];
     if (f.d == 0) face_curved_d<T, FN, VISC, 0>(f, mt, el, u, grad, ff, tab, ph, sL, sR, sF);
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(64) void k_face_avg_curved(const Face *__restrict__
                                                         const ElemInfo *__restrict__ el, const T *__restrict__ u,
                                                         T *__restrict__ fq, const T *__restrict__ tab, PhysParams ph) {
     __shared__ T sL[NV][FN], sR[NV][FN], sP[3 * NV][FN];
-    const int fi = blockIdx.x;
+    const int fi = xcd_remap(blockIdx.x, gridDim.x);  // XCD-contiguous face ranges
     const Face f = faces[fi];
     const T *mt = fmet + 3 * fmo[fi];
     if (f.d == 0) face_avg_curved_d<T, FN, 0>(f, mt, el, u, fq, tab, ph, sL, sR, sP);

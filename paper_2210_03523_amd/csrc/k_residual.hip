@@ -23,14 +23,6 @@
 
 namespace dgt {
 
-// Map workgroup ids so that each XCD (dispatch is round-robin over the 8 XCDs)
-// works on a contiguous range of tiles and keeps neighbours in its own L2.
-__device__ __forceinline__ int xcd_remap(int bid, int G) {
-    int q = G >> 3, r = G & 7;
-    int x = bid & 7, l = bid >> 3;
-    return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
-}
-
 __device__ __forceinline__ int face_node(const int32_t *n, int d, int side, int a, int b) {
     int idx[3];
     idx[d] = side > 0 ? n[d] - 1 : 0;
@@ -266,7 +258,8 @@ __global__ __launch_bounds__(64) void k_face(const Face *__restrict__ faces, con
                                              const T *__restrict__ u, T *__restrict__ ff,
                                              const T *__restrict__ tab, Geom g, PhysParams ph) {
     __shared__ FaceSmem<T, FN> sm;
-    face_body<T, FN>(faces[blockIdx.x], el, u, ff, tab, g, ph, sm);
+    // XCD-contiguous face ranges: both sides' element blocks stay in one L2
+    face_body<T, FN>(faces[xcd_remap(blockIdx.x, gridDim.x)], el, u, ff, tab, g, ph, sm);
 }
 
 template <typename T>
@@ -562,7 +555,7 @@ __global__ __launch_bounds__(64) void k_face_avg(const Face *__restrict__ faces,
                                                  const T *__restrict__ u, T *__restrict__ fq,
                                                  const T *__restrict__ tab, Geom g, PhysParams ph) {
     __shared__ FaceSmem<T, FN> sm;
-    face_body<T, FN, 1>(faces[blockIdx.x], el, u, fq, tab, g, ph, sm);
+    face_body<T, FN, 1>(faces[xcd_remap(blockIdx.x, gridDim.x)], el, u, fq, tab, g, ph, sm);
 }
 
 template <typename T, int NPT>
@@ -759,7 +752,7 @@ __global__ __launch_bounds__(64) void k_face_ns(const Face *__restrict__ faces, 
                                                 T *__restrict__ ff, const T *__restrict__ tab, Geom g,
                                                 PhysParams ph) {
     __shared__ T sL[4 * NV][FN], sR[4 * NV][FN], sF[NV][FN];
-    const Face f = faces[blockIdx.x];
+    const Face f = faces[xcd_remap(blockIdx.x, gridDim.x)];
     if (f.d == 0) face_ns_d<T, FN, 0>(f, el, u, grad, ff, tab, g, ph, sL, sR, sF);
     else if (f.d == 1) face_ns_d<T, FN, 1>(f, el, u, grad, ff, tab, g, ph, sL, sR, sF);
     else face_ns_d<T, FN, 2>(f, el, u, grad, ff, tab, g, ph, sL, sR, sF);

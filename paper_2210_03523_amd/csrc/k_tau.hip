@@ -18,11 +18,6 @@
 
 namespace dgt {
 
-__device__ __forceinline__ int xcd_remap_t(int bid, int G) {
-    int q = G >> 3, r = G & 7;
-    int x = bid & 7, l = bid >> 3;
-    return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
-}
 
 // ---------------------------------------------------------------------------- restriction
 // One workgroup per coarse element.  The three interpolation matrices are staged into
@@ -43,7 +38,7 @@ __global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ 
                                                     int capA) {
     extern __shared__ double lds[];
     double *sI = lds, *sA = lds + RS_TAB, *sB = lds + RS_TAB + capA;
-    const int p = xcd_remap_t(blockIdx.x, gridDim.x);
+    const int p = xcd_remap(blockIdx.x, gridDim.x);
     const ElemInfo C = cel[p];
     const ElemInfo F = fel[fine_of[p]];
     const int f1 = F.n[0], f2 = F.n[1], f3 = F.n[2], nef = f1 * f2 * f3;
@@ -135,7 +130,7 @@ __global__ __launch_bounds__(SW_WG) void k_sweep(const SweepTask *__restrict__ t
     double *sX2Q = sX1 + x1cap;
     double *sX2R = sX2Q + x2cap;
     double *sRed = sX2R + x2cap;
-    const SweepTask task = tasks[xcd_remap_t(blockIdx.x, ntasks)];
+    const SweepTask task = tasks[xcd_remap(blockIdx.x, ntasks)];
     const ElemInfo E = el[task.p];
     const int f1 = E.n[0], f2 = E.n[1], f3 = E.n[2], nef = f1 * f2 * f3;
     const int m1 = task.c1 + 1, m2 = task.c2 + 1;
@@ -313,7 +308,7 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
     double *S = lds;                                                     // staging / X1
     unsigned long long *slot = (unsigned long long *)(lds + 2 * NV * MM * NL);
 
-    const int job = xcd_remap_t(blockIdx.x, njobs);
+    const int job = xcd_remap(blockIdx.x, njobs);
     const int pair = job % NPAIR;
     const int p = elems[job / NPAIR];
     const ElemInfo E = el[p];

@@ -27,11 +27,6 @@ __device__ __forceinline__ int vjp_face_node(const int32_t *n, int d, int side, 
     return idx[0] + n[0] * (idx[1] + n[1] * idx[2]);
 }
 
-__device__ __forceinline__ int remap8(int bid, int G) {
-    int q = G >> 3, r = G & 7;
-    int x = bid & 7, l = bid >> 3;
-    return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
-}
 
 // Residual-form weight c_n at a node.
 __device__ __forceinline__ double form_weight(const ElemInfo &E, int node, const double *tab, int form,
@@ -231,7 +226,7 @@ __global__ __launch_bounds__(64) void k_face_vjp(const Face *__restrict__ faces,
                                                  double *__restrict__ fa, const double *__restrict__ tab, Geom g,
                                                  PhysParams ph, int form) {
     __shared__ double sQL[NV][FNV], sQR[NV][FNV], sLL[NV][FNV], sLR[NV][FNV], sAL[NV][FNV], sAR[NV][FNV];
-    const Face f = faces[blockIdx.x];
+    const Face f = faces[xcd_remap(blockIdx.x, gridDim.x)];  // XCD-contiguous face ranges
     if (f.d == 0) face_vjp_d<0>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR);
     else if (f.d == 1) face_vjp_d<1>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR);
     else face_vjp_d<2>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR);
@@ -247,7 +242,7 @@ __global__ __launch_bounds__(WG) void k_elem_vjp(const Tile *__restrict__ tiles,
     __shared__ double sV[NV][WG * NPT];
     __shared__ double sD[3 * NNMAX * NNMAX];  // the tile's derivative matrices (per-lane columns)
     const int tid = threadIdx.x;
-    const Tile tl = tiles[tile0 + remap8(blockIdx.x, ntiles)];
+    const Tile tl = tiles[tile0 + xcd_remap(blockIdx.x, ntiles)];
     const ElemInfo E0 = el[tl.first];
     const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
     {
