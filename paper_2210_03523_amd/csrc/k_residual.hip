@@ -274,15 +274,16 @@ hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems
 }
 
 // ---------------------------------------------------------------------------- elements
-// One tile of elements, processed by one workgroup of WG lanes.
+// One tile of elements, processed by one workgroup of BS lanes (NPT nodes per lane).
 // u is not __restrict__: the RK epilogue writes the stage update in place.
 // CURVED: per-node metric terms (epi.met), contravariant fluxes Ja^d . f and per-node J.
+// VISC: Navier-Stokes (gradients in epi.grad); the Euler instances carry no viscous registers.
 // sD (LDS, 3 NNMAX^2): the tile's derivative matrices, staged so that the per-lane rows are
 // read from LDS rather than through vector memory loads.
-template <typename T, int NPT, bool CURVED = false>
+template <typename T, int NPT, bool CURVED = false, int BS = WG, bool VISC = true>
 __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restrict__ el, const T *u,
                                           const T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
-                                          const PhysParams &ph, const EpiArgs &epi, T (&sF)[NV][WG * NPT],
+                                          const PhysParams &ph, const EpiArgs &epi, T (&sF)[NV][BS * NPT],
                                           T *sD) {
     const int tid = threadIdx.x;
     const ElemInfo E0 = el[tl.first];
@@ -291,7 +292,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
         const int ns[3] = {n1, n2, n3};
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-            for (int t = tid; t < ns[d] * ns[d]; t += WG) sD[d * NNMAX * NNMAX + t] = tab[T_D + doff(ns[d] - 1) + t];
+            for (int t = tid; t < ns[d] * ns[d]; t += BS) sD[d * NNMAX * NNMAX + t] = tab[T_D + doff(ns[d] - 1) + t];
     }  // ordered before the first read by the barrier after the first flux staging
     const int npe = n1 * n2 * n3;
     const int total = tl.count * npe;
@@ -302,11 +303,11 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
     T M[CURVED ? NPT : 1][10];  // curved: Ja^1, Ja^2, Ja^3, J at the node
     int loc[NPT][3], le[NPT], nd[NPT];
     bool ok[NPT];
-    const bool visc = epi.grad != nullptr;
+    const bool visc = VISC && epi.grad != nullptr;
     const T mu = (T)epi.mu, kappa = (T)epi.kappa, gam = (T)ph.gamma;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int t = tid + k * WG;
+        const int t = tid + k * BS;
         ok[k] = t < total;
         le[k] = ok[k] ? t / npe : 0;
         nd[k] = ok[k] ? t - le[k] * npe : 0;
@@ -365,7 +366,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
         for (int k = 0; k < NPT; ++k) {
             T f[NV];
             total_flux(k, d, f);
-            const int t = tid + k * WG;
+            const int t = tid + k * BS;
             if (ok[k]) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) sF[v][t] = f[v];
@@ -377,7 +378,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             if (!ok[k]) continue;
-            const int t = tid + k * WG;
+            const int t = tid + k * BS;
             const int id = loc[k][d];
             const T *Drow = Dm + id * nd_;
             const int tb = t - id * stride[d];
@@ -470,17 +471,17 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int t = tid + k * WG;
+            const int t = tid + k * BS;
             sF[0][t] = mx[k][0];
             sF[1][t] = mx[k][1];
             sF[2][t] = mx[k][2];
         }
         __syncthreads();
         if (tl.count == 1) {
-            for (int s = WG * NPT / 2; s > 0; s >>= 1) {
+            for (int s = BS * NPT / 2; s > 0; s >>= 1) {
 #pragma unroll
                 for (int k = 0; k < NPT; ++k) {
-                    const int t = tid + k * WG;
+                    const int t = tid + k * BS;
                     if (t < s) {
                         sF[0][t] = fmax(sF[0][t], sF[0][t + s]);
                         sF[1][t] = fmax(sF[1][t], sF[1][t + s]);
@@ -512,31 +513,44 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restr
     }
 }
 
-template <typename T, int NPT, bool CURVED>
-__global__ __launch_bounds__(WG) void k_elem(const Tile *__restrict__ tiles, int tile0, int ntiles,
+// One node per lane for tiles of up to 256 and 512 nodes (BS = 256, 512 lanes): the
+// register footprint of one node per lane keeps several waves per SIMD.  Tiles of up to
+// 1024 nodes take 1024 lanes on box elements and 512 lanes of two nodes on curved ones
+// (whose per-node metric terms do not fit the register budget of 1024-lane groups).
+template <typename T, int NPT, bool CURVED, bool VISC, int BS>
+__global__ __launch_bounds__(BS) void k_elem(const Tile *__restrict__ tiles, int tile0, int ntiles,
                                              const ElemInfo *__restrict__ el, const T *u,
                                              const T *__restrict__ ff, const T *__restrict__ tab, Geom g,
                                              PhysParams ph, EpiArgs epi) {
-    __shared__ T sF[NV][WG * NPT];
+    __shared__ T sF[NV][BS * NPT];
     __shared__ T sD[3 * NNMAX * NNMAX];
-    elem_body<T, NPT, CURVED>(tiles[tile0 + xcd_remap(blockIdx.x, ntiles)], el, u, ff, tab, g, ph, epi, sF, sD);
+    elem_body<T, NPT, CURVED, BS, VISC>(tiles[tile0 + xcd_remap(blockIdx.x, ntiles)], el, u, ff, tab, g, ph, epi,
+                                        sF, sD);
 }
 
 template <typename T>
 hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, const ElemInfo *elems, const T *u,
                           const T *fflux, const T *tab, Geom g, PhysParams ph, EpiArgs epi, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    dim3 grid(ntiles), block(WG);
+    dim3 grid(ntiles);
     const bool curved = epi.met != nullptr;
-#define DGT_ELEM(NP, CU) \
-    hipLaunchKernelGGL((k_elem<T, NP, CU>), grid, block, 0, s, tiles, tile0, ntiles, elems, u, fflux, tab, g, ph, epi)
+    const bool visc = epi.grad != nullptr;
+#define DGT_ELEM(NP, CU, BSZ)                                                                                  \
+    do {                                                                                                       \
+        if (visc)                                                                                              \
+            hipLaunchKernelGGL((k_elem<T, NP, CU, true, BSZ>), grid, dim3(BSZ), 0, s, tiles, tile0, ntiles,    \
+                               elems, u, fflux, tab, g, ph, epi);                                              \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_elem<T, NP, CU, false, BSZ>), grid, dim3(BSZ), 0, s, tiles, tile0, ntiles,   \
+                               elems, u, fflux, tab, g, ph, epi);                                              \
+    } while (0)
     switch (npt * 2 + (curved ? 1 : 0)) {
-        case 2: DGT_ELEM(1, false); break;
-        case 3: DGT_ELEM(1, true); break;
-        case 4: DGT_ELEM(2, false); break;
-        case 5: DGT_ELEM(2, true); break;
-        case 8: DGT_ELEM(4, false); break;
-        case 9: DGT_ELEM(4, true); break;
+        case 2: DGT_ELEM(1, false, WG); break;
+        case 3: DGT_ELEM(1, true, WG); break;
+        case 4: DGT_ELEM(1, false, 2 * WG); break;
+        case 5: DGT_ELEM(1, true, 2 * WG); break;
+        case 8: DGT_ELEM(1, false, 4 * WG); break;
+        case 9: DGT_ELEM(2, true, 2 * WG); break;
         default: return hipErrorInvalidValue;
     }
 #undef DGT_ELEM
@@ -812,11 +826,11 @@ __global__ __launch_bounds__(64) void k_face_batch(const int2 *__restrict__ face
     }
 }
 
-template <typename T, int NPT>
-__global__ __launch_bounds__(WG) void k_elem_batch(const BatchTile *__restrict__ tiles, int ntiles,
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void k_elem_batch(const BatchTile *__restrict__ tiles, int ntiles,
                                                    const ProbDesc<T> *__restrict__ probs, const T *__restrict__ tab,
                                                    EpiArgs epi0) {
-    __shared__ T sF[NV][WG * NPT];
+    __shared__ T sF[NV][BS];
     __shared__ T sD[3 * NNMAX * NNMAX];
     for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const BatchTile bt = tiles[i];
@@ -824,7 +838,7 @@ __global__ __launch_bounds__(WG) void k_elem_batch(const BatchTile *__restrict__
         EpiArgs epi = epi0;
         epi.out = pd.out;
         epi.g = pd.g;
-        elem_body<T, NPT>(Tile{bt.first, bt.count}, pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, epi, sF, sD);
+        elem_body<T, 1, false, BS, false>(Tile{bt.first, bt.count}, pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, epi, sF, sD);
         __syncthreads();
     }
 }
@@ -841,7 +855,7 @@ template <typename T>
 hipError_t launch_elem_batch(const BatchTile *tiles, int ntiles, const ProbDesc<T> *probs, const T *tab, int grid,
                              EpiArgs epi, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_elem_batch<T, 2>), dim3(grid), dim3(WG), 0, s, tiles, ntiles, probs, tab, epi);
+    hipLaunchKernelGGL((k_elem_batch<T, 2 * WG>), dim3(grid), dim3(2 * WG), 0, s, tiles, ntiles, probs, tab, epi);
     return hipGetLastError();
 }
 
