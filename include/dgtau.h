@@ -168,6 +168,44 @@ dg_status dg_sweep_layout(dg_plan fine, int64_t *combo_offset);
 dg_status dg_tau_sweep(dg_plan fine, const double *u, const double *dudt, double *te_new,
                        double *te_trad, hipStream_t stream);
 
+/* Polynomial-degree selection from truncation-error maps (Section 2.4.2, static
+ * p-adaptation, approaches 1 and 2 with the maximum aggregator F_max; jump
+ * conditions of Section 3.1, eqs. (a) N >= floor(2/3 N_j) and (b) N >= N_j - 1).
+ *
+ * A combination (N1, N2, N3) of a map qualifies when its value is below tau_max, every
+ * N_i lies in [nmin, nmax], and N_i < P_i (P the plan's orders: combinations at or
+ * above P have the high value of the paper's fallback, since no map is extrapolated).
+ * Among the qualifying combinations the one with the fewest degrees of freedom
+ * prod (N_i + 1) is selected; ties go to the smaller map value, then to the smaller
+ * (N1, N2, N3) compared lexicographically (N1 first).  An element without a qualifying
+ * combination gets (nmax, nmax, nmax).
+ *   approach 1: select per map (one map per estimation stage), then the maximum
+ *               over the stages in every direction;
+ *   approach 2: a combination qualifies when it does in every map (the F_max total
+ *               map below tau_max); its value is the maximum over the maps.
+ * The jump condition (jump 1: (a), jump 2: (b), 0: none) is then enforced against
+ * the face neighbours (across periodic box faces too), in the matching direction,
+ * by raising degrees to the least fixed point.  Integer results are exact; a NaN in
+ * a map never qualifies.
+ *   maps: host array of nstages (1..DG_SELECT_MAX_STAGES) device double pointers,
+ *         each a map in the layout of dg_tau_sweep (te_new or te_trad).
+ *   orders: device int32 [E][3], natural element order (the layout dg_plan_create
+ *           takes), written by the call; the plan's own scratch holds the
+ *           intermediate degrees, so one plan runs one selection at a time.
+ * Errors: DG_EINVAL for null arguments, nstages outside 1..DG_SELECT_MAX_STAGES,
+ * approach not 1 or 2, jump not 0..2, 1 <= nmin <= nmax <= DG_NMAX violated or a
+ * NaN tau_max; DG_EHIP for launch failures.  Asynchronous on stream. */
+#define DG_SELECT_MAX_STAGES 32
+typedef struct {
+    double tau_max;
+    int32_t nmin, nmax;
+    int32_t approach; /* 1 or 2 */
+    int32_t jump;     /* 0 none, 1 (a), 2 (b) */
+} dg_select_params;
+
+dg_status dg_select_orders(dg_plan fine, const double *const *maps, int32_t nstages,
+                           const dg_select_params *params, int32_t *orders, hipStream_t stream);
+
 /* Vector-Jacobian product of the residual: out = (d r / d u)^T v, r the form and
  * operator of dg_residual (FP64 only).  Written by hand: transposed derivative
  * matrices, transposed lifting, transposed mortar interpolation and projection, and

@@ -39,6 +39,13 @@ class _MeshDesc(ctypes.Structure):
                 ("map_kind", ctypes.c_int32), ("map_amp", ctypes.c_double), ("geo_order", ctypes.c_int32 * 3)]
 
 
+class _SelectParams(ctypes.Structure):
+    _fields_ = [("tau_max", ctypes.c_double), ("nmin", ctypes.c_int32), ("nmax", ctypes.c_int32),
+                ("approach", ctypes.c_int32), ("jump", ctypes.c_int32)]
+
+
+SELECT_MAX_STAGES = 32
+
 _lib = None
 _P = ctypes.c_void_p
 _I64P = ctypes.POINTER(ctypes.c_int64)
@@ -58,6 +65,7 @@ SIGNATURES = {
     "dg_functional": [_P, _P, _P, _P, _P],
     "dg_sweep_layout": [_P, _I64P],
     "dg_tau_sweep": [_P, _P, _P, _P, _P, _P],
+    "dg_select_orders": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_SelectParams), _P, _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_check": [],
     "dg_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)],
@@ -235,6 +243,29 @@ class Plan:
         _call("dg_sweep_layout", self.handle, off.ctypes.data_as(_I64P))
         return off
 
+    def _combo_index(self) -> np.ndarray:
+        """Gather index of the sweep layout: plan position -> natural position."""
+        if "combo" not in self._idx:
+            off = self.combo_offsets()
+            cnt = np.diff(off)
+            nat_cnt = np.empty_like(cnt)
+            nat_cnt[self.perm] = cnt
+            nat_off = np.concatenate([[0], np.cumsum(nat_cnt)]).astype(np.int64)
+            self._idx["combo"] = np.repeat(nat_off[self.perm] - off[:-1], cnt) + np.arange(int(off[-1]))
+        return self._idx["combo"]
+
+    def map_to_plan(self, m_nat):
+        """Map in natural element order (combinations of each element contiguous) -> device
+        tensor in the sweep layout."""
+        torch = _torch()
+        return torch.from_numpy(np.ascontiguousarray(np.asarray(m_nat, dtype=np.float64)[self._combo_index()])).cuda()
+
+    def map_to_natural(self, t) -> np.ndarray:
+        a = t.detach().cpu().numpy()
+        out = np.empty_like(a)
+        out[self._combo_index()] = a
+        return out
+
 
 # ---------------------------------------------------------------------- entry points
 def residual(plan: Plan, u, form: int = FORM_NEW, isolated: bool = False, out=None):
@@ -326,6 +357,25 @@ def tau_sweep(plan: Plan, u, dudt=None):
     tet = torch.empty_like(ten)
     _call("dg_tau_sweep", plan.handle, _ptr(u), _ptr(dudt), _ptr(ten), _ptr(tet), _stream())
     return ten, tet
+
+
+def select_orders(plan: Plan, maps, tau_max: float, nmin: int = 1, nmax: int = NMAX, approach: int = 2,
+                  jump: int = 0):
+    """Degrees [E][3] (device int32, natural element order) selected from truncation-error
+    maps of the plan's sweep layout, one map per estimation stage (approach 1: select per
+    stage then the maximum; approach 2: select from the maximum of the maps), with the
+    jump condition jump = 1 (floor(2/3 N_j)), 2 (N_j - 1) or 0 (none) enforced."""
+    torch = _torch()
+    maps = list(maps)
+    n = int(plan.combo_offsets()[-1])
+    for m in maps:
+        if m.dtype != torch.float64 or m.numel() != n:
+            raise DGError("maps must be float64 tensors in the sweep layout of the plan")
+    out = torch.empty((plan.n_elems, 3), dtype=torch.int32, device="cuda")
+    prm = _SelectParams(float(tau_max), int(nmin), int(nmax), int(approach), int(jump))
+    arr = (_P * max(1, len(maps)))(*[_ptr(m).value for m in maps])
+    _call("dg_select_orders", plan.handle, arr, len(maps), ctypes.byref(prm), _ptr(out), _stream())
+    return out
 
 
 def rk3_step(plan: Plan, u, g, dt: float, nsteps: int = 1):

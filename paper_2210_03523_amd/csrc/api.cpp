@@ -129,6 +129,7 @@ struct dg_plan_s {
     SweepTask *d_tasks = nullptr;
     int ntasks = 0, x1cap = 0, x2cap = 0, max_order = 0;
     int32_t *d_iso = nullptr;           // isotropic elements grouped by fine node count F
+    int32_t *d_sel = nullptr;           // degree selection: [E][3] intermediate of the jump steps
     int iso_first[NNMAX + 1] = {0}, iso_count[NNMAX + 1] = {0};
     // RK3 graphs
     hipStream_t cap_stream = nullptr;
@@ -152,7 +153,7 @@ void destroy_plan(dg_plan p) {
     void *bufs[] = {p->d_el,    p->d_faces,  p->d_tiles,  p->d_ff,     p->d_dudt,   p->d_fine_of, p->d_uc,
                     p->d_rdc,   p->d_psic,   p->d_combo_off, p->d_tasks, p->d_iso,  p->d_wallx,   p->d_part,
                     p->d_grad,  p->d_xyz,    p->d_met64,  p->d_fmet64, p->d_met32,  p->d_fmet32,  p->d_fmo,
-                    p->d_ctasks};
+                    p->d_ctasks, p->d_sel};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -540,6 +541,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     if (hipMalloc(&p->d_ff, sizeof(double) * ff_alloc) != hipSuccess ||
         hipMalloc((void **)&p->d_part, sizeof(double) * std::max(1, p->nwallx)) != hipSuccess ||
         hipMalloc((void **)&p->d_dudt, sizeof(double) * NV * p->n_nodes) != hipSuccess ||
+        hipMalloc((void **)&p->d_sel, sizeof(int32_t) * 3 * std::max(1, E)) != hipSuccess ||
         hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         (p->ns && hipMalloc(&p->d_grad, sizeof(double) * 3 * NV * p->n_nodes) != hipSuccess)) {
         destroy_plan(p);
@@ -779,6 +781,25 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *t
                                      dudt, p->tabs.t64, p->geom, p->mesh.gamma, te_new, te_trad, stream));
     HIP_TRY(launch_sweep_tasks(p->d_tasks, p->ntasks, p->d_el, p->d_combo_off, u, dudt, p->tabs.t64, p->geom,
                                p->mesh.gamma, p->x1cap, p->x2cap, te_new, te_trad, stream));
+    return DG_OK;
+}
+
+dg_status dg_select_orders(dg_plan p, const double *const *maps, int32_t nstages, const dg_select_params *prm,
+                           int32_t *orders, hipStream_t stream) {
+    if (!p || !maps || !prm || !orders) return fail(DG_EINVAL, "null argument");
+    if (nstages < 1 || nstages > DG_SELECT_MAX_STAGES) return fail(DG_EINVAL, "nstages must be in 1..32");
+    for (int s = 0; s < nstages; ++s)
+        if (!maps[s]) return fail(DG_EINVAL, "null map");
+    if (prm->approach != 1 && prm->approach != 2) return fail(DG_EINVAL, "approach must be 1 or 2");
+    if (prm->jump < 0 || prm->jump > 2) return fail(DG_EINVAL, "jump must be 0, 1 or 2");
+    if (prm->nmin < 1 || prm->nmin > prm->nmax || prm->nmax > DG_NMAX)
+        return fail(DG_EINVAL, "degrees must satisfy 1 <= nmin <= nmax <= 9");
+    if (std::isnan(prm->tau_max)) return fail(DG_EINVAL, "tau_max is NaN");
+    const dg_mesh_desc &m = p->mesh;
+    const int periodic = (m.bc[0] == DG_BC_PERIODIC ? 1 : 0) | (m.bc[2] == DG_BC_PERIODIC ? 2 : 0) |
+                         (m.bc[4] == DG_BC_PERIODIC ? 4 : 0);
+    HIP_TRY(launch_select(p->d_el, p->E, p->d_combo_off, maps, nstages, prm->tau_max, prm->nmin, prm->nmax,
+                          prm->approach, prm->jump, m.nx, m.ny, m.nz, periodic, orders, p->d_sel, stream));
     return DG_OK;
 }
 

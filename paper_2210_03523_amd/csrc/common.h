@@ -144,6 +144,11 @@ hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *ele
                               int x1cap, int x2cap, double *te_new, double *te_trad, hipStream_t s);
 
 // Isotropic fast path of the sweep (fine nodes F per direction, 2 <= F <= 8).
+// Degree selection from truncation-error maps (maps: host array of nst device pointers)
+// and nmax Jacobi steps of the jump condition; orders natural [E][3]; tmp: [E][3] scratch.
+hipError_t launch_select(const ElemInfo *el, int E, const int64_t *combo_off, const double *const *maps, int nst,
+                         double tau_max, int nmin, int nmax, int approach, int jump, int nx, int ny, int nz,
+                         int periodic, int32_t *orders, int32_t *tmp, hipStream_t s);
 hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
                             const double *u, const double *dudt, const double *tab, Geom g, double gamma,
                             double *te_new, double *te_trad, hipStream_t s);
