@@ -136,6 +136,15 @@ def main():
     torch.cuda.synchronize()
     t_res64 = a.elapsed_time(b) / reps
 
+    # degree selection from the sweep's map: three estimation stages (the map of this
+    # step thrice), approach 2 with jump condition (b); tau_max the median map value
+    ten_s, _ = step()
+    tau_sel = float(torch.median(ten_s))
+    t_select = _timed(torch, stream, lambda: dg.select_orders(plan, [ten_s] * 3, tau_max=tau_sel, nmin=1, nmax=8,
+                                                              approach=2, jump=2), 10)
+    sel_orders = dg.select_orders(plan, [ten_s] * 3, tau_max=tau_sel, nmin=1, nmax=8, approach=2, jump=2)
+    sel_ndof = int(torch.prod(sel_orders.long() + 1, dim=1).sum())
+
     flops_sweep = sweep_flops_per_element(8) * E
     t_sweep_ms = float(np.mean(t_swp))
     achieved = flops_sweep / (t_sweep_ms * 1e-3) / 1e12
@@ -166,6 +175,9 @@ def main():
             "tau_estimates_per_s": n_est / (t_sweep_ms * 1e-3),
             "residual_fp32_gdof_s": n_fine / (t_res32 * 1e-3) / 1e9,
             "fp32_over_fp64_residual_speedup": t_res64 / t_res32,
+            "select_degrees_ms": t_select,
+            "select_note": "3 stages of the sweep map, approach 2, jump (b), tau_max = median map value",
+            "selected_nodes": sel_ndof,
         },
         "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
