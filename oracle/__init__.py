@@ -65,6 +65,7 @@ def _load():
                              ctypes.c_int, _D, _D],
             "orc_residual": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_int, ctypes.c_int],
             "orc_restrict": [ctypes.c_int, _I, _I, _D, _D],
+            "orc_project": [ctypes.c_int, _I, _I, _D, _D],
             "orc_tau": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, _D, _D, _D, _D],
             "orc_num_combos": [_I],
             "orc_sweep": [ctypes.POINTER(_Mesh), _I, _D, _D, _I, ctypes.c_int, _D, _D],
@@ -221,6 +222,15 @@ def restrict(fine_orders, coarse_orders, u):
     uc = np.zeros(5 * num_nodes(co))
     _check(_load().orc_restrict(E, _i(fo), _i(co), _d(u), _d(uc)), "restrict")
     return uc
+
+
+def project(from_orders, to_orders, u):
+    """Solution transfer onto another order map (interpolation up, L2 projection down)."""
+    fo, to, u = _i32(from_orders), _i32(to_orders), _f64(u)
+    E = fo.size // 3
+    ut = np.zeros(5 * num_nodes(to))
+    _check(_load().orc_project(E, _i(fo), _i(to), _d(u), _d(ut)), "project")
+    return ut
 
 
 def tau(mesh: dict, fine_orders, coarse_orders, u, dudt, isolated: bool = False):

@@ -1105,6 +1105,51 @@ int orc_restrict(int E, const int *fine_orders, const int *coarse_orders, const 
     return 0;
 }
 
+/* Solution transfer onto a new order map (Section 2.4.1: storage reallocated and the
+ * solution projected onto the new polynomial spaces): per direction, the 1D operator is
+ * the interpolation I^{M<-N} when the order rises or stays (the old polynomial lies in
+ * the new space, so this is its exact L2 projection), and the exact L2 projection
+ * P^{M<-N} when it falls; the element operator is their tensor product (the L2 projection
+ * onto the tensor-product space of the reference cube). */
+static void project_element(const int *from, const int *to, const double *in, double *out)
+{
+    int nf[3] = {from[0] + 1, from[1] + 1, from[2] + 1};
+    int nt[3] = {to[0] + 1, to[1] + 1, to[2] + 1};
+    int nef = nf[0] * nf[1] * nf[2], net = nt[0] * nt[1] * nt[2];
+    double A[3][(ORC_NMAX + 1) * (ORC_NMAX + 1)];
+    for (int d = 0; d < 3; ++d) {
+        if (to[d] >= from[d])
+            orc_interp(to[d], from[d], A[d]);
+        else
+            orc_proj(to[d], from[d], A[d]);
+    }
+    for (int v = 0; v < NV; ++v)
+        for (int c = 0; c < nt[2]; ++c)
+            for (int b = 0; b < nt[1]; ++b)
+                for (int a = 0; a < nt[0]; ++a) {
+                    double acc = 0.0;
+                    for (int k = 0; k < nf[2]; ++k)
+                        for (int j = 0; j < nf[1]; ++j)
+                            for (int i = 0; i < nf[0]; ++i)
+                                acc += A[0][a * nf[0] + i] * A[1][b * nf[1] + j] * A[2][c * nf[2] + k] *
+                                       in[v * nef + i + nf[0] * (j + nf[1] * k)];
+                    out[v * net + a + nt[0] * (b + nt[1] * c)] = acc;
+                }
+}
+
+int orc_project(int E, const int *from_orders, const int *to_orders, const double *u, double *ut)
+{
+    if (E <= 0 || check_orders(E, from_orders) || check_orders(E, to_orders)) return -1;
+    ensure_tables();
+    long *off = node_offsets(E, from_orders), *offt = node_offsets(E, to_orders);
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e)
+        project_element(from_orders + 3 * e, to_orders + 3 * e, u + NV * off[e], ut + NV * offt[e]);
+    free(off);
+    free(offt);
+    return 0;
+}
+
 int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders, const double *u,
             const double *dudt, int isolated, double *tau_new, double *tau_trad, double *norms,
             double *varnorms)

@@ -79,6 +79,11 @@ int orc_residual(const orc_mesh *m, const int *orders, const double *u, double *
 int orc_restrict(int E, const int *fine_orders, const int *coarse_orders,
                  const double *u, double *uc);
 
+/* Transfer of a solution onto another order map: per element and direction,
+ * interpolation where the order rises or stays, exact L2 projection where it falls
+ * (Section 2.4.1, the solution projected onto the new polynomial spaces). */
+int orc_project(int E, const int *from_orders, const int *to_orders, const double *u, double *ut);
+
 /* Coupled (isolated=0) or isolated tau-estimate on one coarse order map.
  * dudt: fine r = -dQ/dt (new form, non-isolated residual of u on the fine map).
  * Outputs in the coarse natural ragged layout; norms[e*2+{0,1}] = max |tau_new|,

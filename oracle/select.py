@@ -18,6 +18,8 @@ What it follows (arXiv 2210.03523):
     (P the order the estimate was computed on), those combinations get a high
     value, i.e. they never qualify.  No extrapolation is done here, so only the
     combinations of the sweep below P qualify.
+  * Section 3.2 (dynamic adaptation of the cylinder case): a degree may fall by at most
+    one per adaptation stage (applied before the jump conditions; both only raise).
   * Section 3.1, jump conditions (a) N_i^e >= max_j floor(2/3 N_i^j) and
     (b) N_i^e >= max_j (N_i^j - 1) over the face neighbours j of e, in the matching
     direction i; applied after the selection and iterated until no degree changes.
@@ -92,6 +94,17 @@ def select_orders(orders, maps, tau_max: float, nmin: int, nmax: int, approach: 
         else:
             raise ValueError("approach is 1 or 2")
     return out
+
+
+def limit_decrease(orders, prev, max_decrease: int, nmax: int) -> np.ndarray:
+    """Per-stage decrease limit of dynamic adaptation (Section 3.2: degrees may fall by
+    at most one per adaptation stage): N_i >= min(N_max, N_i^prev - max_decrease)."""
+    o = np.array(orders, dtype=np.int32).reshape(-1, 3)
+    pv = np.asarray(prev, dtype=np.int32).reshape(-1, 3)
+    for e in range(len(o)):
+        for i in range(3):
+            o[e, i] = max(int(o[e, i]), min(nmax, int(pv[e, i]) - max_decrease))
+    return o
 
 
 def face_neighbours(mesh: dict):
