@@ -183,6 +183,9 @@ dg_status dg_tau_sweep(dg_plan fine, const double *u, const double *dudt, double
  *               over the stages in every direction;
  *   approach 2: a combination qualifies when it does in every map (the F_max total
  *               map below tau_max); its value is the maximum over the maps.
+ * With prev (the current degrees, device int32 [E][3] natural order), no degree falls
+ * by more than max_decrease: N_i >= min(nmax, prev_i - max_decrease) (Section 3.2,
+ * dynamic adaptation: one order per stage).
  * The jump condition (jump 1: (a), jump 2: (b), 0: none) is then enforced against
  * the face neighbours (across periodic box faces too), in the matching direction,
  * by raising degrees to the least fixed point.  Integer results are exact; a NaN in
@@ -193,18 +196,35 @@ dg_status dg_tau_sweep(dg_plan fine, const double *u, const double *dudt, double
  *           takes), written by the call; the plan's own scratch holds the
  *           intermediate degrees, so one plan runs one selection at a time.
  * Errors: DG_EINVAL for null arguments, nstages outside 1..DG_SELECT_MAX_STAGES,
- * approach not 1 or 2, jump not 0..2, 1 <= nmin <= nmax <= DG_NMAX violated or a
- * NaN tau_max; DG_EHIP for launch failures.  Asynchronous on stream. */
+ * approach not 1 or 2, jump not 0..2, 1 <= nmin <= nmax <= DG_NMAX violated, a
+ * NaN tau_max or a negative max_decrease; DG_EHIP for launch failures.  Asynchronous
+ * on stream. */
 #define DG_SELECT_MAX_STAGES 32
 typedef struct {
     double tau_max;
     int32_t nmin, nmax;
     int32_t approach; /* 1 or 2 */
     int32_t jump;     /* 0 none, 1 (a), 2 (b) */
+    const int32_t *prev;  /* NULL, or current degrees (device, [E][3] natural) */
+    int32_t max_decrease; /* with prev: largest decrease per direction, >= 0 */
 } dg_select_params;
 
 dg_status dg_select_orders(dg_plan fine, const double *const *maps, int32_t nstages,
                            const dg_select_params *params, int32_t *orders, hipStream_t stream);
+
+/* Solution transfer onto another order map of the same mesh (Section 2.4.1: after an
+ * adaptation the solution is projected onto the new polynomial spaces).  Per element
+ * and direction the 1D operator is the interpolation from the old to the new
+ * Gauss-Lobatto nodes where the order rises or stays (the old polynomial belongs to the
+ * new space) and the exact L2 projection where it falls; the element operator is their
+ * tensor product, i.e. the L2 projection onto the new tensor-product space of the
+ * reference element.
+ *   from, to: plans of the same mesh (any orders; coarse plans allowed).
+ *   u: device double, layout of from; ut: device double, layout of to (5 * n_nodes(to)),
+ *      not overlapping u.
+ * Errors: DG_EINVAL for null arguments or plans of different meshes.  FP64 only.
+ * Asynchronous on stream. */
+dg_status dg_project(dg_plan from, dg_plan to, const double *u, double *ut, hipStream_t stream);
 
 /* Vector-Jacobian product of the residual: out = (d r / d u)^T v, r the form and
  * operator of dg_residual (FP64 only).  Written by hand: transposed derivative

@@ -41,7 +41,8 @@ class _MeshDesc(ctypes.Structure):
 
 class _SelectParams(ctypes.Structure):
     _fields_ = [("tau_max", ctypes.c_double), ("nmin", ctypes.c_int32), ("nmax", ctypes.c_int32),
-                ("approach", ctypes.c_int32), ("jump", ctypes.c_int32)]
+                ("approach", ctypes.c_int32), ("jump", ctypes.c_int32),
+                ("prev", ctypes.c_void_p), ("max_decrease", ctypes.c_int32)]
 
 
 SELECT_MAX_STAGES = 32
@@ -66,6 +67,7 @@ SIGNATURES = {
     "dg_sweep_layout": [_P, _I64P],
     "dg_tau_sweep": [_P, _P, _P, _P, _P, _P],
     "dg_select_orders": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_SelectParams), _P, _P],
+    "dg_project": [_P, _P, _P, _P, _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_check": [],
     "dg_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)],
@@ -360,11 +362,12 @@ def tau_sweep(plan: Plan, u, dudt=None):
 
 
 def select_orders(plan: Plan, maps, tau_max: float, nmin: int = 1, nmax: int = NMAX, approach: int = 2,
-                  jump: int = 0):
+                  jump: int = 0, prev=None, max_decrease: int = 1):
     """Degrees [E][3] (device int32, natural element order) selected from truncation-error
     maps of the plan's sweep layout, one map per estimation stage (approach 1: select per
-    stage then the maximum; approach 2: select from the maximum of the maps), with the
-    jump condition jump = 1 (floor(2/3 N_j)), 2 (N_j - 1) or 0 (none) enforced."""
+    stage then the maximum; approach 2: select from the maximum of the maps), no degree
+    more than max_decrease below prev (device int32 [E][3], optional), with the jump
+    condition jump = 1 (floor(2/3 N_j)), 2 (N_j - 1) or 0 (none) enforced."""
     torch = _torch()
     maps = list(maps)
     n = int(plan.combo_offsets()[-1])
@@ -372,10 +375,24 @@ def select_orders(plan: Plan, maps, tau_max: float, nmin: int = 1, nmax: int = N
         if m.dtype != torch.float64 or m.numel() != n:
             raise DGError("maps must be float64 tensors in the sweep layout of the plan")
     out = torch.empty((plan.n_elems, 3), dtype=torch.int32, device="cuda")
-    prm = _SelectParams(float(tau_max), int(nmin), int(nmax), int(approach), int(jump))
+    if prev is not None and (prev.dtype != torch.int32 or prev.numel() != 3 * plan.n_elems):
+        raise DGError("prev must be an int32 [E][3] device tensor")
+    prm = _SelectParams(float(tau_max), int(nmin), int(nmax), int(approach), int(jump),
+                        None if prev is None else _ptr(prev).value, int(max_decrease))
     arr = (_P * max(1, len(maps)))(*[_ptr(m).value for m in maps])
     _call("dg_select_orders", plan.handle, arr, len(maps), ctypes.byref(prm), _ptr(out), _stream())
     return out
+
+
+def project(src: Plan, dst: Plan, u):
+    """Solution u (plan layout of src, float64) transferred onto the order map of dst:
+    interpolation where an order rises, exact L2 projection where it falls."""
+    torch = _torch()
+    if u.dtype != torch.float64 or u.numel() != 5 * src.n_nodes:
+        raise DGError("u must be a float64 state of the source plan")
+    ut = torch.empty(5 * dst.n_nodes, dtype=torch.float64, device="cuda")
+    _call("dg_project", src.handle, dst.handle, _ptr(u), _ptr(ut), _stream())
+    return ut
 
 
 def rk3_step(plan: Plan, u, g, dt: float, nsteps: int = 1):

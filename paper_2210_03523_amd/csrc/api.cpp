@@ -130,6 +130,7 @@ struct dg_plan_s {
     int ntasks = 0, x1cap = 0, x2cap = 0, max_order = 0;
     int32_t *d_iso = nullptr;           // isotropic elements grouped by fine node count F
     int32_t *d_sel = nullptr;           // degree selection: [E][3] intermediate of the jump steps
+    int32_t *d_inv = nullptr;           // natural element -> plan position
     int iso_first[NNMAX + 1] = {0}, iso_count[NNMAX + 1] = {0};
     // RK3 graphs
     hipStream_t cap_stream = nullptr;
@@ -153,7 +154,7 @@ void destroy_plan(dg_plan p) {
     void *bufs[] = {p->d_el,    p->d_faces,  p->d_tiles,  p->d_ff,     p->d_dudt,   p->d_fine_of, p->d_uc,
                     p->d_rdc,   p->d_psic,   p->d_combo_off, p->d_tasks, p->d_iso,  p->d_wallx,   p->d_part,
                     p->d_grad,  p->d_xyz,    p->d_met64,  p->d_fmet64, p->d_met32,  p->d_fmet32,  p->d_fmo,
-                    p->d_ctasks, p->d_sel};
+                    p->d_ctasks, p->d_sel, p->d_inv};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -532,7 +533,8 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
         (st = upload(&p->d_iso, iso_all)) || (st = upload(&p->d_wallx, wallx)) ||
         (st = upload(&p->d_ctasks, ctasks)) || (st = upload(&p->d_xyz, p->xyz_h)) ||
         (st = upload(&p->d_met64, met_h)) || (st = upload(&p->d_met32, met32)) ||
-        (st = upload(&p->d_fmet64, fmet_h)) || (st = upload(&p->d_fmet32, fmet32)) || (st = upload(&p->d_fmo, fmo))) {
+        (st = upload(&p->d_fmet64, fmet_h)) || (st = upload(&p->d_fmet32, fmet32)) || (st = upload(&p->d_fmo, fmo)) ||
+        (st = upload(&p->d_inv, std::vector<int32_t>(p->inv.begin(), p->inv.end())))) {
         destroy_plan(p);
         return st;
     }
@@ -795,11 +797,28 @@ dg_status dg_select_orders(dg_plan p, const double *const *maps, int32_t nstages
     if (prm->nmin < 1 || prm->nmin > prm->nmax || prm->nmax > DG_NMAX)
         return fail(DG_EINVAL, "degrees must satisfy 1 <= nmin <= nmax <= 9");
     if (std::isnan(prm->tau_max)) return fail(DG_EINVAL, "tau_max is NaN");
+    if (prm->prev && prm->max_decrease < 0) return fail(DG_EINVAL, "max_decrease must be >= 0");
     const dg_mesh_desc &m = p->mesh;
     const int periodic = (m.bc[0] == DG_BC_PERIODIC ? 1 : 0) | (m.bc[2] == DG_BC_PERIODIC ? 2 : 0) |
                          (m.bc[4] == DG_BC_PERIODIC ? 4 : 0);
     HIP_TRY(launch_select(p->d_el, p->E, p->d_combo_off, maps, nstages, prm->tau_max, prm->nmin, prm->nmax,
-                          prm->approach, prm->jump, m.nx, m.ny, m.nz, periodic, orders, p->d_sel, stream));
+                          prm->approach, prm->prev, prm->max_decrease, prm->jump, m.nx, m.ny, m.nz, periodic, orders,
+                          p->d_sel, stream));
+    return DG_OK;
+}
+
+dg_status dg_project(dg_plan from, dg_plan to, const double *u, double *ut, hipStream_t stream) {
+    if (!from || !to || !u || !ut) return fail(DG_EINVAL, "null argument");
+    if (from->mesh.nx != to->mesh.nx || from->mesh.ny != to->mesh.ny || from->mesh.nz != to->mesh.nz)
+        return fail(DG_EINVAL, "plans of different meshes");
+    int capA = 1, capB = 1;
+    for (int p = 0; p < to->E; ++p) {
+        const int32_t *t = &to->ord[3 * p];
+        const int32_t *f = &from->ord[3 * from->inv[to->perm[p]]];
+        capA = std::max(capA, NV * (t[0] + 1) * (f[1] + 1) * (f[2] + 1));
+        capB = std::max(capB, NV * std::max((t[0] + 1) * (t[1] + 1) * (f[2] + 1), (f[0] + 1) * (f[1] + 1) * (f[2] + 1)));
+    }
+    HIP_TRY(launch_project(from->d_inv, to->E, to->d_el, from->d_el, u, ut, from->tabs.t64, capA, capB, stream));
     return DG_OK;
 }
 

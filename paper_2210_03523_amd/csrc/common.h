@@ -123,6 +123,12 @@ hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *
                            const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
                            double *psic, const double *tab, int capA, int capB, hipStream_t s);
 
+// Solution transfer onto another order map: target plan elements tel, source plan
+// elements sel, src_inv[natural] = source plan position; capA = max 5 t1 s2 s3,
+// capB = max 5 max(t1 t2 s3, s1 s2 s3) over the elements.
+hipError_t launch_project(const int32_t *src_inv, int ntarget, const ElemInfo *tel, const ElemInfo *sel,
+                          const double *u, double *ut, const double *tab, int capA, int capB, hipStream_t s);
+
 hipError_t launch_vjp(const Face *faces, int nfaces, const Tile *tiles, int tile0, int ntiles, int npt,
                       const ElemInfo *el, const double *u, const double *v, double *fa, double *out,
                       const double *tab, Geom g, PhysParams ph, int form, int isolated, bool do_faces,
@@ -147,8 +153,9 @@ hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *ele
 // Degree selection from truncation-error maps (maps: host array of nst device pointers)
 // and nmax Jacobi steps of the jump condition; orders natural [E][3]; tmp: [E][3] scratch.
 hipError_t launch_select(const ElemInfo *el, int E, const int64_t *combo_off, const double *const *maps, int nst,
-                         double tau_max, int nmin, int nmax, int approach, int jump, int nx, int ny, int nz,
-                         int periodic, int32_t *orders, int32_t *tmp, hipStream_t s);
+                         double tau_max, int nmin, int nmax, int approach, const int32_t *prev, int max_decrease,
+                         int jump, int nx, int ny, int nz, int periodic, int32_t *orders, int32_t *tmp,
+                         hipStream_t s);
 hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
                             const double *u, const double *dudt, const double *tab, Geom g, double gamma,
                             double *te_new, double *te_trad, hipStream_t s);

@@ -2,7 +2,7 @@
 // between face neighbours (arXiv 2210.03523, Section 2.4.2 approaches 1 and 2 with the
 // maximum aggregator; Section 3.1 jump conditions (a) and (b)).
 //
-// k_select: one wave per plan element.  Lanes stride over the element's combinations of
+// k_select: one wave per plan element (then the optional per-stage decrease limit).  Lanes stride over the element's combinations of
 // the sweep layout (c1 fastest), each keeping its best qualifying candidate under the
 // total order (degrees of freedom, map value, N1, N2, N3); a butterfly of cross-lane
 // exchanges leaves the minimum in every lane.
@@ -73,6 +73,7 @@ __device__ Cand element_best(const int P[3], int64_t off, const SelectMaps &maps
 __global__ __launch_bounds__(256) void k_select(const ElemInfo *__restrict__ el, int E,
                                                 const int64_t *__restrict__ combo_off, SelectMaps maps, int nst,
                                                 double tau_max, int nmin, int nmax, int approach,
+                                                const int32_t *__restrict__ prev, int max_decrease,
                                                 int32_t *__restrict__ orders) {
     const int p = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
@@ -100,6 +101,11 @@ __global__ __launch_bounds__(256) void k_select(const ElemInfo *__restrict__ el,
 #pragma unroll
             for (int d = 0; d < 3; ++d) out[d] = max(out[d], N[d]);
         }
+    }
+    if (prev) {  // at most max_decrease lower than the current degrees
+        const int32_t *pv = prev + 3 * (int64_t)e.nat;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) out[d] = max(out[d], min(nmax, pv[d] - max_decrease));
     }
     if (lane == 0) {
         int32_t *o = orders + 3 * (int64_t)e.nat;
@@ -141,14 +147,15 @@ __global__ __launch_bounds__(256) void k_jump(const int32_t *__restrict__ cur, i
 }
 
 hipError_t launch_select(const ElemInfo *el, int E, const int64_t *combo_off, const double *const *maps, int nst,
-                         double tau_max, int nmin, int nmax, int approach, int jump, int nx, int ny, int nz,
-                         int periodic, int32_t *orders, int32_t *tmp, hipStream_t s) {
+                         double tau_max, int nmin, int nmax, int approach, const int32_t *prev, int max_decrease,
+                         int jump, int nx, int ny, int nz, int periodic, int32_t *orders, int32_t *tmp,
+                         hipStream_t s) {
     if (E == 0) return hipSuccess;
     SelectMaps m{};
     for (int i = 0; i < nst; ++i) m.p[i] = maps[i];
     const int blocks = (int)((E * 64LL + 255) / 256);
     hipLaunchKernelGGL(k_select, dim3(blocks), dim3(256), 0, s, el, E, combo_off, m, nst, tau_max, nmin, nmax,
-                       approach, orders);
+                       approach, prev, max_decrease, orders);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess || jump == 0) return err;
     // an even number of steps (at least nmax) ends in orders

@@ -26,9 +26,15 @@ namespace dgt {
 // is staged with coalesced loads, then the three sum-factorisation passes run over all
 // five variables at once.  Dynamic LDS: sI [I1 | I2 | I3], sA [5][c1][f2 f3],
 // sB [5][f1 f2 f3] (the staged block) and later [5][c1 c2][f3].
+// PROJECT: the solution transfer onto another order map (Section 2.4.1): the "coarse"
+// element is the target, of any orders; per direction the operator is the
+// interpolation where the order rises or stays and the exact L2 projection where it
+// falls; the source element is found through the source plan's natural -> plan index
+// (fine_of), one field (Q).
 constexpr int RS_WG = 256;
 constexpr int RS_TAB = 3 * NNMAX * NNMAX;
 
+template <bool PROJECT>
 __global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ fine_of,
                                                     const ElemInfo *__restrict__ cel,
                                                     const ElemInfo *__restrict__ fel, const double *__restrict__ u,
@@ -40,20 +46,21 @@ __global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ 
     double *sI = lds, *sA = lds + RS_TAB, *sB = lds + RS_TAB + capA;
     const int p = xcd_remap(blockIdx.x, gridDim.x);
     const ElemInfo C = cel[p];
-    const ElemInfo F = fel[fine_of[p]];
+    const ElemInfo F = fel[fine_of[PROJECT ? C.nat : p]];
     const int f1 = F.n[0], f2 = F.n[1], f3 = F.n[2], nef = f1 * f2 * f3;
     const int c1 = C.n[0], c2 = C.n[1], c3 = C.n[2], nec = c1 * c2 * c3;
     const int tid = threadIdx.x;
     double *I1 = sI, *I2 = sI + c1 * f1, *I3 = I2 + c2 * f2;
     {
-        const double *g1 = tab + T_I + moff(c1 - 1, f1 - 1), *g2 = tab + T_I + moff(c2 - 1, f2 - 1);
-        const double *g3 = tab + T_I + moff(c3 - 1, f3 - 1);
+        auto op = [&](int c, int f) { return tab + (PROJECT && c < f ? T_P : T_I) + moff(c - 1, f - 1); };
+        const double *g1 = op(c1, f1), *g2 = op(c2, f2);
+        const double *g3 = op(c3, f3);
         for (int t = tid; t < c1 * f1; t += RS_WG) I1[t] = g1[t];
         for (int t = tid; t < c2 * f2; t += RS_WG) I2[t] = g2[t];
         for (int t = tid; t < c3 * f3; t += RS_WG) I3[t] = g3[t];
     }
     const int nA = c1 * f2 * f3, nB = c1 * c2 * f3;
-    const int nfield = psi ? 3 : 2;
+    const int nfield = PROJECT ? 1 : psi ? 3 : 2;
     for (int field = 0; field < nfield; ++field) {
         const double *src = (field == 0 ? u : field == 1 ? dudt : psi) + NV * F.noff;
         double *dst = (field == 0 ? uc : field == 1 ? rdc : psic) + NV * C.noff;
@@ -99,12 +106,26 @@ hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *
     if (ncoarse == 0) return hipSuccess;
     const size_t lds = sizeof(double) * (size_t)(RS_TAB + capA + capB);
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_restrict, hipFuncAttributeMaxDynamicSharedMemorySize,
+        hipError_t e = hipFuncSetAttribute((const void *)k_restrict<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_restrict<false>, dim3(ncoarse), dim3(RS_WG), lds, s, fine_of, celems, felems, u, dudt, psi,
+                       uc, rdc, psic, tab, capA);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const int32_t *src_inv, int ntarget, const ElemInfo *tel, const ElemInfo *sel,
+                          const double *u, double *ut, const double *tab, int capA, int capB, hipStream_t s) {
+    if (ntarget == 0) return hipSuccess;
+    const size_t lds = sizeof(double) * (size_t)(RS_TAB + capA + capB);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_restrict<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_restrict, dim3(ncoarse), dim3(RS_WG), lds, s, fine_of, celems, felems, u, dudt, psi, uc,
-                       rdc, psic, tab, capA);
+    hipLaunchKernelGGL(k_restrict<true>, dim3(ntarget), dim3(RS_WG), lds, s, src_inv, tel, sel, u, nullptr, nullptr,
+                       ut, nullptr, nullptr, tab, capA);
     return hipGetLastError();
 }
 
