@@ -144,6 +144,15 @@ def main():
                                                               approach=2, jump=2), 10)
     sel_orders = dg.select_orders(plan, [ten_s] * 3, tau_max=tau_sel, nmin=1, nmax=8, approach=2, jump=2)
     sel_ndof = int(torch.prod(sel_orders.long() + 1, dim=1).sum())
+    # adaptation onto the selected map: plan rebuild (host tables, sort, faces, uploads)
+    # and the projection of the solution onto it
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    new_plan = dg.Plan(mesh, sel_orders.cpu().numpy())
+    torch.cuda.synchronize()
+    t_replan = (time.perf_counter() - t0) * 1e3
+    t_project = _timed(torch, stream, lambda: dg.project(plan, new_plan, u), 10)
+    proj_bytes = 40.0 * (n_fine + new_plan.n_nodes)
 
     flops_sweep = sweep_flops_per_element(8) * E
     t_sweep_ms = float(np.mean(t_swp))
@@ -178,6 +187,9 @@ def main():
             "select_degrees_ms": t_select,
             "select_note": "3 stages of the sweep map, approach 2, jump (b), tau_max = median map value",
             "selected_nodes": sel_ndof,
+            "adapt_replan_ms": t_replan,
+            "adapt_project_ms": t_project,
+            "adapt_project_hbm_frac": proj_bytes / (t_project * 1e-3) / 1e9 / PEAK_HBM_GBS,
         },
         "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,

@@ -212,6 +212,14 @@ typedef struct {
 dg_status dg_select_orders(dg_plan fine, const double *const *maps, int32_t nstages,
                            const dg_select_params *params, int32_t *orders, hipStream_t stream);
 
+/* Total truncation-error map of static adaptation (Section 2.4.2, eq. totalTruncMap with
+ * F_max): acc <- max(acc, map) entry by entry, over the sweep layout of the plan
+ * (dg_sweep_layout); a NaN in either operand gives NaN (it never qualifies in
+ * dg_select_orders).  Selecting from the accumulated map equals approach 2 over the
+ * individual stage maps.  acc, map: device double; they may be the same array.
+ * Errors: DG_EINVAL for null arguments.  Asynchronous on stream. */
+dg_status dg_map_fmax(dg_plan fine, double *acc, const double *map, hipStream_t stream);
+
 /* Solution transfer onto another order map of the same mesh (Section 2.4.1: after an
  * adaptation the solution is projected onto the new polynomial spaces).  Per element
  * and direction the 1D operator is the interpolation from the old to the new

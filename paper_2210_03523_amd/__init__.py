@@ -68,6 +68,7 @@ SIGNATURES = {
     "dg_tau_sweep": [_P, _P, _P, _P, _P, _P],
     "dg_select_orders": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_SelectParams), _P, _P],
     "dg_project": [_P, _P, _P, _P, _P],
+    "dg_map_fmax": [_P, _P, _P, _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_check": [],
     "dg_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)],
@@ -382,6 +383,17 @@ def select_orders(plan: Plan, maps, tau_max: float, nmin: int = 1, nmax: int = N
     arr = (_P * max(1, len(maps)))(*[_ptr(m).value for m in maps])
     _call("dg_select_orders", plan.handle, arr, len(maps), ctypes.byref(prm), _ptr(out), _stream())
     return out
+
+
+def map_fmax(plan: Plan, acc, m):
+    """acc <- max(acc, m) in place (F_max total map of static adaptation; NaN sticky)."""
+    torch = _torch()
+    n = int(plan.combo_offsets()[-1])
+    for t in (acc, m):
+        if t.dtype != torch.float64 or t.numel() != n:
+            raise DGError("maps must be float64 tensors in the sweep layout of the plan")
+    _call("dg_map_fmax", plan.handle, _ptr(acc), _ptr(m), _stream())
+    return acc
 
 
 def project(src: Plan, dst: Plan, u):

@@ -807,6 +807,12 @@ dg_status dg_select_orders(dg_plan p, const double *const *maps, int32_t nstages
     return DG_OK;
 }
 
+dg_status dg_map_fmax(dg_plan p, double *acc, const double *map, hipStream_t stream) {
+    if (!p || !acc || !map) return fail(DG_EINVAL, "null argument");
+    HIP_TRY(launch_map_fmax(acc, map, p->combo_off[p->E], stream));
+    return DG_OK;
+}
+
 dg_status dg_project(dg_plan from, dg_plan to, const double *u, double *ut, hipStream_t stream) {
     if (!from || !to || !u || !ut) return fail(DG_EINVAL, "null argument");
     if (from->mesh.nx != to->mesh.nx || from->mesh.ny != to->mesh.ny || from->mesh.nz != to->mesh.nz)
@@ -912,7 +918,8 @@ struct BatchKey {
 struct dg_batch_s {
     std::vector<dg_plan> plans;
     int dtype = DG_F64;
-    int tile_cap = 256, elem_grid = 1024, face_grid = 2048;
+    int tile_cap = 512, elem_grid = 1024, face_grid = 2048;
+    int shape = 1;  // element-kernel shape (launch_elem_batch); valid for every tile of <= 512 nodes
     int ntiles = 0, nfaces = 0;
     BatchTile *d_tiles = nullptr;
     int2 *d_faces = nullptr;
@@ -983,7 +990,7 @@ dg_status batch_pass(dg_batch b, const ProbDesc<T> *probs, EpiArgs epi, hipStrea
     const T *tab = std::is_same<T, double>::value ? (const T *)b->plans[0]->tabs.t64
                                                   : (const T *)b->plans[0]->tabs.t32;
     HIP_TRY(launch_face_batch<T>(b->d_faces, b->nfaces, probs, tab, b->face_grid, s));
-    HIP_TRY(launch_elem_batch<T>(b->d_tiles, b->ntiles, probs, tab, b->elem_grid, epi, s));
+    HIP_TRY(launch_elem_batch<T>(b->d_tiles, b->ntiles, probs, tab, b->elem_grid, b->shape, epi, s));
     return DG_OK;
 }
 
@@ -1028,8 +1035,18 @@ dg_status autotune(dg_batch b) {
     EpiArgs epi{};
     epi.mode = EPI_RESIDUAL;
     float best = 1e30f;
-    int bc = 256, be = cus, bf = 4 * cus;
-    for (int cap : {256, 512}) {
+    int bc = 512, be = cus, bf = 4 * cus, bs = 1;
+    // (tile capacity, element-kernel shape): 256 lanes x 1 node, 256 x 2, 512 x 1.  A
+    // tile holds at least one element, so the 256-node shape needs every element to fit.
+    int max_npe = 1;
+    for (dg_plan p : b->plans)
+        for (int e = 0; e < p->E; ++e)
+            max_npe = std::max(max_npe, (p->ord[3 * e] + 1) * (p->ord[3 * e + 1] + 1) * (p->ord[3 * e + 2] + 1));
+    const int cand[3][2] = {{256, 0}, {512, 1}, {512, 2}};
+    for (const auto &cs : cand) {
+        const int cap = cs[0];
+        if (cap < max_npe) continue;
+        b->shape = cs[1];
         if ((st = set_tiles(b, cap))) break;
         // persistent grids of a few waves per CU, or one workgroup per work item
         for (int eg : {2 * cus, 8 * cus, std::max(1, b->ntiles)})
@@ -1048,6 +1065,7 @@ dg_status autotune(dg_batch b) {
                     bc = cap;
                     be = eg;
                     bf = fg;
+                    bs = cs[1];
                 }
             }
     }
@@ -1059,6 +1077,7 @@ dg_status autotune(dg_batch b) {
     if (st) return st;
     b->elem_grid = be;
     b->face_grid = bf;
+    b->shape = bs;
     return set_tiles(b, bc);
 }
 

@@ -156,6 +156,7 @@ hipError_t launch_select(const ElemInfo *el, int E, const int64_t *combo_off, co
                          double tau_max, int nmin, int nmax, int approach, const int32_t *prev, int max_decrease,
                          int jump, int nx, int ny, int nz, int periodic, int32_t *orders, int32_t *tmp,
                          hipStream_t s);
+hipError_t launch_map_fmax(double *acc, const double *m, int64_t n, hipStream_t s);
 hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
                             const double *u, const double *dudt, const double *tab, Geom g, double gamma,
                             double *te_new, double *te_trad, hipStream_t s);
@@ -182,9 +183,10 @@ struct BatchTile {
 template <typename T>
 hipError_t launch_face_batch(const int2 *faces, int nfaces, const ProbDesc<T> *probs, const T *tab, int grid,
                              hipStream_t s);
+// shape: 0 = 256 lanes x 1 node, 1 = 256 x 2, 2 = 512 x 1 (tile capacity 256 for shape 0, 512 otherwise)
 template <typename T>
 hipError_t launch_elem_batch(const BatchTile *tiles, int ntiles, const ProbDesc<T> *probs, const T *tab, int grid,
-                             EpiArgs epi, hipStream_t s);
+                             int shape, EpiArgs epi, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_state(const ElemInfo *el, int E, T *u, hipStream_t s);
 

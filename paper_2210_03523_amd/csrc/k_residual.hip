@@ -826,11 +826,11 @@ __global__ __launch_bounds__(64) void k_face_batch(const int2 *__restrict__ face
     }
 }
 
-template <typename T, int BS>
+template <typename T, int BS, int NPT>
 __global__ __launch_bounds__(BS) void k_elem_batch(const BatchTile *__restrict__ tiles, int ntiles,
                                                    const ProbDesc<T> *__restrict__ probs, const T *__restrict__ tab,
                                                    EpiArgs epi0) {
-    __shared__ T sF[NV][BS];
+    __shared__ T sF[NV][BS * NPT];
     __shared__ T sD[3 * NNMAX * NNMAX];
     for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const BatchTile bt = tiles[i];
@@ -838,7 +838,8 @@ __global__ __launch_bounds__(BS) void k_elem_batch(const BatchTile *__restrict__
         EpiArgs epi = epi0;
         epi.out = pd.out;
         epi.g = pd.g;
-        elem_body<T, 1, false, BS, false>(Tile{bt.first, bt.count}, pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, epi, sF, sD);
+        elem_body<T, NPT, false, BS, false>(Tile{bt.first, bt.count}, pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, epi,
+                                           sF, sD);
         __syncthreads();
     }
 }
@@ -851,11 +852,25 @@ hipError_t launch_face_batch(const int2 *faces, int nfaces, const ProbDesc<T> *p
     return hipGetLastError();
 }
 
+// Element-kernel shapes of the batch (tiles of at most 256 or 512 nodes):
+// 0: 256 lanes x 1 node, 1: 256 lanes x 2 nodes, 2: 512 lanes x 1 node.
 template <typename T>
 hipError_t launch_elem_batch(const BatchTile *tiles, int ntiles, const ProbDesc<T> *probs, const T *tab, int grid,
-                             EpiArgs epi, hipStream_t s) {
+                             int shape, EpiArgs epi, hipStream_t s) {
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_elem_batch<T, 2 * WG>), dim3(grid), dim3(2 * WG), 0, s, tiles, ntiles, probs, tab, epi);
+    switch (shape) {
+        case 0:
+            hipLaunchKernelGGL((k_elem_batch<T, WG, 1>), dim3(grid), dim3(WG), 0, s, tiles, ntiles, probs, tab, epi);
+            break;
+        case 1:
+            hipLaunchKernelGGL((k_elem_batch<T, WG, 2>), dim3(grid), dim3(WG), 0, s, tiles, ntiles, probs, tab, epi);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_elem_batch<T, 2 * WG, 1>), dim3(grid), dim3(2 * WG), 0, s, tiles, ntiles, probs,
+                               tab, epi);
+            break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -880,9 +895,9 @@ template hipError_t launch_face_batch<double>(const int2 *, int, const ProbDesc<
                                               hipStream_t);
 template hipError_t launch_face_batch<float>(const int2 *, int, const ProbDesc<float> *, const float *, int,
                                              hipStream_t);
-template hipError_t launch_elem_batch<double>(const BatchTile *, int, const ProbDesc<double> *, const double *, int,
+template hipError_t launch_elem_batch<double>(const BatchTile *, int, const ProbDesc<double> *, const double *, int, int,
                                               EpiArgs, hipStream_t);
-template hipError_t launch_elem_batch<float>(const BatchTile *, int, const ProbDesc<float> *, const float *, int,
+template hipError_t launch_elem_batch<float>(const BatchTile *, int, const ProbDesc<float> *, const float *, int, int,
                                              EpiArgs, hipStream_t);
 template hipError_t launch_fill_state<double>(const ElemInfo *, int, double *, hipStream_t);
 template hipError_t launch_fill_state<float>(const ElemInfo *, int, float *, hipStream_t);

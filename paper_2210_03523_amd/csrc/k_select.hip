@@ -146,6 +146,23 @@ __global__ __launch_bounds__(256) void k_jump(const int32_t *__restrict__ cur, i
     for (int i = 0; i < 3; ++i) nxt[3 * e + i] = o[i];
 }
 
+// acc <- max(acc, m), NaN sticky (a NaN in either operand gives NaN)
+__global__ __launch_bounds__(256) void k_map_fmax(double *acc, const double *m, int64_t n) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double a = acc[i], b = m[i];
+    double r = b > a ? b : a;
+    if (b != b) r = b;
+    if (a != a) r = a;
+    acc[i] = r;
+}
+
+hipError_t launch_map_fmax(double *acc, const double *m, int64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_map_fmax, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, acc, m, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_select(const ElemInfo *el, int E, const int64_t *combo_off, const double *const *maps, int nst,
                          double tau_max, int nmin, int nmax, int approach, const int32_t *prev, int max_decrease,
                          int jump, int nx, int ny, int nz, int periodic, int32_t *orders, int32_t *tmp,

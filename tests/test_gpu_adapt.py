@@ -118,3 +118,32 @@ def test_dynamic_adaptation_two_stages():
         plan, orders = new_plan, new
         g = torch.empty_like(u)
         assert _rel(plan.to_natural(u), u_ref) < 1e-11
+
+
+def test_total_map_fmax():
+    """Static adaptation: the F_max total map accumulated on the GPU equals numpy's
+    NaN-propagating maximum, and selecting from it equals approach 2 over the stages."""
+    rng = np.random.default_rng(7)
+    mesh = wl.box_mesh((5, 4, 3))
+    orders = rng.integers(1, 10, (60, 3)).astype(np.int32)
+    plan = dg.Plan(mesh, orders)
+    n = int(plan.combo_offsets()[-1])
+    maps = []
+    for _ in range(4):
+        m = rng.integers(0, 12, n) / 8.0
+        m[rng.random(n) < 0.005] = np.nan
+        maps.append(m)
+    dev = [torch.from_numpy(m).cuda() for m in maps]
+    acc = dev[0].clone()
+    for m in dev[1:]:
+        dg.map_fmax(plan, acc, m)
+    exp = maps[0]
+    for m in maps[1:]:
+        exp = np.maximum(exp, m)
+    got = acc.cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(exp))
+    assert np.array_equal(got[~np.isnan(got)], exp[~np.isnan(exp)])
+    for jump in (0, 2):
+        a = dg.select_orders(plan, [acc], tau_max=0.7, nmin=1, nmax=9, approach=2, jump=jump)
+        b = dg.select_orders(plan, dev, tau_max=0.7, nmin=1, nmax=9, approach=2, jump=jump)
+        assert torch.equal(a, b)
