@@ -66,6 +66,9 @@ def _load():
             "orc_residual": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_int, ctypes.c_int],
             "orc_restrict": [ctypes.c_int, _I, _I, _D, _D],
             "orc_project": [ctypes.c_int, _I, _I, _D, _D],
+            "orc_bdf_weights": [ctypes.c_int, _D],
+            "orc_tau_dual": [ctypes.c_void_p, _I, _I, ctypes.POINTER(_D), ctypes.c_int, ctypes.c_double,
+                             ctypes.c_int, _D, _D],
             "orc_tau": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, _D, _D, _D, _D],
             "orc_num_combos": [_I],
             "orc_sweep": [ctypes.POINTER(_Mesh), _I, _D, _D, _I, ctypes.c_int, _D, _D],
@@ -231,6 +234,26 @@ def project(from_orders, to_orders, u):
     ut = np.zeros(5 * num_nodes(to))
     _check(_load().orc_project(E, _i(fo), _i(to), _d(u), _d(ut)), "project")
     return ut
+
+
+def bdf_weights(k: int) -> np.ndarray:
+    w = np.zeros(k + 1)
+    _check(_load().orc_bdf_weights(int(k), _d(w)), "bdf_weights")
+    return w
+
+
+def tau_dual(mesh: dict, fine_orders, coarse_orders, states, dt: float, isolated: bool = False):
+    """Dual time-stepping estimate from stored fine states [Q(t_{n+1}), Q(t_n), ...];
+    returns (tau_new, tau_trad) in the coarse layout."""
+    fo, co = _i32(fine_orders), _i32(coarse_orders)
+    st = [_f64(q) for q in states]
+    arr = (_D * len(st))(*[_d(q) for q in st])
+    nc = num_nodes(co)
+    tn, tt = np.zeros(5 * nc), np.zeros(5 * nc)
+    m = _mesh(mesh)
+    _check(_load().orc_tau_dual(ctypes.byref(m), _i(fo), _i(co), arr, len(st), float(dt), int(bool(isolated)),
+                                _d(tn), _d(tt)), "tau_dual")
+    return tn, tt
 
 
 def tau(mesh: dict, fine_orders, coarse_orders, u, dudt, isolated: bool = False):

@@ -1286,6 +1286,76 @@ int orc_sweep_ns(const orc_mesh *m, const int *orders, const double *u, const do
     return sweep_impl(m, orders, u, dudt, 1, mu, Pr, elems, nelems, te_new, te_trad);
 }
 
+/* Weights of the backward-difference rate at t_{n+1} from k+1 equally spaced samples
+ * Q(t_{n+1-j}), j = 0..k: the derivative at s = 0 of the Lagrange polynomial through the
+ * abscissae s_j = -j (in units of the step), w_j = l_j'(0). */
+int orc_bdf_weights(int k, double *w)
+{
+    if (k < 1 || k > 6) return -1;
+    for (int j = 0; j <= k; ++j) {
+        /* l_j(s) = prod_{m != j} (s - s_m) / (s_j - s_m); l_j'(0) = sum_{m != j} 1/(s_j - s_m) prod_{q != j,m} (0 - s_q)/(s_j - s_q) */
+        long double sj = -j, acc = 0.0L;
+        for (int m = 0; m <= k; ++m) {
+            if (m == j) continue;
+            long double term = 1.0L / (sj - (long double)(-m));
+            for (int q = 0; q <= k; ++q) {
+                if (q == j || q == m) continue;
+                term *= (0.0L - (long double)(-q)) / (sj - (long double)(-q));
+            }
+            acc += term;
+        }
+        w[j] = (double)acc;
+    }
+    return 0;
+}
+
+/* Dual time-stepping estimate (Section 2.3, item 2): the physical time derivative
+ * discretised by the backward difference of order nstates-1 over the stored fine
+ * solutions states[j] = Q^P(t_{n+1-j}) at step dt, applied to the sampled coarse
+ * solutions:  new form  tau_new = (delta_p/delta t)(I Q) + (M^N)^-1 F^N(I Q_0),
+ *             traditional tau_trad = J w_i w_j w_k tau_new  (coarse weights). */
+int orc_tau_dual(const orc_mesh *m, const int *fine_orders, const int *coarse_orders, const double *const *states,
+                 int nstates, double dt, int isolated, double *tau_new, double *tau_trad)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (check_mesh(m) || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
+    if (nstates < 2 || nstates > 7 || !(dt > 0.0)) return -1;
+    for (int i = 0; i < 3 * E; ++i)
+        if (coarse_orders[i] > fine_orders[i]) return -1;
+    double w[8];
+    orc_bdf_weights(nstates - 1, w);
+    long nc = orc_num_nodes(E, coarse_orders);
+    double *qc = malloc(sizeof(double) * NV * nc), *rate = calloc(NV * nc, sizeof(double));
+    for (int j = 0; j < nstates; ++j) {
+        orc_restrict(E, fine_orders, coarse_orders, states[j], qc);
+        for (long i = 0; i < NV * nc; ++i) rate[i] += w[j] * qc[i] / dt;
+    }
+    orc_restrict(E, fine_orders, coarse_orders, states[0], qc);
+    orc_residual(m, coarse_orders, qc, tau_new, 0, isolated);
+    long *offc = node_offsets(E, coarse_orders);
+    for (int e = 0; e < E; ++e) {
+        const int *o = coarse_orders + 3 * e;
+        int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+        double *Ja = malloc(sizeof(double) * 9 * ne), *Jn = malloc(sizeof(double) * ne);
+        elem_metrics(m, o, e, Ja, Jn);
+        for (int v = 0; v < NV; ++v)
+            for (int c = 0; c < n[2]; ++c)
+                for (int b = 0; b < n[1]; ++b)
+                    for (int a = 0; a < n[0]; ++a) {
+                        int node = a + n[0] * (b + n[1] * c);
+                        long x = NV * offc[e] + (long)v * ne + node;
+                        tau_new[x] += rate[x];
+                        tau_trad[x] = Jn[node] * g_w[o[0]][a] * g_w[o[1]][b] * g_w[o[2]][c] * tau_new[x];
+                    }
+        free(Ja);
+        free(Jn);
+    }
+    free(offc);
+    free(qc);
+    free(rate);
+    return 0;
+}
+
 int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_orders, const double *u,
                 const double *dudt, int isolated, const double *psi, double *eta)
 {

@@ -92,6 +92,15 @@ int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
             const double *u, const double *dudt, int isolated,
             double *tau_new, double *tau_trad, double *norms, double *varnorms);
 
+/* Backward-difference weights: rate at t_{n+1} = (1/dt) sum_j w[j] Q(t_{n+1-j}),
+ * j = 0..k (exact for polynomials of degree k in time). */
+int orc_bdf_weights(int k, double *w);
+/* Dual time-stepping estimate (Section 2.3, item 2) with the backward difference of
+ * order nstates-1 over stored fine solutions states[j] = Q^P(t_{n+1-j}):
+ * tau_new = (delta_p/delta t)(I Q) + (M^N)^-1 F^N(I Q_0); tau_trad = J w w w tau_new. */
+int orc_tau_dual(const orc_mesh *m, const int *fine_orders, const int *coarse_orders, const double *const *states,
+                 int nstates, double dt, int isolated, double *tau_new, double *tau_trad);
+
 /* Number of coarse combinations of an element: prod_d max(1, N_d - 1). */
 int orc_num_combos(const int *order3);
 /* Isolated sweep over every coarse combination (c1 fastest, then c2, then c3;
