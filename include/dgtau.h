@@ -234,6 +234,20 @@ dg_status dg_map_fmax(dg_plan fine, double *acc, const double *map, hipStream_t 
  * Asynchronous on stream. */
 dg_status dg_project(dg_plan from, dg_plan to, const double *u, double *ut, hipStream_t stream);
 
+/* Physical time derivative of the dual time-stepping estimate (Section 2.3, item 2):
+ * dudt = -(1/dt) sum_j b_j states[j], the backward difference of order nstates-1 at
+ * t_{n+1} over stored solutions states[j] = Q(t_{n+1-j}) on one plan (BDF1: b = (1, -1);
+ * BDF2: (3/2, -2, 1/2); BDF3: (11/6, -3, 3/2, -1/3)).  Passed as dudt to dg_tau_estimate
+ * or dg_tau_sweep it gives the dual time-stepping estimate
+ * (delta_p/delta t)(I Q) + (M^N)^-1 F^N(I Q_0) (the sampling I is linear and element-local;
+ * u of those calls is states[0]).
+ *   states: host array of nstates (2..4) device double pointers, plan layout.
+ *   dudt: device double, plan layout (5 n_nodes), not aliasing a state.
+ * Errors: DG_EINVAL for null arguments, nstates outside 2..4 or dt <= 0.
+ * Asynchronous on stream. */
+dg_status dg_bdf_rate(dg_plan plan, const double *const *states, int32_t nstates, double dt, double *dudt,
+                      hipStream_t stream);
+
 /* Vector-Jacobian product of the residual: out = (d r / d u)^T v, r the form and
  * operator of dg_residual (FP64 only).  Written by hand: transposed derivative
  * matrices, transposed lifting, transposed mortar interpolation and projection, and

@@ -69,6 +69,7 @@ SIGNATURES = {
     "dg_select_orders": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_SelectParams), _P, _P],
     "dg_project": [_P, _P, _P, _P, _P],
     "dg_map_fmax": [_P, _P, _P, _P],
+    "dg_bdf_rate": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_double, _P, _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_check": [],
     "dg_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)],
@@ -382,6 +383,20 @@ def select_orders(plan: Plan, maps, tau_max: float, nmin: int = 1, nmax: int = N
                         None if prev is None else _ptr(prev).value, int(max_decrease))
     arr = (_P * max(1, len(maps)))(*[_ptr(m).value for m in maps])
     _call("dg_select_orders", plan.handle, arr, len(maps), ctypes.byref(prm), _ptr(out), _stream())
+    return out
+
+
+def bdf_rate(plan: Plan, states, dt: float):
+    """dudt = -(delta_p/delta t) Q from stored states [Q(t_{n+1}), Q(t_n), ...] (2..4 of
+    them, float64 plan layout): the fine term of the dual time-stepping estimate."""
+    torch = _torch()
+    states = list(states)
+    for q in states:
+        if q.dtype != torch.float64 or q.numel() != 5 * plan.n_nodes:
+            raise DGError("states must be float64 states of the plan")
+    out = torch.empty(5 * plan.n_nodes, dtype=torch.float64, device="cuda")
+    arr = (_P * max(1, len(states)))(*[_ptr(q).value for q in states])
+    _call("dg_bdf_rate", plan.handle, arr, len(states), float(dt), _ptr(out), _stream())
     return out
 
 

@@ -807,6 +807,19 @@ dg_status dg_select_orders(dg_plan p, const double *const *maps, int32_t nstages
     return DG_OK;
 }
 
+dg_status dg_bdf_rate(dg_plan p, const double *const *states, int32_t nstates, double dt, double *dudt,
+                      hipStream_t stream) {
+    if (!p || !states || !dudt) return fail(DG_EINVAL, "null argument");
+    if (nstates < 2 || nstates > 4) return fail(DG_EINVAL, "nstates must be in 2..4");
+    if (!(dt > 0.0)) return fail(DG_EINVAL, "dt must be positive");
+    for (int j = 0; j < nstates; ++j) {
+        if (!states[j]) return fail(DG_EINVAL, "null state");
+        if (states[j] == dudt) return fail(DG_EINVAL, "dudt must not alias a state");
+    }
+    HIP_TRY(launch_bdf_rate(states, nstates, dt, (int64_t)NV * p->n_nodes, dudt, stream));
+    return DG_OK;
+}
+
 dg_status dg_map_fmax(dg_plan p, double *acc, const double *map, hipStream_t stream) {
     if (!p || !acc || !map) return fail(DG_EINVAL, "null argument");
     HIP_TRY(launch_map_fmax(acc, map, p->combo_off[p->E], stream));
