@@ -257,6 +257,36 @@ dg_status dg_bdf_rate(dg_plan plan, const double *const *states, int32_t nstates
 dg_status dg_residual_vjp(dg_plan plan, const double *u, const double *v, double *out, int32_t form,
                           int32_t isolated, hipStream_t stream);
 
+/* Adjoint solve (the adjoint problem behind the adjoint-weighted estimate: psi of
+ * dg_tau_estimate): (d r / d u)^T psi = g, r the residual of the given form and
+ * operator of dg_residual at the state u (box Euler plans), g e.g. dJ/du of
+ * dg_functional.  Restarted GMRES (modified Gram-Schmidt, Givens rotations) whose
+ * matrix-vector product is dg_residual_vjp; inner products are deterministic device
+ * reductions.  The problem must be non-singular: on fully periodic meshes the discrete
+ * conservation makes (d r / d u)^T singular, so use wall or far-field boundaries.
+ *   psi: device double, plan layout; initial guess in, solution out.
+ *   work: device double of dg_adjoint_workspace(plan, restart) values (caller-owned;
+ *         nothing is allocated here).
+ *   iters, relres (host, nullable): products done and the final ||g - A^T psi|| / ||g||.
+ * Stops at relres <= rtol or after max_iter products.  SYNCHRONOUS: the host drives the
+ * iteration and waits on stream for every inner product.
+ * Errors: DG_EINVAL (null arguments, restart outside 1..DG_ADJOINT_MAX_RESTART,
+ * negative max_iter or rtol, unknown form, psi overlapping u or g), DG_EUNSUPPORTED
+ * (Navier-Stokes or curved plans), DG_EHIP. */
+#define DG_ADJOINT_MAX_RESTART 200
+typedef struct {
+    int32_t restart;  /* Krylov vectors per cycle */
+    int32_t max_iter; /* largest number of matrix-vector products */
+    double rtol;      /* relative residual target */
+    int32_t form;     /* DG_FORM_NEW or DG_FORM_TRAD */
+    int32_t isolated;
+} dg_adjoint_params;
+
+dg_status dg_adjoint_workspace(dg_plan plan, int32_t restart, int64_t *doubles);
+dg_status dg_adjoint_solve(dg_plan plan, const double *u, const double *g, double *psi,
+                           const dg_adjoint_params *params, double *work, int32_t *iters,
+                           double *relres, hipStream_t stream);
+
 /* Pressure force along x on the slip walls (faces normal to x):
  *   J = sum over those faces of sum_{a,b} w_a w_b |Ja^1| p(Q_ab) n_x,
  * the quadrature of the face integral of p n_x with the face's own nodes.

@@ -39,6 +39,11 @@ class _MeshDesc(ctypes.Structure):
                 ("map_kind", ctypes.c_int32), ("map_amp", ctypes.c_double), ("geo_order", ctypes.c_int32 * 3)]
 
 
+class _AdjointParams(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double),
+                ("form", ctypes.c_int32), ("isolated", ctypes.c_int32)]
+
+
 class _SelectParams(ctypes.Structure):
     _fields_ = [("tau_max", ctypes.c_double), ("nmin", ctypes.c_int32), ("nmax", ctypes.c_int32),
                 ("approach", ctypes.c_int32), ("jump", ctypes.c_int32),
@@ -70,6 +75,9 @@ SIGNATURES = {
     "dg_project": [_P, _P, _P, _P, _P],
     "dg_map_fmax": [_P, _P, _P, _P],
     "dg_bdf_rate": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_double, _P, _P],
+    "dg_adjoint_workspace": [_P, ctypes.c_int32, _I64P],
+    "dg_adjoint_solve": [_P, _P, _P, _P, ctypes.POINTER(_AdjointParams), _P, _I32P,
+                         ctypes.POINTER(ctypes.c_double), _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_check": [],
     "dg_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)],
@@ -384,6 +392,27 @@ def select_orders(plan: Plan, maps, tau_max: float, nmin: int = 1, nmax: int = N
     arr = (_P * max(1, len(maps)))(*[_ptr(m).value for m in maps])
     _call("dg_select_orders", plan.handle, arr, len(maps), ctypes.byref(prm), _ptr(out), _stream())
     return out
+
+
+def adjoint_solve(plan: Plan, u, g, psi=None, restart: int = 30, max_iter: int = 2000, rtol: float = 1e-10,
+                  form: int = FORM_NEW, isolated: bool = False):
+    """Solve (dr/du)^T psi = g by restarted GMRES on the residual VJP; returns
+    (psi, iterations, relative residual).  psi (optional) is the initial guess."""
+    torch = _torch()
+    n = 5 * plan.n_nodes
+    for t in (u, g):
+        if t.dtype != torch.float64 or t.numel() != n:
+            raise DGError("u and g must be float64 states of the plan")
+    x = torch.zeros(n, dtype=torch.float64, device="cuda") if psi is None else psi.clone()
+    nw = ctypes.c_int64()
+    _call("dg_adjoint_workspace", plan.handle, int(restart), ctypes.byref(nw))
+    work = torch.empty(int(nw.value), dtype=torch.float64, device="cuda")
+    prm = _AdjointParams(int(restart), int(max_iter), float(rtol), int(form), int(bool(isolated)))
+    it = ctypes.c_int32()
+    rr = ctypes.c_double()
+    _call("dg_adjoint_solve", plan.handle, _ptr(u), _ptr(g), _ptr(x), ctypes.byref(prm), _ptr(work),
+          ctypes.byref(it), ctypes.byref(rr), _stream())
+    return x, int(it.value), float(rr.value)
 
 
 def bdf_rate(plan: Plan, states, dt: float):

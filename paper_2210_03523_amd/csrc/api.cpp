@@ -894,6 +894,112 @@ dg_status dg_residual_vjp(dg_plan p, const double *u, const double *v, double *o
     return DG_OK;
 }
 
+dg_status dg_adjoint_workspace(dg_plan p, int32_t restart, int64_t *doubles) {
+    if (!p || !doubles) return fail(DG_EINVAL, "null argument");
+    if (restart < 1 || restart > DG_ADJOINT_MAX_RESTART) return fail(DG_EINVAL, "restart must be in 1..200");
+    *doubles = (int64_t)(restart + 2) * NV * p->n_nodes + dot_partials() + 8;
+    return DG_OK;
+}
+
+// Restarted GMRES on A^T psi = g, A = d r / d Q (the residual of the given form), with
+// modified Gram-Schmidt and Givens rotations; the host holds the small Hessenberg system,
+// the device the Krylov vectors.  Workspace: V_0..V_m, one spare vector, the dot
+// partials and the dot result.
+dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *psi, const dg_adjoint_params *prm,
+                           double *work, int32_t *iters_out, double *relres_out, hipStream_t stream) {
+    if (!p || !u || !g || !psi || !prm || !work) return fail(DG_EINVAL, "null argument");
+    const int m = prm->restart;
+    if (m < 1 || m > DG_ADJOINT_MAX_RESTART) return fail(DG_EINVAL, "restart must be in 1..200");
+    if (prm->max_iter < 0 || !(prm->rtol >= 0.0)) return fail(DG_EINVAL, "max_iter >= 0 and rtol >= 0 required");
+    if (prm->form != DG_FORM_NEW && prm->form != DG_FORM_TRAD) return fail(DG_EINVAL, "unknown form");
+    if (p->ns || p->curved) return fail(DG_EUNSUPPORTED, "the adjoint solve uses the VJP of box Euler plans");
+    if (psi == g || psi == u) return fail(DG_EINVAL, "psi must not overlap u or g");
+    const int64_t n = (int64_t)NV * p->n_nodes;
+    double *V = work;                        // V_j = V + j n, j = 0..m
+    double *part = work + (int64_t)(m + 2) * n;
+    double *dres = part + dot_partials();
+    auto dot = [&](const double *a, const double *b, double *out) -> dg_status {
+        HIP_TRY(launch_dot(a, b, n, part, dres, stream));
+        HIP_TRY(hipMemcpyAsync(out, dres, sizeof(double), hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        return DG_OK;
+    };
+    auto matvec = [&](const double *v, double *out) {
+        return dg_residual_vjp(p, u, v, out, prm->form, prm->isolated, stream);
+    };
+    dg_status st;
+    double gn2 = 0.0;
+    if ((st = dot(g, g, &gn2))) return st;
+    const double gnorm = std::sqrt(gn2);
+    int iters = 0;
+    double relres = 0.0;
+    if (gnorm == 0.0) {
+        HIP_TRY(launch_axpby(0.0, g, 0.0, psi, n, stream));
+        if (iters_out) *iters_out = 0;
+        if (relres_out) *relres_out = 0.0;
+        return DG_OK;
+    }
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), sv(m + 1), y(m);
+    for (;;) {
+        // r = g - A^T psi in V_0
+        if ((st = matvec(psi, V + n))) return st;
+        HIP_TRY(launch_axpby(1.0, g, 0.0, V, n, stream));
+        HIP_TRY(launch_axpby(-1.0, V + n, 1.0, V, n, stream));
+        double b2 = 0.0;
+        if ((st = dot(V, V, &b2))) return st;
+        const double beta = std::sqrt(b2);
+        relres = beta / gnorm;
+        if (relres <= prm->rtol || iters >= prm->max_iter || beta == 0.0) break;
+        HIP_TRY(launch_axpby(1.0 / beta, V, 0.0, V, n, stream));
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(sv.begin(), sv.end(), 0.0);
+        sv[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && iters < prm->max_iter; ++j) {
+            double *vj = V + (int64_t)j * n, *w = V + (int64_t)(j + 1) * n;
+            if ((st = matvec(vj, w))) return st;
+            ++iters;
+            for (int i = 0; i <= j; ++i) {
+                double h = 0.0;
+                if ((st = dot(w, V + (int64_t)i * n, &h))) return st;
+                H[(size_t)i * m + j] = h;
+                HIP_TRY(launch_axpby(-h, V + (int64_t)i * n, 1.0, w, n, stream));
+            }
+            double h2 = 0.0;
+            if ((st = dot(w, w, &h2))) return st;
+            const double h1 = std::sqrt(h2);
+            H[(size_t)(j + 1) * m + j] = h1;
+            if (h1 > 0.0) HIP_TRY(launch_axpby(1.0 / h1, w, 0.0, w, n, stream));
+            // previous rotations on column j, then the one that zeroes H[j+1][j]
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+            const double r = std::hypot(a, b);
+            cs[j] = r > 0.0 ? a / r : 1.0;
+            sn[j] = r > 0.0 ? b / r : 0.0;
+            H[(size_t)j * m + j] = r;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            sv[j + 1] = -sn[j] * sv[j];
+            sv[j] = cs[j] * sv[j];
+            k = j + 1;
+            if (std::fabs(sv[j + 1]) <= prm->rtol * gnorm || h1 == 0.0) break;
+        }
+        // y = H^-1 s (upper triangular), psi += V y
+        for (int i = k - 1; i >= 0; --i) {
+            double t = sv[i];
+            for (int c = i + 1; c < k; ++c) t -= H[(size_t)i * m + c] * y[c];
+            y[i] = H[(size_t)i * m + i] != 0.0 ? t / H[(size_t)i * m + i] : 0.0;
+        }
+        for (int i = 0; i < k; ++i) HIP_TRY(launch_axpby(y[i], V + (int64_t)i * n, 1.0, psi, n, stream));
+    }
+    if (iters_out) *iters_out = iters;
+    if (relres_out) *relres_out = relres;
+    return DG_OK;
+}
+
 dg_status dg_functional(dg_plan p, const double *u, double *J, double *dJdu, hipStream_t stream) {
     if (!p || !u || !J) return fail(DG_EINVAL, "null argument");
     if (p->curved) return fail(DG_EUNSUPPORTED, "the functional is implemented for box elements");
