@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--n", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 256 MiB device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--only", choices=["c3", "c4", "c5"], default=None,
+                    help="run one secondary leg alone and print its JSON (for kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -69,6 +71,13 @@ def main():
     import paper_2210_03523_amd as dg
 
     torch.cuda.set_device(0)
+    if args.only:
+        stream = torch.cuda.current_stream()
+        leg = {"c3": lambda: c3_leg(dg, torch, stream, check=not args.no_cpu),
+               "c4": lambda: c4_leg(dg, torch, stream, check=not args.no_cpu),
+               "c5": lambda: c5_leg(dg, torch, stream, steps=5, warmup=1, check=not args.no_cpu)}[args.only]
+        print(json.dumps({"leg": args.only, "result": leg()}))
+        return
     if args.copy_probe:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -812,13 +812,18 @@ template hipError_t launch_ns_faces<float>(const Face *, int, const ElemInfo *, 
                                            const float *, Geom, PhysParams, hipStream_t);
 
 // ---------------------------------------------------------------------------- batches
-// Persistent forms: a fixed grid walks a cost-sorted work list (static cyclic
-// schedule, no atomics), so one launch covers every problem of a batch.
+// Persistent forms, so one launch covers every problem of a batch (no atomics).  Faces
+// (listed problem by problem, neighbours close together) go in contiguous ranges, one
+// per workgroup, and the workgroups of one XCD take neighbouring ranges, so both sides'
+// element blocks stay in that XCD's L2; element tiles (sorted by cost) go cyclically.
 template <typename T>
 __global__ __launch_bounds__(64) void k_face_batch(const int2 *__restrict__ faces, int nfaces,
                                                    const ProbDesc<T> *__restrict__ probs, const T *__restrict__ tab) {
     __shared__ FaceSmem<T, 64> sm;  // batches hold orders up to 7
-    for (int i = blockIdx.x; i < nfaces; i += gridDim.x) {
+    const int chunk = (nfaces + gridDim.x - 1) / gridDim.x;
+    const int i0 = xcd_remap(blockIdx.x, gridDim.x) * chunk;
+    const int i1 = min(nfaces, i0 + chunk);
+    for (int i = i0; i < i1; ++i) {
         const int2 pf = faces[i];
         const ProbDesc<T> pd = probs[pf.x];
         face_body<T, 64>(pd.faces[pf.y], pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, sm);
