@@ -66,7 +66,20 @@ __global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ 
         double *dst = (field == 0 ? uc : field == 1 ? rdc : psic) + NV * C.noff;
         // stage the fine block (the previous field's z-pass has finished reading sB)
         if (field > 0) __syncthreads();
-        for (int t = tid; t < NV * nef; t += RS_WG) sB[t] = src[t];
+        // eight coalesced loads in flight per lane before their LDS stores
+        for (int t0 = 0; t0 < NV * nef; t0 += 8 * RS_WG) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int t = t0 + tid + k * RS_WG;
+                v[k] = t < NV * nef ? src[t] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int t = t0 + tid + k * RS_WG;
+                if (t < NV * nef) sB[t] = v[k];
+            }
+        }
         __syncthreads();
         // x: sA[v][a + c1 jk] = sum_i I1[a,i] Q_v[i + f1 jk]
         for (int t = tid; t < NV * nA; t += RS_WG) {
