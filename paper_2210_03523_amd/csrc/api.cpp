@@ -116,7 +116,7 @@ struct dg_plan_s {
     int64_t *d_fmo = nullptr;
     // sweep of curved and Navier-Stokes plans: one task per (element, c1, c2, c3)
     int4 *d_ctasks = nullptr;
-    int nctasks = 0, capA = 0, capB = 0, capS = 0;
+    int nctasks = 0, capA = 0, capB = 0, capS = 0, max_nc = 0;
     // restriction from the fine plan (coarse plans): LDS staging capacities
     int rcapA = 0, rcapB = 0;
     // x-force functional: boundary faces on slip walls normal to x, and their partial sums
@@ -504,6 +504,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
             p->capA = std::max(p->capA, NFLD_SWEEP * std::max(m1 * f2 * f3, nc));
             p->capB = std::max(p->capB, std::max(NFLD_SWEEP * m1 * m2 * f3, 10 * nc));
             p->capS = std::max(p->capS, std::max(3 * NV * nc, 2 * WG));
+            p->max_nc = std::max(p->max_nc, nc);
             continue;
         }
         const int F = el[i].n[0];
@@ -774,7 +775,8 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *t
     }
     if (p->curved || p->ns) {
         HIP_TRY(launch_sweep_curved(p->d_ctasks, p->nctasks, p->d_el, p->d_combo_off, u, dudt, p->d_xyz, p->tabs.t64,
-                                    p->phys, p->capA, p->capB, p->capS, p->ns ? 1 : 0, te_new, te_trad, stream));
+                                    p->phys, p->capA, p->capB, p->capS, p->max_nc, p->ns ? 1 : 0, te_new, te_trad,
+                                    stream));
         return DG_OK;
     }
     for (int F = 2; F <= 8; ++F)

@@ -223,7 +223,7 @@ hipError_t launch_grad_curved(const Face *faces, const int64_t *fmo, const T *fm
                               hipStream_t s);
 hipError_t launch_sweep_curved(const int4 *tasks, int ntasks, const ElemInfo *el, const int64_t *combo_off,
                                const double *u, const double *dudt, const double *xyz, const double *tab,
-                               PhysParams ph, int capA, int capB, int capS, int viscous, double *te_new,
+                               PhysParams ph, int capA, int capB, int capS, int max_nc, int viscous, double *te_new,
                                double *te_trad, hipStream_t s);
 
 // Host tables (tables.cpp): fills T_TOT values.

@@ -463,7 +463,8 @@ template hipError_t launch_grad_curved<float>(const Face *, const int64_t *, con
 //   S: [15][nc] staging of products and contravariant fluxes (and of the reduction).
 constexpr int NFLD = NFLD_SWEEP;
 
-__global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ tasks, const ElemInfo *__restrict__ el,
+template <int BS, int NPT>
+__global__ __launch_bounds__(BS) void k_sweep_curved(const int4 *__restrict__ tasks, const ElemInfo *__restrict__ el,
                                                      const int64_t *__restrict__ combo_off,
                                                      const double *__restrict__ u, const double *__restrict__ dudt,
                                                      const double *__restrict__ xyz, const double *__restrict__ tab,
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
     // restriction, one direction at a time: sampling of the fine polynomial at the coarse nodes
     {
         const double *I1 = tab + T_I + moff(c[0], f1 - 1);
-        for (int r = tid; r < NFLD * m1 * f2 * f3; r += WG) {
+        for (int r = tid; r < NFLD * m1 * f2 * f3; r += BS) {
             const int a = r % m1, jk = (r / m1) % (f2 * f3), fld = r / (m1 * f2 * f3);
             const double *src = field(fld) + (int64_t)jk * f1;
             double acc = 0.0;
@@ -498,7 +499,7 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
     __syncthreads();
     {
         const double *I2 = tab + T_I + moff(c[1], f2 - 1);
-        for (int r = tid; r < NFLD * m1 * m2 * f3; r += WG) {
+        for (int r = tid; r < NFLD * m1 * m2 * f3; r += BS) {
             const int a = r % m1, b = (r / m1) % m2, k = (r / (m1 * m2)) % f3, fld = r / (m1 * m2 * f3);
             double acc = 0.0;
             for (int j = 0; j < f2; ++j) acc += I2[b * f2 + j] * A[((fld * f3 + k) * f2 + j) * m1 + a];
@@ -508,7 +509,7 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
     __syncthreads();
     {
         const double *I3 = tab + T_I + moff(c[2], f3 - 1);
-        for (int r = tid; r < NFLD * nc; r += WG) {
+        for (int r = tid; r < NFLD * nc; r += BS) {
             const int ab = r % (m1 * m2), cc = (r / (m1 * m2)) % m3, fld = r / nc;
             double acc = 0.0;
             for (int k = 0; k < f3; ++k) acc += I3[cc * f3 + k] * B[(fld * f3 + k) * m1 * m2 + ab];
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
     const double *Dm[3] = {tab + T_D + doff(c[0]), tab + T_D + doff(c[1]), tab + T_D + doff(c[2])};
     const int stride[3] = {1, m1, m1 * m2};
     // metric terms of the coarse element from its coordinates (cross-product form)
-    for (int t = tid; t < nc; t += WG) {
+    for (int t = tid; t < nc; t += BS) {
         const int idx[3] = {t % m1, (t / m1) % m2, t / (m1 * m2)};
         double a[3][3];
 #pragma unroll
@@ -543,8 +544,7 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
         B[9 * nc + t] = a[0][0] * B[0 * nc + t] + a[0][1] * B[1 * nc + t] + a[0][2] * B[2 * nc + t];
     }
     __syncthreads();
-    // at most two coarse nodes per thread (nc <= 2 * WG)
-    constexpr int NPT = 2;
+    // at most NPT coarse nodes per thread (nc <= NPT * BS)
     double G[NPT][3 * NV], V[NPT][NV];
 #pragma unroll
     for (int k = 0; k < NPT; ++k)
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
             for (int l = 0; l < 3; ++l) {
 #pragma unroll
                 for (int k = 0; k < NPT; ++k) {
-                    const int t = tid + k * WG;
+                    const int t = tid + k * BS;
                     if (t < nc)
 #pragma unroll
                         for (int v = 0; v < NV; ++v) S[v * nc + t] = B[(3 * d + l) * nc + t] * A[v * nc + t];
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < NPT; ++k) {
-                    const int t = tid + k * WG;
+                    const int t = tid + k * BS;
                     if (t >= nc) continue;
                     const int id = d == 0 ? t % m1 : (d == 1 ? (t / m1) % m2 : t / (m1 * m2));
                     const double *Drow = Dm[d] + id * mm[d];
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
             }
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int t = tid + k * WG;
+            const int t = tid + k * BS;
             if (t >= nc) continue;
             const double iJ = 1.0 / B[9 * nc + t];
 #pragma unroll
@@ -587,7 +587,7 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
     // contravariant fluxes Ja^d . (f^a - f^v), staged for all three directions
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int t = tid + k * WG;
+        const int t = tid + k * BS;
 #pragma unroll
         for (int v = 0; v < NV; ++v) V[k][v] = 0.0;
         if (t >= nc) continue;
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
     double mx0 = 0.0, mx1 = 0.0;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int t = tid + k * WG;
+        const int t = tid + k * BS;
         if (t >= nc) continue;
         const int idx[3] = {t % m1, (t / m1) % m2, t / (m1 * m2)};
 #pragma unroll
@@ -637,12 +637,12 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
     // workgroup maxima
     __syncthreads();
     S[tid] = mx0;
-    S[WG + tid] = mx1;
+    S[BS + tid] = mx1;
     __syncthreads();
-    for (int h = WG / 2; h > 0; h >>= 1) {
+    for (int h = BS / 2; h > 0; h >>= 1) {
         if (tid < h) {
             S[tid] = fmax(S[tid], S[tid + h]);
-            S[WG + tid] = fmax(S[WG + tid], S[WG + tid + h]);
+            S[BS + tid] = fmax(S[BS + tid], S[BS + tid + h]);
         }
         __syncthreads();
     }
@@ -650,24 +650,44 @@ __global__ __launch_bounds__(WG) void k_sweep_curved(const int4 *__restrict__ ta
         const int C1 = E.n[0] > 2 ? E.n[0] - 2 : 1, C2 = E.n[1] > 2 ? E.n[1] - 2 : 1;
         const int64_t slot = combo_off[tk.x] + (c[0] - 1) + (int64_t)C1 * ((c[1] - 1) + (int64_t)C2 * (c[2] - 1));
         te_new[slot] = S[0];
-        te_trad[slot] = S[WG];
+        te_trad[slot] = S[BS];
     }
+}
+
+// Workgroup shape from the largest combination: 128 lanes x 1 node up to 128 coarse
+// nodes, 256 x 1 up to 256, 256 x 2 up to 512 (the sweep's fine orders are at most 7).
+template <int BS, int NPT>
+static hipError_t launch_sweep_curved_bs(const int4 *tasks, int ntasks, const ElemInfo *el, const int64_t *combo_off,
+                                         const double *u, const double *dudt, const double *xyz, const double *tab,
+                                         PhysParams ph, int capA, int capB, int capS, int viscous, double *te_new,
+                                         double *te_trad, hipStream_t s) {
+    const size_t lds = sizeof(double) * (size_t)(capA + capB + capS);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_sweep_curved<BS, NPT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_sweep_curved<BS, NPT>), dim3(ntasks), dim3(BS), lds, s, tasks, el, combo_off, u, dudt, xyz,
+                       tab, ph, capA, capB, viscous, te_new, te_trad);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_curved(const int4 *tasks, int ntasks, const ElemInfo *el, const int64_t *combo_off,
                                const double *u, const double *dudt, const double *xyz, const double *tab,
-                               PhysParams ph, int capA, int capB, int capS, int viscous, double *te_new,
+                               PhysParams ph, int capA, int capB, int capS, int max_nc, int viscous, double *te_new,
                                double *te_trad, hipStream_t s) {
     if (ntasks == 0) return hipSuccess;
-    const size_t lds = sizeof(double) * (size_t)(capA + capB + capS);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_sweep_curved, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_sweep_curved, dim3(ntasks), dim3(WG), lds, s, tasks, el, combo_off, u, dudt, xyz, tab, ph,
-                       capA, capB, viscous, te_new, te_trad);
-    return hipGetLastError();
+    if (capS < 2 * WG) return hipErrorInvalidValue;  // the maxima reduction stages 2 BS values
+    if (max_nc <= 128)
+        return launch_sweep_curved_bs<128, 1>(tasks, ntasks, el, combo_off, u, dudt, xyz, tab, ph, capA, capB, capS,
+                                              viscous, te_new, te_trad, s);
+    if (max_nc <= 256)
+        return launch_sweep_curved_bs<256, 1>(tasks, ntasks, el, combo_off, u, dudt, xyz, tab, ph, capA, capB, capS,
+                                              viscous, te_new, te_trad, s);
+    if (max_nc <= 512)
+        return launch_sweep_curved_bs<256, 2>(tasks, ntasks, el, combo_off, u, dudt, xyz, tab, ph, capA, capB, capS,
+                                              viscous, te_new, te_trad, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace dgt
