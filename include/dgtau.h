@@ -39,7 +39,8 @@ enum {
     DG_EINVAL = -1,       /* invalid argument (null pointer, bad order, size mismatch) */
     DG_ENOMEM = -2,       /* device or host allocation failed (plan creation only) */
     DG_EHIP = -3,         /* a HIP runtime call failed; message in dg_last_error() */
-    DG_EUNSUPPORTED = -4  /* valid request this build does not implement */
+    DG_EUNSUPPORTED = -4, /* valid request this build does not implement */
+    DG_ENONPHYSICAL = -5  /* a state holds non-physical values (dg_check_state) */
 };
 
 enum { DG_BC_PERIODIC = 0, DG_BC_SLIP_WALL = 1, DG_BC_FARFIELD = 2 };
@@ -332,6 +333,16 @@ dg_status dg_batch_rk3_step(dg_batch batch, void *const *u, void *const *g, doub
 
 /* Synchronise the device and report a deferred HIP error, if any. */
 dg_status dg_check(void);
+
+/* Admissibility of a state: counts the nodes where rho <= 0, the pressure
+ * (gamma - 1)(rho E - |rho u|^2 / (2 rho)) <= 0, or any variable is not finite (the
+ * Euler and Navier-Stokes fluxes are defined only for positive density and pressure).
+ *   u: device array of 5 n_nodes values of type dtype (DG_F64 or DG_F32), plan layout.
+ *   bad (host, nullable): receives the count.
+ * Returns DG_ENONPHYSICAL when the count is positive.  SYNCHRONOUS on stream (the count
+ * is read back); the reduction is deterministic and allocates nothing (it uses the
+ * plan's scratch, so one plan runs one check at a time). */
+dg_status dg_check_state(dg_plan plan, const void *u, int32_t dtype, int64_t *bad, hipStream_t stream);
 
 /* Message of the last non-OK status on this thread ("" if none). */
 const char *dg_last_error(void);

@@ -80,6 +80,7 @@ SIGNATURES = {
                          ctypes.POINTER(ctypes.c_double), _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_check": [],
+    "dg_check_state": [_P, _P, ctypes.c_int32, _I64P, _P],
     "dg_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)],
     "dg_batch_destroy": [_P],
     "dg_batch_schedule": [_P, _I32P, _I32P, _I32P],
@@ -449,6 +450,14 @@ def project(src: Plan, dst: Plan, u):
     ut = torch.empty(5 * dst.n_nodes, dtype=torch.float64, device="cuda")
     _call("dg_project", src.handle, dst.handle, _ptr(u), _ptr(ut), _stream())
     return ut
+
+
+def check_state(plan: Plan, u) -> int:
+    """Number of non-physical nodes of u (rho <= 0, p <= 0 or not finite); raises DGError
+    (status -5) when there are any."""
+    n = ctypes.c_int64()
+    _call("dg_check_state", plan.handle, _ptr(u), _dtype_code(u), ctypes.byref(n), _stream())
+    return int(n.value)
 
 
 def rk3_step(plan: Plan, u, g, dt: float, nsteps: int = 1):

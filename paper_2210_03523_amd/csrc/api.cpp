@@ -131,6 +131,7 @@ struct dg_plan_s {
     int32_t *d_iso = nullptr;           // isotropic elements grouped by fine node count F
     int32_t *d_sel = nullptr;           // degree selection: [E][3] intermediate of the jump steps
     int32_t *d_inv = nullptr;           // natural element -> plan position
+    double *d_red = nullptr;            // reduction partials of dg_check_state
     int iso_first[NNMAX + 1] = {0}, iso_count[NNMAX + 1] = {0};
     // RK3 graphs
     hipStream_t cap_stream = nullptr;
@@ -154,7 +155,7 @@ void destroy_plan(dg_plan p) {
     void *bufs[] = {p->d_el,    p->d_faces,  p->d_tiles,  p->d_ff,     p->d_dudt,   p->d_fine_of, p->d_uc,
                     p->d_rdc,   p->d_psic,   p->d_combo_off, p->d_tasks, p->d_iso,  p->d_wallx,   p->d_part,
                     p->d_grad,  p->d_xyz,    p->d_met64,  p->d_fmet64, p->d_met32,  p->d_fmet32,  p->d_fmo,
-                    p->d_ctasks, p->d_sel, p->d_inv};
+                    p->d_ctasks, p->d_sel, p->d_inv, p->d_red};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -545,6 +546,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
         hipMalloc((void **)&p->d_part, sizeof(double) * std::max(1, p->nwallx)) != hipSuccess ||
         hipMalloc((void **)&p->d_dudt, sizeof(double) * NV * p->n_nodes) != hipSuccess ||
         hipMalloc((void **)&p->d_sel, sizeof(int32_t) * 3 * std::max(1, E)) != hipSuccess ||
+        hipMalloc((void **)&p->d_red, sizeof(double) * (dot_partials() + 8)) != hipSuccess ||
         hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
         (p->ns && hipMalloc(&p->d_grad, sizeof(double) * 3 * NV * p->n_nodes) != hipSuccess)) {
         destroy_plan(p);
@@ -1007,6 +1009,22 @@ dg_status dg_functional(dg_plan p, const double *u, double *J, double *dJdu, hip
     if (p->curved) return fail(DG_EUNSUPPORTED, "the functional is implemented for box elements");
     HIP_TRY(launch_functional(p->d_faces, p->d_wallx, p->nwallx, p->d_el, u, p->tabs.t64, p->geom, p->mesh.gamma,
                               p->d_part, J, dJdu, (int64_t)NV * p->n_nodes, stream));
+    return DG_OK;
+}
+
+dg_status dg_check_state(dg_plan p, const void *u, int32_t dtype, int64_t *bad, hipStream_t stream) {
+    if (!p || !u) return fail(DG_EINVAL, "null argument");
+    if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_EINVAL, "unknown dtype");
+    double *part = p->d_red, *out = p->d_red + dot_partials();
+    if (dtype == DG_F64)
+        HIP_TRY(launch_count_bad<double>(p->d_el, p->E, (const double *)u, p->mesh.gamma, part, out, stream));
+    else
+        HIP_TRY(launch_count_bad<float>(p->d_el, p->E, (const float *)u, p->mesh.gamma, part, out, stream));
+    double cnt = 0.0;
+    HIP_TRY(hipMemcpyAsync(&cnt, out, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (bad) *bad = (int64_t)cnt;
+    if (cnt > 0.0) return fail(DG_ENONPHYSICAL, "non-physical state: " + std::to_string((int64_t)cnt) + " nodes");
     return DG_OK;
 }
 

@@ -162,6 +162,11 @@ hipError_t launch_map_fmax(double *acc, const double *m, int64_t n, hipStream_t 
 hipError_t launch_dot(const double *a, const double *b, int64_t n, double *part, double *out, hipStream_t s);
 hipError_t launch_axpby(double alpha, const double *x, double beta, double *y, int64_t n, hipStream_t s);
 int dot_partials();
+// Count of non-physical nodes (rho <= 0, p <= 0 or not finite) into out[0]; part holds
+// dot_partials() doubles of scratch.
+template <typename T>
+hipError_t launch_count_bad(const ElemInfo *el, int E, const T *u, double gamma, double *part, double *out,
+                            hipStream_t s);
 // dudt = -(1/dt) sum_j b_j states[j], backward difference of order nst-1 (nst in 2..4)
 hipError_t launch_bdf_rate(const double *const *states, int nst, double dt, int64_t n, double *dudt, hipStream_t s);
 hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,

@@ -58,4 +58,41 @@ hipError_t launch_axpby(double alpha, const double *x, double beta, double *y, i
 
 int dot_partials() { return KR_BLOCKS; }
 
+// Non-physical nodes of a state [elem][var][node] (plan layout): partial counts per
+// workgroup over fixed node ranges, then summed in a fixed order (as doubles: exact for
+// counts below 2^53).
+template <typename T>
+__global__ __launch_bounds__(KR_WG) void k_bad_part(const ElemInfo *__restrict__ el, int E, const T *__restrict__ u,
+                                                    double gm1, double *__restrict__ part) {
+    __shared__ double sm[KR_WG / 64];
+    double cnt = 0.0;
+    for (int p = blockIdx.x; p < E; p += KR_BLOCKS) {
+        const ElemInfo e = el[p];
+        const int ne = e.n[0] * e.n[1] * e.n[2];
+        const T *q = u + NV * e.noff;
+        for (int t = threadIdx.x; t < ne; t += KR_WG) {
+            const double r = (double)q[t], mx = (double)q[ne + t], my = (double)q[2 * ne + t],
+                         mz = (double)q[3 * ne + t], en = (double)q[4 * ne + t];
+            const double pr = gm1 * (en - 0.5 * (mx * mx + my * my + mz * mz) / r);
+            const bool finite = isfinite(r) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(en);
+            if (!(finite && r > 0.0 && pr > 0.0)) cnt += 1.0;
+        }
+    }
+    const double s = block_sum(cnt, sm);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T>
+hipError_t launch_count_bad(const ElemInfo *el, int E, const T *u, double gamma, double *part, double *out,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_bad_part<T>, dim3(KR_BLOCKS), dim3(KR_WG), 0, s, el, E, u, gamma - 1.0, part);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(KR_WG), 0, s, part, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_count_bad<double>(const ElemInfo *, int, const double *, double, double *, double *,
+                                             hipStream_t);
+template hipError_t launch_count_bad<float>(const ElemInfo *, int, const float *, double, double *, double *,
+                                            hipStream_t);
+
 }  // namespace dgt

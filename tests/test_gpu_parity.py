@@ -241,3 +241,23 @@ def test_c2_workload_sampled():
     full = _sweep_natural(plan, ten)
     got = np.concatenate([full[216 * e:216 * (e + 1)] for e in sample])
     assert err(got, ten_r, s) < TOL64
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_check_state(dtype):
+    """Admissibility check: a valid state passes; negative density, negative pressure and
+    a NaN are each counted once."""
+    mesh, orders, u, _ = _case((3, 2, 2), 1, 5, 11, (0,) * 6, wl.ROE, (1.0, 1.0, 1.0))
+    plan = dg.Plan(mesh, orders)
+    assert dg.check_state(plan, plan.to_plan(u, dtype=dtype)) == 0
+    offs = wl.node_offsets(orders)
+    bad = u.copy()
+    ne0 = int(offs[1] - offs[0])
+    bad[0] = -1.0                              # density of node 0, element 0
+    e3 = 5 * offs[3]
+    ne3 = int(offs[4] - offs[3])
+    bad[e3 + 4 * ne3 + 1] = 0.0                # rho E = 0: negative pressure at node 1
+    e7 = 5 * offs[7]
+    bad[e7 + 2 * int(offs[8] - offs[7])] = np.nan
+    with pytest.raises(dg.DGError, match="non-physical state: 3 nodes"):
+        dg.check_state(plan, plan.to_plan(bad, dtype=dtype))
