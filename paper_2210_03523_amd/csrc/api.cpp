@@ -616,6 +616,13 @@ dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s) {
 }
 
 bool aligned(const void *x) { return ((uintptr_t)x & 15) == 0; }
+// every non-null device array argument 16-byte aligned
+template <typename... P>
+bool all_aligned(P... p) {
+    return ((p == nullptr || aligned((const void *)p)) && ...);
+}
+#define DG_ALIGNED(...) \
+    if (!all_aligned(__VA_ARGS__)) return fail(DG_EINVAL, "device arrays must be 16-byte aligned")
 
 }  // namespace
 
@@ -678,6 +685,7 @@ dg_status dg_plan_layout(dg_plan p, int64_t *n_elems, int64_t *n_nodes, int64_t 
 
 dg_status dg_node_coords(dg_plan p, double *xyz, hipStream_t stream) {
     if (!p || !xyz) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(xyz);
     if (p->d_xyz) {
         HIP_TRY(hipMemcpyAsync(xyz, p->d_xyz, sizeof(double) * 3 * p->n_nodes, hipMemcpyDeviceToDevice, stream));
         return DG_OK;
@@ -688,6 +696,7 @@ dg_status dg_node_coords(dg_plan p, double *xyz, hipStream_t stream) {
 
 dg_status dg_plan_metrics(dg_plan p, double *met, hipStream_t stream) {
     if (!p || !met) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(met);
     if (p->curved) {
         HIP_TRY(hipMemcpyAsync(met, p->d_met64, sizeof(double) * 10 * p->n_nodes, hipMemcpyDeviceToDevice, stream));
         return DG_OK;
@@ -727,6 +736,7 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
                           double *tau_new, double *tau_trad, double *norms, const double *psi, double *eta,
                           hipStream_t stream) {
     if (!fine || !coarse || !u) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(u, dudt, tau_new, tau_trad, norms, psi, eta);
     if (coarse->parent != fine) return fail(DG_EINVAL, "coarse plan was not built from this fine plan");
     if (fine->curved && !isolated)
         return fail(DG_EUNSUPPORTED, "on curved meshes the tau-estimate is the isolated one");
@@ -764,6 +774,7 @@ dg_status dg_sweep_layout(dg_plan p, int64_t *combo_offset) {
 dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *te_new, double *te_trad,
                        hipStream_t stream) {
     if (!p || !u || !te_new || !te_trad) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(u, dudt, te_new, te_trad);
     if (p->max_order > 8) return fail(DG_EUNSUPPORTED, "the sweep supports fine orders up to 8");
     if ((p->curved || p->ns) && p->max_order > 7)
         return fail(DG_EUNSUPPORTED, "the sweep of curved and Navier-Stokes plans supports fine orders up to 7");
@@ -793,9 +804,12 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *t
 dg_status dg_select_orders(dg_plan p, const double *const *maps, int32_t nstages, const dg_select_params *prm,
                            int32_t *orders, hipStream_t stream) {
     if (!p || !maps || !prm || !orders) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(orders, prm->prev);
     if (nstages < 1 || nstages > DG_SELECT_MAX_STAGES) return fail(DG_EINVAL, "nstages must be in 1..32");
-    for (int s = 0; s < nstages; ++s)
+    for (int s = 0; s < nstages; ++s) {
         if (!maps[s]) return fail(DG_EINVAL, "null map");
+        DG_ALIGNED(maps[s]);
+    }
     if (prm->approach != 1 && prm->approach != 2) return fail(DG_EINVAL, "approach must be 1 or 2");
     if (prm->jump < 0 || prm->jump > 2) return fail(DG_EINVAL, "jump must be 0, 1 or 2");
     if (prm->nmin < 1 || prm->nmin > prm->nmax || prm->nmax > DG_NMAX)
@@ -814,10 +828,12 @@ dg_status dg_select_orders(dg_plan p, const double *const *maps, int32_t nstages
 dg_status dg_bdf_rate(dg_plan p, const double *const *states, int32_t nstates, double dt, double *dudt,
                       hipStream_t stream) {
     if (!p || !states || !dudt) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(dudt);
     if (nstates < 2 || nstates > 4) return fail(DG_EINVAL, "nstates must be in 2..4");
     if (!(dt > 0.0)) return fail(DG_EINVAL, "dt must be positive");
     for (int j = 0; j < nstates; ++j) {
         if (!states[j]) return fail(DG_EINVAL, "null state");
+        DG_ALIGNED(states[j]);
         if (states[j] == dudt) return fail(DG_EINVAL, "dudt must not alias a state");
     }
     HIP_TRY(launch_bdf_rate(states, nstates, dt, (int64_t)NV * p->n_nodes, dudt, stream));
@@ -826,12 +842,14 @@ dg_status dg_bdf_rate(dg_plan p, const double *const *states, int32_t nstates, d
 
 dg_status dg_map_fmax(dg_plan p, double *acc, const double *map, hipStream_t stream) {
     if (!p || !acc || !map) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(acc, map);
     HIP_TRY(launch_map_fmax(acc, map, p->combo_off[p->E], stream));
     return DG_OK;
 }
 
 dg_status dg_project(dg_plan from, dg_plan to, const double *u, double *ut, hipStream_t stream) {
     if (!from || !to || !u || !ut) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(u, ut);
     if (from->mesh.nx != to->mesh.nx || from->mesh.ny != to->mesh.ny || from->mesh.nz != to->mesh.nz)
         return fail(DG_EINVAL, "plans of different meshes");
     int capA = 1, capB = 1;
@@ -849,6 +867,7 @@ dg_status dg_rk3_step(dg_plan p, void *u, void *g, double dt, int32_t nsteps, in
     static const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
     static const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
     if (!p || !u || !g) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(u, g);
     if (u == g) return fail(DG_EINVAL, "u and g must not overlap");
     if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_EINVAL, "unknown dtype");
     if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
@@ -885,6 +904,7 @@ dg_status dg_rk3_step(dg_plan p, void *u, void *g, double dt, int32_t nsteps, in
 dg_status dg_residual_vjp(dg_plan p, const double *u, const double *v, double *out, int32_t form,
                           int32_t isolated, hipStream_t stream) {
     if (!p || !u || !v || !out) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(u, v, out);
     if (out == u || out == v) return fail(DG_EINVAL, "out must not overlap u or v");
     if (form != DG_FORM_NEW && form != DG_FORM_TRAD) return fail(DG_EINVAL, "unknown form");
     if (p->ns) return fail(DG_EUNSUPPORTED, "the VJP is implemented for the Euler equations");
@@ -901,7 +921,8 @@ dg_status dg_residual_vjp(dg_plan p, const double *u, const double *v, double *o
 dg_status dg_adjoint_workspace(dg_plan p, int32_t restart, int64_t *doubles) {
     if (!p || !doubles) return fail(DG_EINVAL, "null argument");
     if (restart < 1 || restart > DG_ADJOINT_MAX_RESTART) return fail(DG_EINVAL, "restart must be in 1..200");
-    *doubles = (int64_t)(restart + 2) * NV * p->n_nodes + dot_partials() + 8;
+    const int64_t ld = ((int64_t)NV * p->n_nodes + 1) & ~(int64_t)1;  // vectors 16-byte aligned
+    *doubles = (int64_t)(restart + 2) * ld + dot_partials() + 8;
     return DG_OK;
 }
 
@@ -912,6 +933,7 @@ dg_status dg_adjoint_workspace(dg_plan p, int32_t restart, int64_t *doubles) {
 dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *psi, const dg_adjoint_params *prm,
                            double *work, int32_t *iters_out, double *relres_out, hipStream_t stream) {
     if (!p || !u || !g || !psi || !prm || !work) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(u, g, psi, work);
     const int m = prm->restart;
     if (m < 1 || m > DG_ADJOINT_MAX_RESTART) return fail(DG_EINVAL, "restart must be in 1..200");
     if (prm->max_iter < 0 || !(prm->rtol >= 0.0)) return fail(DG_EINVAL, "max_iter >= 0 and rtol >= 0 required");
@@ -919,8 +941,9 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
     if (p->ns || p->curved) return fail(DG_EUNSUPPORTED, "the adjoint solve uses the VJP of box Euler plans");
     if (psi == g || psi == u) return fail(DG_EINVAL, "psi must not overlap u or g");
     const int64_t n = (int64_t)NV * p->n_nodes;
-    double *V = work;                        // V_j = V + j n, j = 0..m
-    double *part = work + (int64_t)(m + 2) * n;
+    const int64_t ld = (n + 1) & ~(int64_t)1;  // vector stride: every V_j 16-byte aligned
+    double *V = work;                        // V_j = V + j ld, j = 0..m
+    double *part = work + (int64_t)(m + 2) * ld;
     double *dres = part + dot_partials();
     auto dot = [&](const double *a, const double *b, double *out) -> dg_status {
         HIP_TRY(launch_dot(a, b, n, part, dres, stream));
@@ -946,9 +969,9 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), sv(m + 1), y(m);
     for (;;) {
         // r = g - A^T psi in V_0
-        if ((st = matvec(psi, V + n))) return st;
+        if ((st = matvec(psi, V + ld))) return st;
         HIP_TRY(launch_axpby(1.0, g, 0.0, V, n, stream));
-        HIP_TRY(launch_axpby(-1.0, V + n, 1.0, V, n, stream));
+        HIP_TRY(launch_axpby(-1.0, V + ld, 1.0, V, n, stream));
         double b2 = 0.0;
         if ((st = dot(V, V, &b2))) return st;
         const double beta = std::sqrt(b2);
@@ -960,14 +983,14 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
         sv[0] = beta;
         int k = 0;
         for (int j = 0; j < m && iters < prm->max_iter; ++j) {
-            double *vj = V + (int64_t)j * n, *w = V + (int64_t)(j + 1) * n;
+            double *vj = V + (int64_t)j * ld, *w = V + (int64_t)(j + 1) * ld;
             if ((st = matvec(vj, w))) return st;
             ++iters;
             for (int i = 0; i <= j; ++i) {
                 double h = 0.0;
-                if ((st = dot(w, V + (int64_t)i * n, &h))) return st;
+                if ((st = dot(w, V + (int64_t)i * ld, &h))) return st;
                 H[(size_t)i * m + j] = h;
-                HIP_TRY(launch_axpby(-h, V + (int64_t)i * n, 1.0, w, n, stream));
+                HIP_TRY(launch_axpby(-h, V + (int64_t)i * ld, 1.0, w, n, stream));
             }
             double h2 = 0.0;
             if ((st = dot(w, w, &h2))) return st;
@@ -997,7 +1020,7 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
             for (int c = i + 1; c < k; ++c) t -= H[(size_t)i * m + c] * y[c];
             y[i] = H[(size_t)i * m + i] != 0.0 ? t / H[(size_t)i * m + i] : 0.0;
         }
-        for (int i = 0; i < k; ++i) HIP_TRY(launch_axpby(y[i], V + (int64_t)i * n, 1.0, psi, n, stream));
+        for (int i = 0; i < k; ++i) HIP_TRY(launch_axpby(y[i], V + (int64_t)i * ld, 1.0, psi, n, stream));
     }
     if (iters_out) *iters_out = iters;
     if (relres_out) *relres_out = relres;
@@ -1006,6 +1029,7 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
 
 dg_status dg_functional(dg_plan p, const double *u, double *J, double *dJdu, hipStream_t stream) {
     if (!p || !u || !J) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(u, J, dJdu);
     if (p->curved) return fail(DG_EUNSUPPORTED, "the functional is implemented for box elements");
     HIP_TRY(launch_functional(p->d_faces, p->d_wallx, p->nwallx, p->d_el, u, p->tabs.t64, p->geom, p->mesh.gamma,
                               p->d_part, J, dJdu, (int64_t)NV * p->n_nodes, stream));
@@ -1014,6 +1038,7 @@ dg_status dg_functional(dg_plan p, const double *u, double *J, double *dJdu, hip
 
 dg_status dg_check_state(dg_plan p, const void *u, int32_t dtype, int64_t *bad, hipStream_t stream) {
     if (!p || !u) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(u);
     if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_EINVAL, "unknown dtype");
     double *part = p->d_red, *out = p->d_red + dot_partials();
     if (dtype == DG_F64)
@@ -1270,7 +1295,8 @@ dg_status dg_batch_schedule(dg_batch b, int32_t *tile_cap, int32_t *elem_grid, i
 dg_status dg_batch_residual(dg_batch b, const void *const *u, void *const *r, hipStream_t stream) {
     if (!b || !u || !r) return fail(DG_EINVAL, "null argument");
     for (size_t i = 0; i < b->plans.size(); ++i)
-        if (!u[i] || !r[i] || u[i] == r[i]) return fail(DG_EINVAL, "bad state or residual pointer");
+        if (!u[i] || !r[i] || u[i] == r[i] || !aligned(u[i]) || !aligned(r[i]))
+            return fail(DG_EINVAL, "bad state or residual pointer (null, shared or not 16-byte aligned)");
     EpiArgs epi{};
     epi.mode = EPI_RESIDUAL;
     // the descriptor array is written with an ordered copy on the same stream
@@ -1294,7 +1320,8 @@ dg_status dg_batch_rk3_step(dg_batch b, void *const *u, void *const *g, double d
     if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
     const size_t n = b->plans.size();
     for (size_t i = 0; i < n; ++i)
-        if (!u[i] || !g[i] || u[i] == g[i]) return fail(DG_EINVAL, "bad state or register pointer");
+        if (!u[i] || !g[i] || u[i] == g[i] || !aligned(u[i]) || !aligned(g[i]))
+            return fail(DG_EINVAL, "bad state or register pointer (null, shared or not 16-byte aligned)");
     if (nsteps == 0) return DG_OK;
     BatchKey key{std::vector<void *>(u, u + n), std::vector<void *>(g, g + n), dt};
     auto it = b->graphs.find(key);

@@ -261,3 +261,23 @@ def test_check_state(dtype):
     bad[e7 + 2 * int(offs[8] - offs[7])] = np.nan
     with pytest.raises(dg.DGError, match="non-physical state: 3 nodes"):
         dg.check_state(plan, plan.to_plan(bad, dtype=dtype))
+
+
+def test_misaligned_pointers_rejected():
+    """Device arrays off a 16-byte boundary are refused before any launch."""
+    import ctypes
+    mesh, orders, u, _ = _case((2, 2, 2), 1, 3, 12)
+    plan = dg.Plan(mesh, orders)
+    n = 5 * plan.n_nodes
+    buf = torch.zeros(n + 2, dtype=torch.float64, device="cuda")
+    good = torch.zeros(n, dtype=torch.float64, device="cuda")
+    off = ctypes.c_void_p(buf.data_ptr() + 8)
+    L = dg.lib()
+    st = L.dg_residual(plan.handle, off, ctypes.c_void_p(good.data_ptr()), 0, 0, 0, None)
+    assert st == -1 and b"aligned" in L.dg_last_error()
+    m = torch.zeros(int(plan.combo_offsets()[-1]) + 2, dtype=torch.float64, device="cuda")
+    st = L.dg_tau_sweep(plan.handle, ctypes.c_void_p(good.data_ptr()), None, ctypes.c_void_p(m.data_ptr() + 8),
+                        ctypes.c_void_p(m.data_ptr()), None)
+    assert st == -1
+    st = L.dg_check_state(plan.handle, off, 0, None, None)
+    assert st == -1
