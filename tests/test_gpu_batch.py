@@ -71,3 +71,33 @@ def test_batch_rejects_mismatched_tensors():
     us = [p.to_plan(u, dtype=torch.float64) for p, (_, _, u) in zip(plans, probs)]
     with pytest.raises(dg.DGError):
         dg.batch_residual(batch, us)
+
+
+@pytest.mark.slow
+def test_c5_workload():
+    """The 64-problem batched workload at full size (26.3M nodes, orders U{1..7}^3): six
+    FP32 batched RK3 steps and six FP64 per-problem steps at dt = 1e-4, checked against
+    the oracle on the two smallest problems and, on every problem, FP32 against FP64."""
+    probs = wl.c5()
+    plans, u0 = [], []
+    for mesh, orders, centre, sigma in probs:
+        p = dg.Plan(mesh, orders)
+        plans.append(p)
+        u0.append(wl.pulse_state(p.to_natural(p.node_coords(), nv=3), orders, centre=centre, sigma=sigma))
+    batch = dg.Batch(plans, dtype=torch.float32)
+    u32 = [p.to_plan(u, dtype=torch.float32) for p, u in zip(plans, u0)]
+    g32 = [torch.empty_like(u) for u in u32]
+    u64 = [p.to_plan(u) for p, u in zip(plans, u0)]
+    g64 = [torch.empty_like(u) for u in u64]
+    dt, n = 1e-4, 6
+    dg.batch_rk3_step(batch, u32, g32, dt, n)
+    for p, u, g in zip(plans, u64, g64):
+        dg.rk3_step(p, u, g, dt, n)
+    for i in np.argsort([p.n_nodes for p in plans])[:2]:
+        mesh, orders, _, _ = probs[i]
+        ref = oracle.rk3(mesh, orders, u0[i], dt, n)
+        s = np.max(np.abs(ref))
+        assert np.max(np.abs(plans[i].to_natural(u64[i]) - ref)) < 1e-12 * s
+        assert np.max(np.abs(plans[i].to_natural(u32[i]).astype(np.float64) - ref)) < 2e-5 * s
+    for a, b in zip(u32, u64):
+        assert float((a.double() - b).abs().max()) < 2e-5 * float(b.abs().max())
