@@ -23,6 +23,10 @@ _LIB = os.environ.get("DG_ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
 
 NMAX = 12
 
+# restriction operators of the tau-estimate (Section 2.3)
+SAMPLE = 0  # sampling of the fine polynomial at the coarse nodes
+L2 = 1      # exact L2 projection onto the coarse tensor-product space
+
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, OpenMP over elements)."""
@@ -61,19 +65,19 @@ def _load():
             "orc_proj": [ctypes.c_int, ctypes.c_int, _D],
             "orc_node_coords": [ctypes.POINTER(_Mesh), _I, _D],
             "orc_metrics": [ctypes.POINTER(_Mesh), _I, _D],
-            "orc_sweep_ns": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_double, ctypes.c_double, _I,
-                             ctypes.c_int, _D, _D],
+            "orc_sweep_ns": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                             _I, ctypes.c_int, _D, _D],
             "orc_residual": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_int, ctypes.c_int],
             "orc_restrict": [ctypes.c_int, _I, _I, _D, _D],
             "orc_project": [ctypes.c_int, _I, _I, _D, _D],
             "orc_bdf_weights": [ctypes.c_int, _D],
             "orc_tau_dual": [ctypes.c_void_p, _I, _I, ctypes.POINTER(_D), ctypes.c_int, ctypes.c_double,
                              ctypes.c_int, _D, _D],
-            "orc_tau": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, _D, _D, _D, _D],
+            "orc_tau": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D],
             "orc_num_combos": [_I],
-            "orc_sweep": [ctypes.POINTER(_Mesh), _I, _D, _D, _I, ctypes.c_int, _D, _D],
+            "orc_sweep": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_int, _I, ctypes.c_int, _D, _D],
             "orc_rk3": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_double, ctypes.c_int],
-            "orc_tau_eta": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, _D, _D],
+            "orc_tau_eta": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, ctypes.c_int, _D, _D],
             "orc_functional": [ctypes.POINTER(_Mesh), _I, _D, _D, _D],
             "orc_gradient": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_int, _D],
             "orc_residual_ns": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_double, ctypes.c_double, _D,
@@ -256,8 +260,9 @@ def tau_dual(mesh: dict, fine_orders, coarse_orders, states, dt: float, isolated
     return tn, tt
 
 
-def tau(mesh: dict, fine_orders, coarse_orders, u, dudt, isolated: bool = False):
-    """Returns (tau_new, tau_trad, norms[E,2], varnorms[E,2,5]) in the coarse layout."""
+def tau(mesh: dict, fine_orders, coarse_orders, u, dudt, isolated: bool = False, restriction: int = SAMPLE):
+    """Returns (tau_new, tau_trad, norms[E,2], varnorms[E,2,5]) in the coarse layout.
+    restriction: SAMPLE (the coarse-node sampling) or L2 (the exact L2 projection)."""
     fo, co, u, dudt = _i32(fine_orders), _i32(coarse_orders), _f64(u), _f64(dudt)
     E = fo.size // 3
     nc = num_nodes(co)
@@ -267,7 +272,7 @@ def tau(mesh: dict, fine_orders, coarse_orders, u, dudt, isolated: bool = False)
     vn = np.zeros((E, 2, 5))
     m = _mesh(mesh)
     _check(_load().orc_tau(ctypes.byref(m), _i(fo), _i(co), _d(u), _d(dudt), int(bool(isolated)),
-                           _d(tn), _d(tt), _d(norms), _d(vn)), "tau")
+                           int(restriction), _d(tn), _d(tt), _d(norms), _d(vn)), "tau")
     return tn, tt, norms, vn
 
 
@@ -276,7 +281,7 @@ def num_combos(order3) -> int:
     return int(_load().orc_num_combos(_i(o)))
 
 
-def sweep(mesh: dict, orders, u, dudt, elems=None):
+def sweep(mesh: dict, orders, u, dudt, elems=None, restriction: int = SAMPLE):
     """Isolated sweep; returns (te_new, te_trad, combo_offsets) for the listed elements."""
     o, u, dudt = _i32(orders), _f64(u), _f64(dudt)
     E = o.size // 3
@@ -287,12 +292,12 @@ def sweep(mesh: dict, orders, u, dudt, elems=None):
     ten = np.zeros(int(offs[-1]))
     tet = np.zeros(int(offs[-1]))
     m = _mesh(mesh)
-    _check(_load().orc_sweep(ctypes.byref(m), _i(o), _d(u), _d(dudt), _i(el), len(el), _d(ten), _d(tet)),
-           "sweep")
+    _check(_load().orc_sweep(ctypes.byref(m), _i(o), _d(u), _d(dudt), int(restriction), _i(el), len(el),
+                             _d(ten), _d(tet)), "sweep")
     return ten, tet, offs
 
 
-def sweep_ns(mesh: dict, orders, u, dudt, mu: float, Pr: float = 0.72, elems=None):
+def sweep_ns(mesh: dict, orders, u, dudt, mu: float, Pr: float = 0.72, elems=None, restriction: int = SAMPLE):
     """Isolated sweep of the Navier-Stokes residual; same outputs as sweep()."""
     o, u, dudt = _i32(orders), _f64(u), _f64(dudt)
     E = o.size // 3
@@ -303,8 +308,8 @@ def sweep_ns(mesh: dict, orders, u, dudt, mu: float, Pr: float = 0.72, elems=Non
     ten = np.zeros(int(offs[-1]))
     tet = np.zeros(int(offs[-1]))
     m = _mesh(mesh)
-    _check(_load().orc_sweep_ns(ctypes.byref(m), _i(o), _d(u), _d(dudt), float(mu), float(Pr), _i(el), len(el),
-                                _d(ten), _d(tet)), "sweep_ns")
+    _check(_load().orc_sweep_ns(ctypes.byref(m), _i(o), _d(u), _d(dudt), float(mu), float(Pr), int(restriction),
+                                _i(el), len(el), _d(ten), _d(tet)), "sweep_ns")
     return ten, tet, offs
 
 
@@ -316,15 +321,17 @@ def rk3(mesh: dict, orders, u, dt: float, nsteps: int):
     return out
 
 
-def tau_eta(mesh: dict, fine_orders, coarse_orders, u, dudt, psi, isolated: bool = False):
-    """eta[e] = sum over the coarse nodes and variables of (I psi) * tau_trad."""
+def tau_eta(mesh: dict, fine_orders, coarse_orders, u, dudt, psi, isolated: bool = False,
+            restriction: int = SAMPLE):
+    """eta[e] = sum over the coarse nodes and variables of (I psi) * tau_trad, I the
+    restriction of the estimate."""
     fo, co = _i32(fine_orders), _i32(coarse_orders)
     u, dudt, psi = _f64(u), _f64(dudt), _f64(psi)
     E = fo.size // 3
     eta = np.zeros(E)
     m = _mesh(mesh)
     _check(_load().orc_tau_eta(ctypes.byref(m), _i(fo), _i(co), _d(u), _d(dudt), int(bool(isolated)),
-                               _d(psi), _d(eta)), "tau_eta")
+                               int(restriction), _d(psi), _d(eta)), "tau_eta")
     return eta
 
 

@@ -1151,8 +1151,8 @@ int orc_project(int E, const int *from_orders, const int *to_orders, const doubl
 }
 
 int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders, const double *u,
-            const double *dudt, int isolated, double *tau_new, double *tau_trad, double *norms,
-            double *varnorms)
+            const double *dudt, int isolated, int restriction, double *tau_new, double *tau_trad,
+            double *norms, double *varnorms)
 {
     int E = m->nx * m->ny * m->nz;
     if (check_mesh(m) || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
@@ -1162,9 +1162,20 @@ int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
     long nc = orc_num_nodes(E, coarse_orders);
     double *uc = malloc(sizeof(double) * NV * nc);
     double *rdc = malloc(sizeof(double) * NV * nc);
-    /* I^N q^P and I^N (M^P)^-1 F^P(q^P) */
-    orc_restrict(E, fine_orders, coarse_orders, u, uc);
-    orc_restrict(E, fine_orders, coarse_orders, dudt, rdc);
+    /* I^N q^P and I^N (M^P)^-1 F^P(q^P), I^N the sampling or the exact L2 projection
+     * (Section 2.3: I^N maps the solution from one space to another) */
+    if (restriction != 0 && restriction != 1) {
+        free(uc);
+        free(rdc);
+        return -1;
+    }
+    if (restriction) {
+        orc_project(E, fine_orders, coarse_orders, u, uc);
+        orc_project(E, fine_orders, coarse_orders, dudt, rdc);
+    } else {
+        orc_restrict(E, fine_orders, coarse_orders, u, uc);
+        orc_restrict(E, fine_orders, coarse_orders, dudt, rdc);
+    }
     /* (M^N)^-1 F^N (I^N q^P) on the coarse mesh */
     orc_residual(m, coarse_orders, uc, tau_new, 0, isolated);
     long *offc = node_offsets(E, coarse_orders);
@@ -1217,10 +1228,11 @@ int orc_num_combos(const int *o)
  * element's isolated coarse residual (its geometry sampled at the coarse nodes)
  * minus the restricted fine time derivative, both forms, maxima. */
 static int sweep_impl(const orc_mesh *m, const int *orders, const double *u, const double *dudt, int viscous,
-                      double mu, double Pr, const int *elems, int nelems, double *te_new, double *te_trad)
+                      double mu, double Pr, int restriction, const int *elems, int nelems, double *te_new,
+                      double *te_trad)
 {
     int E = m->nx * m->ny * m->nz;
-    if (check_mesh(m) || check_orders(E, orders)) return -1;
+    if (check_mesh(m) || check_orders(E, orders) || (restriction != 0 && restriction != 1)) return -1;
     for (int i = 0; i < nelems; ++i)
         if (elems[i] < 0 || elems[i] >= E) return -1;
     ensure_tables();
@@ -1246,8 +1258,13 @@ static int sweep_impl(const orc_mesh *m, const int *orders, const double *u, con
                 for (int c1 = 1; c1 <= cmax[0]; ++c1) {
                     int oc[3] = {c1, c2, c3};
                     int n[3] = {c1 + 1, c2 + 1, c3 + 1}, ne = n[0] * n[1] * n[2];
-                    restrict_element(of, oc, Q, qc);
-                    restrict_element(of, oc, R, rc);
+                    if (restriction) {
+                        project_element(of, oc, Q, qc);
+                        project_element(of, oc, R, rc);
+                    } else {
+                        restrict_element(of, oc, Q, qc);
+                        restrict_element(of, oc, R, rc);
+                    }
                     if (viscous) gradient_core(m, NULL, NULL, NULL, oc, e, qc, 1, G);
                     residual_core(m, NULL, NULL, NULL, NULL, mu, Pr, oc, e, qc, viscous ? G : NULL, 0, 1, res);
                     elem_metrics(m, oc, e, Ja, Jn);
@@ -1274,16 +1291,16 @@ static int sweep_impl(const orc_mesh *m, const int *orders, const double *u, con
     return 0;
 }
 
-int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const double *dudt,
+int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const double *dudt, int restriction,
               const int *elems, int nelems, double *te_new, double *te_trad)
 {
-    return sweep_impl(m, orders, u, dudt, 0, 0.0, 0.0, elems, nelems, te_new, te_trad);
+    return sweep_impl(m, orders, u, dudt, 0, 0.0, 0.0, restriction, elems, nelems, te_new, te_trad);
 }
 
 int orc_sweep_ns(const orc_mesh *m, const int *orders, const double *u, const double *dudt, double mu,
-                 double Pr, const int *elems, int nelems, double *te_new, double *te_trad)
+                 double Pr, int restriction, const int *elems, int nelems, double *te_new, double *te_trad)
 {
-    return sweep_impl(m, orders, u, dudt, 1, mu, Pr, elems, nelems, te_new, te_trad);
+    return sweep_impl(m, orders, u, dudt, 1, mu, Pr, restriction, elems, nelems, te_new, te_trad);
 }
 
 /* Weights of the backward-difference rate at t_{n+1} from k+1 equally spaced samples
@@ -1357,16 +1374,19 @@ int orc_tau_dual(const orc_mesh *m, const int *fine_orders, const int *coarse_or
 }
 
 int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_orders, const double *u,
-                const double *dudt, int isolated, const double *psi, double *eta)
+                const double *dudt, int isolated, int restriction, const double *psi, double *eta)
 {
     int E = m->nx * m->ny * m->nz;
     if (check_mesh(m) || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
     long nc = orc_num_nodes(E, coarse_orders);
     double *tn = malloc(sizeof(double) * NV * nc), *tt = malloc(sizeof(double) * NV * nc);
     double *norms = malloc(sizeof(double) * 2 * E), *psic = malloc(sizeof(double) * NV * nc);
-    int rc = orc_tau(m, fine_orders, coarse_orders, u, dudt, isolated, tn, tt, norms, NULL);
+    int rc = orc_tau(m, fine_orders, coarse_orders, u, dudt, isolated, restriction, tn, tt, norms, NULL);
     if (rc == 0) {
-        orc_restrict(E, fine_orders, coarse_orders, psi, psic);
+        if (restriction)
+            orc_project(E, fine_orders, coarse_orders, psi, psic);
+        else
+            orc_restrict(E, fine_orders, coarse_orders, psi, psic);
         long *offc = node_offsets(E, coarse_orders);
         for (int e = 0; e < E; ++e) {
             long a = NV * offc[e], b = NV * offc[e + 1];

@@ -86,10 +86,12 @@ int orc_project(int E, const int *from_orders, const int *to_orders, const doubl
 
 /* Coupled (isolated=0) or isolated tau-estimate on one coarse order map.
  * dudt: fine r = -dQ/dt (new form, non-isolated residual of u on the fine map).
+ * restriction: the operator I^N of the estimate (Section 2.3), 0 = sampling at the
+ * coarse nodes, 1 = exact L2 projection onto the coarse tensor-product space.
  * Outputs in the coarse natural ragged layout; norms[e*2+{0,1}] = max |tau_new|,
  * max |tau_trad| over nodes and variables; varnorms[(e*2+f)*5+v] (nullable). */
 int orc_tau(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
-            const double *u, const double *dudt, int isolated,
+            const double *u, const double *dudt, int isolated, int restriction,
             double *tau_new, double *tau_trad, double *norms, double *varnorms);
 
 /* Backward-difference weights: rate at t_{n+1} = (1/dt) sum_j w[j] Q(t_{n+1-j}),
@@ -104,21 +106,23 @@ int orc_tau_dual(const orc_mesh *m, const int *fine_orders, const int *coarse_or
 /* Number of coarse combinations of an element: prod_d max(1, N_d - 1). */
 int orc_num_combos(const int *order3);
 /* Isolated sweep over every coarse combination (c1 fastest, then c2, then c3;
- * c_d in 1..max(1,N_d-1)) for the listed elements (natural indices).
+ * c_d in 1..max(1,N_d-1)) for the listed elements (natural indices); restriction as
+ * for orc_tau.
  * te_new/te_trad: for list entry i, the combos of element elems[i] are stored
  * contiguously, entries ordered as the list. */
-int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const double *dudt,
+int orc_sweep(const orc_mesh *m, const int *orders, const double *u, const double *dudt, int restriction,
               const int *elems, int nelems, double *te_new, double *te_trad);
 
 /* The isolated sweep for the Navier-Stokes equations (BR1 gradients with the
  * isolated flag, viscous flux of constant mu and Prandtl number Pr). */
 int orc_sweep_ns(const orc_mesh *m, const int *orders, const double *u, const double *dudt, double mu,
-                 double Pr, const int *elems, int nelems, double *te_new, double *te_trad);
+                 double Pr, int restriction, const int *elems, int nelems, double *te_new, double *te_trad);
 
 /* Adjoint-weighted truncation error (used with an adjoint state psi on the fine
  * layout): eta[e] = sum over coarse nodes and variables of (I psi) * tau_trad. */
 int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
-                const double *u, const double *dudt, int isolated, const double *psi, double *eta);
+                const double *u, const double *dudt, int isolated, int restriction, const double *psi,
+                double *eta);
 
 /* Pressure force along x on the slip walls: J = sum over slip-wall faces with
  * normal +-e_x of sum_{a,b} w_a w_b |Ja^1| p(Q) n_x; dJdu (nullable, natural
