@@ -51,6 +51,11 @@ enum { DG_MAP_BOX = 0, DG_MAP_SINE = 1 };
 enum { DG_F64 = 0, DG_F32 = 1 };
 /* Residual forms (Section 2.2): NEW = M^-1 F^N(Q) = -dQ/dt, TRAD = F^N(Q) = M * NEW. */
 enum { DG_FORM_NEW = 0, DG_FORM_TRAD = 1 };
+/* Restriction operator I of the tau-estimate (Section 2.3, the operator of eq.
+ * TEderivation1 that maps the fine solution into the coarse space): sampling of the
+ * fine element polynomial at the coarse Gauss-Lobatto nodes (the paper's choice), or
+ * the exact L2 projection onto the coarse tensor-product space of the reference cube. */
+enum { DG_RESTRICT_SAMPLE = 0, DG_RESTRICT_L2 = 1 };
 
 #define DG_NMAX 9 /* polynomial orders 1..DG_NMAX in every direction */
 
@@ -138,11 +143,12 @@ dg_status dg_residual(dg_plan plan, const void *u, void *r, int32_t dtype, int32
  * and TEdef with the variational DG estimate I F(q) ~ I (M^P)^-1 F^P(q^P)):
  *   tau_new  = r^Nc(I u) - I dudt        (new form, "without the mass matrix")
  *   tau_trad = J w_i w_j w_k * tau_new    (traditional form, coarse weights)
- * I = sampling of the fine element polynomial at the coarse Gauss-Lobatto nodes.
+ * I = the restriction operator: DG_RESTRICT_SAMPLE or DG_RESTRICT_L2.
  *   u: device double, fine plan layout (5*n_fine values).
  *   dudt: device double fine new-form residual -du/dt (non-isolated), or NULL to
  *         have it computed here into the fine plan's scratch.
  *   isolated: 0 coupled coarse residual (mortars between coarse orders), 1 isolated.
+ *   restriction: DG_RESTRICT_SAMPLE or DG_RESTRICT_L2, for u, dudt and psi alike.
  *   tau_new, tau_trad: device double, coarse plan layout (either may be NULL).
  *   norms: device double [E_coarse][2], max |tau_new|, max |tau_trad| over nodes and
  *          the 5 variables of each coarse plan element (may be NULL).
@@ -151,8 +157,8 @@ dg_status dg_residual(dg_plan plan, const void *u, void *r, int32_t dtype, int32
  *          receives sum over coarse nodes and variables of (I psi) * tau_trad; the
  *          functional error estimate is -sum(eta). */
 dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt,
-                          int32_t isolated, double *tau_new, double *tau_trad, double *norms,
-                          const double *psi, double *eta, hipStream_t stream);
+                          int32_t isolated, int32_t restriction, double *tau_new, double *tau_trad,
+                          double *norms, const double *psi, double *eta, hipStream_t stream);
 
 /* Number of coarse combinations per fine plan element for the sweep:
  * prod_d max(1, N_d - 1); combo_offset[E+1] (host) gets their prefix sums. */
@@ -163,12 +169,14 @@ dg_status dg_sweep_layout(dg_plan fine, int64_t *combo_offset);
  * (c1, c2, c3), c_d in 1..max(1, N_d - 1), enumerated c1 fastest, the maxima
  * over nodes and variables of |tau_new| and |tau_trad| of the isolated estimate
  * (Euler or Navier-Stokes; on curved plans the element's geometry sampled at the
- * coarse nodes).  Fine orders up to 8 (7 for Navier-Stokes and curved plans).
+ * coarse nodes whatever the restriction).  Fine orders up to 8 (7 for Navier-Stokes
+ * and curved plans).
  *   u, dudt: device double, fine plan layout (dudt as for dg_tau_estimate,
  *            NULL computes it).
+ *   restriction: DG_RESTRICT_SAMPLE or DG_RESTRICT_L2 (of u and dudt).
  *   te_new, te_trad: device double [combo_offset[E]] (dg_sweep_layout). */
-dg_status dg_tau_sweep(dg_plan fine, const double *u, const double *dudt, double *te_new,
-                       double *te_trad, hipStream_t stream);
+dg_status dg_tau_sweep(dg_plan fine, const double *u, const double *dudt, int32_t restriction,
+                       double *te_new, double *te_trad, hipStream_t stream);
 
 /* Polynomial-degree selection from truncation-error maps (Section 2.4.2, static
  * p-adaptation, approaches 1 and 2 with the maximum aggregator F_max; jump

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libdgtau.so")
 
 DG_F64, DG_F32 = 0, 1
 FORM_NEW, FORM_TRAD = 0, 1
+RESTRICT_SAMPLE, RESTRICT_L2 = 0, 1  # restriction of the tau-estimate: sampling, L2 projection
 NMAX = 9
 
 
@@ -66,11 +67,11 @@ SIGNATURES = {
     "dg_node_coords": [_P, _P, _P],
     "dg_plan_metrics": [_P, _P, _P],
     "dg_residual": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
-    "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, _P, _P, _P, _P, _P, _P],
+    "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P],
     "dg_residual_vjp": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_functional": [_P, _P, _P, _P, _P],
     "dg_sweep_layout": [_P, _I64P],
-    "dg_tau_sweep": [_P, _P, _P, _P, _P, _P],
+    "dg_tau_sweep": [_P, _P, _P, ctypes.c_int32, _P, _P, _P],
     "dg_select_orders": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_SelectParams), _P, _P],
     "dg_project": [_P, _P, _P, _P, _P],
     "dg_map_fmax": [_P, _P, _P, _P],
@@ -292,9 +293,11 @@ def residual(plan: Plan, u, form: int = FORM_NEW, isolated: bool = False, out=No
     return r
 
 
-def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False, psi=None):
+def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False, psi=None,
+                 restriction: int = RESTRICT_SAMPLE):
     """Returns (tau_new, tau_trad, norms[E,2]) in the coarse plan layout (float64), plus
-    eta[E] (sum of (I psi) * tau_trad per coarse element) when an adjoint weight psi is given."""
+    eta[E] (sum of (I psi) * tau_trad per coarse element) when an adjoint weight psi is given.
+    restriction: RESTRICT_SAMPLE (coarse-node sampling) or RESTRICT_L2 (L2 projection)."""
     torch = _torch()
     if coarse.parent is not fine:
         raise DGError("coarse plan was not built from this fine plan")
@@ -306,7 +309,7 @@ def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False,
     norms = torch.empty((coarse.n_elems, 2), dtype=torch.float64, device="cuda")
     eta = torch.empty(coarse.n_elems, dtype=torch.float64, device="cuda") if psi is not None else None
     _call("dg_tau_estimate", fine.handle, coarse.handle, _ptr(u), _ptr(dudt), int(bool(isolated)),
-          _ptr(tn), _ptr(tt), _ptr(norms), _ptr(psi), _ptr(eta), _stream())
+          int(restriction), _ptr(tn), _ptr(tt), _ptr(norms), _ptr(psi), _ptr(eta), _stream())
     return (tn, tt, norms) if psi is None else (tn, tt, norms, eta)
 
 
@@ -362,13 +365,13 @@ def _residual_fn():
     return _RES_FN
 
 
-def tau_sweep(plan: Plan, u, dudt=None):
+def tau_sweep(plan: Plan, u, dudt=None, restriction: int = RESTRICT_SAMPLE):
     """Isolated TE map: (te_new, te_trad) per (plan element, combo), c1 fastest."""
     torch = _torch()
     off = plan.combo_offsets()
     ten = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda")
     tet = torch.empty_like(ten)
-    _call("dg_tau_sweep", plan.handle, _ptr(u), _ptr(dudt), _ptr(ten), _ptr(tet), _stream())
+    _call("dg_tau_sweep", plan.handle, _ptr(u), _ptr(dudt), int(restriction), _ptr(ten), _ptr(tet), _stream())
     return ten, tet
 
 

@@ -733,9 +733,11 @@ dg_status dg_residual(dg_plan p, const void *u, void *r, int32_t dtype, int32_t 
 }
 
 dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt, int32_t isolated,
-                          double *tau_new, double *tau_trad, double *norms, const double *psi, double *eta,
-                          hipStream_t stream) {
+                          int32_t restriction, double *tau_new, double *tau_trad, double *norms, const double *psi,
+                          double *eta, hipStream_t stream) {
     if (!fine || !coarse || !u) return fail(DG_EINVAL, "null argument");
+    if (restriction != DG_RESTRICT_SAMPLE && restriction != DG_RESTRICT_L2)
+        return fail(DG_EINVAL, "restriction must be DG_RESTRICT_SAMPLE or DG_RESTRICT_L2");
     DG_ALIGNED(u, dudt, tau_new, tau_trad, norms, psi, eta);
     if (coarse->parent != fine) return fail(DG_EINVAL, "coarse plan was not built from this fine plan");
     if (fine->curved && !isolated)
@@ -752,7 +754,7 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
     }
     HIP_TRY(launch_restrict(coarse->d_fine_of, coarse->E, coarse->d_el, fine->d_el, u, dudt, psi, coarse->d_uc,
                             coarse->d_rdc, coarse->d_psic, fine->tabs.t64, coarse->rcapA, coarse->rcapB,
-                            stream));
+                            restriction, stream));
     EpiArgs epi{};
     epi.mode = EPI_TAU;
     epi.isolated = isolated ? 1 : 0;
@@ -771,9 +773,11 @@ dg_status dg_sweep_layout(dg_plan p, int64_t *combo_offset) {
     return DG_OK;
 }
 
-dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *te_new, double *te_trad,
-                       hipStream_t stream) {
+dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, int32_t restriction, double *te_new,
+                       double *te_trad, hipStream_t stream) {
     if (!p || !u || !te_new || !te_trad) return fail(DG_EINVAL, "null argument");
+    if (restriction != DG_RESTRICT_SAMPLE && restriction != DG_RESTRICT_L2)
+        return fail(DG_EINVAL, "restriction must be DG_RESTRICT_SAMPLE or DG_RESTRICT_L2");
     DG_ALIGNED(u, dudt, te_new, te_trad);
     if (p->max_order > 8) return fail(DG_EUNSUPPORTED, "the sweep supports fine orders up to 8");
     if ((p->curved || p->ns) && p->max_order > 7)
@@ -788,16 +792,17 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, double *t
     }
     if (p->curved || p->ns) {
         HIP_TRY(launch_sweep_curved(p->d_ctasks, p->nctasks, p->d_el, p->d_combo_off, u, dudt, p->d_xyz, p->tabs.t64,
-                                    p->phys, p->capA, p->capB, p->capS, p->max_nc, p->ns ? 1 : 0, te_new, te_trad,
-                                    stream));
+                                    p->phys, p->capA, p->capB, p->capS, p->max_nc, p->ns ? 1 : 0, restriction,
+                                    te_new, te_trad, stream));
         return DG_OK;
     }
     for (int F = 2; F <= 8; ++F)
         if (p->iso_count[F])
             HIP_TRY(launch_sweep_iso(F, p->d_iso + p->iso_first[F], p->iso_count[F], p->d_el, p->d_combo_off, u,
-                                     dudt, p->tabs.t64, p->geom, p->mesh.gamma, te_new, te_trad, stream));
+                                     dudt, p->tabs.t64, p->geom, p->mesh.gamma, restriction, te_new, te_trad,
+                                     stream));
     HIP_TRY(launch_sweep_tasks(p->d_tasks, p->ntasks, p->d_el, p->d_combo_off, u, dudt, p->tabs.t64, p->geom,
-                               p->mesh.gamma, p->x1cap, p->x2cap, te_new, te_trad, stream));
+                               p->mesh.gamma, p->x1cap, p->x2cap, restriction, te_new, te_trad, stream));
     return DG_OK;
 }
 

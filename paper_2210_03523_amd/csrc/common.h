@@ -118,10 +118,11 @@ hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, con
                           const T *fflux, const T *tab, Geom g, PhysParams ph, EpiArgs epi, hipStream_t s);
 
 // capA, capB: LDS capacities (doubles) of the two staging buffers, 5 c1 f2 f3 and
-// 5 max(c1 c2 f3, f1 f2 f3) maximised over the coarse plan's elements.
+// 5 max(c1 c2 f3, f1 f2 f3) maximised over the coarse plan's elements.  restriction:
+// 0 samples at the coarse nodes, 1 takes the exact L2 projection (also for the sweeps).
 hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
                            const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
-                           double *psic, const double *tab, int capA, int capB, hipStream_t s);
+                           double *psic, const double *tab, int capA, int capB, int restriction, hipStream_t s);
 
 // Solution transfer onto another order map: target plan elements tel, source plan
 // elements sel, src_inv[natural] = source plan position; capA = max 5 t1 s2 s3,
@@ -147,7 +148,8 @@ struct SweepTask {
 
 hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *elems, const int64_t *combo_off,
                               const double *u, const double *dudt, const double *tab, Geom g, double gamma,
-                              int x1cap, int x2cap, double *te_new, double *te_trad, hipStream_t s);
+                              int x1cap, int x2cap, int restriction, double *te_new, double *te_trad,
+                              hipStream_t s);
 
 // Isotropic fast path of the sweep (fine nodes F per direction, 2 <= F <= 8).
 // Degree selection from truncation-error maps (maps: host array of nst device pointers)
@@ -171,7 +173,7 @@ hipError_t launch_count_bad(const ElemInfo *el, int E, const T *u, double gamma,
 hipError_t launch_bdf_rate(const double *const *states, int nst, double dt, int64_t n, double *dudt, hipStream_t s);
 hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
                             const double *u, const double *dudt, const double *tab, Geom g, double gamma,
-                            double *te_new, double *te_trad, hipStream_t s);
+                            int restriction, double *te_new, double *te_trad, hipStream_t s);
 
 // ---------------------------------------------------------------------------- batches
 // One independent problem of a batch, as seen by the persistent kernels.
@@ -228,8 +230,8 @@ hipError_t launch_grad_curved(const Face *faces, const int64_t *fmo, const T *fm
                               hipStream_t s);
 hipError_t launch_sweep_curved(const int4 *tasks, int ntasks, const ElemInfo *el, const int64_t *combo_off,
                                const double *u, const double *dudt, const double *xyz, const double *tab,
-                               PhysParams ph, int capA, int capB, int capS, int max_nc, int viscous, double *te_new,
-                               double *te_trad, hipStream_t s);
+                               PhysParams ph, int capA, int capB, int capS, int max_nc, int viscous, int restriction,
+                               double *te_new, double *te_trad, hipStream_t s);
 
 // Host tables (tables.cpp): fills T_TOT values.
 void build_tables(double *tab64, float *tab32);

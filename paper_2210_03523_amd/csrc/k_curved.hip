@@ -468,7 +468,7 @@ __global__ __launch_bounds__(BS) void k_sweep_curved(const int4 *__restrict__ ta
                                                      const int64_t *__restrict__ combo_off,
                                                      const double *__restrict__ u, const double *__restrict__ dudt,
                                                      const double *__restrict__ xyz, const double *__restrict__ tab,
-                                                     PhysParams ph, int capA, int capB, int viscous,
+                                                     PhysParams ph, int capA, int capB, int viscous, int rt,
                                                      double *__restrict__ te_new, double *__restrict__ te_trad) {
     extern __shared__ double lds[];
     double *A = lds, *B = lds + capA, *S = lds + capA + capB;
@@ -485,34 +485,38 @@ __global__ __launch_bounds__(BS) void k_sweep_curved(const int4 *__restrict__ ta
         if (fld < 2 * NV) return dudt + NV * E.noff + (int64_t)(fld - NV) * nf;
         return xyz + 3 * E.noff + (int64_t)(fld - 2 * NV) * nf;
     };
-    // restriction, one direction at a time: sampling of the fine polynomial at the coarse nodes
+    // restriction, one direction at a time: Q and dQ/dt by the estimate's operator (sampling
+    // at the coarse nodes or L2 projection), the node coordinates always by sampling
     {
-        const double *I1 = tab + T_I + moff(c[0], f1 - 1);
+        const double *I1 = tab + T_I + moff(c[0], f1 - 1), *R1 = tab + rt + moff(c[0], f1 - 1);
         for (int r = tid; r < NFLD * m1 * f2 * f3; r += BS) {
             const int a = r % m1, jk = (r / m1) % (f2 * f3), fld = r / (m1 * f2 * f3);
             const double *src = field(fld) + (int64_t)jk * f1;
+            const double *w = (fld < 2 * NV ? R1 : I1) + a * f1;
             double acc = 0.0;
-            for (int i = 0; i < f1; ++i) acc += I1[a * f1 + i] * src[i];
+            for (int i = 0; i < f1; ++i) acc += w[i] * src[i];
             A[r] = acc;  // [fld][jk][a]
         }
     }
     __syncthreads();
     {
-        const double *I2 = tab + T_I + moff(c[1], f2 - 1);
+        const double *I2 = tab + T_I + moff(c[1], f2 - 1), *R2 = tab + rt + moff(c[1], f2 - 1);
         for (int r = tid; r < NFLD * m1 * m2 * f3; r += BS) {
             const int a = r % m1, b = (r / m1) % m2, k = (r / (m1 * m2)) % f3, fld = r / (m1 * m2 * f3);
+            const double *w = (fld < 2 * NV ? R2 : I2) + b * f2;
             double acc = 0.0;
-            for (int j = 0; j < f2; ++j) acc += I2[b * f2 + j] * A[((fld * f3 + k) * f2 + j) * m1 + a];
+            for (int j = 0; j < f2; ++j) acc += w[j] * A[((fld * f3 + k) * f2 + j) * m1 + a];
             B[r] = acc;  // [fld][k][b][a]
         }
     }
     __syncthreads();
     {
-        const double *I3 = tab + T_I + moff(c[2], f3 - 1);
+        const double *I3 = tab + T_I + moff(c[2], f3 - 1), *R3 = tab + rt + moff(c[2], f3 - 1);
         for (int r = tid; r < NFLD * nc; r += BS) {
             const int ab = r % (m1 * m2), cc = (r / (m1 * m2)) % m3, fld = r / nc;
+            const double *w = (fld < 2 * NV ? R3 : I3) + cc * f3;
             double acc = 0.0;
-            for (int k = 0; k < f3; ++k) acc += I3[cc * f3 + k] * B[(fld * f3 + k) * m1 * m2 + ab];
+            for (int k = 0; k < f3; ++k) acc += w[k] * B[(fld * f3 + k) * m1 * m2 + ab];
             A[r] = acc;  // coarse fields [fld][node], node = a + m1 (b + m2 cc)
         }
     }
@@ -659,8 +663,8 @@ __global__ __launch_bounds__(BS) void k_sweep_curved(const int4 *__restrict__ ta
 template <int BS, int NPT>
 static hipError_t launch_sweep_curved_bs(const int4 *tasks, int ntasks, const ElemInfo *el, const int64_t *combo_off,
                                          const double *u, const double *dudt, const double *xyz, const double *tab,
-                                         PhysParams ph, int capA, int capB, int capS, int viscous, double *te_new,
-                                         double *te_trad, hipStream_t s) {
+                                         PhysParams ph, int capA, int capB, int capS, int viscous, int rt,
+                                         double *te_new, double *te_trad, hipStream_t s) {
     const size_t lds = sizeof(double) * (size_t)(capA + capB + capS);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)k_sweep_curved<BS, NPT>,
@@ -668,25 +672,26 @@ static hipError_t launch_sweep_curved_bs(const int4 *tasks, int ntasks, const El
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_sweep_curved<BS, NPT>), dim3(ntasks), dim3(BS), lds, s, tasks, el, combo_off, u, dudt, xyz,
-                       tab, ph, capA, capB, viscous, te_new, te_trad);
+                       tab, ph, capA, capB, viscous, rt, te_new, te_trad);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_curved(const int4 *tasks, int ntasks, const ElemInfo *el, const int64_t *combo_off,
                                const double *u, const double *dudt, const double *xyz, const double *tab,
-                               PhysParams ph, int capA, int capB, int capS, int max_nc, int viscous, double *te_new,
-                               double *te_trad, hipStream_t s) {
+                               PhysParams ph, int capA, int capB, int capS, int max_nc, int viscous, int restriction,
+                               double *te_new, double *te_trad, hipStream_t s) {
     if (ntasks == 0) return hipSuccess;
+    const int rt = restriction ? T_P : T_I;
     if (capS < 2 * WG) return hipErrorInvalidValue;  // the maxima reduction stages 2 BS values
     if (max_nc <= 128)
         return launch_sweep_curved_bs<128, 1>(tasks, ntasks, el, combo_off, u, dudt, xyz, tab, ph, capA, capB, capS,
-                                              viscous, te_new, te_trad, s);
+                                              viscous, rt, te_new, te_trad, s);
     if (max_nc <= 256)
         return launch_sweep_curved_bs<256, 1>(tasks, ntasks, el, combo_off, u, dudt, xyz, tab, ph, capA, capB, capS,
-                                              viscous, te_new, te_trad, s);
+                                              viscous, rt, te_new, te_trad, s);
     if (max_nc <= 512)
         return launch_sweep_curved_bs<256, 2>(tasks, ntasks, el, combo_off, u, dudt, xyz, tab, ph, capA, capB, capS,
-                                              viscous, te_new, te_trad, s);
+                                              viscous, rt, te_new, te_trad, s);
     return hipErrorInvalidValue;
 }
 

@@ -1,8 +1,9 @@
 // Tau-estimation kernels for gfx950 (Section 2.3, variational DG estimate).
 //
-//   k_restrict : samples the fine element polynomial of Q and of the fine time
-//                derivative at the coarse Gauss-Lobatto nodes (sum-factorised
-//                I3 (x) I2 (x) I1, staged through LDS), writing the coarse plan
+//   k_restrict : restricts the fine element polynomial of Q and of the fine time
+//                derivative to the coarse orders, by sampling at the coarse
+//                Gauss-Lobatto nodes or by the exact L2 projection (sum-factorised
+//                A3 (x) A2 (x) A1, staged through LDS), writing the coarse plan
 //                layout.  The coarse residual and the tau difference then run in
 //                the element kernel's tau epilogue.
 //   k_sweep    : the isolated truncation-error map.  One workgroup per (fine
@@ -26,11 +27,11 @@ namespace dgt {
 // is staged with coalesced loads, then the three sum-factorisation passes run over all
 // five variables at once.  Dynamic LDS: sI [I1 | I2 | I3], sA [5][c1][f2 f3],
 // sB [5][f1 f2 f3] (the staged block) and later [5][c1 c2][f3].
-// PROJECT: the solution transfer onto another order map (Section 2.4.1): the "coarse"
-// element is the target, of any orders; per direction the operator is the
-// interpolation where the order rises or stays and the exact L2 projection where it
-// falls; the source element is found through the source plan's natural -> plan index
-// (fine_of), one field (Q).
+// Per direction the operator is the interpolation where the order rises or stays and,
+// where it falls, the table at offset `down`: T_I (sampling) or T_P (exact L2
+// projection).  PROJECT: the solution transfer onto another order map (Section 2.4.1,
+// down = T_P): the "coarse" element is the target, of any orders, the source element is
+// found through the source plan's natural -> plan index (fine_of), one field (Q).
 constexpr int RS_WG = 256;
 constexpr int RS_TAB = 3 * NNMAX * NNMAX;
 
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ 
                                                     const double *__restrict__ dudt, const double *__restrict__ psi,
                                                     double *__restrict__ uc, double *__restrict__ rdc,
                                                     double *__restrict__ psic, const double *__restrict__ tab,
-                                                    int capA) {
+                                                    int capA, int down) {
     extern __shared__ double lds[];
     double *sI = lds, *sA = lds + RS_TAB, *sB = lds + RS_TAB + capA;
     const int p = xcd_remap(blockIdx.x, gridDim.x);
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ 
     const int tid = threadIdx.x;
     double *I1 = sI, *I2 = sI + c1 * f1, *I3 = I2 + c2 * f2;
     {
-        auto op = [&](int c, int f) { return tab + (PROJECT && c < f ? T_P : T_I) + moff(c - 1, f - 1); };
+        auto op = [&](int c, int f) { return tab + (c < f ? down : T_I) + moff(c - 1, f - 1); };
         const double *g1 = op(c1, f1), *g2 = op(c2, f2);
         const double *g3 = op(c3, f3);
         for (int t = tid; t < c1 * f1; t += RS_WG) I1[t] = g1[t];
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ 
 
 hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
                            const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
-                           double *psic, const double *tab, int capA, int capB, hipStream_t s) {
+                           double *psic, const double *tab, int capA, int capB, int restriction, hipStream_t s) {
     if (ncoarse == 0) return hipSuccess;
     const size_t lds = sizeof(double) * (size_t)(RS_TAB + capA + capB);
     if (lds > 64 * 1024) {
@@ -124,7 +125,7 @@ hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_restrict<false>, dim3(ncoarse), dim3(RS_WG), lds, s, fine_of, celems, felems, u, dudt, psi,
-                       uc, rdc, psic, tab, capA);
+                       uc, rdc, psic, tab, capA, restriction ? T_P : T_I);
     return hipGetLastError();
 }
 
@@ -138,7 +139,7 @@ hipError_t launch_project(const int32_t *src_inv, int ntarget, const ElemInfo *t
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_restrict<true>, dim3(ntarget), dim3(RS_WG), lds, s, src_inv, tel, sel, u, nullptr, nullptr,
-                       ut, nullptr, nullptr, tab, capA);
+                       ut, nullptr, nullptr, tab, capA, T_P);
     return hipGetLastError();
 }
 
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(SW_WG) void k_sweep(const SweepTask *__restrict__ t
                                                  const int64_t *__restrict__ combo_off,
                                                  const double *__restrict__ u, const double *__restrict__ dudt,
                                                  const double *__restrict__ tab, Geom g, double gamma,
-                                                 int x1cap, int x2cap, double *__restrict__ te_new,
+                                                 int x1cap, int x2cap, int rt, double *__restrict__ te_new,
                                                  double *__restrict__ te_trad) {
     extern __shared__ double lds[];
     double *sX1 = lds;
@@ -169,8 +170,8 @@ __global__ __launch_bounds__(SW_WG) void k_sweep(const SweepTask *__restrict__ t
     const int f1 = E.n[0], f2 = E.n[1], f3 = E.n[2], nef = f1 * f2 * f3;
     const int m1 = task.c1 + 1, m2 = task.c2 + 1;
     const int C1 = f1 > 2 ? f1 - 2 : 1, C2 = f2 > 2 ? f2 - 2 : 1, C3 = f3 > 2 ? f3 - 2 : 1;
-    const double *I1 = tab + T_I + moff(m1 - 1, f1 - 1);
-    const double *I2 = tab + T_I + moff(m2 - 1, f2 - 1);
+    const double *I1 = tab + rt + moff(m1 - 1, f1 - 1);
+    const double *I2 = tab + rt + moff(m2 - 1, f2 - 1);
     const int tid = threadIdx.x;
     const double gm1 = gamma - 1.0;
 
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(SW_WG) void k_sweep(const SweepTask *__restrict__ t
     double *sF = sX1;  // X1 is dead now
     for (int c3 = 1; c3 <= C3; ++c3) {
         const int m3 = c3 + 1, M = m1 * m2 * m3;
-        const double *I3 = tab + T_I + moff(m3 - 1, f3 - 1);
+        const double *I3 = tab + rt + moff(m3 - 1, f3 - 1);
         const double *w3 = tab + T_W + xoff(m3 - 1);
         double q[2][NV], V[2][NV];
         int loc[2][3];
@@ -287,7 +288,8 @@ __global__ __launch_bounds__(SW_WG) void k_sweep(const SweepTask *__restrict__ t
 
 hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *elems, const int64_t *combo_off,
                               const double *u, const double *dudt, const double *tab, Geom g, double gamma,
-                              int x1cap, int x2cap, double *te_new, double *te_trad, hipStream_t s) {
+                              int x1cap, int x2cap, int restriction, double *te_new, double *te_trad,
+                              hipStream_t s) {
     if (ntasks == 0) return hipSuccess;
     size_t lds = sizeof(double) * (size_t)(x1cap + 2 * x2cap + 8);
     static bool attr_set = false;
@@ -298,7 +300,7 @@ hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *ele
         attr_set = true;
     }
     hipLaunchKernelGGL(k_sweep, dim3(ntasks), dim3(SW_WG), lds, s, (const SweepTask *)tasks, ntasks, elems,
-                       combo_off, u, dudt, tab, g, gamma, x1cap, x2cap, te_new, te_trad);
+                       combo_off, u, dudt, tab, g, gamma, x1cap, x2cap, restriction ? T_P : T_I, te_new, te_trad);
     return hipGetLastError();
 }
 
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
                                                    const ElemInfo *__restrict__ el,
                                                    const int64_t *__restrict__ combo_off,
                                                    const double *__restrict__ u, const double *__restrict__ dudt,
-                                                   const double *__restrict__ tab, Geom g, double gamma,
+                                                   const double *__restrict__ tab, Geom g, double gamma, int rt,
                                                    double *__restrict__ te_new, double *__restrict__ te_trad) {
     constexpr int C = F > 2 ? F - 2 : 1;        // coarse orders per direction
     constexpr int NPAIR = (C + 1) / 2;
@@ -357,8 +359,8 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
 
     // x-interpolation: X1[f][v][row][j][k], row over the pair's stacked coarse x-nodes
     {
-        const double *IA = tab + T_I + moff(mA - 1, F - 1);
-        const double *IB = tab + T_I + moff((mB ? mB : 2) - 1, F - 1);
+        const double *IA = tab + rt + moff(mA - 1, F - 1);
+        const double *IB = tab + rt + moff((mB ? mB : 2) - 1, F - 1);
         for (int r = lane; r < 2 * NV * F * F; r += NL) {
             const int f = r / (NV * F * F), rem = r - f * NV * F * F;  // rem = v*F*F + jk
             const double *src = (f == 0 ? u : dudt) + NV * E.noff + (int64_t)rem * F;
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
     {
         const double *dx = tab + T_D + doff(m1 - 1) + al * m1;
         const double *dy = tab + T_D + doff(m2 - 1) + b * m2;
-        const double *i2 = tab + T_I + moff(m2 - 1, F - 1) + b * F;
+        const double *i2 = tab + rt + moff(m2 - 1, F - 1) + b * F;
 #pragma unroll
         for (int q = 0; q < MM; ++q) {
             Dx[q] = q < m1 ? dx[q] : 0.0;
@@ -442,7 +444,7 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
 #pragma unroll
     for (int c3 = 1; c3 <= C; ++c3) {
         const int m3 = c3 + 1;
-        const double *I3 = tab + T_I + moff(m3 - 1, F - 1);
+        const double *I3 = tab + rt + moff(m3 - 1, F - 1);
         const double *D3 = tab + T_D + doff(m3 - 1);
         const double *w3 = tab + T_W + xoff(m3 - 1);
         double V[NV][MM];
@@ -546,7 +548,7 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
 template <int F>
 static hipError_t launch_iso(const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
                              const double *u, const double *dudt, const double *tab, Geom g, double gamma,
-                             double *te_new, double *te_trad, hipStream_t s) {
+                             int rt, double *te_new, double *te_trad, hipStream_t s) {
     constexpr int C = F > 2 ? F - 2 : 1;
     constexpr int MM = C + 1;
     constexpr int NPAIR = (C + 1) / 2;
@@ -560,22 +562,23 @@ static hipError_t launch_iso(const int32_t *elems, int nelem, const ElemInfo *el
     }
     const int njobs = nelem * NPAIR;
     hipLaunchKernelGGL(k_sweep_iso<F>, dim3(njobs), dim3(256), lds, s, elems, njobs, el, combo_off, u, dudt, tab,
-                       g, gamma, te_new, te_trad);
+                       g, gamma, rt, te_new, te_trad);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
                             const double *u, const double *dudt, const double *tab, Geom g, double gamma,
-                            double *te_new, double *te_trad, hipStream_t s) {
+                            int restriction, double *te_new, double *te_trad, hipStream_t s) {
     if (nelem == 0) return hipSuccess;
+    const int rt = restriction ? T_P : T_I;
     switch (F) {
-        case 2: return launch_iso<2>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
-        case 3: return launch_iso<3>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
-        case 4: return launch_iso<4>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
-        case 5: return launch_iso<5>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
-        case 6: return launch_iso<6>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
-        case 7: return launch_iso<7>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
-        case 8: return launch_iso<8>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, te_new, te_trad, s);
+        case 2: return launch_iso<2>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 3: return launch_iso<3>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 4: return launch_iso<4>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 5: return launch_iso<5>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 6: return launch_iso<6>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 7: return launch_iso<7>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 8: return launch_iso<8>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -276,7 +276,7 @@ def test_misaligned_pointers_rejected():
     st = L.dg_residual(plan.handle, off, ctypes.c_void_p(good.data_ptr()), 0, 0, 0, None)
     assert st == -1 and b"aligned" in L.dg_last_error()
     m = torch.zeros(int(plan.combo_offsets()[-1]) + 2, dtype=torch.float64, device="cuda")
-    st = L.dg_tau_sweep(plan.handle, ctypes.c_void_p(good.data_ptr()), None, ctypes.c_void_p(m.data_ptr() + 8),
+    st = L.dg_tau_sweep(plan.handle, ctypes.c_void_p(good.data_ptr()), None, 0, ctypes.c_void_p(m.data_ptr() + 8),
                         ctypes.c_void_p(m.data_ptr()), None)
     assert st == -1
     st = L.dg_check_state(plan.handle, off, 0, None, None)
