@@ -97,8 +97,9 @@ typedef struct {
  * solution trace, viscous face flux = average of both sides' viscous fluxes; at
  * boundaries the ghost state carries the inner gradient.  Navier-Stokes plans
  * support orders up to 7, and neither the VJP nor batches (DG_EUNSUPPORTED).
- * Curved (DG_MAP_SINE) plans support the residual, RK3, the isolated
- * tau-estimate and the sweep (fine orders up to 7); the coupled tau-estimate, the
+ * Curved (DG_MAP_SINE) plans need orders >= the geometry order and support the
+ * residual, RK3, the tau-estimate (coupled: coarse orders >= the geometry order too,
+ * so that the coarse faces stay watertight) and the sweep (fine orders up to 7); the
  * VJP, the functional and batches return DG_EUNSUPPORTED.
  *   orders_host: host int32 [E][3], natural element order, each in 1..DG_NMAX.
  *   out: receives the plan (release with dg_plan_destroy).
@@ -155,7 +156,10 @@ dg_status dg_residual(dg_plan plan, const void *u, void *r, int32_t dtype, int32
  *   psi, eta: optional adjoint weighting (both NULL or both set): psi is a fine-layout
  *          device double field (e.g. the adjoint of a force functional), eta[E_coarse]
  *          receives sum over coarse nodes and variables of (I psi) * tau_trad; the
- *          functional error estimate is -sum(eta). */
+ *          functional error estimate is -sum(eta).
+ * Errors: DG_EINVAL (null u, foreign coarse plan, psi without eta, bad restriction,
+ * misaligned arrays), DG_EUNSUPPORTED (coupled estimate on a curved mesh with a coarse
+ * order below the geometry order), DG_EHIP. */
 dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt,
                           int32_t isolated, int32_t restriction, double *tau_new, double *tau_trad,
                           double *norms, const double *psi, double *eta, hipStream_t stream);

@@ -741,7 +741,10 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
     DG_ALIGNED(u, dudt, tau_new, tau_trad, norms, psi, eta);
     if (coarse->parent != fine) return fail(DG_EINVAL, "coarse plan was not built from this fine plan");
     if (fine->curved && !isolated)
-        return fail(DG_EUNSUPPORTED, "on curved meshes the tau-estimate is the isolated one");
+        for (int i = 0; i < 3 * coarse->E; ++i)
+            if (coarse->ord[i] < fine->mesh.geo_order[i % 3])
+                return fail(DG_EUNSUPPORTED, "the coupled tau-estimate on curved meshes needs coarse orders >= the "
+                                             "geometry order (watertight coarse faces); the isolated one takes any");
     if ((psi == nullptr) != (eta == nullptr)) return fail(DG_EINVAL, "psi and eta go together");
     if (!tau_new && !tau_trad && !norms && !eta) return DG_OK;
     if (!dudt) {

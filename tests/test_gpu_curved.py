@@ -1,8 +1,9 @@
 """GPU parity on curved elements (the sine-mapped box of the Navier-Stokes workload)
 against the FP64 oracle: node coordinates and metric terms; the Euler and
 Navier-Stokes residuals (both forms, isolated, periodic and far-field boxes, mortars on
-the x and y faces) in FP64 and FP32; RK3 steps; the isolated tau-estimate and its
-refusal in coupled form; the isolated sweep (Euler and Navier-Stokes, curved and box);
+the x and y faces) in FP64 and FP32; RK3 steps; the isolated and coupled
+tau-estimates (sampling and L2 restriction) and the coupled one's refusal below the
+geometry order; the isolated sweep (Euler and Navier-Stokes, curved and box);
 the 32 x 32 x 2 vortex workload on the curved mesh."""
 import numpy as np
 import pytest
@@ -124,16 +125,21 @@ def test_rk3_ns(dtype, tol):
     assert np.max(np.abs(plan.to_natural(ud).astype(np.float64) - ref)) < tol * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("ns", [False, True])
-def test_isolated_tau(ns):
+@pytest.mark.parametrize("ns,isolated,restriction", [(False, True, 0), (True, True, 0), (False, False, 0),
+                                                     (True, False, 0), (False, False, 1), (True, True, 1)])
+def test_tau(ns, isolated, restriction):
+    """Isolated estimates at any coarse order; coupled ones with coarse orders at or
+    above the geometry order (2, 2, 1), mortars between the coarse orders."""
     mesh, fo, u, rng = _case((3, 3, 2), (2, 6), 97, ns=ns, state="pulse")
     co = fo.copy()
-    co[:, :2] = np.minimum(fo[:, :2], rng.integers(1, 6, (len(fo), 2)))
+    lo = 1 if isolated else 2
+    co[:, :2] = np.maximum(lo, np.minimum(fo[:, :2], rng.integers(1, 6, (len(fo), 2))))
     dudt = _resid(mesh, fo, u)
-    ref = _resid(mesh, co, oracle.restrict(fo, co, u), isolated=True) - oracle.restrict(fo, co, dudt)
+    R = oracle.project if restriction else oracle.restrict
+    ref = _resid(mesh, co, R(fo, co, u), isolated=isolated) - R(fo, co, dudt)
     fine = dg.Plan(mesh, fo)
     coarse = fine.coarse(co)
-    tn, tt, norms = dg.tau_estimate(fine, coarse, fine.to_plan(u), None, True)
+    tn, tt, norms = dg.tau_estimate(fine, coarse, fine.to_plan(u), None, isolated, restriction=restriction)
     s = residual_scale(mesh, fo, u)
     assert err(coarse.to_natural(tn), ref, s) < TOL64
     Jc = oracle.metrics(mesh, co).reshape(-1)
@@ -147,8 +153,20 @@ def test_isolated_tau(ns):
         www.append(np.tile(J * np.einsum("k,j,i->kji", w[2], w[1], w[0]).reshape(-1), 5))
     jw = np.concatenate(www)
     assert err(coarse.to_natural(tt), ref * jw, s * np.max(jw)) < TOL64
+    nrm = coarse.elem_to_natural(norms.cpu().numpy())
+    mx = np.array([np.max(np.abs(ref[5 * offs[e]:5 * offs[e + 1]])) for e in range(len(co))])
+    assert err(nrm[:, 0], mx, s) < TOL64
+
+
+def test_coupled_tau_below_the_geometry_order_refused():
+    mesh, fo, u, _ = _case((2, 2, 2), (2, 4), 96)
+    co = fo.copy()
+    co[0, 0] = 1
+    fine = dg.Plan(mesh, fo)
+    coarse = fine.coarse(co)
     with pytest.raises(dg.DGError):
         dg.tau_estimate(fine, coarse, fine.to_plan(u), None, False)
+    dg.tau_estimate(fine, coarse, fine.to_plan(u), None, True)  # the isolated one is defined
 
 
 @pytest.mark.parametrize("curved,ns", [(True, False), (True, True), (False, True)])
