@@ -14,7 +14,11 @@ One step is one pass of the whole estimation path on that state:
 line also carries the per-stage rates (residual GDOF/s, tau-estimates/s), the
 FP32 residual rate and its speed-up over FP64 with both errors against the
 oracle, the roofline of the dominant kernel (the sweep, FP64 vector ALU) and the
-oracle's CPU rate on a bounded sample.
+oracle's CPU rate on a bounded sample.  Outside the timed step: degree selection,
+plan rebuild and projection, the L2-restriction estimate and sweep, the dual
+time-stepping rate, and the secondary legs (64-problem FP32 batch, curved
+Navier-Stokes mesh with its sweep and coupled estimate, adjoint VJP / functional /
+GMRES solve).
 """
 from __future__ import annotations
 
@@ -163,6 +167,15 @@ def main():
     t_project = _timed(torch, stream, lambda: dg.project(plan, new_plan, u), 10)
     proj_bytes = 40.0 * (n_fine + new_plan.n_nodes)
 
+    # estimator variants on the same state: the L2-projection restriction (coupled
+    # estimate and sweep) and the dual time-stepping rate over three stored states
+    L2 = dg.RESTRICT_L2
+    t_tau_l2 = _timed(torch, stream, lambda: dg.tau_estimate(plan, cplan, u, r, restriction=L2), 10)
+    t_sweep_l2 = _timed(torch, stream, lambda: dg.tau_sweep(plan, u, r, restriction=L2), 5)
+    hist = [u, u * (1.0 + 1e-6), u * (1.0 + 2e-6)]
+    t_bdf = _timed(torch, stream, lambda: dg.bdf_rate(plan, hist, 1e-3), 10)
+    del hist
+
     flops_sweep = sweep_flops_per_element(8) * E
     t_sweep_ms = float(np.mean(t_swp))
     achieved = flops_sweep / (t_sweep_ms * 1e-3) / 1e12
@@ -199,6 +212,10 @@ def main():
             "adapt_replan_ms": t_replan,
             "adapt_project_ms": t_project,
             "adapt_project_hbm_frac": proj_bytes / (t_project * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "coupled_tau_l2_restriction_ms": t_tau_l2,
+            "sweep_l2_restriction_ms": t_sweep_l2,
+            "dual_bdf2_rate_ms": t_bdf,
+            "dual_bdf2_rate_hbm_frac": 160.0 * n_fine / (t_bdf * 1e-3) / 1e9 / PEAK_HBM_GBS,
         },
         "roofline": {"bound": "alu", "kernel": "k_sweep", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
@@ -272,6 +289,11 @@ def c3_leg(dg, torch, stream, check=True, dt=1e-5, nsteps=10):
     dudt = dg.residual(plan, u64)
     n_est = int(plan.combo_offsets()[-1])
     tsw = _timed(torch, stream, lambda: dg.tau_sweep(plan, u64, dudt), 10)
+    # coupled estimate on a coarse map at or above the geometry order (2, 2, 1)
+    co = orders.copy()
+    co[:, :2] = np.maximum(2, np.minimum(orders[:, :2], np.random.default_rng(33).integers(1, 6, (len(orders), 2))))
+    cplan = plan.coarse(co)
+    tcp = _timed(torch, stream, lambda: dg.tau_estimate(plan, cplan, u64, dudt), 10)
     us = u32.clone()
     g = torch.empty_like(us)
     dg.rk3_step(plan, us, g, dt, 1)          # capture
@@ -289,7 +311,8 @@ def c3_leg(dg, torch, stream, check=True, dt=1e-5, nsteps=10):
            "residual_fp64_ms": t64, "residual_fp64_gdof_s": n / (t64 * 1e-3) / 1e9,
            "residual_fp32_ms": t32, "residual_fp32_gdof_s": n / (t32 * 1e-3) / 1e9,
            "rk3_fp32_ms_per_step": trk, "rk3_fp32_gdof_steps_s": n / (trk * 1e-3) / 1e9,
-           "sweep_fp64_ms": tsw, "tau_estimates_per_s": n_est / (tsw * 1e-3)}
+           "sweep_fp64_ms": tsw, "tau_estimates_per_s": n_est / (tsw * 1e-3),
+           "coupled_tau_fp64_ms": tcp, "coupled_tau_coarse_nodes": cplan.n_nodes}
     if check:
         import oracle
         A, B = (0.0, -5.0 / 9.0, -153.0 / 128.0), (1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0)
@@ -330,10 +353,21 @@ def c4_leg(dg, torch, stream, check=True):
     out = torch.empty_like(u)
     tv = _timed(torch, stream, lambda: dg.residual_vjp(plan, u, v), 10)
     tf = _timed(torch, stream, lambda: dg.functional(plan, u), 10)
+    # adjoint of the wall force: (dr/du)^T psi = dJ/du by GMRES(30) on the VJP
+    _, dJ = dg.functional(plan, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi, iters, relres = dg.adjoint_solve(plan, u, dJ, restart=30, max_iter=300, rtol=1e-8)
+    torch.cuda.synchronize()
+    t_adj = (time.perf_counter() - t0) * 1e3
+    true_rel = float((dg.residual_vjp(plan, u, psi) - dJ).norm() / dJ.norm())
     res = {"workload": "Euler 24^3 N=5, slip wall x=0, far field x=1, seed 4", "nodes": n,
            "vjp_ms": tv, "vjp_gdof_s": n / (tv * 1e-3) / 1e9,
            "vjp_hbm_frac": 120.0 * n / (tv * 1e-3) / 1e9 / PEAK_HBM_GBS,
-           "functional_ms": tf}
+           "functional_ms": tf,
+           "adjoint_solve": {"method": "GMRES(30) on the residual VJP, rtol 1e-8, at most 300 iterations",
+                             "ms": t_adj, "iterations": iters, "ms_per_iteration": t_adj / max(iters, 1),
+                             "gmres_relres": relres, "true_relres": true_rel}}
     if check:
         import oracle
         w = rng.normal(size=u_nat.shape)
