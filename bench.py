@@ -14,8 +14,8 @@ One step is one pass of the whole estimation path on that state:
 line also carries the per-stage rates (residual GDOF/s, tau-estimates/s), the
 FP32 residual rate and its speed-up over FP64 with both errors against the
 oracle, the roofline of the dominant kernel (the sweep, FP64 vector ALU) and the
-oracle's CPU rate on a bounded sample.  Outside the timed step: degree selection,
-plan rebuild and projection, the L2-restriction estimate and sweep, the dual
+oracle's CPU rate on a bounded sample.  Outside the timed step: degree selection
+(from the map and from its extrapolation to N_max = 9), plan rebuild and projection, the L2-restriction estimate and sweep, the dual
 time-stepping rate, and the secondary legs (64-problem FP32 batch, curved
 Navier-Stokes mesh with its sweep and coupled estimate, adjoint VJP / functional /
 GMRES solve).
@@ -157,6 +157,11 @@ def main():
                                                               approach=2, jump=2), 10)
     sel_orders = dg.select_orders(plan, [ten_s] * 3, tau_max=tau_sel, nmin=1, nmax=8, approach=2, jump=2)
     sel_ndof = int(torch.prod(sel_orders.long() + 1, dim=1).sum())
+    # tau-extrapolation of the map to N_max = 9 and the selection from the extended maps
+    t_extrap = _timed(torch, stream, lambda: dg.tau_extrapolate(plan, ten_s, 9), 10)
+    ext_s = dg.tau_extrapolate(plan, ten_s, 9)
+    t_select_ext = _timed(torch, stream, lambda: dg.select_orders(plan, [ext_s] * 3, tau_max=tau_sel, nmin=1,
+                                                                  nmax=9, approach=2, jump=2, ext_nmax=9), 10)
     # adaptation onto the selected map: plan rebuild (host tables, sort, faces, uploads)
     # and the projection of the solution onto it
     torch.cuda.synchronize()
@@ -212,6 +217,8 @@ def main():
             "adapt_replan_ms": t_replan,
             "adapt_project_ms": t_project,
             "adapt_project_hbm_frac": proj_bytes / (t_project * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "extrapolate_to_nmax9_ms": t_extrap,
+            "select_degrees_extended_ms": t_select_ext,
             "coupled_tau_l2_restriction_ms": t_tau_l2,
             "sweep_l2_restriction_ms": t_sweep_l2,
             "dual_bdf2_rate_ms": t_bdf,

@@ -186,9 +186,11 @@ dg_status dg_tau_sweep(dg_plan fine, const double *u, const double *dudt, int32_
  * p-adaptation, approaches 1 and 2 with the maximum aggregator F_max; jump
  * conditions of Section 3.1, eqs. (a) N >= floor(2/3 N_j) and (b) N >= N_j - 1).
  *
- * A combination (N1, N2, N3) of a map qualifies when its value is below tau_max, every
- * N_i lies in [nmin, nmax], and N_i < P_i (P the plan's orders: combinations at or
- * above P have the high value of the paper's fallback, since no map is extrapolated).
+ * A combination (N1, N2, N3) of a map qualifies when its value is below tau_max and every
+ * N_i lies in [nmin, nmax].  Maps in the sweep layout (ext_nmax = 0) hold the
+ * combinations below the plan's orders P only: those at or above P have the high value
+ * of the paper's fallback.  Extended maps (ext_nmax > 0, from dg_tau_extrapolate) hold
+ * every N_i in 1..ext_nmax, with the extrapolated value or the high value at N_i >= P_i.
  * Among the qualifying combinations the one with the fewest degrees of freedom
  * prod (N_i + 1) is selected; ties go to the smaller map value, then to the smaller
  * (N1, N2, N3) compared lexicographically (N1 first).  An element without a qualifying
@@ -205,14 +207,15 @@ dg_status dg_tau_sweep(dg_plan fine, const double *u, const double *dudt, int32_
  * by raising degrees to the least fixed point.  Integer results are exact; a NaN in
  * a map never qualifies.
  *   maps: host array of nstages (1..DG_SELECT_MAX_STAGES) device double pointers,
- *         each a map in the layout of dg_tau_sweep (te_new or te_trad).
+ *         each a map in the layout of dg_tau_sweep (te_new or te_trad), or with
+ *         ext_nmax > 0 in the extended layout of dg_tau_extrapolate.
  *   orders: device int32 [E][3], natural element order (the layout dg_plan_create
  *           takes), written by the call; the plan's own scratch holds the
  *           intermediate degrees, so one plan runs one selection at a time.
  * Errors: DG_EINVAL for null arguments, nstages outside 1..DG_SELECT_MAX_STAGES,
  * approach not 1 or 2, jump not 0..2, 1 <= nmin <= nmax <= DG_NMAX violated, a
- * NaN tau_max or a negative max_decrease; DG_EHIP for launch failures.  Asynchronous
- * on stream. */
+ * NaN tau_max, a negative max_decrease, or ext_nmax outside 0..DG_NMAX or below nmax
+ * when positive; DG_EHIP for launch failures.  Asynchronous on stream. */
 #define DG_SELECT_MAX_STAGES 32
 typedef struct {
     double tau_max;
@@ -221,6 +224,7 @@ typedef struct {
     int32_t jump;     /* 0 none, 1 (a), 2 (b) */
     const int32_t *prev;  /* NULL, or current degrees (device, [E][3] natural) */
     int32_t max_decrease; /* with prev: largest decrease per direction, >= 0 */
+    int32_t ext_nmax;     /* 0: maps in the sweep layout; > 0: extended maps of that nmax */
 } dg_select_params;
 
 dg_status dg_select_orders(dg_plan fine, const double *const *maps, int32_t nstages,
@@ -228,11 +232,34 @@ dg_status dg_select_orders(dg_plan fine, const double *const *maps, int32_t nsta
 
 /* Total truncation-error map of static adaptation (Section 2.4.2, eq. totalTruncMap with
  * F_max): acc <- max(acc, map) entry by entry, over the sweep layout of the plan
- * (dg_sweep_layout); a NaN in either operand gives NaN (it never qualifies in
+ * (dg_sweep_layout, ext_nmax = 0) or the extended layout of dg_tau_extrapolate
+ * (ext_nmax > 0); a NaN in either operand gives NaN (it never qualifies in
  * dg_select_orders).  Selecting from the accumulated map equals approach 2 over the
  * individual stage maps.  acc, map: device double; they may be the same array.
- * Errors: DG_EINVAL for null arguments.  Asynchronous on stream. */
-dg_status dg_map_fmax(dg_plan fine, double *acc, const double *map, hipStream_t stream);
+ * Errors: DG_EINVAL for null arguments or ext_nmax outside 0..DG_NMAX.  Asynchronous
+ * on stream. */
+dg_status dg_map_fmax(dg_plan fine, double *acc, const double *map, int32_t ext_nmax, hipStream_t stream);
+
+/* tau-extrapolation of an isolated truncation-error map to degrees at and above the
+ * reference degree (Sections 1 and 2.3: the truncation error of smooth solutions decays
+ * exponentially with the degree, so the map computed below P can be extended; Section
+ * 2.4.2, last paragraph: approach 2 works on the extrapolated maps, and a direction
+ * outside the asymptotic range gives the high value).  The paper cites the method
+ * without stating it; this library's reading, per plan element of fine orders P with
+ * computed degrees C_d = max(1, P_d - 1):
+ *   - N_d <= C_d in every direction: the computed value;
+ *   - otherwise, from the inner corner N' (N'_d = C_d where N_d > C_d, N_d elsewhere),
+ *     along every direction d with N_d > C_d the map line through N' is fitted over its
+ *     last L = min(3, C_d) degrees by least squares, ln tau = a + b_d n; the value is
+ *     tau(N') prod_d exp(b_d (N_d - C_d)); a direction with L < 2, a value of its window
+ *     that is not positive and finite, or b_d >= 0 gives +inf (the high value).
+ *   map: device double, sweep layout of the plan (te_new or te_trad of dg_tau_sweep).
+ *   nmax: 1..DG_NMAX, the largest degree of the extended map.
+ *   ext: device double [E][nmax^3], plan element order, (N1, N2, N3) with N1 fastest,
+ *        N_d in 1..nmax; not overlapping map.
+ * Errors: DG_EINVAL (null or misaligned arrays, nmax outside 1..DG_NMAX).  Asynchronous
+ * on stream. */
+dg_status dg_tau_extrapolate(dg_plan fine, const double *map, int32_t nmax, double *ext, hipStream_t stream);
 
 /* Solution transfer onto another order map of the same mesh (Section 2.4.1: after an
  * adaptation the solution is projected onto the new polynomial spaces).  Per element

@@ -48,7 +48,7 @@ class _AdjointParams(ctypes.Structure):
 class _SelectParams(ctypes.Structure):
     _fields_ = [("tau_max", ctypes.c_double), ("nmin", ctypes.c_int32), ("nmax", ctypes.c_int32),
                 ("approach", ctypes.c_int32), ("jump", ctypes.c_int32),
-                ("prev", ctypes.c_void_p), ("max_decrease", ctypes.c_int32)]
+                ("prev", ctypes.c_void_p), ("max_decrease", ctypes.c_int32), ("ext_nmax", ctypes.c_int32)]
 
 
 SELECT_MAX_STAGES = 32
@@ -74,7 +74,8 @@ SIGNATURES = {
     "dg_tau_sweep": [_P, _P, _P, ctypes.c_int32, _P, _P, _P],
     "dg_select_orders": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_SelectParams), _P, _P],
     "dg_project": [_P, _P, _P, _P, _P],
-    "dg_map_fmax": [_P, _P, _P, _P],
+    "dg_map_fmax": [_P, _P, _P, ctypes.c_int32, _P],
+    "dg_tau_extrapolate": [_P, _P, ctypes.c_int32, _P, _P],
     "dg_bdf_rate": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_double, _P, _P],
     "dg_adjoint_workspace": [_P, ctypes.c_int32, _I64P],
     "dg_adjoint_solve": [_P, _P, _P, _P, ctypes.POINTER(_AdjointParams), _P, _I32P,
@@ -280,6 +281,19 @@ class Plan:
         out[self._combo_index()] = a
         return out
 
+    def ext_to_natural(self, t, nmax: int) -> np.ndarray:
+        """Extended map (plan element order) -> numpy [E, nmax^3] in natural element order."""
+        a = t.detach().cpu().numpy().reshape(self.n_elems, int(nmax) ** 3)
+        out = np.empty_like(a)
+        out[self.perm] = a
+        return out
+
+    def ext_to_plan(self, m_nat, nmax: int):
+        """Extended maps [E, nmax^3] in natural element order -> device tensor, plan order."""
+        torch = _torch()
+        a = np.asarray(m_nat, dtype=np.float64).reshape(self.n_elems, int(nmax) ** 3)
+        return torch.from_numpy(np.ascontiguousarray(a[self.perm]).reshape(-1)).cuda()
+
 
 # ---------------------------------------------------------------------- entry points
 def residual(plan: Plan, u, form: int = FORM_NEW, isolated: bool = False, out=None):
@@ -376,23 +390,24 @@ def tau_sweep(plan: Plan, u, dudt=None, restriction: int = RESTRICT_SAMPLE):
 
 
 def select_orders(plan: Plan, maps, tau_max: float, nmin: int = 1, nmax: int = NMAX, approach: int = 2,
-                  jump: int = 0, prev=None, max_decrease: int = 1):
+                  jump: int = 0, prev=None, max_decrease: int = 1, ext_nmax: int = 0):
     """Degrees [E][3] (device int32, natural element order) selected from truncation-error
-    maps of the plan's sweep layout, one map per estimation stage (approach 1: select per
-    stage then the maximum; approach 2: select from the maximum of the maps), no degree
-    more than max_decrease below prev (device int32 [E][3], optional), with the jump
-    condition jump = 1 (floor(2/3 N_j)), 2 (N_j - 1) or 0 (none) enforced."""
+    maps of the plan's sweep layout (or extended maps of tau_extrapolate, ext_nmax > 0),
+    one map per estimation stage (approach 1: select per stage then the maximum;
+    approach 2: select from the maximum of the maps), no degree more than max_decrease
+    below prev (device int32 [E][3], optional), with the jump condition jump = 1
+    (floor(2/3 N_j)), 2 (N_j - 1) or 0 (none) enforced."""
     torch = _torch()
     maps = list(maps)
-    n = int(plan.combo_offsets()[-1])
+    n = plan.n_elems * ext_nmax ** 3 if ext_nmax else int(plan.combo_offsets()[-1])
     for m in maps:
         if m.dtype != torch.float64 or m.numel() != n:
-            raise DGError("maps must be float64 tensors in the sweep layout of the plan")
+            raise DGError("maps must be float64 tensors in the layout of the plan")
     out = torch.empty((plan.n_elems, 3), dtype=torch.int32, device="cuda")
     if prev is not None and (prev.dtype != torch.int32 or prev.numel() != 3 * plan.n_elems):
         raise DGError("prev must be an int32 [E][3] device tensor")
     prm = _SelectParams(float(tau_max), int(nmin), int(nmax), int(approach), int(jump),
-                        None if prev is None else _ptr(prev).value, int(max_decrease))
+                        None if prev is None else _ptr(prev).value, int(max_decrease), int(ext_nmax))
     arr = (_P * max(1, len(maps)))(*[_ptr(m).value for m in maps])
     _call("dg_select_orders", plan.handle, arr, len(maps), ctypes.byref(prm), _ptr(out), _stream())
     return out
@@ -433,15 +448,28 @@ def bdf_rate(plan: Plan, states, dt: float):
     return out
 
 
-def map_fmax(plan: Plan, acc, m):
-    """acc <- max(acc, m) in place (F_max total map of static adaptation; NaN sticky)."""
+def map_fmax(plan: Plan, acc, m, ext_nmax: int = 0):
+    """acc <- max(acc, m) in place (F_max total map of static adaptation; NaN sticky);
+    maps in the sweep layout, or extended maps of tau_extrapolate with ext_nmax > 0."""
     torch = _torch()
-    n = int(plan.combo_offsets()[-1])
+    n = plan.n_elems * ext_nmax ** 3 if ext_nmax else int(plan.combo_offsets()[-1])
     for t in (acc, m):
         if t.dtype != torch.float64 or t.numel() != n:
-            raise DGError("maps must be float64 tensors in the sweep layout of the plan")
-    _call("dg_map_fmax", plan.handle, _ptr(acc), _ptr(m), _stream())
+            raise DGError("maps must be float64 tensors in the layout of the plan")
+    _call("dg_map_fmax", plan.handle, _ptr(acc), _ptr(m), int(ext_nmax), _stream())
     return acc
+
+
+def tau_extrapolate(plan: Plan, m, nmax: int = NMAX):
+    """Extended truncation-error map [E * nmax^3] (plan element order, N1 fastest, N_i in
+    1..nmax) from a sweep-layout map: computed values below the reference degree, the
+    extrapolated decay (or +inf, the high value) at and above it."""
+    torch = _torch()
+    if m.dtype != torch.float64 or m.numel() != int(plan.combo_offsets()[-1]):
+        raise DGError("the map must be a float64 tensor in the sweep layout of the plan")
+    out = torch.empty(plan.n_elems * int(nmax) ** 3, dtype=torch.float64, device="cuda")
+    _call("dg_tau_extrapolate", plan.handle, _ptr(m), int(nmax), _ptr(out), _stream())
+    return out
 
 
 def project(src: Plan, dst: Plan, u):

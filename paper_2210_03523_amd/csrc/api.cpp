@@ -824,12 +824,14 @@ dg_status dg_select_orders(dg_plan p, const double *const *maps, int32_t nstages
         return fail(DG_EINVAL, "degrees must satisfy 1 <= nmin <= nmax <= 9");
     if (std::isnan(prm->tau_max)) return fail(DG_EINVAL, "tau_max is NaN");
     if (prm->prev && prm->max_decrease < 0) return fail(DG_EINVAL, "max_decrease must be >= 0");
+    if (prm->ext_nmax < 0 || prm->ext_nmax > DG_NMAX || (prm->ext_nmax > 0 && prm->ext_nmax < prm->nmax))
+        return fail(DG_EINVAL, "ext_nmax must be 0 (sweep layout) or in nmax..9");
     const dg_mesh_desc &m = p->mesh;
     const int periodic = (m.bc[0] == DG_BC_PERIODIC ? 1 : 0) | (m.bc[2] == DG_BC_PERIODIC ? 2 : 0) |
                          (m.bc[4] == DG_BC_PERIODIC ? 4 : 0);
     HIP_TRY(launch_select(p->d_el, p->E, p->d_combo_off, maps, nstages, prm->tau_max, prm->nmin, prm->nmax,
-                          prm->approach, prm->prev, prm->max_decrease, prm->jump, m.nx, m.ny, m.nz, periodic, orders,
-                          p->d_sel, stream));
+                          prm->approach, prm->prev, prm->max_decrease, prm->ext_nmax, prm->jump, m.nx, m.ny, m.nz,
+                          periodic, orders, p->d_sel, stream));
     return DG_OK;
 }
 
@@ -848,10 +850,20 @@ dg_status dg_bdf_rate(dg_plan p, const double *const *states, int32_t nstates, d
     return DG_OK;
 }
 
-dg_status dg_map_fmax(dg_plan p, double *acc, const double *map, hipStream_t stream) {
+dg_status dg_map_fmax(dg_plan p, double *acc, const double *map, int32_t ext_nmax, hipStream_t stream) {
     if (!p || !acc || !map) return fail(DG_EINVAL, "null argument");
     DG_ALIGNED(acc, map);
-    HIP_TRY(launch_map_fmax(acc, map, p->combo_off[p->E], stream));
+    if (ext_nmax < 0 || ext_nmax > DG_NMAX) return fail(DG_EINVAL, "ext_nmax must be in 0..9");
+    const int64_t n = ext_nmax ? (int64_t)p->E * ext_nmax * ext_nmax * ext_nmax : p->combo_off[p->E];
+    HIP_TRY(launch_map_fmax(acc, map, n, stream));
+    return DG_OK;
+}
+
+dg_status dg_tau_extrapolate(dg_plan p, const double *map, int32_t nmax, double *ext, hipStream_t stream) {
+    if (!p || !map || !ext) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(map, ext);
+    if (nmax < 1 || nmax > DG_NMAX) return fail(DG_EINVAL, "nmax must be in 1..9");
+    HIP_TRY(launch_extrapolate(p->d_el, p->E, p->d_combo_off, map, nmax, ext, stream));
     return DG_OK;
 }
 

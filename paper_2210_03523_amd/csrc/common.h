@@ -154,11 +154,15 @@ hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *ele
 // Isotropic fast path of the sweep (fine nodes F per direction, 2 <= F <= 8).
 // Degree selection from truncation-error maps (maps: host array of nst device pointers)
 // and nmax Jacobi steps of the jump condition; orders natural [E][3]; tmp: [E][3] scratch.
+// X = 0: maps in the sweep layout; X > 0: extended maps [E][X^3] (plan order, N1 fastest).
 hipError_t launch_select(const ElemInfo *el, int E, const int64_t *combo_off, const double *const *maps, int nst,
                          double tau_max, int nmin, int nmax, int approach, const int32_t *prev, int max_decrease,
-                         int jump, int nx, int ny, int nz, int periodic, int32_t *orders, int32_t *tmp,
+                         int X, int jump, int nx, int ny, int nz, int periodic, int32_t *orders, int32_t *tmp,
                          hipStream_t s);
 hipError_t launch_map_fmax(double *acc, const double *m, int64_t n, hipStream_t s);
+// tau-extrapolation of a sweep-layout map into the extended layout [E][X^3]
+hipError_t launch_extrapolate(const ElemInfo *el, int E, const int64_t *combo_off, const double *map, int X,
+                              double *ext, hipStream_t s);
 // Krylov vector operations: out[0] = sum a b (part: dot_partials() doubles of scratch);
 // y <- alpha x + beta y (x may equal y)
 hipError_t launch_dot(const double *a, const double *b, int64_t n, double *part, double *out, hipStream_t s);

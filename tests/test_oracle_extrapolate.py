@@ -69,9 +69,9 @@ def test_two_degrees_are_fitted_one_is_not():
 
 @pytest.mark.parametrize("line", [[0.3, 0.3, 0.3], [0.1, 0.2, 0.4], [0.4, 0.0, 0.1], [0.4, np.nan, 0.1]])
 def test_directions_out_of_the_asymptotic_range_get_the_high_value(line):
-    P = (4, 2, 2)  # C = (3, 1, 1)
     """Flat, growing, touching zero, or not finite (the slope of three points ignores the
     middle one, but a NaN or a zero there still leaves the asymptotic range)."""
+    P = (4, 2, 2)  # C = (3, 1, 1)
     ext = ex.extrapolate_element(P, np.array(line, dtype=np.float64), 6)
     assert np.all(np.isinf(ext[3:6]))
     assert np.array_equal(ext[:3], np.array(line), equal_nan=True)
