@@ -933,7 +933,7 @@ dg_status dg_residual_vjp(dg_plan p, const double *u, const double *v, double *o
         const TileClass &c = p->classes[i];
         HIP_TRY(launch_vjp(p->d_faces, p->nfaces, p->d_tiles, c.first, c.count, c.npt, p->d_el, u, v,
                            (double *)p->d_ff, out, p->tabs.t64, p->geom, p->phys, form, isolated ? 1 : 0,
-                           i == 0 && !isolated, stream));
+                           i == 0 && !isolated, p->max_order, stream));
     }
     return DG_OK;
 }

@@ -132,7 +132,7 @@ hipError_t launch_project(const int32_t *src_inv, int ntarget, const ElemInfo *t
 
 hipError_t launch_vjp(const Face *faces, int nfaces, const Tile *tiles, int tile0, int ntiles, int npt,
                       const ElemInfo *el, const double *u, const double *v, double *fa, double *out,
-                      const double *tab, Geom g, PhysParams ph, int form, int isolated, bool do_faces,
+                      const double *tab, Geom g, PhysParams ph, int form, int isolated, bool do_faces, int max_order,
                       hipStream_t s);
 hipError_t launch_functional(const Face *faces, const int32_t *wall, int nwall, const ElemInfo *el,
                              const double *u, const double *tab, Geom g, double gamma, double *part, double *J,

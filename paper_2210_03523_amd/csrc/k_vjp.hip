@@ -38,14 +38,15 @@ __device__ __forceinline__ double form_weight(const ElemInfo &E, int node, const
 
 // ---------------------------------------------------------------------------- faces
 // D: the face direction as a compile-time constant (a wave-uniform branch in the kernel),
-// so no register array is indexed at run time.
-constexpr int FNV = NNMAX * NNMAX;
-template <int D>
+// so no register array is indexed at run time; KIND: the Riemann flux (0 Roe, 1 Rusanov)
+// as a compile-time constant, so the register budget is that of one flux.  The LDS
+// arrays hold [5][fnv] doubles each, fnv the plan's largest face node count.
+template <int D, int KIND>
 __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restrict__ el, const double *__restrict__ u,
                                            const double *__restrict__ v, double *__restrict__ fa,
                                            const double *__restrict__ tab, const Geom &g, const PhysParams &ph,
-                                           int form, double (*sQL)[FNV], double (*sQR)[FNV], double (*sLL)[FNV],
-                                           double (*sLR)[FNV], double (*sAL)[FNV], double (*sAR)[FNV]) {
+                                           int form, double *sQL, double *sQR, double *sLL, double *sLR, double *sAL,
+                                           double *sAR, int fnv) {
     constexpr int d = D, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const double Ja = g.Ja[d], invJ = 1.0 / g.J;
     const int lane = threadIdx.x;
@@ -80,7 +81,7 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
 #pragma unroll
                 for (int k = 0; k < NV; ++k) qg[k] = f.bc == 1 ? qd[k] : Dual<1>(ph.qfar[k]);
                 if (f.bc == 1) qg[1 + d] = -qd[1 + d];
-                numflux_axis(qd, qg, d, Dual<1>((double)s), Dual<1>(ph.gamma), ph.flux, F);
+                numflux_axis(qd, qg, d, Dual<1>((double)s), Dual<1>(ph.gamma), KIND, F);
                 double a0 = 0.0;
 #pragma unroll
                 for (int w = 0; w < NV; ++w) a0 += lam[w] * F[w].d[0];
@@ -100,8 +101,8 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
         const double c = form_weight(L, node, tab, form, invJ) * iwL;
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-            sQL[k][m] = u[NV * L.noff + k * neL + node];
-            sLL[k][m] = c * v[NV * L.noff + k * neL + node];
+            sQL[k * fnv + m] = u[NV * L.noff + k * neL + node];
+            sLL[k * fnv + m] = c * v[NV * L.noff + k * neL + node];
         }
     }
     for (int m = lane; m < aR * bR; m += 64) {
@@ -109,8 +110,8 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
         const double c = form_weight(R, node, tab, form, invJ) * iwR;
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-            sQR[k][m] = u[NV * R.noff + k * neR + node];
-            sLR[k][m] = c * v[NV * R.noff + k * neR + node];
+            sQR[k * fnv + m] = u[NV * R.noff + k * neR + node];
+            sLR[k * fnv + m] = c * v[NV * R.noff + k * neR + node];
         }
     }
     __syncthreads();
@@ -124,15 +125,15 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
         for (int side = 0; side < 2; ++side) {
             const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
             const bool conf = side == 0 ? confL : confR;
-            double(*sQ)[FNV] = side == 0 ? sQL : sQR;
-            double(*sL)[FNV] = side == 0 ? sLL : sLR;
+            double *sQ = side == 0 ? sQL : sQR;
+            double *sL = side == 0 ? sLL : sLR;
             double *q = side == 0 ? qL : qR;
             const double sg = side == 0 ? 1.0 : -1.0;
             if (conf) {
 #pragma unroll
                 for (int k = 0; k < NV; ++k) {
-                    q[k] = sQ[k][m];
-                    gK[k] = (side == 0 ? 0.0 : gK[k]) + sg * sL[k][m];
+                    q[k] = sQ[k * fnv + m];
+                    gK[k] = (side == 0 ? 0.0 : gK[k]) + sg * sL[k * fnv + m];
                 }
                 continue;
             }
@@ -147,8 +148,8 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
                     const double s1 = S1[a], p1 = P1[a * K1 + A];
 #pragma unroll
                     for (int k = 0; k < NV; ++k) {
-                        qi[k] += s1 * sQ[k][a + na * b];
-                        gi[k] += p1 * sL[k][a + na * b];
+                        qi[k] += s1 * sQ[k * fnv + a + na * b];
+                        gi[k] += p1 * sL[k * fnv + a + na * b];
                     }
                 }
                 const double s2 = S2[b], p2 = P2[b * K2 + B];
@@ -177,13 +178,13 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
                 dl[k].d[0] = k == i0 ? 1.0 : 0.0;
                 dr[k].d[0] = NV + k == i0 ? 1.0 : 0.0;
             }
-            numflux_axis(dl, dr, d, Dual<1>(1.0), Dual<1>(ph.gamma), ph.flux, F);
+            numflux_axis(dl, dr, d, Dual<1>(1.0), Dual<1>(ph.gamma), KIND, F);
             double a0 = 0.0;
 #pragma unroll
             for (int w = 0; w < NV; ++w) a0 += gK[w] * F[w].d[0];
             // the direction index is a loop variable: write to LDS, not a register array
-            if (i0 < NV) sAL[i0][m] = Ja * a0;
-            else sAR[i0 - NV][m] = Ja * a0;
+            if (i0 < NV) sAL[i0 * fnv + m] = Ja * a0;
+            else sAR[(i0 - NV) * fnv + m] = Ja * a0;
         }
     }
     __syncthreads();
@@ -192,7 +193,7 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
         const ElemInfo &E = side == 0 ? L : R;
         const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
         const bool conf = side == 0 ? confL : confR;
-        double(*sA)[FNV] = side == 0 ? sAL : sAR;
+        double *sA = side == 0 ? sAL : sAR;
         double *out = fa + E.foff + fslot(E.n, d, side == 0 ? 1 : -1);
         const double *S1 = tab + T_I + moff(K1 - 1, na - 1);
         const double *S2 = tab + T_I + moff(K2 - 1, nb - 1);
@@ -200,7 +201,7 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
             const int a = m % na, b = m / na;
             if (conf) {
 #pragma unroll
-                for (int k = 0; k < NV; ++k) out[k * na * nb + m] = sA[k][m];
+                for (int k = 0; k < NV; ++k) out[k * na * nb + m] = sA[k * fnv + m];
                 continue;
             }
             double acc[NV] = {0, 0, 0, 0, 0};
@@ -209,7 +210,7 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
                 for (int A = 0; A < K1; ++A) {
                     const double s1 = S1[A * na + a];
 #pragma unroll
-                    for (int k = 0; k < NV; ++k) in[k] += s1 * sA[k][A + K1 * B];
+                    for (int k = 0; k < NV; ++k) in[k] += s1 * sA[k * fnv + A + K1 * B];
                 }
                 const double s2 = S2[B * nb + b];
 #pragma unroll
@@ -221,15 +222,20 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
     }
 }
 
-__global__ __launch_bounds__(64) void k_face_vjp(const Face *__restrict__ faces, const ElemInfo *__restrict__ el,
-                                                 const double *__restrict__ u, const double *__restrict__ v,
-                                                 double *__restrict__ fa, const double *__restrict__ tab, Geom g,
-                                                 PhysParams ph, int form) {
-    __shared__ double sQL[NV][FNV], sQR[NV][FNV], sLL[NV][FNV], sLR[NV][FNV], sAL[NV][FNV], sAR[NV][FNV];
+// Two waves per SIMD: the dual Roe flux needs about 250 registers, so the budget of two
+// waves holds it without spills (the default would allow one wave).
+template <int KIND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_face_vjp(
+    const Face *__restrict__ faces, const ElemInfo *__restrict__ el, const double *__restrict__ u,
+    const double *__restrict__ v, double *__restrict__ fa, const double *__restrict__ tab, Geom g, PhysParams ph,
+    int form, int fnv) {
+    extern __shared__ double lds[];
+    double *sQL = lds, *sQR = lds + NV * fnv, *sLL = lds + 2 * NV * fnv, *sLR = lds + 3 * NV * fnv;
+    double *sAL = lds + 4 * NV * fnv, *sAR = lds + 5 * NV * fnv;
     const Face f = faces[xcd_remap(blockIdx.x, gridDim.x)];  // XCD-contiguous face ranges
-    if (f.d == 0) face_vjp_d<0>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR);
-    else if (f.d == 1) face_vjp_d<1>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR);
-    else face_vjp_d<2>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR);
+    if (f.d == 0) face_vjp_d<0, KIND>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR, fnv);
+    else if (f.d == 1) face_vjp_d<1, KIND>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR, fnv);
+    else face_vjp_d<2, KIND>(f, el, u, v, fa, tab, g, ph, form, sQL, sQR, sLL, sLR, sAL, sAR, fnv);
 }
 
 // ---------------------------------------------------------------------------- elements
@@ -336,10 +342,18 @@ __global__ __launch_bounds__(WG) void k_elem_vjp(const Tile *__restrict__ tiles,
 
 hipError_t launch_vjp(const Face *faces, int nfaces, const Tile *tiles, int tile0, int ntiles, int npt,
                       const ElemInfo *el, const double *u, const double *v, double *fa, double *out,
-                      const double *tab, Geom g, PhysParams ph, int form, int isolated, bool do_faces,
+                      const double *tab, Geom g, PhysParams ph, int form, int isolated, bool do_faces, int max_order,
                       hipStream_t s) {
-    if (do_faces && nfaces > 0)
-        hipLaunchKernelGGL(k_face_vjp, dim3(nfaces), dim3(64), 0, s, faces, el, u, v, fa, tab, g, ph, form);
+    if (do_faces && nfaces > 0) {
+        const int fnv = (max_order + 1) * (max_order + 1);  // largest face node count
+        const size_t lds = sizeof(double) * 6 * NV * (size_t)fnv;
+        if (ph.flux == 1)
+            hipLaunchKernelGGL(k_face_vjp<1>, dim3(nfaces), dim3(64), lds, s, faces, el, u, v, fa, tab, g, ph, form,
+                               fnv);
+        else
+            hipLaunchKernelGGL(k_face_vjp<0>, dim3(nfaces), dim3(64), lds, s, faces, el, u, v, fa, tab, g, ph, form,
+                               fnv);
+    }
     if (ntiles == 0) return hipGetLastError();
     switch (npt) {
         case 1: hipLaunchKernelGGL(k_elem_vjp<1>, dim3(ntiles), dim3(WG), 0, s, tiles, tile0, ntiles, el, u, v, fa, out, tab, g, ph, form, isolated); break;
