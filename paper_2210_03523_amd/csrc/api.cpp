@@ -1106,7 +1106,7 @@ struct dg_batch_s {
     int shape = 1;  // element-kernel shape (launch_elem_batch); valid for every tile of <= 512 nodes
     int ntiles = 0, nfaces = 0;
     BatchTile *d_tiles = nullptr;
-    int2 *d_faces = nullptr;
+    BatchFace *d_faces = nullptr;
     hipStream_t cap_stream = nullptr;
     std::map<BatchKey, std::pair<void *, hipGraphExec_t>> graphs;  // ProbDesc array + graph
     void *d_probs_eager = nullptr;                                    // ProbDesc array of eager calls
@@ -1281,11 +1281,29 @@ dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_bat
     dg_batch b = new dg_batch_s();
     b->plans.assign(plans, plans + n);
     b->dtype = dtype;
-    std::vector<int2> faces;
-    for (int i = 0; i < n; ++i)
-        for (int f = 0; f < plans[i]->nfaces; ++f) faces.push_back(make_int2(i, f));
+    // face records: each face with both sides' element descriptors (read back once here)
+    std::vector<BatchFace> faces;
+    dg_status st = DG_OK;
+    for (int i = 0; i < n && !st; ++i) {
+        const dg_plan p = plans[i];
+        std::vector<Face> pf(p->nfaces);
+        std::vector<ElemInfo> pe(p->E);
+        if (hipMemcpy(pf.data(), p->d_faces, sizeof(Face) * pf.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(pe.data(), p->d_el, sizeof(ElemInfo) * pe.size(), hipMemcpyDeviceToHost) != hipSuccess) {
+            st = fail(DG_EHIP, "reading back a plan's faces failed");
+            break;
+        }
+        for (const Face &f : pf) {
+            BatchFace r{};
+            r.f = f;
+            r.L = pe[f.eL >= 0 ? f.eL : f.eR];
+            r.R = pe[f.eR >= 0 ? f.eR : f.eL];
+            r.prob = i;
+            faces.push_back(r);
+        }
+    }
     b->nfaces = (int)faces.size();
-    dg_status st = upload(&b->d_faces, faces);
+    if (!st) st = upload(&b->d_faces, faces);
     if (!st && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
         st = fail(DG_EHIP, "stream creation failed");
     if (!st) st = dtype == DG_F64 ? autotune<double>(b) : autotune<float>(b);

@@ -193,13 +193,21 @@ struct ProbDesc {
     PhysParams phys;
 };
 
+// A face of a batch: the face of problem `prob` with both sides' element descriptors
+// (a boundary face's one element in both).
+struct BatchFace {
+    Face f;
+    ElemInfo L, R;
+    int32_t prob, pad[3];
+};
+
 // A tile of a batch: `count` consecutive plan elements of problem `prob`.
 struct BatchTile {
     int32_t prob, first, count, pad;
 };
 
 template <typename T>
-hipError_t launch_face_batch(const int2 *faces, int nfaces, const ProbDesc<T> *probs, const T *tab, int grid,
+hipError_t launch_face_batch(const BatchFace *faces, int nfaces, const ProbDesc<T> *probs, const T *tab, int grid,
                              hipStream_t s);
 // shape: 0 = 256 lanes x 1 node, 1 = 256 x 2, 2 = 512 x 1 (tile capacity 256 for shape 0, 512 otherwise)
 template <typename T>

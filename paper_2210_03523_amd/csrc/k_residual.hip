@@ -51,19 +51,19 @@ struct FaceSmem {
 // solution, (Q_L + Q_R)/2 on the mortar projected back onto both sides (no sign, no
 // metric), the face input of the gradient pass.
 // D: the face direction as a compile-time constant (see face_body below).
+// L, R: the elements of the two sides (a boundary face passes its one element in both).
 template <typename T, int FN, int MODE, int D>
-__device__ __forceinline__ void face_body_d(const Face f, const ElemInfo *__restrict__ el, const T *__restrict__ u,
-                                            T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
-                                            const PhysParams &ph, FaceSmem<T, FN> &sm) {
+__device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, const ElemInfo &R,
+                                            const T *__restrict__ u, T *__restrict__ ff, const T *__restrict__ tab,
+                                            const Geom &g, const PhysParams &ph, FaceSmem<T, FN> &sm) {
     constexpr int d = D, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const T Ja = (T)g.Ja[d];
     const T gam = (T)ph.gamma;
     const int lane = threadIdx.x;
 
     if (f.bc != 0) {
-        const int e = f.eL >= 0 ? f.eL : f.eR;
         const int s = f.eL >= 0 ? 1 : -1;
-        const ElemInfo E = el[e];
+        const ElemInfo &E = f.eL >= 0 ? L : R;
         const int na = E.n[t1], nb = E.n[t2], ne = E.n[0] * E.n[1] * E.n[2];
         const T *Q = u + NV * E.noff;
         T *out = ff + E.foff + fslot(E.n, d, s);
@@ -92,7 +92,6 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo *__rest
         return;
     }
 
-    const ElemInfo L = el[f.eL], R = el[f.eR];
     const int aL = L.n[t1], bL = L.n[t2], aR = R.n[t1], bR = R.n[t2];
     const int K1 = aL > aR ? aL : aR, K2 = bL > bR ? bL : bR;
     const int neL = L.n[0] * L.n[1] * L.n[2], neR = R.n[0] * R.n[1] * R.n[2];
@@ -245,12 +244,20 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo *__rest
 // made a compile-time constant by a wave-uniform branch, so nothing is indexed at run
 // time (which would put the arrays in scratch memory).
 template <typename T, int FN, int MODE = 0>
-__device__ __forceinline__ void face_body(const Face f, const ElemInfo *__restrict__ el, const T *__restrict__ u,
-                                          T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
-                                          const PhysParams &ph, FaceSmem<T, FN> &sm) {
-    if (f.d == 0) face_body_d<T, FN, MODE, 0>(f, el, u, ff, tab, g, ph, sm);
-    else if (f.d == 1) face_body_d<T, FN, MODE, 1>(f, el, u, ff, tab, g, ph, sm);
-    else face_body_d<T, FN, MODE, 2>(f, el, u, ff, tab, g, ph, sm);
+__device__ __forceinline__ void face_body(const Face f, const ElemInfo &L, const ElemInfo &R,
+                                          const T *__restrict__ u, T *__restrict__ ff, const T *__restrict__ tab,
+                                          const Geom &g, const PhysParams &ph, FaceSmem<T, FN> &sm) {
+    if (f.d == 0) face_body_d<T, FN, MODE, 0>(f, L, R, u, ff, tab, g, ph, sm);
+    else if (f.d == 1) face_body_d<T, FN, MODE, 1>(f, L, R, u, ff, tab, g, ph, sm);
+    else face_body_d<T, FN, MODE, 2>(f, L, R, u, ff, tab, g, ph, sm);
+}
+
+// The two sides' elements of a face (a boundary face's one element twice), loaded side
+// by side rather than one after the other.
+__device__ __forceinline__ void face_elems(const Face &f, const ElemInfo *__restrict__ el, ElemInfo &L,
+                                           ElemInfo &R) {
+    L = el[f.eL >= 0 ? f.eL : f.eR];
+    R = el[f.eR >= 0 ? f.eR : f.eL];
 }
 
 template <typename T, int FN>
@@ -259,7 +266,10 @@ __global__ __launch_bounds__(64) void k_face(const Face *__restrict__ faces, con
                                              const T *__restrict__ tab, Geom g, PhysParams ph) {
     __shared__ FaceSmem<T, FN> sm;
     // XCD-contiguous face ranges: both sides' element blocks stay in one L2
-    face_body<T, FN>(faces[xcd_remap(blockIdx.x, gridDim.x)], el, u, ff, tab, g, ph, sm);
+    const Face f = faces[xcd_remap(blockIdx.x, gridDim.x)];
+    ElemInfo L, R;
+    face_elems(f, el, L, R);
+    face_body<T, FN>(f, L, R, u, ff, tab, g, ph, sm);
 }
 
 template <typename T>
@@ -569,7 +579,10 @@ __global__ __launch_bounds__(64) void k_face_avg(const Face *__restrict__ faces,
                                                  const T *__restrict__ u, T *__restrict__ fq,
                                                  const T *__restrict__ tab, Geom g, PhysParams ph) {
     __shared__ FaceSmem<T, FN> sm;
-    face_body<T, FN, 1>(faces[xcd_remap(blockIdx.x, gridDim.x)], el, u, fq, tab, g, ph, sm);
+    const Face f = faces[xcd_remap(blockIdx.x, gridDim.x)];
+    ElemInfo L, R;
+    face_elems(f, el, L, R);
+    face_body<T, FN, 1>(f, L, R, u, fq, tab, g, ph, sm);
 }
 
 template <typename T, int NPT>
@@ -816,17 +829,19 @@ template hipError_t launch_ns_faces<float>(const Face *, int, const ElemInfo *, 
 // (listed problem by problem, neighbours close together) go in contiguous ranges, one
 // per workgroup, and the workgroups of one XCD take neighbouring ranges, so both sides'
 // element blocks stay in that XCD's L2; element tiles (sorted by cost) go cyclically.
+// Each face record carries the face and both sides' element descriptors, so a face
+// waits on two loads (its record, then its problem's descriptor) before its data.
 template <typename T>
-__global__ __launch_bounds__(64) void k_face_batch(const int2 *__restrict__ faces, int nfaces,
+__global__ __launch_bounds__(64) void k_face_batch(const BatchFace *__restrict__ faces, int nfaces,
                                                    const ProbDesc<T> *__restrict__ probs, const T *__restrict__ tab) {
     __shared__ FaceSmem<T, 64> sm;  // batches hold orders up to 7
     const int chunk = (nfaces + gridDim.x - 1) / gridDim.x;
     const int i0 = xcd_remap(blockIdx.x, gridDim.x) * chunk;
     const int i1 = min(nfaces, i0 + chunk);
     for (int i = i0; i < i1; ++i) {
-        const int2 pf = faces[i];
-        const ProbDesc<T> pd = probs[pf.x];
-        face_body<T, 64>(pd.faces[pf.y], pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, sm);
+        const BatchFace bf = faces[i];
+        const ProbDesc<T> pd = probs[bf.prob];
+        face_body<T, 64>(bf.f, bf.L, bf.R, pd.u, pd.ff, tab, pd.geom, pd.phys, sm);
         __syncthreads();
     }
 }
@@ -850,7 +865,7 @@ __global__ __launch_bounds__(BS) void k_elem_batch(const BatchTile *__restrict__
 }
 
 template <typename T>
-hipError_t launch_face_batch(const int2 *faces, int nfaces, const ProbDesc<T> *probs, const T *tab, int grid,
+hipError_t launch_face_batch(const BatchFace *faces, int nfaces, const ProbDesc<T> *probs, const T *tab, int grid,
                              hipStream_t s) {
     if (nfaces == 0) return hipSuccess;
     hipLaunchKernelGGL(k_face_batch<T>, dim3(grid), dim3(64), 0, s, faces, nfaces, probs, tab);
@@ -896,9 +911,9 @@ hipError_t launch_fill_state(const ElemInfo *el, int E, T *u, hipStream_t s) {
     return hipGetLastError();
 }
 
-template hipError_t launch_face_batch<double>(const int2 *, int, const ProbDesc<double> *, const double *, int,
+template hipError_t launch_face_batch<double>(const BatchFace *, int, const ProbDesc<double> *, const double *, int,
                                               hipStream_t);
-template hipError_t launch_face_batch<float>(const int2 *, int, const ProbDesc<float> *, const float *, int,
+template hipError_t launch_face_batch<float>(const BatchFace *, int, const ProbDesc<float> *, const float *, int,
                                              hipStream_t);
 template hipError_t launch_elem_batch<double>(const BatchTile *, int, const ProbDesc<double> *, const double *, int, int,
                                               EpiArgs, hipStream_t);
