@@ -1107,6 +1107,7 @@ struct dg_batch_s {
     int ntiles = 0, nfaces = 0;
     BatchTile *d_tiles = nullptr;
     BatchFace *d_faces = nullptr;
+    std::vector<std::vector<ElemInfo>> hel;  // element descriptors of every plan (host copies)
     hipStream_t cap_stream = nullptr;
     std::map<BatchKey, std::pair<void *, hipGraphExec_t>> graphs;  // ProbDesc array + graph
     void *d_probs_eager = nullptr;                                    // ProbDesc array of eager calls
@@ -1128,7 +1129,8 @@ void destroy_batch(dg_batch b) {
 }
 
 // Tiles of every problem for a tile capacity, sorted by node count (largest first).
-std::vector<BatchTile> batch_tiles(const std::vector<dg_plan> &plans, int cap) {
+std::vector<BatchTile> batch_tiles(const std::vector<dg_plan> &plans, const std::vector<std::vector<ElemInfo>> &hel,
+                                   int cap) {
     std::vector<std::pair<int, BatchTile>> t;
     for (int pi = 0; pi < (int)plans.size(); ++pi) {
         const dg_plan p = plans[pi];
@@ -1141,7 +1143,7 @@ std::vector<BatchTile> batch_tiles(const std::vector<dg_plan> &plans, int cap) {
             const int per = std::max(1, cap / npe);
             for (int k = i; k < j; k += per) {
                 const int cnt = std::min(per, j - k);
-                t.push_back({cnt * npe, BatchTile{pi, k, cnt, 0}});
+                t.push_back({cnt * npe, BatchTile{pi, k, cnt, 0, hel[pi][k]}});
             }
             i = j;
         }
@@ -1179,7 +1181,7 @@ dg_status batch_pass(dg_batch b, const ProbDesc<T> *probs, EpiArgs epi, hipStrea
 }
 
 dg_status set_tiles(dg_batch b, int cap) {
-    auto tiles = batch_tiles(b->plans, cap);
+    auto tiles = batch_tiles(b->plans, b->hel, cap);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     b->d_tiles = nullptr;
     b->ntiles = (int)tiles.size();
@@ -1301,6 +1303,7 @@ dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_bat
             r.prob = i;
             faces.push_back(r);
         }
+        b->hel.push_back(std::move(pe));
     }
     b->nfaces = (int)faces.size();
     if (!st) st = upload(&b->d_faces, faces);

@@ -201,9 +201,11 @@ struct BatchFace {
     int32_t prob, pad[3];
 };
 
-// A tile of a batch: `count` consecutive plan elements of problem `prob`.
+// A tile of a batch: `count` consecutive plan elements of problem `prob`, e0 the
+// descriptor of the first.
 struct BatchTile {
     int32_t prob, first, count, pad;
+    ElemInfo e0;
 };
 
 template <typename T>

@@ -290,13 +290,13 @@ hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems
 // VISC: Navier-Stokes (gradients in epi.grad); the Euler instances carry no viscous registers.
 // sD (LDS, 3 NNMAX^2): the tile's derivative matrices, staged so that the per-lane rows are
 // read from LDS rather than through vector memory loads.
+// E0: the descriptor of the tile's first element (every element of a tile has its orders).
 template <typename T, int NPT, bool CURVED = false, int BS = WG, bool VISC = true>
-__device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo *__restrict__ el, const T *u,
+__device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, const T *u,
                                           const T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
                                           const PhysParams &ph, const EpiArgs &epi, T (&sF)[NV][BS * NPT],
                                           T *sD) {
     const int tid = threadIdx.x;
-    const ElemInfo E0 = el[tl.first];
     const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
     {
         const int ns[3] = {n1, n2, n3};
@@ -534,8 +534,8 @@ __global__ __launch_bounds__(BS) void k_elem(const Tile *__restrict__ tiles, int
                                              PhysParams ph, EpiArgs epi) {
     __shared__ T sF[NV][BS * NPT];
     __shared__ T sD[3 * NNMAX * NNMAX];
-    elem_body<T, NPT, CURVED, BS, VISC>(tiles[tile0 + xcd_remap(blockIdx.x, ntiles)], el, u, ff, tab, g, ph, epi,
-                                        sF, sD);
+    const Tile tl = tiles[tile0 + xcd_remap(blockIdx.x, ntiles)];
+    elem_body<T, NPT, CURVED, BS, VISC>(tl, el[tl.first], u, ff, tab, g, ph, epi, sF, sD);
 }
 
 template <typename T>
@@ -858,8 +858,8 @@ __global__ __launch_bounds__(BS) void k_elem_batch(const BatchTile *__restrict__
         EpiArgs epi = epi0;
         epi.out = pd.out;
         epi.g = pd.g;
-        elem_body<T, NPT, false, BS, false>(Tile{bt.first, bt.count}, pd.el, pd.u, pd.ff, tab, pd.geom, pd.phys, epi,
-                                           sF, sD);
+        elem_body<T, NPT, false, BS, false>(Tile{bt.first, bt.count}, bt.e0, pd.u, pd.ff, tab, pd.geom, pd.phys,
+                                           epi, sF, sD);
         __syncthreads();
     }
 }
