@@ -292,12 +292,10 @@ hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *ele
                               hipStream_t s) {
     if (ntasks == 0) return hipSuccess;
     size_t lds = sizeof(double) * (size_t)(x1cap + 2 * x2cap + 8);
-    static bool attr_set = false;
-    if (lds > 64 * 1024 && !attr_set) {
+    if (lds > 64 * 1024) {  // per device: set on every launch (a host-side call)
         hipError_t e = hipFuncSetAttribute((const void *)k_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            160 * 1024);
         if (e != hipSuccess) return e;
-        attr_set = true;
     }
     hipLaunchKernelGGL(k_sweep, dim3(ntasks), dim3(SW_WG), lds, s, (const SweepTask *)tasks, ntasks, elems,
                        combo_off, u, dudt, tab, g, gamma, x1cap, x2cap, restriction ? T_P : T_I, te_new, te_trad);
@@ -553,12 +551,10 @@ static hipError_t launch_iso(const int32_t *elems, int nelem, const ElemInfo *el
     constexpr int MM = C + 1;
     constexpr int NPAIR = (C + 1) / 2;
     const size_t lds = sizeof(double) * (size_t)(2 * NV * MM * 256) + sizeof(unsigned long long) * 2 * C * C * 2;
-    static bool attr = false;
-    if (!attr) {
+    {  // per device: set on every launch (a host-side call)
         hipError_t e = hipFuncSetAttribute((const void *)k_sweep_iso<F>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
         if (e != hipSuccess) return e;
-        attr = true;
     }
     const int njobs = nelem * NPAIR;
     hipLaunchKernelGGL(k_sweep_iso<F>, dim3(njobs), dim3(256), lds, s, elems, njobs, el, combo_off, u, dudt, tab,
