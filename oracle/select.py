@@ -16,8 +16,9 @@ What it follows (arXiv 2210.03523):
     fewest degrees of freedom prod_i (N_i + 1).
   * Section 2.4.2, last paragraph: where the map cannot be extended to N_i >= P_i
     (P the order the estimate was computed on), those combinations get a high
-    value, i.e. they never qualify.  No extrapolation is done here, so only the
-    combinations of the sweep below P qualify.
+    value, i.e. they never qualify.  This module selects from the computed maps, so
+    only the combinations of the sweep below P qualify; the extrapolated maps and the
+    selection from them are in extrapolate.py.
   * Section 3.2 (dynamic adaptation of the cylinder case): a degree may fall by at most
     one per adaptation stage (applied before the jump conditions; both only raise).
   * Section 3.1, jump conditions (a) N_i^e >= max_j floor(2/3 N_i^j) and
