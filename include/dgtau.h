@@ -12,8 +12,9 @@
  *     throws across this interface.
  *   - Device pointers are HIP device memory owned by the caller; host pointers
  *     are marked "host".  Device arrays must be 16-byte aligned (every hipMalloc
- *     or torch allocation is); a misaligned one returns DG_EINVAL.  Compute calls are asynchronous on the given stream
- *     (NULL = the legacy default stream) and allocate no memory.
+ *     or torch allocation is); a misaligned one returns DG_EINVAL.  Compute calls
+ *     are asynchronous on the given stream (NULL = the legacy default stream) and
+ *     allocate no memory.
  *   - Plans own only their internal device buffers (tables, tiles, face lists,
  *     face-flux and tau scratch).  A plan is immutable after creation; because
  *     it holds scratch buffers, one plan must not be used by two streams at once.
