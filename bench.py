@@ -420,7 +420,8 @@ def c5_leg(dg, torch, stream, steps=5, warmup=1, check=True, dt=1e-4):
     t64 = timed(lambda k: [dg.rk3_step(p, u, g, dt, k) for p, u, g in zip(plans, u64, g64)])
     res = {"workload": "64 periodic Euler problems, n ~ U{8..20}^3 elements, orders U{1..7}^3, seed 5",
            "problems": len(plans), "nodes": nodes, "dt": dt,
-           "schedule": dict(zip(("tile_cap", "elem_grid", "face_grid"), batch.schedule())),
+           "schedule": dict(zip(("tile_cap", "elem_grid", "face_grid", "elem_shape", "from_cache"),
+                                batch.schedule_info())),
            "fp32_batched_ms_per_rk3_step": t32, "fp64_plain_ms_per_rk3_step": t64,
            "fp32_batched_gdof_steps_s": nodes / (t32 * 1e-3) / 1e9,
            "fp64_plain_gdof_steps_s": nodes / (t64 * 1e-3) / 1e9,

@@ -349,10 +349,14 @@ dg_status dg_rk3_step(dg_plan plan, void *u, void *g, double dt, int32_t nsteps,
  * Batches: many independent problems (plans) advanced by the same launches.
  * Each residual evaluation / RK3 stage of a batch is one persistent face launch
  * and one persistent element launch over the cost-sorted work lists of every
- * problem.  The schedule (tile capacity in nodes, grid sizes) is chosen at
- * creation by timing candidates on a uniform scratch state (the library's own
- * autotuner).  The plans must outlive the batch and must not be used on another
- * stream while the batch runs (their face-flux scratch is shared).
+ * problem.  The schedule (tile capacity in nodes, element-kernel shape, grid sizes)
+ * is chosen at creation by timing candidates on a uniform scratch state (the
+ * library's own autotuner), and cached for the process by device architecture and
+ * compute-unit count, precision and batch composition (per problem the element and
+ * face counts and the element count of every order triple): a later batch of the
+ * same composition takes the cached schedule without timing.  The plans must
+ * outlive the batch and must not be used on another stream while the batch runs
+ * (their face-flux scratch is shared).
  * ------------------------------------------------------------------------- */
 typedef struct dg_batch_s *dg_batch;
 
@@ -361,8 +365,11 @@ typedef struct dg_batch_s *dg_batch;
  * search.  Errors: DG_EINVAL, DG_EUNSUPPORTED (order > 7), DG_ENOMEM, DG_EHIP. */
 dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_batch *out);
 dg_status dg_batch_destroy(dg_batch batch);
-/* The schedule the autotuner chose (host outputs, any may be NULL). */
-dg_status dg_batch_schedule(dg_batch batch, int32_t *tile_cap, int32_t *elem_grid, int32_t *face_grid);
+/* The schedule the autotuner chose (host outputs, any may be NULL): tile capacity in
+ * nodes, element and face grid sizes, element-kernel shape (0: 256 lanes x 1 node,
+ * 1: 256 x 2, 2: 512 x 1), and from_cache = 1 when it came from the cache. */
+dg_status dg_batch_schedule(dg_batch batch, int32_t *tile_cap, int32_t *elem_grid, int32_t *face_grid,
+                            int32_t *shape, int32_t *from_cache);
 /* New-form residual of every problem (Section 2.1): u[i], r[i] device arrays of
  * problem i in its plan layout (host arrays of n device pointers). */
 dg_status dg_batch_residual(dg_batch batch, const void *const *u, void *const *r, hipStream_t stream);

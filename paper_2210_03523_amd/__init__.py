@@ -85,7 +85,7 @@ SIGNATURES = {
     "dg_check_state": [_P, _P, ctypes.c_int32, _I64P, _P],
     "dg_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)],
     "dg_batch_destroy": [_P],
-    "dg_batch_schedule": [_P, _I32P, _I32P, _I32P],
+    "dg_batch_schedule": [_P, _I32P, _I32P, _I32P, _I32P, _I32P],
     "dg_batch_residual": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P],
     "dg_batch_rk3_step": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_double, ctypes.c_int32, _P],
 }
@@ -526,9 +526,13 @@ class Batch:
 
     def schedule(self):
         """(tile capacity in nodes, element grid, face grid) chosen by the autotuner."""
-        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _call("dg_batch_schedule", self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
-        return a.value, b.value, c.value
+        return self.schedule_info()[:3]
+
+    def schedule_info(self):
+        """(tile capacity, element grid, face grid, element-kernel shape, from_cache)."""
+        v = [ctypes.c_int32() for _ in range(5)]
+        _call("dg_batch_schedule", self.handle, *[ctypes.byref(x) for x in v])
+        return tuple(x.value for x in v[:4]) + (bool(v[4].value),)
 
     def _ptrs(self, ts):
         if len(ts) != len(self.plans):

@@ -1111,6 +1111,7 @@ struct dg_batch_s {
     hipStream_t cap_stream = nullptr;
     std::map<BatchKey, std::pair<void *, hipGraphExec_t>> graphs;  // ProbDesc array + graph
     void *d_probs_eager = nullptr;                                    // ProbDesc array of eager calls
+    bool from_cache = false;  // schedule taken from the autotuner's cache
 };
 
 namespace {
@@ -1267,6 +1268,35 @@ dg_status autotune(dg_batch b) {
     return set_tiles(b, bc);
 }
 
+// Schedules found by the autotuner, per device (architecture and compute-unit count),
+// precision and batch composition (per problem: element and face counts and the number
+// of elements of every order triple), so that a batch of the same shape -- for example
+// one re-created after an adaptation stage that kept every problem's orders -- skips the
+// timing search.  Process-wide, guarded by a mutex.
+struct TunedSchedule {
+    int tile_cap, shape, elem_grid, face_grid;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TunedSchedule> g_tune_cache;
+
+std::string tune_key(dg_batch b) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t prop{};
+    hipGetDeviceProperties(&prop, dev);
+    std::string k = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "/" +
+                    std::to_string(b->dtype);
+    for (dg_plan p : b->plans) {
+        std::map<std::tuple<int, int, int>, int> hist;
+        for (int e = 0; e < p->E; ++e) ++hist[std::make_tuple(p->ord[3 * e], p->ord[3 * e + 1], p->ord[3 * e + 2])];
+        k += "|" + std::to_string(p->E) + "," + std::to_string(p->nfaces);
+        for (const auto &kv : hist)
+            k += ";" + std::to_string(std::get<0>(kv.first)) + "." + std::to_string(std::get<1>(kv.first)) + "." +
+                 std::to_string(std::get<2>(kv.first)) + ":" + std::to_string(kv.second);
+    }
+    return k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1309,7 +1339,32 @@ dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_bat
     if (!st) st = upload(&b->d_faces, faces);
     if (!st && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
         st = fail(DG_EHIP, "stream creation failed");
-    if (!st) st = dtype == DG_F64 ? autotune<double>(b) : autotune<float>(b);
+    if (!st) {
+        const std::string key = tune_key(b);
+        TunedSchedule ts{};
+        bool hit = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                ts = it->second;
+                hit = true;
+            }
+        }
+        if (hit) {
+            b->shape = ts.shape;
+            b->elem_grid = ts.elem_grid;
+            b->face_grid = ts.face_grid;
+            b->from_cache = true;
+            st = set_tiles(b, ts.tile_cap);
+        } else {
+            st = dtype == DG_F64 ? autotune<double>(b) : autotune<float>(b);
+            if (!st) {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                g_tune_cache[key] = TunedSchedule{b->tile_cap, b->shape, b->elem_grid, b->face_grid};
+            }
+        }
+    }
     if (!st && hipMalloc(&b->d_probs_eager, sizeof(ProbDesc<double>) * n) != hipSuccess)
         st = fail(DG_ENOMEM, "device allocation failed");
     if (st) {
@@ -1325,11 +1380,14 @@ dg_status dg_batch_destroy(dg_batch b) {
     return DG_OK;
 }
 
-dg_status dg_batch_schedule(dg_batch b, int32_t *tile_cap, int32_t *elem_grid, int32_t *face_grid) {
+dg_status dg_batch_schedule(dg_batch b, int32_t *tile_cap, int32_t *elem_grid, int32_t *face_grid, int32_t *shape,
+                            int32_t *from_cache) {
     if (!b) return fail(DG_EINVAL, "null batch");
     if (tile_cap) *tile_cap = b->tile_cap;
     if (elem_grid) *elem_grid = b->elem_grid;
     if (face_grid) *face_grid = b->face_grid;
+    if (shape) *shape = b->shape;
+    if (from_cache) *from_cache = b->from_cache ? 1 : 0;
     return DG_OK;
 }
 

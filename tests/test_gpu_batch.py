@@ -46,6 +46,26 @@ def test_batch_residual(dtype, tol):
             assert torch.allclose(r1, r, rtol=0, atol=1e-13 * s)
 
 
+def test_schedule_cache():
+    """A second batch of the same composition (new plans of the same meshes and orders)
+    takes the autotuner's cached schedule and gives the same residuals bit for bit; a
+    batch of the other precision is tuned afresh."""
+    probs = _problems(nprob=5, seed=33)
+    pa = [dg.Plan(m, o) for m, o, _ in probs]
+    a = dg.Batch(pa, dtype=torch.float32)
+    assert a.schedule_info()[4] is False
+    pb = [dg.Plan(m, o) for m, o, _ in probs]
+    b = dg.Batch(pb, dtype=torch.float32)
+    ia, ib = a.schedule_info(), b.schedule_info()
+    assert ib[4] is True and ia[:4] == ib[:4]
+    ua = [p.to_plan(u, dtype=torch.float32) for p, (_, _, u) in zip(pa, probs)]
+    ub = [p.to_plan(u, dtype=torch.float32) for p, (_, _, u) in zip(pb, probs)]
+    for ra, rb in zip(dg.batch_residual(a, ua), dg.batch_residual(b, ub)):
+        assert torch.equal(ra, rb)
+    c = dg.Batch(pb, dtype=torch.float64)
+    assert c.schedule_info()[4] is False
+
+
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 2e-5)])
 def test_batch_rk3_graph(dtype, tol):
     probs = _problems(nprob=5, seed=32)
