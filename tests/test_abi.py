@@ -36,3 +36,20 @@ def test_last_error_is_empty_string_initially():
     if not os.path.exists(dg.LIB_PATH):
         pytest.skip("library not built")
     assert dg.lib().dg_last_error() == b""
+
+
+def _arities():
+    """Parameter count of every declared entry point, read from the header."""
+    src = open(os.path.join(ROOT, "include", "dgtau.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(dg_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", src):
+        params = m.group(2).strip()
+        out[m.group(1)] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_arities_match_the_header():
+    ar = _arities()
+    for name, args in dg.SIGNATURES.items():
+        assert ar[name] == len(args), (name, ar[name], len(args))
