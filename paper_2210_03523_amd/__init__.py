@@ -170,6 +170,9 @@ class Plan:
     def __init__(self, mesh: dict, orders, _parent: "Plan | None" = None):
         self.mesh = dict(mesh)
         o = np.ascontiguousarray(np.asarray(orders, dtype=np.int32).reshape(-1, 3))
+        E = int(np.prod(mesh["n"])) if _parent is None else _parent.n_elems
+        if o.shape[0] != E:
+            raise DGError(f"{o.shape[0]} order triples given for {E} elements")
         self.orders_natural = o
         h = ctypes.c_void_p()
         if _parent is None:
