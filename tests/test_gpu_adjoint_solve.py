@@ -58,3 +58,32 @@ def test_zero_right_hand_side_and_errors():
         dg.adjoint_solve(plan, u, u, restart=0)
     with pytest.raises(dg.DGError):
         dg.adjoint_solve(plan, u, u, restart=201)
+
+
+def test_adjoint_weighted_estimate_from_the_solved_adjoint():
+    """The chain the adjoint serves: the x-force adjoint of the traditional form solved on
+    the GPU, then eta = sum over coarse nodes of (I psi) tau_trad per element, against the
+    oracle's dense adjoint and its adjoint-weighted estimate."""
+    rng = np.random.default_rng(42)
+    mesh = wl.box_mesh((2, 2, 2), bc=(1, 2, 0, 0, 0, 0), qfar=wl.conserved(*(np.array(x) for x in
+                                                                           (1.0, 0.3, 0.0, 0.0, 1.0))))
+    fo = wl.random_orders(8, 1, 2, rng)
+    co = np.ones_like(fo)
+    u = wl.pulse_state(oracle.node_coords(mesh, fo), fo, sigma=0.3, amp=0.2)
+    u = wl.add_rho_noise(u, fo, rng, 1e-3)
+    _, g = oracle.functional(mesh, fo, u)
+    psi_ref, Jac = adjoint.adjoint_solve(mesh, fo, u, g, form=dg.FORM_TRAD)
+    dudt = oracle.residual(mesh, fo, u)
+    eta_ref = oracle.tau_eta(mesh, fo, co, u, dudt, psi_ref)
+    fine = dg.Plan(mesh, fo)
+    coarse = fine.coarse(co)
+    ud = fine.to_plan(u)
+    psi, _, relres = dg.adjoint_solve(fine, ud, fine.to_plan(g), restart=200, max_iter=4000, rtol=1e-11,
+                                      form=dg.FORM_TRAD)
+    assert relres <= 1e-11
+    _, tt, _, eta = dg.tau_estimate(fine, coarse, ud, None, False, psi)
+    got = coarse.elem_to_natural(eta.cpu().numpy())
+    # error budget: the dense adjoint's finite-difference Jacobian (1e-9 relative) times
+    # its condition number, carried through the sum of |I psi| |tau_trad|
+    scale = np.sum(np.abs(oracle.restrict(fo, co, psi_ref)) * np.abs(coarse.to_natural(tt)))
+    assert np.max(np.abs(got - eta_ref)) <= 1e-9 * np.linalg.cond(Jac) * scale
