@@ -291,11 +291,19 @@ hipError_t launch_face_flux(const Face *faces, int nfaces, const ElemInfo *elems
 // sD (LDS, 3 NNMAX^2): the tile's derivative matrices, staged so that the per-lane rows are
 // read from LDS rather than through vector memory loads.
 // E0: the descriptor of the tile's first element (every element of a tile has its orders).
+// sF: elem_rows<T, BS * NPT>() rows of BS * NPT values.  With three flux sets of rows the
+// fluxes of all three directions are staged at once, behind one barrier; with one set the
+// directions take turns (tiles too large for 64 KB of LDS).
+template <typename T, int N>
+constexpr int elem_rows() {
+    return (3 * NV * N + 3 * NNMAX * NNMAX) * (int)sizeof(T) <= 64 * 1024 ? 3 * NV : NV;
+}
+
 template <typename T, int NPT, bool CURVED = false, int BS = WG, bool VISC = true>
 __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, const T *u,
                                           const T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
-                                          const PhysParams &ph, const EpiArgs &epi, T (&sF)[NV][BS * NPT],
-                                          T *sD) {
+                                          const PhysParams &ph, const EpiArgs &epi, T (*sF)[BS * NPT], T *sD) {
+    constexpr bool ALLD = elem_rows<T, BS * NPT>() == 3 * NV;
     const int tid = threadIdx.x;
     const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
     {
@@ -372,17 +380,23 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
     const int stride[3] = {1, n1, n1 * n2};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
+        if (!ALLD || d == 0) {
 #pragma unroll
-        for (int k = 0; k < NPT; ++k) {
-            T f[NV];
-            total_flux(k, d, f);
-            const int t = tid + k * BS;
-            if (ok[k]) {
+            for (int dd = 0; dd < (ALLD ? 3 : 1); ++dd) {
+                const int df = ALLD ? dd : d;  // direction of the staged flux
 #pragma unroll
-                for (int v = 0; v < NV; ++v) sF[v][t] = f[v];
+                for (int k = 0; k < NPT; ++k) {
+                    T f[NV];
+                    total_flux(k, df, f);
+                    const int t = tid + k * BS;
+                    if (ok[k]) {
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) sF[(ALLD ? df * NV : 0) + v][t] = f[v];
+                    }
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
         const int nd_ = nn[d];
         const T *Dm = sD + d * NNMAX * NNMAX;
 #pragma unroll
@@ -395,10 +409,12 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
             for (int m = 0; m < nd_; ++m) {
                 const T dm = Drow[m];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) V[k][v] += dm * sF[v][tb + m * stride[d]];
+                for (int v = 0; v < NV; ++v) V[k][v] += dm * sF[(ALLD ? d * NV : 0) + v][tb + m * stride[d]];
             }
         }
-        __syncthreads();
+        // the next direction's staging (or, after the last, the next tile of a persistent
+        // loop and the epilogue's reduction) overwrites sF only after this barrier
+        if (!ALLD || d == 2) __syncthreads();
     }
     // lifted surface terms from the face pass
     if (!epi.isolated) {
@@ -532,7 +548,7 @@ __global__ __launch_bounds__(BS) void k_elem(const Tile *__restrict__ tiles, int
                                              const ElemInfo *__restrict__ el, const T *u,
                                              const T *__restrict__ ff, const T *__restrict__ tab, Geom g,
                                              PhysParams ph, EpiArgs epi) {
-    __shared__ T sF[NV][BS * NPT];
+    __shared__ T sF[elem_rows<T, BS * NPT>()][BS * NPT];
     __shared__ T sD[3 * NNMAX * NNMAX];
     const Tile tl = tiles[tile0 + xcd_remap(blockIdx.x, ntiles)];
     elem_body<T, NPT, CURVED, BS, VISC>(tl, el[tl.first], u, ff, tab, g, ph, epi, sF, sD);
@@ -850,7 +866,7 @@ template <typename T, int BS, int NPT>
 __global__ __launch_bounds__(BS) void k_elem_batch(const BatchTile *__restrict__ tiles, int ntiles,
                                                    const ProbDesc<T> *__restrict__ probs, const T *__restrict__ tab,
                                                    EpiArgs epi0) {
-    __shared__ T sF[NV][BS * NPT];
+    __shared__ T sF[elem_rows<T, BS * NPT>()][BS * NPT];
     __shared__ T sD[3 * NNMAX * NNMAX];
     for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
         const BatchTile bt = tiles[i];
