@@ -47,6 +47,15 @@ struct FaceSmem {
 // One face, processed by one wavefront (64 lanes).  Mortar interpolation S2 (x) S1 and
 // projection P2 (x) P1 are applied one tangential direction at a time, and only in a
 // direction where the two sides' orders differ.
+// m = a + n b split into (a, b) for m < 2^20 and n <= 1000 through the float reciprocal
+// of n (the exact quotient of m + 1/2 sits at least 1/(2n) from an integer, far beyond
+// the rounding): the face loops split their lane index this way instead of by integer
+// division, which takes tens of instructions.
+__device__ __forceinline__ void split2(int m, int n, float inv, int &a, int &b) {
+    b = (int)(((float)m + 0.5f) * inv);
+    a = m - b * n;
+}
+
 // MODE 0: outward Riemann flux F*_out (plus side negated).  MODE 1: the BR1 trace of the
 // solution, (Q_L + Q_R)/2 on the mortar projected back onto both sides (no sign, no
 // metric), the face input of the gradient pass.
@@ -67,8 +76,11 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
         const int na = E.n[t1], nb = E.n[t2], ne = E.n[0] * E.n[1] * E.n[2];
         const T *Q = u + NV * E.noff;
         T *out = ff + E.foff + fslot(E.n, d, s);
+        const float ina = 1.0f / na;
         for (int m = lane; m < na * nb; m += 64) {
-            int node = face_node(E.n, d, s, m % na, m / na);
+            int ma, mb;
+            split2(m, na, ina, ma, mb);
+            int node = face_node(E.n, d, s, ma, mb);
             T qin[NV], qg[NV], F[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) qin[v] = Q[v * ne + node];
@@ -94,6 +106,7 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
 
     const int aL = L.n[t1], bL = L.n[t2], aR = R.n[t1], bR = R.n[t2];
     const int K1 = aL > aR ? aL : aR, K2 = bL > bR ? bL : bR;
+    const float iaL = 1.0f / aL, iaR = 1.0f / aR, iK1 = 1.0f / K1;
     const int neL = L.n[0] * L.n[1] * L.n[2], neR = R.n[0] * R.n[1] * R.n[2];
     T *oL = ff + L.foff + fslot(L.n, d, 1);
     T *oR = ff + R.foff + fslot(R.n, d, -1);
@@ -101,8 +114,10 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
     if (aL == aR && bL == bR) {
         // conforming face: one node pair per lane, no staging
         for (int m = lane; m < aL * bL; m += 64) {
-            const int nl = face_node(L.n, d, 1, m % aL, m / aL);
-            const int nr = face_node(R.n, d, -1, m % aL, m / aL);
+            int ma, mb;
+            split2(m, aL, iaL, ma, mb);
+            const int nl = face_node(L.n, d, 1, ma, mb);
+            const int nr = face_node(R.n, d, -1, ma, mb);
             T qL[NV], qR[NV], F[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -129,12 +144,16 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
     }
 
     for (int m = lane; m < aL * bL; m += 64) {
-        int node = face_node(L.n, d, 1, m % aL, m / aL);
+        int ma, mb;
+        split2(m, aL, iaL, ma, mb);
+        int node = face_node(L.n, d, 1, ma, mb);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sm.QL[v][m] = u[NV * L.noff + v * neL + node];
     }
     for (int m = lane; m < aR * bR; m += 64) {
-        int node = face_node(R.n, d, -1, m % aR, m / aR);
+        int ma, mb;
+        split2(m, aR, iaR, ma, mb);
+        int node = face_node(R.n, d, -1, ma, mb);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sm.QR[v][m] = u[NV * R.noff + v * neR + node];
     }
@@ -147,7 +166,8 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
         T(*Tt)[FN] = side == 0 ? sm.TL : sm.TR;
         const T *S1 = tab + T_I + moff(K1 - 1, na - 1);
         for (int m = lane; m < K1 * nb; m += 64) {
-            const int A = m % K1, b = m / K1;
+            int A, b;
+            split2(m, K1, iK1, A, b);
             T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
             for (int a = 0; a < na; ++a) {
                 const T s1 = S1[A * na + a];
@@ -161,7 +181,8 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
     __syncthreads();
     // second tangential direction, then the Riemann flux on the mortar
     for (int m = lane; m < K1 * K2; m += 64) {
-        const int A = m % K1, B = m / K1;
+        int A, B;
+        split2(m, K1, iK1, A, B);
         T q[2][NV], F[NV];
         for (int side = 0; side < 2; ++side) {
             const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
@@ -198,7 +219,8 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
         T(*U)[FN] = side == 0 ? sm.QL : sm.QR;
         const T *P1 = tab + T_P + moff(na - 1, K1 - 1);
         for (int m = lane; m < na * K2; m += 64) {
-            const int a = m % na, B = m / na;
+            int a, B;
+            split2(m, na, 1.0f / na, a, B);
             T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
             for (int A = 0; A < K1; ++A) {
                 const T p1 = P1[a * K1 + A];
@@ -220,7 +242,8 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
         const int ld = x1 ? na : K1;
         const T *P2 = tab + T_P + moff(nb - 1, K2 - 1);
         for (int m = lane; m < na * nb; m += 64) {
-            const int a = m % na, b = m / na;
+            int a, b;
+            split2(m, na, 1.0f / na, a, b);
             T acc[NV];
             if (nb == K2) {
 #pragma unroll
