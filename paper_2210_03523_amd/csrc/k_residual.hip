@@ -37,11 +37,15 @@ __device__ __forceinline__ int face_node(const int32_t *n, int d, int side, int 
 // of faces resident per CU.
 template <typename T, int FN>
 struct FaceSmem {
+    // FP32 faces stage their mortar operators (S1, S2, P1, P2 of each side) in LDS; FP64
+    // ones read them through the cache (their larger LDS would cost occupancy)
+    static constexpr int OPS = sizeof(T) == 4 ? 8 : 1;
     T QL[NV][FN];   // left trace, later the left projection intermediate
     T QR[NV][FN];   // right trace, later the right projection intermediate
     T TL[NV][FN];   // left trace interpolated along the first tangential direction
     T TR[NV][FN];
     T F[NV][FN];    // Riemann flux on the mortar
+    T op[OPS][FN];  // [side]: S1; [2 + side]: S2; [4 + side]: P1; [6 + side]: P2
 };
 
 // One face, processed by one wavefront (64 lanes).  Mortar interpolation S2 (x) S1 and
@@ -157,6 +161,27 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
 #pragma unroll
         for (int v = 0; v < NV; ++v) sm.QR[v][m] = u[NV * R.noff + v * neR + node];
     }
+    const bool stage = FaceSmem<T, FN>::OPS == 8;
+    if (stage) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
+            if (na != K1) {
+                const T *s1 = tab + T_I + moff(K1 - 1, na - 1), *p1 = tab + T_P + moff(na - 1, K1 - 1);
+                for (int t = lane; t < K1 * na; t += 64) {
+                    sm.op[side][t] = s1[t];
+                    sm.op[4 + side][t] = p1[t];
+                }
+            }
+            if (nb != K2) {
+                const T *s2 = tab + T_I + moff(K2 - 1, nb - 1), *p2 = tab + T_P + moff(nb - 1, K2 - 1);
+                for (int t = lane; t < K2 * nb; t += 64) {
+                    sm.op[2 + side][t] = s2[t];
+                    sm.op[6 + side][t] = p2[t];
+                }
+            }
+        }
+    }
     __syncthreads();
     // first tangential direction: T[A + K1 b] = sum_a S1[A][a] Q[a + na b]
     for (int side = 0; side < 2; ++side) {
@@ -164,7 +189,7 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
         if (na == K1) continue;
         T(*Q)[FN] = side == 0 ? sm.QL : sm.QR;
         T(*Tt)[FN] = side == 0 ? sm.TL : sm.TR;
-        const T *S1 = tab + T_I + moff(K1 - 1, na - 1);
+        const T *S1 = stage ? sm.op[side & (FaceSmem<T, FN>::OPS - 1)] : tab + T_I + moff(K1 - 1, na - 1);
         for (int m = lane; m < K1 * nb; m += 64) {
             int A, b;
             split2(m, K1, iK1, A, b);
@@ -191,7 +216,8 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
 #pragma unroll
                 for (int v = 0; v < NV; ++v) q[side][v] = src[v][A + K1 * B];
             } else {
-                const T *S2 = tab + T_I + moff(K2 - 1, nb - 1) + B * nb;
+                const T *S2 = (stage ? sm.op[(2 + side) & (FaceSmem<T, FN>::OPS - 1)]
+                                     : tab + T_I + moff(K2 - 1, nb - 1)) + B * nb;
                 T acc[NV] = {T(0), T(0), T(0), T(0), T(0)};
                 for (int b = 0; b < nb; ++b) {
                     const T s2 = S2[b];
@@ -217,7 +243,7 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
         const int na = side == 0 ? aL : aR;
         if (na == K1) continue;
         T(*U)[FN] = side == 0 ? sm.QL : sm.QR;
-        const T *P1 = tab + T_P + moff(na - 1, K1 - 1);
+        const T *P1 = stage ? sm.op[(4 + side) & (FaceSmem<T, FN>::OPS - 1)] : tab + T_P + moff(na - 1, K1 - 1);
         for (int m = lane; m < na * K2; m += 64) {
             int a, B;
             split2(m, na, 1.0f / na, a, B);
@@ -240,7 +266,7 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
         const bool x1 = na != K1;  // the first pass ran: intermediate in QL/QR as [a + na B]
         T(*U)[FN] = x1 ? (side == 0 ? sm.QL : sm.QR) : sm.F;
         const int ld = x1 ? na : K1;
-        const T *P2 = tab + T_P + moff(nb - 1, K2 - 1);
+        const T *P2 = stage ? sm.op[(6 + side) & (FaceSmem<T, FN>::OPS - 1)] : tab + T_P + moff(nb - 1, K2 - 1);
         for (int m = lane; m < na * nb; m += 64) {
             int a, b;
             split2(m, na, 1.0f / na, a, b);
