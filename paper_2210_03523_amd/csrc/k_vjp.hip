@@ -7,15 +7,16 @@
 //   volume     : out_m += sum_d |Ja^d| A_d(Q_m)^T (sum_n D^d_{n m} vt_n)      (D transposed)
 //   inner trace: out_m -= s |Ja^d| A_d(Q_m)^T vt_m / w_end  at face nodes of face (d, s)
 //   Riemann    : the face pass transposes P (projection), the Riemann-flux Jacobian
-//                (formed with forward-mode duals) and S (mortar interpolation), and
+//                (its reverse-mode derivative) and S (mortar interpolation), and
 //                stores each side's share in per-element face slots, which the
 //                element pass gathers -- no atomics, deterministic.
-// A_d = df_d/dQ is formed per node with 5-component duals.
+// The transposed Jacobians A_d^T = (df_d/dQ)^T act through the fluxes' reverse-mode
+// derivatives (euler_adj.h), never formed as matrices.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
-#include "dual.h"
 #include "euler.h"
+#include "euler_adj.h"
 
 namespace dgt {
 
@@ -67,25 +68,17 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
                 q0[k] = u[NV * E.noff + k * ne + node];
                 lam[k] = c * v[NV * E.noff + k * ne + node];
             }
-            // lam^T dF/dq of the boundary flux (the ghost depends on q for walls), one
-            // direction per forward-mode pass
-#pragma unroll 1
-            for (int j = 0; j < NV; ++j) {
-                const int i0 = j;
-                Dual<1> qd[NV], qg[NV], F[NV];
+            // lam^T dF/dq of the boundary flux; a wall's ghost is the mirrored state, so
+            // its cotangent returns through the mirror; the far-field state is fixed
+            double qg[NV], gI[NV], gG[NV];
 #pragma unroll
-                for (int k = 0; k < NV; ++k) {
-                    qd[k] = Dual<1>(q0[k]);
-                    qd[k].d[0] = k == i0 ? 1.0 : 0.0;
-                }
+            for (int k = 0; k < NV; ++k) qg[k] = f.bc == 1 ? q0[k] : ph.qfar[k];
+            if (f.bc == 1) qg[1 + d] = -q0[1 + d];
+            numflux_axis_adj_d<d>(q0, qg, (double)s, ph.gamma, KIND, lam, gI, gG);
 #pragma unroll
-                for (int k = 0; k < NV; ++k) qg[k] = f.bc == 1 ? qd[k] : Dual<1>(ph.qfar[k]);
-                if (f.bc == 1) qg[1 + d] = -qd[1 + d];
-                numflux_axis(qd, qg, d, Dual<1>((double)s), Dual<1>(ph.gamma), KIND, F);
-                double a0 = 0.0;
-#pragma unroll
-                for (int w = 0; w < NV; ++w) a0 += lam[w] * F[w].d[0];
-                out[i0 * na * nb + m] = Ja * a0;
+            for (int k = 0; k < NV; ++k) {
+                if (f.bc == 1) gI[k] += k == 1 + d ? -gG[k] : gG[k];
+                out[k * na * nb + m] = Ja * gI[k];
             }
         }
         return;
@@ -165,26 +158,13 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
                 gK[k] = (side == 0 ? 0.0 : gK[k]) + sg * ga[k];
             }
         }
-        // gK^T dF/dq for the 10 inputs (q_L then q_R), one direction per forward-mode
-        // pass: single-direction duals keep the Roe flux in registers
-#pragma unroll 1
-        for (int j = 0; j < 2 * NV; ++j) {
-            const int i0 = j;
-            Dual<1> dl[NV], dr[NV], F[NV];
+        // gK^T dF/dq for both traces, by the flux's reverse-mode derivative
+        double gL[NV], gR[NV];
+        numflux_axis_adj_d<d>(qL, qR, 1.0, ph.gamma, KIND, gK, gL, gR);
 #pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                dl[k] = Dual<1>(qL[k]);
-                dr[k] = Dual<1>(qR[k]);
-                dl[k].d[0] = k == i0 ? 1.0 : 0.0;
-                dr[k].d[0] = NV + k == i0 ? 1.0 : 0.0;
-            }
-            numflux_axis(dl, dr, d, Dual<1>(1.0), Dual<1>(ph.gamma), KIND, F);
-            double a0 = 0.0;
-#pragma unroll
-            for (int w = 0; w < NV; ++w) a0 += gK[w] * F[w].d[0];
-            // the direction index is a loop variable: write to LDS, not a register array
-            if (i0 < NV) sAL[i0 * fnv + m] = Ja * a0;
-            else sAR[(i0 - NV) * fnv + m] = Ja * a0;
+        for (int k = 0; k < NV; ++k) {
+            sAL[k * fnv + m] = Ja * gL[k];
+            sAR[k * fnv + m] = Ja * gR[k];
         }
     }
     __syncthreads();
@@ -222,8 +202,8 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
     }
 }
 
-// Two waves per SIMD: the dual Roe flux needs about 250 registers, so the budget of two
-// waves holds it without spills (the default would allow one wave).
+// Two waves per SIMD: the Roe flux with its reverse-mode derivative needs about 200
+// registers, which the budget of two waves holds without spills.
 template <int KIND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_face_vjp(
     const Face *__restrict__ faces, const ElemInfo *__restrict__ el, const double *__restrict__ u,
@@ -289,7 +269,7 @@ __global__ __launch_bounds__(WG) void k_elem_vjp(const Tile *__restrict__ tiles,
     for (int k = 0; k < NPT; ++k) {
         if (!ok[k]) continue;
         const int t = tid + k * WG;
-        double acc[NV] = {0, 0, 0, 0, 0};
+        double acc[NV] = {0, 0, 0, 0, 0}, yd[3][NV];
         const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -308,22 +288,9 @@ __global__ __launch_bounds__(WG) void k_elem_vjp(const Tile *__restrict__ tiles,
 #pragma unroll
                 for (int w = 0; w < NV; ++w) y[w] -= s * vt[k][w] * iw;
             }
-            // A_d(Q)^T (Ja y)
-            Dual<5> qd[NV], fd[NV];
-#pragma unroll
-            for (int w = 0; w < NV; ++w) {
-                qd[w] = Dual<5>(q[k][w]);
-                qd[w].d[w] = 1.0;
-            }
-            flux_axis(qd, d, Dual<5>(gm1), fd);
             const double Ja = g.Ja[d];
 #pragma unroll
-            for (int kk = 0; kk < NV; ++kk) {
-                double s = 0.0;
-#pragma unroll
-                for (int w = 0; w < NV; ++w) s += fd[w].d[kk] * y[w];
-                acc[kk] += Ja * s;
-            }
+            for (int w = 0; w < NV; ++w) yd[d][w] = Ja * y[w];
             // Riemann-flux share gathered from the face pass
             if (!isolated && (id == 0 || id == nd_ - 1)) {
                 const int side = id == 0 ? -1 : 1;
@@ -335,6 +302,8 @@ __global__ __launch_bounds__(WG) void k_elem_vjp(const Tile *__restrict__ tiles,
                 for (int kk = 0; kk < NV; ++kk) acc[kk] += fs[kk * na * nb + fm];
             }
         }
+        // sum_d A_d(Q)^T (Ja_d y_d), one reverse-mode pass over the three axis fluxes
+        flux3_adj(q[k], gm1, yd, acc);
 #pragma unroll
         for (int kk = 0; kk < NV; ++kk) out[base + kk * npe + nd[k]] = acc[kk];
     }
