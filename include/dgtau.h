@@ -293,7 +293,8 @@ dg_status dg_bdf_rate(dg_plan plan, const double *const *states, int32_t nstates
 /* Vector-Jacobian product of the residual: out = (d r / d u)^T v, r the form and
  * operator of dg_residual (FP64 only).  Written by hand: transposed derivative
  * matrices, transposed lifting, transposed mortar interpolation and projection, and
- * the per-node Jacobians of the physical and Riemann fluxes (forward-mode duals).
+ * the transposed Jacobians of the physical and Riemann fluxes applied per node by
+ * their reverse-mode derivatives (never formed as matrices).
  * Deterministic: the face pass stores per-element shares that the element pass
  * gathers.  u, v, out: device double, plan layout; out must not overlap u or v. */
 dg_status dg_residual_vjp(dg_plan plan, const double *u, const double *v, double *out, int32_t form,
