@@ -303,16 +303,18 @@ dg_status dg_residual_vjp(dg_plan plan, const double *u, const double *v, double
 /* Adjoint solve (the adjoint problem behind the adjoint-weighted estimate: psi of
  * dg_tau_estimate): (d r / d u)^T psi = g, r the residual of the given form and
  * operator of dg_residual at the state u (box Euler plans), g e.g. dJ/du of
- * dg_functional.  Restarted GMRES (modified Gram-Schmidt, Givens rotations) whose
- * matrix-vector product is dg_residual_vjp; inner products are deterministic device
- * reductions.  The problem must be non-singular: on fully periodic meshes the discrete
+ * dg_functional.  Restarted GMRES (Givens rotations) whose matrix-vector product is
+ * dg_residual_vjp; each Arnoldi step orthogonalises by classical Gram-Schmidt (one
+ * pass for all inner products, one for the update), repeated once when the first round
+ * removes more than half of the vector's squared norm.  Inner products are
+ * deterministic device reductions (fixed partition, fixed summation order).  The problem must be non-singular: on fully periodic meshes the discrete
  * conservation makes (d r / d u)^T singular, so use wall or far-field boundaries.
  *   psi: device double, plan layout; initial guess in, solution out.
  *   work: device double of dg_adjoint_workspace(plan, restart) values (caller-owned;
  *         nothing is allocated here).
  *   iters, relres (host, nullable): products done and the final ||g - A^T psi|| / ||g||.
  * Stops at relres <= rtol or after max_iter products.  SYNCHRONOUS: the host drives the
- * iteration and waits on stream for every inner product.
+ * iteration and waits on stream once or twice per Arnoldi step.
  * Errors: DG_EINVAL (null arguments, restart outside 1..DG_ADJOINT_MAX_RESTART,
  * negative max_iter or rtol, unknown form, psi overlapping u or g), DG_EUNSUPPORTED
  * (Navier-Stokes or curved plans), DG_EHIP. */

@@ -942,14 +942,19 @@ dg_status dg_adjoint_workspace(dg_plan p, int32_t restart, int64_t *doubles) {
     if (!p || !doubles) return fail(DG_EINVAL, "null argument");
     if (restart < 1 || restart > DG_ADJOINT_MAX_RESTART) return fail(DG_EINVAL, "restart must be in 1..200");
     const int64_t ld = ((int64_t)NV * p->n_nodes + 1) & ~(int64_t)1;  // vectors 16-byte aligned
-    *doubles = (int64_t)(restart + 2) * ld + dot_partials() + 8;
+    *doubles = (int64_t)(restart + 2) * ld + mdot_partials() + 2 * (restart + 4);
     return DG_OK;
 }
+static_assert(DG_KRYLOV_MAX == DG_ADJOINT_MAX_RESTART + 1, "Krylov kernels sized for the largest restart");
 
 // Restarted GMRES on A^T psi = g, A = d r / d Q (the residual of the given form), with
-// modified Gram-Schmidt and Givens rotations; the host holds the small Hessenberg system,
-// the device the Krylov vectors.  Workspace: V_0..V_m, one spare vector, the dot
-// partials and the dot result.
+// Givens rotations; the host holds the small Hessenberg system, the device the Krylov
+// vectors.  Orthogonalisation: classical Gram-Schmidt (all inner products of a step in
+// one pass over the vectors, then one update pass), repeated once when it removed more
+// than half of w's squared norm (the Daniel-Gragg-Kaufman-Stewart criterion, ||w'|| <
+// ||w|| / sqrt 2), which keeps the basis orthogonal to working precision as modified
+// Gram-Schmidt does, with one or two host waits per step instead of one per vector.
+// Workspace: V_0..V_m, one spare vector, the partials, the step's coefficients.
 dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *psi, const dg_adjoint_params *prm,
                            double *work, int32_t *iters_out, double *relres_out, hipStream_t stream) {
     if (!p || !u || !g || !psi || !prm || !work) return fail(DG_EINVAL, "null argument");
@@ -964,12 +969,15 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
     const int64_t ld = (n + 1) & ~(int64_t)1;  // vector stride: every V_j 16-byte aligned
     double *V = work;                        // V_j = V + j ld, j = 0..m
     double *part = work + (int64_t)(m + 2) * ld;
-    double *dres = part + dot_partials();
-    auto dot = [&](const double *a, const double *b, double *out) -> dg_status {
-        HIP_TRY(launch_dot(a, b, n, part, dres, stream));
-        HIP_TRY(hipMemcpyAsync(out, dres, sizeof(double), hipMemcpyDeviceToHost, stream));
+    double *hb = part + mdot_partials();  // 2 (m + 4) doubles: a step's coefficients and norms
+    auto fetch = [&](double *dst, int count) -> dg_status {
+        HIP_TRY(hipMemcpyAsync(dst, hb, sizeof(double) * count, hipMemcpyDeviceToHost, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         return DG_OK;
+    };
+    auto dot = [&](const double *a, const double *b, double *out) -> dg_status {
+        HIP_TRY(launch_dot(a, b, n, part, hb, stream));
+        return fetch(out, 1);
     };
     auto matvec = [&](const double *v, double *out) {
         return dg_residual_vjp(p, u, v, out, prm->form, prm->isolated, stream);
@@ -1006,15 +1014,23 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
             double *vj = V + (int64_t)j * ld, *w = V + (int64_t)(j + 1) * ld;
             if ((st = matvec(vj, w))) return st;
             ++iters;
-            for (int i = 0; i <= j; ++i) {
-                double h = 0.0;
-                if ((st = dot(w, V + (int64_t)i * ld, &h))) return st;
-                H[(size_t)i * m + j] = h;
-                HIP_TRY(launch_axpby(-h, V + (int64_t)i * ld, 1.0, w, n, stream));
+            // classical Gram-Schmidt against V_0..V_j: coefficients and ||w||^2 in one
+            // pass, the update with the new ||w||^2 in another, and a second round when
+            // the first removed more than half of the squared norm
+            std::vector<double> hv(j + 3), h2v(j + 2);
+            HIP_TRY(launch_mdot(V, ld, j + 1, w, true, n, part, hb, stream));
+            HIP_TRY(launch_maxpy(V, ld, j + 1, hb, w, n, part, hb + j + 2, stream));
+            if ((st = fetch(hv.data(), j + 3))) return st;
+            double nw = hv[j + 2];
+            if (nw < 0.5 * hv[j + 1]) {
+                HIP_TRY(launch_mdot(V, ld, j + 1, w, false, n, part, hb, stream));
+                HIP_TRY(launch_maxpy(V, ld, j + 1, hb, w, n, part, hb + j + 1, stream));
+                if ((st = fetch(h2v.data(), j + 2))) return st;
+                for (int i = 0; i <= j; ++i) hv[i] += h2v[i];
+                nw = h2v[j + 1];
             }
-            double h2 = 0.0;
-            if ((st = dot(w, w, &h2))) return st;
-            const double h1 = std::sqrt(h2);
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hv[i];
+            const double h1 = std::sqrt(nw);
             H[(size_t)(j + 1) * m + j] = h1;
             if (h1 > 0.0) HIP_TRY(launch_axpby(1.0 / h1, w, 0.0, w, n, stream));
             // previous rotations on column j, then the one that zeroes H[j+1][j]

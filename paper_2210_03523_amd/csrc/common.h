@@ -168,6 +168,15 @@ hipError_t launch_extrapolate(const ElemInfo *el, int E, const int64_t *combo_of
 hipError_t launch_dot(const double *a, const double *b, int64_t n, double *part, double *out, hipStream_t s);
 hipError_t launch_axpby(double alpha, const double *x, double beta, double *y, int64_t n, hipStream_t s);
 int dot_partials();
+// Gram-Schmidt passes over Krylov vectors x_k = X + k ld, k < c: out[k] = x_k . w (and
+// out[c] = w . w when self); w <- w - sum h_k x_k (h on the device, c <= DG_KRYLOV_MAX)
+// and *nrm2 = the new w . w when nrm2 is given.  part: mdot_partials() doubles.
+constexpr int DG_KRYLOV_MAX = 201;  // restart + 1 vectors for the largest restart, 200
+hipError_t launch_mdot(const double *X, int64_t ld, int c, const double *w, bool self, int64_t n, double *part,
+                       double *out, hipStream_t s);
+hipError_t launch_maxpy(const double *X, int64_t ld, int c, const double *h, double *w, int64_t n, double *part,
+                        double *nrm2, hipStream_t s);
+int mdot_partials();
 // Count of non-physical nodes (rho <= 0, p <= 0 or not finite) into out[0]; part holds
 // dot_partials() doubles of scratch.
 template <typename T>

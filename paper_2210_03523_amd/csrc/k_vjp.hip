@@ -219,8 +219,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 }
 
 // ---------------------------------------------------------------------------- elements
+// One node per lane: five waves per SIMD (86 registers, no spills), more element tiles
+// in flight to cover the load-compute-store phases; the multi-node instances keep the
+// default budget, which they need without spills.
 template <int NPT>
-__global__ __launch_bounds__(WG) void k_elem_vjp(const Tile *__restrict__ tiles, int tile0, int ntiles,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(NPT == 1 ? 5 : 1))) void k_elem_vjp(const Tile *__restrict__ tiles, int tile0, int ntiles,
                                                  const ElemInfo *__restrict__ el, const double *__restrict__ u,
                                                  const double *__restrict__ v, const double *__restrict__ fa,
                                                  double *__restrict__ out, const double *__restrict__ tab, Geom g,
