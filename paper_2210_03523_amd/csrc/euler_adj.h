@@ -2,9 +2,8 @@
 // hand: for a cotangent y of the flux they return y^T (df/dq), the transposed
 // Jacobian applied to y, at the cost of about one more flux evaluation (instead of one
 // forward-mode pass per input component).  Each backward statement mirrors one
-// forward statement of euler.h, in reverse order; the non-smooth points take the
-// conventions of the forward-mode duals: d|x|/dx = sign(x) with 0 at x = 0, and
-// max(a, b) follows a when a >= b.
+// forward statement of euler.h, in reverse order.  At the non-smooth points:
+// d|x|/dx = sign(x) with 0 at x = 0, and max(a, b) follows a when a >= b.
 #pragma once
 
 #include <hip/hip_runtime.h>
