@@ -89,6 +89,31 @@ __device__ __forceinline__ void face_vjp_d(const Face f, const ElemInfo *__restr
     const int K1 = aL > aR ? aL : aR, K2 = bL > bR ? bL : bR;
     const int neL = L.n[0] * L.n[1] * L.n[2], neR = R.n[0] * R.n[1] * R.n[2];
     const double iwL = 1.0 / tab[T_W + xoff(L.n[d] - 1)], iwR = 1.0 / tab[T_W + xoff(R.n[d] - 1)];
+    if (aL == aR && bL == bR) {
+        // conforming face: the mortar is both traces, so every lane works on its own node
+        // from global memory to global memory (no staging, no barrier)
+        double *outL = fa + L.foff + fslot(L.n, d, 1), *outR = fa + R.foff + fslot(R.n, d, -1);
+        for (int m = lane; m < aL * bL; m += 64) {
+            const int a = m % aL, b = m / aL;
+            const int nL = vjp_face_node(L.n, d, 1, a, b), nR = vjp_face_node(R.n, d, -1, a, b);
+            const double cL = form_weight(L, nL, tab, form, invJ) * iwL;
+            const double cR = form_weight(R, nR, tab, form, invJ) * iwR;
+            double qL[NV], qR[NV], gK[NV], gL[NV], gR[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                qL[k] = u[NV * L.noff + k * neL + nL];
+                qR[k] = u[NV * R.noff + k * neR + nR];
+                gK[k] = cL * v[NV * L.noff + k * neL + nL] - cR * v[NV * R.noff + k * neR + nR];
+            }
+            numflux_axis_adj_d<d>(qL, qR, 1.0, ph.gamma, KIND, gK, gL, gR);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                outL[k * aL * bL + m] = Ja * gL[k];
+                outR[k * aL * bL + m] = Ja * gR[k];
+            }
+        }
+        return;
+    }
     for (int m = lane; m < aL * bL; m += 64) {
         const int node = vjp_face_node(L.n, d, 1, m % aL, m / aL);
         const double c = form_weight(L, node, tab, form, invJ) * iwL;
