@@ -87,3 +87,27 @@ def test_adjoint_weighted_estimate_from_the_solved_adjoint():
     # its condition number, carried through the sum of |I psi| |tau_trad|
     scale = np.sum(np.abs(oracle.restrict(fo, co, psi_ref)) * np.abs(coarse.to_natural(tt)))
     assert np.max(np.abs(got - eta_ref)) <= 1e-9 * np.linalg.cond(Jac) * scale
+
+
+@pytest.mark.parametrize("restart", [7, 8, 9, 17])
+def test_restart_lengths_and_determinism(restart):
+    """Krylov bases around the eight-vector width of one inner-product pass: two solves
+    agree bitwise (fixed partition and summation order of every reduction), and the
+    reported relative residual is that of the returned psi, recomputed with a separate
+    VJP."""
+    rng = np.random.default_rng(50 + restart)
+    mesh = wl.box_mesh((2, 2, 2), bc=(1, 2, 0, 0, 0, 0), qfar=wl.conserved(*(np.array(x) for x in
+                                                                           (1.0, 0.3, 0.0, 0.0, 1.0))))
+    orders = wl.random_orders(8, 1, 3, rng)
+    u = wl.pulse_state(oracle.node_coords(mesh, orders), orders, sigma=0.3, amp=0.2)
+    u = wl.add_rho_noise(u, orders, rng, 1e-3)
+    _, g = oracle.functional(mesh, orders, u)
+    plan = dg.Plan(mesh, orders)
+    ud, gd = plan.to_plan(u), plan.to_plan(g)
+    psi1, it1, rr1 = dg.adjoint_solve(plan, ud, gd, restart=restart, max_iter=400, rtol=1e-10)
+    psi2, it2, rr2 = dg.adjoint_solve(plan, ud, gd, restart=restart, max_iter=400, rtol=1e-10)
+    assert torch.equal(psi1, psi2) and it1 == it2 and rr1 == rr2
+    assert it1 > restart  # at least one restart
+    r = dg.residual_vjp(plan, ud, psi1) - gd
+    true_rel = float(torch.linalg.vector_norm(r)) / float(torch.linalg.vector_norm(gd))
+    assert abs(true_rel - rr1) <= 1e-8 * rr1 + 1e-14
