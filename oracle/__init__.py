@@ -77,11 +77,16 @@ def _load():
             "orc_num_combos": [_I],
             "orc_sweep": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_int, _I, ctypes.c_int, _D, _D],
             "orc_rk3": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_double, ctypes.c_int],
-            "orc_tau_eta": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, ctypes.c_int, _D, _D],
+            "orc_tau_eta": [ctypes.POINTER(_Mesh), _I, _I, _D, _D, ctypes.c_int, ctypes.c_int, _D, ctypes.c_int,
+                            _D],
             "orc_functional": [ctypes.POINTER(_Mesh), _I, _D, _D, _D],
             "orc_gradient": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_int, _D],
             "orc_residual_ns": [ctypes.POINTER(_Mesh), _I, _D, ctypes.c_double, ctypes.c_double, _D,
                                 ctypes.c_int, ctypes.c_int],
+            "orc_residual_cstep": [ctypes.POINTER(_Mesh), _I, _D, _D, ctypes.c_double, _D, _D, ctypes.c_int,
+                                   ctypes.c_int],
+            "orc_residual_jvp": [ctypes.POINTER(_Mesh), _I, _D, _D, _D, ctypes.c_int, ctypes.c_int],
+            "orc_residual_vjp": [ctypes.POINTER(_Mesh), _I, _D, _D, _D, ctypes.c_int, ctypes.c_int],
         }.items():
             fn = getattr(lib, name)
             fn.argtypes = args
@@ -96,6 +101,10 @@ def _load():
         lib.orc_roe_waves.restype = None
         lib.orc_viscous_flux.argtypes = [_D, _D, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
         lib.orc_viscous_flux.restype = None
+        lib.orc_flux_jacobian.argtypes = [_D, _D, ctypes.c_double, _D]
+        lib.orc_flux_jacobian.restype = None
+        lib.orc_numflux_jacobian.argtypes = [_D, _D, _D, ctypes.c_double, ctypes.c_int, _D, _D]
+        lib.orc_numflux_jacobian.restype = None
         _lib = lib
     return _lib
 
@@ -189,6 +198,22 @@ def roe_waves(qL, qR, n, gamma=1.4):
     return lam, wave
 
 
+def flux_jacobian(q, n, gamma=1.4):
+    """A[i, j] = d (f.n)_i / d q_j (closed form)."""
+    q, n = _f64(q), _f64(n)
+    A = np.zeros((5, 5))
+    _load().orc_flux_jacobian(_d(q), _d(n), gamma, _d(A))
+    return A
+
+
+def numflux_jacobian(qL, qR, n, gamma=1.4, kind=0):
+    """(AL, AR): Jacobians of the numerical flux in qL and qR (complex step)."""
+    qL, qR, n = _f64(qL), _f64(qR), _f64(n)
+    AL, AR = np.zeros((5, 5)), np.zeros((5, 5))
+    _load().orc_numflux_jacobian(_d(qL), _d(qR), _d(n), gamma, int(kind), _d(AL), _d(AR))
+    return AL, AR
+
+
 # --------------------------------------------------------------------------- mesh-level
 def num_nodes(orders) -> int:
     o = np.asarray(orders).reshape(-1, 3)
@@ -221,6 +246,37 @@ def residual(mesh: dict, orders, u, form: int = 0, isolated: bool = False):
     _check(_load().orc_residual(ctypes.byref(m), _i(o), _d(u), _d(r), int(form), int(bool(isolated))),
            "residual")
     return r
+
+
+def residual_cstep(mesh: dict, orders, u, d, h: float, form: int = 0, isolated: bool = False):
+    """Real and imaginary parts of the residual evaluated in complex arithmetic at u + i h d
+    (box Euler meshes)."""
+    o, u, d = _i32(orders), _f64(u), _f64(d)
+    re, im = np.zeros_like(u), np.zeros_like(u)
+    m = _mesh(mesh)
+    _check(_load().orc_residual_cstep(ctypes.byref(m), _i(o), _d(u), _d(d), float(h), _d(re), _d(im), int(form),
+                                      int(bool(isolated))), "residual_cstep")
+    return re, im
+
+
+def residual_jvp(mesh: dict, orders, u, d, form: int = 0, isolated: bool = False):
+    """(d r / d u) d by complex step (box Euler meshes)."""
+    o, u, d = _i32(orders), _f64(u), _f64(d)
+    out = np.zeros_like(u)
+    m = _mesh(mesh)
+    _check(_load().orc_residual_jvp(ctypes.byref(m), _i(o), _d(u), _d(d), _d(out), int(form), int(bool(isolated))),
+           "residual_jvp")
+    return out
+
+
+def residual_vjp(mesh: dict, orders, u, v, form: int = 0, isolated: bool = False):
+    """(d r / d u)^T v, the residual's steps transposed by hand (box Euler meshes)."""
+    o, u, v = _i32(orders), _f64(u), _f64(v)
+    out = np.zeros_like(u)
+    m = _mesh(mesh)
+    _check(_load().orc_residual_vjp(ctypes.byref(m), _i(o), _d(u), _d(v), _d(out), int(form), int(bool(isolated))),
+           "residual_vjp")
+    return out
 
 
 def restrict(fine_orders, coarse_orders, u):
@@ -322,16 +378,18 @@ def rk3(mesh: dict, orders, u, dt: float, nsteps: int):
 
 
 def tau_eta(mesh: dict, fine_orders, coarse_orders, u, dudt, psi, isolated: bool = False,
-            restriction: int = SAMPLE):
-    """eta[e] = sum over the coarse nodes and variables of (I psi) * tau_trad, I the
-    restriction of the estimate."""
+            restriction: int = SAMPLE, psi_form: int = 1):
+    """eta[e] = sum over the coarse nodes and variables of (I psi_t) * tau_trad, I the
+    restriction of the estimate and psi_t the traditional-form adjoint: psi itself
+    (psi_form 1) or, for the adjoint of the new form (psi_form 0), psi divided by the fine
+    mass matrix."""
     fo, co = _i32(fine_orders), _i32(coarse_orders)
     u, dudt, psi = _f64(u), _f64(dudt), _f64(psi)
     E = fo.size // 3
     eta = np.zeros(E)
     m = _mesh(mesh)
     _check(_load().orc_tau_eta(ctypes.byref(m), _i(fo), _i(co), _d(u), _d(dudt), int(bool(isolated)),
-                               int(restriction), _d(psi), _d(eta)), "tau_eta")
+                               int(restriction), _d(psi), int(psi_form), _d(eta)), "tau_eta")
     return eta
 
 

@@ -4,9 +4,10 @@ TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline l
 the benchmark are the only users.  The GPU library never loads it and shares no code
 with it.
 
-The Jacobian d r / d u of the oracle residual is formed column by column with central
-differences, and the adjoint problem (d r / d u)^T psi = g is solved with numpy's dense
-solver (a library primitive).  This is the adjoint problem behind the adjoint-weighted
+The Jacobian d r / d u of the oracle residual is formed column by column, either by the
+oracle's complex-step directional derivative (exact to rounding; box Euler meshes) or by
+central differences, and the adjoint problem (d r / d u)^T psi = g is solved with numpy's
+dense solver (a library primitive).  This is the adjoint problem behind the adjoint-weighted
 truncation error (the functional error estimate as the truncation error weighted by the
 adjoint of the functional).  Layouts are natural (see the package docstring).
 """
@@ -14,7 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import residual
+from . import residual, residual_jvp
 
 
 def fd_jacobian(mesh: dict, orders, u, form: int = 0, isolated: bool = False, rel_eps: float = 1e-6):
@@ -32,7 +33,21 @@ def fd_jacobian(mesh: dict, orders, u, form: int = 0, isolated: bool = False, re
     return J
 
 
+def cs_jacobian(mesh: dict, orders, u, form: int = 0, isolated: bool = False):
+    """J[:, j] = (d r / d u) e_j by complex step."""
+    u = np.asarray(u, dtype=np.float64)
+    n = u.size
+    J = np.empty((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[j] = 1.0
+        J[:, j] = residual_jvp(mesh, orders, u, e, form=form, isolated=isolated)
+        e[j] = 0.0
+    return J
+
+
 def adjoint_solve(mesh: dict, orders, u, g, form: int = 0, isolated: bool = False):
-    """psi with (d r / d u)^T psi = g (dense); also returns the Jacobian."""
-    J = fd_jacobian(mesh, orders, u, form=form, isolated=isolated)
+    """psi with (d r / d u)^T psi = g (dense, complex-step Jacobian); also returns the
+    Jacobian."""
+    J = cs_jacobian(mesh, orders, u, form=form, isolated=isolated)
     return np.linalg.solve(J.T, np.asarray(g, dtype=np.float64)), J

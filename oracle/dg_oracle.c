@@ -28,6 +28,10 @@
  */
 #include "dg_oracle.h"
 
+#include <complex.h>
+/* The name I is used for interpolation matrices below; the imaginary unit of the
+ * complex-step derivatives is written _Complex_I. */
+#undef I
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1374,19 +1378,47 @@ int orc_tau_dual(const orc_mesh *m, const int *fine_orders, const int *coarse_or
 }
 
 int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_orders, const double *u,
-                const double *dudt, int isolated, int restriction, const double *psi, double *eta)
+                const double *dudt, int isolated, int restriction, const double *psi, int psi_form, double *eta)
 {
     int E = m->nx * m->ny * m->nz;
     if (check_mesh(m) || check_orders(E, fine_orders) || check_orders(E, coarse_orders)) return -1;
+    if (psi_form != 0 && psi_form != 1) return -1;
+    ensure_tables();
     long nc = orc_num_nodes(E, coarse_orders);
     double *tn = malloc(sizeof(double) * NV * nc), *tt = malloc(sizeof(double) * NV * nc);
     double *norms = malloc(sizeof(double) * 2 * E), *psic = malloc(sizeof(double) * NV * nc);
     int rc = orc_tau(m, fine_orders, coarse_orders, u, dudt, isolated, restriction, tn, tt, norms, NULL);
+    const double *pt = psi;
+    double *scaled = NULL;
+    if (rc == 0 && psi_form == 0) {
+        /* the adjoint of the new form, (d(M^-1 F)/du)^T psi = g, is M times the adjoint of
+         * the traditional form: back to the nodal field psi / (J w_i w_j w_k) (fine map) */
+        long *off = node_offsets(E, fine_orders);
+        scaled = malloc(sizeof(double) * NV * off[E]);
+        for (int e = 0; e < E; ++e) {
+            const int *o = fine_orders + 3 * e;
+            int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+            double *Ja = malloc(sizeof(double) * 9 * ne), *Jn = malloc(sizeof(double) * ne);
+            elem_metrics(m, o, e, Ja, Jn);
+            for (int k = 0; k < n[2]; ++k)
+                for (int j = 0; j < n[1]; ++j)
+                    for (int i = 0; i < n[0]; ++i) {
+                        int node = i + n[0] * (j + n[1] * k);
+                        double mass = Jn[node] * g_w[o[0]][i] * g_w[o[1]][j] * g_w[o[2]][k];
+                        for (int v = 0; v < NV; ++v)
+                            scaled[NV * off[e] + v * ne + node] = psi[NV * off[e] + v * ne + node] / mass;
+                    }
+            free(Ja);
+            free(Jn);
+        }
+        free(off);
+        pt = scaled;
+    }
     if (rc == 0) {
         if (restriction)
-            orc_project(E, fine_orders, coarse_orders, psi, psic);
+            orc_project(E, fine_orders, coarse_orders, pt, psic);
         else
-            orc_restrict(E, fine_orders, coarse_orders, psi, psic);
+            orc_restrict(E, fine_orders, coarse_orders, pt, psic);
         long *offc = node_offsets(E, coarse_orders);
         for (int e = 0; e < E; ++e) {
             long a = NV * offc[e], b = NV * offc[e + 1];
@@ -1396,7 +1428,7 @@ int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_ord
         }
         free(offc);
     }
-    free(tn); free(tt); free(norms); free(psic);
+    free(tn); free(tt); free(norms); free(psic); free(scaled);
     return rc;
 }
 
@@ -1465,5 +1497,635 @@ int orc_rk3(const orc_mesh *m, const int *orders, double *u, double dt, int nste
         }
     free(r);
     free(G);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Derivatives of the residual (box Euler meshes).                           */
+/*
+ * The adjoint-weighted estimate (the remark of Section 2.2 relating the truncation
+ * error to functional errors) needs the transpose of the residual's Jacobian.  Two
+ * routes are written here, independently of each other:
+ *
+ *   - The directional derivative (d r / d u) d by complex step (Squire and Trapp, 1998):
+ *     the residual evaluated in complex arithmetic at u + i h d, whose imaginary part
+ *     divided by h is the derivative, with no subtraction and hence exact to rounding
+ *     for h = 1e-30.  |x| continues as x sign(Re x) (0 at 0) and max by the real parts
+ *     (the first argument on ties).
+ *   - The vector-Jacobian product (d r / d u)^T v, each step of the residual transposed
+ *     by hand: the form's diagonal scaling, D^T along every direction, the transposed
+ *     lifting, the transposed mortar projection P^T and interpolation S^T, the
+ *     transposed Jacobian of the physical flux (closed form), of the Riemann flux (its
+ *     5 x 10 Jacobian by complex step at each mortar node) and of the boundary ghost
+ *     states (slip wall: the mirror, a reflection; far field: a constant).
+ *
+ * The two agree through <v, (d r/d u) d> = <(d r/d u)^T v, d>; the transposed product
+ * also keeps the discrete conservation of the residual (mass-weighted sums of a
+ * variable over a periodic mesh are independent of the state).
+ */
+
+typedef double _Complex zdbl;
+
+static const double CSTEP_H = 1e-30;
+
+static zdbl z_abs(zdbl x)
+{
+    double r = creal(x);
+    return r > 0.0 ? x : (r < 0.0 ? -x : 0.0);
+}
+
+static zdbl z_max(zdbl a, zdbl b) { return creal(a) >= creal(b) ? a : b; }
+
+static zdbl z_pressure(const zdbl *q, double g)
+{
+    zdbl ke = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+    return (g - 1.0) * (q[4] - ke);
+}
+
+static void z_flux_n(const zdbl *q, const double *n, double g, zdbl *f)
+{
+    zdbl rho = q[0];
+    zdbl u = q[1] / rho, v = q[2] / rho, w = q[3] / rho;
+    zdbl p = z_pressure(q, g);
+    zdbl un = u * n[0] + v * n[1] + w * n[2];
+    f[0] = rho * un;
+    f[1] = q[1] * un + p * n[0];
+    f[2] = q[2] * un + p * n[1];
+    f[3] = q[3] * un + p * n[2];
+    f[4] = (q[4] + p) * un;
+}
+
+/* The numerical flux of orc_numflux in complex arithmetic (same steps, same order). */
+static void z_numflux(const zdbl *qL, const zdbl *qR, const double *n, double g, int kind, zdbl *f)
+{
+    zdbl fL[NV], fR[NV];
+    z_flux_n(qL, n, g, fL);
+    z_flux_n(qR, n, g, fR);
+    if (kind == 0) {
+        zdbl rL = qL[0], rR = qR[0];
+        zdbl uL[3] = {qL[1] / rL, qL[2] / rL, qL[3] / rL};
+        zdbl uR[3] = {qR[1] / rR, qR[2] / rR, qR[3] / rR};
+        zdbl pL = z_pressure(qL, g), pR = z_pressure(qR, g);
+        zdbl HL = (qL[4] + pL) / rL, HR = (qR[4] + pR) / rR;
+        zdbl sL = csqrt(rL), sR = csqrt(rR);
+        zdbl ut[3];
+        for (int d = 0; d < 3; ++d) ut[d] = (sL * uL[d] + sR * uR[d]) / (sL + sR);
+        zdbl Ht = (sL * HL + sR * HR) / (sL + sR);
+        zdbl rt = sL * sR;
+        zdbl q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+        zdbl c2 = (g - 1.0) * (Ht - 0.5 * q2);
+        zdbl c = csqrt(c2);
+        zdbl un = ut[0] * n[0] + ut[1] * n[1] + ut[2] * n[2];
+        zdbl du[3] = {uR[0] - uL[0], uR[1] - uL[1], uR[2] - uL[2]};
+        zdbl dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+        zdbl dut[3] = {du[0] - dun * n[0], du[1] - dun * n[1], du[2] - dun * n[2]};
+        zdbl drho = rR - rL, dp = pR - pL;
+        zdbl a1 = (dp - rt * c * dun) / (2.0 * c2);
+        zdbl a2 = drho - dp / c2;
+        zdbl a4 = (dp + rt * c * dun) / (2.0 * c2);
+        zdbl lam[4] = {un - c, un, un, un + c};
+        zdbl wave[20];
+        wave[0] = a1;
+        for (int d = 0; d < 3; ++d) wave[1 + d] = a1 * (ut[d] - c * n[d]);
+        wave[4] = a1 * (Ht - c * un);
+        wave[5] = a2;
+        for (int d = 0; d < 3; ++d) wave[6 + d] = a2 * ut[d];
+        wave[9] = a2 * 0.5 * q2;
+        wave[10] = 0.0;
+        for (int d = 0; d < 3; ++d) wave[11 + d] = rt * dut[d];
+        wave[14] = rt * (ut[0] * dut[0] + ut[1] * dut[1] + ut[2] * dut[2]);
+        wave[15] = a4;
+        for (int d = 0; d < 3; ++d) wave[16 + d] = a4 * (ut[d] + c * n[d]);
+        wave[19] = a4 * (Ht + c * un);
+        for (int v = 0; v < NV; ++v) {
+            zdbl diss = 0.0;
+            for (int k = 0; k < 4; ++k) diss += z_abs(lam[k]) * wave[k * NV + v];
+            f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * diss;
+        }
+    } else {
+        zdbl rL = qL[0], rR = qR[0];
+        zdbl unL = (qL[1] * n[0] + qL[2] * n[1] + qL[3] * n[2]) / rL;
+        zdbl unR = (qR[1] * n[0] + qR[2] * n[1] + qR[3] * n[2]) / rR;
+        zdbl cL = csqrt(g * z_pressure(qL, g) / rL), cR = csqrt(g * z_pressure(qR, g) / rR);
+        zdbl s = z_max(z_abs(unL) + cL, z_abs(unR) + cR);
+        for (int v = 0; v < NV; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * s * (qR[v] - qL[v]);
+    }
+}
+
+/* Ghost state of a boundary face in complex arithmetic (as ghost_state). */
+static void z_ghost_state(const orc_mesh *m, int bc, const double *nout, const zdbl *qin, zdbl *qg)
+{
+    if (bc == 1) {
+        zdbl mn = qin[1] * nout[0] + qin[2] * nout[1] + qin[3] * nout[2];
+        qg[0] = qin[0];
+        for (int k = 0; k < 3; ++k) qg[1 + k] = qin[1 + k] - 2.0 * mn * nout[k];
+        qg[4] = qin[4];
+    } else {
+        for (int v = 0; v < NV; ++v) qg[v] = m->qfar[v];
+    }
+}
+
+/* Apply the real tensor-product operator A1 (rows x na) (x) A2 (cols x nb) to nv complex
+ * face fields: out[v][r + R1*c] = sum A1[r][a] A2[c][b] in[v][a + na*b]. */
+static void z_face_apply(int nv, int na, int nb, int R1, int R2, const double *A1, const double *A2, const zdbl *in,
+                         zdbl *out)
+{
+    for (int v = 0; v < nv; ++v)
+        for (int c = 0; c < R2; ++c)
+            for (int r = 0; r < R1; ++r) {
+                zdbl acc = 0.0;
+                for (int b = 0; b < nb; ++b)
+                    for (int a = 0; a < na; ++a) acc += A1[r * na + a] * A2[c * nb + b] * in[v * na * nb + a + na * b];
+                out[v * R1 * R2 + r + R1 * c] = acc;
+            }
+}
+
+/* Outward numerical flux of face (d, s) of element e in complex arithmetic (box Euler;
+ * the steps of face_flux). */
+static void z_face_flux(const orc_mesh *m, const int *orders, const long *off, const zdbl *u, int e, int d, int s,
+                        zdbl *fout)
+{
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
+    int na = n[t1], nb = n[t2], ne = n[0] * n[1] * n[2];
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+    const double g = m->gamma;
+    zdbl *own = malloc(sizeof(zdbl) * NV * na * nb);
+    for (int v = 0; v < NV; ++v)
+        for (int b = 0; b < nb; ++b)
+            for (int a = 0; a < na; ++a) own[v * na * nb + a + na * b] = u[NV * off[e] + v * ne + face_node(n, d, s, a, b)];
+    int bc;
+    int nbr = neighbour(m, e, d, s, &bc);
+    if (nbr < 0) {
+        double mv[3] = {0.0, 0.0, 0.0}, nh[3];
+        mv[d] = (double)s * Ja[d];
+        double len = unit_normal(mv, nh);
+        for (int x = 0; x < na * nb; ++x) {
+            zdbl qin[NV], qg[NV], fa[NV];
+            for (int v = 0; v < NV; ++v) qin[v] = own[v * na * nb + x];
+            z_ghost_state(m, bc, nh, qin, qg);
+            z_numflux(qin, qg, nh, g, m->flux, fa);
+            for (int v = 0; v < NV; ++v) fout[v * na * nb + x] = len * fa[v];
+        }
+        free(own);
+        return;
+    }
+    const int *on = orders + 3 * nbr;
+    int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1}, nen = nn[0] * nn[1] * nn[2];
+    int ma = nn[t1], mb = nn[t2];
+    zdbl *oth = malloc(sizeof(zdbl) * NV * ma * mb);
+    for (int v = 0; v < NV; ++v)
+        for (int b = 0; b < mb; ++b)
+            for (int a = 0; a < ma; ++a)
+                oth[v * ma * mb + a + ma * b] = u[NV * off[nbr] + v * nen + face_node(nn, d, -s, a, b)];
+    int K1 = na > ma ? na : ma, K2 = nb > mb ? nb : mb, KK = K1 * K2;
+    double *S1 = malloc(sizeof(double) * K1 * na), *S2 = malloc(sizeof(double) * K2 * nb);
+    double *T1 = malloc(sizeof(double) * K1 * ma), *T2 = malloc(sizeof(double) * K2 * mb);
+    double *P1 = malloc(sizeof(double) * na * K1), *P2 = malloc(sizeof(double) * nb * K2);
+    orc_interp(K1 - 1, na - 1, S1);
+    orc_interp(K2 - 1, nb - 1, S2);
+    orc_interp(K1 - 1, ma - 1, T1);
+    orc_interp(K2 - 1, mb - 1, T2);
+    orc_proj(na - 1, K1 - 1, P1);
+    orc_proj(nb - 1, K2 - 1, P2);
+    zdbl *A = malloc(sizeof(zdbl) * NV * KK), *B = malloc(sizeof(zdbl) * NV * KK), *FK = malloc(sizeof(zdbl) * NV * KK);
+    z_face_apply(NV, na, nb, K1, K2, S1, S2, own, A);
+    z_face_apply(NV, ma, mb, K1, K2, T1, T2, oth, B);
+    zdbl *L = s > 0 ? A : B, *R = s > 0 ? B : A;
+    double mv[3] = {0.0, 0.0, 0.0}, nh[3];
+    mv[d] = Ja[d];
+    double len = unit_normal(mv, nh);
+    for (int x = 0; x < KK; ++x) {
+        zdbl qL[NV], qR[NV], fa[NV];
+        for (int v = 0; v < NV; ++v) {
+            qL[v] = L[v * KK + x];
+            qR[v] = R[v * KK + x];
+        }
+        z_numflux(qL, qR, nh, g, m->flux, fa);
+        for (int v = 0; v < NV; ++v) FK[v * KK + x] = len * fa[v];
+    }
+    z_face_apply(NV, K1, K2, na, nb, P1, P2, FK, fout);
+    for (int x = 0; x < NV * na * nb; ++x) fout[x] *= (double)s;
+    free(own); free(oth); free(S1); free(S2); free(T1); free(T2); free(P1); free(P2);
+    free(A); free(B); free(FK);
+}
+
+/* Residual of box element e in complex arithmetic (the steps of residual_core for the
+ * Euler equations: Ft^d = |Ja^d| f_d, V = sum_d D_d Ft^d, lifting, form scaling). */
+static void z_residual_elem(const orc_mesh *m, const int *orders, const long *off, const zdbl *u, int e, int form,
+                            int isolated, zdbl *r)
+{
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+    const zdbl *Q = u + NV * off[e];
+    zdbl *Ft = malloc(sizeof(zdbl) * 3 * NV * ne), *V = malloc(sizeof(zdbl) * NV * ne);
+    for (int node = 0; node < ne; ++node) {
+        zdbl q[NV], f[NV];
+        for (int v = 0; v < NV; ++v) q[v] = Q[v * ne + node];
+        for (int d = 0; d < 3; ++d) {
+            double ed[3] = {0.0, 0.0, 0.0};
+            ed[d] = 1.0;
+            z_flux_n(q, ed, m->gamma, f);
+            for (int v = 0; v < NV; ++v) Ft[(d * NV + v) * ne + node] = Ja[d] * f[v];
+        }
+    }
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int node = i + n[0] * (j + n[1] * k);
+                for (int v = 0; v < NV; ++v) {
+                    zdbl acc = 0.0;
+                    for (int q = 0; q < n[0]; ++q)
+                        acc += g_D[o[0]][i * n[0] + q] * Ft[(0 * NV + v) * ne + q + n[0] * (j + n[1] * k)];
+                    for (int q = 0; q < n[1]; ++q)
+                        acc += g_D[o[1]][j * n[1] + q] * Ft[(1 * NV + v) * ne + i + n[0] * (q + n[1] * k)];
+                    for (int q = 0; q < n[2]; ++q)
+                        acc += g_D[o[2]][k * n[2] + q] * Ft[(2 * NV + v) * ne + i + n[0] * (j + n[1] * q)];
+                    V[v * ne + node] = acc;
+                }
+            }
+    if (!isolated) {
+        for (int d = 0; d < 3; ++d) {
+            int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            int na = n[t1], nb = n[t2];
+            double wend = g_w[o[d]][0];
+            zdbl *fout = malloc(sizeof(zdbl) * NV * na * nb);
+            for (int s = -1; s <= 1; s += 2) {
+                z_face_flux(m, orders, off, u, e, d, s, fout);
+                for (int b = 0; b < nb; ++b)
+                    for (int a = 0; a < na; ++a) {
+                        int node = face_node(n, d, s, a, b);
+                        for (int v = 0; v < NV; ++v)
+                            V[v * ne + node] += (fout[v * na * nb + a + na * b] -
+                                                 (double)s * Ft[(d * NV + v) * ne + node]) / wend;
+                    }
+            }
+            free(fout);
+        }
+    }
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int node = i + n[0] * (j + n[1] * k);
+                double www = g_w[o[0]][i] * g_w[o[1]][j] * g_w[o[2]][k];
+                for (int v = 0; v < NV; ++v)
+                    r[v * ne + node] = form == 0 ? V[v * ne + node] / J : www * V[v * ne + node];
+            }
+    free(Ft);
+    free(V);
+}
+
+static int check_box_euler(const orc_mesh *m, const int *orders, int form)
+{
+    int E = m->nx * m->ny * m->nz;
+    if (check_mesh(m) || m->map_kind != 0 || check_orders(E, orders) || (form != 0 && form != 1)) return -1;
+    return 0;
+}
+
+int orc_residual_cstep(const orc_mesh *m, const int *orders, const double *u, const double *dir, double h,
+                       double *r_re, double *r_im, int form, int isolated)
+{
+    if (check_box_euler(m, orders, form)) return -1;
+    ensure_tables();
+    int E = m->nx * m->ny * m->nz;
+    long *off = node_offsets(E, orders);
+    long N = NV * off[E];
+    zdbl *zu = malloc(sizeof(zdbl) * N), *zr = malloc(sizeof(zdbl) * N);
+    for (long x = 0; x < N; ++x) zu[x] = u[x] + h * dir[x] * _Complex_I;
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e) z_residual_elem(m, orders, off, zu, e, form, isolated, zr + NV * off[e]);
+    for (long x = 0; x < N; ++x) {
+        if (r_re) r_re[x] = creal(zr[x]);
+        if (r_im) r_im[x] = cimag(zr[x]);
+    }
+    free(zu);
+    free(zr);
+    free(off);
+    return 0;
+}
+
+int orc_residual_jvp(const orc_mesh *m, const int *orders, const double *u, const double *dir, double *out, int form,
+                     int isolated)
+{
+    int rc = orc_residual_cstep(m, orders, u, dir, CSTEP_H, NULL, out, form, isolated);
+    if (rc == 0) {
+        long N = NV * orc_num_nodes(m->nx * m->ny * m->nz, orders);
+        for (long x = 0; x < N; ++x) out[x] /= CSTEP_H;
+    }
+    return rc;
+}
+
+/* Jacobian of the physical flux f.n in the conserved variables (closed form; e.g.
+ * Toro, "Riemann Solvers and Numerical Methods for Fluid Dynamics", ch. 3):
+ * A[i*5 + j] = d (f.n)_i / d q_j, with u the velocity, u_n = u.n, H the total enthalpy
+ * and phi = (gamma - 1) |u|^2 / 2. */
+void orc_flux_jacobian(const double *q, const double *n, double g, double *A)
+{
+    double rho = q[0], u[3] = {q[1] / q[0], q[2] / q[0], q[3] / q[0]};
+    double p = pressure(q, g), H = (q[4] + p) / rho;
+    double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+    double phi = 0.5 * (g - 1.0) * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    A[0] = 0.0;
+    for (int l = 0; l < 3; ++l) A[1 + l] = n[l];
+    A[4] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        double *row = A + 5 * (1 + k);
+        row[0] = -u[k] * un + phi * n[k];
+        for (int l = 0; l < 3; ++l) row[1 + l] = (k == l ? un : 0.0) + u[k] * n[l] - (g - 1.0) * u[l] * n[k];
+        row[4] = (g - 1.0) * n[k];
+    }
+    double *row = A + 20;
+    row[0] = un * (phi - H);
+    for (int l = 0; l < 3; ++l) row[1 + l] = H * n[l] - (g - 1.0) * u[l] * un;
+    row[4] = g * un;
+}
+
+/* Jacobians of the numerical flux with respect to either state, column by column by
+ * complex step: AL[i*5 + j] = d f*_i / d qL_j, AR[i*5 + j] = d f*_i / d qR_j. */
+void orc_numflux_jacobian(const double *qL, const double *qR, const double *n, double g, int kind, double *AL,
+                          double *AR)
+{
+    for (int side = 0; side < 2; ++side)
+        for (int j = 0; j < NV; ++j) {
+            zdbl zl[NV], zr[NV], f[NV];
+            for (int v = 0; v < NV; ++v) {
+                zl[v] = qL[v];
+                zr[v] = qR[v];
+            }
+            if (side == 0) zl[j] += CSTEP_H * _Complex_I;
+            else zr[j] += CSTEP_H * _Complex_I;
+            z_numflux(zl, zr, n, g, kind, f);
+            double *Aout = side == 0 ? AL : AR;
+            for (int i = 0; i < NV; ++i) Aout[i * NV + j] = cimag(f[i]) / CSTEP_H;
+        }
+}
+
+/* Transpose of face_flux on a box Euler mesh.  Fb[v][a + na*b] is the adjoint of the
+ * outward flux F*_out on the own face nodes of face (d, s) of element e; the
+ * contributions to the adjoints of the own face trace are added to bo[v][a + na*b], and
+ * those of the neighbour's face trace to bn[v][a' + ma*b'] (untouched at boundaries). */
+static void face_flux_vjp(const orc_mesh *m, const int *orders, const long *off, const double *u, int e, int d, int s,
+                          const double *Fb, double *bo, double *bn)
+{
+    int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
+    int na = n[t1], nb = n[t2];
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+    const double g = m->gamma;
+    double *own = malloc(sizeof(double) * NV * na * nb);
+    face_trace(n, d, s, NV, u + NV * off[e], own);
+    int bc;
+    int nbr = neighbour(m, e, d, s, &bc);
+    double AL[NV * NV], AR[NV * NV];
+    if (nbr < 0) {
+        /* F*_out = len f*(q, ghost(q), n): adjoint len (AL + AR G)^T Fb, G the ghost Jacobian */
+        double mv[3] = {0.0, 0.0, 0.0}, nh[3];
+        mv[d] = (double)s * Ja[d];
+        double len = unit_normal(mv, nh);
+        double G[NV * NV];
+        for (int i = 0; i < NV * NV; ++i) G[i] = 0.0;
+        if (bc == 1) {
+            G[0] = 1.0;
+            for (int k = 0; k < 3; ++k)
+                for (int l = 0; l < 3; ++l) G[(1 + k) * NV + 1 + l] = (k == l ? 1.0 : 0.0) - 2.0 * nh[k] * nh[l];
+            G[4 * NV + 4] = 1.0;
+        }
+        for (int x = 0; x < na * nb; ++x) {
+            double qin[NV], qg[NV];
+            for (int v = 0; v < NV; ++v) qin[v] = own[v * na * nb + x];
+            ghost_state(m, bc, nh, qin, qg);
+            orc_numflux_jacobian(qin, qg, nh, g, m->flux, AL, AR);
+            for (int w = 0; w < NV; ++w) {
+                double acc = 0.0;
+                for (int v = 0; v < NV; ++v) {
+                    double dfdq = AL[v * NV + w];
+                    for (int k = 0; k < NV; ++k) dfdq += AR[v * NV + k] * G[k * NV + w];
+                    acc += Fb[v * na * nb + x] * dfdq;
+                }
+                bo[w * na * nb + x] += len * acc;
+            }
+        }
+        free(own);
+        return;
+    }
+    const int *on = orders + 3 * nbr;
+    int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1};
+    int ma = nn[t1], mb = nn[t2];
+    double *oth = malloc(sizeof(double) * NV * ma * mb);
+    face_trace(nn, d, -s, NV, u + NV * off[nbr], oth);
+    int K1 = na > ma ? na : ma, K2 = nb > mb ? nb : mb, KK = K1 * K2;
+    double *S1 = malloc(sizeof(double) * K1 * na), *S2 = malloc(sizeof(double) * K2 * nb);
+    double *T1 = malloc(sizeof(double) * K1 * ma), *T2 = malloc(sizeof(double) * K2 * mb);
+    double *P1 = malloc(sizeof(double) * na * K1), *P2 = malloc(sizeof(double) * nb * K2);
+    orc_interp(K1 - 1, na - 1, S1);
+    orc_interp(K2 - 1, nb - 1, S2);
+    orc_interp(K1 - 1, ma - 1, T1);
+    orc_interp(K2 - 1, mb - 1, T2);
+    orc_proj(na - 1, K1 - 1, P1);
+    orc_proj(nb - 1, K2 - 1, P2);
+    /* forward: A = (S1 x S2) own, B = (T1 x T2) oth on the mortar */
+    double *A = malloc(sizeof(double) * NV * KK), *B = malloc(sizeof(double) * NV * KK);
+    to_mortar(NV, na, nb, K1, K2, own, A);
+    to_mortar(NV, ma, mb, K1, K2, oth, B);
+    const double *Lq = s > 0 ? A : B, *Rq = s > 0 ? B : A;
+    /* forward: F*_out = s (P1 x P2) FK; adjoint FKb = s (P1 x P2)^T Fb */
+    double *FKb = malloc(sizeof(double) * NV * KK);
+    for (int v = 0; v < NV; ++v)
+        for (int Bm = 0; Bm < K2; ++Bm)
+            for (int Am = 0; Am < K1; ++Am) {
+                double acc = 0.0;
+                for (int b = 0; b < nb; ++b)
+                    for (int a = 0; a < na; ++a) acc += P1[a * K1 + Am] * P2[b * K2 + Bm] * Fb[v * na * nb + a + na * b];
+                FKb[v * KK + Am + K1 * Bm] = (double)s * acc;
+            }
+    /* forward: FK = len f*(L, R, e_d) per mortar node; adjoints of L and R */
+    double mv[3] = {0.0, 0.0, 0.0}, nh[3];
+    mv[d] = Ja[d];
+    double len = unit_normal(mv, nh);
+    double *Lb = malloc(sizeof(double) * NV * KK), *Rb = malloc(sizeof(double) * NV * KK);
+    for (int x = 0; x < KK; ++x) {
+        double qL[NV], qR[NV];
+        for (int v = 0; v < NV; ++v) {
+            qL[v] = Lq[v * KK + x];
+            qR[v] = Rq[v * KK + x];
+        }
+        orc_numflux_jacobian(qL, qR, nh, g, m->flux, AL, AR);
+        for (int w = 0; w < NV; ++w) {
+            double aL = 0.0, aR = 0.0;
+            for (int v = 0; v < NV; ++v) {
+                aL += AL[v * NV + w] * FKb[v * KK + x];
+                aR += AR[v * NV + w] * FKb[v * KK + x];
+            }
+            Lb[w * KK + x] = len * aL;
+            Rb[w * KK + x] = len * aR;
+        }
+    }
+    const double *Ab = s > 0 ? Lb : Rb, *Bb = s > 0 ? Rb : Lb;
+    /* adjoint of the interpolations onto the mortar: (S1 x S2)^T and (T1 x T2)^T */
+    for (int w = 0; w < NV; ++w) {
+        for (int b = 0; b < nb; ++b)
+            for (int a = 0; a < na; ++a) {
+                double acc = 0.0;
+                for (int Bm = 0; Bm < K2; ++Bm)
+                    for (int Am = 0; Am < K1; ++Am) acc += S1[Am * na + a] * S2[Bm * nb + b] * Ab[w * KK + Am + K1 * Bm];
+                bo[w * na * nb + a + na * b] += acc;
+            }
+        for (int b = 0; b < mb; ++b)
+            for (int a = 0; a < ma; ++a) {
+                double acc = 0.0;
+                for (int Bm = 0; Bm < K2; ++Bm)
+                    for (int Am = 0; Am < K1; ++Am) acc += T1[Am * ma + a] * T2[Bm * mb + b] * Bb[w * KK + Am + K1 * Bm];
+                bn[w * ma * mb + a + ma * b] += acc;
+            }
+    }
+    free(own); free(oth); free(S1); free(S2); free(T1); free(T2); free(P1); free(P2);
+    free(A); free(B); free(FKb); free(Lb); free(Rb);
+}
+
+/* Form scaling of the residual at the nodes of element orders o: 1/J (new form) or
+ * w_i w_j w_k (traditional form). */
+static void form_scale(const orc_mesh *m, const int *o, int form, double *sc)
+{
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1};
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i)
+                sc[i + n[0] * (j + n[1] * k)] = form == 0 ? 1.0 / J : g_w[o[0]][i] * g_w[o[1]][j] * g_w[o[2]][k];
+}
+
+/* (d r / d u)^T v restricted to the unknowns of element e: the transposed steps of e's
+ * own residual, plus, through each shared face, the transposed face flux of the
+ * neighbour's residual (which reads e's face trace). */
+static void vjp_elem(const orc_mesh *m, const int *orders, const long *off, const double *u, const double *v, int e,
+                     int form, int isolated, double *out)
+{
+    const int *o = orders + 3 * e;
+    int n[3] = {o[0] + 1, o[1] + 1, o[2] + 1}, ne = n[0] * n[1] * n[2];
+    double h[3], J, Ja[3];
+    geometry(m, h, &J, Ja);
+    const double *Q = u + NV * off[e];
+    double *sc = malloc(sizeof(double) * ne), *vt = malloc(sizeof(double) * NV * ne);
+    double *Ftb = malloc(sizeof(double) * 3 * NV * ne);
+    form_scale(m, o, form, sc);
+    for (int w = 0; w < NV; ++w)
+        for (int x = 0; x < ne; ++x) vt[w * ne + x] = sc[x] * v[NV * off[e] + w * ne + x];
+    /* V = sum_d D_d Ft^d: adjoint Ftb^d = D_d^T vt along d */
+    for (int k = 0; k < n[2]; ++k)
+        for (int j = 0; j < n[1]; ++j)
+            for (int i = 0; i < n[0]; ++i) {
+                int node = i + n[0] * (j + n[1] * k);
+                for (int w = 0; w < NV; ++w) {
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+                    for (int q = 0; q < n[0]; ++q) a0 += g_D[o[0]][q * n[0] + i] * vt[w * ne + q + n[0] * (j + n[1] * k)];
+                    for (int q = 0; q < n[1]; ++q) a1 += g_D[o[1]][q * n[1] + j] * vt[w * ne + i + n[0] * (q + n[1] * k)];
+                    for (int q = 0; q < n[2]; ++q) a2 += g_D[o[2]][q * n[2] + k] * vt[w * ne + i + n[0] * (j + n[1] * q)];
+                    Ftb[(0 * NV + w) * ne + node] = a0;
+                    Ftb[(1 * NV + w) * ne + node] = a1;
+                    Ftb[(2 * NV + w) * ne + node] = a2;
+                }
+            }
+    /* lifting -s Ft^d / w_end at the face nodes: adjoint -s vt / w_end */
+    if (!isolated)
+        for (int d = 0; d < 3; ++d) {
+            int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            double wend = g_w[o[d]][0];
+            for (int s = -1; s <= 1; s += 2)
+                for (int b = 0; b < n[t2]; ++b)
+                    for (int a = 0; a < n[t1]; ++a) {
+                        int node = face_node(n, d, s, a, b);
+                        for (int w = 0; w < NV; ++w) Ftb[(d * NV + w) * ne + node] -= (double)s * vt[w * ne + node] / wend;
+                    }
+        }
+    /* Ft^d = |Ja^d| f_d(Q): adjoint |Ja^d| A_d(Q)^T Ftb^d */
+    for (int x = 0; x < ne; ++x) {
+        double q[NV], A[NV * NV];
+        for (int w = 0; w < NV; ++w) q[w] = Q[w * ne + x];
+        for (int w = 0; w < NV; ++w) out[w * ne + x] = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double ed[3] = {0.0, 0.0, 0.0};
+            ed[d] = 1.0;
+            orc_flux_jacobian(q, ed, m->gamma, A);
+            for (int w = 0; w < NV; ++w) {
+                double acc = 0.0;
+                for (int vv = 0; vv < NV; ++vv) acc += A[vv * NV + w] * Ftb[(d * NV + vv) * ne + x];
+                out[w * ne + x] += Ja[d] * acc;
+            }
+        }
+    }
+    if (!isolated) {
+        for (int d = 0; d < 3; ++d) {
+            int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            int na = n[t1], nb = n[t2];
+            double wend = g_w[o[d]][0];
+            double *Fb = malloc(sizeof(double) * NV * (ORC_NMAX + 1) * (ORC_NMAX + 1));
+            double *bo = malloc(sizeof(double) * NV * (ORC_NMAX + 1) * (ORC_NMAX + 1));
+            double *bn = malloc(sizeof(double) * NV * (ORC_NMAX + 1) * (ORC_NMAX + 1));
+            for (int s = -1; s <= 1; s += 2) {
+                /* e's own surface term (F*_out / w_end at its face nodes) */
+                for (int w = 0; w < NV; ++w)
+                    for (int b = 0; b < nb; ++b)
+                        for (int a = 0; a < na; ++a) {
+                            Fb[w * na * nb + a + na * b] = vt[w * ne + face_node(n, d, s, a, b)] / wend;
+                            bo[w * na * nb + a + na * b] = 0.0;
+                        }
+                /* (the neighbour's share of e's own surface term is collected by the
+                 * neighbour itself; bn is only a sink here) */
+                for (int x = 0; x < NV * (ORC_NMAX + 1) * (ORC_NMAX + 1); ++x) bn[x] = 0.0;
+                face_flux_vjp(m, orders, off, u, e, d, s, Fb, bo, bn);
+                for (int w = 0; w < NV; ++w)
+                    for (int b = 0; b < nb; ++b)
+                        for (int a = 0; a < na; ++a) out[w * ne + face_node(n, d, s, a, b)] += bo[w * na * nb + a + na * b];
+                /* the neighbour's surface term on the same face reads e's trace */
+                int bc;
+                int nbr = neighbour(m, e, d, s, &bc);
+                if (nbr < 0) continue;
+                const int *on = orders + 3 * nbr;
+                int nn[3] = {on[0] + 1, on[1] + 1, on[2] + 1}, nen = nn[0] * nn[1] * nn[2];
+                int ma = nn[t1], mb = nn[t2];
+                double *scn = malloc(sizeof(double) * nen);
+                form_scale(m, on, form, scn);
+                double wendn = g_w[on[d]][0];
+                for (int w = 0; w < NV; ++w)
+                    for (int b = 0; b < mb; ++b)
+                        for (int a = 0; a < ma; ++a) {
+                            int node = face_node(nn, d, -s, a, b);
+                            Fb[w * ma * mb + a + ma * b] = scn[node] * v[NV * off[nbr] + w * nen + node] / wendn;
+                            bo[w * ma * mb + a + ma * b] = 0.0;
+                        }
+                for (int x = 0; x < NV * na * nb; ++x) bn[x] = 0.0;
+                face_flux_vjp(m, orders, off, u, nbr, d, -s, Fb, bo, bn);
+                for (int w = 0; w < NV; ++w)
+                    for (int b = 0; b < nb; ++b)
+                        for (int a = 0; a < na; ++a) out[w * ne + face_node(n, d, s, a, b)] += bn[w * na * nb + a + na * b];
+                free(scn);
+            }
+            free(Fb);
+            free(bo);
+            free(bn);
+        }
+    }
+    free(sc);
+    free(vt);
+    free(Ftb);
+}
+
+int orc_residual_vjp(const orc_mesh *m, const int *orders, const double *u, const double *v, double *out, int form,
+                     int isolated)
+{
+    if (check_box_euler(m, orders, form)) return -1;
+    ensure_tables();
+    int E = m->nx * m->ny * m->nz;
+    long *off = node_offsets(E, orders);
+#pragma omp parallel for schedule(guided)
+    for (int e = 0; e < E; ++e) vjp_elem(m, orders, off, u, v, e, form, isolated, out + NV * off[e]);
+    free(off);
     return 0;
 }

@@ -119,10 +119,13 @@ int orc_sweep_ns(const orc_mesh *m, const int *orders, const double *u, const do
                  double Pr, int restriction, const int *elems, int nelems, double *te_new, double *te_trad);
 
 /* Adjoint-weighted truncation error (used with an adjoint state psi on the fine
- * layout): eta[e] = sum over coarse nodes and variables of (I psi) * tau_trad. */
+ * layout): eta[e] = sum over coarse nodes and variables of (I psi_t) * tau_trad, where
+ * psi_t is the adjoint of the traditional-form residual F (a nodal field): psi itself for
+ * psi_form 1, and psi / (J w_i w_j w_k) for psi_form 0, the adjoint of the new form
+ * M^-1 F (which is M psi_t).  The estimate of the functional error is -sum(eta). */
 int orc_tau_eta(const orc_mesh *m, const int *fine_orders, const int *coarse_orders,
                 const double *u, const double *dudt, int isolated, int restriction, const double *psi,
-                double *eta);
+                int psi_form, double *eta);
 
 /* Pressure force along x on the slip walls: J = sum over slip-wall faces with
  * normal +-e_x of sum_{a,b} w_a w_b |Ja^1| p(Q) n_x; dJdu (nullable, natural
@@ -139,6 +142,25 @@ int orc_residual_ns(const orc_mesh *m, const int *orders, const double *u, doubl
                     double *r, int form, int isolated);
 /* Viscous flux f^v_d(Q, G) along direction d, G[l*5 + v] = d(var v)/dx_l. */
 void orc_viscous_flux(const double *q, const double *G, int d, double gamma, double mu, double Pr, double *f);
+
+/* Derivatives of the residual (box Euler meshes, map_kind 0; form and isolated as for
+ * orc_residual).  Natural layout for u, dir, v and the outputs.
+ *   orc_residual_cstep: real and imaginary parts of the residual evaluated in complex
+ *     arithmetic at u + i h dir (r_re or r_im may be NULL).
+ *   orc_residual_jvp: (d r / d u) dir by complex step (h = 1e-30), exact to rounding.
+ *   orc_residual_vjp: (d r / d u)^T v, every step of the residual transposed by hand. */
+int orc_residual_cstep(const orc_mesh *m, const int *orders, const double *u, const double *dir, double h,
+                       double *r_re, double *r_im, int form, int isolated);
+int orc_residual_jvp(const orc_mesh *m, const int *orders, const double *u, const double *dir, double *out, int form,
+                     int isolated);
+int orc_residual_vjp(const orc_mesh *m, const int *orders, const double *u, const double *v, double *out, int form,
+                     int isolated);
+/* Jacobian of the physical flux f.n, A[i*5 + j] = d (f.n)_i / d q_j (closed form). */
+void orc_flux_jacobian(const double *q, const double *n, double gamma, double *A);
+/* Jacobians of the numerical flux (kind 0 Roe, 1 LF) in either state by complex step,
+ * AL[i*5 + j] = d f*_i / d qL_j and AR likewise. */
+void orc_numflux_jacobian(const double *qL, const double *qR, const double *n, double gamma, int kind, double *AL,
+                          double *AR);
 
 /* Williamson low-storage RK3, nsteps steps of size dt, in place on u. */
 int orc_rk3(const orc_mesh *m, const int *orders, double *u, double dt, int nsteps);

@@ -61,3 +61,37 @@ def test_jacobian_vector_products_converge():
         d = (oracle.residual(mesh, orders, u + h * v) - oracle.residual(mesh, orders, u - h * v)) / (2 * h)
         errs.append(np.max(np.abs(d - Jac @ v)))
     assert errs[1] < errs[0] / 20.0  # O(h^2) directional differences approach J v
+
+
+def test_complex_step_jacobian_matches_differences():
+    rng = np.random.default_rng(3)
+    mesh = wl.box_mesh((2, 1, 2), bc=(1, 2, 0, 0, 0, 0))
+    orders = wl.random_orders(4, 1, 2, rng)
+    u = wl.random_state(orders, rng)
+    Jc = adjoint.cs_jacobian(mesh, orders, u, form=1)
+    Jf = adjoint.fd_jacobian(mesh, orders, u, form=1)
+    assert np.max(np.abs(Jc - Jf)) < 1e-8 * np.max(np.abs(Jc))
+
+
+def test_eta_independent_of_the_adjoint_form():
+    """The adjoint of the new form r = M^-1 F is M times the adjoint of the traditional
+    form F, so the adjoint-weighted estimate of a consistent pair does not depend on the
+    form the adjoint was solved in; feeding the new-form adjoint as if it were the
+    traditional one does."""
+    rng = np.random.default_rng(6)
+    qinf = wl.conserved(*(np.array(x) for x in (1.0, 0.3, 0.0, 0.0, 1.0)))
+    mesh = wl.box_mesh((2, 2, 1), bc=(1, 2, 0, 0, 0, 0), qfar=qinf)
+    fo = wl.random_orders(4, 1, 3, rng)
+    co = np.minimum(fo, wl.random_orders(4, 1, 2, rng))
+    u = wl.pulse_state(oracle.node_coords(mesh, fo), fo, sigma=0.3, amp=0.2)
+    _, g = oracle.functional(mesh, fo, u)
+    dudt = oracle.residual(mesh, fo, u)
+    psi_t, _ = adjoint.adjoint_solve(mesh, fo, u, g, form=1)
+    psi_n, _ = adjoint.adjoint_solve(mesh, fo, u, g, form=0)
+    M = _mass(mesh, fo)
+    assert np.max(np.abs(psi_n - M * psi_t)) < 1e-9 * np.max(np.abs(psi_n))
+    eta_t = oracle.tau_eta(mesh, fo, co, u, dudt, psi_t, psi_form=1)
+    eta_n = oracle.tau_eta(mesh, fo, co, u, dudt, psi_n, psi_form=0)
+    assert np.max(np.abs(eta_t - eta_n)) < 1e-9 * np.max(np.abs(eta_t))
+    wrong = oracle.tau_eta(mesh, fo, co, u, dudt, psi_n, psi_form=1)
+    assert np.max(np.abs(wrong - eta_t)) > 1e-3 * np.max(np.abs(eta_t))
