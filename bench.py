@@ -346,8 +346,8 @@ def c3_leg(dg, torch, stream, check=True, dt=1e-5, nsteps=10):
 
 def c4_leg(dg, torch, stream, check=True):
     """Adjoint workload (24^3, N = 5, slip wall at x = 0, far field at x = 1): the residual
-    VJP and the wall functional; the VJP is checked by a central-difference dot test on
-    the oracle residual."""
+    VJP and the wall functional; the VJP is checked against the oracle's hand-transposed
+    VJP over the whole field."""
     mesh, orders = wl.c4()
     plan = dg.Plan(mesh, orders)
     xyz = plan.to_natural(plan.node_coords(), nv=3)
@@ -364,10 +364,10 @@ def c4_leg(dg, torch, stream, check=True):
     _, dJ = dg.functional(plan, u)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    psi, iters, relres = dg.adjoint_solve(plan, u, dJ, restart=30, max_iter=300, rtol=1e-8)
+    psi, iters, relres = dg.adjoint_solve(plan, u, dJ, restart=30, max_iter=300, rtol=1e-8, form=dg.FORM_TRAD)
     torch.cuda.synchronize()
     t_adj = (time.perf_counter() - t0) * 1e3
-    true_rel = float((dg.residual_vjp(plan, u, psi) - dJ).norm() / dJ.norm())
+    true_rel = float((dg.residual_vjp(plan, u, psi, form=dg.FORM_TRAD) - dJ).norm() / dJ.norm())
     res = {"workload": "Euler 24^3 N=5, slip wall x=0, far field x=1, seed 4", "nodes": n,
            "vjp_ms": tv, "vjp_gdof_s": n / (tv * 1e-3) / 1e9,
            "vjp_hbm_frac": 120.0 * n / (tv * 1e-3) / 1e9 / PEAK_HBM_GBS,
@@ -377,14 +377,10 @@ def c4_leg(dg, torch, stream, check=True):
                              "gmres_relres": relres, "true_relres": true_rel}}
     if check:
         import oracle
-        w = rng.normal(size=u_nat.shape)
-        w *= 1.0 / np.max(np.abs(w))
-        eps = 1e-6
-        fd = (oracle.residual(mesh, orders, u_nat + eps * w) - oracle.residual(mesh, orders, u_nat - eps * w)) / (2 * eps)
         jtv = plan.to_natural(dg.residual_vjp(plan, u, v))
-        lhs, rhs = float(v_nat @ fd), float(jtv @ w)
-        res["err_vs_oracle"] = {"dot_test_rel": abs(lhs - rhs) / abs(lhs),
-                                "measure": "|<v, (r(u+eps w) - r(u-eps w))/2eps> - <J^T v, w>| / |<v, ...>|, eps=1e-6"}
+        ref = oracle.residual_vjp(mesh, orders, u_nat, v_nat)
+        res["err_vs_oracle"] = {"vjp": float(np.max(np.abs(jtv - ref)) / np.max(np.abs(ref))),
+                                "measure": "max|J^T v - oracle J^T v| / max|oracle J^T v| over the whole field"}
     return res
 
 

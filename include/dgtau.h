@@ -155,15 +155,22 @@ dg_status dg_residual(dg_plan plan, const void *u, void *r, int32_t dtype, int32
  *   norms: device double [E_coarse][2], max |tau_new|, max |tau_trad| over nodes and
  *          the 5 variables of each coarse plan element (may be NULL).
  *   psi, eta: optional adjoint weighting (both NULL or both set): psi is a fine-layout
- *          device double field (e.g. the adjoint of a force functional), eta[E_coarse]
- *          receives sum over coarse nodes and variables of (I psi) * tau_trad; the
- *          functional error estimate is -sum(eta).
- * Errors: DG_EINVAL (null u, foreign coarse plan, psi without eta, bad restriction,
- * misaligned arrays), DG_EUNSUPPORTED (coupled estimate on a curved mesh with a coarse
- * order below the geometry order), DG_EHIP. */
+ *          device double field, the adjoint of a functional (e.g. dg_adjoint_solve's
+ *          solution for dg_functional's gradient) for the residual of form psi_form;
+ *          eta[E_coarse] receives sum over coarse nodes and variables of (I psi_t) * tau_trad,
+ *          psi_t the traditional-form adjoint, a nodal field: psi itself for
+ *          psi_form = DG_FORM_TRAD; for DG_FORM_NEW the adjoint of M^-1 F, which is M psi_t,
+ *          so psi is divided by the fine mass matrix M = J w_i w_j w_k before the
+ *          restriction.  Either consistent pair gives the same eta (Section 2.2: the
+ *          truncation error and functional errors); the functional error estimate is
+ *          -sum(eta).
+ *   psi_form: DG_FORM_TRAD or DG_FORM_NEW (ignored without psi).
+ * Errors: DG_EINVAL (null u, foreign coarse plan, psi without eta, bad restriction or
+ * psi_form, misaligned arrays), DG_EUNSUPPORTED (coupled estimate on a curved mesh with a
+ * coarse order below the geometry order), DG_EHIP. */
 dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt,
                           int32_t isolated, int32_t restriction, double *tau_new, double *tau_trad,
-                          double *norms, const double *psi, double *eta, hipStream_t stream);
+                          double *norms, const double *psi, int32_t psi_form, double *eta, hipStream_t stream);
 
 /* Number of coarse combinations per fine plan element for the sweep:
  * prod_d max(1, N_d - 1); combo_offset[E+1] (host) gets their prefix sums. */

@@ -67,7 +67,7 @@ SIGNATURES = {
     "dg_node_coords": [_P, _P, _P],
     "dg_plan_metrics": [_P, _P, _P],
     "dg_residual": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
-    "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P],
+    "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P, _P],
     "dg_residual_vjp": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_functional": [_P, _P, _P, _P, _P],
     "dg_sweep_layout": [_P, _I64P],
@@ -311,9 +311,11 @@ def residual(plan: Plan, u, form: int = FORM_NEW, isolated: bool = False, out=No
 
 
 def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False, psi=None,
-                 restriction: int = RESTRICT_SAMPLE):
+                 restriction: int = RESTRICT_SAMPLE, psi_form: int = FORM_TRAD):
     """Returns (tau_new, tau_trad, norms[E,2]) in the coarse plan layout (float64), plus
-    eta[E] (sum of (I psi) * tau_trad per coarse element) when an adjoint weight psi is given.
+    eta[E] (sum of (I psi_t) * tau_trad per coarse element, psi_t the traditional-form
+    adjoint) when an adjoint weight psi is given; psi_form is the form of the residual psi
+    is the adjoint of (FORM_NEW: psi is divided by the fine mass matrix first).
     restriction: RESTRICT_SAMPLE (coarse-node sampling) or RESTRICT_L2 (L2 projection)."""
     torch = _torch()
     if coarse.parent is not fine:
@@ -326,7 +328,7 @@ def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False,
     norms = torch.empty((coarse.n_elems, 2), dtype=torch.float64, device="cuda")
     eta = torch.empty(coarse.n_elems, dtype=torch.float64, device="cuda") if psi is not None else None
     _call("dg_tau_estimate", fine.handle, coarse.handle, _ptr(u), _ptr(dudt), int(bool(isolated)),
-          int(restriction), _ptr(tn), _ptr(tt), _ptr(norms), _ptr(psi), _ptr(eta), _stream())
+          int(restriction), _ptr(tn), _ptr(tt), _ptr(norms), _ptr(psi), int(psi_form), _ptr(eta), _stream())
     return (tn, tt, norms) if psi is None else (tn, tt, norms, eta)
 
 
@@ -417,7 +419,7 @@ def select_orders(plan: Plan, maps, tau_max: float, nmin: int = 1, nmax: int = N
 
 
 def adjoint_solve(plan: Plan, u, g, psi=None, restart: int = 30, max_iter: int = 2000, rtol: float = 1e-10,
-                  form: int = FORM_NEW, isolated: bool = False):
+                  form: int = FORM_TRAD, isolated: bool = False):
     """Solve (dr/du)^T psi = g by restarted GMRES on the residual VJP; returns
     (psi, iterations, relative residual).  psi (optional) is the initial guess."""
     torch = _torch()

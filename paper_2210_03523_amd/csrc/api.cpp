@@ -734,7 +734,7 @@ dg_status dg_residual(dg_plan p, const void *u, void *r, int32_t dtype, int32_t 
 
 dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt, int32_t isolated,
                           int32_t restriction, double *tau_new, double *tau_trad, double *norms, const double *psi,
-                          double *eta, hipStream_t stream) {
+                          int32_t psi_form, double *eta, hipStream_t stream) {
     if (!fine || !coarse || !u) return fail(DG_EINVAL, "null argument");
     if (restriction != DG_RESTRICT_SAMPLE && restriction != DG_RESTRICT_L2)
         return fail(DG_EINVAL, "restriction must be DG_RESTRICT_SAMPLE or DG_RESTRICT_L2");
@@ -746,6 +746,8 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
                 return fail(DG_EUNSUPPORTED, "the coupled tau-estimate on curved meshes needs coarse orders >= the "
                                              "geometry order (watertight coarse faces); the isolated one takes any");
     if ((psi == nullptr) != (eta == nullptr)) return fail(DG_EINVAL, "psi and eta go together");
+    if (psi_form != DG_FORM_NEW && psi_form != DG_FORM_TRAD)
+        return fail(DG_EINVAL, "psi_form must be DG_FORM_NEW or DG_FORM_TRAD");
     if (!tau_new && !tau_trad && !norms && !eta) return DG_OK;
     if (!dudt) {
         EpiArgs epi{};
@@ -757,7 +759,8 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
     }
     HIP_TRY(launch_restrict(coarse->d_fine_of, coarse->E, coarse->d_el, fine->d_el, u, dudt, psi, coarse->d_uc,
                             coarse->d_rdc, coarse->d_psic, fine->tabs.t64, coarse->rcapA, coarse->rcapB,
-                            restriction, stream));
+                            restriction, psi && psi_form == DG_FORM_NEW, fine->curved ? fine->d_met64 : nullptr,
+                            1.0 / fine->geom.J, stream));
     EpiArgs epi{};
     epi.mode = EPI_TAU;
     epi.isolated = isolated ? 1 : 0;

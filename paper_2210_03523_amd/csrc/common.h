@@ -120,9 +120,12 @@ hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, con
 // capA, capB: LDS capacities (doubles) of the two staging buffers, 5 c1 f2 f3 and
 // 5 max(c1 c2 f3, f1 f2 f3) maximised over the coarse plan's elements.  restriction:
 // 0 samples at the coarse nodes, 1 takes the exact L2 projection (also for the sweeps).
+// psi_new: psi is the new-form adjoint and is divided by the fine mass matrix J w w w
+// (met: curved metric terms [elem][10][node], or null with invJ = 1/J of box elements).
 hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
                            const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
-                           double *psic, const double *tab, int capA, int capB, int restriction, hipStream_t s);
+                           double *psic, const double *tab, int capA, int capB, int restriction, int psi_new,
+                           const double *met, double invJ, hipStream_t s);
 
 // Solution transfer onto another order map: target plan elements tel, source plan
 // elements sel, src_inv[natural] = source plan position; capA = max 5 t1 s2 s3,

@@ -32,6 +32,9 @@ namespace dgt {
 // projection).  PROJECT: the solution transfer onto another order map (Section 2.4.1,
 // down = T_P): the "coarse" element is the target, of any orders, the source element is
 // found through the source plan's natural -> plan index (fine_of), one field (Q).
+// psi_new: the adjoint weight is the adjoint of the new-form residual M^-1 F, i.e. M times
+// the traditional-form adjoint (M = J w_i w_j w_k of the fine element); it is divided by
+// M as it is staged (box elements: J = 1/invJ; curved: J per node from met).
 constexpr int RS_WG = 256;
 constexpr int RS_TAB = 3 * NNMAX * NNMAX;
 
@@ -42,7 +45,8 @@ __global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ 
                                                     const double *__restrict__ dudt, const double *__restrict__ psi,
                                                     double *__restrict__ uc, double *__restrict__ rdc,
                                                     double *__restrict__ psic, const double *__restrict__ tab,
-                                                    int capA, int down) {
+                                                    int capA, int down, int psi_new,
+                                                    const double *__restrict__ met, double invJ) {
     extern __shared__ double lds[];
     double *sI = lds, *sA = lds + RS_TAB, *sB = lds + RS_TAB + capA;
     const int p = xcd_remap(blockIdx.x, gridDim.x);
@@ -74,6 +78,19 @@ __global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ 
             for (int k = 0; k < 8; ++k) {
                 const int t = t0 + tid + k * RS_WG;
                 v[k] = t < NV * nef ? src[t] : 0.0;
+            }
+            if (!PROJECT && field == 2 && psi_new) {
+                const double *w1 = tab + T_W + xoff(f1 - 1), *w2 = tab + T_W + xoff(f2 - 1);
+                const double *w3 = tab + T_W + xoff(f3 - 1);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int t = t0 + tid + k * RS_WG;
+                    if (t < NV * nef) {
+                        const int node = t % nef, i = node % f1, j = (node / f1) % f2, kk = node / (f1 * f2);
+                        const double ij = met ? 1.0 / met[10 * F.noff + 9 * nef + node] : invJ;
+                        v[k] *= ij / (w1[i] * w2[j] * w3[kk]);
+                    }
+                }
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -116,7 +133,8 @@ __global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ 
 
 hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
                            const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
-                           double *psic, const double *tab, int capA, int capB, int restriction, hipStream_t s) {
+                           double *psic, const double *tab, int capA, int capB, int restriction, int psi_new,
+                           const double *met, double invJ, hipStream_t s) {
     if (ncoarse == 0) return hipSuccess;
     const size_t lds = sizeof(double) * (size_t)(RS_TAB + capA + capB);
     if (lds > 64 * 1024) {
@@ -125,7 +143,7 @@ hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_restrict<false>, dim3(ncoarse), dim3(RS_WG), lds, s, fine_of, celems, felems, u, dudt, psi,
-                       uc, rdc, psic, tab, capA, restriction ? T_P : T_I);
+                       uc, rdc, psic, tab, capA, restriction ? T_P : T_I, psi_new, met, invJ);
     return hipGetLastError();
 }
 
@@ -139,7 +157,7 @@ hipError_t launch_project(const int32_t *src_inv, int ntarget, const ElemInfo *t
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_restrict<true>, dim3(ntarget), dim3(RS_WG), lds, s, src_inv, tel, sel, u, nullptr, nullptr,
-                       ut, nullptr, nullptr, tab, capA, T_P);
+                       ut, nullptr, nullptr, tab, capA, T_P, 0, nullptr, 0.0);
     return hipGetLastError();
 }
 

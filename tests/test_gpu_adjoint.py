@@ -1,17 +1,20 @@
-"""GPU adjoint path against the oracle: the hand-written VJP of the residual
-checked by central differences of the FP64 oracle residual (dot tests and a
-brute-force Jacobian on a tiny mesh), the autograd wrapper, the wall-force
-functional and its gradient, and the adjoint-weighted tau (eta).
+"""GPU adjoint path against the oracle: the hand-written VJP of the residual compared
+element by element with the oracle's hand-transposed VJP (itself pinned by complex-step
+dot tests and discrete conservation, tests/test_oracle_vjp.py) on random mixed-order
+meshes with periodic, slip-wall and far-field faces, on periodic chains covering every
+ordered mortar pair of orders 1..7 in each direction, on a tiny mesh against the whole
+complex-step Jacobian, and at the full 24^3, N = 5 adjoint workload; the autograd
+wrapper, the wall-force functional and its gradient, and the adjoint-weighted tau
+(eta) with the adjoint in either form.
 
-Finite-difference tolerance: central differences at eps = 1e-6 carry a truncation
-error O(eps^2 |r'''|) and a rounding error O(1e-16 |r| / eps) ~ 1e-10 |r|; the
-checks allow 1e-7 of the scale |v| |r| (dot tests) or of max |J| (Jacobian)."""
+Bar: FP64 fields within 1e-12 of max |out_oracle| (the transposed operator has no
+cancellation beyond that of its inputs' scale)."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads as wl
-from helpers import residual_scale
+from helpers import mortar_chain
 
 pytestmark = pytest.mark.gpu
 
@@ -21,54 +24,68 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 
 import paper_2210_03523_amd as dg  # noqa: E402
 
-EPS = 1e-6
+TOL = 1e-12
+QINF = tuple(wl.conserved(np.array(1.0), np.array(0.3), np.array(0.4), np.array(0.5), np.array(1.0)))
 
 
 def _setup(shape, lo, hi, seed, bc=(0,) * 6, flux=wl.ROE):
     rng = np.random.default_rng(seed)
-    qinf = tuple(wl.conserved(np.array(1.0), np.array(0.3), np.array(0.4), np.array(0.5), np.array(1.0)))
-    mesh = wl.box_mesh(shape, bc=bc, flux=flux, qfar=qinf)
+    mesh = wl.box_mesh(shape, bc=bc, flux=flux, qfar=QINF)
     orders = wl.random_orders(int(np.prod(shape)), lo, hi, rng)
     u = wl.random_state(orders, rng)
     return mesh, orders, u, rng
 
 
+def _rel(x, ref):
+    return float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
+
+
 CASES = [((2, 2, 2), 1, 5, 50, (0,) * 6, wl.ROE),
          ((3, 2, 1), 2, 4, 51, (1, 2, 0, 0, 0, 0), wl.ROE),
-         ((2, 1, 2), 1, 3, 52, (0, 0, 1, 2, 0, 0), wl.LF)]
+         ((2, 1, 2), 1, 3, 52, (0, 0, 1, 2, 0, 0), wl.LF),
+         ((2, 2, 1), 1, 9, 57, (2, 1, 1, 2, 0, 0), wl.ROE),
+         ((1, 2, 3), 1, 7, 58, (0, 0, 0, 0, 1, 2), wl.LF)]
 
 
 @pytest.mark.parametrize("shape,lo,hi,seed,bc,flux", CASES)
-@pytest.mark.parametrize("form,isolated", [(0, False), (1, False), (0, True)])
-def test_vjp_dot_against_oracle_differences(shape, lo, hi, seed, bc, flux, form, isolated):
+@pytest.mark.parametrize("form,isolated", [(0, False), (1, False), (0, True), (1, True)])
+def test_vjp_against_oracle(shape, lo, hi, seed, bc, flux, form, isolated):
     mesh, orders, u, rng = _setup(shape, lo, hi, seed, bc, flux)
     plan = dg.Plan(mesh, orders)
     ud = plan.to_plan(u)
-    r0 = oracle.residual(mesh, orders, u, form=form, isolated=isolated)
-    for _ in range(8):
+    for _ in range(2):
         v = rng.normal(size=u.size)
-        d = rng.normal(size=u.size) * np.abs(u) * 1e-2
-        g = plan.to_natural(dg.residual_vjp(plan, ud, plan.to_plan(v), form=form, isolated=isolated))
-        fd = (oracle.residual(mesh, orders, u + EPS * d, form, isolated)
-              - oracle.residual(mesh, orders, u - EPS * d, form, isolated)) / (2 * EPS)
-        lhs, rhs = g @ d, v @ fd
-        scale = np.linalg.norm(v) * np.linalg.norm(r0) * 1e-2
-        assert abs(lhs - rhs) < 1e-7 * scale + 1e-9 * abs(rhs), (lhs, rhs)
+        got = plan.to_natural(dg.residual_vjp(plan, ud, plan.to_plan(v), form=form, isolated=isolated))
+        ref = oracle.residual_vjp(mesh, orders, u, v, form, isolated)
+        assert _rel(got, ref) < TOL
 
 
-def test_vjp_full_jacobian_tiny_mesh():
+@pytest.mark.parametrize("d", [0, 1, 2])
+@pytest.mark.parametrize("flux", [wl.ROE, wl.LF])
+def test_vjp_every_mortar_pair(d, flux):
+    rng = np.random.default_rng(60 + d + 3 * flux)
+    mesh, orders = mortar_chain(d, rng)
+    mesh["flux"] = flux
+    u = wl.random_state(orders, rng)
+    plan = dg.Plan(mesh, orders)
+    ud = plan.to_plan(u)
+    for form in (0, 1):
+        v = rng.normal(size=u.size)
+        got = plan.to_natural(dg.residual_vjp(plan, ud, plan.to_plan(v), form=form))
+        assert _rel(got, oracle.residual_vjp(mesh, orders, u, v, form)) < TOL
+
+
+def test_vjp_whole_jacobian_tiny_mesh():
+    """Rows of the GPU's transposed product against the oracle's complex-step Jacobian."""
+    from oracle import adjoint
     mesh, orders, u, rng = _setup((2, 1, 2), 1, 2, 53, bc=(1, 2, 0, 0, 0, 0))
     plan = dg.Plan(mesh, orders)
-    n = u.size
-    J = np.zeros((n, n))
-    for i in range(n):
-        e = np.zeros(n)
-        e[i] = EPS * max(abs(u[i]), 1.0)
-        J[:, i] = (oracle.residual(mesh, orders, u + e) - oracle.residual(mesh, orders, u - e)) / (2 * e[i])
-    v = rng.normal(size=n)
-    g = plan.to_natural(dg.residual_vjp(plan, plan.to_plan(u), plan.to_plan(v)))
-    ref = J.T @ v
-    assert np.max(np.abs(g - ref)) < 1e-6 * np.max(np.abs(ref))
+    Jac = adjoint.cs_jacobian(mesh, orders, u)
+    ud = plan.to_plan(u)
+    for _ in range(4):
+        v = rng.normal(size=u.size)
+        got = plan.to_natural(dg.residual_vjp(plan, ud, plan.to_plan(v)))
+        assert _rel(got, Jac.T @ v) < TOL
 
 
 def test_autograd_function():
@@ -81,6 +98,7 @@ def test_autograd_function():
     ref = dg.residual_vjp(plan, ud.detach(), w)
     assert torch.equal(ud.grad, ref)
     assert torch.equal(r.detach(), dg.residual(plan, ud.detach()))
+    assert _rel(plan.to_natural(ud.grad), oracle.residual_vjp(mesh, orders, u, plan.to_natural(w))) < TOL
 
 
 def test_functional_and_gradient():
@@ -92,27 +110,43 @@ def test_functional_and_gradient():
     assert np.max(np.abs(plan.to_natural(g) - gr)) < 1e-13 * np.max(np.abs(gr))
 
 
+def _mass(mesh, orders):
+    h = (np.asarray(mesh["hi"]) - np.asarray(mesh["lo"])) / np.asarray(mesh["n"])
+    J = np.prod(h) / 8.0
+    out = []
+    for o in np.asarray(orders).reshape(-1, 3):
+        w = [oracle.lgl(int(N))[1] for N in o]
+        out.append(np.tile(J * np.einsum("k,j,i->kji", w[2], w[1], w[0]).ravel(), 5))
+    return np.concatenate(out)
+
+
 @pytest.mark.parametrize("isolated", [False, True])
-def test_adjoint_weighted_tau(isolated):
+@pytest.mark.parametrize("psi_form", [dg.FORM_TRAD, dg.FORM_NEW])
+def test_adjoint_weighted_tau(isolated, psi_form):
     mesh, fo, u, rng = _setup((2, 2, 2), 2, 6, 56, bc=(1, 2, 0, 0, 0, 0))
     co = np.minimum(fo, wl.random_orders(8, 1, 5, rng))
-    psi = rng.normal(size=u.size)
+    psi_t = rng.normal(size=u.size)
+    # the new-form adjoint of the same functional is M times the traditional one
+    psi = psi_t if psi_form == dg.FORM_TRAD else _mass(mesh, fo) * psi_t
     dudt = oracle.residual(mesh, fo, u)
-    eta_r = oracle.tau_eta(mesh, fo, co, u, dudt, psi, isolated=isolated)
+    eta_r = oracle.tau_eta(mesh, fo, co, u, dudt, psi, isolated=isolated, psi_form=psi_form)
+    eta_t = oracle.tau_eta(mesh, fo, co, u, dudt, psi_t, isolated=isolated, psi_form=dg.FORM_TRAD)
+    assert np.max(np.abs(eta_r - eta_t)) < 1e-12 * np.abs(eta_t).sum()
     fine = dg.Plan(mesh, fo)
     coarse = fine.coarse(co)
-    tn, tt, norms, eta = dg.tau_estimate(fine, coarse, fine.to_plan(u), None, isolated, psi=fine.to_plan(psi))
+    tn, tt, norms, eta = dg.tau_estimate(fine, coarse, fine.to_plan(u), None, isolated, psi=fine.to_plan(psi),
+                                         psi_form=psi_form)
     _, tt_r, _, _ = oracle.tau(mesh, fo, co, u, dudt, isolated=isolated)
-    scale = np.abs(tt_r).sum() * np.max(np.abs(psi)) + 1e-300
+    scale = np.abs(tt_r).sum() * np.max(np.abs(psi_t)) + 1e-300
     got = coarse.elem_to_natural(eta.cpu().numpy())
     assert np.max(np.abs(got - eta_r)) < 1e-12 * scale
 
 
 @pytest.mark.slow
 def test_c4_workload():
-    """24^3, N = 5 (3.0M nodes), slip wall at x = 0: VJP checked by central differences of
-    the oracle residual at eps = 1e-6 on 64 seeded random directions; functional and its
-    gradient; coupled tau at Nc = 4 weighted by dJ/du."""
+    """24^3, N = 5 (3.0M nodes), slip wall at x = 0, far field at x = 1: the VJP against the
+    oracle's over the whole field (both forms), the functional and its gradient, and the
+    coupled tau at Nc = 4 weighted by dJ/du."""
     mesh, orders = wl.c4()
     u = wl.c4_state(oracle.node_coords(mesh, orders), orders)
     plan = dg.Plan(mesh, orders)
@@ -122,18 +156,13 @@ def test_c4_workload():
     Jr, gr = oracle.functional(mesh, orders, u)
     assert abs(float(J) - Jr) < 1e-12 * abs(Jr)
     assert np.max(np.abs(plan.to_natural(g) - gr)) < 1e-13 * np.max(np.abs(gr))
-    v = rng.normal(size=u.size)
-    vjp = plan.to_natural(dg.residual_vjp(plan, ud, plan.to_plan(v)))
-    r0 = oracle.residual(mesh, orders, u)
-    worst = 0.0
-    for _ in range(64):
-        d = rng.normal(size=u.size)
-        d /= np.max(np.abs(d))
-        fd = (oracle.residual(mesh, orders, u + EPS * d) - oracle.residual(mesh, orders, u - EPS * d)) / (2 * EPS)
-        worst = max(worst, abs(vjp @ d - v @ fd) / (np.linalg.norm(v) * np.linalg.norm(r0)))
-    assert worst < 1e-7
+    for form in (0, 1):
+        v = rng.normal(size=u.size)
+        got = plan.to_natural(dg.residual_vjp(plan, ud, plan.to_plan(v), form=form))
+        assert _rel(got, oracle.residual_vjp(mesh, orders, u, v, form)) < TOL
     co = wl.uniform_orders(len(orders), 4)
     coarse = plan.coarse(co)
+    r0 = oracle.residual(mesh, orders, u)
     _, _, _, eta = dg.tau_estimate(plan, coarse, ud, psi=g)
     eta_r = oracle.tau_eta(mesh, orders, co, u, r0, gr)
     assert np.max(np.abs(coarse.elem_to_natural(eta.cpu().numpy()) - eta_r)) < 1e-12 * (np.abs(eta_r).sum() + 1e-300)

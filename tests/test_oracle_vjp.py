@@ -28,6 +28,7 @@ import pytest
 
 import oracle
 import workloads as wl
+from helpers import de_bruijn_pairs, mortar_chain
 
 G = 1.4
 
@@ -152,41 +153,6 @@ def _dot_err(mesh, orders, u, rng, form, isolated, ntries=4):
 def test_vjp_dot_test(i, form, isolated):
     mesh, orders, u, rng = _case(*MESHES[i], seed=20 + i)
     assert _dot_err(mesh, orders, u, rng, form, isolated) < 1e-12
-
-
-def de_bruijn_pairs(k: int):
-    """Cyclic sequence over 1..k in which every ordered pair (a, b) appears once as
-    consecutive entries (de Bruijn sequence of order 2)."""
-    seq, a = [], [0] * 2 * k
-
-    def db(t, p):
-        if t > 2:
-            if 2 % p == 0:
-                seq.extend(a[1:p + 1])
-        else:
-            a[t] = a[t - p]
-            db(t + 1, p)
-            for j in range(a[t - p] + 1, k):
-                a[t] = j
-                db(t + 1, t)
-    db(1, 1)
-    return [s + 1 for s in seq]
-
-
-def mortar_chain(d: int, rng, kmax: int = 7):
-    """Periodic chain of k^2 elements along direction d whose consecutive elements'
-    orders in both tangential directions run through every ordered pair of 1..k (the
-    second tangential direction shifted along the cycle); small orders along d."""
-    seq = de_bruijn_pairs(kmax)
-    L = len(seq)
-    shape = [1, 1, 1]
-    shape[d] = L
-    t1, t2 = (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
-    orders = np.zeros((L, 3), dtype=np.int32)
-    orders[:, d] = rng.integers(1, 3, L)
-    orders[:, t1] = seq
-    orders[:, t2] = np.roll(seq, 7)
-    return wl.box_mesh(tuple(shape), hi=(1.0, 0.7, 1.3)), orders
 
 
 def test_de_bruijn_covers_every_pair():
