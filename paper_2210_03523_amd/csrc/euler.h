@@ -2,7 +2,7 @@
 // coordinate axis and the numerical fluxes at an axis-aligned face.
 //
 // Roe's approximate Riemann solver (the advective flux of the paper's
-// numerical set-up, Section 4): F = (f_L + f_R)/2 - (1/2) sum_k |lam_k| alpha_k r_k
+// numerical set-up at the start of Section 3): F = (f_L + f_R)/2 - (1/2) sum_k |lam_k| alpha_k r_k
 // with Roe averages, acoustic waves u_n -/+ c, an entropy wave and both shear
 // waves combined; no entropy fix.  The Rusanov (local Lax-Friedrichs) flux is
 // the alternative: F = (f_L + f_R)/2 - (s/2)(Q_R - Q_L), s = max(|u_n| + c).

@@ -1,4 +1,4 @@
-"""Pins of the oracle's Euler fluxes (Roe advective flux, Section 4 set-up; Rusanov option).
+"""Pins of the oracle's Euler fluxes (Roe advective flux, set-up at the start of Section 3; Rusanov option).
 
 Checks use Roe's defining properties (the wave vectors sum to the jump, and
 their eigenvalue-weighted sum to the flux jump), consistency, antisymmetry,

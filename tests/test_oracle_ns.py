@@ -1,6 +1,6 @@
 """Pins of the oracle's Navier-Stokes (BR1) operator: the first-order system of
 Section 2.1 (eqs. SystemAdvDiff, DGSEMsystem:2) with the BR1 diffusive flux of the
-paper's set-up (Section 4).
+paper's set-up (start of Section 3).
 
 Pins: the viscous flux against the Stokes stress and Fourier heat flux built from
 primitive gradients; free-stream preservation; discrete conservation; exact BR1

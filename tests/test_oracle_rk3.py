@@ -1,4 +1,4 @@
-"""Pins of the oracle's Williamson low-storage RK3 (Section 4 set-up).
+"""Pins of the oracle's Williamson low-storage RK3 (set-up at the start of Section 3).
 
 Third-order convergence in dt, conservation of sum(J w U) and free-stream
 preservation; together they fix the three (A_k, B_k) coefficient pairs.
