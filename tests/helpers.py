@@ -76,3 +76,28 @@ def mortar_chain(d: int, rng, kmax: int = 7):
     orders[:, t1] = seq
     orders[:, t2] = np.roll(seq, 7)
     return wl.box_mesh(tuple(shape), hi=(1.0, 0.7, 1.3)), orders
+
+
+def tau_scale(mesh, fine_orders, coarse_orders, u, isolated=False, restriction=0):
+    """Denominators of the tau tolerances: max |r^Nc(Q^c)| of the coarse residual of the
+    restricted state (new form) and of its traditional form, from the oracle's estimate
+    with a zero fine time derivative (tau = r^Nc(I u) - I dudt).  The estimate is the
+    difference of two terms of this size, so its rounding is measured against it."""
+    import oracle
+    z = np.zeros_like(u)
+    tn, tt, _, _ = oracle.tau(mesh, fine_orders, coarse_orders, u, z, isolated=isolated,
+                              restriction=restriction)
+    return float(np.max(np.abs(tn))), float(np.max(np.abs(tt)))
+
+
+def sweep_scale(mesh, orders, u, elems=None, restriction=0, ns=None):
+    """As tau_scale for the isolated sweep: the largest entry of the maps of the coarse
+    isolated residuals alone (zero fine time derivative), both forms.  ns = (mu, Pr)
+    for Navier-Stokes meshes."""
+    import oracle
+    z = np.zeros_like(u)
+    if ns is None:
+        ten, tet, _ = oracle.sweep(mesh, orders, u, z, elems=elems, restriction=restriction)
+    else:
+        ten, tet, _ = oracle.sweep_ns(mesh, orders, u, z, ns[0], ns[1], elems=elems, restriction=restriction)
+    return float(np.max(np.abs(ten))), float(np.max(np.abs(tet)))

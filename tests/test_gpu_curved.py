@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from helpers import residual_scale
+from helpers import residual_scale, sweep_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -36,10 +36,15 @@ def err(x, ref, s):
     return float(np.max(np.abs(x - ref)) / max(float(np.max(np.abs(ref))), s))
 
 
-def _case(n, orng, seed, bc=(0,) * 6, flux=wl.ROE, ns=False, state="random"):
+def _case(n, orng, seed, bc=(0,) * 6, flux=wl.ROE, ns=False, state="random", per_element=False):
+    """per_element: (Nx, Ny) drawn per element and Nz in 1..2, so faces between the
+    layers are non-conforming too; otherwise per element column with Nz = 1."""
     rng = np.random.default_rng(seed)
     mesh = _mesh(n, bc, flux, ns)
-    orders = wl.column_orders(mesh, *orng, rng)
+    if per_element:
+        orders = wl.element_orders(mesh, *orng, rng, nz_range=(1, 2))
+    else:
+        orders = wl.column_orders(mesh, *orng, rng)
     if state == "random":
         u = wl.random_state(orders, rng)
     else:
@@ -71,16 +76,18 @@ def test_coordinates_and_metrics():
     assert np.max(np.abs(metc - refc)) < 1e-13 * np.max(np.abs(refc))
 
 
-CASES = [((3, 3, 2), (2, 6), 91, (0,) * 6, wl.ROE),
-         ((3, 2, 2), (2, 5), 92, (2, 2, 0, 0, 0, 0), wl.ROE),
-         ((2, 3, 2), (2, 4), 93, (0, 0, 1, 1, 0, 0), wl.LF)]
+CASES = [((3, 3, 2), (2, 6), 91, (0,) * 6, wl.ROE, False),
+         ((3, 2, 2), (2, 5), 92, (2, 2, 0, 0, 0, 0), wl.ROE, False),
+         ((2, 3, 2), (2, 4), 93, (0, 0, 1, 1, 0, 0), wl.LF, False),
+         ((3, 3, 2), (2, 6), 191, (0,) * 6, wl.ROE, True),
+         ((3, 2, 3), (2, 5), 192, (2, 2, 0, 0, 0, 0), wl.LF, True)]
 
 
-@pytest.mark.parametrize("n,orng,seed,bc,flux", CASES)
+@pytest.mark.parametrize("n,orng,seed,bc,flux,per_element", CASES)
 @pytest.mark.parametrize("ns", [False, True])
 @pytest.mark.parametrize("form,isolated", [(0, False), (1, False), (0, True)])
-def test_residual_fp64(n, orng, seed, bc, flux, ns, form, isolated):
-    mesh, orders, u, _ = _case(n, orng, seed, bc, flux, ns)
+def test_residual_fp64(n, orng, seed, bc, flux, per_element, ns, form, isolated):
+    mesh, orders, u, _ = _case(n, orng, seed, bc, flux, ns, per_element=per_element)
     plan = dg.Plan(mesh, orders)
     ref = _resid(mesh, orders, u, form=form, isolated=isolated)
     got = plan.to_natural(dg.residual(plan, plan.to_plan(u), form=form, isolated=isolated))
@@ -90,26 +97,29 @@ def test_residual_fp64(n, orng, seed, bc, flux, ns, form, isolated):
     assert err(got, ref, s) < TOL64
 
 
+@pytest.mark.parametrize("per_element", [False, True])
 @pytest.mark.parametrize("ns", [False, True])
-def test_residual_fp32(ns):
-    mesh, orders, u, _ = _case((3, 3, 2), (2, 6), 94, ns=ns)
+def test_residual_fp32(ns, per_element):
+    mesh, orders, u, _ = _case((3, 3, 2), (2, 6), 94, ns=ns, per_element=per_element)
     plan = dg.Plan(mesh, orders)
     ref = _resid(mesh, orders, u)
     got = plan.to_natural(dg.residual(plan, plan.to_plan(u, dtype=torch.float32))).astype(np.float64)
     assert err(got, ref, residual_scale(mesh, orders, u)) < TOL32
 
 
-def test_free_stream_on_the_gpu():
-    mesh, orders, _, _ = _case((3, 3, 2), (2, 6), 95, bc=(2, 2, 0, 0, 0, 0), ns=True)
+@pytest.mark.parametrize("per_element", [False, True])
+def test_free_stream_on_the_gpu(per_element):
+    mesh, orders, _, _ = _case((3, 3, 2), (2, 6), 95, bc=(2, 2, 0, 0, 0, 0), ns=True, per_element=per_element)
     u = wl.uniform_state(orders, np.array(QINF))
     plan = dg.Plan(mesh, orders)
     r = dg.residual(plan, plan.to_plan(u)).cpu().numpy()
     assert np.max(np.abs(r)) < 1e-13 * residual_scale(mesh, orders, u)
 
 
+@pytest.mark.parametrize("per_element", [False, True])
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
-def test_rk3_ns(dtype, tol):
-    mesh, orders, u, _ = _case((3, 3, 2), (2, 5), 96, ns=True, state="pulse")
+def test_rk3_ns(dtype, tol, per_element):
+    mesh, orders, u, _ = _case((3, 3, 2), (2, 5), 96, ns=True, state="pulse", per_element=per_element)
     plan = dg.Plan(mesh, orders)
     ud = plan.to_plan(u, dtype=dtype)
     g = torch.empty_like(ud)
@@ -125,22 +135,24 @@ def test_rk3_ns(dtype, tol):
     assert np.max(np.abs(plan.to_natural(ud).astype(np.float64) - ref)) < tol * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("per_element", [False, True])
 @pytest.mark.parametrize("ns,isolated,restriction", [(False, True, 0), (True, True, 0), (False, False, 0),
                                                      (True, False, 0), (False, False, 1), (True, True, 1)])
-def test_tau(ns, isolated, restriction):
+def test_tau(ns, isolated, restriction, per_element):
     """Isolated estimates at any coarse order; coupled ones with coarse orders at or
     above the geometry order (2, 2, 1), mortars between the coarse orders."""
-    mesh, fo, u, rng = _case((3, 3, 2), (2, 6), 97, ns=ns, state="pulse")
+    mesh, fo, u, rng = _case((3, 3, 2), (2, 6), 97, ns=ns, state="pulse", per_element=per_element)
     co = fo.copy()
     lo = 1 if isolated else 2
     co[:, :2] = np.maximum(lo, np.minimum(fo[:, :2], rng.integers(1, 6, (len(fo), 2))))
     dudt = _resid(mesh, fo, u)
     R = oracle.project if restriction else oracle.restrict
-    ref = _resid(mesh, co, R(fo, co, u), isolated=isolated) - R(fo, co, dudt)
+    rc = _resid(mesh, co, R(fo, co, u), isolated=isolated)
+    ref = rc - R(fo, co, dudt)
     fine = dg.Plan(mesh, fo)
     coarse = fine.coarse(co)
     tn, tt, norms = dg.tau_estimate(fine, coarse, fine.to_plan(u), None, isolated, restriction=restriction)
-    s = residual_scale(mesh, fo, u)
+    s = np.max(np.abs(rc))  # the coarse residual of which tau is a difference
     assert err(coarse.to_natural(tn), ref, s) < TOL64
     Jc = oracle.metrics(mesh, co).reshape(-1)
     # traditional form: J w w w tau_new with the coarse J of every node
@@ -152,7 +164,7 @@ def test_tau(ns, isolated, restriction):
         J = Jc[10 * offs[e] + 9 * ne: 10 * offs[e] + 10 * ne]
         www.append(np.tile(J * np.einsum("k,j,i->kji", w[2], w[1], w[0]).reshape(-1), 5))
     jw = np.concatenate(www)
-    assert err(coarse.to_natural(tt), ref * jw, s * np.max(jw)) < TOL64
+    assert err(coarse.to_natural(tt), ref * jw, np.max(np.abs(rc * jw))) < TOL64
     nrm = coarse.elem_to_natural(norms.cpu().numpy())
     mx = np.array([np.max(np.abs(ref[5 * offs[e]:5 * offs[e + 1]])) for e in range(len(co))])
     assert err(nrm[:, 0], mx, s) < TOL64
@@ -177,7 +189,7 @@ def test_sweep(curved, ns):
     mesh = wl.sine_mapped(base) if curved else base
     if ns:
         mesh = wl.ns_mesh(mesh, MU, PR)
-    orders = wl.column_orders(mesh, 2, 5, rng, nz_order=2) if curved else wl.random_orders(8, 1, 5, rng)
+    orders = wl.element_orders(mesh, 2, 5, rng, nz_range=(1, 3)) if curved else wl.random_orders(8, 1, 5, rng)
     u = wl.pulse_state(oracle.node_coords(mesh, orders), orders, sigma=0.2)
     u = wl.add_rho_noise(u, orders, rng, 1e-3)
     dudt = _resid(mesh, orders, u)
@@ -189,9 +201,9 @@ def test_sweep(curved, ns):
     ten, tet = dg.tau_sweep(plan, plan.to_plan(u), plan.to_plan(dudt))
     off = plan.combo_offsets()
     nat = lambda t: np.concatenate([t.cpu().numpy()[off[p]:off[p + 1]] for p in np.argsort(plan.perm)])
-    s = residual_scale(mesh, orders, u)
-    assert err(nat(ten), ten_r, s) < TOL64
-    assert err(nat(tet), tet_r, s * np.prod(1.0 / np.asarray(mesh["n"])) / 8) < TOL64
+    sn, st = sweep_scale(mesh, orders, u, ns=(MU, PR) if ns else None)
+    assert err(nat(ten), ten_r, sn) < TOL64
+    assert err(nat(tet), tet_r, st) < TOL64
 
 
 @pytest.mark.slow
@@ -220,6 +232,10 @@ def test_c3_workload_curved():
     tref = _resid(mesh, co, oracle.restrict(orders, co, u), isolated=True) - oracle.restrict(orders, co, dudt)
     coarse = plan.coarse(co)
     tn, _, _ = dg.tau_estimate(plan, coarse, plan.to_plan(u), None, True)
+    # At p = 1/(gamma Ma^2) = 17.9 on curved elements the residuals' own rounding exceeds
+    # 1e-12 of max |r^Nc(Q^c)| (about 85 here): the oracle's residual of the exact free
+    # stream on this mesh, zero in exact arithmetic, is 2.7e-8 (fine) and 9.5e-9 (coarse,
+    # isolated).  The estimate is measured against the cancelling-term scale s instead.
     s = residual_scale(mesh, orders, u)
     assert err(coarse.to_natural(tn), tref, s) < TOL64
     ten, tet = dg.tau_sweep(plan, plan.to_plan(u), plan.to_plan(dudt))

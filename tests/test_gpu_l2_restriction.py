@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from helpers import residual_scale
+from helpers import residual_scale, sweep_scale, tau_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -50,16 +50,22 @@ def test_tau_estimate_l2(shape, orng, seed, bc, isolated):
     eta_r = oracle.tau_eta(mesh, fo, co, u, dudt, psi, isolated=isolated, restriction=oracle.L2)
     fine = dg.Plan(mesh, fo)
     coarse = fine.coarse(co)
-    s = residual_scale(mesh, fo, u)
-    J = np.prod(1.0 / np.asarray(mesh["n"])) / 8
+    sn, st = tau_scale(mesh, fo, co, u, isolated=isolated, restriction=oracle.L2)
     tn, tt, norms, eta = dg.tau_estimate(fine, coarse, fine.to_plan(u), None, isolated, fine.to_plan(psi),
                                          restriction=L2)
-    assert err(coarse.to_natural(tn), tn_r, s) < TOL64
-    assert err(coarse.to_natural(tt), tt_r, s * J) < TOL64
+    assert err(coarse.to_natural(tn), tn_r, sn) < TOL64
+    assert err(coarse.to_natural(tt), tt_r, st) < TOL64
     nrm = coarse.elem_to_natural(norms.cpu().numpy())
-    assert err(nrm[:, 0], n_r[:, 0], s) < TOL64 and err(nrm[:, 1], n_r[:, 1], s * J) < TOL64
+    assert err(nrm[:, 0], n_r[:, 0], sn) < TOL64 and err(nrm[:, 1], n_r[:, 1], st) < TOL64
+    # eta_e sums (I psi) * tau over the element: its rounding scale is the same sum of
+    # |I psi| * |r^Nc| (traditional form)
+    rct = np.abs(oracle.tau(mesh, fo, co, u, np.zeros_like(u), isolated=isolated, restriction=oracle.L2)[1])
+    ip = np.abs(oracle.project(fo, co, psi))
+    offs = wl.node_offsets(co)
+    s_eta = max(float(np.sum(ip[5 * offs[k]:5 * offs[k + 1]] * rct[5 * offs[k]:5 * offs[k + 1]]))
+                for k in range(E))
     e = coarse.elem_to_natural(eta.cpu().numpy())
-    assert np.max(np.abs(e - eta_r)) < 1e-11 * max(np.max(np.abs(eta_r)), s * J)
+    assert np.max(np.abs(e - eta_r)) < 1e-12 * max(np.max(np.abs(eta_r)), s_eta)
     # the sampling estimate on the same inputs is a different result
     tn_s = dg.tau_estimate(fine, coarse, fine.to_plan(u), None, isolated)[0]
     assert float((tn_s - tn).abs().max()) > 1e-6 * float(tn.abs().max())
@@ -80,10 +86,9 @@ def test_sweep_l2(iso):
     ten_r, tet_r, _ = oracle.sweep(mesh, fo, u, dudt, restriction=oracle.L2)
     plan = dg.Plan(mesh, fo)
     ten, tet = dg.tau_sweep(plan, plan.to_plan(u), None, restriction=L2)
-    s = residual_scale(mesh, fo, u)
-    J = np.prod(1.0 / np.asarray(mesh["n"])) / 8
-    assert err(_sweep_natural(plan, ten), ten_r, s) < TOL64
-    assert err(_sweep_natural(plan, tet), tet_r, s * J) < TOL64
+    sn, st = sweep_scale(mesh, fo, u, restriction=oracle.L2)
+    assert err(_sweep_natural(plan, ten), ten_r, sn) < TOL64
+    assert err(_sweep_natural(plan, tet), tet_r, st) < TOL64
 
 
 @pytest.mark.parametrize("ns", [False, True])
@@ -102,9 +107,9 @@ def test_sweep_l2_curved(ns):
         ten_r, tet_r, _ = oracle.sweep(mesh, fo, u, dudt, restriction=oracle.L2)
     plan = dg.Plan(mesh, fo)
     ten, tet = dg.tau_sweep(plan, plan.to_plan(u), plan.to_plan(dudt), restriction=L2)
-    s = residual_scale(mesh, fo, u)
-    assert err(_sweep_natural(plan, ten), ten_r, s) < TOL64
-    assert err(_sweep_natural(plan, tet), tet_r, s / 64) < TOL64
+    sn, st = sweep_scale(mesh, fo, u, restriction=oracle.L2, ns=(0.01, 0.72) if ns else None)
+    assert err(_sweep_natural(plan, ten), ten_r, sn) < TOL64
+    assert err(_sweep_natural(plan, tet), tet_r, st) < TOL64
 
 
 @pytest.mark.slow
@@ -116,20 +121,21 @@ def test_c2_workload_l2_sampled():
     u, co = wl.c2_state_and_coarse(oracle.node_coords(mesh, fo), mesh, fo)
     plan = dg.Plan(mesh, fo)
     ud = plan.to_plan(u)
-    s = residual_scale(mesh, fo, u)
     dudt = oracle.residual(mesh, fo, u)
     r = dg.residual(plan, ud)
     cp = plan.coarse(co)
     tn, _, norms = dg.tau_estimate(plan, cp, ud, r, restriction=L2)
     tn_r, _, n_r, _ = oracle.tau(mesh, fo, co, u, dudt, restriction=oracle.L2)
-    assert err(cp.to_natural(tn), tn_r, s) < TOL64
-    assert err(cp.elem_to_natural(norms.cpu().numpy())[:, 0], n_r[:, 0], s) < TOL64
+    sn, _ = tau_scale(mesh, fo, co, u, restriction=oracle.L2)
+    assert err(cp.to_natural(tn), tn_r, sn) < TOL64
+    assert err(cp.elem_to_natural(norms.cpu().numpy())[:, 0], n_r[:, 0], sn) < TOL64
     ten, _ = dg.tau_sweep(plan, ud, r, restriction=L2)
     sample = np.sort(np.random.default_rng(100).choice(4096, 16, replace=False))
     ten_r, _, _ = oracle.sweep(mesh, fo, u, dudt, elems=sample, restriction=oracle.L2)
+    sn, _ = sweep_scale(mesh, fo, u, elems=sample, restriction=oracle.L2)
     full = _sweep_natural(plan, ten)
     got = np.concatenate([full[216 * e:216 * (e + 1)] for e in sample])
-    assert err(got, ten_r, s) < TOL64
+    assert err(got, ten_r, sn) < TOL64
 
 
 def test_invalid_restriction():

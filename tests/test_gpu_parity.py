@@ -1,15 +1,17 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle, element by element.
 
-Tolerance (FP64): max |x - x_oracle| <= 1e-12 * max(max |x_oracle|, s), with s the scale
-of the cancelling terms of the residual (largest |f| * |Ja| * ||D|| / J).  FP32 state
-and arithmetic: 1e-5 on the same measure.  Integer layout data must match exactly.
+Tolerance (FP64): max |x - x_oracle| <= 1e-12 * max(max |x_oracle|, s).  For residuals s
+is the scale of their cancelling terms (largest |f| * |Ja| * ||D|| / J); for tau-estimates
+and the sweep's maps s is max |r^Nc(Q^c)|, the size of the coarse residual of the
+restricted state, of which the estimate is a difference (same form as the output).  FP32
+state and arithmetic: 1e-5 on the same measure.  Integer layout data must match exactly.
 """
 import numpy as np
 import pytest
 
 import oracle
 import workloads as wl
-from helpers import residual_scale
+from helpers import residual_scale, sweep_scale, tau_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -108,16 +110,15 @@ def test_tau_estimate(shape, orng, seed, bc, flux, box, isolated):
     coarse = fine.coarse(co)
     dudt = oracle.residual(mesh, fo, u)
     tn_r, tt_r, n_r, _ = oracle.tau(mesh, fo, co, u, dudt, isolated=isolated)
-    s = residual_scale(mesh, fo, u)
+    sn, st = tau_scale(mesh, fo, co, u, isolated=isolated)
     ud = fine.to_plan(u)
     for pass_dudt in (False, True):
         tn, tt, norms = dg.tau_estimate(fine, coarse, ud, fine.to_plan(dudt) if pass_dudt else None,
                                         isolated=isolated)
-        assert err(coarse.to_natural(tn), tn_r, s) < TOL64
-        J = np.prod((np.asarray(mesh["hi"]) - np.asarray(mesh["lo"])) / np.asarray(mesh["n"])) / 8
-        assert err(coarse.to_natural(tt), tt_r, s * J) < TOL64
+        assert err(coarse.to_natural(tn), tn_r, sn) < TOL64
+        assert err(coarse.to_natural(tt), tt_r, st) < TOL64
         nrm = coarse.elem_to_natural(norms.cpu().numpy())
-        assert err(nrm[:, 0], n_r[:, 0], s) < TOL64 and err(nrm[:, 1], n_r[:, 1], s * J) < TOL64
+        assert err(nrm[:, 0], n_r[:, 0], sn) < TOL64 and err(nrm[:, 1], n_r[:, 1], st) < TOL64
 
 
 def test_tau_vanishes_at_fine_orders():
@@ -146,13 +147,12 @@ def test_sweep(shape, orng, seed):
     ten_r, tet_r, offs = oracle.sweep(mesh, fo, u, dudt)
     ud = plan.to_plan(u)
     ten, tet = dg.tau_sweep(plan, ud, plan.to_plan(dudt))
-    s = residual_scale(mesh, fo, u)
-    J = np.prod(1.0 / np.asarray(mesh["n"])) / 8
-    assert err(_sweep_natural(plan, ten), ten_r, s) < TOL64
-    assert err(_sweep_natural(plan, tet), tet_r, s * J) < TOL64
+    sn, st = sweep_scale(mesh, fo, u)
+    assert err(_sweep_natural(plan, ten), ten_r, sn) < TOL64
+    assert err(_sweep_natural(plan, tet), tet_r, st) < TOL64
     # dudt computed inside the call gives the same map
     ten2, _ = dg.tau_sweep(plan, ud)
-    assert err(_sweep_natural(plan, ten2), ten_r, s) < TOL64
+    assert err(_sweep_natural(plan, ten2), ten_r, sn) < TOL64
 
 
 def test_sweep_isotropic_fast_path():
@@ -168,10 +168,9 @@ def test_sweep_isotropic_fast_path():
     ten_r, tet_r, offs = oracle.sweep(mesh, fo, u, dudt)
     plan = dg.Plan(mesh, fo)
     ten, tet = dg.tau_sweep(plan, plan.to_plan(u), plan.to_plan(dudt))
-    s = residual_scale(mesh, fo, u)
-    J = np.prod(1.0 / np.asarray(mesh["n"])) / 8
-    assert err(_sweep_natural(plan, ten), ten_r, s) < TOL64
-    assert err(_sweep_natural(plan, tet), tet_r, s * J) < TOL64
+    sn, st = sweep_scale(mesh, fo, u)
+    assert err(_sweep_natural(plan, ten), ten_r, sn) < TOL64
+    assert err(_sweep_natural(plan, tet), tet_r, st) < TOL64
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
@@ -208,7 +207,9 @@ def test_c1_workload():
         for iso in (False, True):
             tn, _, norms = dg.tau_estimate(plan, cp, ud, isolated=iso)
             tn_r, _, n_r, _ = oracle.tau(mesh, fo, co, u, dudt, isolated=iso)
-            assert err(cp.to_natural(tn), tn_r, s) < TOL64
+            sn, _ = tau_scale(mesh, fo, co, u, isolated=iso)
+            assert err(cp.to_natural(tn), tn_r, sn) < TOL64
+            assert err(cp.elem_to_natural(norms.cpu().numpy())[:, 0], n_r[:, 0], sn) < TOL64
     g = torch.empty_like(ud)
     dg.rk3_step(plan, ud, g, 1e-3, 10)
     ref = oracle.rk3(mesh, fo, u, 1e-3, 10)
@@ -232,15 +233,21 @@ def test_c2_workload_sampled():
     cp = plan.coarse(co)
     tn, tt, norms = dg.tau_estimate(plan, cp, ud, r)
     tn_r, tt_r, n_r, _ = oracle.tau(mesh, fo, co, u, dudt)
-    assert err(cp.to_natural(tn), tn_r, s) < TOL64
-    assert err(cp.elem_to_natural(norms.cpu().numpy())[:, 0], n_r[:, 0], s) < TOL64
+    sn, st = tau_scale(mesh, fo, co, u)
+    assert err(cp.to_natural(tn), tn_r, sn) < TOL64
+    assert err(cp.to_natural(tt), tt_r, st) < TOL64
+    assert err(cp.elem_to_natural(norms.cpu().numpy())[:, 0], n_r[:, 0], sn) < TOL64
     ten, tet = dg.tau_sweep(plan, ud, r)
     rng = np.random.default_rng(99)
     sample = np.sort(rng.choice(4096, 24, replace=False))
     ten_r, tet_r, offs = oracle.sweep(mesh, fo, u, dudt, elems=sample)
+    sn, st = sweep_scale(mesh, fo, u, elems=sample)
     full = _sweep_natural(plan, ten)
     got = np.concatenate([full[216 * e:216 * (e + 1)] for e in sample])
-    assert err(got, ten_r, s) < TOL64
+    assert err(got, ten_r, sn) < TOL64
+    full = _sweep_natural(plan, tet)
+    got = np.concatenate([full[216 * e:216 * (e + 1)] for e in sample])
+    assert err(got, tet_r, st) < TOL64
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])

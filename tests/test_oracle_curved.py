@@ -108,12 +108,21 @@ def test_volume_and_metric_identities():
     assert abs(vol - box) < 1e-14
 
 
+def _draw(mesh, lo, hi, rng, per_element):
+    """Per-column orders (conforming faces between layers) or per-element orders with
+    Nz in 1..2 (non-conforming faces in every direction)."""
+    if per_element:
+        return wl.element_orders(mesh, lo, hi, rng, nz_range=(1, 2))
+    return wl.column_orders(mesh, lo, hi, rng)
+
+
+@pytest.mark.parametrize("per_element", [False, True])
 @pytest.mark.parametrize("flux,bc", [(wl.ROE, (0,) * 6), (wl.LF, (0,) * 6), (wl.ROE, (2, 2, 0, 0, 0, 0))])
-def test_free_stream(flux, bc):
+def test_free_stream(flux, bc, per_element):
     q = wl.conserved(*(np.array(v) for v in (1.1, 0.3, -0.2, 0.1, 0.9)))
     mesh = _mesh((3, 3, 2), bc=bc, flux=flux, qfar=tuple(float(v) for v in q))
     rng = np.random.default_rng(82)
-    orders = wl.column_orders(mesh, 2, 6, rng)
+    orders = _draw(mesh, 2, 6, rng, per_element)
     u = wl.uniform_state(orders, q)
     s = residual_scale(mesh, orders, u)
     assert np.max(np.abs(oracle.residual(mesh, orders, u))) < 1e-13 * s
@@ -123,10 +132,11 @@ def test_free_stream(flux, bc):
     assert np.max(np.abs(oracle.residual_ns(mesh, orders, u, MU, PR))) < 1e-13 * s
 
 
-def test_conservation():
+@pytest.mark.parametrize("per_element", [False, True])
+def test_conservation(per_element):
     mesh = _mesh((3, 3, 2))
     rng = np.random.default_rng(83)
-    orders = wl.column_orders(mesh, 2, 6, rng)
+    orders = _draw(mesh, 2, 6, rng, per_element)
     u = wl.random_state(orders, rng)
     met = oracle.metrics(mesh, orders)
     Jn = np.concatenate([elem_view(met, orders, e, nv=10)[9] for e in range(len(orders))])

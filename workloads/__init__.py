@@ -57,6 +57,17 @@ def column_orders(mesh, lo: int, hi: int, rng, nz_order: int = 1) -> np.ndarray:
     return orders
 
 
+def element_orders(mesh, lo: int, hi: int, rng, nz_range=(1, 1)) -> np.ndarray:
+    """Orders (Nx, Ny) drawn i.i.d. uniform in {lo..hi} per element, then Nz uniform in
+    nz_range per element (a fixed Nz = 1 draws nothing more)."""
+    E = num_elems(mesh)
+    orders = np.full((E, 3), nz_range[0], dtype=np.int32)
+    orders[:, :2] = rng.integers(lo, hi + 1, (E, 2))
+    if nz_range[1] > nz_range[0]:
+        orders[:, 2] = rng.integers(nz_range[0], nz_range[1] + 1, E)
+    return orders
+
+
 def num_elems(mesh) -> int:
     n = mesh["n"]
     return int(n[0] * n[1] * n[2])
@@ -243,14 +254,14 @@ def c3(seed: int = 3, n=(32, 32, 2), Re: float = 100.0, Ma: float = 0.2, Pr: flo
        curved: bool = True):
     """Navier-Stokes, Re = 100, Ma = 0.2, Pr = 0.72 on [0,1]^2 x [0, 1/16] (32 x 32 x 2 cubes)
     under the sine map of amplitude 0.05 (geometry order (2, 2, 1)), periodic; orders
-    (Nx, Ny) drawn U{2..6} per element column (both layers of a column share them, so
-    the faces between layers are conforming), Nz = 1.  Nondimensional with rho = 1,
-    |u| = 1, L = 1: mu = 1/Re, p = 1/(gamma Ma^2).  Returns (mesh, orders, rng)."""
+    (Nx, Ny) drawn U{2..6} per element (the faces between the two layers are
+    non-conforming where the layers' orders differ), Nz = 1.  Nondimensional with
+    rho = 1, |u| = 1, L = 1: mu = 1/Re, p = 1/(gamma Ma^2).  Returns (mesh, orders, rng)."""
     rng = np.random.default_rng(seed)
     mesh = ns_mesh(box_mesh(n, hi=(1.0, 1.0, n[2] / n[0])), mu=1.0 / Re, Pr=Pr)
     if curved:
         mesh = sine_mapped(mesh)
-    orders = column_orders(mesh, 2, 6, rng)
+    orders = element_orders(mesh, 2, 6, rng)
     mesh["p_inf"] = 1.0 / (GAMMA * Ma * Ma)
     return mesh, orders, rng
 
