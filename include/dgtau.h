@@ -14,7 +14,11 @@
  *     are marked "host".  Device arrays must be 16-byte aligned (every hipMalloc
  *     or torch allocation is); a misaligned one returns DG_EINVAL.  Compute calls
  *     are asynchronous on the given stream (NULL = the legacy default stream) and
- *     allocate no memory.
+ *     allocate no device memory.  The exception is the first RK3 call with a new
+ *     (u, g, dt) pointer set: it captures and instantiates a HIP graph (host-side
+ *     runtime allocations); each plan and batch keeps at most 8 such graphs and
+ *     destroys the least recently used one, after a device synchronisation, to
+ *     make room.
  *   - Plans own only their internal device buffers (tables, tiles, face lists,
  *     face-flux and tau scratch).  A plan is immutable after creation; because
  *     it holds scratch buffers, one plan must not be used by two streams at once.
@@ -176,7 +180,7 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
  * prod_d max(1, N_d - 1); combo_offset[E+1] (host) gets their prefix sums. */
 dg_status dg_sweep_layout(dg_plan fine, int64_t *combo_offset);
 
-/* Isolated anisotropic truncation-error map (Section 2.3 and Section 3,
+/* Isolated anisotropic truncation-error map (Section 2.3 and Section 2.4.2,
  * approach 2): for every fine plan element and every coarse combination
  * (c1, c2, c3), c_d in 1..max(1, N_d - 1), enumerated c1 fastest, the maxima
  * over nodes and variables of |tau_new| and |tau_trad| of the isolated estimate
@@ -346,7 +350,7 @@ dg_status dg_adjoint_solve(dg_plan plan, const double *u, const double *g, doubl
  *   dJ/du (zero away from the wall nodes).  Deterministic reduction. */
 dg_status dg_functional(dg_plan plan, const double *u, double *J, double *dJdu, hipStream_t stream);
 
-/* nsteps steps of Williamson's low-storage RK3 (Section 4 set-up):
+/* nsteps steps of Williamson's low-storage RK3 (set-up of Section 3):
  * for k = 0,1,2:  g = A_k g - dt * r(u);  u = u + B_k g,
  * A = (0, -5/9, -153/128), B = (1/3, 15/16, 8/15), r = dg_residual new form.
  *   u, g: device arrays (dtype) of 5*n_nodes values, updated in place; g is
@@ -366,13 +370,16 @@ dg_status dg_rk3_step(dg_plan plan, void *u, void *g, double dt, int32_t nsteps,
  * face counts and the element count of every order triple): a later batch of the
  * same composition takes the cached schedule without timing.  The plans must
  * outlive the batch and must not be used on another stream while the batch runs
- * (their face-flux scratch is shared).
+ * (their face-flux scratch is shared); for the same reason a plan may appear only
+ * once in a batch (problems on the same mesh each need a plan of their own).
  * ------------------------------------------------------------------------- */
 typedef struct dg_batch_s *dg_batch;
 
 /* plans: host array of n plans with orders <= 7; dtype DG_F64 or DG_F32 fixes the
  * state type of every later call.  Allocates and frees scratch for the schedule
- * search.  Errors: DG_EINVAL, DG_EUNSUPPORTED (order > 7), DG_ENOMEM, DG_EHIP. */
+ * search, and allocates the problem-descriptor slots later calls use.  Errors:
+ * DG_EINVAL (null or repeated plan handle, checked before any plan is read),
+ * DG_EUNSUPPORTED (order > 7), DG_ENOMEM, DG_EHIP. */
 dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_batch *out);
 dg_status dg_batch_destroy(dg_batch batch);
 /* The schedule the autotuner chose (host outputs, any may be NULL): tile capacity in
@@ -381,8 +388,23 @@ dg_status dg_batch_destroy(dg_batch batch);
 dg_status dg_batch_schedule(dg_batch batch, int32_t *tile_cap, int32_t *elem_grid, int32_t *face_grid,
                             int32_t *shape, int32_t *from_cache);
 /* New-form residual of every problem (Section 2.1): u[i], r[i] device arrays of
- * problem i in its plan layout (host arrays of n device pointers). */
+ * problem i in its plan layout (host arrays of n device pointers).  The pointer
+ * arrays are staged through a ring of four pinned descriptor slots; the call
+ * blocks only when the call four before it has not yet finished on the device. */
 dg_status dg_batch_residual(dg_batch batch, const void *const *u, void *const *r, hipStream_t stream);
+/* Every problem's state in FP64 for the truncation-error estimate (Section 2.3; the
+ * estimate is a difference of two nearly equal residuals and is formed in double
+ * precision whatever precision the time stepping uses): u[i] in the batch's dtype,
+ * u64[i] device double[5 n_nodes(i)] (plan layout, caller-owned, not overlapping u[i]).
+ * An FP32 batch promotes (exactly) with one launch per problem; an FP64 batch copies. */
+dg_status dg_batch_to_f64(dg_batch batch, const void *const *u, double *const *u64, hipStream_t stream);
+/* FP64 isolated truncation-error map of every problem (as dg_tau_sweep with dudt =
+ * NULL: each problem's FP64 non-isolated fine residual is computed first, into its
+ * plan's scratch), problem after problem on the stream.  u64[i] as produced by
+ * dg_batch_to_f64; te_new[i], te_trad[i] device double[combo_offset[E_i]] of problem
+ * i's sweep layout (dg_sweep_layout).  Errors as dg_tau_sweep. */
+dg_status dg_batch_tau_sweep(dg_batch batch, const double *const *u64, int32_t restriction,
+                             double *const *te_new, double *const *te_trad, hipStream_t stream);
 /* nsteps Williamson RK3 steps of every problem (as dg_rk3_step), in place on u[i],
  * g[i] scratch; one step is captured once per (u, g, dt) pointer set into a HIP graph
  * of three stages, each one persistent face launch and one persistent element launch. */

@@ -88,6 +88,8 @@ SIGNATURES = {
     "dg_batch_schedule": [_P, _I32P, _I32P, _I32P, _I32P, _I32P],
     "dg_batch_residual": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P],
     "dg_batch_rk3_step": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_double, ctypes.c_int32, _P],
+    "dg_batch_to_f64": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P],
+    "dg_batch_tau_sweep": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P), _P],
 }
 
 
@@ -557,3 +559,36 @@ def batch_residual(batch: Batch, us, rs=None):
 def batch_rk3_step(batch: Batch, us, gs, dt: float, nsteps: int = 1):
     _call("dg_batch_rk3_step", batch.handle, batch._ptrs(us), batch._ptrs(gs), float(dt), int(nsteps), _stream())
     return us
+
+
+def batch_to_f64(batch: Batch, us, u64=None):
+    """Every problem's state in float64 (promoted exactly from a float32 batch)."""
+    torch = _torch()
+    u64 = [torch.empty(u.numel(), dtype=torch.float64, device="cuda") for u in us] if u64 is None else u64
+    for t, p in zip(u64, batch.plans):
+        if t.dtype != torch.float64 or t.numel() != 5 * p.n_nodes:
+            raise DGError("u64 tensors must be float64 and match their plans")
+    arr = (_P * len(u64))(*[t.data_ptr() for t in u64])
+    _call("dg_batch_to_f64", batch.handle, batch._ptrs(us), arr, _stream())
+    return u64
+
+
+def batch_tau_sweep(batch: Batch, u64, restriction: int = RESTRICT_SAMPLE):
+    """FP64 isolated truncation-error maps of every problem: [(te_new, te_trad)] per
+    problem in its sweep layout."""
+    torch = _torch()
+    if len(u64) != len(batch.plans):
+        raise DGError("one state per problem expected")
+    maps = []
+    for t, p in zip(u64, batch.plans):
+        if t.dtype != torch.float64 or t.numel() != 5 * p.n_nodes:
+            raise DGError("u64 tensors must be float64 and match their plans")
+        n = int(p.combo_offsets()[-1])
+        maps.append((torch.empty(n, dtype=torch.float64, device="cuda"),
+                     torch.empty(n, dtype=torch.float64, device="cuda")))
+    n = len(u64)
+    ua = (_P * n)(*[t.data_ptr() for t in u64])
+    na = (_P * n)(*[m[0].data_ptr() for m in maps])
+    ta = (_P * n)(*[m[1].data_ptr() for m in maps])
+    _call("dg_batch_tau_sweep", batch.handle, ua, int(restriction), na, ta, _stream())
+    return maps

@@ -12,7 +12,7 @@ OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libdgtau.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "tables.cpp", "k_residual.hip", "k_tau.hip", "k_vjp.hip", "k_curved.hip", "k_select.hip", "k_dual.hip", "k_krylov.hip"]
+SOURCES = ["api.cpp", "tables.cpp", "k_residual.hip", "k_tau.hip", "k_vjp.hip", "k_curved.hip", "k_select.hip", "k_dual.hip", "k_krylov.hip", "k_convert.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]

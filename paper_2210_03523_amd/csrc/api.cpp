@@ -69,6 +69,18 @@ struct TileClass {
     int npt, first, count;
 };
 
+// RK3 graphs kept per plan and per batch; the least recently used one is destroyed
+// (after a device synchronisation, so no launch of it is in flight) to make room.
+constexpr size_t kGraphCache = 8;
+
+template <typename Map>
+typename Map::iterator lru_victim(Map &m) {
+    auto v = m.begin();
+    for (auto it = m.begin(); it != m.end(); ++it)
+        if (it->second.second < v->second.second) v = it;
+    return v;
+}
+
 struct GraphKey {
     void *u, *g;
     double dt;
@@ -133,9 +145,10 @@ struct dg_plan_s {
     int32_t *d_inv = nullptr;           // natural element -> plan position
     double *d_red = nullptr;            // reduction partials of dg_check_state
     int iso_first[NNMAX + 1] = {0}, iso_count[NNMAX + 1] = {0};
-    // RK3 graphs
+    // RK3 graphs: at most kGraphCache, each with the call count of its last use
     hipStream_t cap_stream = nullptr;
-    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::map<GraphKey, std::pair<hipGraphExec_t, uint64_t>> graphs;
+    uint64_t graph_clock = 0;
 };
 
 namespace {
@@ -150,7 +163,7 @@ dg_status upload(T **dst, const std::vector<T> &src) {
 
 void destroy_plan(dg_plan p) {
     if (!p) return;
-    for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second.first);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     void *bufs[] = {p->d_el,    p->d_faces,  p->d_tiles,  p->d_ff,     p->d_dudt,   p->d_fine_of, p->d_uc,
                     p->d_rdc,   p->d_psic,   p->d_combo_off, p->d_tasks, p->d_iso,  p->d_wallx,   p->d_part,
@@ -898,6 +911,12 @@ dg_status dg_rk3_step(dg_plan p, void *u, void *g, double dt, int32_t nsteps, in
     GraphKey key{u, g, dt, dtype};
     auto it = p->graphs.find(key);
     if (it == p->graphs.end()) {
+        if (p->graphs.size() >= kGraphCache) {
+            HIP_TRY(hipDeviceSynchronize());
+            auto v = lru_victim(p->graphs);
+            (void)hipGraphExecDestroy(v->second.first);
+            p->graphs.erase(v);
+        }
         hipGraph_t graph;
         HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
         dg_status st = DG_OK;
@@ -918,9 +937,10 @@ dg_status dg_rk3_step(dg_plan p, void *u, void *g, double dt, int32_t nsteps, in
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(DG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-        it = p->graphs.emplace(key, exec).first;
+        it = p->graphs.emplace(key, std::make_pair(exec, uint64_t(0))).first;
     }
-    for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(it->second, stream));
+    it->second.second = ++p->graph_clock;
+    for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(it->second.first, stream));
     return DG_OK;
 }
 
@@ -1110,6 +1130,9 @@ const char *dg_last_error(void) { return g_err.c_str(); }
 
 namespace {
 
+constexpr int kEagerRing = 4;
+static_assert(sizeof(ProbDesc<double>) == sizeof(ProbDesc<float>), "one descriptor size for both precisions");
+
 struct BatchKey {
     std::vector<void *> u, g;
     double dt;
@@ -1128,23 +1151,39 @@ struct dg_batch_s {
     BatchFace *d_faces = nullptr;
     std::vector<std::vector<ElemInfo>> hel;  // element descriptors of every plan (host copies)
     hipStream_t cap_stream = nullptr;
-    std::map<BatchKey, std::pair<void *, hipGraphExec_t>> graphs;  // ProbDesc array + graph
-    void *d_probs_eager = nullptr;                                    // ProbDesc array of eager calls
+    // Problem-descriptor arrays, allocated at creation: kGraphCache slots for the RK3
+    // graphs, then kEagerRing slots for eager residual calls, staged from pinned host
+    // memory; a ring slot is reused once the event recorded after its last use is done.
+    void *d_desc = nullptr;
+    void *h_desc = nullptr;
+    hipEvent_t ring_ev[kEagerRing] = {};
+    bool ring_used[kEagerRing] = {};
+    int ring_next = 0;
+    // RK3 graphs: key -> (descriptor slot, graph, call count of the last use)
+    struct Graph {
+        int slot;
+        hipGraphExec_t exec;
+        uint64_t last;
+    };
+    std::map<BatchKey, Graph> graphs;
+    uint64_t graph_clock = 0;
     bool from_cache = false;  // schedule taken from the autotuner's cache
+    size_t desc_bytes() const { return sizeof(ProbDesc<double>) * plans.size(); }
+    void *desc_slot(int k) const { return (char *)d_desc + desc_bytes() * k; }
 };
 
 namespace {
 
 void destroy_batch(dg_batch b) {
     if (!b) return;
-    for (auto &kv : b->graphs) {
-        (void)hipGraphExecDestroy(kv.second.second);
-        (void)hipFree(kv.second.first);
-    }
+    for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+    for (hipEvent_t e : b->ring_ev)
+        if (e) (void)hipEventDestroy(e);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->d_faces) (void)hipFree(b->d_faces);
-    if (b->d_probs_eager) (void)hipFree(b->d_probs_eager);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
     delete b;
 }
 
@@ -1323,8 +1362,15 @@ extern "C" {
 dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_batch *out) {
     if (!plans || n <= 0 || !out) return fail(DG_EINVAL, "null argument or empty batch");
     if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_EINVAL, "unknown dtype");
+    // handles first (no plan is read before every handle is known to be distinct)
     for (int i = 0; i < n; ++i) {
         if (!plans[i]) return fail(DG_EINVAL, "null plan in batch");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i])
+                return fail(DG_EINVAL, "a plan appears twice in the batch (each problem needs its own plan: "
+                                       "the plan's face-flux scratch is written by the batched launches)");
+    }
+    for (int i = 0; i < n; ++i) {
         if (plans[i]->max_order > 7) return fail(DG_EUNSUPPORTED, "batched launches support orders up to 7");
         if (plans[i]->ns) return fail(DG_EUNSUPPORTED, "batched launches run the Euler equations");
         if (plans[i]->curved) return fail(DG_EUNSUPPORTED, "batched launches run box elements");
@@ -1384,8 +1430,12 @@ dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_bat
             }
         }
     }
-    if (!st && hipMalloc(&b->d_probs_eager, sizeof(ProbDesc<double>) * n) != hipSuccess)
-        st = fail(DG_ENOMEM, "device allocation failed");
+    if (!st && (hipMalloc(&b->d_desc, b->desc_bytes() * (kGraphCache + kEagerRing)) != hipSuccess ||
+                hipHostMalloc(&b->h_desc, b->desc_bytes() * kEagerRing, hipHostMallocDefault) != hipSuccess))
+        st = fail(DG_ENOMEM, "device or pinned host allocation failed");
+    for (int k = 0; k < kEagerRing && !st; ++k)
+        if (hipEventCreateWithFlags(&b->ring_ev[k], hipEventDisableTiming) != hipSuccess)
+            st = fail(DG_EHIP, "event creation failed");
     if (st) {
         destroy_batch(b);
         return st;
@@ -1417,17 +1467,55 @@ dg_status dg_batch_residual(dg_batch b, const void *const *u, void *const *r, hi
             return fail(DG_EINVAL, "bad state or residual pointer (null, shared or not 16-byte aligned)");
     EpiArgs epi{};
     epi.mode = EPI_RESIDUAL;
-    // the descriptor array is written with an ordered copy on the same stream
+    // descriptors staged through the next ring slot (pinned host -> device, ordered on
+    // the stream); the slot's previous use must have finished first
+    const int k = b->ring_next;
+    b->ring_next = (k + 1) % kEagerRing;
+    if (b->ring_used[k]) HIP_TRY(hipEventSynchronize(b->ring_ev[k]));
+    void *hs = (char *)b->h_desc + b->desc_bytes() * k;
+    void *ds = b->desc_slot((int)kGraphCache + k);
     if (b->dtype == DG_F64) {
         auto pd = prob_descs<double>(b, (void *const *)u, r, nullptr);
-        HIP_TRY(hipMemcpyAsync(b->d_probs_eager, pd.data(), sizeof(pd[0]) * pd.size(), hipMemcpyHostToDevice, stream));
-        HIP_TRY(hipStreamSynchronize(stream));
-        return batch_pass<double>(b, (const ProbDesc<double> *)b->d_probs_eager, epi, stream);
+        memcpy(hs, pd.data(), b->desc_bytes());
+    } else {
+        auto pd = prob_descs<float>(b, (void *const *)u, r, nullptr);
+        memcpy(hs, pd.data(), b->desc_bytes());
     }
-    auto pd = prob_descs<float>(b, (void *const *)u, r, nullptr);
-    HIP_TRY(hipMemcpyAsync(b->d_probs_eager, pd.data(), sizeof(pd[0]) * pd.size(), hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-    return batch_pass<float>(b, (const ProbDesc<float> *)b->d_probs_eager, epi, stream);
+    HIP_TRY(hipMemcpyAsync(ds, hs, b->desc_bytes(), hipMemcpyHostToDevice, stream));
+    const dg_status st = b->dtype == DG_F64 ? batch_pass<double>(b, (const ProbDesc<double> *)ds, epi, stream)
+                                            : batch_pass<float>(b, (const ProbDesc<float> *)ds, epi, stream);
+    HIP_TRY(hipEventRecord(b->ring_ev[k], stream));
+    b->ring_used[k] = true;
+    return st;
+}
+
+dg_status dg_batch_to_f64(dg_batch b, const void *const *u, double *const *u64, hipStream_t stream) {
+    if (!b || !u || !u64) return fail(DG_EINVAL, "null argument");
+    for (size_t i = 0; i < b->plans.size(); ++i)
+        if (!u[i] || !u64[i] || !aligned(u[i]) || !aligned(u64[i]) || u[i] == (const void *)u64[i])
+            return fail(DG_EINVAL, "bad state pointer (null, shared or not 16-byte aligned)");
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        const int64_t n = NV * b->plans[i]->n_nodes;
+        if (b->dtype == DG_F32)
+            HIP_TRY(launch_promote((const float *)u[i], u64[i], n, stream));
+        else
+            HIP_TRY(hipMemcpyAsync(u64[i], u[i], sizeof(double) * n, hipMemcpyDeviceToDevice, stream));
+    }
+    return DG_OK;
+}
+
+dg_status dg_batch_tau_sweep(dg_batch b, const double *const *u64, int32_t restriction, double *const *te_new,
+                             double *const *te_trad, hipStream_t stream) {
+    if (!b || !u64 || !te_new || !te_trad) return fail(DG_EINVAL, "null argument");
+    for (size_t i = 0; i < b->plans.size(); ++i)
+        if (!u64[i] || !te_new[i] || !te_trad[i]) return fail(DG_EINVAL, "null state or map pointer");
+    // one problem after the other: the FP64 fine residual of each problem (into its
+    // plan's time-derivative scratch), then its isolated sweep
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        const dg_status st = dg_tau_sweep(b->plans[i], u64[i], nullptr, restriction, te_new[i], te_trad[i], stream);
+        if (st) return st;
+    }
+    return DG_OK;
 }
 
 dg_status dg_batch_rk3_step(dg_batch b, void *const *u, void *const *g, double dt, int32_t nsteps,
@@ -1444,16 +1532,27 @@ dg_status dg_batch_rk3_step(dg_batch b, void *const *u, void *const *g, double d
     BatchKey key{std::vector<void *>(u, u + n), std::vector<void *>(g, g + n), dt};
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
-        void *dpd = nullptr;
-        dg_status st;
+        if (b->graphs.size() >= kGraphCache) {
+            HIP_TRY(hipDeviceSynchronize());
+            auto v = b->graphs.begin();
+            for (auto j = b->graphs.begin(); j != b->graphs.end(); ++j)
+                if (j->second.last < v->second.last) v = j;
+            (void)hipGraphExecDestroy(v->second.exec);
+            b->graphs.erase(v);
+        }
+        bool taken[kGraphCache] = {};
+        for (const auto &kv : b->graphs) taken[kv.second.slot] = true;
+        int slot = 0;
+        while (taken[slot]) ++slot;
+        void *dpd = b->desc_slot(slot);
         if (b->dtype == DG_F64) {
             auto pd = prob_descs<double>(b, u, nullptr, g);
-            st = upload((ProbDesc<double> **)&dpd, pd);
+            HIP_TRY(hipMemcpy(dpd, pd.data(), b->desc_bytes(), hipMemcpyHostToDevice));
         } else {
             auto pd = prob_descs<float>(b, u, nullptr, g);
-            st = upload((ProbDesc<float> **)&dpd, pd);
+            HIP_TRY(hipMemcpy(dpd, pd.data(), b->desc_bytes(), hipMemcpyHostToDevice));
         }
-        if (st) return st;
+        dg_status st = DG_OK;
         hipGraph_t graph;
         HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < 3 && !st; ++k) {
@@ -1466,20 +1565,15 @@ dg_status dg_batch_rk3_step(dg_batch b, void *const *u, void *const *g, double d
                                     : batch_pass<float>(b, (const ProbDesc<float> *)dpd, epi, b->cap_stream);
         }
         hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
-        if (st || e != hipSuccess) {
-            (void)hipFree(dpd);
-            return st ? st : fail(DG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-        }
+        if (st || e != hipSuccess) return st ? st : fail(DG_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
         hipGraphExec_t exec;
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            (void)hipFree(dpd);
-            return fail(DG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-        }
-        it = b->graphs.emplace(key, std::make_pair(dpd, exec)).first;
+        if (e != hipSuccess) return fail(DG_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        it = b->graphs.emplace(key, dg_batch_s::Graph{slot, exec, 0}).first;
     }
-    for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(it->second.second, stream));
+    it->second.last = ++b->graph_clock;
+    for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(it->second.exec, stream));
     return DG_OK;
 }
 

@@ -187,6 +187,7 @@ hipError_t launch_count_bad(const ElemInfo *el, int E, const T *u, double gamma,
                             hipStream_t s);
 // dudt = -(1/dt) sum_j b_j states[j], backward difference of order nst-1 (nst in 2..4)
 hipError_t launch_bdf_rate(const double *const *states, int nst, double dt, int64_t n, double *dudt, hipStream_t s);
+hipError_t launch_promote(const float *in, double *out, int64_t n, hipStream_t s);
 hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
                             const double *u, const double *dudt, const double *tab, Geom g, double gamma,
                             int restriction, double *te_new, double *te_trad, hipStream_t s);

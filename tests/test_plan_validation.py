@@ -55,3 +55,16 @@ def test_curved_orders_below_the_geometry_order():
     o[5, 0] = 1  # geometry order (2, 2, 1)
     with pytest.raises(dg.DGError, match="geometry order"):
         dg.Plan(m, o)
+
+
+def test_batch_refuses_a_repeated_plan_handle():
+    """Two problems of a batch may not share a plan (its face-flux scratch would be
+    written by both): the handles are compared before any plan is read, so two copies
+    of one (never dereferenced) handle value are refused on the host."""
+    import ctypes
+    fake = ctypes.c_void_p(0x1000)
+    arr = (ctypes.c_void_p * 2)(fake.value, fake.value)
+    out = ctypes.c_void_p()
+    st = dg.lib().dg_batch_create(arr, 2, dg.DG_F32, ctypes.byref(out))
+    assert st == -1
+    assert b"appears twice" in dg.lib().dg_last_error()
