@@ -61,6 +61,8 @@ enum { DG_FORM_NEW = 0, DG_FORM_TRAD = 1 };
  * fine element polynomial at the coarse Gauss-Lobatto nodes (the paper's choice), or
  * the exact L2 projection onto the coarse tensor-product space of the reference cube. */
 enum { DG_RESTRICT_SAMPLE = 0, DG_RESTRICT_L2 = 1 };
+/* Capacity, in doubles, of the static scratch of dg_residual_noalloc (64 MiB). */
+#define DG_NOALLOC_SCRATCH_DOUBLES (8 * 1024 * 1024)
 
 #define DG_NMAX 9 /* polynomial orders 1..DG_NMAX in every direction */
 
@@ -144,6 +146,21 @@ dg_status dg_plan_metrics(dg_plan plan, double *met, hipStream_t stream);
  *   DG_F32: float), plan layout; u and r must not overlap. */
 dg_status dg_residual(dg_plan plan, const void *u, void *r, int32_t dtype, int32_t form,
                       int32_t isolated, hipStream_t stream);
+
+/* Allocation-free residual, for callers that cannot allocate device memory or call
+ * anything that may (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same computation and arguments as dg_residual, with
+ * the face-flux and BR1-gradient scratch taken from one static device array of
+ * DG_NOALLOC_SCRATCH_DOUBLES doubles (64 MiB) per GPU instead of the plan's buffers.
+ * The array is held by every GPU the call runs on until the process ends; its device
+ * address is looked up on the first call on each device.  A plan needing more
+ * scratch (6 face slots x 5 variables x face nodes per element, tripled for curved
+ * Navier-Stokes plans, plus 15 doubles per node for Navier-Stokes gradients; the 16^3
+ * order-7 mesh needs 7.9 Mi doubles) returns DG_EINVAL.  All calls on one GPU share
+ * the array: calls that overlap on one GPU (two streams, or two host threads) race,
+ * and the caller must serialise them.  The plan's device must be current. */
+dg_status dg_residual_noalloc(dg_plan plan, const void *u, void *r, int32_t dtype, int32_t form, int32_t isolated,
+                              hipStream_t stream);
 
 /* Tau-estimate on the coarse order map of `coarse` (Section 2.3, eqs. TEtildedef
  * and TEdef with the variational DG estimate I F(q) ~ I (M^P)^-1 F^P(q^P)):

@@ -67,6 +67,7 @@ SIGNATURES = {
     "dg_node_coords": [_P, _P, _P],
     "dg_plan_metrics": [_P, _P, _P],
     "dg_residual": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
+    "dg_residual_noalloc": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P, _P],
     "dg_residual_vjp": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_functional": [_P, _P, _P, _P, _P],
@@ -310,6 +311,16 @@ def residual(plan: Plan, u, form: int = FORM_NEW, isolated: bool = False, out=No
     _call("dg_residual", plan.handle, _ptr(u), _ptr(r), _dtype_code(u), int(form), int(bool(isolated)),
           _stream())
     return r
+
+
+def residual_noalloc(plan: Plan, u, out, form: int = FORM_NEW, isolated: bool = False):
+    """As residual(), with the library's static scratch instead of the plan's buffers
+    (dg_residual_noalloc); out is required (nothing is allocated)."""
+    if u.numel() != 5 * plan.n_nodes or out.numel() != u.numel() or out.dtype != u.dtype:
+        raise DGError("state or output size does not match the plan")
+    _call("dg_residual_noalloc", plan.handle, _ptr(u), _ptr(out), _dtype_code(u), int(form),
+          int(bool(isolated)), _stream())
+    return out
 
 
 def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False, psi=None,

@@ -571,7 +571,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
 
 // face pass + element pass with the given epilogue
 template <typename T>
-dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s) {
+dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s, void *ff, void *gradbuf) {
     const bool f64 = std::is_same<T, double>::value;
     const T *tab = f64 ? (const T *)p->tabs.t64 : (const T *)p->tabs.t32;
     if (p->curved) {
@@ -584,19 +584,19 @@ dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s) {
             for (size_t i = 0; i < p->classes.size(); ++i) {
                 const TileClass &c = p->classes[i];
                 HIP_TRY(launch_grad_curved<T>(p->d_faces, p->d_fmo, fmet, p->nfaces, p->d_tiles, c.first, c.count,
-                                              c.npt, i == 0, p->d_el, u, met, (T *)p->d_ff, (T *)p->d_grad, tab,
+                                              c.npt, i == 0, p->d_el, u, met, (T *)ff, (T *)gradbuf, tab,
                                               p->phys, epi.isolated, s));
             }
-            grad = (const T *)p->d_grad;
-            epi.grad = p->d_grad;
+            grad = (const T *)gradbuf;
+            epi.grad = gradbuf;
             epi.mu = p->phys.mu;
             epi.kappa = p->phys.kappa;
         }
         if (!epi.isolated)
-            HIP_TRY(launch_face_curved<T>(p->d_faces, p->d_fmo, fmet, p->nfaces, p->d_el, u, grad, (T *)p->d_ff, tab,
+            HIP_TRY(launch_face_curved<T>(p->d_faces, p->d_fmo, fmet, p->nfaces, p->d_el, u, grad, (T *)ff, tab,
                                           p->phys, p->max_order, s));
         for (const TileClass &c : p->classes)
-            HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)p->d_ff, tab,
+            HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)ff, tab,
                                       p->geom, p->phys, epi, s));
         return DG_OK;
     }
@@ -605,27 +605,32 @@ dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s) {
         for (size_t i = 0; i < p->classes.size(); ++i) {
             const TileClass &c = p->classes[i];
             HIP_TRY(launch_ns_gradient<T>(p->d_faces, p->nfaces, p->d_tiles, c.first, c.count, c.npt, i == 0, p->d_el,
-                                          u, (T *)p->d_ff, (T *)p->d_grad, tab, p->geom, p->phys, p->max_order,
+                                          u, (T *)ff, (T *)gradbuf, tab, p->geom, p->phys, p->max_order,
                                           epi.isolated, s));
         }
         if (!epi.isolated)
-            HIP_TRY(launch_ns_faces<T>(p->d_faces, p->nfaces, p->d_el, u, (const T *)p->d_grad, (T *)p->d_ff, tab,
+            HIP_TRY(launch_ns_faces<T>(p->d_faces, p->nfaces, p->d_el, u, (const T *)gradbuf, (T *)ff, tab,
                                        p->geom, p->phys, s));
-        epi.grad = p->d_grad;
+        epi.grad = gradbuf;
         epi.mu = p->phys.mu;
         epi.kappa = p->phys.kappa;
         for (const TileClass &c : p->classes)
-            HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)p->d_ff, tab,
+            HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)ff, tab,
                                       p->geom, p->phys, epi, s));
         return DG_OK;
     }
     if (!epi.isolated)
-        HIP_TRY(launch_face_flux<T>(p->d_faces, p->nfaces, p->d_el, u, (T *)p->d_ff, tab, p->geom, p->phys,
+        HIP_TRY(launch_face_flux<T>(p->d_faces, p->nfaces, p->d_el, u, (T *)ff, tab, p->geom, p->phys,
                                     p->max_order, s));
     for (const TileClass &c : p->classes)
-        HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)p->d_ff, tab, p->geom,
+        HIP_TRY(launch_element<T>(p->d_tiles, c.first, c.count, c.npt, p->d_el, u, (const T *)ff, tab, p->geom,
                                   p->phys, epi, s));
     return DG_OK;
+}
+
+template <typename T>
+dg_status run_residual(dg_plan p, const T *u, EpiArgs epi, hipStream_t s) {
+    return run_residual<T>(p, u, epi, s, p->d_ff, p->d_grad);
 }
 
 bool aligned(const void *x) { return ((uintptr_t)x & 15) == 0; }
@@ -636,6 +641,35 @@ bool all_aligned(P... p) {
 }
 #define DG_ALIGNED(...) \
     if (!all_aligned(__VA_ARGS__)) return fail(DG_EINVAL, "device arrays must be 16-byte aligned")
+
+// Scratch of the allocation-free residual (dg_residual_noalloc): the face fluxes and
+// BR1 gradients live in this file-scope device array instead of the plan's buffers.
+// Host code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): the device address is looked up once per device with
+// hipGetSymbolAddress, with that device current, and that address is used.
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[kNoAllocDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[DG_NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+
+dg_status noalloc_scratch(int dev, double **out) {
+    if (dev < 0 || dev >= kNoAllocDevices) return fail(DG_EUNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(DG_EHIP, std::string("address of the allocation-free scratch: ") + hipGetErrorString(e));
+        g_noalloc_ptr[dev] = (double *)ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return DG_OK;
+}
 
 }  // namespace
 
@@ -743,6 +777,35 @@ dg_status dg_residual(dg_plan p, const void *u, void *r, int32_t dtype, int32_t 
     if (dtype == DG_F64) return run_residual<double>(p, (const double *)u, epi, stream);
     if (dtype == DG_F32) return run_residual<float>(p, (const float *)u, epi, stream);
     return fail(DG_EINVAL, "unknown dtype");
+}
+
+dg_status dg_residual_noalloc(dg_plan p, const void *u, void *r, int32_t dtype, int32_t form, int32_t isolated,
+                              hipStream_t stream) {
+    if (!p || !u || !r) return fail(DG_EINVAL, "null argument");
+    if (!aligned(u) || !aligned(r)) return fail(DG_EINVAL, "arrays must be 16-byte aligned");
+    if (u == r) return fail(DG_EINVAL, "u and r must not overlap");
+    if (form != DG_FORM_NEW && form != DG_FORM_TRAD) return fail(DG_EINVAL, "unknown form");
+    if (dtype != DG_F64 && dtype != DG_F32) return fail(DG_EINVAL, "unknown dtype");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != p->device) return fail(DG_EINVAL, "the plan's device must be the current device");
+    // face fluxes first, BR1 gradients after them (256-byte aligned), both sized for doubles
+    const int64_t ffd = (std::max<int64_t>(1, (p->curved && p->ns ? 3 : 1) * p->ff_len) + 31) / 32 * 32;
+    const int64_t need = ffd + (p->ns ? int64_t(3) * NV * p->n_nodes : 0);
+    if (need > DG_NOALLOC_SCRATCH_DOUBLES)
+        return fail(DG_EINVAL, "the plan needs " + std::to_string(need) +
+                                   " doubles of residual scratch; the allocation-free residual holds at most " +
+                                   std::to_string((long long)DG_NOALLOC_SCRATCH_DOUBLES));
+    double *base = nullptr;
+    dg_status st = noalloc_scratch(dev, &base);
+    if (st) return st;
+    EpiArgs epi{};
+    epi.mode = EPI_RESIDUAL;
+    epi.form = form;
+    epi.isolated = isolated ? 1 : 0;
+    epi.out = r;
+    if (dtype == DG_F64) return run_residual<double>(p, (const double *)u, epi, stream, base, base + ffd);
+    return run_residual<float>(p, (const float *)u, epi, stream, base, base + ffd);
 }
 
 dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt, int32_t isolated,
