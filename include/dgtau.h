@@ -259,6 +259,65 @@ typedef struct {
 dg_status dg_select_orders(dg_plan fine, const double *const *maps, int32_t nstages,
                            const dg_select_params *params, int32_t *orders, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * Adaptation loops (Section 2.4): the flowcharts of dynamic and static
+ * p-adaptation, every step in this library's kernels: RK3 steps (as
+ * dg_rk3_step, launched directly), the isolated truncation-error map
+ * (dg_tau_sweep, the fine time derivative computed from the state), the degree
+ * selection (dg_select_orders), a new plan for the selected degrees and the
+ * projection of the state onto it (dg_project).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double dt;                /* RK3 time step */
+    int32_t steps_per_stage;  /* RK3 steps between estimations (Delta t_e), >= 0 */
+    int32_t nstages;          /* estimation stages, 1..DG_SELECT_MAX_STAGES */
+    int32_t steps_after;      /* static loop: RK3 steps after the adaptation (to the final time) */
+    int32_t restriction;      /* DG_RESTRICT_SAMPLE or DG_RESTRICT_L2 */
+    int32_t form;             /* map used for the selection: DG_FORM_NEW (te_new) or DG_FORM_TRAD */
+    dg_select_params select;  /* tau_max, nmin, nmax, approach (static loop), jump, max_decrease
+                                 (dynamic loop); prev and ext_nmax must be 0 */
+} dg_adapt_params;
+
+typedef struct {
+    int64_t steps;      /* S: RK3 steps taken */
+    double ndof_dyn;    /* (1/S) sum over the steps of the step's number of degrees of freedom
+                           (nodes), the weighted average of Section 3.2 */
+    int64_t ndof_final; /* nodes of the final plan */
+} dg_adapt_report;
+
+/* Dynamic p-adaptation (Section 2.4.1 and its flowchart; the decrease limit of Section
+ * 3.2): nstages times { advance steps_per_stage RK3 steps; estimate the isolated map
+ * on the current plan; select degrees from it (prev = the current degrees, no degree
+ * falling by more than select.max_decrease, then the jump condition); build the plan of
+ * the selected degrees and project the state onto it }.
+ *   plan: in, the initial plan (never destroyed); out, the final plan, a new plan owned
+ *         by the caller when any stage changed the degrees (intermediate plans are
+ *         destroyed).  Box meshes; orders and select.nmax <= 8 (7 for Navier-Stokes).
+ *   u: device double of capacity values: in, the state in the initial plan's layout;
+ *      out, the state in the final plan's layout.  work: device double of capacity
+ *      values (RK register and projection scratch).  capacity >= 5 E (nmax+1)^3 and
+ *      >= 5 n_nodes of the initial plan.
+ *   stage_orders: host int32 [nstages][E][3] (nullable), the degrees selected at every
+ *      stage (natural element order).  report: nullable.
+ * Allocates the loop's maps and degree buffers and each stage's plan (the storage
+ * reallocation the paper names); synchronous on stream (each stage reads its degrees
+ * back).  Errors: DG_EINVAL, DG_EUNSUPPORTED (curved plans, orders above the sweep's),
+ * DG_ENOMEM, DG_EHIP. */
+dg_status dg_adapt_dynamic(dg_plan *plan, double *u, double *work, int64_t capacity, const dg_adapt_params *params,
+                           int32_t *stage_orders, dg_adapt_report *report, hipStream_t stream);
+
+/* Static p-adaptation (Section 2.4.2 and its flowchart): nstages times { advance
+ * steps_per_stage RK3 steps; estimate the isolated map and store it } on the initial
+ * plan; at T_e one selection from all stored maps (select.approach 1: per map then the
+ * maximum per direction; 2: the F_max total map, eq. totalTruncMap), the jump
+ * condition, the plan of the selected degrees and the projection onto it; then
+ * steps_after RK3 steps on the new plan.  Arguments as dg_adapt_dynamic, except
+ *   orders: host int32 [E][3] (nullable), the degrees of the adaptation;
+ *   select.max_decrease is ignored.
+ * Errors as dg_adapt_dynamic (orders up to 8 on the initial plan; select.nmax up to 9). */
+dg_status dg_adapt_static(dg_plan *plan, double *u, double *work, int64_t capacity, const dg_adapt_params *params,
+                          int32_t *orders, dg_adapt_report *report, hipStream_t stream);
+
 /* Total truncation-error map of static adaptation (Section 2.4.2, eq. totalTruncMap with
  * F_max): acc <- max(acc, map) entry by entry, over the sweep layout of the plan
  * (dg_sweep_layout, ext_nmax = 0) or the extended layout of dg_tau_extrapolate

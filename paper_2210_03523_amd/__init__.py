@@ -53,6 +53,16 @@ class _SelectParams(ctypes.Structure):
 
 SELECT_MAX_STAGES = 32
 
+
+class _AdaptParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("steps_per_stage", ctypes.c_int32), ("nstages", ctypes.c_int32),
+                ("steps_after", ctypes.c_int32), ("restriction", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("select", _SelectParams)]
+
+
+class _AdaptReport(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("ndof_dyn", ctypes.c_double), ("ndof_final", ctypes.c_int64)]
+
 _lib = None
 _P = ctypes.c_void_p
 _I64P = ctypes.POINTER(ctypes.c_int64)
@@ -90,6 +100,10 @@ SIGNATURES = {
     "dg_batch_residual": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P],
     "dg_batch_rk3_step": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_double, ctypes.c_int32, _P],
     "dg_batch_to_f64": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P],
+    "dg_adapt_dynamic": [ctypes.POINTER(_P), _P, _P, ctypes.c_int64, ctypes.POINTER(_AdaptParams), _I32P,
+                         ctypes.POINTER(_AdaptReport), _P],
+    "dg_adapt_static": [ctypes.POINTER(_P), _P, _P, ctypes.c_int64, ctypes.POINTER(_AdaptParams), _I32P,
+                        ctypes.POINTER(_AdaptReport), _P],
     "dg_batch_tau_sweep": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P), _P],
 }
 
@@ -185,6 +199,23 @@ class Plan:
             _call("dg_plan_create_coarse", _parent.handle, o.ctypes.data_as(_I32P), ctypes.byref(h))
         self.handle = h
         self.parent = _parent
+        self._layout()
+
+    @classmethod
+    def _adopt(cls, mesh: dict, handle) -> "Plan":
+        """A Plan object owning a plan handle the library created (adaptation loops)."""
+        self = cls.__new__(cls)
+        self.mesh = dict(mesh)
+        self.handle = handle
+        self.parent = None
+        self._layout()
+        o = np.empty_like(self.orders)
+        o[self.perm] = self.orders
+        self.orders_natural = o
+        return self
+
+    def _layout(self):
+        h = self.handle
         ne = ctypes.c_int64()
         nn = ctypes.c_int64()
         _call("dg_plan_layout", h, ctypes.byref(ne), ctypes.byref(nn), None, None, None)
@@ -194,6 +225,8 @@ class Plan:
         self.orders = np.zeros((self.n_elems, 3), dtype=np.int32)
         _call("dg_plan_layout", h, None, None, self.perm.ctypes.data_as(_I64P),
               self.node_offset.ctypes.data_as(_I64P), self.orders.ctypes.data_as(_I32P))
+        o = np.empty_like(self.orders)
+        o[self.perm] = self.orders
         counts = np.prod(o.astype(np.int64) + 1, axis=1)
         self.natural_offset = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
         self._idx = {}
@@ -603,3 +636,44 @@ def batch_tau_sweep(batch: Batch, u64, restriction: int = RESTRICT_SAMPLE):
     ta = (_P * n)(*[m[1].data_ptr() for m in maps])
     _call("dg_batch_tau_sweep", batch.handle, ua, int(restriction), na, ta, _stream())
     return maps
+
+
+def _adapt(name, plan: Plan, u, dt, steps_per_stage, nstages, tau_max, nmin, nmax, jump, approach,
+           max_decrease, steps_after, restriction, form):
+    torch = _torch()
+    E = plan.n_elems
+    cap = max(5 * E * (nmax + 1) ** 3, 5 * plan.n_nodes)
+    if u.dtype != torch.float64 or u.numel() != 5 * plan.n_nodes:
+        raise DGError("u must be a float64 state of the plan")
+    ub = torch.empty(cap, dtype=torch.float64, device="cuda")
+    ub[:u.numel()].copy_(u)
+    work = torch.empty_like(ub)
+    prm = _AdaptParams(float(dt), int(steps_per_stage), int(nstages), int(steps_after), int(restriction), int(form),
+                       _SelectParams(float(tau_max), int(nmin), int(nmax), int(approach), int(jump), None,
+                                     int(max_decrease), 0))
+    rep = _AdaptReport()
+    h = ctypes.c_void_p(plan.handle.value)
+    orders = np.zeros((nstages if name == "dg_adapt_dynamic" else 1, E, 3), dtype=np.int32)
+    _call(name, ctypes.byref(h), _ptr(ub), _ptr(work), int(cap), ctypes.byref(prm), orders.ctypes.data_as(_I32P),
+          ctypes.byref(rep), _stream())
+    new = plan if h.value == plan.handle.value else Plan._adopt(plan.mesh, h)
+    return new, ub[:5 * new.n_nodes].clone(), orders, {"steps": int(rep.steps), "ndof_dyn": float(rep.ndof_dyn),
+                                                        "ndof_final": int(rep.ndof_final)}
+
+
+def adapt_dynamic(plan: Plan, u, dt: float, steps_per_stage: int, nstages: int, tau_max: float, nmin: int = 1,
+                  nmax: int = 8, jump: int = 2, max_decrease: int = 1, restriction: int = RESTRICT_SAMPLE,
+                  form: int = FORM_NEW):
+    """Dynamic p-adaptation loop: (final plan, final state, degrees selected per stage
+    [nstages][E][3] natural, report with NDOF_dyn)."""
+    return _adapt("dg_adapt_dynamic", plan, u, dt, steps_per_stage, nstages, tau_max, nmin, nmax, jump, 1,
+                  max_decrease, 0, restriction, form)
+
+
+def adapt_static(plan: Plan, u, dt: float, steps_per_stage: int, nstages: int, steps_after: int, tau_max: float,
+                 nmin: int = 1, nmax: int = 8, jump: int = 2, approach: int = 2,
+                 restriction: int = RESTRICT_SAMPLE, form: int = FORM_NEW):
+    """Static p-adaptation loop: (final plan, final state, adapted degrees [1][E][3]
+    natural, report)."""
+    return _adapt("dg_adapt_static", plan, u, dt, steps_per_stage, nstages, tau_max, nmin, nmax, jump, approach,
+                  0, steps_after, restriction, form)

@@ -145,6 +145,7 @@ struct dg_plan_s {
     int32_t *d_inv = nullptr;           // natural element -> plan position
     double *d_red = nullptr;            // reduction partials of dg_check_state
     int iso_first[NNMAX + 1] = {0}, iso_count[NNMAX + 1] = {0};
+    void *d_arena = nullptr;  // the one device allocation every device buffer lives in
     // RK3 graphs: at most kGraphCache, each with the call count of its last use
     hipStream_t cap_stream = nullptr;
     std::map<GraphKey, std::pair<hipGraphExec_t, uint64_t>> graphs;
@@ -161,16 +162,47 @@ dg_status upload(T **dst, const std::vector<T> &src) {
     return DG_OK;
 }
 
+// One device allocation per plan: the uploaded tables (one host image, one copy) followed
+// by the scratch buffers, each 256-byte aligned.  Empty uploads leave their pointer null.
+struct Arena {
+    struct Slot {
+        void **dst;
+        size_t off;
+    };
+    std::vector<Slot> slots;
+    std::vector<char> image;  // host image of the uploaded part
+    size_t off = 0;
+    static size_t align(size_t x) { return (x + 255) & ~size_t(255); }
+    template <typename T>
+    void upload(T **dst, const std::vector<T> &v) {
+        if (v.empty()) return;
+        off = align(off);
+        slots.push_back({(void **)dst, off});
+        const size_t bytes = sizeof(T) * v.size();
+        image.resize(off + bytes);
+        memcpy(image.data() + off, v.data(), bytes);
+        off += bytes;
+    }
+    template <typename T>
+    void scratch(T **dst, size_t bytes) {  // after every upload
+        off = align(off);
+        slots.push_back({(void **)dst, off});
+        off += std::max<size_t>(bytes, 8);
+    }
+    dg_status commit(void **base) {
+        if (hipMalloc(base, std::max<size_t>(off, 256)) != hipSuccess) return fail(DG_ENOMEM, "device allocation failed");
+        if (!image.empty() && hipMemcpy(*base, image.data(), image.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(DG_EHIP, "plan upload failed");
+        for (const Slot &sl : slots) *sl.dst = (char *)*base + sl.off;
+        return DG_OK;
+    }
+};
+
 void destroy_plan(dg_plan p) {
     if (!p) return;
     for (auto &kv : p->graphs) (void)hipGraphExecDestroy(kv.second.first);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    void *bufs[] = {p->d_el,    p->d_faces,  p->d_tiles,  p->d_ff,     p->d_dudt,   p->d_fine_of, p->d_uc,
-                    p->d_rdc,   p->d_psic,   p->d_combo_off, p->d_tasks, p->d_iso,  p->d_wallx,   p->d_part,
-                    p->d_grad,  p->d_xyz,    p->d_met64,  p->d_fmet64, p->d_met32,  p->d_fmet32,  p->d_fmo,
-                    p->d_ctasks, p->d_sel, p->d_inv, p->d_red};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
+    if (p->d_arena) (void)hipFree(p->d_arena);
     delete p;
 }
 
@@ -543,27 +575,51 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
 
     p->nctasks = (int)ctasks.size();
     std::vector<float> met32(met_h.begin(), met_h.end()), fmet32(fmet_h.begin(), fmet_h.end());
-    if ((st = upload(&p->d_el, el)) || (st = upload(&p->d_faces, faces)) || (st = upload(&p->d_tiles, tiles)) ||
-        (st = upload(&p->d_combo_off, p->combo_off)) || (st = upload(&p->d_tasks, tasks)) ||
-        (st = upload(&p->d_iso, iso_all)) || (st = upload(&p->d_wallx, wallx)) ||
-        (st = upload(&p->d_ctasks, ctasks)) || (st = upload(&p->d_xyz, p->xyz_h)) ||
-        (st = upload(&p->d_met64, met_h)) || (st = upload(&p->d_met32, met32)) ||
-        (st = upload(&p->d_fmet64, fmet_h)) || (st = upload(&p->d_fmet32, fmet32)) || (st = upload(&p->d_fmo, fmo)) ||
-        (st = upload(&p->d_inv, std::vector<int32_t>(p->inv.begin(), p->inv.end())))) {
-        destroy_plan(p);
-        return st;
+    // coarse plans: the fine element of every coarse element, restriction LDS capacities
+    std::vector<int32_t> fine_of;
+    if (parent) {
+        fine_of.resize(E);
+        for (int i = 0; i < E; ++i) {
+            fine_of[i] = (int32_t)parent->inv[perm[i]];
+            const int32_t *of = parent->ord.data() + 3 * fine_of[i], *oc = p->ord.data() + 3 * i;
+            p->rcapA = std::max(p->rcapA, NV * (oc[0] + 1) * (of[1] + 1) * (of[2] + 1));
+            p->rcapB = std::max(p->rcapB, NV * std::max((oc[0] + 1) * (oc[1] + 1) * (of[2] + 1),
+                                                        (of[0] + 1) * (of[1] + 1) * (of[2] + 1)));
+        }
     }
+    Arena ar;
+    ar.upload(&p->d_el, el);
+    ar.upload(&p->d_faces, faces);
+    ar.upload(&p->d_tiles, tiles);
+    ar.upload(&p->d_combo_off, p->combo_off);
+    ar.upload(&p->d_tasks, tasks);
+    ar.upload(&p->d_iso, iso_all);
+    ar.upload(&p->d_wallx, wallx);
+    ar.upload(&p->d_ctasks, ctasks);
+    ar.upload(&p->d_xyz, p->xyz_h);
+    ar.upload(&p->d_met64, met_h);
+    ar.upload(&p->d_met32, met32);
+    ar.upload(&p->d_fmet64, fmet_h);
+    ar.upload(&p->d_fmet32, fmet32);
+    ar.upload(&p->d_fmo, fmo);
+    ar.upload(&p->d_inv, std::vector<int32_t>(p->inv.begin(), p->inv.end()));
+    ar.upload(&p->d_fine_of, fine_of);
     // the face buffer also carries the 15-value BR1 face data of curved Navier-Stokes plans
     const int64_t ff_alloc = std::max<int64_t>(1, (p->curved && p->ns ? 3 : 1) * p->ff_len);
-    if (hipMalloc(&p->d_ff, sizeof(double) * ff_alloc) != hipSuccess ||
-        hipMalloc((void **)&p->d_part, sizeof(double) * std::max(1, p->nwallx)) != hipSuccess ||
-        hipMalloc((void **)&p->d_dudt, sizeof(double) * NV * p->n_nodes) != hipSuccess ||
-        hipMalloc((void **)&p->d_sel, sizeof(int32_t) * 3 * std::max(1, E)) != hipSuccess ||
-        hipMalloc((void **)&p->d_red, sizeof(double) * (dot_partials() + 8)) != hipSuccess ||
-        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
-        (p->ns && hipMalloc(&p->d_grad, sizeof(double) * 3 * NV * p->n_nodes) != hipSuccess)) {
+    ar.scratch(&p->d_ff, sizeof(double) * ff_alloc);
+    ar.scratch(&p->d_part, sizeof(double) * std::max(1, p->nwallx));
+    ar.scratch(&p->d_dudt, sizeof(double) * NV * p->n_nodes);
+    ar.scratch(&p->d_sel, sizeof(int32_t) * 3 * std::max(1, E));
+    ar.scratch(&p->d_red, sizeof(double) * (dot_partials() + 8));
+    if (p->ns) ar.scratch(&p->d_grad, sizeof(double) * 3 * NV * p->n_nodes);
+    if (parent) {
+        ar.scratch(&p->d_uc, sizeof(double) * NV * p->n_nodes);
+        ar.scratch(&p->d_rdc, sizeof(double) * NV * p->n_nodes);
+        ar.scratch(&p->d_psic, sizeof(double) * NV * p->n_nodes);
+    }
+    if ((st = ar.commit(&p->d_arena))) {
         destroy_plan(p);
-        return fail(DG_ENOMEM, "device allocation failed");
+        return st;
     }
     *out = p;
     return DG_OK;
@@ -692,24 +748,6 @@ dg_status dg_plan_create_coarse(dg_plan fine, const int32_t *coarse_orders_host,
     dg_status st = build_plan(&fine->mesh, coarse_orders_host, fine, &c);
     if (st) return st;
     c->parent = fine;
-    std::vector<int32_t> fine_of(c->E);
-    for (int i = 0; i < c->E; ++i) {
-        fine_of[i] = (int32_t)fine->inv[c->perm[i]];
-        const int32_t *of = fine->ord.data() + 3 * fine_of[i], *oc = c->ord.data() + 3 * i;
-        c->rcapA = std::max(c->rcapA, NV * (oc[0] + 1) * (of[1] + 1) * (of[2] + 1));
-        c->rcapB = std::max(c->rcapB, NV * std::max((oc[0] + 1) * (oc[1] + 1) * (of[2] + 1),
-                                                    (of[0] + 1) * (of[1] + 1) * (of[2] + 1)));
-    }
-    if ((st = upload(&c->d_fine_of, fine_of))) {
-        destroy_plan(c);
-        return st;
-    }
-    if (hipMalloc((void **)&c->d_uc, sizeof(double) * NV * c->n_nodes) != hipSuccess ||
-        hipMalloc((void **)&c->d_rdc, sizeof(double) * NV * c->n_nodes) != hipSuccess ||
-        hipMalloc((void **)&c->d_psic, sizeof(double) * NV * c->n_nodes) != hipSuccess) {
-        destroy_plan(c);
-        return fail(DG_ENOMEM, "device allocation failed");
-    }
     *out = c;
     return DG_OK;
 }
@@ -980,6 +1018,7 @@ dg_status dg_rk3_step(dg_plan p, void *u, void *g, double dt, int32_t nsteps, in
             (void)hipGraphExecDestroy(v->second.first);
             p->graphs.erase(v);
         }
+        if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
         hipGraph_t graph;
         HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
         dg_status st = DG_OK;
@@ -1004,6 +1043,217 @@ dg_status dg_rk3_step(dg_plan p, void *u, void *g, double dt, int32_t nsteps, in
     }
     it->second.second = ++p->graph_clock;
     for (int s = 0; s < nsteps; ++s) HIP_TRY(hipGraphLaunch(it->second.first, stream));
+    return DG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- adaptation loops
+namespace {
+
+// nsteps RK3 steps launched directly (each stage one face and one element pass): the
+// adaptation loops change plans from stage to stage, where a captured graph would be
+// used once.
+dg_status rk3_eager(dg_plan p, double *u, double *g, double dt, int nsteps, hipStream_t s) {
+    static const double A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+    static const double B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    for (int n = 0; n < nsteps; ++n)
+        for (int k = 0; k < 3; ++k) {
+            EpiArgs epi{};
+            epi.mode = EPI_RK;
+            epi.rkA = A[k];
+            epi.rkB = B[k];
+            epi.dt = dt;
+            epi.g = g;
+            const dg_status st = run_residual<double>(p, u, epi, s);
+            if (st) return st;
+        }
+    return DG_OK;
+}
+
+// Device buffers of one loop call, freed on every exit.
+struct LoopBuffers {
+    std::vector<void *> bufs;
+    ~LoopBuffers() {
+        for (void *b : bufs) (void)hipFree(b);
+    }
+    template <typename T>
+    dg_status alloc(T **p, size_t n) {
+        void *b = nullptr;
+        if (hipMalloc(&b, sizeof(T) * std::max<size_t>(n, 1)) != hipSuccess)
+            return fail(DG_ENOMEM, "device allocation failed");
+        bufs.push_back(b);
+        *p = (T *)b;
+        return DG_OK;
+    }
+};
+
+dg_status check_adapt(dg_plan p, const double *u, const double *work, int64_t capacity, const dg_adapt_params *prm,
+                      bool dynamic) {
+    if (!p || !u || !work || !prm) return fail(DG_EINVAL, "null argument");
+    if (!aligned(u) || !aligned(work)) return fail(DG_EINVAL, "device arrays must be 16-byte aligned");
+    if (u == work) return fail(DG_EINVAL, "u and work must be different arrays");
+    if (p->parent) return fail(DG_EINVAL, "the loop runs on a fine plan, not a coarse one");
+    if (p->curved) return fail(DG_EUNSUPPORTED, "the adaptation loops run box meshes");
+    const dg_select_params &sp = prm->select;
+    if (prm->steps_per_stage < 0 || prm->steps_after < 0) return fail(DG_EINVAL, "step counts must be >= 0");
+    if (prm->nstages < 1 || prm->nstages > DG_SELECT_MAX_STAGES) return fail(DG_EINVAL, "nstages must be in 1..32");
+    if (prm->restriction != DG_RESTRICT_SAMPLE && prm->restriction != DG_RESTRICT_L2)
+        return fail(DG_EINVAL, "restriction must be DG_RESTRICT_SAMPLE or DG_RESTRICT_L2");
+    if (prm->form != DG_FORM_NEW && prm->form != DG_FORM_TRAD) return fail(DG_EINVAL, "unknown form");
+    if (sp.prev || sp.ext_nmax) return fail(DG_EINVAL, "select.prev and select.ext_nmax must be unset");
+    if (sp.approach != 1 && sp.approach != 2) return fail(DG_EINVAL, "approach must be 1 or 2");
+    if (sp.jump < 0 || sp.jump > 2) return fail(DG_EINVAL, "jump must be 0, 1 or 2");
+    if (sp.nmin < 1 || sp.nmin > sp.nmax || sp.nmax > DG_NMAX)
+        return fail(DG_EINVAL, "degrees must satisfy 1 <= nmin <= nmax <= 9");
+    if (std::isnan(sp.tau_max)) return fail(DG_EINVAL, "tau_max is NaN");
+    if (dynamic && sp.max_decrease < 0) return fail(DG_EINVAL, "max_decrease must be >= 0");
+    const int sweep_max = p->ns ? 7 : 8;
+    if (p->max_order > sweep_max || (dynamic && sp.nmax > sweep_max))
+        return fail(DG_EUNSUPPORTED, "every estimated plan needs orders <= 8 (7 for Navier-Stokes)");
+    const int64_t need = (int64_t)NV * p->E * (int64_t)(sp.nmax + 1) * (sp.nmax + 1) * (sp.nmax + 1);
+    if (capacity < std::max<int64_t>(need, NV * p->n_nodes))
+        return fail(DG_EINVAL, "capacity must hold 5 E (nmax+1)^3 doubles and the initial state");
+    return DG_OK;
+}
+
+// A new plan of the same mesh for the degrees selected on the device (natural order),
+// the state projected onto it through work; the previous plan is destroyed unless it is
+// the caller's.
+dg_status replan(dg_plan *cur, dg_plan initial, const int32_t *orders_dev, std::vector<int32_t> &orders_host,
+                 double *u, double *work, hipStream_t s) {
+    dg_plan p = *cur;
+    HIP_TRY(hipMemcpyAsync(orders_host.data(), orders_dev, sizeof(int32_t) * orders_host.size(),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    dg_plan q = nullptr;
+    dg_status st = build_plan(&p->mesh, orders_host.data(), nullptr, &q);
+    if (st) return st;
+    st = dg_project(p, q, u, work, s);
+    if (!st && hipMemcpyAsync(u, work, sizeof(double) * NV * q->n_nodes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        st = fail(DG_EHIP, "state copy failed");
+    if (st) {
+        destroy_plan(q);
+        return st;
+    }
+    if (p != initial) {
+        HIP_TRY(hipStreamSynchronize(s));
+        destroy_plan(p);
+    }
+    *cur = q;
+    return DG_OK;
+}
+
+void natural_orders(dg_plan p, std::vector<int32_t> &o) {
+    o.resize(3 * (size_t)p->E);
+    for (int i = 0; i < p->E; ++i)
+        for (int d = 0; d < 3; ++d) o[3 * p->perm[i] + d] = p->ord[3 * i + d];
+}
+
+}  // namespace
+
+extern "C" {
+
+dg_status dg_adapt_dynamic(dg_plan *plan, double *u, double *work, int64_t capacity, const dg_adapt_params *prm,
+                           int32_t *stage_orders, dg_adapt_report *report, hipStream_t stream) {
+    if (!plan) return fail(DG_EINVAL, "null argument");
+    dg_status st = check_adapt(*plan, u, work, capacity, prm, true);
+    if (st) return st;
+    const dg_plan initial = *plan;
+    const int E = initial->E;
+    const int cmax = std::max(1, std::max(initial->max_order, prm->select.nmax) - 1);
+    LoopBuffers lb;
+    double *te[2] = {nullptr, nullptr};
+    int32_t *prev = nullptr, *sel = nullptr;
+    if ((st = lb.alloc(&te[0], (size_t)E * cmax * cmax * cmax)) || (st = lb.alloc(&te[1], (size_t)E * cmax * cmax * cmax)) ||
+        (st = lb.alloc(&prev, 3 * (size_t)E)) || (st = lb.alloc(&sel, 3 * (size_t)E)))
+        return st;
+    std::vector<int32_t> oh;
+    natural_orders(initial, oh);
+    HIP_TRY(hipMemcpyAsync(prev, oh.data(), sizeof(int32_t) * oh.size(), hipMemcpyHostToDevice, stream));
+    dg_plan cur = initial;
+    double ndof_steps = 0.0;
+    int64_t steps = 0;
+    auto finish = [&](dg_status code) {
+        if (code && cur != initial) {
+            (void)hipStreamSynchronize(stream);
+            destroy_plan(cur);
+            cur = initial;
+        }
+        *plan = cur;
+        return code;
+    };
+    for (int stage = 0; stage < prm->nstages; ++stage) {
+        // advance Delta t_e (the RK register lives in work until the projection)
+        if ((st = rk3_eager(cur, u, work, prm->dt, prm->steps_per_stage, stream))) return finish(st);
+        ndof_steps += (double)cur->n_nodes * prm->steps_per_stage;
+        steps += prm->steps_per_stage;
+        // estimate the error on the current plan, then adapt the degrees
+        if ((st = dg_tau_sweep(cur, u, nullptr, prm->restriction, te[0], te[1], stream))) return finish(st);
+        dg_select_params sp = prm->select;
+        sp.prev = prev;
+        const double *map = te[prm->form == DG_FORM_NEW ? 0 : 1];
+        if ((st = dg_select_orders(cur, &map, 1, &sp, sel, stream))) return finish(st);
+        if ((st = replan(&cur, initial, sel, oh, u, work, stream))) return finish(st);
+        if (stage_orders) std::copy(oh.begin(), oh.end(), stage_orders + (size_t)stage * oh.size());
+        std::swap(prev, sel);
+    }
+    if (report) {
+        report->steps = steps;
+        report->ndof_dyn = steps ? ndof_steps / (double)steps : (double)cur->n_nodes;
+        report->ndof_final = cur->n_nodes;
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess) return finish(fail(DG_EHIP, "stream synchronisation failed"));
+    return finish(DG_OK);
+}
+
+dg_status dg_adapt_static(dg_plan *plan, double *u, double *work, int64_t capacity, const dg_adapt_params *prm,
+                          int32_t *orders, dg_adapt_report *report, hipStream_t stream) {
+    if (!plan) return fail(DG_EINVAL, "null argument");
+    dg_status st = check_adapt(*plan, u, work, capacity, prm, false);
+    if (st) return st;
+    const dg_plan initial = *plan;
+    const int64_t nmap = initial->combo_off[initial->E];
+    LoopBuffers lb;
+    std::vector<double *> maps(prm->nstages);
+    double *other = nullptr;
+    int32_t *sel = nullptr;
+    for (auto &m : maps)
+        if ((st = lb.alloc(&m, (size_t)nmap))) return st;
+    if ((st = lb.alloc(&other, (size_t)nmap)) || (st = lb.alloc(&sel, 3 * (size_t)initial->E))) return st;
+    // estimation stages on the fixed plan, every map stored until T_e
+    for (int stage = 0; stage < prm->nstages; ++stage) {
+        if ((st = rk3_eager(initial, u, work, prm->dt, prm->steps_per_stage, stream))) return st;
+        double *tn = prm->form == DG_FORM_NEW ? maps[stage] : other;
+        double *tt = prm->form == DG_FORM_NEW ? other : maps[stage];
+        if ((st = dg_tau_sweep(initial, u, nullptr, prm->restriction, tn, tt, stream))) return st;
+    }
+    // one adaptation from all stored maps (approach 1 or 2), then the rest of the run
+    dg_select_params sp = prm->select;
+    if ((st = dg_select_orders(initial, (const double *const *)maps.data(), prm->nstages, &sp, sel, stream)))
+        return st;
+    std::vector<int32_t> oh(3 * (size_t)initial->E);
+    dg_plan cur = initial;
+    if ((st = replan(&cur, initial, sel, oh, u, work, stream))) return st;
+    if (orders) std::copy(oh.begin(), oh.end(), orders);
+    if ((st = rk3_eager(cur, u, work, prm->dt, prm->steps_after, stream))) {
+        (void)hipStreamSynchronize(stream);
+        destroy_plan(cur);
+        return st;
+    }
+    const int64_t steps = (int64_t)prm->nstages * prm->steps_per_stage + prm->steps_after;
+    if (report) {
+        report->steps = steps;
+        report->ndof_dyn = steps ? ((double)initial->n_nodes * prm->nstages * prm->steps_per_stage +
+                                    (double)cur->n_nodes * prm->steps_after) / (double)steps
+                                 : (double)cur->n_nodes;
+        report->ndof_final = cur->n_nodes;
+    }
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        destroy_plan(cur);
+        return fail(DG_EHIP, "stream synchronisation failed");
+    }
+    *plan = cur;
     return DG_OK;
 }
 
