@@ -1,10 +1,10 @@
 // Tau-estimation kernels for gfx950 (Section 2.3, variational DG estimate).
 //
-//   k_restrict : restricts the fine element polynomial of Q and of the fine time
+//   k_restrict_w : restricts the fine element polynomial of Q and of the fine time
 //                derivative to the coarse orders, by sampling at the coarse
 //                Gauss-Lobatto nodes or by the exact L2 projection (sum-factorised
-//                A3 (x) A2 (x) A1, staged through LDS), writing the coarse plan
-//                layout.  The coarse residual and the tau difference then run in
+//                A3 (x) A2 (x) A1: x in registers, y and z through LDS), writing the
+//                coarse plan layout.  The coarse residual and the tau difference then run in
 //                the element kernel's tau epilogue.
 //   k_sweep    : the isolated truncation-error map.  One workgroup per (fine
 //                element, c1, c2): the x-interpolation of Q and of the time
@@ -21,12 +21,6 @@ namespace dgt {
 
 
 // ---------------------------------------------------------------------------- restriction
-// One workgroup per coarse element.  The three interpolation matrices are staged into
-// LDS first (their rows vary across lanes, so read from global memory every FMA would
-// wait on a vector load); per field (Q, dQ/dt, optionally psi) the fine element block
-// is staged with coalesced loads, then the three sum-factorisation passes run over all
-// five variables at once.  Dynamic LDS: sI [I1 | I2 | I3], sA [5][c1][f2 f3],
-// sB [5][f1 f2 f3] (the staged block) and later [5][c1 c2][f3].
 // Per direction the operator is the interpolation where the order rises or stays and,
 // where it falls, the table at offset `down`: T_I (sampling) or T_P (exact L2
 // projection).  PROJECT: the solution transfer onto another order map (Section 2.4.1,
@@ -34,99 +28,95 @@ namespace dgt {
 // found through the source plan's natural -> plan index (fine_of), one field (Q).
 // psi_new: the adjoint weight is the adjoint of the new-form residual M^-1 F, i.e. M times
 // the traditional-form adjoint (M = J w_i w_j w_k of the fine element); it is divided by
-// M as it is staged (box elements: J = 1/invJ; curved: J per node from met).
-constexpr int RS_WG = 256;
-constexpr int RS_TAB = 3 * NNMAX * NNMAX;
-
+// M as it is loaded (box elements: J = 1/invJ; curved: J per node from met).
+// One wave per (coarse element, field): the fine x-lines of the element (lane = line
+// (j, k)) are loaded into registers for all five variables at once, so a wave keeps
+// its whole block in flight; then per variable the x-pass (registers -> LDS), the
+// y-pass and the z-pass (LDS -> the coarse plan layout), with barriers of one wave
+// only.  LDS: s1 [c1][f2 f3] and s2 [c1 c2][f3] of one variable.  Elements with more
+// than 64 fine x-lines (f2 f3 > 64) reload each variable's lines per pass.
 template <bool PROJECT>
-__global__ __launch_bounds__(RS_WG) void k_restrict(const int32_t *__restrict__ fine_of,
-                                                    const ElemInfo *__restrict__ cel,
-                                                    const ElemInfo *__restrict__ fel, const double *__restrict__ u,
-                                                    const double *__restrict__ dudt, const double *__restrict__ psi,
-                                                    double *__restrict__ uc, double *__restrict__ rdc,
-                                                    double *__restrict__ psic, const double *__restrict__ tab,
-                                                    int capA, int down, int psi_new,
-                                                    const double *__restrict__ met, double invJ) {
+__global__ __launch_bounds__(64) void k_restrict_w(const int32_t *__restrict__ fine_of,
+                                                   const ElemInfo *__restrict__ cel,
+                                                   const ElemInfo *__restrict__ fel, const double *__restrict__ u,
+                                                   const double *__restrict__ dudt, const double *__restrict__ psi,
+                                                   double *__restrict__ uc, double *__restrict__ rdc,
+                                                   double *__restrict__ psic, const double *__restrict__ tab,
+                                                   int cap1, int down, int psi_new, const double *__restrict__ met,
+                                                   double invJ, int nfield) {
     extern __shared__ double lds[];
-    double *sI = lds, *sA = lds + RS_TAB, *sB = lds + RS_TAB + capA;
-    const int p = xcd_remap(blockIdx.x, gridDim.x);
+    double *s1 = lds, *s2 = lds + cap1;
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    const int p = w / nfield, field = w - p * nfield;
     const ElemInfo C = cel[p];
     const ElemInfo F = fel[fine_of[PROJECT ? C.nat : p]];
-    const int f1 = F.n[0], f2 = F.n[1], f3 = F.n[2], nef = f1 * f2 * f3;
-    const int c1 = C.n[0], c2 = C.n[1], c3 = C.n[2], nec = c1 * c2 * c3;
-    const int tid = threadIdx.x;
-    double *I1 = sI, *I2 = sI + c1 * f1, *I3 = I2 + c2 * f2;
-    {
-        auto op = [&](int c, int f) { return tab + (c < f ? down : T_I) + moff(c - 1, f - 1); };
-        const double *g1 = op(c1, f1), *g2 = op(c2, f2);
-        const double *g3 = op(c3, f3);
-        for (int t = tid; t < c1 * f1; t += RS_WG) I1[t] = g1[t];
-        for (int t = tid; t < c2 * f2; t += RS_WG) I2[t] = g2[t];
-        for (int t = tid; t < c3 * f3; t += RS_WG) I3[t] = g3[t];
+    const int f1 = F.n[0], f2 = F.n[1], f3 = F.n[2], nl = f2 * f3, nef = f1 * nl;
+    const int c1 = C.n[0], c2 = C.n[1], c3 = C.n[2], n12 = c1 * c2, nec = n12 * c3;
+    auto op = [&](int c, int f) { return tab + (c < f ? down : T_I) + moff(c - 1, f - 1); };
+    const double *I1 = op(c1, f1), *I2 = op(c2, f2), *I3 = op(c3, f3);
+    const double *src = (field == 0 ? u : field == 1 ? dudt : psi) + NV * F.noff;
+    double *dst = (field == 0 ? uc : field == 1 ? rdc : psic) + NV * C.noff;
+    const int lane = threadIdx.x;
+    const bool scale = !PROJECT && field == 2 && psi_new;
+
+    double ln[NV][NNMAX];
+    auto load = [&](int v, int jk) {
+        double sc = 1.0;
+        if (scale && jk < nl) {
+            const double *w1 = tab + T_W + xoff(f1 - 1), *w2 = tab + T_W + xoff(f2 - 1);
+            const double *w3 = tab + T_W + xoff(f3 - 1);
+            sc = 1.0 / (w2[jk % f2] * w3[jk / f2]);
+        }
+#pragma unroll
+        for (int i = 0; i < NNMAX; ++i) {
+            double x = (jk < nl && i < f1) ? src[v * nef + f1 * jk + i] : 0.0;
+            if (scale && jk < nl && i < f1) {
+                const int node = i + f1 * jk;
+                const double ij = met ? 1.0 / met[10 * F.noff + 9 * nef + node] : invJ;
+                x *= ij * sc / tab[T_W + xoff(f1 - 1) + i];
+            }
+            ln[v][i] = x;
+        }
+    };
+    const bool one = nl <= 64;
+    if (one) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) load(v, lane);
     }
-    const int nA = c1 * f2 * f3, nB = c1 * c2 * f3;
-    const int nfield = PROJECT ? 1 : psi ? 3 : 2;
-    for (int field = 0; field < nfield; ++field) {
-        const double *src = (field == 0 ? u : field == 1 ? dudt : psi) + NV * F.noff;
-        double *dst = (field == 0 ? uc : field == 1 ? rdc : psic) + NV * C.noff;
-        // stage the fine block (the previous field's z-pass has finished reading sB)
-        if (field > 0) __syncthreads();
-        // eight coalesced loads in flight per lane before their LDS stores
-        for (int t0 = 0; t0 < NV * nef; t0 += 8 * RS_WG) {
-            double v[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int t = t0 + tid + k * RS_WG;
-                v[k] = t < NV * nef ? src[t] : 0.0;
-            }
-            if (!PROJECT && field == 2 && psi_new) {
-                const double *w1 = tab + T_W + xoff(f1 - 1), *w2 = tab + T_W + xoff(f2 - 1);
-                const double *w3 = tab + T_W + xoff(f3 - 1);
+    for (int v = 0; v < NV; ++v) {
+        // x: s1[a + c1 jk] = sum_i I1[a, i] Q_v[i + f1 jk]
+        for (int l0 = 0; l0 < nl; l0 += 64) {
+            const int jk = l0 + lane;
+            if (!one) load(v, jk);
+            if (jk < nl)
+                for (int a = 0; a < c1; ++a) {
+                    double acc = 0.0;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int t = t0 + tid + k * RS_WG;
-                    if (t < NV * nef) {
-                        const int node = t % nef, i = node % f1, j = (node / f1) % f2, kk = node / (f1 * f2);
-                        const double ij = met ? 1.0 / met[10 * F.noff + 9 * nef + node] : invJ;
-                        v[k] *= ij / (w1[i] * w2[j] * w3[kk]);
-                    }
+                    for (int i = 0; i < NNMAX; ++i)
+                        if (i < f1) acc += I1[a * f1 + i] * ln[v][i];
+                    s1[a + c1 * jk] = acc;
                 }
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int t = t0 + tid + k * RS_WG;
-                if (t < NV * nef) sB[t] = v[k];
-            }
         }
         __syncthreads();
-        // x: sA[v][a + c1 jk] = sum_i I1[a,i] Q_v[i + f1 jk]
-        for (int t = tid; t < NV * nA; t += RS_WG) {
-            const int v = t / nA, r = t - v * nA, a = r % c1, jk = r / c1;
-            const double *row = sB + v * nef + f1 * jk;
-            const double *w = I1 + a * f1;
+        // y: s2[a + c1 (b + c2 k)] = sum_j I2[b, j] s1[a + c1 (j + f2 k)]
+        for (int t = lane; t < n12 * f3; t += 64) {
+            const int a = t % c1, b = (t / c1) % c2, k = t / n12;
+            const double *x = s1 + a + c1 * f2 * k;
+            const double *wy = I2 + b * f2;
             double acc = 0.0;
-            for (int i = 0; i < f1; ++i) acc += w[i] * row[i];
-            sA[t] = acc;
+            for (int j = 0; j < f2; ++j) acc += wy[j] * x[c1 * j];
+            s2[t] = acc;
         }
         __syncthreads();
-        // y: sB[v][a + c1 (b + c2 k)] = sum_j I2[b,j] sA[v][a + c1 (j + f2 k)]
-        for (int t = tid; t < NV * nB; t += RS_WG) {
-            const int v = t / nB, r = t - v * nB, a = r % c1, b = (r / c1) % c2, k = r / (c1 * c2);
-            const double *x = sA + v * nA + a + c1 * f2 * k;
-            const double *w = I2 + b * f2;
+        // z: the coarse plan layout, node a + c1 (b + c2 c)
+        for (int t = lane; t < nec; t += 64) {
+            const int ab = t % n12, c = t / n12;
+            const double *x = s2 + ab;
+            const double *wz = I3 + c * f3;
             double acc = 0.0;
-            for (int j = 0; j < f2; ++j) acc += w[j] * x[c1 * j];
-            sB[t] = acc;
-        }
-        __syncthreads();
-        // z: straight to the coarse plan layout
-        for (int t = tid; t < NV * nec; t += RS_WG) {
-            const int v = t / nec, r = t - v * nec, ab = r % (c1 * c2), c = r / (c1 * c2);
-            const double *x = sB + v * nB + ab;
-            const double *w = I3 + c * f3;
-            double acc = 0.0;
-            for (int k = 0; k < f3; ++k) acc += w[k] * x[c1 * c2 * k];
-            dst[t] = acc;
+            for (int k = 0; k < f3; ++k) acc += wz[k] * x[n12 * k];
+            dst[v * nec + t] = acc;
         }
     }
 }
@@ -136,28 +126,19 @@ hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *
                            double *psic, const double *tab, int capA, int capB, int restriction, int psi_new,
                            const double *met, double invJ, hipStream_t s) {
     if (ncoarse == 0) return hipSuccess;
-    const size_t lds = sizeof(double) * (size_t)(RS_TAB + capA + capB);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_restrict<false>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_restrict<false>, dim3(ncoarse), dim3(RS_WG), lds, s, fine_of, celems, felems, u, dudt, psi,
-                       uc, rdc, psic, tab, capA, restriction ? T_P : T_I, psi_new, met, invJ);
+    const int nfield = psi ? 3 : 2;
+    const size_t lds = sizeof(double) * (size_t)(capA / NV + capB / NV);
+    hipLaunchKernelGGL(k_restrict_w<false>, dim3(ncoarse * nfield), dim3(64), lds, s, fine_of, celems, felems, u,
+                       dudt, psi, uc, rdc, psic, tab, capA / NV, restriction ? T_P : T_I, psi_new, met, invJ, nfield);
     return hipGetLastError();
 }
 
 hipError_t launch_project(const int32_t *src_inv, int ntarget, const ElemInfo *tel, const ElemInfo *sel,
                           const double *u, double *ut, const double *tab, int capA, int capB, hipStream_t s) {
     if (ntarget == 0) return hipSuccess;
-    const size_t lds = sizeof(double) * (size_t)(RS_TAB + capA + capB);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_restrict<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_restrict<true>, dim3(ntarget), dim3(RS_WG), lds, s, src_inv, tel, sel, u, nullptr, nullptr,
-                       ut, nullptr, nullptr, tab, capA, T_P, 0, nullptr, 0.0);
+    const size_t lds = sizeof(double) * (size_t)(capA / NV + capB / NV);
+    hipLaunchKernelGGL(k_restrict_w<true>, dim3(ntarget), dim3(64), lds, s, src_inv, tel, sel, u, nullptr, nullptr,
+                       ut, nullptr, nullptr, tab, capA / NV, T_P, 0, nullptr, 0.0, 1);
     return hipGetLastError();
 }
 
