@@ -497,30 +497,62 @@ def _err(x, ref, s):
     return float(np.max(np.abs(x - ref)) / max(float(np.max(np.abs(ref))), s))
 
 
-def cpu_baseline(mesh, fo, co, u_nat, n_fine, n_est, E):
-    """The oracle as it stands on the host cores: the full fine residual, the full
-    coupled tau-estimate and the isolated sweep on half of the elements (every other
-    element), scaled to one step.  Returns the rate and the oracle outputs."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(mesh, fo, co, u_nat, n_fine, n_est, E, runs=5):
+    """The oracle as it stands on the host cores, median of `runs` timings after one
+    warm-up, on all the process's cores and on one core: the full fine residual and the
+    full coupled tau-estimate, and the isolated sweep on an evenly spaced sample of the
+    elements (256 on all cores, 32 on one core), scaled to one step.  Returns the rate
+    and the oracle outputs of the all-core run (the sweep on its sample)."""
     import oracle
     cores = len(os.sched_getaffinity(0))
-    t0 = time.perf_counter()
-    dudt = oracle.residual(mesh, fo, u_nat)
-    t_res = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    tn, tt, norms, _ = oracle.tau(mesh, fo, co, u_nat, dudt)
-    t_tau = time.perf_counter() - t0
-    sample = np.arange(0, E, 2)
-    t0 = time.perf_counter()
-    ten, tet, _ = oracle.sweep(mesh, fo, u_nat, dudt, elems=sample)
-    t_swp = (time.perf_counter() - t0) * E / len(sample)
-    t_step = t_res + t_tau + t_swp
-    base = {"value": n_fine / t_step / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
-            "sample": f"full fine residual ({t_res:.2f} s) and coupled tau ({t_tau:.2f} s) on the whole "
-                      f"mesh; isolated sweep on {len(sample)} of {E} elements ({t_swp * len(sample) / E:.1f} s), "
-                      f"scaled to all elements",
-            "residual_gdof_s": n_fine / t_res / 1e9,
-            "tau_estimates_per_s": n_est / t_swp}
-    return base, {"dudt": dudt, "tau_new": tn, "sweep_elems": sample, "te_new": ten, "te_trad": tet}
+
+    def leg(threads, nsample):
+        oracle.set_threads(threads)
+        sample = np.linspace(0, E - 1, nsample).astype(np.int64)
+        t = {"res": [], "tau": [], "swp": []}
+        out = None
+        for r in range(runs + 1):
+            t0 = time.perf_counter()
+            dudt = oracle.residual(mesh, fo, u_nat)
+            t1 = time.perf_counter()
+            tn, tt, norms, _ = oracle.tau(mesh, fo, co, u_nat, dudt)
+            t2 = time.perf_counter()
+            ten, tet, _ = oracle.sweep(mesh, fo, u_nat, dudt, elems=sample)
+            t3 = time.perf_counter()
+            if r == 0:  # warm-up
+                out = {"dudt": dudt, "tau_new": tn, "sweep_elems": sample, "te_new": ten, "te_trad": tet}
+                continue
+            t["res"].append(t1 - t0)
+            t["tau"].append(t2 - t1)
+            t["swp"].append((t3 - t2) * E / nsample)
+        med = {k: float(np.median(v)) for k, v in t.items()}
+        step = med["res"] + med["tau"] + med["swp"]
+        return {"value": n_fine / step / 1e9, "threads": threads, "ms_per_step": step * 1e3,
+                "residual_gdof_s": n_fine / med["res"] / 1e9, "coupled_tau_s": med["tau"],
+                "tau_estimates_per_s": n_est / med["swp"], "sweep_sample_elements": nsample}, out
+
+    allc, out = leg(cores, 256)
+    one, _ = leg(1, 32)
+    oracle.set_threads(cores)
+    base = {"value": allc["value"], "unit": "GDOF/s", "cores": cores, "kind": "oracle",
+            "sample": f"median of {runs} runs after one warm-up: the full fine residual and coupled tau on "
+                      f"the whole mesh, the isolated sweep on {allc['sweep_sample_elements']} of {E} evenly "
+                      f"spaced elements scaled to all elements; the one-core leg samples "
+                      f"{one['sweep_sample_elements']} elements",
+            "cpu_model": _cpu_model(), "statistic": "median", "runs": runs,
+            "residual_gdof_s": allc["residual_gdof_s"], "tau_estimates_per_s": allc["tau_estimates_per_s"],
+            "all_cores": allc, "one_core": one}
+    return base, out
 
 
 if __name__ == "__main__":

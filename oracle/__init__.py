@@ -105,6 +105,10 @@ def _load():
         lib.orc_flux_jacobian.restype = None
         lib.orc_numflux_jacobian.argtypes = [_D, _D, _D, ctypes.c_double, ctypes.c_int, _D, _D]
         lib.orc_numflux_jacobian.restype = None
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
+        lib.orc_max_threads.argtypes = []
+        lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -330,6 +334,15 @@ def tau(mesh: dict, fine_orders, coarse_orders, u, dudt, isolated: bool = False,
     _check(_load().orc_tau(ctypes.byref(m), _i(fo), _i(co), _d(u), _d(dudt), int(bool(isolated)),
                            int(restriction), _d(tn), _d(tt), _d(norms), _d(vn)), "tau")
     return tn, tt, norms, vn
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops over elements."""
+    _load().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
 
 
 def num_combos(order3) -> int:

@@ -33,6 +33,7 @@
  * complex-step derivatives is written _Complex_I. */
 #undef I
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -2129,3 +2130,7 @@ int orc_residual_vjp(const orc_mesh *m, const int *orders, const double *u, cons
     free(off);
     return 0;
 }
+
+/* Threads of the OpenMP loops over elements (timing on a stated core count). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }

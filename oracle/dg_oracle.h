@@ -105,6 +105,9 @@ int orc_tau_dual(const orc_mesh *m, const int *fine_orders, const int *coarse_or
 
 /* Number of coarse combinations of an element: prod_d max(1, N_d - 1). */
 int orc_num_combos(const int *order3);
+/* Threads of the OpenMP loops over elements (for timing on a stated core count). */
+void orc_set_threads(int n);
+int orc_max_threads(void);
 /* Isolated sweep over every coarse combination (c1 fastest, then c2, then c3;
  * c_d in 1..max(1,N_d-1)) for the listed elements (natural indices); restriction as
  * for orc_tau.

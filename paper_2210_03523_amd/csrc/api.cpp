@@ -333,8 +333,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     p->mesh = *mesh;
     p->E = E;
     hipGetDevice(&p->device);
-    dg_status st = device_tables(&p->tabs);
-    if (st) { destroy_plan(p); return st; }
+    dg_status st = DG_OK;
 
     // stable sort by (tile class, N1, N2, N3), ties by natural index
     std::vector<int64_t> perm(E);
@@ -586,6 +585,11 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
             p->rcapB = std::max(p->rcapB, NV * std::max((oc[0] + 1) * (oc[1] + 1) * (of[2] + 1),
                                                         (of[0] + 1) * (of[1] + 1) * (of[2] + 1)));
         }
+    }
+    // device work starts here: everything above is host code
+    if ((st = device_tables(&p->tabs))) {
+        destroy_plan(p);
+        return st;
     }
     Arena ar;
     ar.upload(&p->d_el, el);
