@@ -202,7 +202,7 @@ dg_status dg_sweep_layout(dg_plan fine, int64_t *combo_offset);
  * (c1, c2, c3), c_d in 1..max(1, N_d - 1), enumerated c1 fastest, the maxima
  * over nodes and variables of |tau_new| and |tau_trad| of the isolated estimate
  * (Euler or Navier-Stokes; on curved plans the element's geometry sampled at the
- * coarse nodes whatever the restriction).  Fine orders up to 8 (7 for Navier-Stokes
+ * coarse nodes whatever the restriction).  Fine orders up to 9 (7 for Navier-Stokes
  * and curved plans).
  *   u, dudt: device double, fine plan layout (dudt as for dg_tau_estimate,
  *            NULL computes it).
@@ -292,7 +292,7 @@ typedef struct {
  * the selected degrees and project the state onto it }.
  *   plan: in, the initial plan (never destroyed); out, the final plan, a new plan owned
  *         by the caller when any stage changed the degrees (intermediate plans are
- *         destroyed).  Box meshes; orders and select.nmax <= 8 (7 for Navier-Stokes).
+ *         destroyed).  Box meshes; orders and select.nmax <= 7 for Navier-Stokes.
  *   u: device double of capacity values: in, the state in the initial plan's layout;
  *      out, the state in the final plan's layout.  work: device double of capacity
  *      values (RK register and projection scratch).  capacity >= 5 E (nmax+1)^3 and
@@ -314,7 +314,7 @@ dg_status dg_adapt_dynamic(dg_plan *plan, double *u, double *work, int64_t capac
  * steps_after RK3 steps on the new plan.  Arguments as dg_adapt_dynamic, except
  *   orders: host int32 [E][3] (nullable), the degrees of the adaptation;
  *   select.max_decrease is ignored.
- * Errors as dg_adapt_dynamic (orders up to 8 on the initial plan; select.nmax up to 9). */
+ * Errors as dg_adapt_dynamic. */
 dg_status dg_adapt_static(dg_plan *plan, double *u, double *work, int64_t capacity, const dg_adapt_params *params,
                           int32_t *orders, dg_adapt_report *report, hipStream_t stream);
 

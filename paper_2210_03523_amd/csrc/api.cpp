@@ -145,6 +145,8 @@ struct dg_plan_s {
     int32_t *d_inv = nullptr;           // natural element -> plan position
     double *d_red = nullptr;            // reduction partials of dg_check_state
     int iso_first[NNMAX + 1] = {0}, iso_count[NNMAX + 1] = {0};
+    SweepTask *d_an = nullptr;          // anisotropic sweep jobs (element, pair) grouped by F3
+    int an_first[NNMAX + 1] = {0}, an_count[NNMAX + 1] = {0};
     void *d_arena = nullptr;  // the one device allocation every device buffer lives in
     // RK3 graphs: at most kGraphCache, each with the call count of its last use
     hipStream_t cap_stream = nullptr;
@@ -530,12 +532,15 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     }
 
     // sweep layout: combos per element; on box Euler plans isotropic elements (F <= 8)
-    // go to the fast path grouped by F and the others to the generic (p, c1, c2) work
-    // list; curved and Navier-Stokes plans take one task per (element, c1, c2, c3)
+    // go to the isotropic fast path grouped by F, anisotropic ones with every F_d <= 8 to
+    // the anisotropic kernel as (element, pair of x-orders) jobs grouped by F3, and the
+    // rest (a direction of 9 or 10 nodes) to the generic (p, c1, c2) work list; curved
+    // and Navier-Stokes plans take one task per (element, c1, c2, c3)
     p->combo_off.assign(E + 1, 0);
     std::vector<SweepTask> tasks;
     std::vector<int4> ctasks;
     std::vector<std::vector<int32_t>> iso(NNMAX + 1);
+    std::vector<std::vector<SweepTask>> an(NNMAX + 1);
     for (int i = 0; i < E; ++i) {
         int C[3];
         for (int d = 0; d < 3; ++d) C[d] = std::max(1, p->ord[3 * i + d] - 1);
@@ -557,6 +562,10 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
             iso[F].push_back(i);
             continue;
         }
+        if (el[i].n[0] <= 8 && el[i].n[1] <= 8 && el[i].n[2] <= 8) {
+            for (int pr = 0; pr < (C[0] + 1) / 2; ++pr) an[el[i].n[2]].push_back({i, pr, 0, 0});
+            continue;
+        }
         for (int c2 = 1; c2 <= C[1]; ++c2)
             for (int c1 = 1; c1 <= C[0]; ++c1) tasks.push_back({i, c1, c2, 0});
         int f2 = el[i].n[1], f3 = el[i].n[2];
@@ -566,10 +575,14 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     }
     p->ntasks = (int)tasks.size();
     std::vector<int32_t> iso_all;
+    std::vector<SweepTask> an_all;
     for (int F = 0; F <= NNMAX; ++F) {
         p->iso_first[F] = (int)iso_all.size();
         p->iso_count[F] = (int)iso[F].size();
         iso_all.insert(iso_all.end(), iso[F].begin(), iso[F].end());
+        p->an_first[F] = (int)an_all.size();
+        p->an_count[F] = (int)an[F].size();
+        an_all.insert(an_all.end(), an[F].begin(), an[F].end());
     }
 
     p->nctasks = (int)ctasks.size();
@@ -598,6 +611,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     ar.upload(&p->d_combo_off, p->combo_off);
     ar.upload(&p->d_tasks, tasks);
     ar.upload(&p->d_iso, iso_all);
+    ar.upload(&p->d_an, an_all);
     ar.upload(&p->d_wallx, wallx);
     ar.upload(&p->d_ctasks, ctasks);
     ar.upload(&p->d_xyz, p->xyz_h);
@@ -903,7 +917,6 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, int32_t r
     if (restriction != DG_RESTRICT_SAMPLE && restriction != DG_RESTRICT_L2)
         return fail(DG_EINVAL, "restriction must be DG_RESTRICT_SAMPLE or DG_RESTRICT_L2");
     DG_ALIGNED(u, dudt, te_new, te_trad);
-    if (p->max_order > 8) return fail(DG_EUNSUPPORTED, "the sweep supports fine orders up to 8");
     if ((p->curved || p->ns) && p->max_order > 7)
         return fail(DG_EUNSUPPORTED, "the sweep of curved and Navier-Stokes plans supports fine orders up to 7");
     if (!dudt) {
@@ -920,6 +933,10 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, int32_t r
                                     te_new, te_trad, stream));
         return DG_OK;
     }
+    for (int F = 2; F <= 8; ++F)
+        if (p->an_count[F])
+            HIP_TRY(launch_sweep_an(F, p->d_an + p->an_first[F], p->an_count[F], p->d_el, p->d_combo_off, u, dudt,
+                                    p->tabs.t64, p->geom, p->mesh.gamma, restriction, te_new, te_trad, stream));
     for (int F = 2; F <= 8; ++F)
         if (p->iso_count[F])
             HIP_TRY(launch_sweep_iso(F, p->d_iso + p->iso_first[F], p->iso_count[F], p->d_el, p->d_combo_off, u,
@@ -1112,9 +1129,9 @@ dg_status check_adapt(dg_plan p, const double *u, const double *work, int64_t ca
         return fail(DG_EINVAL, "degrees must satisfy 1 <= nmin <= nmax <= 9");
     if (std::isnan(sp.tau_max)) return fail(DG_EINVAL, "tau_max is NaN");
     if (dynamic && sp.max_decrease < 0) return fail(DG_EINVAL, "max_decrease must be >= 0");
-    const int sweep_max = p->ns ? 7 : 8;
+    const int sweep_max = p->ns ? 7 : 9;
     if (p->max_order > sweep_max || (dynamic && sp.nmax > sweep_max))
-        return fail(DG_EUNSUPPORTED, "every estimated plan needs orders <= 8 (7 for Navier-Stokes)");
+        return fail(DG_EUNSUPPORTED, "every estimated plan needs orders <= 7 for Navier-Stokes");
     const int64_t need = (int64_t)NV * p->E * (int64_t)(sp.nmax + 1) * (sp.nmax + 1) * (sp.nmax + 1);
     if (capacity < std::max<int64_t>(need, NV * p->n_nodes))
         return fail(DG_EINVAL, "capacity must hold 5 E (nmax+1)^3 doubles and the initial state");

@@ -149,6 +149,9 @@ struct SweepTask {
     int32_t p, c1, c2, pad;
 };
 
+hipError_t launch_sweep_an(int F3, const void *jobs, int njobs, const ElemInfo *el, const int64_t *combo_off,
+                           const double *u, const double *dudt, const double *tab, Geom g, double gamma,
+                           int restriction, double *te_new, double *te_trad, hipStream_t s);
 hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *elems, const int64_t *combo_off,
                               const double *u, const double *dudt, const double *tab, Geom g, double gamma,
                               int x1cap, int x2cap, int restriction, double *te_new, double *te_trad,

@@ -14,6 +14,8 @@
 //                time derivative, both forms and their maxima.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "euler.h"
 
@@ -149,6 +151,7 @@ __device__ __forceinline__ double wave_max(double x) {
 }
 
 constexpr int SW_WG = 256;
+constexpr int SW_NPL = 3;  // coarse nodes per lane: up to 768 (order 9 in every direction: 729)
 
 // Dynamic LDS layout (doubles): X1 [5][m1][f2][f3] (aliased by the flux stage
 // [5][m1 m2 m3]), X2Q and X2R [5][m1][m2][f3], red [2][4].
@@ -204,11 +207,11 @@ __global__ __launch_bounds__(SW_WG) void k_sweep(const SweepTask *__restrict__ t
         const int m3 = c3 + 1, M = m1 * m2 * m3;
         const double *I3 = tab + rt + moff(m3 - 1, f3 - 1);
         const double *w3 = tab + T_W + xoff(m3 - 1);
-        double q[2][NV], V[2][NV];
-        int loc[2][3];
-        bool ok[2];
+        double q[SW_NPL][NV], V[SW_NPL][NV];
+        int loc[SW_NPL][3];
+        bool ok[SW_NPL];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < SW_NPL; ++k) {
             const int t = tid + k * SW_WG;
             ok[k] = t < M;
             const int tt = ok[k] ? t : 0;
@@ -230,7 +233,7 @@ __global__ __launch_bounds__(SW_WG) void k_sweep(const SweepTask *__restrict__ t
         for (int d = 0; d < 3; ++d) {
             const double Ja = g.Ja[d];
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
+            for (int k = 0; k < SW_NPL; ++k) {
                 if (!ok[k]) continue;
                 double f[NV];
                 flux_axis(q[k], d, gm1, f);
@@ -240,7 +243,7 @@ __global__ __launch_bounds__(SW_WG) void k_sweep(const SweepTask *__restrict__ t
             __syncthreads();
             const double *Dm = tab + T_D + doff(mm[d] - 1);
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
+            for (int k = 0; k < SW_NPL; ++k) {
                 if (!ok[k]) continue;
                 const int id = loc[k][d];
                 const int tb = tid + k * SW_WG - id * st[d];
@@ -254,7 +257,7 @@ __global__ __launch_bounds__(SW_WG) void k_sweep(const SweepTask *__restrict__ t
         }
         double mx0 = 0.0, mx1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < SW_NPL; ++k) {
             if (!ok[k]) continue;
             const int ab = loc[k][0] + m1 * loc[k][1];
             const double Jw = g.J * w1[loc[k][0]] * w2[loc[k][1]] * w3[loc[k][2]];
@@ -559,6 +562,265 @@ static hipError_t launch_iso(const int32_t *elems, int nelem, const ElemInfo *el
     hipLaunchKernelGGL(k_sweep_iso<F>, dim3(njobs), dim3(256), lds, s, elems, njobs, el, combo_off, u, dudt, tab,
                        g, gamma, rt, te_new, te_trad);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- anisotropic sweep
+// The same scheme for elements whose fine orders differ between directions (fine node
+// counts F1, F2 <= 8 at run time, F3 <= 8 at compile time): a workgroup per (element,
+// pair of coarse x-orders c1 and C1 + 1 - c1), a lane per coarse z-line (a, B) with the
+// x-rows of the pair and the y-rows of every c2 stacked, the z direction in registers.
+template <int F3>
+__global__ __launch_bounds__(256) void k_sweep_an(const SweepTask *__restrict__ jobs, int njobs,
+                                                  const ElemInfo *__restrict__ el,
+                                                  const int64_t *__restrict__ combo_off,
+                                                  const double *__restrict__ u, const double *__restrict__ dudt,
+                                                  const double *__restrict__ tab, Geom g, double gamma, int rt,
+                                                  double *__restrict__ te_new, double *__restrict__ te_trad) {
+    constexpr int C3 = F3 > 2 ? F3 - 2 : 1;     // coarse z-orders
+    constexpr int MM = C3 + 1;                  // largest coarse z node count
+    constexpr int FM = 8;                       // largest fine x and y node count
+    constexpr int MX = FM - 1;                  // largest coarse x and y node count
+    constexpr int CM = FM - 2;                  // largest number of coarse x or y orders
+    constexpr int RMAX = CM + 3;                // rows of a pair of x-orders
+    constexpr int NL = 256;
+    extern __shared__ double lds[];
+    double *S = lds;                                                     // staging / X1
+    unsigned long long *slot = (unsigned long long *)(lds + 2 * NV * MM * NL);
+
+    const int job = xcd_remap(blockIdx.x, njobs);
+    const SweepTask T = jobs[job];
+    const int p = T.p, pair = T.c1;
+    const ElemInfo E = el[p];
+    const int F1 = E.n[0], F2 = E.n[1];
+    const int C1 = F1 > 2 ? F1 - 2 : 1, C2 = F2 > 2 ? F2 - 2 : 1;
+    const int SUMM = C2 * (C2 + 3) / 2;         // stacked coarse y-rows over every c2
+    const int X1S = F2 * F3 + 1;                // odd row stride of X1 (LDS banks)
+    const int cA = pair + 1, cBr = C1 - pair;
+    const int cB = cBr == cA ? 0 : cBr;
+    const int mA = cA + 1, mB = cB ? cB + 1 : 0;
+    const int rows = mA + mB;
+    const int lane = threadIdx.x;
+    const double gm1 = gamma - 1.0;
+
+    for (int i = lane; i < 2 * C3 * 2 * CM; i += NL) slot[i] = 0ull;
+
+    // x-interpolation: X1[f][v][row][j][k], row over the pair's stacked coarse x-nodes
+    {
+        const double *IA = tab + rt + moff(mA - 1, F1 - 1);
+        const double *IB = tab + rt + moff((mB ? mB : 2) - 1, F1 - 1);
+        const int nl = F2 * F3;
+        for (int r = lane; r < 2 * NV * nl; r += NL) {
+            const int f = r / (NV * nl), rem = r - f * NV * nl;  // rem = v*nl + jk
+            const double *src = (f == 0 ? u : dudt) + NV * E.noff + (int64_t)rem * F1;
+            double row[FM];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) row[i] = i < F1 ? src[i] : 0.0;
+            const int v = rem / nl, jk = rem - v * nl;
+            double *dst = S + ((f * NV + v) * RMAX) * X1S + jk;
+            for (int a = 0; a < mA; ++a) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    if (i < F1) acc += IA[a * F1 + i] * row[i];
+                dst[a * X1S] = acc;
+            }
+            for (int a = 0; a < mB; ++a) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    if (i < F1) acc += IB[a * F1 + i] * row[i];
+                dst[(mA + a) * X1S] = acc;
+            }
+        }
+    }
+    __syncthreads();
+
+    // lane -> z-line (a, B): a over the pair's rows, B over the stacked y-rows
+    const bool active = lane < rows * SUMM;
+    const int a = active ? lane % rows : 0;
+    const int B = active ? lane / rows : 0;
+    int c2 = 1, b = B;
+    while (c2 < C2 && b >= c2 + 1) {
+        b -= c2 + 1;
+        ++c2;
+    }
+    const int m2 = c2 + 1;
+    const int B0 = B - b;                       // first stacked row of this c2
+    const bool inA = a < mA;
+    const int c1 = inA ? cA : cB;
+    const int m1 = c1 + 1;
+    const int al = inA ? a : a - mA;            // local x-node
+    const int a0 = inA ? 0 : mA;                // first row of this c1
+
+    double Dx[MX], Dy[MX], I2r[FM];
+    {
+        const double *dx = tab + T_D + doff(m1 - 1) + al * m1;
+        const double *dy = tab + T_D + doff(m2 - 1) + b * m2;
+        const double *i2 = tab + rt + moff(m2 - 1, F2 - 1) + b * F2;
+#pragma unroll
+        for (int q = 0; q < MX; ++q) {
+            Dx[q] = q < m1 ? dx[q] : 0.0;
+            Dy[q] = q < m2 ? dy[q] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < FM; ++j) I2r[j] = j < F2 ? i2[j] : 0.0;
+    }
+    const double w12 = g.J * tab[T_W + xoff(m1 - 1) + al] * tab[T_W + xoff(m2 - 1) + b];
+
+    // y-interpolated z-lines of both fields
+    double XQ[NV][F3], XR[NV][F3];
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double *x1 = S + ((f * NV + v) * RMAX + a) * X1S;
+#pragma unroll
+            for (int k = 0; k < F3; ++k) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < FM; ++j)
+                    if (j < F2) acc += I2r[j] * x1[j + F2 * k];
+                if (f == 0) XQ[v][k] = acc; else XR[v][k] = acc;
+            }
+        }
+    }
+    __syncthreads();  // X1 is dead; S becomes the flux staging area
+
+    const double invJ = 1.0 / g.J;
+    const double Jax = g.Ja[0], Jay = g.Ja[1], Jaz = g.Ja[2];
+    const int grp = (inA ? 0 : 1) * CM + (c2 - 1);
+    double *Sx = S, *Sy = S + NV * MM * NL;
+
+#pragma unroll
+    for (int c3 = 1; c3 <= C3; ++c3) {
+        const int m3 = c3 + 1;
+        const double *I3 = tab + rt + moff(m3 - 1, F3 - 1);
+        const double *D3 = tab + T_D + doff(m3 - 1);
+        const double *w3 = tab + T_W + xoff(m3 - 1);
+        double V[NV][MM];
+#pragma unroll
+        for (int c = 0; c < MM; ++c)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) V[v][c] = 0.0;
+#pragma unroll
+        for (int cp = 0; cp < MM; ++cp) {
+            if (cp >= m3) continue;
+            double q[NV], fz[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < F3; ++k) acc += I3[cp * F3 + k] * XQ[v][k];
+                q[v] = acc;
+            }
+            flux_axis(q, 2, gm1, fz);
+#pragma unroll
+            for (int c = 0; c < MM; ++c) {
+                if (c >= m3) continue;
+                const double dz = D3[c * m3 + cp];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) V[v][c] += dz * (Jaz * fz[v]);
+            }
+            double fx[NV], fy[NV];
+            flux_axis(q, 0, gm1, fx);
+            flux_axis(q, 1, gm1, fy);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Sx[(v * MM + cp) * NL + lane] = Jax * fx[v];
+                Sy[(v * MM + cp) * NL + lane] = Jay * fy[v];
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int q = 0; q < MX; ++q) {
+                if (q >= m1) continue;
+                const int ln = (a0 + q) + rows * B;
+                const double d = Dx[q];
+#pragma unroll
+                for (int c = 0; c < MM; ++c) {
+                    if (c >= m3) continue;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) V[v][c] += d * Sx[(v * MM + c) * NL + ln];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < MX; ++q) {
+                if (q >= m2) continue;
+                const int ln = a + rows * (B0 + q);
+                const double d = Dy[q];
+#pragma unroll
+                for (int c = 0; c < MM; ++c) {
+                    if (c >= m3) continue;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) V[v][c] += d * Sy[(v * MM + c) * NL + ln];
+                }
+            }
+            double mx0 = 0.0, mx1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < MM; ++c) {
+                if (c >= m3) continue;
+                const double jw = w12 * w3[c];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double rc = 0.0;
+#pragma unroll
+                    for (int k = 0; k < F3; ++k) rc += I3[c * F3 + k] * XR[v][k];
+                    const double t = V[v][c] * invJ - rc;
+                    mx0 = fmax(mx0, fabs(t));
+                    mx1 = fmax(mx1, fabs(jw * t));
+                }
+            }
+            unsigned long long *sl = slot + ((c3 - 1) * 2 * CM + grp) * 2;
+            atomicMax(sl, (unsigned long long)__double_as_longlong(mx0));
+            atomicMax(sl + 1, (unsigned long long)__double_as_longlong(mx1));
+        }
+        __syncthreads();
+    }
+    for (int i = lane; i < 2 * CM * C3; i += NL) {
+        const int c3 = i / (2 * CM) + 1, gi = i % (2 * CM);
+        const int cc1 = gi < CM ? cA : cB;
+        const int cc2 = gi % CM + 1;
+        if (cc1 == 0 || cc2 > C2) continue;
+        const int64_t s = combo_off[p] + (cc1 - 1) + C1 * ((cc2 - 1) + C2 * (c3 - 1));
+        te_new[s] = __longlong_as_double((long long)slot[2 * i]);
+        te_trad[s] = __longlong_as_double((long long)slot[2 * i + 1]);
+    }
+}
+
+template <int F3>
+static hipError_t launch_an(const SweepTask *jobs, int njobs, const ElemInfo *el, const int64_t *combo_off,
+                            const double *u, const double *dudt, const double *tab, Geom g, double gamma, int rt,
+                            double *te_new, double *te_trad, hipStream_t s) {
+    constexpr int C3 = F3 > 2 ? F3 - 2 : 1;
+    constexpr int MM = C3 + 1;
+    const size_t x1 = (size_t)2 * NV * 9 * (8 * F3 + 1);
+    const size_t lds = sizeof(double) * std::max<size_t>((size_t)2 * NV * MM * 256, x1) +
+                       sizeof(unsigned long long) * 2 * C3 * 2 * 6;
+    hipError_t e = hipFuncSetAttribute((const void *)k_sweep_an<F3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sweep_an<F3>, dim3(njobs), dim3(256), lds, s, jobs, njobs, el, combo_off, u, dudt, tab, g,
+                       gamma, rt, te_new, te_trad);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_an(int F3, const void *jobs, int njobs, const ElemInfo *el, const int64_t *combo_off,
+                           const double *u, const double *dudt, const double *tab, Geom g, double gamma,
+                           int restriction, double *te_new, double *te_trad, hipStream_t s) {
+    if (njobs == 0) return hipSuccess;
+    const int rt = restriction ? T_P : T_I;
+    const SweepTask *j = (const SweepTask *)jobs;
+    switch (F3) {
+        case 2: return launch_an<2>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 3: return launch_an<3>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 4: return launch_an<4>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 5: return launch_an<5>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 6: return launch_an<6>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 7: return launch_an<7>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 8: return launch_an<8>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,

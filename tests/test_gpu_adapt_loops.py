@@ -130,7 +130,8 @@ def test_loop_arguments_refused():
     u = plan.to_plan(u0)
     with pytest.raises(dg.DGError, match="nstages"):
         dg.adapt_dynamic(plan, u, DT, K, 0, 1e-2)
-    with pytest.raises(dg.DGError, match="orders <= 8"):
-        dg.adapt_dynamic(plan, u, DT, K, 1, 1e-2, nmax=9)
+    ns = dg.Plan(wl.ns_mesh(mesh, 0.01, 0.72), orders)
+    with pytest.raises(dg.DGError, match="orders <= 7"):
+        dg.adapt_dynamic(ns, ns.to_plan(u0), DT, K, 1, 1e-2, nmax=8)
     with pytest.raises(dg.DGError, match="approach"):
         dg.adapt_static(plan, u, DT, K, 1, 1, 1e-2, approach=3)
