@@ -139,7 +139,7 @@ def _sweep_natural(plan, t):
 
 
 @pytest.mark.parametrize("shape,orng,seed", [((3, 2, 2), (1, 8), 21), ((2, 2, 2), (7, 7), 22),
-                                             ((4, 3, 1), (1, 4), 23)])
+                                             ((4, 3, 1), (1, 4), 23), ((2, 2, 1), (7, 9), 25)])
 def test_sweep(shape, orng, seed):
     mesh, fo, u, _ = _case(shape, *orng, seed, state="pulse")
     plan = dg.Plan(mesh, fo)
