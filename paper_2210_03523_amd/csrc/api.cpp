@@ -145,7 +145,8 @@ struct dg_plan_s {
     int32_t *d_inv = nullptr;           // natural element -> plan position
     double *d_red = nullptr;            // reduction partials of dg_check_state
     int iso_first[NNMAX + 1] = {0}, iso_count[NNMAX + 1] = {0};
-    SweepTask *d_an = nullptr;          // anisotropic sweep jobs (element, pair) grouped by F3
+    int4 *d_an = nullptr;               // anisotropic sweep jobs (element, pair, lane0, x1 offset)
+    int2 *d_anw = nullptr;              // their workgroups (first job, job count) grouped by F3
     int an_first[NNMAX + 1] = {0}, an_count[NNMAX + 1] = {0};
     void *d_arena = nullptr;  // the one device allocation every device buffer lives in
     // RK3 graphs: at most kGraphCache, each with the call count of its last use
@@ -540,7 +541,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     std::vector<SweepTask> tasks;
     std::vector<int4> ctasks;
     std::vector<std::vector<int32_t>> iso(NNMAX + 1);
-    std::vector<std::vector<SweepTask>> an(NNMAX + 1);
+    std::vector<std::vector<int2>> an(NNMAX + 1);  // (element, pair) per F3
     for (int i = 0; i < E; ++i) {
         int C[3];
         for (int d = 0; d < 3; ++d) C[d] = std::max(1, p->ord[3 * i + d] - 1);
@@ -563,7 +564,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
             continue;
         }
         if (el[i].n[0] <= 8 && el[i].n[1] <= 8 && el[i].n[2] <= 8) {
-            for (int pr = 0; pr < (C[0] + 1) / 2; ++pr) an[el[i].n[2]].push_back({i, pr, 0, 0});
+            for (int pr = 0; pr < (C[0] + 1) / 2; ++pr) an[el[i].n[2]].push_back(make_int2(i, pr));
             continue;
         }
         for (int c2 = 1; c2 <= C[1]; ++c2)
@@ -575,14 +576,33 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     }
     p->ntasks = (int)tasks.size();
     std::vector<int32_t> iso_all;
-    std::vector<SweepTask> an_all;
+    std::vector<int4> an_all;
+    std::vector<int2> anw_all;
     for (int F = 0; F <= NNMAX; ++F) {
         p->iso_first[F] = (int)iso_all.size();
         p->iso_count[F] = (int)iso[F].size();
         iso_all.insert(iso_all.end(), iso[F].begin(), iso[F].end());
-        p->an_first[F] = (int)an_all.size();
-        p->an_count[F] = (int)an[F].size();
-        an_all.insert(an_all.end(), an[F].begin(), an[F].end());
+        // pack the jobs of this F3 greedily into workgroups: a job takes rows * SUMM
+        // lanes and 2 * NV * rows * (F2 * F3 + 1) doubles of x-rows
+        p->an_first[F] = (int)anw_all.size();
+        int lanes = 0, x1 = 0;
+        for (const int2 &jb : an[F]) {
+            const int32_t *n = el[jb.x].n;
+            const int C1 = std::max(1, n[0] - 2), C2 = std::max(1, n[1] - 2);
+            const int cA = jb.y + 1, cB = C1 - jb.y == cA ? 0 : C1 - jb.y;
+            const int rows = cA + 1 + (cB ? cB + 1 : 0);
+            const int nl = rows * (C2 * (C2 + 3) / 2), nx = 2 * NV * rows * (n[1] * F + 1);
+            if (anw_all.size() == (size_t)p->an_first[F] || anw_all.back().y == AN_JOBS_MAX ||
+                lanes + nl > AN_LANES || x1 + nx > an_stage_doubles(F)) {
+                anw_all.push_back(make_int2((int)an_all.size(), 0));
+                lanes = x1 = 0;
+            }
+            an_all.push_back(make_int4(jb.x, jb.y, lanes, x1));
+            ++anw_all.back().y;
+            lanes += nl;
+            x1 += nx;
+        }
+        p->an_count[F] = (int)anw_all.size() - p->an_first[F];
     }
 
     p->nctasks = (int)ctasks.size();
@@ -612,6 +632,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     ar.upload(&p->d_tasks, tasks);
     ar.upload(&p->d_iso, iso_all);
     ar.upload(&p->d_an, an_all);
+    ar.upload(&p->d_anw, anw_all);
     ar.upload(&p->d_wallx, wallx);
     ar.upload(&p->d_ctasks, ctasks);
     ar.upload(&p->d_xyz, p->xyz_h);
@@ -935,8 +956,9 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, int32_t r
     }
     for (int F = 2; F <= 8; ++F)
         if (p->an_count[F])
-            HIP_TRY(launch_sweep_an(F, p->d_an + p->an_first[F], p->an_count[F], p->d_el, p->d_combo_off, u, dudt,
-                                    p->tabs.t64, p->geom, p->mesh.gamma, restriction, te_new, te_trad, stream));
+            HIP_TRY(launch_sweep_an(F, p->d_anw + p->an_first[F], p->an_count[F], p->d_an, p->d_el, p->d_combo_off,
+                                    u, dudt, p->tabs.t64, p->geom, p->mesh.gamma, restriction, te_new, te_trad,
+                                    stream));
     for (int F = 2; F <= 8; ++F)
         if (p->iso_count[F])
             HIP_TRY(launch_sweep_iso(F, p->d_iso + p->iso_first[F], p->iso_count[F], p->d_el, p->d_combo_off, u,

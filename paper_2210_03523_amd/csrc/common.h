@@ -149,9 +149,17 @@ struct SweepTask {
     int32_t p, c1, c2, pad;
 };
 
-hipError_t launch_sweep_an(int F3, const void *jobs, int njobs, const ElemInfo *el, const int64_t *combo_off,
-                           const double *u, const double *dudt, const double *tab, Geom g, double gamma,
-                           int restriction, double *te_new, double *te_trad, hipStream_t s);
+// Anisotropic sweep: workgroups (first job, job count) over jobs (element, pair of
+// x-orders, first lane, offset of the x-rows in the staging area), packed by the host
+// within AN_LANES lanes and an_stage_doubles(F3) doubles of x-rows, AN_JOBS_MAX jobs.
+constexpr int AN_LANES = 256;
+constexpr int AN_JOBS_MAX = 8;
+__host__ __device__ constexpr inline int an_stage_doubles(int F3) {
+    return 2 * NV * ((F3 > 2 ? F3 - 2 : 1) + 1) * AN_LANES;
+}
+hipError_t launch_sweep_an(int F3, const void *wgs, int nwg, const void *jobs, const ElemInfo *el,
+                           const int64_t *combo_off, const double *u, const double *dudt, const double *tab, Geom g,
+                           double gamma, int restriction, double *te_new, double *te_trad, hipStream_t s);
 hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *elems, const int64_t *combo_off,
                               const double *u, const double *dudt, const double *tab, Geom g, double gamma,
                               int x1cap, int x2cap, int restriction, double *te_new, double *te_trad,

@@ -566,12 +566,17 @@ static hipError_t launch_iso(const int32_t *elems, int nelem, const ElemInfo *el
 
 // ---------------------------------------------------------------------------- anisotropic sweep
 // The same scheme for elements whose fine orders differ between directions (fine node
-// counts F1, F2 <= 8 at run time, F3 <= 8 at compile time): a workgroup per (element,
-// pair of coarse x-orders c1 and C1 + 1 - c1), a lane per coarse z-line (a, B) with the
-// x-rows of the pair and the y-rows of every c2 stacked, the z direction in registers.
+// counts F1, F2 <= 8 at run time, F3 <= 8 at compile time): a job per (element, pair of
+// coarse x-orders c1 and C1 + 1 - c1), a lane per coarse z-line (a, B) of the job with
+// the x-rows of the pair and the y-rows of every c2 stacked, the z direction in
+// registers.  A workgroup runs up to AN_JOBS jobs side by side (the host packs them so
+// that their lanes, x-interpolated rows and maxima fit): job j holds lanes
+// [lane0_j, lane0_j + rows_j * SUMM_j) and its x-rows at offset x1_j of the staging area.
+constexpr int AN_JOBS = AN_JOBS_MAX;
+
 template <int F3>
-__global__ __launch_bounds__(256) void k_sweep_an(const SweepTask *__restrict__ jobs, int njobs,
-                                                  const ElemInfo *__restrict__ el,
+__global__ __launch_bounds__(256) void k_sweep_an(const int2 *__restrict__ wgs, int nwg,
+                                                  const int4 *__restrict__ jobs, const ElemInfo *__restrict__ el,
                                                   const int64_t *__restrict__ combo_off,
                                                   const double *__restrict__ u, const double *__restrict__ dudt,
                                                   const double *__restrict__ tab, Geom g, double gamma, int rt,
@@ -581,34 +586,32 @@ __global__ __launch_bounds__(256) void k_sweep_an(const SweepTask *__restrict__ 
     constexpr int FM = 8;                       // largest fine x and y node count
     constexpr int MX = FM - 1;                  // largest coarse x and y node count
     constexpr int CM = FM - 2;                  // largest number of coarse x or y orders
-    constexpr int RMAX = CM + 3;                // rows of a pair of x-orders
+    constexpr int NSL = 2 * C3 * 2 * CM;        // maxima slots of one job: [c3][c1 of the pair][c2][form]
     constexpr int NL = 256;
     extern __shared__ double lds[];
     double *S = lds;                                                     // staging / X1
     unsigned long long *slot = (unsigned long long *)(lds + 2 * NV * MM * NL);
 
-    const int job = xcd_remap(blockIdx.x, njobs);
-    const SweepTask T = jobs[job];
-    const int p = T.p, pair = T.c1;
-    const ElemInfo E = el[p];
-    const int F1 = E.n[0], F2 = E.n[1];
-    const int C1 = F1 > 2 ? F1 - 2 : 1, C2 = F2 > 2 ? F2 - 2 : 1;
-    const int SUMM = C2 * (C2 + 3) / 2;         // stacked coarse y-rows over every c2
-    const int X1S = F2 * F3 + 1;                // odd row stride of X1 (LDS banks)
-    const int cA = pair + 1, cBr = C1 - pair;
-    const int cB = cBr == cA ? 0 : cBr;
-    const int mA = cA + 1, mB = cB ? cB + 1 : 0;
-    const int rows = mA + mB;
+    const int2 W = wgs[xcd_remap(blockIdx.x, nwg)];
     const int lane = threadIdx.x;
     const double gm1 = gamma - 1.0;
 
-    for (int i = lane; i < 2 * C3 * 2 * CM; i += NL) slot[i] = 0ull;
+    for (int i = lane; i < W.y * NSL; i += NL) slot[i] = 0ull;
 
-    // x-interpolation: X1[f][v][row][j][k], row over the pair's stacked coarse x-nodes
-    {
+    // x-interpolation of every job: X1[f][v][row][j][k] at the job's offset
+    for (int jb = 0; jb < W.y; ++jb) {
+        const int4 J = jobs[W.x + jb];
+        const ElemInfo E = el[J.x];
+        const int F1 = E.n[0], F2 = E.n[1];
+        const int C1 = F1 > 2 ? F1 - 2 : 1;
+        const int cA = J.y + 1, cBr = C1 - J.y;
+        const int cB = cBr == cA ? 0 : cBr;
+        const int mA = cA + 1, mB = cB ? cB + 1 : 0, rows = mA + mB;
+        const int X1S = F2 * F3 + 1;            // odd row stride (LDS banks)
         const double *IA = tab + rt + moff(mA - 1, F1 - 1);
         const double *IB = tab + rt + moff((mB ? mB : 2) - 1, F1 - 1);
         const int nl = F2 * F3;
+        double *X1 = S + J.w;
         for (int r = lane; r < 2 * NV * nl; r += NL) {
             const int f = r / (NV * nl), rem = r - f * NV * nl;  // rem = v*nl + jk
             const double *src = (f == 0 ? u : dudt) + NV * E.noff + (int64_t)rem * F1;
@@ -616,7 +619,7 @@ __global__ __launch_bounds__(256) void k_sweep_an(const SweepTask *__restrict__ 
 #pragma unroll
             for (int i = 0; i < FM; ++i) row[i] = i < F1 ? src[i] : 0.0;
             const int v = rem / nl, jk = rem - v * nl;
-            double *dst = S + ((f * NV + v) * RMAX) * X1S + jk;
+            double *dst = X1 + ((f * NV + v) * rows) * X1S + jk;
             for (int a = 0; a < mA; ++a) {
                 double acc = 0.0;
 #pragma unroll
@@ -635,10 +638,23 @@ __global__ __launch_bounds__(256) void k_sweep_an(const SweepTask *__restrict__ 
     }
     __syncthreads();
 
-    // lane -> z-line (a, B): a over the pair's rows, B over the stacked y-rows
-    const bool active = lane < rows * SUMM;
-    const int a = active ? lane % rows : 0;
-    const int B = active ? lane / rows : 0;
+    // lane -> job, then z-line (a, B) of the job
+    int jb = 0;
+    while (jb + 1 < W.y && lane >= jobs[W.x + jb + 1].z) ++jb;
+    const int4 J = jobs[W.x + jb];
+    const ElemInfo E = el[J.x];
+    const int F1 = E.n[0], F2 = E.n[1];
+    const int C1 = F1 > 2 ? F1 - 2 : 1, C2 = F2 > 2 ? F2 - 2 : 1;
+    const int SUMM = C2 * (C2 + 3) / 2;         // stacked coarse y-rows over every c2
+    const int X1S = F2 * F3 + 1;
+    const int cA = J.y + 1, cBr = C1 - J.y;
+    const int cB = cBr == cA ? 0 : cBr;
+    const int mA = cA + 1, mB = cB ? cB + 1 : 0;
+    const int rows = mA + mB;
+    const int lj = lane - J.z;                  // lane within the job
+    const bool active = lj >= 0 && lj < rows * SUMM;
+    const int a = active ? lj % rows : 0;
+    const int B = active ? lj / rows : 0;
     int c2 = 1, b = B;
     while (c2 < C2 && b >= c2 + 1) {
         b -= c2 + 1;
@@ -650,7 +666,7 @@ __global__ __launch_bounds__(256) void k_sweep_an(const SweepTask *__restrict__ 
     const int c1 = inA ? cA : cB;
     const int m1 = c1 + 1;
     const int al = inA ? a : a - mA;            // local x-node
-    const int a0 = inA ? 0 : mA;                // first row of this c1
+    const int a0 = J.z + (inA ? 0 : mA);        // lane of the first row of this c1
 
     double Dx[MX], Dy[MX], I2r[FM];
     {
@@ -673,7 +689,7 @@ __global__ __launch_bounds__(256) void k_sweep_an(const SweepTask *__restrict__ 
     for (int f = 0; f < 2; ++f) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double *x1 = S + ((f * NV + v) * RMAX + a) * X1S;
+            const double *x1 = S + J.w + ((f * NV + v) * rows + a) * X1S;
 #pragma unroll
             for (int k = 0; k < F3; ++k) {
                 double acc = 0.0;
@@ -747,7 +763,7 @@ __global__ __launch_bounds__(256) void k_sweep_an(const SweepTask *__restrict__ 
 #pragma unroll
             for (int q = 0; q < MX; ++q) {
                 if (q >= m2) continue;
-                const int ln = a + rows * (B0 + q);
+                const int ln = J.z + a + rows * (B0 + q);
                 const double d = Dy[q];
 #pragma unroll
                 for (int c = 0; c < MM; ++c) {
@@ -771,54 +787,60 @@ __global__ __launch_bounds__(256) void k_sweep_an(const SweepTask *__restrict__ 
                     mx1 = fmax(mx1, fabs(jw * t));
                 }
             }
-            unsigned long long *sl = slot + ((c3 - 1) * 2 * CM + grp) * 2;
+            unsigned long long *sl = slot + jb * NSL + ((c3 - 1) * 2 * CM + grp) * 2;
             atomicMax(sl, (unsigned long long)__double_as_longlong(mx0));
             atomicMax(sl + 1, (unsigned long long)__double_as_longlong(mx1));
         }
         __syncthreads();
     }
-    for (int i = lane; i < 2 * CM * C3; i += NL) {
-        const int c3 = i / (2 * CM) + 1, gi = i % (2 * CM);
-        const int cc1 = gi < CM ? cA : cB;
+    // every job's maxima
+    for (int i = lane; i < W.y * (NSL / 2); i += NL) {
+        const int j = i / (NSL / 2), r = i - j * (NSL / 2);
+        const int4 Jj = jobs[W.x + j];
+        const ElemInfo Ej = el[Jj.x];
+        const int C1j = Ej.n[0] > 2 ? Ej.n[0] - 2 : 1, C2j = Ej.n[1] > 2 ? Ej.n[1] - 2 : 1;
+        const int cAj = Jj.y + 1, cBrj = C1j - Jj.y;
+        const int cBj = cBrj == cAj ? 0 : cBrj;
+        const int c3 = r / (2 * CM) + 1, gi = r % (2 * CM);
+        const int cc1 = gi < CM ? cAj : cBj;
         const int cc2 = gi % CM + 1;
-        if (cc1 == 0 || cc2 > C2) continue;
-        const int64_t s = combo_off[p] + (cc1 - 1) + C1 * ((cc2 - 1) + C2 * (c3 - 1));
-        te_new[s] = __longlong_as_double((long long)slot[2 * i]);
-        te_trad[s] = __longlong_as_double((long long)slot[2 * i + 1]);
+        if (cc1 == 0 || cc2 > C2j) continue;
+        const int64_t sidx_ = combo_off[Jj.x] + (cc1 - 1) + C1j * ((cc2 - 1) + C2j * (c3 - 1));
+        te_new[sidx_] = __longlong_as_double((long long)slot[j * NSL + 2 * r]);
+        te_trad[sidx_] = __longlong_as_double((long long)slot[j * NSL + 2 * r + 1]);
     }
 }
 
 template <int F3>
-static hipError_t launch_an(const SweepTask *jobs, int njobs, const ElemInfo *el, const int64_t *combo_off,
-                            const double *u, const double *dudt, const double *tab, Geom g, double gamma, int rt,
-                            double *te_new, double *te_trad, hipStream_t s) {
+static hipError_t launch_an(const int2 *wgs, int nwg, const int4 *jobs, const ElemInfo *el,
+                            const int64_t *combo_off, const double *u, const double *dudt, const double *tab, Geom g,
+                            double gamma, int rt, double *te_new, double *te_trad, hipStream_t s) {
     constexpr int C3 = F3 > 2 ? F3 - 2 : 1;
-    constexpr int MM = C3 + 1;
-    const size_t x1 = (size_t)2 * NV * 9 * (8 * F3 + 1);
-    const size_t lds = sizeof(double) * std::max<size_t>((size_t)2 * NV * MM * 256, x1) +
-                       sizeof(unsigned long long) * 2 * C3 * 2 * 6;
+    const size_t lds = sizeof(double) * (size_t)an_stage_doubles(F3) +
+                       sizeof(unsigned long long) * AN_JOBS * 2 * C3 * 2 * 6;
     hipError_t e = hipFuncSetAttribute((const void *)k_sweep_an<F3>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sweep_an<F3>, dim3(njobs), dim3(256), lds, s, jobs, njobs, el, combo_off, u, dudt, tab, g,
+    hipLaunchKernelGGL(k_sweep_an<F3>, dim3(nwg), dim3(256), lds, s, wgs, nwg, jobs, el, combo_off, u, dudt, tab, g,
                        gamma, rt, te_new, te_trad);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_an(int F3, const void *jobs, int njobs, const ElemInfo *el, const int64_t *combo_off,
-                           const double *u, const double *dudt, const double *tab, Geom g, double gamma,
-                           int restriction, double *te_new, double *te_trad, hipStream_t s) {
-    if (njobs == 0) return hipSuccess;
+hipError_t launch_sweep_an(int F3, const void *wgs, int nwg, const void *jobs, const ElemInfo *el,
+                           const int64_t *combo_off, const double *u, const double *dudt, const double *tab, Geom g,
+                           double gamma, int restriction, double *te_new, double *te_trad, hipStream_t s) {
+    if (nwg == 0) return hipSuccess;
     const int rt = restriction ? T_P : T_I;
-    const SweepTask *j = (const SweepTask *)jobs;
+    const int2 *w = (const int2 *)wgs;
+    const int4 *j = (const int4 *)jobs;
     switch (F3) {
-        case 2: return launch_an<2>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 3: return launch_an<3>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 4: return launch_an<4>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 5: return launch_an<5>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 6: return launch_an<6>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 7: return launch_an<7>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 8: return launch_an<8>(j, njobs, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 2: return launch_an<2>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 3: return launch_an<3>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 4: return launch_an<4>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 5: return launch_an<5>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 6: return launch_an<6>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 7: return launch_an<7>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 8: return launch_an<8>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
         default: return hipErrorInvalidValue;
     }
 }
