@@ -175,6 +175,9 @@ dg_status dg_residual_noalloc(dg_plan plan, const void *u, void *r, int32_t dtyp
  *   tau_new, tau_trad: device double, coarse plan layout (either may be NULL).
  *   norms: device double [E_coarse][2], max |tau_new|, max |tau_trad| over nodes and
  *          the 5 variables of each coarse plan element (may be NULL).
+ *   varnorms: device double [E_coarse][2][5], the same maxima per variable (max over
+ *          nodes of |tau_new| for each of the 5 conserved variables, then of |tau_trad|);
+ *          may be NULL.
  *   psi, eta: optional adjoint weighting (both NULL or both set): psi is a fine-layout
  *          device double field, the adjoint of a functional (e.g. dg_adjoint_solve's
  *          solution for dg_functional's gradient) for the residual of form psi_form;
@@ -191,7 +194,8 @@ dg_status dg_residual_noalloc(dg_plan plan, const void *u, void *r, int32_t dtyp
  * coarse order below the geometry order), DG_EHIP. */
 dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt,
                           int32_t isolated, int32_t restriction, double *tau_new, double *tau_trad,
-                          double *norms, const double *psi, int32_t psi_form, double *eta, hipStream_t stream);
+                          double *norms, double *varnorms, const double *psi, int32_t psi_form, double *eta,
+                          hipStream_t stream);
 
 /* Number of coarse combinations per fine plan element for the sweep:
  * prod_d max(1, N_d - 1); combo_offset[E+1] (host) gets their prefix sums. */

@@ -78,7 +78,8 @@ SIGNATURES = {
     "dg_plan_metrics": [_P, _P, _P],
     "dg_residual": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_residual_noalloc": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P],
-    "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P, _P],
+    "dg_tau_estimate": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_int32, _P,
+                        _P],
     "dg_residual_vjp": [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P],
     "dg_functional": [_P, _P, _P, _P, _P],
     "dg_sweep_layout": [_P, _I64P],
@@ -357,12 +358,13 @@ def residual_noalloc(plan: Plan, u, out, form: int = FORM_NEW, isolated: bool = 
 
 
 def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False, psi=None,
-                 restriction: int = RESTRICT_SAMPLE, psi_form: int = FORM_TRAD):
+                 restriction: int = RESTRICT_SAMPLE, psi_form: int = FORM_TRAD, varnorms: bool = False):
     """Returns (tau_new, tau_trad, norms[E,2]) in the coarse plan layout (float64), plus
     eta[E] (sum of (I psi_t) * tau_trad per coarse element, psi_t the traditional-form
     adjoint) when an adjoint weight psi is given; psi_form is the form of the residual psi
     is the adjoint of (FORM_NEW: psi is divided by the fine mass matrix first).
-    restriction: RESTRICT_SAMPLE (coarse-node sampling) or RESTRICT_L2 (L2 projection)."""
+    restriction: RESTRICT_SAMPLE (coarse-node sampling) or RESTRICT_L2 (L2 projection).
+    varnorms=True appends the per-variable maxima [E,2,5] to the returned tuple."""
     torch = _torch()
     if coarse.parent is not fine:
         raise DGError("coarse plan was not built from this fine plan")
@@ -373,9 +375,12 @@ def tau_estimate(fine: Plan, coarse: Plan, u, dudt=None, isolated: bool = False,
     tt = torch.empty_like(tn)
     norms = torch.empty((coarse.n_elems, 2), dtype=torch.float64, device="cuda")
     eta = torch.empty(coarse.n_elems, dtype=torch.float64, device="cuda") if psi is not None else None
+    vn = torch.empty((coarse.n_elems, 2, 5), dtype=torch.float64, device="cuda") if varnorms else None
     _call("dg_tau_estimate", fine.handle, coarse.handle, _ptr(u), _ptr(dudt), int(bool(isolated)),
-          int(restriction), _ptr(tn), _ptr(tt), _ptr(norms), _ptr(psi), int(psi_form), _ptr(eta), _stream())
-    return (tn, tt, norms) if psi is None else (tn, tt, norms, eta)
+          int(restriction), _ptr(tn), _ptr(tt), _ptr(norms), _ptr(vn), _ptr(psi), int(psi_form), _ptr(eta),
+          _stream())
+    out = (tn, tt, norms) if psi is None else (tn, tt, norms, eta)
+    return out + (vn,) if varnorms else out
 
 
 def residual_vjp(plan: Plan, u, v, form: int = FORM_NEW, isolated: bool = False):

@@ -886,12 +886,12 @@ dg_status dg_residual_noalloc(dg_plan p, const void *u, void *r, int32_t dtype, 
 }
 
 dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const double *dudt, int32_t isolated,
-                          int32_t restriction, double *tau_new, double *tau_trad, double *norms, const double *psi,
-                          int32_t psi_form, double *eta, hipStream_t stream) {
+                          int32_t restriction, double *tau_new, double *tau_trad, double *norms, double *varnorms,
+                          const double *psi, int32_t psi_form, double *eta, hipStream_t stream) {
     if (!fine || !coarse || !u) return fail(DG_EINVAL, "null argument");
     if (restriction != DG_RESTRICT_SAMPLE && restriction != DG_RESTRICT_L2)
         return fail(DG_EINVAL, "restriction must be DG_RESTRICT_SAMPLE or DG_RESTRICT_L2");
-    DG_ALIGNED(u, dudt, tau_new, tau_trad, norms, psi, eta);
+    DG_ALIGNED(u, dudt, tau_new, tau_trad, norms, varnorms, psi, eta);
     if (coarse->parent != fine) return fail(DG_EINVAL, "coarse plan was not built from this fine plan");
     if (fine->curved && !isolated)
         for (int i = 0; i < 3 * coarse->E; ++i)
@@ -901,7 +901,7 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
     if ((psi == nullptr) != (eta == nullptr)) return fail(DG_EINVAL, "psi and eta go together");
     if (psi_form != DG_FORM_NEW && psi_form != DG_FORM_TRAD)
         return fail(DG_EINVAL, "psi_form must be DG_FORM_NEW or DG_FORM_TRAD");
-    if (!tau_new && !tau_trad && !norms && !eta) return DG_OK;
+    if (!tau_new && !tau_trad && !norms && !varnorms && !eta) return DG_OK;
     if (!dudt) {
         EpiArgs epi{};
         epi.mode = EPI_RESIDUAL;
@@ -921,6 +921,7 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
     epi.out2 = tau_trad;
     epi.rdc = coarse->d_rdc;
     epi.norms = norms;
+    epi.varnorms = varnorms;
     epi.psic = psi ? coarse->d_psic : nullptr;
     epi.eta = eta;
     return run_residual<double>(coarse, coarse->d_uc, epi, stream);

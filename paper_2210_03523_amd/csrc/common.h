@@ -108,6 +108,7 @@ struct EpiArgs {
     double *norms;      // [E][2] (tau)
     const void *psic;   // restricted adjoint weight (tau, optional)
     double *eta;        // [E] sum of psic * tau_trad (tau, optional)
+    double *varnorms;   // [E][2][5] per-variable maxima of |tau_new|, |tau_trad| (tau, optional)
     const void *grad;   // Navier-Stokes: BR1 gradients [elem][3][5][node] (null for Euler)
     double mu, kappa;   // viscosity and heat conductivity
     const void *met;    // curved elements: metric terms [elem][10][node] (Ja^1, Ja^2, Ja^3, J)

@@ -512,11 +512,14 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
     // epilogue
     const T invJbox = (T)(1.0 / g.J);
     T mx[NPT][3];
+    T vmx[NPT][2][NV];  // per-variable |tau_new|, |tau_trad| (tau with varnorms)
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         mx[k][0] = T(0);
         mx[k][1] = T(0);
         mx[k][2] = T(0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) vmx[k][0][v] = vmx[k][1][v] = T(0);
         if (!ok[k]) continue;
         const T Jn = CURVED ? M[CURVED ? k : 0][9] : (T)g.J;
         const T invJ = CURVED ? T(1) / Jn : invJbox;
@@ -556,20 +559,23 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
                 if (tt) tt[x] = b;
                 mx[k][0] = fmax(mx[k][0], fabs(a));
                 mx[k][1] = fmax(mx[k][1], fabs(b));
+                vmx[k][0][v] = fabs(a);
+                vmx[k][1][v] = fabs(b);
                 if (epi.psic) mx[k][2] += ((const T *)epi.psic)[x] * b;
             }
         }
     }
-    if (epi.mode == EPI_TAU && (epi.norms || epi.eta)) {
-        // per-element maxima (and the eta sum): stage in LDS, then reduce each
-        // element's segment in a fixed order
+    if (epi.mode != EPI_TAU) return;
+    // Per-element reduction of three per-node values (two maxima and a sum): stage in
+    // LDS, then reduce each element's segment in a fixed order; emit(elem, m0, m1, s2).
+    auto reduce = [&](auto val, auto emit) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int t = tid + k * BS;
-            sF[0][t] = mx[k][0];
-            sF[1][t] = mx[k][1];
-            sF[2][t] = mx[k][2];
+            sF[0][t] = val(k, 0);
+            sF[1][t] = val(k, 1);
+            sF[2][t] = val(k, 2);
         }
         __syncthreads();
         if (tl.count == 1) {
@@ -585,13 +591,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
                 }
                 __syncthreads();
             }
-            if (tid == 0) {
-                if (epi.norms) {
-                    epi.norms[2 * (int64_t)tl.first] = (double)sF[0][0];
-                    epi.norms[2 * (int64_t)tl.first + 1] = (double)sF[1][0];
-                }
-                if (epi.eta) epi.eta[tl.first] = (double)sF[2][0];
-            }
+            if (tid == 0) emit((int64_t)tl.first, sF[0][0], sF[1][0], sF[2][0]);
         } else if (tid < tl.count) {
             T m0 = T(0), m1 = T(0), e2 = T(0);
             for (int i = 0; i < npe; ++i) {
@@ -599,13 +599,26 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
                 m1 = fmax(m1, sF[1][tid * npe + i]);
                 e2 += sF[2][tid * npe + i];
             }
-            if (epi.norms) {
-                epi.norms[2 * (int64_t)(tl.first + tid)] = (double)m0;
-                epi.norms[2 * (int64_t)(tl.first + tid) + 1] = (double)m1;
-            }
-            if (epi.eta) epi.eta[tl.first + tid] = (double)e2;
+            emit((int64_t)(tl.first + tid), m0, m1, e2);
         }
-    }
+    };
+    if (epi.norms || epi.eta)
+        reduce([&](int k, int j) { return mx[k][j]; },
+               [&](int64_t e, T m0, T m1, T e2) {
+                   if (epi.norms) {
+                       epi.norms[2 * e] = (double)m0;
+                       epi.norms[2 * e + 1] = (double)m1;
+                   }
+                   if (epi.eta) epi.eta[e] = (double)e2;
+               });
+    if (epi.varnorms)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            reduce([&](int k, int j) { return j < 2 ? vmx[k][j][v] : T(0); },
+                   [&](int64_t e, T m0, T m1, T) {
+                       epi.varnorms[(2 * e) * NV + v] = (double)m0;
+                       epi.varnorms[(2 * e + 1) * NV + v] = (double)m1;
+                   });
 }
 
 // One node per lane for tiles of up to 256 and 512 nodes (BS = 256, 512 lanes): the

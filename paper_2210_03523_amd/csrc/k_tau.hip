@@ -553,15 +553,16 @@ static hipError_t launch_iso(const int32_t *elems, int nelem, const ElemInfo *el
     constexpr int MM = C + 1;
     constexpr int NPAIR = (C + 1) / 2;
     const size_t lds = sizeof(double) * (size_t)(2 * NV * MM * 256) + sizeof(unsigned long long) * 2 * C * C * 2;
-    {  // per device: set on every launch (a host-side call)
-        hipError_t e = hipFuncSetAttribute((const void *)k_sweep_iso<F>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
-        if (e != hipSuccess) return e;
-    }
     const int njobs = nelem * NPAIR;
-    hipLaunchKernelGGL(k_sweep_iso<F>, dim3(njobs), dim3(256), lds, s, elems, njobs, el, combo_off, u, dudt, tab,
-                       g, gamma, rt, te_new, te_trad);
-    return hipGetLastError();
+    auto go = [&](auto kern) {
+        // per device: set on every launch (a host-side call)
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(njobs), dim3(256), lds, s, elems, njobs, el, combo_off, u, dudt, tab, g, gamma,
+                           rt, te_new, te_trad);
+        return hipGetLastError();
+    };
+    return go(k_sweep_iso<F>);
 }
 
 // ---------------------------------------------------------------------------- anisotropic sweep
@@ -574,7 +575,11 @@ static hipError_t launch_iso(const int32_t *elems, int nelem, const ElemInfo *el
 // [lane0_j, lane0_j + rows_j * SUMM_j) and its x-rows at offset x1_j of the staging area.
 constexpr int AN_JOBS = AN_JOBS_MAX;
 
-template <int F3>
+// SAMPLE (the sampling restriction): the coarse LGL end nodes are fine nodes, so the
+// z-interpolation at them is the fine value itself (the table rows there are unit
+// vectors) and is skipped.  (The isotropic kernel keeps the table rows: there the
+// shortcut changes the compiler's schedule into register spills.)
+template <int F3, bool SAMPLE>
 __global__ __launch_bounds__(256) void k_sweep_an(const int2 *__restrict__ wgs, int nwg,
                                                   const int4 *__restrict__ jobs, const ElemInfo *__restrict__ el,
                                                   const int64_t *__restrict__ combo_off,
@@ -724,6 +729,10 @@ __global__ __launch_bounds__(256) void k_sweep_an(const int2 *__restrict__ wgs, 
             double q[NV], fz[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
+                if (SAMPLE && (cp == 0 || cp == m3 - 1)) {
+                    q[v] = XQ[v][cp == 0 ? 0 : F3 - 1];
+                    continue;
+                }
                 double acc = 0.0;
 #pragma unroll
                 for (int k = 0; k < F3; ++k) acc += I3[cp * F3 + k] * XQ[v][k];
@@ -780,8 +789,12 @@ __global__ __launch_bounds__(256) void k_sweep_an(const int2 *__restrict__ wgs, 
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     double rc = 0.0;
+                    if (SAMPLE && (c == 0 || c == m3 - 1)) {
+                        rc = XR[v][c == 0 ? 0 : F3 - 1];
+                    } else {
 #pragma unroll
-                    for (int k = 0; k < F3; ++k) rc += I3[c * F3 + k] * XR[v][k];
+                        for (int k = 0; k < F3; ++k) rc += I3[c * F3 + k] * XR[v][k];
+                    }
                     const double t = V[v][c] * invJ - rc;
                     mx0 = fmax(mx0, fabs(t));
                     mx1 = fmax(mx1, fabs(jw * t));
@@ -818,12 +831,14 @@ static hipError_t launch_an(const int2 *wgs, int nwg, const int4 *jobs, const El
     constexpr int C3 = F3 > 2 ? F3 - 2 : 1;
     const size_t lds = sizeof(double) * (size_t)an_stage_doubles(F3) +
                        sizeof(unsigned long long) * AN_JOBS * 2 * C3 * 2 * 6;
-    hipError_t e = hipFuncSetAttribute((const void *)k_sweep_an<F3>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sweep_an<F3>, dim3(nwg), dim3(256), lds, s, wgs, nwg, jobs, el, combo_off, u, dudt, tab, g,
-                       gamma, rt, te_new, te_trad);
-    return hipGetLastError();
+    auto go = [&](auto kern) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), lds, s, wgs, nwg, jobs, el, combo_off, u, dudt, tab, g, gamma,
+                           rt, te_new, te_trad);
+        return hipGetLastError();
+    };
+    return rt == T_I ? go(k_sweep_an<F3, true>) : go(k_sweep_an<F3, false>);
 }
 
 hipError_t launch_sweep_an(int F3, const void *wgs, int nwg, const void *jobs, const ElemInfo *el,

@@ -109,16 +109,20 @@ def test_tau_estimate(shape, orng, seed, bc, flux, box, isolated):
     fine = dg.Plan(mesh, fo)
     coarse = fine.coarse(co)
     dudt = oracle.residual(mesh, fo, u)
-    tn_r, tt_r, n_r, _ = oracle.tau(mesh, fo, co, u, dudt, isolated=isolated)
+    tn_r, tt_r, n_r, vn_r = oracle.tau(mesh, fo, co, u, dudt, isolated=isolated)
     sn, st = tau_scale(mesh, fo, co, u, isolated=isolated)
     ud = fine.to_plan(u)
     for pass_dudt in (False, True):
-        tn, tt, norms = dg.tau_estimate(fine, coarse, ud, fine.to_plan(dudt) if pass_dudt else None,
-                                        isolated=isolated)
+        tn, tt, norms, vn = dg.tau_estimate(fine, coarse, ud, fine.to_plan(dudt) if pass_dudt else None,
+                                            isolated=isolated, varnorms=True)
         assert err(coarse.to_natural(tn), tn_r, sn) < TOL64
         assert err(coarse.to_natural(tt), tt_r, st) < TOL64
         nrm = coarse.elem_to_natural(norms.cpu().numpy())
         assert err(nrm[:, 0], n_r[:, 0], sn) < TOL64 and err(nrm[:, 1], n_r[:, 1], st) < TOL64
+        # per-variable maxima: their maximum over the variables is the element norm
+        vnn = coarse.elem_to_natural(vn.cpu().numpy())
+        assert err(vnn[:, 0], vn_r[:, 0], sn) < TOL64 and err(vnn[:, 1], vn_r[:, 1], st) < TOL64
+        assert np.array_equal(vnn.max(axis=2), nrm)
 
 
 def test_tau_vanishes_at_fine_orders():
