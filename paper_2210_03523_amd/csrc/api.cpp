@@ -614,9 +614,8 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
         for (int i = 0; i < E; ++i) {
             fine_of[i] = (int32_t)parent->inv[perm[i]];
             const int32_t *of = parent->ord.data() + 3 * fine_of[i], *oc = p->ord.data() + 3 * i;
-            p->rcapA = std::max(p->rcapA, NV * (oc[0] + 1) * (of[1] + 1) * (of[2] + 1));
-            p->rcapB = std::max(p->rcapB, NV * std::max((oc[0] + 1) * (oc[1] + 1) * (of[2] + 1),
-                                                        (of[0] + 1) * (of[1] + 1) * (of[2] + 1)));
+            p->rcapA = std::max(p->rcapA, restrict_cap_a(oc, of));
+            p->rcapB = std::max(p->rcapB, restrict_cap_b(oc, of));
         }
     }
     // device work starts here: everything above is host code
@@ -1037,8 +1036,8 @@ dg_status dg_project(dg_plan from, dg_plan to, const double *u, double *ut, hipS
     for (int p = 0; p < to->E; ++p) {
         const int32_t *t = &to->ord[3 * p];
         const int32_t *f = &from->ord[3 * from->inv[to->perm[p]]];
-        capA = std::max(capA, NV * (t[0] + 1) * (f[1] + 1) * (f[2] + 1));
-        capB = std::max(capB, NV * std::max((t[0] + 1) * (t[1] + 1) * (f[2] + 1), (f[0] + 1) * (f[1] + 1) * (f[2] + 1)));
+        capA = std::max(capA, restrict_cap_a(t, f));
+        capB = std::max(capB, restrict_cap_b(t, f));
     }
     HIP_TRY(launch_project(from->d_inv, to->E, to->d_el, from->d_el, u, ut, from->tabs.t64, capA, capB, stream));
     return DG_OK;

@@ -118,11 +118,20 @@ template <typename T>
 hipError_t launch_element(const Tile *tiles, int tile0, int ntiles, int npt, const ElemInfo *elems, const T *u,
                           const T *fflux, const T *tab, Geom g, PhysParams ph, EpiArgs epi, hipStream_t s);
 
-// capA, capB: LDS capacities (doubles) of the two staging buffers, 5 c1 f2 f3 and
-// 5 max(c1 c2 f3, f1 f2 f3) maximised over the coarse plan's elements.  restriction:
+// capA, capB: LDS capacities of the restriction, NV times the doubles of its two areas
+// maximised over the target plan's elements (restrict_cap_a, restrict_cap_b of the
+// target orders c and source orders f).  restriction:
 // 0 samples at the coarse nodes, 1 takes the exact L2 projection (also for the sweeps).
 // psi_new: psi is the new-form adjoint and is divided by the fine mass matrix J w w w
 // (met: curved metric terms [elem][10][node], or null with invJ = 1/J of box elements).
+// staging of one variable: the x-pass [c1][f2 f3], overwritten by the y-pass [c1 c2][f3]
+inline int restrict_cap_a(const int32_t *c, const int32_t *f) {
+    return NV * (c[0] + 1) * (f[1] > c[1] ? f[1] + 1 : c[1] + 1) * (f[2] + 1);
+}
+// the y and z operators, (c2 + 1)(f2 + 1) + (c3 + 1)(f3 + 1) doubles
+inline int restrict_cap_b(const int32_t *c, const int32_t *f) {
+    return NV * ((c[1] + 1) * (f[1] + 1) + (c[2] + 1) * (f[2] + 1));
+}
 hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
                            const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
                            double *psic, const double *tab, int capA, int capB, int restriction, int psi_new,

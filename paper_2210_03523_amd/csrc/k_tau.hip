@@ -31,12 +31,23 @@ namespace dgt {
 // psi_new: the adjoint weight is the adjoint of the new-form residual M^-1 F, i.e. M times
 // the traditional-form adjoint (M = J w_i w_j w_k of the fine element); it is divided by
 // M as it is loaded (box elements: J = 1/invJ; curved: J per node from met).
-// One wave per (coarse element, field): the fine x-lines of the element (lane = line
-// (j, k)) are loaded into registers for all five variables at once, so a wave keeps
-// its whole block in flight; then per variable the x-pass (registers -> LDS), the
-// y-pass and the z-pass (LDS -> the coarse plan layout), with barriers of one wave
-// only.  LDS: s1 [c1][f2 f3] and s2 [c1 c2][f3] of one variable.  Elements with more
-// than 64 fine x-lines (f2 f3 > 64) reload each variable's lines per pass.
+// m / n for 0 <= m < 2^20 and n <= 1000 through the float reciprocal of n: the exact
+// quotient of m + 1/2 sits at least 1/(2n) from an integer, far beyond the rounding of
+// the product, so the truncation is the integer quotient (integer division by a
+// run-time value takes tens of instructions).
+__device__ __forceinline__ int qdiv(int m, float inv_n) { return (int)(((float)m + 0.5f) * inv_n); }
+
+// One wave per (coarse element, field, variable): lane = fine x-line (j, k) of the
+// element, loaded into registers (8 doubles); the x-pass runs from registers into LDS,
+// the y-pass and the z-pass through LDS into the coarse plan layout, with barriers of
+// one wave only.  Small waves (a few KB of LDS and registers) keep many of them
+// resident per CU, so the loads of some overlap the passes of others (one workgroup of
+// five waves per (element, field) was slower: 98.6 against 77.7 us on 16^3 elements,
+// N = 7).  LDS: s1 [c1][f2 f3], overwritten by the y-pass result [c1 c2][f3] (held in
+// registers across a barrier), then the y and z operators (read there rather than
+// through the vector cache).  Elements with more than 64 fine x-lines (f2 f3 > 64) take
+// them 64 at a time.
+constexpr int RW_YIT = (NNMAX * NNMAX * NNMAX + 63) / 64;  // y-pass outputs per lane
 template <bool PROJECT>
 __global__ __launch_bounds__(64) void k_restrict_w(const int32_t *__restrict__ fine_of,
                                                    const ElemInfo *__restrict__ cel,
@@ -47,79 +58,87 @@ __global__ __launch_bounds__(64) void k_restrict_w(const int32_t *__restrict__ f
                                                    int cap1, int down, int psi_new, const double *__restrict__ met,
                                                    double invJ, int nfield) {
     extern __shared__ double lds[];
-    double *s1 = lds, *s2 = lds + cap1;
+    double *s1 = lds, *sI = lds + cap1;  // sI: the y and z operators
     const int w = xcd_remap(blockIdx.x, gridDim.x);
-    const int p = w / nfield, field = w - p * nfield;
+    const int pf = w / NV, v = w - pf * NV;
+    const int p = pf / nfield, field = pf - p * nfield;
+    const int lane = threadIdx.x;
     const ElemInfo C = cel[p];
     const ElemInfo F = fel[fine_of[PROJECT ? C.nat : p]];
     const int f1 = F.n[0], f2 = F.n[1], f3 = F.n[2], nl = f2 * f3, nef = f1 * nl;
     const int c1 = C.n[0], c2 = C.n[1], c3 = C.n[2], n12 = c1 * c2, nec = n12 * c3;
+    const float ic1 = 1.0f / c1, ic2 = 1.0f / c2, ic12 = 1.0f / n12;
     auto op = [&](int c, int f) { return tab + (c < f ? down : T_I) + moff(c - 1, f - 1); };
-    const double *I1 = op(c1, f1), *I2 = op(c2, f2), *I3 = op(c3, f3);
-    const double *src = (field == 0 ? u : field == 1 ? dudt : psi) + NV * F.noff;
-    double *dst = (field == 0 ? uc : field == 1 ? rdc : psic) + NV * C.noff;
-    const int lane = threadIdx.x;
+    const double *I1 = op(c1, f1);
+    {
+        const double *g2 = op(c2, f2), *g3 = op(c3, f3);
+        for (int t = lane; t < c2 * f2 + c3 * f3; t += 64)
+            sI[t] = t < c2 * f2 ? g2[t] : g3[t - c2 * f2];
+    }  // ordered before their first use by the barrier after the x-pass
+    const double *I2 = sI, *I3 = sI + c2 * f2;
+    const double *src = (field == 0 ? u : field == 1 ? dudt : psi) + NV * F.noff + (int64_t)v * nef;
+    double *dst = (field == 0 ? uc : field == 1 ? rdc : psic) + NV * C.noff + (int64_t)v * nec;
     const bool scale = !PROJECT && field == 2 && psi_new;
 
-    double ln[NV][NNMAX];
-    auto load = [&](int v, int jk) {
+    // x: s1[a + c1 jk] = sum_i I1[a, i] Q_v[i + f1 jk]
+    for (int l0 = 0; l0 < nl; l0 += 64) {
+        const int jk = l0 + lane;
+        if (jk >= nl) continue;
+        double ln[NNMAX];
         double sc = 1.0;
-        if (scale && jk < nl) {
-            const double *w1 = tab + T_W + xoff(f1 - 1), *w2 = tab + T_W + xoff(f2 - 1);
-            const double *w3 = tab + T_W + xoff(f3 - 1);
-            sc = 1.0 / (w2[jk % f2] * w3[jk / f2]);
+        if (scale) {
+            const double *w2 = tab + T_W + xoff(f2 - 1), *w3 = tab + T_W + xoff(f3 - 1);
+            const int k = qdiv(jk, 1.0f / f2);
+            sc = 1.0 / (w2[jk - k * f2] * w3[k]);
         }
 #pragma unroll
         for (int i = 0; i < NNMAX; ++i) {
-            double x = (jk < nl && i < f1) ? src[v * nef + f1 * jk + i] : 0.0;
-            if (scale && jk < nl && i < f1) {
+            double x = i < f1 ? src[f1 * jk + i] : 0.0;
+            if (scale && i < f1) {
                 const int node = i + f1 * jk;
                 const double ij = met ? 1.0 / met[10 * F.noff + 9 * nef + node] : invJ;
                 x *= ij * sc / tab[T_W + xoff(f1 - 1) + i];
             }
-            ln[v][i] = x;
+            ln[i] = x;
         }
-    };
-    const bool one = nl <= 64;
-    if (one) {
+        for (int a = 0; a < c1; ++a) {
+            double acc = 0.0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) load(v, lane);
+            for (int i = 0; i < NNMAX; ++i)
+                if (i < f1) acc += I1[a * f1 + i] * ln[i];
+            s1[a + c1 * jk] = acc;
+        }
     }
+    __syncthreads();
+    // y: s2[a + c1 (b + c2 k)] = sum_j I2[b, j] s1[a + c1 (j + f2 k)], s2 over s1
+    double yv[RW_YIT];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        // x: s1[a + c1 jk] = sum_i I1[a, i] Q_v[i + f1 jk]
-        for (int l0 = 0; l0 < nl; l0 += 64) {
-            const int jk = l0 + lane;
-            if (!one) load(v, jk);
-            if (jk < nl)
-                for (int a = 0; a < c1; ++a) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NNMAX; ++i)
-                        if (i < f1) acc += I1[a * f1 + i] * ln[v][i];
-                    s1[a + c1 * jk] = acc;
-                }
-        }
-        __syncthreads();
-        // y: s2[a + c1 (b + c2 k)] = sum_j I2[b, j] s1[a + c1 (j + f2 k)]
-        for (int t = lane; t < n12 * f3; t += 64) {
-            const int a = t % c1, b = (t / c1) % c2, k = t / n12;
+    for (int it = 0; it < RW_YIT; ++it) {
+        const int t = lane + 64 * it;
+        yv[it] = 0.0;
+        if (t < n12 * f3) {
+            const int r = qdiv(t, ic1), a = t - r * c1, k = qdiv(r, ic2), b = r - k * c2;
             const double *x = s1 + a + c1 * f2 * k;
             const double *wy = I2 + b * f2;
             double acc = 0.0;
             for (int j = 0; j < f2; ++j) acc += wy[j] * x[c1 * j];
-            s2[t] = acc;
+            yv[it] = acc;
         }
-        __syncthreads();
-        // z: the coarse plan layout, node a + c1 (b + c2 c)
-        for (int t = lane; t < nec; t += 64) {
-            const int ab = t % n12, c = t / n12;
-            const double *x = s2 + ab;
-            const double *wz = I3 + c * f3;
-            double acc = 0.0;
-            for (int k = 0; k < f3; ++k) acc += wz[k] * x[n12 * k];
-            dst[v * nec + t] = acc;
-        }
+    }
+    __syncthreads();
+    double *s2 = s1;
+#pragma unroll
+    for (int it = 0; it < RW_YIT; ++it)
+        if (lane + 64 * it < n12 * f3) s2[lane + 64 * it] = yv[it];
+    __syncthreads();
+    // z: the coarse plan layout, node a + c1 (b + c2 c)
+    for (int t = lane; t < nec; t += 64) {
+        const int c = qdiv(t, ic12), ab = t - c * n12;
+        const double *x = s2 + ab;
+        const double *wz = I3 + c * f3;
+        double acc = 0.0;
+        for (int k = 0; k < f3; ++k) acc += wz[k] * x[n12 * k];
+        dst[t] = acc;
     }
 }
 
@@ -130,7 +149,7 @@ hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *
     if (ncoarse == 0) return hipSuccess;
     const int nfield = psi ? 3 : 2;
     const size_t lds = sizeof(double) * (size_t)(capA / NV + capB / NV);
-    hipLaunchKernelGGL(k_restrict_w<false>, dim3(ncoarse * nfield), dim3(64), lds, s, fine_of, celems, felems, u,
+    hipLaunchKernelGGL(k_restrict_w<false>, dim3(ncoarse * nfield * NV), dim3(64), lds, s, fine_of, celems, felems, u,
                        dudt, psi, uc, rdc, psic, tab, capA / NV, restriction ? T_P : T_I, psi_new, met, invJ, nfield);
     return hipGetLastError();
 }
@@ -139,7 +158,7 @@ hipError_t launch_project(const int32_t *src_inv, int ntarget, const ElemInfo *t
                           const double *u, double *ut, const double *tab, int capA, int capB, hipStream_t s) {
     if (ntarget == 0) return hipSuccess;
     const size_t lds = sizeof(double) * (size_t)(capA / NV + capB / NV);
-    hipLaunchKernelGGL(k_restrict_w<true>, dim3(ntarget), dim3(64), lds, s, src_inv, tel, sel, u, nullptr, nullptr,
+    hipLaunchKernelGGL(k_restrict_w<true>, dim3(ntarget * NV), dim3(64), lds, s, src_inv, tel, sel, u, nullptr, nullptr,
                        ut, nullptr, nullptr, tab, capA / NV, T_P, 0, nullptr, 0.0, 1);
     return hipGetLastError();
 }
