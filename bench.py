@@ -429,8 +429,9 @@ def c5_leg(dg, torch, stream, steps=5, warmup=1, check=True, dt=1e-4):
            "fp32_batched_gdof_steps_s": nodes / (t32 * 1e-3) / 1e9,
            "fp64_plain_gdof_steps_s": nodes / (t64 * 1e-3) / 1e9,
            "speedup_fp32_batched_over_fp64_plain": t64 / t32,
-           "fp64_tau": {"what": "promotion of the FP32 batch state to FP64, then per problem the FP64 "
-                                "fine residual and the isolated sweep (both forms)",
+           "fp64_tau": {"what": "promotion of the FP32 batch state to FP64, then the FP64 fine residuals "
+                                "of all problems (one batched pass) and their isolated sweeps (both "
+                                "forms, one launch per fine node count)",
                         "promote_ms": t_prom, "sweep_ms": t_tau, "tau_estimates": combos,
                         "tau_estimates_per_s": combos / ((t_prom + t_tau) * 1e-3)}}
     if check:

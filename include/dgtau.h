@@ -478,11 +478,14 @@ dg_status dg_batch_residual(dg_batch batch, const void *const *u, void *const *r
  * u64[i] device double[5 n_nodes(i)] (plan layout, caller-owned, not overlapping u[i]).
  * An FP32 batch promotes (exactly) with one launch per problem; an FP64 batch copies. */
 dg_status dg_batch_to_f64(dg_batch batch, const void *const *u, double *const *u64, hipStream_t stream);
-/* FP64 isolated truncation-error map of every problem (as dg_tau_sweep with dudt =
- * NULL: each problem's FP64 non-isolated fine residual is computed first, into its
- * plan's scratch), problem after problem on the stream.  u64[i] as produced by
- * dg_batch_to_f64; te_new[i], te_trad[i] device double[combo_offset[E_i]] of problem
- * i's sweep layout (dg_sweep_layout).  Errors as dg_tau_sweep. */
+/* FP64 isolated truncation-error map of every problem (Section 2.3 and Section 2.4.2;
+ * as dg_tau_sweep with dudt = NULL): the FP64 non-isolated fine residual of every
+ * problem in one batched face and element pass, into each plan's scratch, then the
+ * sweeps of all problems in one launch per fine node count (the plans' work lists
+ * merged at batch creation).  u64[i] as produced by dg_batch_to_f64; te_new[i],
+ * te_trad[i] device double[combo_offset[E_i]] of problem i's sweep layout
+ * (dg_sweep_layout), 16-byte aligned.  The pointers are staged through the ring of
+ * descriptor slots of dg_batch_residual.  Errors as dg_tau_sweep. */
 dg_status dg_batch_tau_sweep(dg_batch batch, const double *const *u64, int32_t restriction,
                              double *const *te_new, double *const *te_trad, hipStream_t stream);
 /* nsteps Williamson RK3 steps of every problem (as dg_rk3_step), in place on u[i],

@@ -113,7 +113,7 @@ struct dg_plan_s {
     double *d_dudt = nullptr;    // fine time-derivative scratch (tau without dudt)
     // coarse plans
     dg_plan_s *parent = nullptr;
-    int32_t *d_fine_of = nullptr;
+    ElemInfo *d_fine_el = nullptr;  // coarse plans: the fine element's record per element (foff unused)
     double *d_uc = nullptr, *d_rdc = nullptr, *d_psic = nullptr;
     bool ns = false;              // Navier-Stokes plan
     void *d_grad = nullptr;       // BR1 gradients [elem][3][5][node], sized for doubles
@@ -140,13 +140,15 @@ struct dg_plan_s {
     int64_t *d_combo_off = nullptr;
     SweepTask *d_tasks = nullptr;
     int ntasks = 0, x1cap = 0, x2cap = 0, max_order = 0;
-    int32_t *d_iso = nullptr;           // isotropic elements grouped by fine node count F
+    int2 *d_iso = nullptr;              // isotropic elements (0, element) grouped by fine node count F
     int32_t *d_sel = nullptr;           // degree selection: [E][3] intermediate of the jump steps
     int32_t *d_inv = nullptr;           // natural element -> plan position
     double *d_red = nullptr;            // reduction partials of dg_check_state
     int iso_first[NNMAX + 1] = {0}, iso_count[NNMAX + 1] = {0};
     int4 *d_an = nullptr;               // anisotropic sweep jobs (element, pair, lane0, x1 offset)
-    int2 *d_anw = nullptr;              // their workgroups (first job, job count) grouped by F3
+    int4 *d_anw = nullptr;              // their workgroups (first job, job count, 0, 0) grouped by F3
+    std::vector<int2> h_iso;            // host copies of the three sweep lists (for batches)
+    std::vector<int4> h_an, h_anw;
     int an_first[NNMAX + 1] = {0}, an_count[NNMAX + 1] = {0};
     void *d_arena = nullptr;  // the one device allocation every device buffer lives in
     // RK3 graphs: at most kGraphCache, each with the call count of its last use
@@ -540,7 +542,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     p->combo_off.assign(E + 1, 0);
     std::vector<SweepTask> tasks;
     std::vector<int4> ctasks;
-    std::vector<std::vector<int32_t>> iso(NNMAX + 1);
+    std::vector<std::vector<int2>> iso(NNMAX + 1);
     std::vector<std::vector<int2>> an(NNMAX + 1);  // (element, pair) per F3
     for (int i = 0; i < E; ++i) {
         int C[3];
@@ -560,7 +562,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
         }
         const int F = el[i].n[0];
         if (F == el[i].n[1] && F == el[i].n[2] && F <= 8) {
-            iso[F].push_back(i);
+            iso[F].push_back(make_int2(0, i));
             continue;
         }
         if (el[i].n[0] <= 8 && el[i].n[1] <= 8 && el[i].n[2] <= 8) {
@@ -575,9 +577,9 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
         p->x2cap = std::max(p->x2cap, NV * m1 * m2 * f3);
     }
     p->ntasks = (int)tasks.size();
-    std::vector<int32_t> iso_all;
+    std::vector<int2> iso_all;
     std::vector<int4> an_all;
-    std::vector<int2> anw_all;
+    std::vector<int4> anw_all;
     for (int F = 0; F <= NNMAX; ++F) {
         p->iso_first[F] = (int)iso_all.size();
         p->iso_count[F] = (int)iso[F].size();
@@ -594,7 +596,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
             const int nl = rows * (C2 * (C2 + 3) / 2), nx = 2 * NV * rows * (n[1] * F + 1);
             if (anw_all.size() == (size_t)p->an_first[F] || anw_all.back().y == AN_JOBS_MAX ||
                 lanes + nl > AN_LANES || x1 + nx > an_stage_doubles(F)) {
-                anw_all.push_back(make_int2((int)an_all.size(), 0));
+                anw_all.push_back(make_int4((int)an_all.size(), 0, 0, 0));
                 lanes = x1 = 0;
             }
             an_all.push_back(make_int4(jb.x, jb.y, lanes, x1));
@@ -608,12 +610,16 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     p->nctasks = (int)ctasks.size();
     std::vector<float> met32(met_h.begin(), met_h.end()), fmet32(fmet_h.begin(), fmet_h.end());
     // coarse plans: the fine element of every coarse element, restriction LDS capacities
-    std::vector<int32_t> fine_of;
+    std::vector<ElemInfo> fine_el;
     if (parent) {
-        fine_of.resize(E);
+        fine_el.resize(E);
         for (int i = 0; i < E; ++i) {
-            fine_of[i] = (int32_t)parent->inv[perm[i]];
-            const int32_t *of = parent->ord.data() + 3 * fine_of[i], *oc = p->ord.data() + 3 * i;
+            const int64_t fi = parent->inv[perm[i]];
+            const int32_t *of = parent->ord.data() + 3 * fi, *oc = p->ord.data() + 3 * i;
+            for (int d = 0; d < 3; ++d) fine_el[i].n[d] = of[d] + 1;
+            fine_el[i].nat = (int32_t)perm[i];
+            fine_el[i].noff = parent->noff[fi];
+            fine_el[i].foff = 0;
             p->rcapA = std::max(p->rcapA, restrict_cap_a(oc, of));
             p->rcapB = std::max(p->rcapB, restrict_cap_b(oc, of));
         }
@@ -630,6 +636,9 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     ar.upload(&p->d_combo_off, p->combo_off);
     ar.upload(&p->d_tasks, tasks);
     ar.upload(&p->d_iso, iso_all);
+    p->h_iso = iso_all;
+    p->h_an = an_all;
+    p->h_anw = anw_all;
     ar.upload(&p->d_an, an_all);
     ar.upload(&p->d_anw, anw_all);
     ar.upload(&p->d_wallx, wallx);
@@ -641,7 +650,7 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
     ar.upload(&p->d_fmet32, fmet32);
     ar.upload(&p->d_fmo, fmo);
     ar.upload(&p->d_inv, std::vector<int32_t>(p->inv.begin(), p->inv.end()));
-    ar.upload(&p->d_fine_of, fine_of);
+    ar.upload(&p->d_fine_el, fine_el);
     // the face buffer also carries the 15-value BR1 face data of curved Navier-Stokes plans
     const int64_t ff_alloc = std::max<int64_t>(1, (p->curved && p->ns ? 3 : 1) * p->ff_len);
     ar.scratch(&p->d_ff, sizeof(double) * ff_alloc);
@@ -909,7 +918,7 @@ dg_status dg_tau_estimate(dg_plan fine, dg_plan coarse, const double *u, const d
         if (st) return st;
         dudt = fine->d_dudt;
     }
-    HIP_TRY(launch_restrict(coarse->d_fine_of, coarse->E, coarse->d_el, fine->d_el, u, dudt, psi, coarse->d_uc,
+    HIP_TRY(launch_restrict(coarse->E, coarse->d_el, coarse->d_fine_el, u, dudt, psi, coarse->d_uc,
                             coarse->d_rdc, coarse->d_psic, fine->tabs.t64, coarse->rcapA, coarse->rcapB,
                             restriction, psi && psi_form == DG_FORM_NEW, fine->curved ? fine->d_met64 : nullptr,
                             1.0 / fine->geom.J, stream));
@@ -954,16 +963,15 @@ dg_status dg_tau_sweep(dg_plan p, const double *u, const double *dudt, int32_t r
                                     te_new, te_trad, stream));
         return DG_OK;
     }
+    const SweepProb one{p->d_el, p->d_combo_off, u, dudt, te_new, te_trad, p->geom, p->mesh.gamma};
     for (int F = 2; F <= 8; ++F)
         if (p->an_count[F])
-            HIP_TRY(launch_sweep_an(F, p->d_anw + p->an_first[F], p->an_count[F], p->d_an, p->d_el, p->d_combo_off,
-                                    u, dudt, p->tabs.t64, p->geom, p->mesh.gamma, restriction, te_new, te_trad,
-                                    stream));
+            HIP_TRY(launch_sweep_an(F, p->d_anw + p->an_first[F], p->an_count[F], p->d_an, one, nullptr,
+                                    p->tabs.t64, restriction, stream));
     for (int F = 2; F <= 8; ++F)
         if (p->iso_count[F])
-            HIP_TRY(launch_sweep_iso(F, p->d_iso + p->iso_first[F], p->iso_count[F], p->d_el, p->d_combo_off, u,
-                                     dudt, p->tabs.t64, p->geom, p->mesh.gamma, restriction, te_new, te_trad,
-                                     stream));
+            HIP_TRY(launch_sweep_iso(F, p->d_iso + p->iso_first[F], p->iso_count[F], one, nullptr, p->tabs.t64,
+                                     restriction, stream));
     HIP_TRY(launch_sweep_tasks(p->d_tasks, p->ntasks, p->d_el, p->d_combo_off, u, dudt, p->tabs.t64, p->geom,
                                p->mesh.gamma, p->x1cap, p->x2cap, restriction, te_new, te_trad, stream));
     return DG_OK;
@@ -1524,7 +1532,17 @@ struct dg_batch_s {
     std::map<BatchKey, Graph> graphs;
     uint64_t graph_clock = 0;
     bool from_cache = false;  // schedule taken from the autotuner's cache
+    // Isolated sweep of every problem in one launch per fine node count: the plans' work
+    // lists merged, each record carrying its problem; sweep descriptors staged per call
+    // through the ring slot of the call (d_sdesc, pinned h_sdesc).
+    int2 *d_siso = nullptr;
+    int4 *d_san = nullptr, *d_sanw = nullptr;
+    int siso_first[NNMAX + 1] = {0}, siso_count[NNMAX + 1] = {0};
+    int sanw_first[NNMAX + 1] = {0}, sanw_count[NNMAX + 1] = {0};
+    void *d_sdesc = nullptr;
+    void *h_sdesc = nullptr;
     size_t desc_bytes() const { return sizeof(ProbDesc<double>) * plans.size(); }
+    size_t sdesc_bytes() const { return sizeof(SweepProb) * plans.size(); }
     void *desc_slot(int k) const { return (char *)d_desc + desc_bytes() * k; }
 };
 
@@ -1540,6 +1558,11 @@ void destroy_batch(dg_batch b) {
     if (b->d_faces) (void)hipFree(b->d_faces);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->h_desc) (void)hipHostFree(b->h_desc);
+    if (b->d_siso) (void)hipFree(b->d_siso);
+    if (b->d_san) (void)hipFree(b->d_san);
+    if (b->d_sanw) (void)hipFree(b->d_sanw);
+    if (b->d_sdesc) (void)hipFree(b->d_sdesc);
+    if (b->h_sdesc) (void)hipHostFree(b->h_sdesc);
     delete b;
 }
 
@@ -1593,6 +1616,32 @@ dg_status batch_pass(dg_batch b, const ProbDesc<T> *probs, EpiArgs epi, hipStrea
     HIP_TRY(launch_face_batch<T>(b->d_faces, b->nfaces, probs, tab, b->face_grid, s));
     HIP_TRY(launch_elem_batch<T>(b->d_tiles, b->ntiles, probs, tab, b->elem_grid, b->shape, epi, s));
     return DG_OK;
+}
+
+// The plans' isolated-sweep work lists, merged problem by problem per fine node count.
+dg_status merge_sweep_lists(dg_batch b) {
+    std::vector<int2> iso;
+    std::vector<int4> an, anw;
+    for (int F = 0; F <= NNMAX; ++F) {
+        b->siso_first[F] = (int)iso.size();
+        b->sanw_first[F] = (int)anw.size();
+        for (int pi = 0; pi < (int)b->plans.size(); ++pi) {
+            const dg_plan p = b->plans[pi];
+            for (int k = p->iso_first[F]; k < p->iso_first[F] + p->iso_count[F]; ++k)
+                iso.push_back(make_int2(pi, p->h_iso[k].y));
+            for (int w = p->an_first[F]; w < p->an_first[F] + p->an_count[F]; ++w) {
+                const int4 W = p->h_anw[w];
+                anw.push_back(make_int4((int)an.size(), W.y, pi, 0));
+                an.insert(an.end(), p->h_an.begin() + W.x, p->h_an.begin() + W.x + W.y);
+            }
+        }
+        b->siso_count[F] = (int)iso.size() - b->siso_first[F];
+        b->sanw_count[F] = (int)anw.size() - b->sanw_first[F];
+    }
+    dg_status st = upload(&b->d_siso, iso);
+    if (!st) st = upload(&b->d_san, an);
+    if (!st) st = upload(&b->d_sanw, anw);
+    return st;
 }
 
 dg_status set_tiles(dg_batch b, int cap) {
@@ -1786,6 +1835,10 @@ dg_status dg_batch_create(const dg_plan *plans, int32_t n, int32_t dtype, dg_bat
             }
         }
     }
+    if (!st) st = merge_sweep_lists(b);
+    if (!st && (hipMalloc(&b->d_sdesc, b->sdesc_bytes() * kEagerRing) != hipSuccess ||
+                hipHostMalloc(&b->h_sdesc, b->sdesc_bytes() * kEagerRing, hipHostMallocDefault) != hipSuccess))
+        st = fail(DG_ENOMEM, "sweep descriptor allocation failed");
     if (!st && (hipMalloc(&b->d_desc, b->desc_bytes() * (kGraphCache + kEagerRing)) != hipSuccess ||
                 hipHostMalloc(&b->h_desc, b->desc_bytes() * kEagerRing, hipHostMallocDefault) != hipSuccess))
         st = fail(DG_ENOMEM, "device or pinned host allocation failed");
@@ -1863,14 +1916,50 @@ dg_status dg_batch_to_f64(dg_batch b, const void *const *u, double *const *u64, 
 dg_status dg_batch_tau_sweep(dg_batch b, const double *const *u64, int32_t restriction, double *const *te_new,
                              double *const *te_trad, hipStream_t stream) {
     if (!b || !u64 || !te_new || !te_trad) return fail(DG_EINVAL, "null argument");
-    for (size_t i = 0; i < b->plans.size(); ++i)
-        if (!u64[i] || !te_new[i] || !te_trad[i]) return fail(DG_EINVAL, "null state or map pointer");
-    // one problem after the other: the FP64 fine residual of each problem (into its
-    // plan's time-derivative scratch), then its isolated sweep
-    for (size_t i = 0; i < b->plans.size(); ++i) {
-        const dg_status st = dg_tau_sweep(b->plans[i], u64[i], nullptr, restriction, te_new[i], te_trad[i], stream);
-        if (st) return st;
+    if (restriction != DG_RESTRICT_SAMPLE && restriction != DG_RESTRICT_L2)
+        return fail(DG_EINVAL, "restriction must be DG_RESTRICT_SAMPLE or DG_RESTRICT_L2");
+    const size_t n = b->plans.size();
+    for (size_t i = 0; i < n; ++i)
+        if (!u64[i] || !te_new[i] || !te_trad[i] || !aligned(u64[i]) || !aligned(te_new[i]) || !aligned(te_trad[i]))
+            return fail(DG_EINVAL, "bad state or map pointer (null or not 16-byte aligned)");
+    // descriptors of this call staged through the next ring slot, as for dg_batch_residual
+    const int k = b->ring_next;
+    b->ring_next = (k + 1) % kEagerRing;
+    if (b->ring_used[k]) HIP_TRY(hipEventSynchronize(b->ring_ev[k]));
+    // the FP64 fine residual of every problem, one batched face and element pass, into
+    // each plan's time-derivative scratch
+    std::vector<void *> uu(n), rr(n);
+    for (size_t i = 0; i < n; ++i) {
+        uu[i] = (void *)u64[i];
+        rr[i] = b->plans[i]->d_dudt;
     }
+    auto pd = prob_descs<double>(b, uu.data(), rr.data(), nullptr);
+    void *hs = (char *)b->h_desc + b->desc_bytes() * k;
+    void *ds = b->desc_slot((int)kGraphCache + k);
+    memcpy(hs, pd.data(), b->desc_bytes());
+    HIP_TRY(hipMemcpyAsync(ds, hs, b->desc_bytes(), hipMemcpyHostToDevice, stream));
+    EpiArgs epi{};
+    epi.mode = EPI_RESIDUAL;
+    dg_status st = batch_pass<double>(b, (const ProbDesc<double> *)ds, epi, stream);
+    if (st) return st;
+    // every problem's sweep, one launch per fine node count
+    SweepProb *hsp = (SweepProb *)((char *)b->h_sdesc + b->sdesc_bytes() * k);
+    SweepProb *dsp = (SweepProb *)((char *)b->d_sdesc + b->sdesc_bytes() * k);
+    for (size_t i = 0; i < n; ++i) {
+        const dg_plan p = b->plans[i];
+        hsp[i] = SweepProb{p->d_el, p->d_combo_off, u64[i], p->d_dudt, te_new[i], te_trad[i], p->geom, p->mesh.gamma};
+    }
+    HIP_TRY(hipMemcpyAsync(dsp, hsp, b->sdesc_bytes(), hipMemcpyHostToDevice, stream));
+    const SweepProb none{};
+    const double *tab = b->plans[0]->tabs.t64;
+    for (int F = 2; F <= 8; ++F)
+        HIP_TRY(launch_sweep_an(F, b->d_sanw + b->sanw_first[F], b->sanw_count[F], b->d_san, none, dsp, tab,
+                                restriction, stream));
+    for (int F = 2; F <= 8; ++F)
+        HIP_TRY(launch_sweep_iso(F, b->d_siso + b->siso_first[F], b->siso_count[F], none, dsp, tab, restriction,
+                                 stream));
+    HIP_TRY(hipEventRecord(b->ring_ev[k], stream));
+    b->ring_used[k] = true;
     return DG_OK;
 }
 

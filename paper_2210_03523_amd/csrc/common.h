@@ -132,7 +132,8 @@ inline int restrict_cap_a(const int32_t *c, const int32_t *f) {
 inline int restrict_cap_b(const int32_t *c, const int32_t *f) {
     return NV * ((c[1] + 1) * (f[1] + 1) + (c[2] + 1) * (f[2] + 1));
 }
-hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
+// felems: per coarse element the record of its fine element.
+hipError_t launch_restrict(int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
                            const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
                            double *psic, const double *tab, int capA, int capB, int restriction, int psi_new,
                            const double *met, double invJ, hipStream_t s);
@@ -159,17 +160,27 @@ struct SweepTask {
     int32_t p, c1, c2, pad;
 };
 
-// Anisotropic sweep: workgroups (first job, job count) over jobs (element, pair of
-// x-orders, first lane, offset of the x-rows in the staging area), packed by the host
+// Anisotropic sweep: workgroups (first job, job count, problem, 0) over jobs (element,
+// pair of x-orders, first lane, offset of the x-rows in the staging area), packed by the host
 // within AN_LANES lanes and an_stage_doubles(F3) doubles of x-rows, AN_JOBS_MAX jobs.
 constexpr int AN_LANES = 256;
 constexpr int AN_JOBS_MAX = 8;
 __host__ __device__ constexpr inline int an_stage_doubles(int F3) {
     return 2 * NV * ((F3 > 2 ? F3 - 2 : 1) + 1) * AN_LANES;
 }
-hipError_t launch_sweep_an(int F3, const void *wgs, int nwg, const void *jobs, const ElemInfo *el,
-                           const int64_t *combo_off, const double *u, const double *dudt, const double *tab, Geom g,
-                           double gamma, int restriction, double *te_new, double *te_trad, hipStream_t s);
+// Inputs and outputs of one problem of the isolated sweep.  The sweep kernels take one by
+// value (single) or, for a batch of problems, an array indexed by the problem of each work
+// record (probs, or null).
+struct SweepProb {
+    const ElemInfo *el;
+    const int64_t *combo_off;
+    const double *u, *dudt;
+    double *te_new, *te_trad;
+    Geom g;
+    double gamma;
+};
+hipError_t launch_sweep_an(int F3, const int4 *wgs, int nwg, const int4 *jobs, const SweepProb &single,
+                           const SweepProb *probs, const double *tab, int restriction, hipStream_t s);
 hipError_t launch_sweep_tasks(const void *tasks, int ntasks, const ElemInfo *elems, const int64_t *combo_off,
                               const double *u, const double *dudt, const double *tab, Geom g, double gamma,
                               int x1cap, int x2cap, int restriction, double *te_new, double *te_trad,
@@ -209,9 +220,9 @@ hipError_t launch_count_bad(const ElemInfo *el, int E, const T *u, double gamma,
 // dudt = -(1/dt) sum_j b_j states[j], backward difference of order nst-1 (nst in 2..4)
 hipError_t launch_bdf_rate(const double *const *states, int nst, double dt, int64_t n, double *dudt, hipStream_t s);
 hipError_t launch_promote(const float *in, double *out, int64_t n, hipStream_t s);
-hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
-                            const double *u, const double *dudt, const double *tab, Geom g, double gamma,
-                            int restriction, double *te_new, double *te_trad, hipStream_t s);
+// Isotropic sweep of elements (problem, element) with F fine nodes per direction.
+hipError_t launch_sweep_iso(int F, const int2 *elems, int nelem, const SweepProb &single, const SweepProb *probs,
+                            const double *tab, int restriction, hipStream_t s);
 
 // ---------------------------------------------------------------------------- batches
 // One independent problem of a batch, as seen by the persistent kernels.

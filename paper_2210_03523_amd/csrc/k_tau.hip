@@ -27,7 +27,8 @@ namespace dgt {
 // where it falls, the table at offset `down`: T_I (sampling) or T_P (exact L2
 // projection).  PROJECT: the solution transfer onto another order map (Section 2.4.1,
 // down = T_P): the "coarse" element is the target, of any orders, the source element is
-// found through the source plan's natural -> plan index (fine_of), one field (Q).
+// found through the source plan's natural -> plan index (fine_of), one field (Q); the
+// restriction itself reads the fine element's record at the coarse element's position.
 // psi_new: the adjoint weight is the adjoint of the new-form residual M^-1 F, i.e. M times
 // the traditional-form adjoint (M = J w_i w_j w_k of the fine element); it is divided by
 // M as it is loaded (box elements: J = 1/invJ; curved: J per node from met).
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(64) void k_restrict_w(const int32_t *__restrict__ f
     const int p = pf / nfield, field = pf - p * nfield;
     const int lane = threadIdx.x;
     const ElemInfo C = cel[p];
-    const ElemInfo F = fel[fine_of[PROJECT ? C.nat : p]];
+    const ElemInfo F = PROJECT ? fel[fine_of[C.nat]] : fel[p];
     const int f1 = F.n[0], f2 = F.n[1], f3 = F.n[2], nl = f2 * f3, nef = f1 * nl;
     const int c1 = C.n[0], c2 = C.n[1], c3 = C.n[2], n12 = c1 * c2, nec = n12 * c3;
     const float ic1 = 1.0f / c1, ic2 = 1.0f / c2, ic12 = 1.0f / n12;
@@ -142,14 +143,14 @@ __global__ __launch_bounds__(64) void k_restrict_w(const int32_t *__restrict__ f
     }
 }
 
-hipError_t launch_restrict(const int32_t *fine_of, int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
+hipError_t launch_restrict(int ncoarse, const ElemInfo *celems, const ElemInfo *felems,
                            const double *u, const double *dudt, const double *psi, double *uc, double *rdc,
                            double *psic, const double *tab, int capA, int capB, int restriction, int psi_new,
                            const double *met, double invJ, hipStream_t s) {
     if (ncoarse == 0) return hipSuccess;
     const int nfield = psi ? 3 : 2;
     const size_t lds = sizeof(double) * (size_t)(capA / NV + capB / NV);
-    hipLaunchKernelGGL(k_restrict_w<false>, dim3(ncoarse * nfield * NV), dim3(64), lds, s, fine_of, celems, felems, u,
+    hipLaunchKernelGGL(k_restrict_w<false>, dim3(ncoarse * nfield * NV), dim3(64), lds, s, nullptr, celems, felems, u,
                        dudt, psi, uc, rdc, psic, tab, capA / NV, restriction ? T_P : T_I, psi_new, met, invJ, nfield);
     return hipGetLastError();
 }
@@ -342,12 +343,9 @@ namespace dgt {
 //     are exchanged through LDS; the tau difference and its maxima per
 //     (c1, c2, c3) are folded with LDS atomics on the bit patterns.
 template <int F>
-__global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ elems, int njobs,
-                                                   const ElemInfo *__restrict__ el,
-                                                   const int64_t *__restrict__ combo_off,
-                                                   const double *__restrict__ u, const double *__restrict__ dudt,
-                                                   const double *__restrict__ tab, Geom g, double gamma, int rt,
-                                                   double *__restrict__ te_new, double *__restrict__ te_trad) {
+__global__ __launch_bounds__(256) void k_sweep_iso(const int2 *__restrict__ elems, int njobs, SweepProb single,
+                                                   const SweepProb *__restrict__ probs,
+                                                   const double *__restrict__ tab, int rt) {
     constexpr int C = F > 2 ? F - 2 : 1;        // coarse orders per direction
     constexpr int NPAIR = (C + 1) / 2;
     constexpr int SUMM = C * (C + 3) / 2;       // stacked coarse rows over every order
@@ -365,8 +363,14 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
 
     const int job = xcd_remap(blockIdx.x, njobs);
     const int pair = job % NPAIR;
-    const int p = elems[job / NPAIR];
-    const ElemInfo E = el[p];
+    const int2 pe = elems[job / NPAIR];
+    const SweepProb P = probs ? probs[pe.x] : single;
+    const double *__restrict__ u = P.u;
+    const double *__restrict__ dudt = P.dudt;
+    const Geom g = P.g;
+    const double gamma = P.gamma;
+    const int p = pe.y;
+    const ElemInfo E = P.el[p];
     const int cA = pair + 1, cBr = C - pair;
     const int cB = cBr == cA ? 0 : cBr;
     const int mA = cA + 1, mB = cB ? cB + 1 : 0;
@@ -558,16 +562,15 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int32_t *__restrict__ e
         const int cc1 = gi < C ? cA : cB;
         if (cc1 == 0) continue;
         const int cc2 = gi % C + 1;
-        const int64_t s = combo_off[p] + (cc1 - 1) + C * ((cc2 - 1) + C * (c3 - 1));
-        te_new[s] = __longlong_as_double((long long)slot[2 * i]);
-        te_trad[s] = __longlong_as_double((long long)slot[2 * i + 1]);
+        const int64_t s = P.combo_off[p] + (cc1 - 1) + C * ((cc2 - 1) + C * (c3 - 1));
+        P.te_new[s] = __longlong_as_double((long long)slot[2 * i]);
+        P.te_trad[s] = __longlong_as_double((long long)slot[2 * i + 1]);
     }
 }
 
 template <int F>
-static hipError_t launch_iso(const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
-                             const double *u, const double *dudt, const double *tab, Geom g, double gamma,
-                             int rt, double *te_new, double *te_trad, hipStream_t s) {
+static hipError_t launch_iso(const int2 *elems, int nelem, const SweepProb &single, const SweepProb *probs,
+                             const double *tab, int rt, hipStream_t s) {
     constexpr int C = F > 2 ? F - 2 : 1;
     constexpr int MM = C + 1;
     constexpr int NPAIR = (C + 1) / 2;
@@ -577,8 +580,7 @@ static hipError_t launch_iso(const int32_t *elems, int nelem, const ElemInfo *el
         // per device: set on every launch (a host-side call)
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(njobs), dim3(256), lds, s, elems, njobs, el, combo_off, u, dudt, tab, g, gamma,
-                           rt, te_new, te_trad);
+        hipLaunchKernelGGL(kern, dim3(njobs), dim3(256), lds, s, elems, njobs, single, probs, tab, rt);
         return hipGetLastError();
     };
     return go(k_sweep_iso<F>);
@@ -599,12 +601,10 @@ constexpr int AN_JOBS = AN_JOBS_MAX;
 // vectors) and is skipped.  (The isotropic kernel keeps the table rows: there the
 // shortcut changes the compiler's schedule into register spills.)
 template <int F3, bool SAMPLE>
-__global__ __launch_bounds__(256) void k_sweep_an(const int2 *__restrict__ wgs, int nwg,
-                                                  const int4 *__restrict__ jobs, const ElemInfo *__restrict__ el,
-                                                  const int64_t *__restrict__ combo_off,
-                                                  const double *__restrict__ u, const double *__restrict__ dudt,
-                                                  const double *__restrict__ tab, Geom g, double gamma, int rt,
-                                                  double *__restrict__ te_new, double *__restrict__ te_trad) {
+__global__ __launch_bounds__(256) void k_sweep_an(const int4 *__restrict__ wgs, int nwg,
+                                                  const int4 *__restrict__ jobs, SweepProb single,
+                                                  const SweepProb *__restrict__ probs,
+                                                  const double *__restrict__ tab, int rt) {
     constexpr int C3 = F3 > 2 ? F3 - 2 : 1;     // coarse z-orders
     constexpr int MM = C3 + 1;                  // largest coarse z node count
     constexpr int FM = 8;                       // largest fine x and y node count
@@ -616,9 +616,14 @@ __global__ __launch_bounds__(256) void k_sweep_an(const int2 *__restrict__ wgs, 
     double *S = lds;                                                     // staging / X1
     unsigned long long *slot = (unsigned long long *)(lds + 2 * NV * MM * NL);
 
-    const int2 W = wgs[xcd_remap(blockIdx.x, nwg)];
+    const int4 W = wgs[xcd_remap(blockIdx.x, nwg)];  // (first job, job count, problem, 0)
+    const SweepProb P = probs ? probs[W.z] : single;
+    const ElemInfo *__restrict__ el = P.el;
+    const double *__restrict__ u = P.u;
+    const double *__restrict__ dudt = P.dudt;
+    const Geom g = P.g;
     const int lane = threadIdx.x;
-    const double gm1 = gamma - 1.0;
+    const double gm1 = P.gamma - 1.0;
 
     for (int i = lane; i < W.y * NSL; i += NL) slot[i] = 0ull;
 
@@ -837,61 +842,55 @@ __global__ __launch_bounds__(256) void k_sweep_an(const int2 *__restrict__ wgs, 
         const int cc1 = gi < CM ? cAj : cBj;
         const int cc2 = gi % CM + 1;
         if (cc1 == 0 || cc2 > C2j) continue;
-        const int64_t sidx_ = combo_off[Jj.x] + (cc1 - 1) + C1j * ((cc2 - 1) + C2j * (c3 - 1));
-        te_new[sidx_] = __longlong_as_double((long long)slot[j * NSL + 2 * r]);
-        te_trad[sidx_] = __longlong_as_double((long long)slot[j * NSL + 2 * r + 1]);
+        const int64_t sidx_ = P.combo_off[Jj.x] + (cc1 - 1) + C1j * ((cc2 - 1) + C2j * (c3 - 1));
+        P.te_new[sidx_] = __longlong_as_double((long long)slot[j * NSL + 2 * r]);
+        P.te_trad[sidx_] = __longlong_as_double((long long)slot[j * NSL + 2 * r + 1]);
     }
 }
 
 template <int F3>
-static hipError_t launch_an(const int2 *wgs, int nwg, const int4 *jobs, const ElemInfo *el,
-                            const int64_t *combo_off, const double *u, const double *dudt, const double *tab, Geom g,
-                            double gamma, int rt, double *te_new, double *te_trad, hipStream_t s) {
+static hipError_t launch_an(const int4 *wgs, int nwg, const int4 *jobs, const SweepProb &single,
+                            const SweepProb *probs, const double *tab, int rt, hipStream_t s) {
     constexpr int C3 = F3 > 2 ? F3 - 2 : 1;
     const size_t lds = sizeof(double) * (size_t)an_stage_doubles(F3) +
                        sizeof(unsigned long long) * AN_JOBS * 2 * C3 * 2 * 6;
     auto go = [&](auto kern) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), lds, s, wgs, nwg, jobs, el, combo_off, u, dudt, tab, g, gamma,
-                           rt, te_new, te_trad);
+        hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), lds, s, wgs, nwg, jobs, single, probs, tab, rt);
         return hipGetLastError();
     };
     return rt == T_I ? go(k_sweep_an<F3, true>) : go(k_sweep_an<F3, false>);
 }
 
-hipError_t launch_sweep_an(int F3, const void *wgs, int nwg, const void *jobs, const ElemInfo *el,
-                           const int64_t *combo_off, const double *u, const double *dudt, const double *tab, Geom g,
-                           double gamma, int restriction, double *te_new, double *te_trad, hipStream_t s) {
+hipError_t launch_sweep_an(int F3, const int4 *wgs, int nwg, const int4 *jobs, const SweepProb &single,
+                           const SweepProb *probs, const double *tab, int restriction, hipStream_t s) {
     if (nwg == 0) return hipSuccess;
     const int rt = restriction ? T_P : T_I;
-    const int2 *w = (const int2 *)wgs;
-    const int4 *j = (const int4 *)jobs;
     switch (F3) {
-        case 2: return launch_an<2>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 3: return launch_an<3>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 4: return launch_an<4>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 5: return launch_an<5>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 6: return launch_an<6>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 7: return launch_an<7>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 8: return launch_an<8>(w, nwg, j, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 2: return launch_an<2>(wgs, nwg, jobs, single, probs, tab, rt, s);
+        case 3: return launch_an<3>(wgs, nwg, jobs, single, probs, tab, rt, s);
+        case 4: return launch_an<4>(wgs, nwg, jobs, single, probs, tab, rt, s);
+        case 5: return launch_an<5>(wgs, nwg, jobs, single, probs, tab, rt, s);
+        case 6: return launch_an<6>(wgs, nwg, jobs, single, probs, tab, rt, s);
+        case 7: return launch_an<7>(wgs, nwg, jobs, single, probs, tab, rt, s);
+        case 8: return launch_an<8>(wgs, nwg, jobs, single, probs, tab, rt, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep_iso(int F, const int32_t *elems, int nelem, const ElemInfo *el, const int64_t *combo_off,
-                            const double *u, const double *dudt, const double *tab, Geom g, double gamma,
-                            int restriction, double *te_new, double *te_trad, hipStream_t s) {
+hipError_t launch_sweep_iso(int F, const int2 *elems, int nelem, const SweepProb &single, const SweepProb *probs,
+                            const double *tab, int restriction, hipStream_t s) {
     if (nelem == 0) return hipSuccess;
     const int rt = restriction ? T_P : T_I;
     switch (F) {
-        case 2: return launch_iso<2>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 3: return launch_iso<3>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 4: return launch_iso<4>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 5: return launch_iso<5>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 6: return launch_iso<6>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 7: return launch_iso<7>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
-        case 8: return launch_iso<8>(elems, nelem, el, combo_off, u, dudt, tab, g, gamma, rt, te_new, te_trad, s);
+        case 2: return launch_iso<2>(elems, nelem, single, probs, tab, rt, s);
+        case 3: return launch_iso<3>(elems, nelem, single, probs, tab, rt, s);
+        case 4: return launch_iso<4>(elems, nelem, single, probs, tab, rt, s);
+        case 5: return launch_iso<5>(elems, nelem, single, probs, tab, rt, s);
+        case 6: return launch_iso<6>(elems, nelem, single, probs, tab, rt, s);
+        case 7: return launch_iso<7>(elems, nelem, single, probs, tab, rt, s);
+        case 8: return launch_iso<8>(elems, nelem, single, probs, tab, rt, s);
         default: return hipErrorInvalidValue;
     }
 }
