@@ -363,7 +363,9 @@ constexpr int elem_rows() {
     return (3 * NV * elem_cols<T>(N) + 3 * DSTR) * (int)sizeof(T) <= 64 * 1024 ? 3 * NV : NV;
 }
 
-template <typename T, int NPT, bool CURVED = false, int BS = WG, bool VISC = true>
+// EARLY: the face fluxes of the node's faces and the RK register are requested right
+// after the state, so their latency overlaps the volume terms (more registers).
+template <typename T, int NPT, bool CURVED = false, int BS = WG, bool VISC = true, bool EARLY = false>
 __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, const T *u,
                                           const T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
                                           const PhysParams &ph, const EpiArgs &epi, T (*sF)[elem_cols<T>(BS * NPT)],
@@ -410,6 +412,36 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
             const T *mp = (const T *)epi.met + (int64_t)10 * (E0.noff + (int64_t)le[k] * npe) + nd[k];
 #pragma unroll
             for (int c = 0; c < 10; ++c) M[CURVED ? k : 0][c] = ok[k] ? mp[(int64_t)c * npe] : T(c == 9 ? 1 : 0);
+        }
+    }
+    // the face flux of face (d, side of the node) at this thread's k-th node, variable v
+    auto face_ptr = [&](int k, int d) -> const T * {
+        const int id = loc[k][d], nd_ = d == 0 ? n1 : d == 1 ? n2 : n3;
+        if (id != 0 && id != nd_ - 1) return nullptr;
+        const int s = id == 0 ? -1 : 1;
+        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+        const int na = t1 == 0 ? n1 : n2, nb = t2 == 1 ? n2 : n3;
+        const int fm = loc[k][t1] + na * loc[k][t2];
+        return ff + E0.foff + le[k] * fblk + fslot(E0.n, d, s) + fm;
+    };
+    constexpr int NE = EARLY ? NPT : 1;
+    T fe[NE][3][NV];  // EARLY: face fluxes (per direction; zero off the faces)
+    T ge[NE][NV];     // EARLY: the RK register
+    if (EARLY) {
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T *fp = (ok[k] && !epi.isolated) ? face_ptr(k, d) : nullptr;
+                const int ab = (d == 0 ? n2 * n3 : d == 1 ? n1 * n3 : n1 * n2);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) fe[k][d][v] = fp ? fp[v * ab] : T(0);
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                ge[k][v] = (ok[k] && epi.mode == EPI_RK && epi.rkA != 0.0) ? ((const T *)epi.g)[base + v * npe + nd[k]]
+                                                                           : T(0);
         }
     }
     // contravariant total flux along d at this thread's k-th node, Ja^d . (f^a - f^v):
@@ -505,7 +537,10 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
                 T f[NV];
                 total_flux(k, d, f);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) V[k][v] += (fs[v * na * nb + fm] - T(s) * f[v]) * iw;
+                for (int v = 0; v < NV; ++v) {
+                    const T fv = EARLY ? fe[EARLY ? k : 0][d][v] : fs[v * na * nb + fm];
+                    V[k][v] += (fv - T(s) * f[v]) * iw;
+                }
             }
         }
     }
@@ -538,7 +573,8 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
             for (int v = 0; v < NV; ++v) {
                 const int64_t x = base + v * npe + nd[k];
                 const T r = V[k][v] * invJ;
-                const T gn = (epi.rkA == 0.0) ? -dt * r : A * G[x] - dt * r;
+                const T gold = EARLY ? ge[EARLY ? k : 0][v] : (epi.rkA == 0.0 ? T(0) : G[x]);
+                const T gn = (epi.rkA == 0.0) ? -dt * r : A * gold - dt * r;
                 G[x] = gn;
                 uu[x] = q[k][v] + B * gn;
             }
@@ -956,8 +992,8 @@ __global__ __launch_bounds__(BS) void k_elem_batch(const BatchTile *__restrict__
         EpiArgs epi = epi0;
         epi.out = pd.out;
         epi.g = pd.g;
-        elem_body<T, NPT, false, BS, false>(Tile{bt.first, bt.count}, bt.e0, pd.u, pd.ff, tab, pd.geom, pd.phys,
-                                           epi, sF, sD);
+        elem_body<T, NPT, false, BS, false, true>(Tile{bt.first, bt.count}, bt.e0, pd.u, pd.ff, tab, pd.geom,
+                                                 pd.phys, epi, sF, sD);
         __syncthreads();
     }
 }
