@@ -669,7 +669,10 @@ __global__ __launch_bounds__(BS) void k_elem(const Tile *__restrict__ tiles, int
     __shared__ T sF[elem_rows<T, BS * NPT>()][elem_cols<T>(BS * NPT)];
     __shared__ T sD[3 * DSTR];
     const Tile tl = tiles[tile0 + xcd_remap(blockIdx.x, ntiles)];
-    elem_body<T, NPT, CURVED, BS, VISC>(tl, el[tl.first], u, ff, tab, g, ph, epi, sF, sD);
+    // early loads pay for FP32 box Euler tiles (31.1 -> 32.2 GDOF/s at 16^3, N = 7); the
+    // FP64 pass was slower with them (98 -> 111 us)
+    constexpr bool EARLY = !CURVED && !VISC && sizeof(T) == 4;
+    elem_body<T, NPT, CURVED, BS, VISC, EARLY>(tl, el[tl.first], u, ff, tab, g, ph, epi, sF, sD);
 }
 
 template <typename T>
