@@ -384,7 +384,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
     }  // ordered before the first read by the barrier after the first flux staging
     const int npe = n1 * n2 * n3;
     const int total = tl.count * npe;
-    const T gm1 = (T)(ph.gamma - 1.0);
+    const T gm1 = (T)ph.gamma - T(1);  // as the face fluxes form it (equal states: zero jump)
     const int64_t fblk = fblock(E0.n);
 
     T q[NPT][NV], V[NPT][NV];
@@ -506,11 +506,17 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
             const int id = loc[k][d];
             const T *Drow = Dm + id * dstride(nd_);
             const int tb = t - id * stride[d];
+            // FP32: the flux at the line's first node is subtracted inside every term (the
+            // rows of D sum to zero, so the derivative is unchanged in exact arithmetic),
+            // which keeps the near-constant part of the flux out of the rounding
+            T ref[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) ref[v] = sizeof(T) == 4 ? sF[(ALLD ? d * NV : 0) + v][sidx<T>(tb)] : T(0);
             for (int m = 0; m < nd_; ++m) {
                 const T dm = Drow[m];
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
-                    V[k][v] += dm * sF[(ALLD ? d * NV : 0) + v][sidx<T>(tb + m * stride[d])];
+                    V[k][v] += dm * (sF[(ALLD ? d * NV : 0) + v][sidx<T>(tb + m * stride[d])] - ref[v]);
             }
         }
         // the next direction's staging (or, after the last, the next tile of a persistent

@@ -92,6 +92,28 @@ def test_residual_fp32(shape, orng, seed, bc, flux, box):
     assert err(got.astype(np.float64), ref, residual_scale(mesh, orders, u)) < TOL32
 
 
+@pytest.mark.parametrize("N", [1, 4, 7])
+@pytest.mark.parametrize("flux", [wl.ROE, wl.LF])
+def test_fp32_free_stream_exact(N, flux):
+    """FP32 keeps a uniform state exactly steady on a conforming periodic box: every
+    derivative subtracts the flux at its line's first node (the rows of D sum to zero),
+    and the Riemann flux of equal states is the physical flux, so the residual is a
+    bitwise zero (the FP32 tables' rounded row sums would leave about 1e-7 of |f| ||D||
+    otherwise).  Mixed orders interpolate on the mortars and keep it within rounding."""
+    rng = np.random.default_rng(40 + N)
+    mesh = wl.box_mesh((3, 2, 2), hi=(1.0, 0.7, 1.3), flux=flux)
+    q = (1.2, 0.3, -0.2, 0.25, 2.7)
+    orders = wl.uniform_orders(12, N)
+    plan = dg.Plan(mesh, orders)
+    r = dg.residual(plan, plan.to_plan(wl.uniform_state(orders, q), dtype=torch.float32))
+    assert float(r.abs().max()) == 0.0
+    mixed = wl.random_orders(12, 1, 7, rng)
+    plan = dg.Plan(mesh, mixed)
+    u = wl.uniform_state(mixed, q)
+    r = dg.residual(plan, plan.to_plan(u, dtype=torch.float32))
+    assert float(r.abs().max()) < 1e-5 * residual_scale(mesh, mixed, u)
+
+
 def test_residual_deterministic():
     mesh, orders, u, _ = _case((3, 3, 3), 1, 7, 11)
     plan = dg.Plan(mesh, orders)
