@@ -113,6 +113,20 @@ def test_batch_tau_sweep(dtype):
         assert np.max(np.abs(_sweep_nat(p, tet) - tet_r)) < 1e-12 * max(np.max(np.abs(tet_r)), st)
 
 
+def test_batch_tau_sweep_matches_each_plan():
+    """The merged work lists of the batched sweep (one launch per fine node count over
+    every problem) give each problem exactly its own plan's sweep: the same kernels, the
+    same per-node arithmetic, only the launch composition differs."""
+    probs = _problems(nprob=6, seed=36)
+    plans = [dg.Plan(m, o) for m, o, _ in probs]
+    batch = dg.Batch(plans, dtype=torch.float64)
+    u64 = [p.to_plan(u) for p, (_, _, u) in zip(plans, probs)]
+    maps = dg.batch_tau_sweep(batch, u64)
+    for p, x, (ten, tet) in zip(plans, u64, maps):
+        a, b = dg.tau_sweep(p, x, None)
+        assert torch.equal(ten, a) and torch.equal(tet, b)
+
+
 def test_batch_rejects_a_repeated_plan():
     probs = _problems(nprob=2, seed=33)
     p = dg.Plan(probs[0][0], probs[0][1])
