@@ -404,24 +404,54 @@ dg_status dg_residual_vjp(dg_plan plan, const double *u, const double *v, double
  *   work: device double of dg_adjoint_workspace(plan, restart) values (caller-owned;
  *         nothing is allocated here).
  *   iters, relres (host, nullable): products done and the final ||g - A^T psi|| / ||g||.
+ *   precond (in params, nullable): an element-block Jacobi preconditioner built by
+ *         dg_adjoint_precond_build for the same plan, state, form and isolated flag,
+ *         applied on the right (the Krylov space is that of A^T M^-1; the stopping test
+ *         stays on the true residual).
  * Stops at relres <= rtol or after max_iter products.  SYNCHRONOUS: the host drives the
  * iteration and waits on stream once or twice per Arnoldi step.
  * Errors: DG_EINVAL (null arguments, restart outside 1..DG_ADJOINT_MAX_RESTART,
- * negative max_iter or rtol, unknown form, psi overlapping u or g), DG_EUNSUPPORTED
- * (Navier-Stokes or curved plans), DG_EHIP. */
+ * negative max_iter or rtol, unknown form, psi overlapping u or g, a preconditioner of
+ * another plan), DG_EUNSUPPORTED (Navier-Stokes or curved plans), DG_EHIP. */
 #define DG_ADJOINT_MAX_RESTART 200
 typedef struct {
-    int32_t restart;  /* Krylov vectors per cycle */
-    int32_t max_iter; /* largest number of matrix-vector products */
-    double rtol;      /* relative residual target */
-    int32_t form;     /* DG_FORM_NEW or DG_FORM_TRAD */
+    int32_t restart;     /* Krylov vectors per cycle */
+    int32_t max_iter;    /* largest number of matrix-vector products */
+    double rtol;         /* relative residual target */
+    int32_t form;        /* DG_FORM_NEW or DG_FORM_TRAD */
     int32_t isolated;
+    const void *precond; /* dg_adjoint_precond_build's memory, or NULL */
 } dg_adjoint_params;
 
 dg_status dg_adjoint_workspace(dg_plan plan, int32_t restart, int64_t *doubles);
 dg_status dg_adjoint_solve(dg_plan plan, const double *u, const double *g, double *psi,
                            const dg_adjoint_params *params, double *work, int32_t *iters,
                            double *relres, hipStream_t stream);
+
+/* Element-block Jacobi preconditioner of the adjoint operator A = (d r / d u)^T at u
+ * (Section 2.2's adjoint problem; restarted GMRES alone stalls on transport-dominated
+ * states): M = the block diagonal of A, one block of nd x nd per element (nd = 5 x the
+ * element's nodes), its inverse stored in FP32.  Each block is assembled from probing
+ * products: with v = 1 at local unknown j of every element of one colour (a colouring of
+ * the elements in which face neighbours differ: two colours when every periodic
+ * direction has an even element count), (A v) on an element of that colour is column j
+ * of its block.  colours x nd products of dg_residual_vjp, then an LU factorisation with
+ * partial pivoting and the inverse of every block (rocSOLVER's batched getrf / getri).
+ * Box Euler plans of one order triple with nd <= DG_PRECOND_MAX_ND.
+ *   bytes (precond_bytes): the size of the caller-owned preconditioner memory.
+ *   pc: device memory of that size, 256-byte aligned; filled here (its header, the
+ *       colouring, pivots and the inverted blocks).
+ *   work: device double[2 x 5 n_nodes] scratch.
+ * SYNCHRONOUS; allocates only the rocBLAS handle and the factorisation's workspace
+ * (set-up, not a hot call).  Errors: DG_EINVAL (null or misaligned arguments, a singular
+ * block), DG_EUNSUPPORTED (curved or Navier-Stokes plans, mixed orders, nd too large),
+ * DG_EHIP. */
+#define DG_PRECOND_MAX_ND 4096
+dg_status dg_adjoint_precond_bytes(dg_plan plan, int64_t *bytes);
+dg_status dg_adjoint_precond_build(dg_plan plan, const double *u, int32_t form, int32_t isolated, void *pc,
+                                   double *work, hipStream_t stream);
+/* z = M^-1 x with a built preconditioner (x, z: device double, plan layout, distinct). */
+dg_status dg_adjoint_precond_apply(dg_plan plan, const void *pc, const double *x, double *z, hipStream_t stream);
 
 /* Pressure force along x on the slip walls (faces normal to x):
  *   J = sum over those faces of sum_{a,b} w_a w_b |Ja^1| p(Q_ab) n_x,

@@ -42,7 +42,7 @@ class _MeshDesc(ctypes.Structure):
 
 class _AdjointParams(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double),
-                ("form", ctypes.c_int32), ("isolated", ctypes.c_int32)]
+                ("form", ctypes.c_int32), ("isolated", ctypes.c_int32), ("precond", ctypes.c_void_p)]
 
 
 class _SelectParams(ctypes.Structure):
@@ -90,6 +90,9 @@ SIGNATURES = {
     "dg_tau_extrapolate": [_P, _P, ctypes.c_int32, _P, _P],
     "dg_bdf_rate": [_P, ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_double, _P, _P],
     "dg_adjoint_workspace": [_P, ctypes.c_int32, _I64P],
+    "dg_adjoint_precond_bytes": [_P, _I64P],
+    "dg_adjoint_precond_build": [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P],
+    "dg_adjoint_precond_apply": [_P, _P, _P, _P, _P],
     "dg_adjoint_solve": [_P, _P, _P, _P, ctypes.POINTER(_AdjointParams), _P, _I32P,
                          ctypes.POINTER(ctypes.c_double), _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
@@ -469,10 +472,33 @@ def select_orders(plan: Plan, maps, tau_max: float, nmin: int = 1, nmax: int = N
     return out
 
 
+def adjoint_precond(plan: Plan, u, form: int = FORM_TRAD, isolated: bool = False):
+    """Element-block Jacobi preconditioner of (dr/du)^T at u (dg_adjoint_precond_build):
+    device memory (a uint8 tensor) to pass to adjoint_solve(precond=...)."""
+    torch = _torch()
+    if u.dtype != torch.float64 or u.numel() != 5 * plan.n_nodes:
+        raise DGError("u must be a float64 state of the plan")
+    nb = ctypes.c_int64()
+    _call("dg_adjoint_precond_bytes", plan.handle, ctypes.byref(nb))
+    pc = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    work = torch.empty(2 * u.numel(), dtype=torch.float64, device="cuda")
+    _call("dg_adjoint_precond_build", plan.handle, _ptr(u), int(form), int(bool(isolated)), _ptr(pc), _ptr(work),
+          _stream())
+    return pc
+
+
+def adjoint_precond_apply(plan: Plan, pc, x):
+    """z = M^-1 x with a preconditioner of adjoint_precond."""
+    z = _torch().empty_like(x)
+    _call("dg_adjoint_precond_apply", plan.handle, _ptr(pc), _ptr(x), _ptr(z), _stream())
+    return z
+
+
 def adjoint_solve(plan: Plan, u, g, psi=None, restart: int = 30, max_iter: int = 2000, rtol: float = 1e-10,
-                  form: int = FORM_TRAD, isolated: bool = False):
+                  form: int = FORM_TRAD, isolated: bool = False, precond=None):
     """Solve (dr/du)^T psi = g by restarted GMRES on the residual VJP; returns
-    (psi, iterations, relative residual).  psi (optional) is the initial guess."""
+    (psi, iterations, relative residual).  psi (optional) is the initial guess; precond
+    (optional) a preconditioner of adjoint_precond for the same state, form and flag."""
     torch = _torch()
     n = 5 * plan.n_nodes
     for t in (u, g):
@@ -482,7 +508,8 @@ def adjoint_solve(plan: Plan, u, g, psi=None, restart: int = 30, max_iter: int =
     nw = ctypes.c_int64()
     _call("dg_adjoint_workspace", plan.handle, int(restart), ctypes.byref(nw))
     work = torch.empty(int(nw.value), dtype=torch.float64, device="cuda")
-    prm = _AdjointParams(int(restart), int(max_iter), float(rtol), int(form), int(bool(isolated)))
+    prm = _AdjointParams(int(restart), int(max_iter), float(rtol), int(form), int(bool(isolated)),
+                         _ptr(precond).value if precond is not None else None)
     it = ctypes.c_int32()
     rr = ctypes.c_double()
     _call("dg_adjoint_solve", plan.handle, _ptr(u), _ptr(g), _ptr(x), ctypes.byref(prm), _ptr(work),

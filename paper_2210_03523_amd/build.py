@@ -12,7 +12,8 @@ OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libdgtau.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "tables.cpp", "k_residual.hip", "k_tau.hip", "k_vjp.hip", "k_curved.hip", "k_select.hip", "k_dual.hip", "k_krylov.hip", "k_convert.hip"]
+SOURCES = ["api.cpp", "tables.cpp", "k_residual.hip", "k_tau.hip", "k_vjp.hip", "k_curved.hip", "k_select.hip", "k_dual.hip", "k_krylov.hip", "k_convert.hip",
+           "k_precond.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]
@@ -33,7 +34,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
+    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp, "-lrocsolver", "-lrocblas"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

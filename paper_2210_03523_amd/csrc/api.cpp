@@ -14,6 +14,8 @@
 #include <tuple>
 #include <vector>
 
+#include <rocsolver/rocsolver.h>
+
 #include "../../include/dgtau.h"
 #include "common.h"
 
@@ -1329,7 +1331,158 @@ dg_status dg_adjoint_workspace(dg_plan p, int32_t restart, int64_t *doubles) {
     if (!p || !doubles) return fail(DG_EINVAL, "null argument");
     if (restart < 1 || restart > DG_ADJOINT_MAX_RESTART) return fail(DG_EINVAL, "restart must be in 1..200");
     const int64_t ld = ((int64_t)NV * p->n_nodes + 1) & ~(int64_t)1;  // vectors 16-byte aligned
-    *doubles = (int64_t)(restart + 2) * ld + mdot_partials() + 2 * (restart + 4);
+    *doubles = (int64_t)(restart + 3) * ld + mdot_partials() + 2 * (restart + 4);
+    return DG_OK;
+}
+
+// ---------------------------------------------------------------------------- adjoint preconditioner
+namespace {
+// Preconditioner memory: this header, then (256-byte aligned) the colour starts
+// [ncolor + 1], the plan elements grouped by colour [E], the pivots [E][nd], the
+// factorisation flags [E], and the inverted blocks [E][nd][nd] (FP32, column-major).
+struct PrecondHeader {
+    uint64_t magic;  // identifies the plan the memory was built for
+    int32_t E, nd, ncolor, pad;
+    int64_t off_first, off_elems, off_ipiv, off_info, off_blocks, bytes;
+};
+constexpr int kMaxColors = 27;
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+PrecondHeader precond_layout(int E, int nd) {
+    PrecondHeader h{};
+    h.E = E;
+    h.nd = nd;
+    size_t o = align256(sizeof(PrecondHeader));
+    h.off_first = (int64_t)o;
+    o = align256(o + sizeof(int32_t) * (kMaxColors + 1));
+    h.off_elems = (int64_t)o;
+    o = align256(o + sizeof(int32_t) * E);
+    h.off_ipiv = (int64_t)o;
+    o = align256(o + sizeof(int32_t) * (size_t)E * nd);
+    h.off_info = (int64_t)o;
+    o = align256(o + sizeof(int32_t) * E);
+    h.off_blocks = (int64_t)o;
+    o += sizeof(float) * (size_t)E * nd * nd;
+    h.bytes = (int64_t)o;
+    return h;
+}
+uint64_t plan_magic(dg_plan p) { return 0x4247504a00000000ull ^ (uint64_t)(uintptr_t)p; }
+dg_status precond_check(dg_plan p, int *nd) {
+    if (p->ns || p->curved) return fail(DG_EUNSUPPORTED, "the adjoint preconditioner is built for box Euler plans");
+    for (int i = 0; i < 3 * p->E; ++i)
+        if (p->ord[i] != p->ord[i % 3]) return fail(DG_EUNSUPPORTED, "the adjoint preconditioner needs one order triple");
+    *nd = NV * (p->ord[0] + 1) * (p->ord[1] + 1) * (p->ord[2] + 1);
+    if (*nd > DG_PRECOND_MAX_ND) return fail(DG_EUNSUPPORTED, "element blocks larger than DG_PRECOND_MAX_ND");
+    return DG_OK;
+}
+}  // namespace
+
+dg_status dg_adjoint_precond_bytes(dg_plan p, int64_t *bytes) {
+    if (!p || !bytes) return fail(DG_EINVAL, "null argument");
+    int nd = 0;
+    dg_status st = precond_check(p, &nd);
+    if (st) return st;
+    *bytes = precond_layout(p->E, nd).bytes;
+    return DG_OK;
+}
+
+dg_status dg_adjoint_precond_build(dg_plan p, const double *u, int32_t form, int32_t isolated, void *pc, double *work,
+                                   hipStream_t stream) {
+    if (!p || !u || !pc || !work) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(u, work);
+    if ((uintptr_t)pc & 255) return fail(DG_EINVAL, "the preconditioner memory must be 256-byte aligned");
+    if (form != DG_FORM_NEW && form != DG_FORM_TRAD) return fail(DG_EINVAL, "unknown form");
+    int nd = 0;
+    dg_status st = precond_check(p, &nd);
+    if (st) return st;
+    PrecondHeader h = precond_layout(p->E, nd);
+    h.magic = plan_magic(p);
+    // colouring of the element grid in which face neighbours differ: per direction the
+    // parity of the index, with a third colour for the last element of an odd periodic
+    // direction; the parity of the index sum when every periodic direction is even
+    const int nn[3] = {p->mesh.nx, p->mesh.ny, p->mesh.nz};
+    int K[3];
+    bool odd_periodic = false;
+    for (int d = 0; d < 3; ++d) {
+        const bool per = p->mesh.bc[2 * d] == DG_BC_PERIODIC && p->mesh.bc[2 * d + 1] == DG_BC_PERIODIC;
+        K[d] = per && (nn[d] % 2) && nn[d] > 1 ? 3 : 2;
+        odd_periodic |= K[d] == 3;
+    }
+    auto colour = [&](int nat) {
+        int c[3] = {nat % nn[0], (nat / nn[0]) % nn[1], nat / (nn[0] * nn[1])};
+        if (!odd_periodic) return (c[0] + c[1] + c[2]) & 1;
+        for (int d = 0; d < 3; ++d) c[d] = (K[d] == 3 && c[d] == nn[d] - 1) ? 2 : c[d] & 1;
+        return c[0] + K[0] * (c[1] + K[1] * c[2]);
+    };
+    h.ncolor = odd_periodic ? K[0] * K[1] * K[2] : 2;
+    std::vector<std::vector<int32_t>> byc(h.ncolor);
+    for (int e = 0; e < p->E; ++e) byc[colour((int)p->perm[e])].push_back(e);
+    std::vector<int32_t> first(kMaxColors + 1, 0), elems;
+    for (int c = 0; c < h.ncolor; ++c) {
+        first[c] = (int32_t)elems.size();
+        elems.insert(elems.end(), byc[c].begin(), byc[c].end());
+    }
+    first[h.ncolor] = (int32_t)elems.size();
+    char *base = (char *)pc;
+    HIP_TRY(hipMemcpy(base, &h, sizeof(h), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + h.off_first, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(base + h.off_elems, elems.data(), sizeof(int32_t) * elems.size(), hipMemcpyHostToDevice));
+    const int32_t *d_elems = (const int32_t *)(base + h.off_elems);
+    float *blocks = (float *)(base + h.off_blocks);
+    // probing: v = e_j on one colour, (A v) gathered into column j of those blocks
+    const int64_t n = (int64_t)NV * p->n_nodes;
+    double *v = work, *out = work + n;
+    HIP_TRY(hipMemsetAsync(v, 0, sizeof(double) * n, stream));
+    for (int c = 0; c < h.ncolor; ++c) {
+        const int32_t *ce = d_elems + first[c];
+        const int nc = first[c + 1] - first[c];
+        for (int j = 0; j < nd && nc > 0; ++j) {
+            HIP_TRY(launch_probe_set(v, ce, nc, p->d_el, j, 1.0, stream));
+            if ((st = dg_residual_vjp(p, u, v, out, form, isolated, stream))) return st;
+            HIP_TRY(launch_probe_gather(out, blocks, ce, nc, p->d_el, j, nd, stream));
+            HIP_TRY(launch_probe_set(v, ce, nc, p->d_el, j, 0.0, stream));
+        }
+    }
+    // LU with partial pivoting and the inverse of every block
+    rocblas_handle rh = nullptr;
+    if (rocblas_create_handle(&rh) != rocblas_status_success) return fail(DG_EHIP, "rocBLAS handle creation failed");
+    rocblas_set_stream(rh, stream);
+    int32_t *ipiv = (int32_t *)(base + h.off_ipiv), *info = (int32_t *)(base + h.off_info);
+    const rocblas_stride sA = (rocblas_stride)nd * nd;
+    rocblas_status rs = rocsolver_sgetrf_strided_batched(rh, nd, nd, blocks, nd, sA, ipiv, nd, info, p->E);
+    std::vector<int32_t> hinfo(p->E);
+    if (rs == rocblas_status_success &&
+        hipMemcpyAsync(hinfo.data(), info, sizeof(int32_t) * p->E, hipMemcpyDeviceToHost, stream) == hipSuccess &&
+        hipStreamSynchronize(stream) == hipSuccess) {
+        for (int e = 0; e < p->E; ++e)
+            if (hinfo[e] != 0) {
+                rocblas_destroy_handle(rh);
+                return fail(DG_EINVAL, "a singular element block: the adjoint preconditioner is not defined");
+            }
+        rs = rocsolver_sgetri_strided_batched(rh, nd, blocks, nd, sA, ipiv, nd, info, p->E);
+    }
+    hipError_t he = hipStreamSynchronize(stream);
+    rocblas_destroy_handle(rh);
+    if (rs != rocblas_status_success) return fail(DG_EHIP, "rocSOLVER factorisation failed");
+    if (he != hipSuccess) return fail(DG_EHIP, std::string("preconditioner build: ") + hipGetErrorString(he));
+    return DG_OK;
+}
+
+namespace {
+dg_status precond_view(dg_plan p, const void *pc, PrecondHeader *h) {
+    if (hipMemcpy(h, pc, sizeof(*h), hipMemcpyDeviceToHost) != hipSuccess) return fail(DG_EHIP, "reading the preconditioner");
+    if (h->magic != plan_magic(p) || h->E != p->E) return fail(DG_EINVAL, "the preconditioner was built for another plan");
+    return DG_OK;
+}
+}  // namespace
+
+dg_status dg_adjoint_precond_apply(dg_plan p, const void *pc, const double *x, double *z, hipStream_t stream) {
+    if (!p || !pc || !x || !z) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(x, z);
+    if (x == z) return fail(DG_EINVAL, "x and z must be distinct");
+    PrecondHeader h;
+    dg_status st = precond_view(p, pc, &h);
+    if (st) return st;
+    HIP_TRY(launch_bj_apply((const float *)((const char *)pc + h.off_blocks), x, z, p->d_el, p->E, h.nd, stream));
     return DG_OK;
 }
 static_assert(DG_KRYLOV_MAX == DG_ADJOINT_MAX_RESTART + 1, "Krylov kernels sized for the largest restart");
@@ -1355,7 +1508,15 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
     const int64_t n = (int64_t)NV * p->n_nodes;
     const int64_t ld = (n + 1) & ~(int64_t)1;  // vector stride: every V_j 16-byte aligned
     double *V = work;                        // V_j = V + j ld, j = 0..m
-    double *part = work + (int64_t)(m + 2) * ld;
+    double *Z = work + (int64_t)(m + 2) * ld;  // M^-1 of a Krylov vector (preconditioned solves)
+    double *part = work + (int64_t)(m + 3) * ld;
+    PrecondHeader ph{};
+    const float *pblk = nullptr;
+    if (prm->precond) {
+        dg_status st0 = precond_view(p, prm->precond, &ph);
+        if (st0) return st0;
+        pblk = (const float *)((const char *)prm->precond + ph.off_blocks);
+    }
     double *hb = part + mdot_partials();  // 2 (m + 4) doubles: a step's coefficients and norms
     auto fetch = [&](double *dst, int count) -> dg_status {
         HIP_TRY(hipMemcpyAsync(dst, hb, sizeof(double) * count, hipMemcpyDeviceToHost, stream));
@@ -1368,6 +1529,12 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
     };
     auto matvec = [&](const double *v, double *out) {
         return dg_residual_vjp(p, u, v, out, prm->form, prm->isolated, stream);
+    };
+    // A^T M^-1 v (right preconditioning) or A^T v
+    auto pmatvec = [&](const double *v, double *out) -> dg_status {
+        if (!pblk) return matvec(v, out);
+        HIP_TRY(launch_bj_apply(pblk, v, Z, p->d_el, p->E, ph.nd, stream));
+        return matvec(Z, out);
     };
     dg_status st;
     double gn2 = 0.0;
@@ -1399,7 +1566,7 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
         int k = 0;
         for (int j = 0; j < m && iters < prm->max_iter; ++j) {
             double *vj = V + (int64_t)j * ld, *w = V + (int64_t)(j + 1) * ld;
-            if ((st = matvec(vj, w))) return st;
+            if ((st = pmatvec(vj, w))) return st;
             ++iters;
             // classical Gram-Schmidt against V_0..V_j: coefficients and ||w||^2 in one
             // pass, the update with the new ||w||^2 in another, and a second round when
@@ -1443,7 +1610,16 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
             for (int c = i + 1; c < k; ++c) t -= H[(size_t)i * m + c] * y[c];
             y[i] = H[(size_t)i * m + i] != 0.0 ? t / H[(size_t)i * m + i] : 0.0;
         }
-        for (int i = 0; i < k; ++i) HIP_TRY(launch_axpby(y[i], V + (int64_t)i * ld, 1.0, psi, n, stream));
+        if (!pblk) {
+            for (int i = 0; i < k; ++i) HIP_TRY(launch_axpby(y[i], V + (int64_t)i * ld, 1.0, psi, n, stream));
+        } else if (k > 0) {
+            // psi += M^-1 (V y): V y gathered in V_m+1 (free after the cycle), then mapped
+            double *t = V + (int64_t)(m + 1) * ld;
+            HIP_TRY(launch_axpby(y[0], V, 0.0, t, n, stream));
+            for (int i = 1; i < k; ++i) HIP_TRY(launch_axpby(y[i], V + (int64_t)i * ld, 1.0, t, n, stream));
+            HIP_TRY(launch_bj_apply(pblk, t, Z, p->d_el, p->E, ph.nd, stream));
+            HIP_TRY(launch_axpby(1.0, Z, 1.0, psi, n, stream));
+        }
     }
     if (iters_out) *iters_out = iters;
     if (relres_out) *relres_out = relres;

@@ -201,6 +201,13 @@ hipError_t launch_extrapolate(const ElemInfo *el, int E, const int64_t *combo_of
 // Krylov vector operations: out[0] = sum a b (part: dot_partials() doubles of scratch);
 // y <- alpha x + beta y (x may equal y)
 hipError_t launch_dot(const double *a, const double *b, int64_t n, double *part, double *out, hipStream_t s);
+// element-block Jacobi preconditioner of the adjoint solve (k_precond.hip)
+hipError_t launch_probe_set(double *v, const int32_t *elems, int nel, const ElemInfo *el, int j, double val,
+                            hipStream_t s);
+hipError_t launch_probe_gather(const double *out, float *blocks, const int32_t *elems, int nel, const ElemInfo *el,
+                               int j, int nd, hipStream_t s);
+hipError_t launch_bj_apply(const float *blocks, const double *x, double *z, const ElemInfo *el, int E, int nd,
+                           hipStream_t s);
 hipError_t launch_axpby(double alpha, const double *x, double beta, double *y, int64_t n, hipStream_t s);
 int dot_partials();
 // Gram-Schmidt passes over Krylov vectors x_k = X + k ld, k < c: out[k] = x_k . w (and

@@ -42,9 +42,11 @@ __global__ __launch_bounds__(KR_WG) void k_dot_final(const double *__restrict__ 
 }
 
 // y <- alpha x + beta y (x may be y)
+// beta = 0 overwrites y without reading it (y may hold anything, NaN bit patterns of
+// uninitialised memory included)
 __global__ __launch_bounds__(KR_WG) void k_axpby(double alpha, const double *x, double beta, double *y, int64_t n) {
     const int64_t i = blockIdx.x * (int64_t)KR_WG + threadIdx.x;
-    if (i < n) y[i] = alpha * x[i] + beta * y[i];
+    if (i < n) y[i] = beta == 0.0 ? alpha * x[i] : alpha * x[i] + beta * y[i];
 }
 
 // Block reduction of KR_MD + 1 values at once: wave shuffles, one LDS row per wave,

@@ -1,0 +1,71 @@
+// Element-block Jacobi preconditioner of the adjoint operator A = (dr/du)^T for the
+// GMRES adjoint solve.  The diagonal block A_ee of every element is assembled column by
+// column from probing products: with v = 1 at local unknown j of every element of one
+// colour (no two elements of a colour share a face), (A v) restricted to an element e of
+// that colour is column j of A_ee, since the only other unknowns that the residual of e
+// couples to belong to its face neighbours, which carry zeros.  The blocks (FP32,
+// column-major, nd x nd, nd = 5 x nodes) are factored and inverted in place; applying
+// the preconditioner is then one matrix-vector product per element.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace dgt {
+
+// v[unknown j of element e] = val for the listed plan elements
+__global__ void k_probe_set(double *__restrict__ v, const int32_t *__restrict__ elems, int nel,
+                            const ElemInfo *__restrict__ el, int j, double val) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nel) return;
+    v[(int64_t)NV * el[elems[i]].noff + j] = val;
+}
+
+// column j of the block of every listed element, from the product out (plan layout)
+__global__ __launch_bounds__(256) void k_probe_gather(const double *__restrict__ out, float *__restrict__ blocks,
+                                                      const int32_t *__restrict__ elems, const ElemInfo *__restrict__ el,
+                                                      int j, int nd) {
+    const int e = elems[blockIdx.x];
+    const double *src = out + (int64_t)NV * el[e].noff;
+    float *dst = blocks + ((int64_t)e * nd + j) * nd;
+    for (int i = threadIdx.x; i < nd; i += 256) dst[i] = (float)src[i];
+}
+
+// z_e = B_e x_e per element (B_e the stored inverse, column-major); x staged in LDS, one
+// row per lane and pass, the columns read coalesced
+__global__ __launch_bounds__(256) void k_bj_apply(const float *__restrict__ blocks, const double *__restrict__ x,
+                                                  double *__restrict__ z, const ElemInfo *__restrict__ el, int nd) {
+    extern __shared__ double sx[];
+    const int e = blockIdx.x;
+    const int64_t base = (int64_t)NV * el[e].noff;
+    for (int i = threadIdx.x; i < nd; i += 256) sx[i] = x[base + i];
+    __syncthreads();
+    const float *B = blocks + (int64_t)e * nd * nd;
+    for (int i = threadIdx.x; i < nd; i += 256) {
+        double acc = 0.0;
+        for (int j = 0; j < nd; ++j) acc += (double)B[(int64_t)j * nd + i] * sx[j];
+        z[base + i] = acc;
+    }
+}
+
+hipError_t launch_probe_set(double *v, const int32_t *elems, int nel, const ElemInfo *el, int j, double val,
+                            hipStream_t s) {
+    if (nel == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_set, dim3((nel + 255) / 256), dim3(256), 0, s, v, elems, nel, el, j, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_gather(const double *out, float *blocks, const int32_t *elems, int nel, const ElemInfo *el,
+                               int j, int nd, hipStream_t s) {
+    if (nel == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe_gather, dim3(nel), dim3(256), 0, s, out, blocks, elems, el, j, nd);
+    return hipGetLastError();
+}
+
+hipError_t launch_bj_apply(const float *blocks, const double *x, double *z, const ElemInfo *el, int E, int nd,
+                           hipStream_t s) {
+    if (E == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bj_apply, dim3(E), dim3(256), sizeof(double) * nd, s, blocks, x, z, el, nd);
+    return hipGetLastError();
+}
+
+}  // namespace dgt

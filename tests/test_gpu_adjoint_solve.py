@@ -113,3 +113,89 @@ def test_restart_lengths_and_determinism(restart):
     r = dg.residual_vjp(plan, ud, psi1, form=form) - gd
     true_rel = float(torch.linalg.vector_norm(r)) / float(torch.linalg.vector_norm(gd))
     assert abs(true_rel - rr1) <= 1e-8 * rr1 + 1e-14
+
+
+def _wall_case(shape, N, seed):
+    rng = np.random.default_rng(seed)
+    mesh = wl.box_mesh(shape, bc=(1, 2, 0, 0, 0, 0), qfar=wl.conserved(*(np.array(x) for x in
+                                                                       (1.0, 0.3, 0.0, 0.0, 1.0))))
+    E = int(np.prod(shape))
+    orders = wl.uniform_orders(E, N)
+    u = wl.pulse_state(oracle.node_coords(mesh, orders), orders, sigma=0.3, amp=0.2)
+    u = wl.add_rho_noise(u, orders, rng, 1e-3)
+    return mesh, orders, u, rng
+
+
+# (2, 2, 2): two colours (even periodic directions); (2, 3, 2): a third colour for the odd
+# periodic y direction (12 colours in all)
+@pytest.mark.parametrize("shape,N", [((2, 2, 2), 2), ((2, 3, 2), 1)])
+@pytest.mark.parametrize("form", [dg.FORM_TRAD, dg.FORM_NEW])
+def test_precond_is_the_inverse_of_the_diagonal_blocks(shape, N, form):
+    """The element-block Jacobi preconditioner, assembled on the GPU from probing VJPs and
+    inverted in FP32, applied to a vector, against the inverse diagonal blocks of the
+    oracle's dense adjoint operator (complex-step Jacobian, transposed)."""
+    mesh, orders, u, rng = _wall_case(shape, N, 50 + form)
+    _, g = oracle.functional(mesh, orders, u)
+    _, Jac = adjoint.adjoint_solve(mesh, orders, u, g, form=form)
+    A = Jac.T
+    nd = 5 * (N + 1) ** 3
+    E = len(orders)
+    x = rng.normal(size=E * nd)
+    ref = np.concatenate([np.linalg.solve(A[e * nd:(e + 1) * nd, e * nd:(e + 1) * nd], x[e * nd:(e + 1) * nd])
+                          for e in range(E)])
+    plan = dg.Plan(mesh, orders)
+    pc = dg.adjoint_precond(plan, plan.to_plan(u), form=form)
+    z = plan.to_natural(dg.adjoint_precond_apply(plan, pc, plan.to_plan(x)))
+    conds = [np.linalg.cond(A[e * nd:(e + 1) * nd, e * nd:(e + 1) * nd]) for e in range(E)]
+    # FP32 blocks and inverse: within a few units of 2^-24 times the block condition number
+    assert np.max(np.abs(z - ref)) <= 1e-6 * max(conds) * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("form", [dg.FORM_TRAD, dg.FORM_NEW])
+def test_preconditioned_solve_matches_dense(form):
+    """The right-preconditioned solve converges to the dense oracle adjoint, to the same
+    bar as the plain solve, in fewer products."""
+    mesh, orders, u, _ = _wall_case((2, 2, 2), 2, 60 + form)
+    _, g = oracle.functional(mesh, orders, u)
+    psi_ref, Jac = adjoint.adjoint_solve(mesh, orders, u, g, form=form)
+    plan = dg.Plan(mesh, orders)
+    ud, gd = plan.to_plan(u), plan.to_plan(g)
+    pc = dg.adjoint_precond(plan, ud, form=form)
+    psi, iters, relres = dg.adjoint_solve(plan, ud, gd, restart=30, max_iter=4000, rtol=1e-11, form=form, precond=pc)
+    _, iters0, _ = dg.adjoint_solve(plan, ud, gd, restart=30, max_iter=4000, rtol=1e-11, form=form)
+    assert relres <= 1e-11 and 0 < iters < iters0
+    r = dg.residual_vjp(plan, ud, psi, form=form) - gd
+    assert float(torch.linalg.vector_norm(r)) <= 2e-11 * float(torch.linalg.vector_norm(gd))
+    psi_n = plan.to_natural(psi)
+    assert np.linalg.norm(Jac.T @ psi_n - g) <= 3e-11 * np.linalg.norm(g)
+    assert np.linalg.norm(psi_n - psi_ref) <= 3e-11 * np.linalg.cond(Jac) * np.linalg.norm(psi_ref)
+
+
+def test_precond_refuses_mixed_orders_and_foreign_plans():
+    mesh, orders, u, rng = _wall_case((2, 2, 2), 2, 70)
+    plan = dg.Plan(mesh, orders)
+    pc = dg.adjoint_precond(plan, plan.to_plan(u))
+    other = dg.Plan(mesh, orders)
+    with pytest.raises(dg.DGError, match="another plan"):
+        dg.adjoint_precond_apply(other, pc, other.to_plan(u))
+    mixed = dg.Plan(mesh, wl.random_orders(8, 1, 3, rng))
+    with pytest.raises(dg.DGError, match="one order triple"):
+        dg.adjoint_precond(mixed, mixed.to_plan(wl.random_state(mixed.orders_natural, rng)))
+
+
+def test_preconditioned_solve_converges_where_plain_gmres_stalls():
+    """The adjoint workload's boundaries and state on 8^3 elements of order 5: plain
+    GMRES(30) is still above 1e-2 after 300 products; with the element-block Jacobi
+    preconditioner it reaches 1e-8 (about 350 products; the oracle's scipy GMRES with the
+    same preconditioner needs 346), the reported residual checked with an independent VJP."""
+    mesh, orders = wl.c4(8, 5)
+    plan = dg.Plan(mesh, orders)
+    u = plan.to_plan(wl.c4_state(plan.to_natural(plan.node_coords(), nv=3), orders))
+    _, g = dg.functional(plan, u)
+    _, it0, rr0 = dg.adjoint_solve(plan, u, g, restart=30, max_iter=300, rtol=1e-8, form=dg.FORM_TRAD)
+    assert rr0 > 1e-2
+    pc = dg.adjoint_precond(plan, u, form=dg.FORM_TRAD)
+    psi, it, rr = dg.adjoint_solve(plan, u, g, restart=30, max_iter=1500, rtol=1e-8, form=dg.FORM_TRAD, precond=pc)
+    assert rr <= 1e-8 and it < 1000
+    r = dg.residual_vjp(plan, u, psi, form=dg.FORM_TRAD) - g
+    assert float(torch.linalg.vector_norm(r)) <= 2e-8 * float(torch.linalg.vector_norm(g))

@@ -55,6 +55,7 @@ def test_plan_host_code_under_sanitizers(tmp_path):
         subprocess.run(["hipcc", "-x", "hip", *flags, "-c", f, "-o", o], check=True, capture_output=True)
         objs.append(o)
     exe = str(tmp_path / "plan_driver")
-    subprocess.run(["hipcc", "--offload-arch=gfx950", *host, *objs, *kernels, "-o", exe], check=True,
+    subprocess.run(["hipcc", "--offload-arch=gfx950", *host, *objs, *kernels, "-o", exe, "-lrocsolver", "-lrocblas"],
+                   check=True,
                    capture_output=True)
     assert "plan driver ok" in _run(exe, tmp_path)
