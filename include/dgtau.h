@@ -18,7 +18,9 @@
  *     (u, g, dt) pointer set: it captures and instantiates a HIP graph (host-side
  *     runtime allocations); each plan and batch keeps at most 8 such graphs and
  *     destroys the least recently used one, after a device synchronisation, to
- *     make room.
+ *     make room.  Set-up calls allocate where their comments say so (plan and
+ *     batch creation, the adaptation loops, the adjoint preconditioner's
+ *     factorisation workspace).
  *   - Plans own only their internal device buffers (tables, tiles, face lists,
  *     face-flux and tau scratch).  A plan is immutable after creation; because
  *     it holds scratch buffers, one plan must not be used by two streams at once.
