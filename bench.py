@@ -65,6 +65,8 @@ def main():
                     help="run one plain 256 MiB device copy first (calibrates HBM byte counters)")
     ap.add_argument("--only", choices=["c3", "c4", "c5"], default=None,
                     help="run one secondary leg alone and print its JSON (for kernel traces)")
+    ap.add_argument("--no-precond", action="store_true",
+                    help="adjoint leg: only the unpreconditioned solve (for per-dispatch counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -78,7 +80,7 @@ def main():
     if args.only:
         stream = torch.cuda.current_stream()
         leg = {"c3": lambda: c3_leg(dg, torch, stream, check=not args.no_cpu),
-               "c4": lambda: c4_leg(dg, torch, stream, check=not args.no_cpu),
+               "c4": lambda: c4_leg(dg, torch, stream, check=not args.no_cpu, precond=not args.no_precond),
                "c5": lambda: c5_leg(dg, torch, stream, steps=5, warmup=1, check=not args.no_cpu)}[args.only]
         print(json.dumps({"leg": args.only, "result": leg()}))
         return
@@ -240,7 +242,7 @@ def main():
         out["batched"] = c5_leg(dg, torch, stream, steps=5, warmup=1, check=not args.no_cpu)
     if not args.no_extra:
         out["navier_stokes_curved"] = c3_leg(dg, torch, stream, check=not args.no_cpu)
-        out["adjoint"] = c4_leg(dg, torch, stream, check=not args.no_cpu)
+        out["adjoint"] = c4_leg(dg, torch, stream, check=not args.no_cpu, precond=not args.no_precond)
     if not args.no_cpu:
         base, ref = cpu_baseline(mesh, fo, co, u_nat, n_fine, n_est, E)
         out["cpu_baseline"] = base
@@ -344,7 +346,7 @@ def c3_leg(dg, torch, stream, check=True, dt=1e-5, nsteps=10):
     return res
 
 
-def c4_leg(dg, torch, stream, check=True):
+def c4_leg(dg, torch, stream, check=True, precond=True):
     """Adjoint workload (24^3, N = 5, slip wall at x = 0, far field at x = 1): the residual
     VJP and the wall functional; the VJP is checked against the oracle's hand-transposed
     VJP over the whole field."""
@@ -369,6 +371,10 @@ def c4_leg(dg, torch, stream, check=True):
     _, iters0, relres0 = dg.adjoint_solve(plan, u, dJ, restart=30, max_iter=300, rtol=1e-8, form=dg.FORM_TRAD)
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) * 1e3
+    if not precond:
+        return {"workload": "Euler 24^3 N=5, slip wall x=0, far field x=1, seed 4", "nodes": n, "vjp_ms": tv,
+                "functional_ms": tf, "adjoint_solve": {"unpreconditioned": {"iterations": iters0, "relres": relres0,
+                                                                            "ms": t_plain}}}
     t0 = time.perf_counter()
     pc = dg.adjoint_precond(plan, u, form=dg.FORM_TRAD)
     torch.cuda.synchronize()
