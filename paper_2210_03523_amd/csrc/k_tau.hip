@@ -342,13 +342,43 @@ namespace dgt {
 //     derivative in registers with wave-uniform coefficients; x- and y-fluxes
 //     are exchanged through LDS; the tau difference and its maxima per
 //     (c1, c2, c3) are folded with LDS atomics on the bit patterns.
+// The lanes of one c2 (rows x (c2+1) z-lines) form a block, and the blocks are
+// packed into the four waves largest first, each into the first wave with room, so
+// that every x- and y-neighbour of a lane is in its own wave: the exchange then
+// needs no workgroup barrier, and the waves drift apart, overlapping one wave's
+// LDS reads with another's arithmetic.
+template <int F>
+constexpr bool iso_blocks_fit_waves() {
+    constexpr int C = F > 2 ? F - 2 : 1;
+    for (int pair = 0; pair < (C + 1) / 2; ++pair) {
+        const int cA = pair + 1, cBr = C - pair;
+        const int cB = cBr == cA ? 0 : cBr;
+        const int rows = cA + 1 + (cB ? cB + 1 : 0);
+        int fill[4] = {0, 0, 0, 0};
+        for (int cc = C; cc >= 1; --cc) {
+            const int sz = rows * (cc + 1);
+            int q = 0;
+            while (q < 4 && fill[q] + sz > 64) ++q;
+            if (q == 4) return false;
+            fill[q] += sz;
+        }
+    }
+    return true;
+}
+
+// orders the LDS accesses of one wave (they execute in order; no hardware wait needed)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int F>
 __global__ __launch_bounds__(256) void k_sweep_iso(const int2 *__restrict__ elems, int njobs, SweepProb single,
                                                    const SweepProb *__restrict__ probs,
                                                    const double *__restrict__ tab, int rt) {
     constexpr int C = F > 2 ? F - 2 : 1;        // coarse orders per direction
     constexpr int NPAIR = (C + 1) / 2;
-    constexpr int SUMM = C * (C + 3) / 2;       // stacked coarse rows over every order
     constexpr int RMAX = C + 3;                 // rows of a pair of x-orders
     constexpr int MM = C + 1;                   // largest coarse node count
     constexpr int NL = 256;
@@ -357,6 +387,7 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int2 *__restrict__ elem
     // the same (j, k) fall in different LDS banks
     constexpr int X1S = F * F + 1;
     static_assert(2 * NV * RMAX * X1S <= 2 * NV * MM * 256, "X1 fits in the staging area");
+    static_assert(iso_blocks_fit_waves<F>(), "every c2 block fits in one wave");
     extern __shared__ double lds[];
     double *S = lds;                                                     // staging / X1
     unsigned long long *slot = (unsigned long long *)(lds + 2 * NV * MM * NL);
@@ -408,17 +439,32 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int2 *__restrict__ elem
     }
     __syncthreads();
 
-    // lane -> z-line (a, B): a over the pair's rows, B over the stacked y-rows
-    const bool active = lane < rows * SUMM;
-    const int a = active ? lane % rows : 0;
-    const int B = active ? lane / rows : 0;
-    int c2 = 1, b = B;
-    while (c2 < C && b >= c2 + 1) {
-        b -= c2 + 1;
-        ++c2;
+    // lane -> z-line (a, b) of the c2 block that covers it: lane = lbase + a + rows*b
+    int c2 = 0, lbase = lane;
+    {
+        const int w = lane >> 6, off = lane & 63;
+        int fill[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int cc = C; cc >= 1; --cc) {
+            const int sz = rows * (cc + 1);
+            bool placed = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (placed || fill[q] + sz > 64) continue;
+                if (q == w && off >= fill[q] && off < fill[q] + sz) {
+                    c2 = cc;
+                    lbase = 64 * q + fill[q];
+                }
+                fill[q] += sz;
+                placed = true;
+            }
+        }
     }
+    const bool active = c2 != 0;
+    if (!active) c2 = 1;
+    const int a = active ? (lane - lbase) % rows : 0;
+    const int b = active ? (lane - lbase) / rows : 0;
     const int m2 = c2 + 1;
-    const int B0 = B - b;                       // first stacked row of this c2
     const bool inA = a < mA;
     const int c1 = inA ? cA : cB;
     const int m1 = c1 + 1;
@@ -508,13 +554,13 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int2 *__restrict__ elem
                 Sy[(v * MM + cp) * NL + lane] = Jay * fy[v];
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         if (active) {
             // x: neighbours are the lanes of the same y-row and x-order
 #pragma unroll
             for (int q = 0; q < MM; ++q) {
                 if (q >= m1) continue;
-                const int ln = (a0 + q) + rows * B;
+                const int ln = lbase + (a0 + q) + rows * b;
                 const double d = Dx[q];
 #pragma unroll
                 for (int c = 0; c < MM; ++c) {
@@ -526,7 +572,7 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int2 *__restrict__ elem
 #pragma unroll
             for (int q = 0; q < MM; ++q) {
                 if (q >= m2) continue;
-                const int ln = a + rows * (B0 + q);
+                const int ln = lbase + a + rows * q;
                 const double d = Dy[q];
 #pragma unroll
                 for (int c = 0; c < MM; ++c) {
@@ -554,8 +600,9 @@ __global__ __launch_bounds__(256) void k_sweep_iso(const int2 *__restrict__ elem
             atomicMax(sl, (unsigned long long)__double_as_longlong(mx0));
             atomicMax(sl + 1, (unsigned long long)__double_as_longlong(mx1));
         }
-        __syncthreads();
+        wave_lds_sync();
     }
+    __syncthreads();
     // write the maxima of every (c1, c2, c3) of this workgroup
     for (int i = lane; i < 2 * C * C; i += NL) {
         const int c3 = i / (2 * C) + 1, gi = i % (2 * C);
