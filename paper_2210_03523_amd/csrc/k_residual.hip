@@ -363,13 +363,60 @@ constexpr int elem_rows() {
     return (3 * NV * elem_cols<T>(N) + 3 * DSTR) * (int)sizeof(T) <= 64 * 1024 ? 3 * NV : NV;
 }
 
+// What the element body reads from global memory for its nodes before any work (the
+// EARLY form, box Euler elements): the state, the face fluxes of the node's faces and
+// the RK register.  A persistent loop requests them for the next tile before the
+// current tile's work, so their latency overlaps it.
+template <typename T, int NPT>
+struct ElemPre {
+    T q[NPT][NV];
+    T fe[NPT][3][NV];
+    T ge[NPT][NV];
+};
+
+template <typename T, int NPT, int BS>
+__device__ __forceinline__ void elem_preload(const Tile tl, const ElemInfo E0, const T *u, const T *__restrict__ ff,
+                                             const EpiArgs &epi, ElemPre<T, NPT> &P) {
+    const int tid = threadIdx.x;
+    const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
+    const int npe = n1 * n2 * n3, total = tl.count * npe;
+    const int64_t fblk = fblock(E0.n);
+    const bool rk = epi.mode == EPI_RK && epi.rkA != 0.0;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int t = tid + k * BS;
+        const bool ok = t < total;
+        const int le = ok ? t / npe : 0, nd = ok ? t - le * npe : 0;
+        const int loc[3] = {nd % n1, (nd / n1) % n2, nd / (n1 * n2)};
+        const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le * npe);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) P.q[k][v] = ok ? u[base + v * npe + nd] : T(1);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int id = loc[d], nd_ = d == 0 ? n1 : d == 1 ? n2 : n3;
+            const bool on = ok && !epi.isolated && (id == 0 || id == nd_ - 1);
+            const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            const int na = t1 == 0 ? n1 : n2;
+            const int ab = (d == 0 ? n2 * n3 : d == 1 ? n1 * n3 : n1 * n2);
+            const T *fp = ff + E0.foff + le * fblk + fslot(E0.n, d, id == 0 ? -1 : 1) + loc[t1] + na * loc[t2];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) P.fe[k][d][v] = on ? fp[v * ab] : T(0);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) P.ge[k][v] = (ok && rk) ? ((const T *)epi.g)[base + v * npe + nd] : T(0);
+    }
+}
+
 // EARLY: the face fluxes of the node's faces and the RK register are requested right
 // after the state, so their latency overlaps the volume terms (more registers).
-template <typename T, int NPT, bool CURVED = false, int BS = WG, bool VISC = true, bool EARLY = false>
+// PRE (with EARLY): those values come from pre, requested earlier by elem_preload.
+template <typename T, int NPT, bool CURVED = false, int BS = WG, bool VISC = true, bool EARLY = false,
+          bool PRE = false>
 __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, const T *u,
                                           const T *__restrict__ ff, const T *__restrict__ tab, const Geom &g,
                                           const PhysParams &ph, const EpiArgs &epi, T (*sF)[elem_cols<T>(BS * NPT)],
-                                          T *sD) {
+                                          T *sD, const ElemPre<T, NPT> *pre = nullptr) {
+    static_assert(!PRE || (EARLY && !CURVED && !VISC), "preloaded values are those of the EARLY box form");
     constexpr bool ALLD = elem_rows<T, BS * NPT>() == 3 * NV;
     const int tid = threadIdx.x;
     const int n1 = E0.n[0], n2 = E0.n[1], n3 = E0.n[2];
@@ -405,7 +452,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
         const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            q[k][v] = ok[k] ? u[base + v * npe + nd[k]] : T(1);
+            q[k][v] = PRE ? pre->q[k][v] : ok[k] ? u[base + v * npe + nd[k]] : T(1);
             V[k][v] = T(0);
         }
         if (CURVED) {
@@ -427,7 +474,17 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
     constexpr int NE = EARLY ? NPT : 1;
     T fe[NE][3][NV];  // EARLY: face fluxes (per direction; zero off the faces)
     T ge[NE][NV];     // EARLY: the RK register
-    if (EARLY) {
+    if (PRE) {
+#pragma unroll
+        for (int k = 0; k < NE; ++k)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                fe[k][0][v] = pre->fe[PRE ? k : 0][0][v];
+                fe[k][1][v] = pre->fe[PRE ? k : 0][1][v];
+                fe[k][2][v] = pre->fe[PRE ? k : 0][2][v];
+                ge[k][v] = pre->ge[PRE ? k : 0][v];
+            }
+    } else if (EARLY) {
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
             const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
@@ -995,15 +1052,55 @@ __global__ __launch_bounds__(BS) void k_elem_batch(const BatchTile *__restrict__
                                                    EpiArgs epi0) {
     __shared__ T sF[elem_rows<T, BS * NPT>()][elem_cols<T>(BS * NPT)];
     __shared__ T sD[3 * DSTR];
-    for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
-        const BatchTile bt = tiles[i];
-        const ProbDesc<T> pd = probs[bt.prob];
-        EpiArgs epi = epi0;
-        epi.out = pd.out;
-        epi.g = pd.g;
-        elem_body<T, NPT, false, BS, false, true>(Tile{bt.first, bt.count}, bt.e0, pd.u, pd.ff, tab, pd.geom,
-                                                 pd.phys, epi, sF, sD);
+    __shared__ T sTab[T_I];  // node, weight and derivative tables of every order
+    const int G = gridDim.x;
+    int i = blockIdx.x;
+    if (i >= ntiles) return;
+    if (sizeof(T) == 8) {  // FP64: the pipeline's registers would cost a wave per SIMD
+        for (; i < ntiles; i += G) {
+            const BatchTile bt = tiles[i];
+            const ProbDesc<T> pd = probs[bt.prob];
+            EpiArgs epi = epi0;
+            epi.out = pd.out;
+            epi.g = pd.g;
+            elem_body<T, NPT, false, BS, false, true>(Tile{bt.first, bt.count}, bt.e0, pd.u, pd.ff, tab, pd.geom,
+                                                     pd.phys, epi, sF, sD);
+            __syncthreads();
+        }
+        return;
+    }
+    // A software pipeline over the workgroup's tiles i, i + G, ...: while tile j is
+    // processed, the state, face fluxes and RK register of tile j + 1 are in flight, the
+    // descriptor of tile j + 2 and the record of tile j + 3.  The tables are read from
+    // LDS, so the body waits on no global load of its own (vector loads complete in
+    // order: a wait for a later load would wait for the prefetch as well).
+    for (int t = threadIdx.x; t < T_I; t += BS) sTab[t] = tab[t];
+    auto at = [&](int k) { return k < ntiles ? k : ntiles - 1; };
+    auto epi_of = [&](const ProbDesc<T> &pd) {
+        EpiArgs e = epi0;
+        e.out = pd.out;
+        e.g = pd.g;
+        return e;
+    };
+    BatchTile r0 = tiles[i], r1 = tiles[at(i + G)], r2 = tiles[at(i + 2 * G)];
+    ProbDesc<T> p0 = probs[r0.prob], p1 = probs[r1.prob];
+    ElemPre<T, NPT> d0;
+    elem_preload<T, NPT, BS>(Tile{r0.first, r0.count}, r0.e0, p0.u, p0.ff, epi_of(p0), d0);
+    __syncthreads();  // sTab
+    for (; i < ntiles; i += G) {
+        ElemPre<T, NPT> d1;
+        elem_preload<T, NPT, BS>(Tile{r1.first, r1.count}, r1.e0, p1.u, p1.ff, epi_of(p1), d1);
+        const ProbDesc<T> p2 = probs[r2.prob];
+        const BatchTile r3 = tiles[at(i + 3 * G)];
+        elem_body<T, NPT, false, BS, false, true, true>(Tile{r0.first, r0.count}, r0.e0, p0.u, p0.ff, sTab,
+                                                       p0.geom, p0.phys, epi_of(p0), sF, sD, &d0);
         __syncthreads();
+        r0 = r1;
+        r1 = r2;
+        r2 = r3;
+        p0 = p1;
+        p1 = p2;
+        d0 = d1;
     }
 }
 
