@@ -407,9 +407,27 @@ __device__ __forceinline__ void elem_preload(const Tile tl, const ElemInfo E0, c
     }
 }
 
+// Workgroup barrier of the element body.  LDS_ONLY: the wave's own LDS accesses are
+// completed (lgkmcnt) and the compiler keeps memory accesses on their side of it, but
+// vector-memory loads in flight -- the next tile's, requested before this tile's work --
+// are not waited for, as the full barrier's memory fence would; the body shares nothing
+// between lanes through global memory.
+template <bool LDS_ONLY>
+__device__ __forceinline__ void elem_sync() {
+    if (LDS_ONLY) {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt left alone
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    } else {
+        __syncthreads();
+    }
+}
+
 // EARLY: the face fluxes of the node's faces and the RK register are requested right
 // after the state, so their latency overlaps the volume terms (more registers).
-// PRE (with EARLY): those values come from pre, requested earlier by elem_preload.
+// PRE (with EARLY): those values come from pre, requested earlier by elem_preload; the
+// body's barriers then order LDS only.
 template <typename T, int NPT, bool CURVED = false, int BS = WG, bool VISC = true, bool EARLY = false,
           bool PRE = false>
 __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, const T *u,
@@ -552,7 +570,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
                     }
                 }
             }
-            __syncthreads();
+            elem_sync<PRE>();
         }
         const int nd_ = nn[d];
         const T *Dm = sD + d * DSTR;
@@ -578,7 +596,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
         }
         // the next direction's staging (or, after the last, the next tile of a persistent
         // loop and the epilogue's reduction) overwrites sF only after this barrier
-        if (!ALLD || d == 2) __syncthreads();
+        if (!ALLD || d == 2) elem_sync<PRE>();
     }
     // lifted surface terms from the face pass
     if (!epi.isolated) {
@@ -668,7 +686,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
     // Per-element reduction of three per-node values (two maxima and a sum): stage in
     // LDS, then reduce each element's segment in a fixed order; emit(elem, m0, m1, s2).
     auto reduce = [&](auto val, auto emit) {
-        __syncthreads();
+        elem_sync<PRE>();
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int t = tid + k * BS;
@@ -676,7 +694,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
             sF[1][t] = val(k, 1);
             sF[2][t] = val(k, 2);
         }
-        __syncthreads();
+        elem_sync<PRE>();
         if (tl.count == 1) {
             for (int s = BS * NPT / 2; s > 0; s >>= 1) {
 #pragma unroll
@@ -688,7 +706,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
                         sF[2][t] = sF[2][t] + sF[2][t + s];
                     }
                 }
-                __syncthreads();
+                elem_sync<PRE>();
             }
             if (tid == 0) emit((int64_t)tl.first, sF[0][0], sF[1][0], sF[2][0]);
         } else if (tid < tl.count) {
@@ -1094,7 +1112,7 @@ __global__ __launch_bounds__(BS) void k_elem_batch(const BatchTile *__restrict__
         const BatchTile r3 = tiles[at(i + 3 * G)];
         elem_body<T, NPT, false, BS, false, true, true>(Tile{r0.first, r0.count}, r0.e0, p0.u, p0.ff, sTab,
                                                        p0.geom, p0.phys, epi_of(p0), sF, sD, &d0);
-        __syncthreads();
+        elem_sync<true>();
         r0 = r1;
         r1 = r2;
         r2 = r3;
