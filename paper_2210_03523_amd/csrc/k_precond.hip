@@ -8,6 +8,8 @@
 // the preconditioner is then one matrix-vector product per element.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace dgt {
@@ -30,17 +32,42 @@ __global__ __launch_bounds__(256) void k_probe_gather(const double *__restrict__
     for (int i = threadIdx.x; i < nd; i += 256) dst[i] = (float)src[i];
 }
 
-// z_e = B_e x_e per element (B_e the stored inverse, column-major); x staged in LDS, one
-// row per lane and pass, the columns read coalesced
-__global__ __launch_bounds__(256) void k_bj_apply(const float *__restrict__ blocks, const double *__restrict__ x,
+// z_e = B_e x_e per element (B_e the stored inverse, column-major); x staged in LDS, the
+// columns read coalesced.  Blocks whose size nd is a multiple of 4 (16-byte aligned
+// columns): a lane owns 4 consecutive rows, reads them as one 16-byte load per column and
+// keeps 4 columns' loads in flight; the workgroup has a lane per row quad (nd / 4 rounded
+// up to whole waves, at most 1024).  Otherwise 256 lanes of one row each per pass.
+__global__ __launch_bounds__(1024) void k_bj_apply(const float *__restrict__ blocks, const double *__restrict__ x,
                                                   double *__restrict__ z, const ElemInfo *__restrict__ el, int nd) {
     extern __shared__ double sx[];
     const int e = blockIdx.x;
     const int64_t base = (int64_t)NV * el[e].noff;
-    for (int i = threadIdx.x; i < nd; i += 256) sx[i] = x[base + i];
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) sx[i] = x[base + i];
     __syncthreads();
     const float *B = blocks + (int64_t)e * nd * nd;
-    for (int i = threadIdx.x; i < nd; i += 256) {
+    if ((nd & 3) == 0) {
+        const int nq = nd >> 2;  // row quads
+        for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            const float4 *col = (const float4 *)B + q;
+#pragma unroll 4
+            for (int j = 0; j < nd; ++j) {
+                const float4 b = col[(int64_t)j * nq];
+                const double xj = sx[j];
+                a0 += (double)b.x * xj;
+                a1 += (double)b.y * xj;
+                a2 += (double)b.z * xj;
+                a3 += (double)b.w * xj;
+            }
+            double *zz = z + base + 4 * q;
+            zz[0] = a0;
+            zz[1] = a1;
+            zz[2] = a2;
+            zz[3] = a3;
+        }
+        return;
+    }
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
         double acc = 0.0;
         for (int j = 0; j < nd; ++j) acc += (double)B[(int64_t)j * nd + i] * sx[j];
         z[base + i] = acc;
@@ -64,7 +91,8 @@ hipError_t launch_probe_gather(const double *out, float *blocks, const int32_t *
 hipError_t launch_bj_apply(const float *blocks, const double *x, double *z, const ElemInfo *el, int E, int nd,
                            hipStream_t s) {
     if (E == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bj_apply, dim3(E), dim3(256), sizeof(double) * nd, s, blocks, x, z, el, nd);
+    const int threads = (nd & 3) == 0 ? std::min(1024, (nd / 4 + 63) / 64 * 64) : 256;
+    hipLaunchKernelGGL(k_bj_apply, dim3(E), dim3(threads), sizeof(double) * nd, s, blocks, x, z, el, nd);
     return hipGetLastError();
 }
 
