@@ -499,6 +499,15 @@ dg_status dg_batch_destroy(dg_batch batch);
  * 1: 256 x 2, 2: 512 x 1), and from_cache = 1 when it came from the cache. */
 dg_status dg_batch_schedule(dg_batch batch, int32_t *tile_cap, int32_t *elem_grid, int32_t *face_grid,
                             int32_t *shape, int32_t *from_cache);
+/* Replace the autotuner's schedule (for reproducible timings and tests): tile_cap 256
+ * with shape 0, or 512 with shape 1 or 2, at least the largest element's node count;
+ * positive grid sizes.  Every schedule gives the same results bit for bit.  SYNCHRONOUS:
+ * waits for the device, drops the batch's captured RK3 graphs (they hold the old tiles
+ * and grids) and rebuilds its tile list (a device allocation: set-up, not a hot call).
+ * Errors: DG_EINVAL (null batch, a shape / capacity pair not listed, a capacity below an
+ * element's node count, a non-positive grid), DG_EHIP. */
+dg_status dg_batch_set_schedule(dg_batch batch, int32_t tile_cap, int32_t elem_grid, int32_t face_grid,
+                                int32_t shape);
 /* New-form residual of every problem (Section 2.1): u[i], r[i] device arrays of
  * problem i in its plan layout (host arrays of n device pointers).  The pointer
  * arrays are staged through a ring of four pinned descriptor slots; the call

@@ -101,6 +101,7 @@ SIGNATURES = {
     "dg_batch_create": [ctypes.POINTER(_P), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)],
     "dg_batch_destroy": [_P],
     "dg_batch_schedule": [_P, _I32P, _I32P, _I32P, _I32P, _I32P],
+    "dg_batch_set_schedule": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "dg_batch_residual": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P],
     "dg_batch_rk3_step": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_double, ctypes.c_int32, _P],
     "dg_batch_to_f64": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _P],
@@ -616,6 +617,10 @@ class Batch:
         v = [ctypes.c_int32() for _ in range(5)]
         _call("dg_batch_schedule", self.handle, *[ctypes.byref(x) for x in v])
         return tuple(x.value for x in v[:4]) + (bool(v[4].value),)
+
+    def set_schedule(self, tile_cap: int, elem_grid: int, face_grid: int, shape: int):
+        """Replace the autotuner's schedule (synchronous; drops the captured RK3 graphs)."""
+        _call("dg_batch_set_schedule", self.handle, int(tile_cap), int(elem_grid), int(face_grid), int(shape))
 
     def _ptrs(self, ts):
         if len(ts) != len(self.plans):

@@ -2045,6 +2045,29 @@ dg_status dg_batch_schedule(dg_batch b, int32_t *tile_cap, int32_t *elem_grid, i
     return DG_OK;
 }
 
+dg_status dg_batch_set_schedule(dg_batch b, int32_t tile_cap, int32_t elem_grid, int32_t face_grid,
+                                int32_t shape) {
+    if (!b) return fail(DG_EINVAL, "null batch");
+    if (shape < 0 || shape > 2) return fail(DG_EINVAL, "shape must be 0, 1 or 2");
+    if (tile_cap != (shape == 0 ? 256 : 512))
+        return fail(DG_EINVAL, "tile capacity 256 goes with shape 0, 512 with shapes 1 and 2");
+    if (elem_grid < 1 || face_grid < 1) return fail(DG_EINVAL, "grid sizes must be positive");
+    int max_npe = 1;
+    for (dg_plan p : b->plans)
+        for (int e = 0; e < p->E; ++e)
+            max_npe = std::max(max_npe, (p->ord[3 * e] + 1) * (p->ord[3 * e + 1] + 1) * (p->ord[3 * e + 2] + 1));
+    if (max_npe > tile_cap) return fail(DG_EINVAL, "an element of the batch does not fit the tile capacity");
+    // work in flight and the captured RK3 graphs use the old tiles and grids
+    HIP_TRY(hipDeviceSynchronize());
+    for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+    b->graphs.clear();
+    b->shape = shape;
+    b->elem_grid = elem_grid;
+    b->face_grid = face_grid;
+    b->from_cache = false;
+    return set_tiles(b, tile_cap);
+}
+
 dg_status dg_batch_residual(dg_batch b, const void *const *u, void *const *r, hipStream_t stream) {
     if (!b || !u || !r) return fail(DG_EINVAL, "null argument");
     for (size_t i = 0; i < b->plans.size(); ++i)

@@ -46,6 +46,44 @@ def test_batch_residual(dtype, tol):
             assert torch.allclose(r1, r, rtol=0, atol=1e-13 * s)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_every_schedule_gives_the_same_residual(dtype):
+    """Forced schedules -- both tile capacities and all three element-kernel shapes, grids
+    from one workgroup (one persistent workgroup runs every tile and face, through the
+    element pass's software pipeline from its first tile to its last) to one per work
+    item -- give the tuned schedule's residuals and RK3 states bit for bit."""
+    probs = _problems(nprob=6, seed=41)
+    plans = [dg.Plan(m, o) for m, o, _ in probs]
+    batch = dg.Batch(plans, dtype=dtype)
+    us = [p.to_plan(u, dtype=dtype) for p, (_, _, u) in zip(plans, probs)]
+    ref = [r.clone() for r in dg.batch_residual(batch, us)]
+    ref_rk = [u.clone() for u in us]
+    dg.batch_rk3_step(batch, ref_rk, [torch.zeros_like(u) for u in us], 1e-3)
+    max_npe = max(int(np.prod(np.asarray(o) + 1, axis=1).max()) for _, o, _ in probs)
+    nt_big = sum(p.n_nodes for p in plans)  # above any tile or face count
+    for cap, shape in ((256, 0), (512, 1), (512, 2)):
+        if cap < max_npe:
+            with pytest.raises(dg.DGError, match="tile capacity"):
+                batch.set_schedule(cap, 8, 8, shape)
+            continue
+        for eg, fg in ((1, 1), (3, 7), (64, 1000), (nt_big, nt_big)):
+            batch.set_schedule(cap, eg, fg, shape)
+            assert batch.schedule_info()[:4] == (cap, eg, fg, shape)
+            got = dg.batch_residual(batch, us)
+            for a, b in zip(got, ref):
+                assert torch.equal(a, b), (cap, shape, eg, fg)
+            uu = [u.clone() for u in us]
+            dg.batch_rk3_step(batch, uu, [torch.zeros_like(u) for u in us], 1e-3)
+            for a, b in zip(uu, ref_rk):
+                assert torch.equal(a, b), (cap, shape, eg, fg)
+    with pytest.raises(dg.DGError, match="shape"):
+        batch.set_schedule(512, 8, 8, 3)
+    with pytest.raises(dg.DGError, match="256 goes with shape 0"):
+        batch.set_schedule(256, 8, 8, 2)
+    with pytest.raises(dg.DGError, match="positive"):
+        batch.set_schedule(512, 0, 8, 2)
+
+
 def test_schedule_cache():
     """A second batch of the same composition (new plans of the same meshes and orders)
     takes the autotuner's cached schedule and gives the same residuals bit for bit; a
