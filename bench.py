@@ -376,9 +376,17 @@ def c4_leg(dg, torch, stream, check=True, precond=True):
                 "functional_ms": tf, "adjoint_solve": {"unpreconditioned": {"iterations": iters0, "relres": relres0,
                                                                             "ms": t_plain}}}
     t0 = time.perf_counter()
-    pc = dg.adjoint_precond(plan, u, form=dg.FORM_TRAD)
+    pc32 = dg.adjoint_precond(plan, u, form=dg.FORM_TRAD)
     torch.cuda.synchronize()
     t_pc = (time.perf_counter() - t0) * 1e3
+    pc32_gb = pc32.numel() / 1e9
+    # the compact form (FP16 blocks over per-column scales) is the one the solve uses
+    t0 = time.perf_counter()
+    pc = dg.adjoint_precond_compact(plan, pc32)
+    torch.cuda.synchronize()
+    t_compact = (time.perf_counter() - t0) * 1e3
+    del pc32
+    torch.cuda.empty_cache()
     pc_gb = pc.numel() / 1e9
     t0 = time.perf_counter()
     psi, iters, relres = dg.adjoint_solve(plan, u, dJ, restart=30, max_iter=4000, rtol=1e-8, form=dg.FORM_TRAD,
@@ -393,8 +401,10 @@ def c4_leg(dg, torch, stream, check=True, precond=True):
            "vjp_hbm_frac": 120.0 * n / (tv * 1e-3) / 1e9 / PEAK_HBM_GBS,
            "functional_ms": tf,
            "adjoint_solve": {"method": "GMRES(30) on the residual VJP, right-preconditioned by element-block "
-                                       "Jacobi (FP32 inverse blocks from probing VJPs), rtol 1e-8",
-                             "precond_build_ms": t_pc, "precond_gb": pc_gb,
+                                       "Jacobi (inverse blocks from probing VJPs, inverted in FP32, stored as FP16 "
+                                       "over per-column scales), rtol 1e-8",
+                             "precond_build_ms": t_pc, "precond_fp32_gb": pc32_gb,
+                             "precond_compact_ms": t_compact, "precond_gb": pc_gb,
                              "ms": t_adj, "iterations": iters, "ms_per_iteration": t_adj / max(iters, 1),
                              "gmres_relres": relres, "true_relres": true_rel,
                              "unpreconditioned": {"iterations": iters0, "relres": relres0, "ms": t_plain}}}

@@ -452,7 +452,23 @@ dg_status dg_adjoint_solve(dg_plan plan, const double *u, const double *g, doubl
 dg_status dg_adjoint_precond_bytes(dg_plan plan, int64_t *bytes);
 dg_status dg_adjoint_precond_build(dg_plan plan, const double *u, int32_t form, int32_t isolated, void *pc,
                                    double *work, hipStream_t stream);
-/* z = M^-1 x with a built preconditioner (x, z: device double, plan layout, distinct). */
+/* Compact form of a built preconditioner: every inverse block stored as FP16 values of
+ * B_ij / s_j with the column scale s_j = max_i |B_ij| in FP32 (half the bytes each
+ * application reads; the preconditioner's entries are then known to about 2^-11 of their
+ * column's largest, which right preconditioning tolerates: the iteration and its
+ * stopping test stay FP64).
+ *   compact_bytes: the size of the compact form's caller-owned memory.
+ *   pc: a preconditioner built by dg_adjoint_precond_build for this plan (left as it is;
+ *       the caller may free it afterwards).  pc16: device memory of compact_bytes,
+ *       256-byte aligned, distinct from pc.
+ * The compact form is accepted wherever a preconditioner is (dg_adjoint_precond_apply,
+ * dg_adjoint_params.precond).  SYNCHRONOUS; allocates nothing.  Errors: DG_EINVAL (null
+ * or misaligned arguments, pc of another plan or already compact), DG_EUNSUPPORTED (as
+ * dg_adjoint_precond_bytes), DG_EHIP. */
+dg_status dg_adjoint_precond_compact_bytes(dg_plan plan, int64_t *bytes);
+dg_status dg_adjoint_precond_compact(dg_plan plan, const void *pc, void *pc16, hipStream_t stream);
+/* z = M^-1 x with a built preconditioner, either form (x, z: device double, plan layout,
+ * distinct). */
 dg_status dg_adjoint_precond_apply(dg_plan plan, const void *pc, const double *x, double *z, hipStream_t stream);
 
 /* Pressure force along x on the slip walls (faces normal to x):

@@ -93,6 +93,8 @@ SIGNATURES = {
     "dg_adjoint_precond_bytes": [_P, _I64P],
     "dg_adjoint_precond_build": [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P],
     "dg_adjoint_precond_apply": [_P, _P, _P, _P, _P],
+    "dg_adjoint_precond_compact_bytes": [_P, _I64P],
+    "dg_adjoint_precond_compact": [_P, _P, _P, _P],
     "dg_adjoint_solve": [_P, _P, _P, _P, ctypes.POINTER(_AdjointParams), _P, _I32P,
                          ctypes.POINTER(ctypes.c_double), _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
@@ -486,6 +488,17 @@ def adjoint_precond(plan: Plan, u, form: int = FORM_TRAD, isolated: bool = False
     _call("dg_adjoint_precond_build", plan.handle, _ptr(u), int(form), int(bool(isolated)), _ptr(pc), _ptr(work),
           _stream())
     return pc
+
+
+def adjoint_precond_compact(plan: Plan, pc):
+    """The compact (FP16 blocks, per-column scales) form of a preconditioner of
+    adjoint_precond (dg_adjoint_precond_compact): new device memory; pc is left as it is."""
+    torch = _torch()
+    nb = ctypes.c_int64()
+    _call("dg_adjoint_precond_compact_bytes", plan.handle, ctypes.byref(nb))
+    pc16 = torch.empty(int(nb.value), dtype=torch.uint8, device="cuda")
+    _call("dg_adjoint_precond_compact", plan.handle, _ptr(pc), _ptr(pc16), _stream())
+    return pc16
 
 
 def adjoint_precond_apply(plan: Plan, pc, x):

@@ -1342,8 +1342,10 @@ namespace {
 // factorisation flags [E], and the inverted blocks [E][nd][nd] (FP32, column-major).
 struct PrecondHeader {
     uint64_t magic;  // identifies the plan the memory was built for
-    int32_t E, nd, ncolor, pad;
+    int32_t E, nd, ncolor;
+    int32_t compact;  // 0: FP32 inverse blocks; 1: FP16 blocks with per-column FP32 scales
     int64_t off_first, off_elems, off_ipiv, off_info, off_blocks, bytes;
+    int64_t off_scales;  // compact form only
 };
 constexpr int kMaxColors = 27;
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1473,7 +1475,57 @@ dg_status precond_view(dg_plan p, const void *pc, PrecondHeader *h) {
     if (h->magic != plan_magic(p) || h->E != p->E) return fail(DG_EINVAL, "the preconditioner was built for another plan");
     return DG_OK;
 }
+PrecondHeader compact_layout(int E, int nd) {
+    PrecondHeader h{};
+    h.E = E;
+    h.nd = nd;
+    h.compact = 1;
+    size_t o = align256(sizeof(PrecondHeader));
+    h.off_scales = (int64_t)o;
+    o = align256(o + sizeof(float) * (size_t)E * nd);
+    h.off_blocks = (int64_t)o;
+    o += sizeof(uint16_t) * (size_t)E * nd * nd;
+    h.bytes = (int64_t)o;
+    return h;
+}
+// z = M^-1 x with a built preconditioner of either form
+hipError_t precond_apply(const PrecondHeader &h, const void *pc, const double *x, double *z, dg_plan p,
+                         hipStream_t stream) {
+    const char *b = (const char *)pc;
+    if (h.compact)
+        return launch_bj_apply16(b + h.off_blocks, (const float *)(b + h.off_scales), x, z, p->d_el, p->E, h.nd,
+                                 stream);
+    return launch_bj_apply((const float *)(b + h.off_blocks), x, z, p->d_el, p->E, h.nd, stream);
+}
 }  // namespace
+
+dg_status dg_adjoint_precond_compact_bytes(dg_plan p, int64_t *bytes) {
+    if (!p || !bytes) return fail(DG_EINVAL, "null argument");
+    int nd = 0;
+    dg_status st = precond_check(p, &nd);
+    if (st) return st;
+    *bytes = compact_layout(p->E, nd).bytes;
+    return DG_OK;
+}
+
+dg_status dg_adjoint_precond_compact(dg_plan p, const void *pc, void *pc16, hipStream_t stream) {
+    if (!p || !pc || !pc16) return fail(DG_EINVAL, "null argument");
+    if ((uintptr_t)pc16 & 255) return fail(DG_EINVAL, "the preconditioner memory must be 256-byte aligned");
+    if (pc == pc16) return fail(DG_EINVAL, "the compact preconditioner needs memory of its own");
+    PrecondHeader h;
+    dg_status st = precond_view(p, pc, &h);
+    if (st) return st;
+    if (h.compact) return fail(DG_EINVAL, "the preconditioner is already compact");
+    PrecondHeader hc = compact_layout(p->E, h.nd);
+    hc.magic = h.magic;
+    hc.ncolor = h.ncolor;
+    char *b = (char *)pc16;
+    HIP_TRY(launch_bj_compact((const float *)((const char *)pc + h.off_blocks), b + hc.off_blocks,
+                              (float *)(b + hc.off_scales), p->E, h.nd, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipMemcpy(pc16, &hc, sizeof(hc), hipMemcpyHostToDevice));
+    return DG_OK;
+}
 
 dg_status dg_adjoint_precond_apply(dg_plan p, const void *pc, const double *x, double *z, hipStream_t stream) {
     if (!p || !pc || !x || !z) return fail(DG_EINVAL, "null argument");
@@ -1482,7 +1534,7 @@ dg_status dg_adjoint_precond_apply(dg_plan p, const void *pc, const double *x, d
     PrecondHeader h;
     dg_status st = precond_view(p, pc, &h);
     if (st) return st;
-    HIP_TRY(launch_bj_apply((const float *)((const char *)pc + h.off_blocks), x, z, p->d_el, p->E, h.nd, stream));
+    HIP_TRY(precond_apply(h, pc, x, z, p, stream));
     return DG_OK;
 }
 static_assert(DG_KRYLOV_MAX == DG_ADJOINT_MAX_RESTART + 1, "Krylov kernels sized for the largest restart");
@@ -1511,11 +1563,11 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
     double *Z = work + (int64_t)(m + 2) * ld;  // M^-1 of a Krylov vector (preconditioned solves)
     double *part = work + (int64_t)(m + 3) * ld;
     PrecondHeader ph{};
-    const float *pblk = nullptr;
+    const void *pblk = nullptr;  // the preconditioner, if any (either form)
     if (prm->precond) {
         dg_status st0 = precond_view(p, prm->precond, &ph);
         if (st0) return st0;
-        pblk = (const float *)((const char *)prm->precond + ph.off_blocks);
+        pblk = prm->precond;
     }
     double *hb = part + mdot_partials();  // 2 (m + 4) doubles: a step's coefficients and norms
     auto fetch = [&](double *dst, int count) -> dg_status {
@@ -1533,7 +1585,7 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
     // A^T M^-1 v (right preconditioning) or A^T v
     auto pmatvec = [&](const double *v, double *out) -> dg_status {
         if (!pblk) return matvec(v, out);
-        HIP_TRY(launch_bj_apply(pblk, v, Z, p->d_el, p->E, ph.nd, stream));
+        HIP_TRY(precond_apply(ph, pblk, v, Z, p, stream));
         return matvec(Z, out);
     };
     dg_status st;
@@ -1617,7 +1669,7 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
             double *t = V + (int64_t)(m + 1) * ld;
             HIP_TRY(launch_axpby(y[0], V, 0.0, t, n, stream));
             for (int i = 1; i < k; ++i) HIP_TRY(launch_axpby(y[i], V + (int64_t)i * ld, 1.0, t, n, stream));
-            HIP_TRY(launch_bj_apply(pblk, t, Z, p->d_el, p->E, ph.nd, stream));
+            HIP_TRY(precond_apply(ph, pblk, t, Z, p, stream));
             HIP_TRY(launch_axpby(1.0, Z, 1.0, psi, n, stream));
         }
     }

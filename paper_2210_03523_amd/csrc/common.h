@@ -208,6 +208,10 @@ hipError_t launch_probe_gather(const double *out, float *blocks, const int32_t *
                                int j, int nd, hipStream_t s);
 hipError_t launch_bj_apply(const float *blocks, const double *x, double *z, const ElemInfo *el, int E, int nd,
                            hipStream_t s);
+// Compact FP16 storage of the inverse blocks with per-column FP32 scales, and its apply.
+hipError_t launch_bj_compact(const float *blocks, void *hblocks, float *scales, int E, int nd, hipStream_t s);
+hipError_t launch_bj_apply16(const void *hblocks, const float *scales, const double *x, double *z,
+                             const ElemInfo *el, int E, int nd, hipStream_t s);
 hipError_t launch_axpby(double alpha, const double *x, double beta, double *y, int64_t n, hipStream_t s);
 int dot_partials();
 // Gram-Schmidt passes over Krylov vectors x_k = X + k ld, k < c: out[k] = x_k . w (and

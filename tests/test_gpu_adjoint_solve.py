@@ -199,3 +199,57 @@ def test_preconditioned_solve_converges_where_plain_gmres_stalls():
     assert rr <= 1e-8 and it < 1000
     r = dg.residual_vjp(plan, u, psi, form=dg.FORM_TRAD) - g
     assert float(torch.linalg.vector_norm(r)) <= 2e-8 * float(torch.linalg.vector_norm(g))
+
+
+@pytest.mark.parametrize("shape,N", [((2, 2, 2), 2), ((2, 3, 2), 1)])
+def test_compact_precond_against_dense_blocks(shape, N):
+    """The compact form (FP16 blocks over per-column scales) applied to a vector, against
+    the inverse diagonal blocks of the oracle's dense adjoint operator: within the FP32
+    form's bar plus the FP16 rounding of every block entry, 2^-11 of its column's largest
+    (the scales taken from the exact inverse)."""
+    mesh, orders, u, rng = _wall_case(shape, N, 80)
+    _, g = oracle.functional(mesh, orders, u)
+    _, Jac = adjoint.adjoint_solve(mesh, orders, u, g, form=dg.FORM_TRAD)
+    A = Jac.T
+    nd = 5 * (N + 1) ** 3
+    E = len(orders)
+    x = rng.normal(size=E * nd)
+    blocks = [np.linalg.inv(A[e * nd:(e + 1) * nd, e * nd:(e + 1) * nd]) for e in range(E)]
+    ref = np.concatenate([blocks[e] @ x[e * nd:(e + 1) * nd] for e in range(E)])
+    conds = [np.linalg.cond(A[e * nd:(e + 1) * nd, e * nd:(e + 1) * nd]) for e in range(E)]
+    fp16 = max(float(np.abs(blocks[e]).max(axis=0) @ np.abs(x[e * nd:(e + 1) * nd])) for e in range(E))
+    plan = dg.Plan(mesh, orders)
+    pc = dg.adjoint_precond(plan, plan.to_plan(u))
+    pc16 = dg.adjoint_precond_compact(plan, pc)
+    assert pc16.numel() < 0.6 * pc.numel()
+    z = plan.to_natural(dg.adjoint_precond_apply(plan, pc16, plan.to_plan(x)))
+    err = np.max(np.abs(z - ref))
+    assert err <= 1e-6 * max(conds) * np.max(np.abs(ref)) + 1.01 * 2.0 ** -11 * fp16
+    # and not merely within that bound: the FP16 form does differ from the FP32 one
+    z32 = plan.to_natural(dg.adjoint_precond_apply(plan, pc, plan.to_plan(x)))
+    assert np.max(np.abs(z - z32)) > 0
+    with pytest.raises(dg.DGError, match="already compact"):
+        dg.adjoint_precond_compact(plan, pc16)
+    other = dg.Plan(mesh, orders)
+    with pytest.raises(dg.DGError, match="another plan"):
+        dg.adjoint_precond_compact(other, pc)
+
+
+@pytest.mark.parametrize("form", [dg.FORM_TRAD, dg.FORM_NEW])
+def test_compact_preconditioned_solve_matches_dense(form):
+    """With the compact preconditioner the solve reaches the same FP64 bar and the dense
+    oracle adjoint; its product count stays within a few of the FP32 form's."""
+    mesh, orders, u, _ = _wall_case((2, 2, 2), 2, 90 + form)
+    _, g = oracle.functional(mesh, orders, u)
+    psi_ref, Jac = adjoint.adjoint_solve(mesh, orders, u, g, form=form)
+    plan = dg.Plan(mesh, orders)
+    ud, gd = plan.to_plan(u), plan.to_plan(g)
+    pc = dg.adjoint_precond(plan, ud, form=form)
+    pc16 = dg.adjoint_precond_compact(plan, pc)
+    _, it32, _ = dg.adjoint_solve(plan, ud, gd, restart=30, max_iter=4000, rtol=1e-11, form=form, precond=pc)
+    psi, it, relres = dg.adjoint_solve(plan, ud, gd, restart=30, max_iter=4000, rtol=1e-11, form=form, precond=pc16)
+    assert relres <= 1e-11 and it <= it32 + max(3, it32 // 10)
+    r = dg.residual_vjp(plan, ud, psi, form=form) - gd
+    assert float(torch.linalg.vector_norm(r)) <= 2e-11 * float(torch.linalg.vector_norm(gd))
+    psi_n = plan.to_natural(psi)
+    assert np.linalg.norm(psi_n - psi_ref) <= 3e-11 * np.linalg.cond(Jac) * np.linalg.norm(psi_ref)
