@@ -336,10 +336,12 @@ dg_status build_plan(const dg_mesh_desc *mesh, const int32_t *orders, dg_plan pa
             if (orders[i] < mesh->geo_order[i % 3])
                 return fail(DG_EINVAL, "curved elements need orders >= the geometry order");
 
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail(DG_EHIP, "no current device");
     dg_plan p = new dg_plan_s();
     p->mesh = *mesh;
     p->E = E;
-    hipGetDevice(&p->device);
+    p->device = device;
     dg_status st = DG_OK;
 
     // stable sort by (tile class, N1, N2, N3), ties by natural index
@@ -1908,8 +1910,8 @@ dg_status autotune(dg_batch b) {
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     int dev = 0, cus = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     EpiArgs epi{};
     epi.mode = EPI_RESIDUAL;
     float best = 1e30f;
@@ -1972,9 +1974,10 @@ std::map<std::string, TunedSchedule> g_tune_cache;
 
 std::string tune_key(dg_batch b) {
     int dev = 0;
-    hipGetDevice(&dev);
     hipDeviceProp_t prop{};
-    hipGetDeviceProperties(&prop, dev);
+    // a failed query leaves an empty architecture name: such a key matches no tuned
+    // device, so the batch is tuned afresh
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) prop = hipDeviceProp_t{};
     std::string k = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "/" +
                     std::to_string(b->dtype);
     for (dg_plan p : b->plans) {

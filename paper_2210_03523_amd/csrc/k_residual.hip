@@ -485,7 +485,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
         if (id != 0 && id != nd_ - 1) return nullptr;
         const int s = id == 0 ? -1 : 1;
         const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        const int na = t1 == 0 ? n1 : n2, nb = t2 == 1 ? n2 : n3;
+        const int na = t1 == 0 ? n1 : n2;
         const int fm = loc[k][t1] + na * loc[k][t2];
         return ff + E0.foff + le[k] * fblk + fslot(E0.n, d, s) + fm;
     };
