@@ -399,7 +399,7 @@ dg_status dg_residual_vjp(dg_plan plan, const double *u, const double *v, double
  * dg_functional.  Restarted GMRES (Givens rotations) whose matrix-vector product is
  * dg_residual_vjp; each Arnoldi step orthogonalises by classical Gram-Schmidt (one
  * pass for all inner products, one for the update), repeated once when the first round
- * removes more than half of the vector's squared norm.  Inner products are
+ * removes more than 99 % of the vector's squared norm.  Inner products are
  * deterministic device reductions (fixed partition, fixed summation order).  The problem must be non-singular: on fully periodic meshes the discrete
  * conservation makes (d r / d u)^T singular, so use wall or far-field boundaries.
  *   psi: device double, plan layout; initial guess in, solution out.
