@@ -416,13 +416,20 @@ dg_status dg_residual_vjp(dg_plan plan, const double *u, const double *v, double
  * negative max_iter or rtol, unknown form, psi overlapping u or g, a preconditioner of
  * another plan), DG_EUNSUPPORTED (Navier-Stokes or curved plans), DG_EHIP. */
 #define DG_ADJOINT_MAX_RESTART 200
+/* How the solve applies its element-block preconditioner: DG_PRECOND_JACOBI, z = D^-1 x
+ * (D the diagonal blocks); DG_PRECOND_GAUSS_SEIDEL, z = (D + L)^-1 x with L the
+ * couplings of each element to the elements of the colours before its own (the colours
+ * of the preconditioner's colouring, in order): one more dg_residual_vjp per colour
+ * after the first, on the adjoint workloads here well under half the products. */
+enum { DG_PRECOND_JACOBI = 0, DG_PRECOND_GAUSS_SEIDEL = 1 };
 typedef struct {
     int32_t restart;     /* Krylov vectors per cycle */
     int32_t max_iter;    /* largest number of matrix-vector products */
     double rtol;         /* relative residual target */
     int32_t form;        /* DG_FORM_NEW or DG_FORM_TRAD */
     int32_t isolated;
-    const void *precond; /* dg_adjoint_precond_build's memory, or NULL */
+    const void *precond; /* dg_adjoint_precond_build's memory (either form), or NULL */
+    int32_t precond_sweep; /* DG_PRECOND_JACOBI or DG_PRECOND_GAUSS_SEIDEL */
 } dg_adjoint_params;
 
 dg_status dg_adjoint_workspace(dg_plan plan, int32_t restart, int64_t *doubles);
@@ -470,6 +477,14 @@ dg_status dg_adjoint_precond_compact(dg_plan plan, const void *pc, void *pc16, h
 /* z = M^-1 x with a built preconditioner, either form (x, z: device double, plan layout,
  * distinct). */
 dg_status dg_adjoint_precond_apply(dg_plan plan, const void *pc, const double *x, double *z, hipStream_t stream);
+/* z = (D + L)^-1 x, the colour-ordered block Gauss-Seidel sweep of the solve's
+ * DG_PRECOND_GAUSS_SEIDEL (u, form, isolated: those the preconditioner was built for;
+ * work: device double[5 n_nodes] scratch; x, z, work distinct). */
+dg_status dg_adjoint_precond_apply_gs(dg_plan plan, const void *pc, const double *u, int32_t form, int32_t isolated,
+                                      const double *x, double *z, double *work, hipStream_t stream);
+/* The preconditioner's colouring (host output colour[natural element]): face neighbours
+ * differ in colour; the Gauss-Seidel sweep visits the colours in increasing order. */
+dg_status dg_adjoint_precond_colours(dg_plan plan, const void *pc, int32_t *colour);
 
 /* Pressure force along x on the slip walls (faces normal to x):
  *   J = sum over those faces of sum_{a,b} w_a w_b |Ja^1| p(Q_ab) n_x,

@@ -42,7 +42,11 @@ class _MeshDesc(ctypes.Structure):
 
 class _AdjointParams(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double),
-                ("form", ctypes.c_int32), ("isolated", ctypes.c_int32), ("precond", ctypes.c_void_p)]
+                ("form", ctypes.c_int32), ("isolated", ctypes.c_int32), ("precond", ctypes.c_void_p),
+                ("precond_sweep", ctypes.c_int32)]
+
+
+PRECOND_JACOBI, PRECOND_GAUSS_SEIDEL = 0, 1
 
 
 class _SelectParams(ctypes.Structure):
@@ -95,6 +99,8 @@ SIGNATURES = {
     "dg_adjoint_precond_apply": [_P, _P, _P, _P, _P],
     "dg_adjoint_precond_compact_bytes": [_P, _I64P],
     "dg_adjoint_precond_compact": [_P, _P, _P, _P],
+    "dg_adjoint_precond_apply_gs": [_P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P],
+    "dg_adjoint_precond_colours": [_P, _P, _I32P],
     "dg_adjoint_solve": [_P, _P, _P, _P, ctypes.POINTER(_AdjointParams), _P, _I32P,
                          ctypes.POINTER(ctypes.c_double), _P],
     "dg_rk3_step": [_P, _P, _P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P],
@@ -501,6 +507,24 @@ def adjoint_precond_compact(plan: Plan, pc):
     return pc16
 
 
+def adjoint_precond_apply_gs(plan: Plan, pc, u, x, form: int = FORM_TRAD, isolated: bool = False):
+    """z = (D + L)^-1 x, the colour-ordered block Gauss-Seidel sweep (dg_adjoint_precond_apply_gs)."""
+    torch = _torch()
+    z = torch.empty_like(x)
+    work = torch.empty_like(x)
+    _call("dg_adjoint_precond_apply_gs", plan.handle, _ptr(pc), _ptr(u), int(form), int(bool(isolated)), _ptr(x),
+          _ptr(z), _ptr(work), _stream())
+    return z
+
+
+def adjoint_precond_colours(plan: Plan, pc):
+    """The preconditioner's colour of every element (natural order, numpy int32)."""
+    import numpy as np
+    c = np.empty(plan.n_elems, dtype=np.int32)
+    _call("dg_adjoint_precond_colours", plan.handle, _ptr(pc), c.ctypes.data_as(_I32P))
+    return c
+
+
 def adjoint_precond_apply(plan: Plan, pc, x):
     """z = M^-1 x with a preconditioner of adjoint_precond."""
     z = _torch().empty_like(x)
@@ -509,10 +533,11 @@ def adjoint_precond_apply(plan: Plan, pc, x):
 
 
 def adjoint_solve(plan: Plan, u, g, psi=None, restart: int = 30, max_iter: int = 2000, rtol: float = 1e-10,
-                  form: int = FORM_TRAD, isolated: bool = False, precond=None):
+                  form: int = FORM_TRAD, isolated: bool = False, precond=None, sweep: int = PRECOND_JACOBI):
     """Solve (dr/du)^T psi = g by restarted GMRES on the residual VJP; returns
     (psi, iterations, relative residual).  psi (optional) is the initial guess; precond
-    (optional) a preconditioner of adjoint_precond for the same state, form and flag."""
+    (optional) a preconditioner of adjoint_precond for the same state, form and flag,
+    applied as block Jacobi or as the colour-ordered block Gauss-Seidel sweep."""
     torch = _torch()
     n = 5 * plan.n_nodes
     for t in (u, g):
@@ -523,7 +548,7 @@ def adjoint_solve(plan: Plan, u, g, psi=None, restart: int = 30, max_iter: int =
     _call("dg_adjoint_workspace", plan.handle, int(restart), ctypes.byref(nw))
     work = torch.empty(int(nw.value), dtype=torch.float64, device="cuda")
     prm = _AdjointParams(int(restart), int(max_iter), float(rtol), int(form), int(bool(isolated)),
-                         _ptr(precond).value if precond is not None else None)
+                         _ptr(precond).value if precond is not None else None, int(sweep))
     it = ctypes.c_int32()
     rr = ctypes.c_double()
     _call("dg_adjoint_solve", plan.handle, _ptr(u), _ptr(g), _ptr(x), ctypes.byref(prm), _ptr(work),

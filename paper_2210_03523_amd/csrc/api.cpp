@@ -1483,6 +1483,10 @@ PrecondHeader compact_layout(int E, int nd) {
     h.nd = nd;
     h.compact = 1;
     size_t o = align256(sizeof(PrecondHeader));
+    h.off_first = (int64_t)o;
+    o = align256(o + sizeof(int32_t) * (kMaxColors + 1));
+    h.off_elems = (int64_t)o;
+    o = align256(o + sizeof(int32_t) * E);
     h.off_scales = (int64_t)o;
     o = align256(o + sizeof(float) * (size_t)E * nd);
     h.off_blocks = (int64_t)o;
@@ -1490,16 +1494,79 @@ PrecondHeader compact_layout(int E, int nd) {
     h.bytes = (int64_t)o;
     return h;
 }
-// z = M^-1 x with a built preconditioner of either form
+// z = M^-1 x with a built preconditioner of either form; with elems (count of them) only
+// for those elements, and x - t in place of x when t is given
 hipError_t precond_apply(const PrecondHeader &h, const void *pc, const double *x, double *z, dg_plan p,
-                         hipStream_t stream) {
+                         hipStream_t stream, const int32_t *elems = nullptr, int count = 0,
+                         const double *t = nullptr) {
     const char *b = (const char *)pc;
+    const int ne = elems ? count : p->E;
     if (h.compact)
-        return launch_bj_apply16(b + h.off_blocks, (const float *)(b + h.off_scales), x, z, p->d_el, p->E, h.nd,
-                                 stream);
-    return launch_bj_apply((const float *)(b + h.off_blocks), x, z, p->d_el, p->E, h.nd, stream);
+        return launch_bj_apply16(b + h.off_blocks, (const float *)(b + h.off_scales), x, z, p->d_el, ne, h.nd,
+                                 stream, elems, t);
+    return launch_bj_apply((const float *)(b + h.off_blocks), x, z, p->d_el, ne, h.nd, stream, elems, t);
+}
+// the colour offsets of a built preconditioner (host copy): first[c]..first[c + 1] index
+// the plan elements of colour c in its element list
+dg_status precond_colour_offsets(const PrecondHeader &h, const void *pc, std::vector<int32_t> &first) {
+    first.assign(h.ncolor + 1, 0);
+    if (hipMemcpy(first.data(), (const char *)pc + h.off_first, sizeof(int32_t) * first.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(DG_EHIP, "reading the preconditioner's colouring");
+    return DG_OK;
+}
+// z = (D + L)^-1 x: the block lower triangle of A^T in colour order (colour-ordered block
+// Gauss-Seidel).  z = 0; for each colour c in turn: t = A^T z (c > 0; z then holds the
+// colours before c, so on an element of colour c, t is its coupling to them), and
+// z_e = D_e^-1 (x_e - t_e) on the elements of colour c.  One VJP per colour after the
+// first; t: device scratch of 5 n_nodes doubles.
+dg_status precond_apply_gs(const PrecondHeader &h, const void *pc, const std::vector<int32_t> &first, dg_plan p,
+                           const double *u, int form, int isolated, const double *x, double *z, double *t,
+                           hipStream_t stream) {
+    const int64_t n = (int64_t)NV * p->n_nodes;
+    const int32_t *elems = (const int32_t *)((const char *)pc + h.off_elems);
+    HIP_TRY(launch_axpby(0.0, x, 0.0, z, n, stream));
+    for (int c = 0; c < h.ncolor; ++c) {
+        const int cnt = first[c + 1] - first[c];
+        if (cnt == 0) continue;
+        if (c > 0) {
+            dg_status st = dg_residual_vjp(p, u, z, t, form, isolated, stream);
+            if (st) return st;
+        }
+        HIP_TRY(precond_apply(h, pc, x, z, p, stream, elems + first[c], cnt, c > 0 ? t : nullptr));
+    }
+    return DG_OK;
 }
 }  // namespace
+
+dg_status dg_adjoint_precond_apply_gs(dg_plan p, const void *pc, const double *u, int32_t form, int32_t isolated,
+                                      const double *x, double *z, double *work, hipStream_t stream) {
+    if (!p || !pc || !u || !x || !z || !work) return fail(DG_EINVAL, "null argument");
+    DG_ALIGNED(u, x, z, work);
+    if (x == z || work == x || work == z) return fail(DG_EINVAL, "x, z and work must be distinct");
+    if (form != DG_FORM_NEW && form != DG_FORM_TRAD) return fail(DG_EINVAL, "unknown form");
+    PrecondHeader h;
+    dg_status st = precond_view(p, pc, &h);
+    if (st) return st;
+    std::vector<int32_t> first;
+    if ((st = precond_colour_offsets(h, pc, first))) return st;
+    return precond_apply_gs(h, pc, first, p, u, form, isolated, x, z, work, stream);
+}
+
+dg_status dg_adjoint_precond_colours(dg_plan p, const void *pc, int32_t *colour) {
+    if (!p || !pc || !colour) return fail(DG_EINVAL, "null argument");
+    PrecondHeader h;
+    dg_status st = precond_view(p, pc, &h);
+    if (st) return st;
+    std::vector<int32_t> first, elems(p->E);
+    if ((st = precond_colour_offsets(h, pc, first))) return st;
+    if (hipMemcpy(elems.data(), (const char *)pc + h.off_elems, sizeof(int32_t) * elems.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(DG_EHIP, "reading the preconditioner's colouring");
+    for (int c = 0; c < h.ncolor; ++c)
+        for (int i = first[c]; i < first[c + 1]; ++i) colour[p->perm[elems[i]]] = c;
+    return DG_OK;
+}
 
 dg_status dg_adjoint_precond_compact_bytes(dg_plan p, int64_t *bytes) {
     if (!p || !bytes) return fail(DG_EINVAL, "null argument");
@@ -1522,6 +1589,10 @@ dg_status dg_adjoint_precond_compact(dg_plan p, const void *pc, void *pc16, hipS
     hc.magic = h.magic;
     hc.ncolor = h.ncolor;
     char *b = (char *)pc16;
+    HIP_TRY(hipMemcpyAsync(b + hc.off_first, (const char *)pc + h.off_first, sizeof(int32_t) * (kMaxColors + 1),
+                           hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(b + hc.off_elems, (const char *)pc + h.off_elems, sizeof(int32_t) * p->E,
+                           hipMemcpyDeviceToDevice, stream));
     HIP_TRY(launch_bj_compact((const float *)((const char *)pc + h.off_blocks), b + hc.off_blocks,
                               (float *)(b + hc.off_scales), p->E, h.nd, stream));
     HIP_TRY(hipStreamSynchronize(stream));
@@ -1567,11 +1638,22 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
     double *part = work + (int64_t)(m + 3) * ld;
     PrecondHeader ph{};
     const void *pblk = nullptr;  // the preconditioner, if any (either form)
+    std::vector<int32_t> pfirst;
+    if (prm->precond_sweep != DG_PRECOND_JACOBI && prm->precond_sweep != DG_PRECOND_GAUSS_SEIDEL)
+        return fail(DG_EINVAL, "unknown preconditioner sweep");
+    const bool gs = prm->precond && prm->precond_sweep == DG_PRECOND_GAUSS_SEIDEL;
     if (prm->precond) {
         dg_status st0 = precond_view(p, prm->precond, &ph);
         if (st0) return st0;
         pblk = prm->precond;
+        if (gs && (st0 = precond_colour_offsets(ph, pblk, pfirst))) return st0;
     }
+    // M^-1 v into out; T: scratch of the Gauss-Seidel sweep
+    auto papply = [&](const double *v, double *out, double *T) -> dg_status {
+        if (gs) return precond_apply_gs(ph, pblk, pfirst, p, u, prm->form, prm->isolated, v, out, T, stream);
+        HIP_TRY(precond_apply(ph, pblk, v, out, p, stream));
+        return DG_OK;
+    };
     double *hb = part + mdot_partials();  // 2 (m + 4) doubles: a step's coefficients and norms
     auto fetch = [&](double *dst, int count) -> dg_status {
         HIP_TRY(hipMemcpyAsync(dst, hb, sizeof(double) * count, hipMemcpyDeviceToHost, stream));
@@ -1588,7 +1670,8 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
     // A^T M^-1 v (right preconditioning) or A^T v
     auto pmatvec = [&](const double *v, double *out) -> dg_status {
         if (!pblk) return matvec(v, out);
-        HIP_TRY(precond_apply(ph, pblk, v, Z, p, stream));
+        dg_status s2 = papply(v, Z, V + (int64_t)(m + 1) * ld);  // V_m+1 is free during a cycle
+        if (s2) return s2;
         return matvec(Z, out);
     };
     dg_status st;
@@ -1672,7 +1755,7 @@ dg_status dg_adjoint_solve(dg_plan p, const double *u, const double *g, double *
             double *t = V + (int64_t)(m + 1) * ld;
             HIP_TRY(launch_axpby(y[0], V, 0.0, t, n, stream));
             for (int i = 1; i < k; ++i) HIP_TRY(launch_axpby(y[i], V + (int64_t)i * ld, 1.0, t, n, stream));
-            HIP_TRY(precond_apply(ph, pblk, t, Z, p, stream));
+            if ((st = papply(t, Z, V + ld))) return st;  // V_1 is free once V y is formed
             HIP_TRY(launch_axpby(1.0, Z, 1.0, psi, n, stream));
         }
     }

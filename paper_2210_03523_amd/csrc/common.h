@@ -207,11 +207,12 @@ hipError_t launch_probe_set(double *v, const int32_t *elems, int nel, const Elem
 hipError_t launch_probe_gather(const double *out, float *blocks, const int32_t *elems, int nel, const ElemInfo *el,
                                int j, int nd, hipStream_t s);
 hipError_t launch_bj_apply(const float *blocks, const double *x, double *z, const ElemInfo *el, int E, int nd,
-                           hipStream_t s);
+                           hipStream_t s, const int32_t *elems = nullptr, const double *t = nullptr);
 // Compact FP16 storage of the inverse blocks with per-column FP32 scales, and its apply.
 hipError_t launch_bj_compact(const float *blocks, void *hblocks, float *scales, int E, int nd, hipStream_t s);
 hipError_t launch_bj_apply16(const void *hblocks, const float *scales, const double *x, double *z,
-                             const ElemInfo *el, int E, int nd, hipStream_t s);
+                             const ElemInfo *el, int E, int nd, hipStream_t s, const int32_t *elems = nullptr,
+                             const double *t = nullptr);
 hipError_t launch_axpby(double alpha, const double *x, double beta, double *y, int64_t n, hipStream_t s);
 int dot_partials();
 // Gram-Schmidt passes over Krylov vectors x_k = X + k ld, k < c: out[k] = x_k . w (and

@@ -39,11 +39,13 @@ __global__ __launch_bounds__(256) void k_probe_gather(const double *__restrict__
 // keeps 4 columns' loads in flight; the workgroup has a lane per row quad (nd / 4 rounded
 // up to whole waves, at most 1024).  Otherwise 256 lanes of one row each per pass.
 __global__ __launch_bounds__(1024) void k_bj_apply(const float *__restrict__ blocks, const double *__restrict__ x,
-                                                  double *__restrict__ z, const ElemInfo *__restrict__ el, int nd) {
+                                                  const double *__restrict__ t, double *__restrict__ z,
+                                                  const ElemInfo *__restrict__ el, const int32_t *__restrict__ elems,
+                                                  int nd) {
     extern __shared__ double sx[];
-    const int e = blockIdx.x;
+    const int e = elems ? elems[blockIdx.x] : blockIdx.x;
     const int64_t base = (int64_t)NV * el[e].noff;
-    for (int i = threadIdx.x; i < nd; i += blockDim.x) sx[i] = x[base + i];
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) sx[i] = t ? x[base + i] - t[base + i] : x[base + i];
     __syncthreads();
     const float *B = blocks + (int64_t)e * nd * nd;
     if ((nd & 3) == 0) {
@@ -98,11 +100,14 @@ __global__ __launch_bounds__(256) void k_bj_compact(const float *__restrict__ bl
 // (a lane per row quad, 8-byte loads of four FP16 values; one row per lane otherwise).
 __global__ __launch_bounds__(1024) void k_bj_apply16(const __half *__restrict__ hblocks,
                                                      const float *__restrict__ scales, const double *__restrict__ x,
-                                                     double *__restrict__ z, const ElemInfo *__restrict__ el, int nd) {
+                                                     const double *__restrict__ t, double *__restrict__ z,
+                                                     const ElemInfo *__restrict__ el,
+                                                     const int32_t *__restrict__ elems, int nd) {
     extern __shared__ double sx[];
-    const int e = blockIdx.x;
+    const int e = elems ? elems[blockIdx.x] : blockIdx.x;
     const int64_t base = (int64_t)NV * el[e].noff;
-    for (int i = threadIdx.x; i < nd; i += blockDim.x) sx[i] = x[base + i] * (double)scales[(int64_t)e * nd + i];
+    for (int i = threadIdx.x; i < nd; i += blockDim.x)
+        sx[i] = (t ? x[base + i] - t[base + i] : x[base + i]) * (double)scales[(int64_t)e * nd + i];
     __syncthreads();
     const __half *B = hblocks + (int64_t)e * nd * nd;
     if ((nd & 3) == 0) {
@@ -143,11 +148,12 @@ hipError_t launch_bj_compact(const float *blocks, void *hblocks, float *scales, 
 }
 
 hipError_t launch_bj_apply16(const void *hblocks, const float *scales, const double *x, double *z,
-                             const ElemInfo *el, int E, int nd, hipStream_t s) {
+                             const ElemInfo *el, int E, int nd, hipStream_t s, const int32_t *elems,
+                             const double *t) {
     if (E == 0) return hipSuccess;
     const int threads = (nd & 3) == 0 ? std::min(1024, (nd / 4 + 63) / 64 * 64) : 256;
     hipLaunchKernelGGL(k_bj_apply16, dim3(E), dim3(threads), sizeof(double) * nd, s, (const __half *)hblocks, scales,
-                       x, z, el, nd);
+                       x, t, z, el, elems, nd);
     return hipGetLastError();
 }
 
@@ -166,10 +172,10 @@ hipError_t launch_probe_gather(const double *out, float *blocks, const int32_t *
 }
 
 hipError_t launch_bj_apply(const float *blocks, const double *x, double *z, const ElemInfo *el, int E, int nd,
-                           hipStream_t s) {
+                           hipStream_t s, const int32_t *elems, const double *t) {
     if (E == 0) return hipSuccess;
     const int threads = (nd & 3) == 0 ? std::min(1024, (nd / 4 + 63) / 64 * 64) : 256;
-    hipLaunchKernelGGL(k_bj_apply, dim3(E), dim3(threads), sizeof(double) * nd, s, blocks, x, z, el, nd);
+    hipLaunchKernelGGL(k_bj_apply, dim3(E), dim3(threads), sizeof(double) * nd, s, blocks, x, t, z, el, elems, nd);
     return hipGetLastError();
 }
 
