@@ -406,15 +406,17 @@ dg_status dg_residual_vjp(dg_plan plan, const double *u, const double *v, double
  *   work: device double of dg_adjoint_workspace(plan, restart) values (caller-owned;
  *         nothing is allocated here).
  *   iters, relres (host, nullable): products done and the final ||g - A^T psi|| / ||g||.
- *   precond (in params, nullable): an element-block Jacobi preconditioner built by
- *         dg_adjoint_precond_build for the same plan, state, form and isolated flag,
- *         applied on the right (the Krylov space is that of A^T M^-1; the stopping test
- *         stays on the true residual).
+ *   precond (in params, nullable): an element-block preconditioner built by
+ *         dg_adjoint_precond_build (or its compact form) for the same plan, state, form
+ *         and isolated flag, applied on the right (the Krylov space is that of A^T M^-1;
+ *         the stopping test stays on the true residual) as params.precond_sweep says.
+ *         The Gauss-Seidel sweep uses the workspace's spare vectors as its scratch.
  * Stops at relres <= rtol or after max_iter products.  SYNCHRONOUS: the host drives the
  * iteration and waits on stream once or twice per Arnoldi step.
  * Errors: DG_EINVAL (null arguments, restart outside 1..DG_ADJOINT_MAX_RESTART,
  * negative max_iter or rtol, unknown form, psi overlapping u or g, a preconditioner of
- * another plan), DG_EUNSUPPORTED (Navier-Stokes or curved plans), DG_EHIP. */
+ * another plan, an unknown precond_sweep), DG_EUNSUPPORTED (Navier-Stokes or curved
+ * plans), DG_EHIP. */
 #define DG_ADJOINT_MAX_RESTART 200
 /* How the solve applies its element-block preconditioner: DG_PRECOND_JACOBI, z = D^-1 x
  * (D the diagonal blocks); DG_PRECOND_GAUSS_SEIDEL, z = (D + L)^-1 x with L the
