@@ -50,7 +50,7 @@ __device__ __forceinline__ int qdiv(int m, float inv_n) { return (int)(((float)m
 // them 64 at a time.
 constexpr int RW_YIT = (NNMAX * NNMAX * NNMAX + 63) / 64;  // y-pass outputs per lane
 template <bool PROJECT>
-__global__ __launch_bounds__(64) void k_restrict_w(const int32_t *__restrict__ fine_of,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_restrict_w(const int32_t *__restrict__ fine_of,
                                                    const ElemInfo *__restrict__ cel,
                                                    const ElemInfo *__restrict__ fel, const double *__restrict__ u,
                                                    const double *__restrict__ dudt, const double *__restrict__ psi,
