@@ -39,6 +39,12 @@ __device__ __forceinline__ int xcd_remap(int bid, int G) {
     return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
 }
 
+// A value in the global address space.  Pointers read from a descriptor in memory are
+// cast to `gmem<T> *` before use, so that their accesses compile to global (not flat)
+// memory instructions.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+
 // Per plan element record (device).
 struct ElemInfo {
     int32_t n[3];     // nodes per direction (order + 1)

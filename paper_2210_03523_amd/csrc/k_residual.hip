@@ -65,10 +65,14 @@ __device__ __forceinline__ void split2(int m, int n, float inv, int &a, int &b) 
 // metric), the face input of the gradient pass.
 // D: the face direction as a compile-time constant (see face_body below).
 // L, R: the elements of the two sides (a boundary face passes its one element in both).
-template <typename T, int FN, int MODE, int D>
-__device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, const ElemInfo &R,
-                                            const T *__restrict__ u, T *__restrict__ ff, const T *__restrict__ tab,
-                                            const Geom &g, const PhysParams &ph, FaceSmem<T, FN> &sm) {
+// UP, FP: pointer types of the state and the face fluxes (generic, or in the global
+// address space where the pointers come from a descriptor in memory: the compiler cannot
+// tell their address space then and would issue flat accesses, which also count against
+// the LDS wait counter and need 64-bit address arithmetic per access).
+template <typename T, int FN, int MODE, int D, typename UP, typename FP>
+__device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, const ElemInfo &R, UP __restrict__ u,
+                                            FP __restrict__ ff, const T *__restrict__ tab, const Geom &g,
+                                            const PhysParams &ph, FaceSmem<T, FN> &sm) {
     constexpr int d = D, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const T Ja = (T)g.Ja[d];
     const T gam = (T)ph.gamma;
@@ -78,8 +82,8 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
         const int s = f.eL >= 0 ? 1 : -1;
         const ElemInfo &E = f.eL >= 0 ? L : R;
         const int na = E.n[t1], nb = E.n[t2], ne = E.n[0] * E.n[1] * E.n[2];
-        const T *Q = u + NV * E.noff;
-        T *out = ff + E.foff + fslot(E.n, d, s);
+        const UP Q = u + NV * E.noff;
+        const FP out = ff + E.foff + fslot(E.n, d, s);
         const float ina = 1.0f / na;
         for (int m = lane; m < na * nb; m += 64) {
             int ma, mb;
@@ -112,8 +116,8 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
     const int K1 = aL > aR ? aL : aR, K2 = bL > bR ? bL : bR;
     const float iaL = 1.0f / aL, iaR = 1.0f / aR, iK1 = 1.0f / K1;
     const int neL = L.n[0] * L.n[1] * L.n[2], neR = R.n[0] * R.n[1] * R.n[2];
-    T *oL = ff + L.foff + fslot(L.n, d, 1);
-    T *oR = ff + R.foff + fslot(R.n, d, -1);
+    const FP oL = ff + L.foff + fslot(L.n, d, 1);
+    const FP oR = ff + R.foff + fslot(R.n, d, -1);
 
     if (aL == aR && bL == bR) {
         // conforming face: one node pair per lane, no staging
@@ -261,7 +265,7 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
     // second tangential direction, outward sign (+ for L, - for R)
     for (int side = 0; side < 2; ++side) {
         const int na = side == 0 ? aL : aR, nb = side == 0 ? bL : bR;
-        T *out = side == 0 ? oL : oR;
+        const FP out = side == 0 ? oL : oR;
         const T sg = (side == 0 || MODE == 1) ? T(1) : T(-1);
         const bool x1 = na != K1;  // the first pass ran: intermediate in QL/QR as [a + na B]
         T(*U)[FN] = x1 ? (side == 0 ? sm.QL : sm.QR) : sm.F;
@@ -292,10 +296,10 @@ __device__ __forceinline__ void face_body_d(const Face f, const ElemInfo &L, con
 // The face direction selects register-array elements all through the face body; it is
 // made a compile-time constant by a wave-uniform branch, so nothing is indexed at run
 // time (which would put the arrays in scratch memory).
-template <typename T, int FN, int MODE = 0>
-__device__ __forceinline__ void face_body(const Face f, const ElemInfo &L, const ElemInfo &R,
-                                          const T *__restrict__ u, T *__restrict__ ff, const T *__restrict__ tab,
-                                          const Geom &g, const PhysParams &ph, FaceSmem<T, FN> &sm) {
+template <typename T, int FN, int MODE = 0, typename UP = const T *, typename FP = T *>
+__device__ __forceinline__ void face_body(const Face f, const ElemInfo &L, const ElemInfo &R, UP u, FP ff,
+                                          const T *__restrict__ tab, const Geom &g, const PhysParams &ph,
+                                          FaceSmem<T, FN> &sm) {
     if (f.d == 0) face_body_d<T, FN, MODE, 0>(f, L, R, u, ff, tab, g, ph, sm);
     else if (f.d == 1) face_body_d<T, FN, MODE, 1>(f, L, R, u, ff, tab, g, ph, sm);
     else face_body_d<T, FN, MODE, 2>(f, L, R, u, ff, tab, g, ph, sm);
@@ -390,7 +394,7 @@ __device__ __forceinline__ void elem_preload(const Tile tl, const ElemInfo E0, c
         const int loc[3] = {nd % n1, (nd / n1) % n2, nd / (n1 * n2)};
         const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le * npe);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) P.q[k][v] = ok ? u[base + v * npe + nd] : T(1);
+        for (int v = 0; v < NV; ++v) P.q[k][v] = ok ? ((const gmem<T> *)u)[base + v * npe + nd] : T(1);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const int id = loc[d], nd_ = d == 0 ? n1 : d == 1 ? n2 : n3;
@@ -398,12 +402,13 @@ __device__ __forceinline__ void elem_preload(const Tile tl, const ElemInfo E0, c
             const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
             const int na = t1 == 0 ? n1 : n2;
             const int ab = (d == 0 ? n2 * n3 : d == 1 ? n1 * n3 : n1 * n2);
-            const T *fp = ff + E0.foff + le * fblk + fslot(E0.n, d, id == 0 ? -1 : 1) + loc[t1] + na * loc[t2];
+            const gmem<T> *fp =
+                (const gmem<T> *)ff + E0.foff + le * fblk + fslot(E0.n, d, id == 0 ? -1 : 1) + loc[t1] + na * loc[t2];
 #pragma unroll
             for (int v = 0; v < NV; ++v) P.fe[k][d][v] = on ? fp[v * ab] : T(0);
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) P.ge[k][v] = (ok && rk) ? ((const T *)epi.g)[base + v * npe + nd] : T(0);
+        for (int v = 0; v < NV; ++v) P.ge[k][v] = (ok && rk) ? ((const gmem<T> *)epi.g)[base + v * npe + nd] : T(0);
     }
 }
 
@@ -470,7 +475,7 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
         const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            q[k][v] = PRE ? pre->q[k][v] : ok[k] ? u[base + v * npe + nd[k]] : T(1);
+            q[k][v] = PRE ? pre->q[k][v] : ok[k] ? ((const gmem<T> *)u)[base + v * npe + nd[k]] : T(1);
             V[k][v] = T(0);
         }
         if (CURVED) {
@@ -480,14 +485,14 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
         }
     }
     // the face flux of face (d, side of the node) at this thread's k-th node, variable v
-    auto face_ptr = [&](int k, int d) -> const T * {
+    auto face_ptr = [&](int k, int d) -> const gmem<T> * {
         const int id = loc[k][d], nd_ = d == 0 ? n1 : d == 1 ? n2 : n3;
         if (id != 0 && id != nd_ - 1) return nullptr;
         const int s = id == 0 ? -1 : 1;
         const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
         const int na = t1 == 0 ? n1 : n2;
         const int fm = loc[k][t1] + na * loc[k][t2];
-        return ff + E0.foff + le[k] * fblk + fslot(E0.n, d, s) + fm;
+        return (const gmem<T> *)ff + E0.foff + le[k] * fblk + fslot(E0.n, d, s) + fm;
     };
     constexpr int NE = EARLY ? NPT : 1;
     T fe[NE][3][NV];  // EARLY: face fluxes (per direction; zero off the faces)
@@ -508,14 +513,14 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
             const int64_t base = (int64_t)NV * (E0.noff + (int64_t)le[k] * npe);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const T *fp = (ok[k] && !epi.isolated) ? face_ptr(k, d) : nullptr;
+                const gmem<T> *fp = (ok[k] && !epi.isolated) ? face_ptr(k, d) : nullptr;
                 const int ab = (d == 0 ? n2 * n3 : d == 1 ? n1 * n3 : n1 * n2);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) fe[k][d][v] = fp ? fp[v * ab] : T(0);
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                ge[k][v] = (ok[k] && epi.mode == EPI_RK && epi.rkA != 0.0) ? ((const T *)epi.g)[base + v * npe + nd[k]]
+                ge[k][v] = (ok[k] && epi.mode == EPI_RK && epi.rkA != 0.0) ? ((const gmem<T> *)epi.g)[base + v * npe + nd[k]]
                                                                            : T(0);
         }
     }
@@ -643,12 +648,12 @@ __device__ __forceinline__ void elem_body(const Tile tl, const ElemInfo E0, cons
         const T www = tab[T_W + xoff(n1 - 1) + loc[k][0]] * tab[T_W + xoff(n2 - 1) + loc[k][1]] *
                       tab[T_W + xoff(n3 - 1) + loc[k][2]];
         if (epi.mode == EPI_RESIDUAL) {
-            T *r = (T *)epi.out;
+            gmem<T> *r = (gmem<T> *)epi.out;
 #pragma unroll
             for (int v = 0; v < NV; ++v) r[base + v * npe + nd[k]] = epi.form == 0 ? V[k][v] * invJ : www * V[k][v];
         } else if (epi.mode == EPI_RK) {
-            T *uu = (T *)u;
-            T *G = (T *)epi.g;
+            gmem<T> *uu = (gmem<T> *)u;
+            gmem<T> *G = (gmem<T> *)epi.g;
             const T A = (T)epi.rkA, B = (T)epi.rkB, dt = (T)epi.dt;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -1059,7 +1064,7 @@ __global__ __launch_bounds__(64) void k_face_batch(const BatchFace *__restrict__
     for (int i = i0; i < i1; ++i) {
         const BatchFace bf = faces[i];
         const ProbDesc<T> pd = probs[bf.prob];
-        face_body<T, 64>(bf.f, bf.L, bf.R, pd.u, pd.ff, tab, pd.geom, pd.phys, sm);
+        face_body<T, 64>(bf.f, bf.L, bf.R, (const gmem<T> *)pd.u, (gmem<T> *)pd.ff, tab, pd.geom, pd.phys, sm);
         __syncthreads();
     }
 }
